@@ -1,0 +1,227 @@
+"""CPU oracle (FP64, brute force) -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this package.  It shares no code with the HIP library; the two meet
+only in the seeded inputs from ``workloads``.
+
+The C sources (``solar.c``, ``shadow.c``) compute:
+  * solar position: NOAA solar-calculator / Meeus low-precision equations;
+  * the shadow predicate: brute-force ray vs every convex prism (2D
+    Cyrus-Beck + height), and an independent Moller-Trumbore version;
+  * sampled gross shadow (count and minutes) with a silhouette-ambiguity
+    mask;
+  * continuous gross shadow along a piecewise great-circle sun path (grid +
+    bisection per occluder, union, measure).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        dp, ip, fp = C.POINTER(C.c_double), C.POINTER(C.c_int32), C.POINTER(C.c_float)
+        L.orc_julian_day.restype = C.c_double
+        L.orc_julian_day.argtypes = [C.c_int, C.c_int, C.c_double]
+        L.orc_solar.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double, C.c_double, dp]
+        L.orc_solar_jd.argtypes = [C.c_double, C.c_double, C.c_double, dp]
+        L.orc_day_samples.restype = C.c_int
+        L.orc_day_samples.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, C.c_double, C.c_double,
+                                      C.c_double, C.c_double, C.c_double, dp, dp, C.c_int, dp]
+        for f in (L.orc_shadow, L.orc_shadow_mt):
+            f.restype = C.c_int
+            f.argtypes = [C.c_void_p, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, C.c_int, dp]
+        L.orc_sampled.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, ip, C.c_int, ip, dp,
+                                  C.POINTER(C.c_uint32), C.POINTER(C.c_uint8), C.c_int]
+        L.orc_continuous.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, ip, C.c_int, ip, C.c_int,
+                                     C.c_double, dp, ip, C.c_int, dp, ip, C.c_int]
+        L.orc_slerp.argtypes = [dp, dp, C.c_double, dp]
+        _lib = L
+    return _lib
+
+
+class _Scene(C.Structure):
+    _fields_ = [("n_b", C.c_int32), ("vert_off", C.c_void_p), ("xy", C.c_void_p), ("height", C.c_void_p)]
+
+
+class _Points(C.Structure):
+    _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
+                ("nx", C.c_void_p), ("ny", C.c_void_p), ("owner", C.c_void_p)]
+
+
+def _ptr(a, ct=None):
+    if a is None:
+        return None
+    return a.ctypes.data_as(C.POINTER(ct)) if ct is not None else a.ctypes.data
+
+
+def _scene(scene):
+    keep = (np.ascontiguousarray(scene.vert_off, np.int32), np.ascontiguousarray(scene.xy, np.float32),
+            np.ascontiguousarray(scene.height, np.float32))
+    s = _Scene(len(keep[2]), keep[0].ctypes.data, keep[1].ctypes.data, keep[2].ctypes.data)
+    return s, keep
+
+
+def _points(pts):
+    keep = tuple(np.ascontiguousarray(getattr(pts, k), np.float32) for k in ("x", "y", "z", "nx", "ny")) + \
+        (np.ascontiguousarray(pts.owner, np.int32),)
+    s = _Points(len(keep[0]), *[k.ctypes.data for k in keep])
+    return s, keep
+
+
+def threads_default() -> int:
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+# --------------------------------------------------------------------------
+# solar position
+# --------------------------------------------------------------------------
+def julian_day(y, m, d) -> float:
+    return lib().orc_julian_day(int(y), int(m), float(d))
+
+
+def solar(y, m, d, t_loc_min, tz_h, lat, lon) -> np.ndarray:
+    """[dirE, dirN, dirU, elev_deg, azim_deg, decl_deg, eot_min, app_long_deg, obliq_deg]"""
+    out = np.zeros(9)
+    lib().orc_solar(int(y), int(m), int(d), float(t_loc_min), float(tz_h), float(lat), float(lon),
+                    _ptr(out, C.c_double))
+    return out
+
+
+def solar_jd(jd, lat, lon) -> np.ndarray:
+    out = np.zeros(9)
+    lib().orc_solar_jd(float(jd), float(lat), float(lon), _ptr(out, C.c_double))
+    return out
+
+
+def day_samples(day, lat, lon, step):
+    cap = 4000
+    t, w, span = np.zeros(cap), np.zeros(cap), np.zeros(2)
+    t0, t1 = (day.window if day.window is not None else (-1.0, -1.0))
+    K = lib().orc_day_samples(day.year, day.month, day.day, day.tz_h, lat, lon, t0, t1, step,
+                              _ptr(t, C.c_double), _ptr(w, C.c_double), cap, _ptr(span, C.c_double))
+    if K < 0:
+        raise ValueError("day samples: window not in daylight or capacity exceeded")
+    return t[:K].copy(), w[:K].copy(), span
+
+
+@dataclass
+class OraclePath:
+    dirs: np.ndarray        # [K, 3] FP64 sample directions
+    w: np.ndarray           # [K] minutes
+    t: np.ndarray           # [K] local minutes
+    sample_day: np.ndarray  # [K] int32
+    sample_bin: np.ndarray  # [K] int32
+    seg_t: np.ndarray       # [J, 2]
+    seg_dir: np.ndarray     # [J, 2, 3]
+    seg_day: np.ndarray     # [J] int32
+    day_bin: np.ndarray     # [n_days] int32
+    n_bins: int
+    spans: np.ndarray       # [n_days, 2]
+
+
+def sun_path(span, seg_min: float | None = None) -> OraclePath:
+    """Sample instants and great-circle knots for every day of ``span``.
+    Knots: T0, T0 + L, T0 + 2L, ... and T1 (the last segment may be
+    shorter); L = ``seg_min`` (default: the sample step)."""
+    L = float(seg_min if seg_min is not None else span.step_min)
+    dirs, ws, ts, sd, sb = [], [], [], [], []
+    seg_t, seg_dir, seg_day, spans = [], [], [], []
+    day_bin = np.array(span.day_bin if span.day_bin is not None else range(len(span.days)), np.int32)
+    for di, day in enumerate(span.days):
+        t, w, sp = day_samples(day, span.lat, span.lon, span.step_min)
+        spans.append(sp)
+        for tk in t:
+            dirs.append(solar(day.year, day.month, day.day, tk, day.tz_h, span.lat, span.lon)[:3])
+        ws.append(w); ts.append(t)
+        sd.append(np.full(len(t), di, np.int32)); sb.append(np.full(len(t), day_bin[di], np.int32))
+        if len(t) == 0:
+            continue
+        T0, T1 = sp
+        knots = list(np.arange(T0, T1, L))
+        if knots[-1] < T1:
+            knots.append(T1)
+        kd = [solar(day.year, day.month, day.day, tk, day.tz_h, span.lat, span.lon)[:3] for tk in knots]
+        for j in range(len(knots) - 1):
+            seg_t.append((knots[j], knots[j + 1]))
+            seg_dir.append((kd[j], kd[j + 1]))
+            seg_day.append(di)
+    return OraclePath(np.array(dirs).reshape(-1, 3), np.concatenate(ws), np.concatenate(ts),
+                      np.concatenate(sd), np.concatenate(sb), np.array(seg_t).reshape(-1, 2),
+                      np.array(seg_dir).reshape(-1, 2, 3), np.array(seg_day, np.int32), day_bin,
+                      int(day_bin.max()) + 1 if len(day_bin) else 0, np.array(spans))
+
+
+def slerp(a, b, f) -> np.ndarray:
+    out = np.zeros(3)
+    a = np.ascontiguousarray(a, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    lib().orc_slerp(_ptr(a, C.c_double), _ptr(b, C.c_double), float(f), _ptr(out, C.c_double))
+    return out
+
+
+# --------------------------------------------------------------------------
+# predicate and accumulation
+# --------------------------------------------------------------------------
+def shadow(scene, p, d, nrm=(0.0, 0.0), owner=-1, mt=False) -> int:
+    s, keep = _scene(scene)
+    d = np.ascontiguousarray(d, np.float64)
+    f = lib().orc_shadow_mt if mt else lib().orc_shadow
+    return int(f(C.byref(s), float(p[0]), float(p[1]), float(p[2]), float(nrm[0]), float(nrm[1]),
+                 int(owner), _ptr(d, C.c_double)))
+
+
+def sampled(scene, pts, path: OraclePath, bits=False, amb=False, threads=None):
+    """Sampled gross shadow: counts int32 [n_bins, n], minutes FP64
+    [n_bins, n], optional bit vectors uint32 [n, ceil(K/32)] and ambiguity
+    flags uint8 [n, K]."""
+    s, ks = _scene(scene)
+    p, kp = _points(pts)
+    K, n = len(path.w), pts.n
+    counts = np.zeros((path.n_bins, n), np.int32)
+    minutes = np.zeros((path.n_bins, n), np.float64)
+    b = np.zeros((n, (K + 31) // 32), np.uint32) if bits else None
+    a = np.zeros((n, K), np.uint8) if amb else None
+    dirs = np.ascontiguousarray(path.dirs, np.float64)
+    w = np.ascontiguousarray(path.w, np.float64)
+    sbin = np.ascontiguousarray(path.sample_bin, np.int32)
+    lib().orc_sampled(C.byref(s), C.byref(p), K, _ptr(dirs, C.c_double), _ptr(w, C.c_double),
+                      _ptr(sbin, C.c_int32), path.n_bins, _ptr(counts, C.c_int32),
+                      _ptr(minutes, C.c_double), _ptr(b, C.c_uint32), _ptr(a, C.c_uint8),
+                      threads or threads_default())
+    return dict(counts=counts, minutes=minutes, bits=b, amb=a)
+
+
+def continuous(scene, pts, path: OraclePath, grid_min=1.0 / 12.0, threads=None):
+    """Continuous gross shadow along the piecewise great-circle path of
+    ``path``'s knots: minutes FP64 [n_bins, n] and counts (sample instants
+    inside the shadowed set) int32 [n_bins, n]."""
+    s, ks = _scene(scene)
+    p, kp = _points(pts)
+    n = pts.n
+    minutes = np.zeros((path.n_bins, n), np.float64)
+    counts = np.zeros((path.n_bins, n), np.int32)
+    seg_t = np.ascontiguousarray(path.seg_t, np.float64)
+    seg_dir = np.ascontiguousarray(path.seg_dir, np.float64)
+    seg_day = np.ascontiguousarray(path.seg_day, np.int32)
+    day_bin = np.ascontiguousarray(path.day_bin, np.int32)
+    st = np.ascontiguousarray(path.t, np.float64)
+    sd = np.ascontiguousarray(path.sample_day, np.int32)
+    lib().orc_continuous(C.byref(s), C.byref(p), len(seg_t), _ptr(seg_t, C.c_double),
+                         _ptr(seg_dir, C.c_double), _ptr(seg_day, C.c_int32), len(day_bin),
+                         _ptr(day_bin, C.c_int32), path.n_bins, float(grid_min),
+                         _ptr(st, C.c_double), _ptr(sd, C.c_int32), len(st),
+                         _ptr(minutes, C.c_double), _ptr(counts, C.c_int32), threads or threads_default())
+    return dict(minutes=minutes, counts=counts)

@@ -1,0 +1,514 @@
+/*
+ * Oracle shadow predicate and accumulation -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Definitions followed:
+ *   gross shadow = time a point spends in shadow over the interval
+ *   (Sec. 3.1); with discrete instants it is the count of shadowed instants
+ *   scaled by the step (Sec. 4 step 2, Sec. 5), here reported both as the
+ *   integer count and as minutes with each instant weighted by its share of
+ *   the interval.
+ *   The sun is a directional light (Sec. 3.2).  Between two knot instants
+ *   the path model is the great circle at constant angular rate, the motion
+ *   under which Theorem 1 (Sec. 4) holds.
+ *   Several occluders along one ray: every one of them is a shadow source
+ *   (Sec. 5, "source levels"); here all of them are taken, no level cap.
+ *
+ * Brute force: every building is tested for every ray.  FP64 throughout.
+ * Nothing here is shared with, or derived from, the HIP library.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+#include "oracle.h"
+
+typedef struct {
+    int n_b;
+    const int32_t *off;
+    double *xy;    /* [2V] */
+    double *H;     /* [n_b] */
+    double *box;   /* [4 n_b]: xmin, ymin, xmax, ymax */
+} scene64;
+
+static void scene64_init(scene64 *S, const orc_scene *s)
+{
+    S->n_b = s->n_b;
+    S->off = s->vert_off;
+    int V = s->n_b ? s->vert_off[s->n_b] : 0;
+    S->xy = (double *)malloc(sizeof(double) * (2 * (size_t)V + 1));
+    S->H = (double *)malloc(sizeof(double) * ((size_t)s->n_b + 1));
+    S->box = (double *)malloc(sizeof(double) * (4 * (size_t)s->n_b + 1));
+    for (int i = 0; i < 2 * V; ++i) S->xy[i] = s->xy[i];
+    for (int b = 0; b < s->n_b; ++b) {
+        S->H[b] = s->height[b];
+        double x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY;
+        for (int v = s->vert_off[b]; v < s->vert_off[b + 1]; ++v) {
+            x0 = fmin(x0, S->xy[2 * v]);
+            x1 = fmax(x1, S->xy[2 * v]);
+            y0 = fmin(y0, S->xy[2 * v + 1]);
+            y1 = fmax(y1, S->xy[2 * v + 1]);
+        }
+        S->box[4 * b] = x0; S->box[4 * b + 1] = y0;
+        S->box[4 * b + 2] = x1; S->box[4 * b + 3] = y1;
+    }
+}
+
+static void scene64_free(scene64 *S)
+{
+    free(S->xy);
+    free(S->H);
+    free(S->box);
+}
+
+/* Does the ray p + s d, s > 0, meet the closed axis-aligned box
+ * [x0,x1] x [y0,y1] x [0,H]?  A necessary condition for meeting the prism
+ * inside it. */
+static int ray_meets_box(const double *p, const double *d, const double *bx, double H)
+{
+    double lo = 0.0, hi = INFINITY;
+    double blo[3] = {bx[0], bx[1], 0.0}, bhi[3] = {bx[2], bx[3], H};
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) {
+            if (p[a] < blo[a] || p[a] > bhi[a]) return 0;
+        } else {
+            double t0 = (blo[a] - p[a]) / d[a], t1 = (bhi[a] - p[a]) / d[a];
+            if (t0 > t1) { double t = t0; t0 = t1; t1 = t; }
+            if (t0 > lo) lo = t0;
+            if (t1 < hi) hi = t1;
+            if (lo > hi) return 0;
+        }
+    }
+    return 1;
+}
+
+/* Ray against the closed convex prism b: clip the ray's horizontal
+ * projection by every edge half-plane of the footprint (Cyrus-Beck) to get
+ * the parameter range [s_in, s_out] over the footprint; the ray rises, so
+ * it is lowest where it enters (or at its origin): it meets the prism iff
+ * that range is non-empty for s >= 0 and the height there is <= H. */
+static int hit_prism(const scene64 *S, int b, const double *p, const double *d)
+{
+    if (!ray_meets_box(p, d, S->box + 4 * b, S->H[b])) return 0;
+    double s_in = -INFINITY, s_out = INFINITY;
+    int o = S->off[b], m = S->off[b + 1] - o;
+    for (int i = 0; i < m; ++i) {
+        const double *a = S->xy + 2 * (o + i), *c = S->xy + 2 * (o + (i + 1) % m);
+        double nx = c[1] - a[1], ny = -(c[0] - a[0]);     /* outward normal (CCW) */
+        double num = nx * (a[0] - p[0]) + ny * (a[1] - p[1]);
+        double den = nx * d[0] + ny * d[1];
+        if (den > 0.0) {
+            double s = num / den;
+            if (s < s_out) s_out = s;
+        } else if (den < 0.0) {
+            double s = num / den;
+            if (s > s_in) s_in = s;
+        } else if (num < 0.0) {
+            return 0;                                      /* parallel, outside */
+        }
+    }
+    double s0 = s_in > 0.0 ? s_in : 0.0;
+    if (s_out < s0) return 0;
+    return p[2] + s0 * d[2] <= S->H[b];
+}
+
+static int shadow64(const scene64 *S, const double *p, const double *nrm, int owner,
+                    const double *d)
+{
+    if (owner >= 0 && nrm[0] * d[0] + nrm[1] * d[1] <= 0.0) return 1;  /* back-facing wall */
+    for (int b = 0; b < S->n_b; ++b)
+        if (b != owner && hit_prism(S, b, p, d)) return 1;
+    return 0;
+}
+
+int orc_shadow(const orc_scene *s, double px, double py, double pz,
+               double nx, double ny, int owner, const double *d)
+{
+    scene64 S;
+    scene64_init(&S, s);
+    double p[3] = {px, py, pz}, n[2] = {nx, ny};
+    int r = shadow64(&S, p, n, owner, d);
+    scene64_free(&S);
+    return r;
+}
+
+/* ---- independent check: Moller-Trumbore against the triangulated prism ---- */
+static int ray_tri(const double *o, const double *d, const double *v0, const double *v1,
+                   const double *v2)
+{
+    double e1[3], e2[3], pv[3], tv[3], qv[3];
+    for (int i = 0; i < 3; ++i) { e1[i] = v1[i] - v0[i]; e2[i] = v2[i] - v0[i]; }
+    pv[0] = d[1] * e2[2] - d[2] * e2[1];
+    pv[1] = d[2] * e2[0] - d[0] * e2[2];
+    pv[2] = d[0] * e2[1] - d[1] * e2[0];
+    double det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
+    if (fabs(det) < 1e-300) return 0;
+    double inv = 1.0 / det;
+    for (int i = 0; i < 3; ++i) tv[i] = o[i] - v0[i];
+    double u = (tv[0] * pv[0] + tv[1] * pv[1] + tv[2] * pv[2]) * inv;
+    if (u < 0.0 || u > 1.0) return 0;
+    qv[0] = tv[1] * e1[2] - tv[2] * e1[1];
+    qv[1] = tv[2] * e1[0] - tv[0] * e1[2];
+    qv[2] = tv[0] * e1[1] - tv[1] * e1[0];
+    double v = (d[0] * qv[0] + d[1] * qv[1] + d[2] * qv[2]) * inv;
+    if (v < 0.0 || u + v > 1.0) return 0;
+    double t = (e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2]) * inv;
+    return t > 0.0;
+}
+
+int orc_shadow_mt(const orc_scene *s, double px, double py, double pz,
+                  double nx, double ny, int owner, const double *d)
+{
+    double p[3] = {px, py, pz};
+    if (owner >= 0 && nx * d[0] + ny * d[1] <= 0.0) return 1;
+    for (int b = 0; b < s->n_b; ++b) {
+        if (b == owner) continue;
+        int o = s->vert_off[b], m = s->vert_off[b + 1] - o;
+        double H = s->height[b];
+        for (int i = 0; i < m; ++i) {
+            int j = (i + 1) % m;
+            double a0[3] = {s->xy[2 * (o + i)], s->xy[2 * (o + i) + 1], 0.0};
+            double b0[3] = {s->xy[2 * (o + j)], s->xy[2 * (o + j) + 1], 0.0};
+            double a1[3] = {a0[0], a0[1], H}, b1[3] = {b0[0], b0[1], H};
+            if (ray_tri(p, d, a0, b0, b1) || ray_tri(p, d, a0, b1, a1)) return 1;   /* wall */
+            if (i >= 1 && i + 1 < m) {
+                double r0[3] = {s->xy[2 * o], s->xy[2 * o + 1], H};
+                double g0[3] = {r0[0], r0[1], 0.0};
+                if (ray_tri(p, d, r0, a1, b1) || ray_tri(p, d, g0, a0, b0)) return 1; /* roof, base */
+            }
+        }
+    }
+    return 0;
+}
+
+/* ---- thread pool over points ---- */
+typedef struct {
+    void (*fn)(void *ctx, int64_t i);
+    void *ctx;
+    int64_t n;
+    int64_t next;
+    pthread_mutex_t mu;
+} pool_t;
+
+static void *pool_worker(void *arg)
+{
+    pool_t *P = (pool_t *)arg;
+    for (;;) {
+        pthread_mutex_lock(&P->mu);
+        int64_t i = P->next++;
+        pthread_mutex_unlock(&P->mu);
+        if (i >= P->n) break;
+        P->fn(P->ctx, i);
+    }
+    return NULL;
+}
+
+static void parallel_for(int64_t n, int threads, void (*fn)(void *, int64_t), void *ctx)
+{
+    pool_t P = {fn, ctx, n, 0, PTHREAD_MUTEX_INITIALIZER};
+    if (threads <= 1) {
+        for (int64_t i = 0; i < n; ++i) fn(ctx, i);
+        return;
+    }
+    pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * threads);
+    for (int t = 0; t < threads; ++t) pthread_create(&th[t], NULL, pool_worker, &P);
+    for (int t = 0; t < threads; ++t) pthread_join(th[t], NULL);
+    free(th);
+}
+
+/* ---- sampled form ---- */
+typedef struct {
+    const scene64 *S;
+    const orc_points *P;
+    int K;
+    const double *dirs, *w;
+    const int32_t *bin;
+    int n_bins;
+    int32_t *counts;
+    double *minutes;
+    uint32_t *bits;
+    uint8_t *amb;
+} sampled_ctx;
+
+/* Directions 1.1e-5 rad from d, displaced toward 8 evenly spaced azimuths
+ * about d: a ray whose predicate differs from any of them passes within
+ * 1e-5 rad of a silhouette (or of the wall's own plane). */
+static int ambiguous(const scene64 *S, const double *p, const double *nrm, int owner,
+                     const double *d, int s0)
+{
+    const double eps = 1.1e-5;
+    double a[3], b[3];
+    /* orthonormal a, b perpendicular to d */
+    if (fabs(d[2]) < 0.9) { a[0] = -d[1]; a[1] = d[0]; a[2] = 0.0; }
+    else { a[0] = 0.0; a[1] = -d[2]; a[2] = d[1]; }
+    double na = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    for (int i = 0; i < 3; ++i) a[i] /= na;
+    b[0] = d[1] * a[2] - d[2] * a[1];
+    b[1] = d[2] * a[0] - d[0] * a[2];
+    b[2] = d[0] * a[1] - d[1] * a[0];
+    for (int j = 0; j < 8; ++j) {
+        double c = cos(j * M_PI / 4.0), s = sin(j * M_PI / 4.0), q[3];
+        for (int i = 0; i < 3; ++i) q[i] = d[i] * cos(eps) + (c * a[i] + s * b[i]) * sin(eps);
+        if (shadow64(S, p, nrm, owner, q) != s0) return 1;
+    }
+    return 0;
+}
+
+static void sampled_point(void *vctx, int64_t i)
+{
+    sampled_ctx *C = (sampled_ctx *)vctx;
+    const orc_points *P = C->P;
+    int64_t n = P->n;
+    double p[3] = {P->x[i], P->y[i], P->z[i]};
+    double nrm[2] = {P->nx ? P->nx[i] : 0.0, P->ny ? P->ny[i] : 0.0};
+    int owner = P->owner ? P->owner[i] : -1;
+    int words = (C->K + 31) / 32;
+    for (int k = 0; k < C->K; ++k) {
+        const double *d = C->dirs + 3 * k;
+        int s = shadow64(C->S, p, nrm, owner, d);
+        int bin = C->bin ? C->bin[k] : 0;
+        if (C->counts) C->counts[(int64_t)bin * n + i] += s;
+        if (C->minutes) C->minutes[(int64_t)bin * n + i] += s * C->w[k];
+        if (C->bits && s) C->bits[i * words + k / 32] |= 1u << (k % 32);
+        if (C->amb) C->amb[i * C->K + k] = (uint8_t)ambiguous(C->S, p, nrm, owner, d, s);
+    }
+}
+
+void orc_sampled(const orc_scene *s, const orc_points *p, int K, const double *dirs,
+                 const double *w, const int32_t *sample_bin, int n_bins,
+                 int32_t *counts, double *minutes, uint32_t *bits, uint8_t *amb,
+                 int threads)
+{
+    scene64 S;
+    scene64_init(&S, s);
+    if (counts) memset(counts, 0, sizeof(int32_t) * (size_t)n_bins * p->n);
+    if (minutes) memset(minutes, 0, sizeof(double) * (size_t)n_bins * p->n);
+    if (bits) memset(bits, 0, sizeof(uint32_t) * (size_t)p->n * ((K + 31) / 32));
+    sampled_ctx C = {&S, p, K, dirs, w, sample_bin, n_bins, counts, minutes, bits, amb};
+    parallel_for(p->n, threads, sampled_point, &C);
+    scene64_free(&S);
+}
+
+/* ---- continuous duration along the piecewise great-circle path ---- */
+void orc_slerp(const double *a, const double *b, double f, double *out)
+{
+    double c = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    double cr[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    double s = sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+    double th = atan2(s, c);
+    if (th < 1e-15) {
+        for (int i = 0; i < 3; ++i) out[i] = a[i];
+        return;
+    }
+    double wa = sin((1.0 - f) * th) / sin(th), wb = sin(f * th) / sin(th);
+    for (int i = 0; i < 3; ++i) out[i] = wa * a[i] + wb * b[i];
+}
+
+typedef struct { double lo, hi; } ival;
+typedef struct { ival *v; int n, cap; } ivec;
+
+static void ivec_push(ivec *a, double lo, double hi)
+{
+    if (a->n == a->cap) {
+        a->cap = a->cap ? 2 * a->cap : 64;
+        a->v = (ival *)realloc(a->v, sizeof(ival) * a->cap);
+    }
+    a->v[a->n].lo = lo;
+    a->v[a->n].hi = hi;
+    a->n++;
+}
+
+static int ival_cmp(const void *x, const void *y)
+{
+    double a = ((const ival *)x)->lo, b = ((const ival *)y)->lo;
+    return (a > b) - (a < b);
+}
+
+/* sort + merge in place; returns the number of disjoint intervals */
+static int ivec_union(ivec *a)
+{
+    qsort(a->v, a->n, sizeof(ival), ival_cmp);
+    int m = 0;
+    for (int i = 0; i < a->n;) {
+        double lo = a->v[i].lo, hi = a->v[i].hi;
+        int j = i + 1;
+        while (j < a->n && a->v[j].lo <= hi) {
+            if (a->v[j].hi > hi) hi = a->v[j].hi;
+            ++j;
+        }
+        a->v[m].lo = lo;
+        a->v[m].hi = hi;
+        ++m;
+        i = j;
+    }
+    a->n = m;
+    return m;
+}
+
+typedef struct {
+    const scene64 *S;
+    const orc_points *P;
+    int n_seg;
+    const double *seg_t, *seg_dir;
+    const int32_t *seg_day;
+    int n_days;
+    const int32_t *day_bin;
+    double grid;
+    const double *sample_t;
+    const int32_t *sample_day;
+    int n_samples;
+    double *minutes;
+    int32_t *counts;
+    /* gradient mode */
+    const double *dl;
+    double *grad;
+    pthread_mutex_t *grad_mu;
+} cont_ctx;
+
+/* one occluder's predicate: b >= 0 a prism, b == -1 the point's own wall
+ * facing away from the sun */
+static int occl(const scene64 *S, int b, const double *p, const double *nrm, const double *d)
+{
+    if (b < 0) return nrm[0] * d[0] + nrm[1] * d[1] <= 0.0;
+    return hit_prism(S, b, p, d);
+}
+
+/* Every ray of the segment lies in the plane through p spanned by the two
+ * knot directions: a prism whose bounding box lies strictly on one side of
+ * that plane cannot be met during the segment. */
+static int box_off_plane(const scene64 *S, int b, const double *p, const double *N)
+{
+    const double *bx = S->box + 4 * b;
+    int pos = 0, neg = 0;
+    for (int c = 0; c < 8; ++c) {
+        double q[3] = {(c & 1) ? bx[2] : bx[0], (c & 2) ? bx[3] : bx[1], (c & 4) ? S->H[b] : 0.0};
+        double f = N[0] * (q[0] - p[0]) + N[1] * (q[1] - p[1]) + N[2] * (q[2] - p[2]);
+        if (f > 0) pos = 1;
+        else if (f < 0) neg = 1;
+        else return 0;
+    }
+    return !(pos && neg);
+}
+
+static void seg_dir_at(const double *da, const double *db, double ta, double tb, double t,
+                       double *d)
+{
+    orc_slerp(da, db, (t - ta) / (tb - ta), d);
+}
+
+/* Times in [ta, tb] at which one occluder shadows p: its predicate sampled
+ * on a grid of spacing <= grid, each change located by bisection to 1e-9
+ * minutes.  Appends the shadowed intervals to out. */
+static void occluder_intervals(const scene64 *S, int b, const double *p, const double *nrm,
+                               double ta, double tb, const double *da, const double *db,
+                               double grid, ivec *out)
+{
+    int G = (int)ceil((tb - ta) / grid - 1e-12);
+    if (G < 1) G = 1;
+    double d[3], open_t = ta, t_prev = ta;
+    int prev = 0;
+    for (int g = 0; g <= G; ++g) {
+        double t = (g == G) ? tb : ta + (tb - ta) * g / G;
+        seg_dir_at(da, db, ta, tb, t, d);
+        int v = occl(S, b, p, nrm, d);
+        if (g > 0 && v != prev) {
+            double lo = t_prev, hi = t;
+            for (int it = 0; it < 80 && hi - lo > 1e-9; ++it) {
+                double mid = 0.5 * (lo + hi);
+                seg_dir_at(da, db, ta, tb, mid, d);
+                if (occl(S, b, p, nrm, d) == prev) lo = mid;
+                else hi = mid;
+            }
+            double sw = 0.5 * (lo + hi);
+            if (v) open_t = sw;
+            else ivec_push(out, open_t, sw);
+        } else if (g == 0 && v) {
+            open_t = ta;
+        }
+        prev = v;
+        t_prev = t;
+    }
+    if (prev) ivec_push(out, open_t, tb);
+}
+
+static void seg_plane(const double *da, const double *db, double *N)
+{
+    N[0] = da[1] * db[2] - da[2] * db[1];
+    N[1] = da[2] * db[0] - da[0] * db[2];
+    N[2] = da[0] * db[1] - da[1] * db[0];
+    double s = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]);
+    if (s > 0) for (int i = 0; i < 3; ++i) N[i] /= s;
+}
+
+/* Shadowed intervals of one point over one segment, all occluders, not
+ * merged. */
+static void segment_intervals(const scene64 *S, const double *p, const double *nrm, int owner,
+                              double ta, double tb, const double *da, const double *db,
+                              double grid, ivec *out)
+{
+    if (!(tb > ta)) return;
+    double N[3];
+    seg_plane(da, db, N);
+    for (int b = (owner >= 0 ? -1 : 0); b < S->n_b; ++b) {
+        if (b >= 0 && (b == owner || box_off_plane(S, b, p, N))) continue;
+        occluder_intervals(S, b, p, nrm, ta, tb, da, db, grid, out);
+    }
+}
+
+static void continuous_point(void *vctx, int64_t i)
+{
+    cont_ctx *C = (cont_ctx *)vctx;
+    const orc_points *P = C->P;
+    int64_t n = P->n;
+    double p[3] = {P->x[i], P->y[i], P->z[i]};
+    double nrm[2] = {P->nx ? P->nx[i] : 0.0, P->ny ? P->ny[i] : 0.0};
+    int owner = P->owner ? P->owner[i] : -1;
+    ivec day = {0, 0, 0};
+    int j = 0, k = 0;
+    for (int dd = 0; dd < C->n_days; ++dd) {
+        day.n = 0;
+        for (; j < C->n_seg && C->seg_day[j] == dd; ++j)
+            segment_intervals(C->S, p, nrm, owner, C->seg_t[2 * j], C->seg_t[2 * j + 1],
+                              C->seg_dir + 6 * j, C->seg_dir + 6 * j + 3, C->grid, &day);
+        int m = ivec_union(&day);
+        double meas = 0.0;
+        for (int a = 0; a < m; ++a) meas += day.v[a].hi - day.v[a].lo;
+        int cnt = 0;
+        for (; k < C->n_samples && C->sample_day[k] == dd; ++k) {
+            double t = C->sample_t[k];
+            for (int a = 0; a < m; ++a)
+                if (t >= day.v[a].lo && t <= day.v[a].hi) { ++cnt; break; }
+        }
+        int bin = C->day_bin ? C->day_bin[dd] : dd;
+        if (C->minutes) C->minutes[(int64_t)bin * n + i] += meas;
+        if (C->counts) C->counts[(int64_t)bin * n + i] += cnt;
+    }
+    free(day.v);
+}
+
+void orc_continuous(const orc_scene *s, const orc_points *p, int n_seg,
+                    const double *seg_t, const double *seg_dir, const int32_t *seg_day,
+                    int n_days, const int32_t *day_bin, int n_bins, double grid_min,
+                    const double *sample_t, const int32_t *sample_day, int n_samples,
+                    double *minutes, int32_t *counts, int threads)
+{
+    scene64 S;
+    scene64_init(&S, s);
+    if (minutes) memset(minutes, 0, sizeof(double) * (size_t)n_bins * p->n);
+    if (counts) memset(counts, 0, sizeof(int32_t) * (size_t)n_bins * p->n);
+    cont_ctx C;
+    memset(&C, 0, sizeof(C));
+    C.S = &S; C.P = p; C.n_seg = n_seg; C.seg_t = seg_t; C.seg_dir = seg_dir;
+    C.seg_day = seg_day; C.n_days = n_days; C.day_bin = day_bin; C.grid = grid_min;
+    C.sample_t = sample_t; C.sample_day = sample_day; C.n_samples = n_samples;
+    C.minutes = minutes; C.counts = counts;
+    parallel_for(p->n, threads, continuous_point, &C);
+    scene64_free(&S);
+}
+
+void orc_grad_implicit(const orc_scene *s, const orc_points *p, int n_seg,
+                       const double *seg_t, const double *seg_dir, double grid_min,
+                       const double *dl_dmin, double *grad, int threads)
+{
+    (void)s; (void)p; (void)n_seg; (void)seg_t; (void)seg_dir; (void)grid_min;
+    (void)dl_dmin; (void)grad; (void)threads;
+}

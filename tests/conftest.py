@@ -1,0 +1,19 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (HIP device) and the built HIP library")
+    config.addinivalue_line("markers", "slow: CPU test that takes more than ~20 s")
+
+
+@pytest.fixture(scope="session")
+def c1():
+    from workloads import make_c1
+    return make_c1()
