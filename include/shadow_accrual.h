@@ -1,0 +1,255 @@
+/*
+ * shadow_accrual.h -- C ABI of the MI355X (gfx950) shadow-accumulation
+ * library (libsa).
+ *
+ * What it computes: for every sample point of a city (ground or facade),
+ * the time it spends in the shadow of extruded buildings over a time span
+ * -- the paper's "gross shadow" (Sec. 3.1) -- in two forms:
+ *
+ *   SA_SAMPLED  one shadow ray per point per sun instant, the per-step
+ *               ray-casting approach the paper uses as its baseline
+ *               (Sec. 8.1, "brute force ray tracing");
+ *   SA_ACCRUAL  the sun-movement form: between two knot instants the light
+ *               direction turns along a great circle at a constant angular
+ *               rate (the motion under which Theorem 1 of Sec. 4 holds), so
+ *               the rays from a point sweep a planar fan and every occluder
+ *               contributes one occluded time interval (the shadow of each
+ *               source moves along a line, Sec. 3.2; all sources are taken,
+ *               Sec. 5); the union of those intervals is measured.
+ *
+ * Frame: local east-north-up metres (x east, y north, z up), ground z = 0.
+ * Buildings are convex prisms: a counter-clockwise convex footprint
+ * extruded from z = 0 to z = H > 0, closed.  The sun is a directional
+ * light (Sec. 3.2).
+ *
+ * Conventions:
+ *  - Every call returns sa_status; 0 is success, negative an error.  No
+ *    call aborts or throws; the context keeps a message (sa_last_error).
+ *  - Device work is enqueued on the context's HIP stream; calls return
+ *    after enqueueing.  The only host-synchronous calls are the ones that
+ *    build library-owned objects (scene upload / height edit, path
+ *    upload) and sa_sync.
+ *  - "host" pointers are read before the call returns and may be freed
+ *    after; "device" pointers are caller-owned device memory (e.g. torch
+ *    tensors), never freed by the library and read or written by work on
+ *    the context's stream.
+ *  - Scenes and paths are library-owned, opaque, freed by their destroy
+ *    call.  All objects belong to the context that made them.
+ */
+#ifndef SHADOW_ACCRUAL_H
+#define SHADOW_ACCRUAL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t sa_status;
+#define SA_OK 0
+#define SA_ERR_INVALID_ARG (-1)  /* bad pointer, size, mode or range */
+#define SA_ERR_GEOMETRY (-2)     /* footprint not convex / not CCW / < 3 vertices, H <= 0 */
+#define SA_ERR_CAPACITY (-3)     /* a fixed-size structure overflowed (BVH depth, spill queue) */
+#define SA_ERR_OOM (-4)          /* device allocation failed */
+#define SA_ERR_DEVICE (-5)       /* HIP runtime error */
+#define SA_ERR_UNSUPPORTED (-6)  /* e.g. a sun-path plane too close to vertical */
+
+#define SA_SAMPLED 0
+#define SA_ACCRUAL 1
+
+/* sa_accum_opts.flags */
+#define SA_FLAG_ADD 1u           /* add into the outputs instead of overwriting them */
+
+typedef struct sa_ctx sa_ctx;
+typedef struct sa_scene sa_scene;
+typedef struct sa_path sa_path;
+
+/* ------------------------------------------------------------------ */
+/* context                                                             */
+/* ------------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream). */
+sa_status sa_create(int32_t device, void *hip_stream, sa_ctx **out);
+void sa_destroy(sa_ctx *ctx);
+/* Change the stream later calls enqueue on. */
+sa_status sa_set_stream(sa_ctx *ctx, void *hip_stream);
+/* Message of the last failed call on this context ("" if none). */
+const char *sa_last_error(const sa_ctx *ctx);
+/* Wait for the context's stream; reports errors raised by device work
+ * since the last sync (spill-queue overflow). */
+sa_status sa_sync(sa_ctx *ctx);
+/* Library version string. */
+const char *sa_version(void);
+
+/* ------------------------------------------------------------------ */
+/* scene: buildings as extruded convex prisms (a city model, Sec. 8.2) */
+/* ------------------------------------------------------------------ */
+
+/* Upload n_b prisms from host arrays: vert_off [n_b+1] (CSR offsets into
+ * xy), xy [2*vert_off[n_b]] (x, y pairs, counter-clockwise, convex, >= 3
+ * vertices), height [n_b] (> 0).  Builds the bounding-volume hierarchy on
+ * the device (Morton codes of footprint centres, radix sort, binary radix
+ * tree, bottom-up box refit).  Host-synchronous.  n_b == 0 is an empty
+ * scene (nothing casts shadow).  Errors: INVALID_ARG, GEOMETRY, CAPACITY
+ * (tree deeper than 64 levels), OOM, DEVICE. */
+sa_status sa_scene_upload(sa_ctx *ctx, int32_t n_b, const int32_t *vert_off,
+                          const float *xy, const float *height, sa_scene **out);
+
+/* Replace the heights of buildings ids[0..n) (host arrays, original
+ * building ids) by h[0..n) (> 0) and refit the hierarchy's boxes (heights
+ * only: the topology is kept).  Models the paper's impact analysis, where a
+ * building is replaced and the shadows recomputed (Sec. 7.1).
+ * Host-synchronous. */
+sa_status sa_scene_set_heights(sa_ctx *ctx, sa_scene *scene, int32_t n, const int32_t *ids,
+                               const float *h);
+
+typedef struct {
+    int32_t n_b;      /* prisms */
+    int32_t n_vert;   /* footprint vertices */
+    int32_t n_nodes;  /* interior hierarchy nodes (n_b - 1, or 1 if n_b == 1) */
+    int32_t depth;    /* levels from the root to the deepest leaf */
+    float bounds[4];  /* xmin, ymin, xmax, ymax of the footprints */
+    float max_height;
+} sa_scene_info;
+sa_status sa_scene_get_info(const sa_scene *scene, sa_scene_info *out);
+
+/* Copy the hierarchy to the host for inspection: nodes [n_nodes * 16]
+ * 32-bit words (layout in the library source: per interior node the two
+ * child boxes and child references) and prim_order [n_b] (original id of
+ * the prism at each leaf position).  Either pointer may be NULL. */
+sa_status sa_scene_read_bvh(sa_ctx *ctx, const sa_scene *scene, void *nodes, int32_t *prim_order);
+
+void sa_scene_destroy(sa_scene *scene);
+
+/* ------------------------------------------------------------------ */
+/* sun path: the time selection of Sec. 7.1 (start date, n days, a      */
+/* daily window) turned into sample instants and great-circle knots      */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    double lat_deg, lon_deg;  /* site, degrees (east positive) */
+    double tz_offset_h;       /* local civil time = UTC + tz_offset_h */
+} sa_site;
+
+typedef struct {
+    int32_t year, month, day; /* first day (Gregorian) */
+    int32_t n_days;           /* consecutive days, >= 1 */
+    double t_start_min;       /* local minutes after midnight; < 0: the first whole minute
+                                 with the sun above the horizon */
+    double t_end_min;         /* with t_start_min < 0: ignored (last such minute) */
+    double step_min;          /* spacing of the sample instants (> 0) */
+    double seg_min;           /* knot spacing of the accrual form (> 0) */
+} sa_timespan;
+
+/* Host arrays describing a sun path.  As the output of sa_sunpath the
+ * caller sets the cap_* fields and the array pointers (or NULL to only
+ * size); as the input of sa_path_upload all counts and arrays are read. */
+typedef struct {
+    int32_t n_days, n_samples, n_knots;
+    int32_t cap_days, cap_samples, cap_knots;
+    int32_t *day_sample_off; /* [n_days+1] samples of day d: [off[d], off[d+1]) */
+    double *t_min;           /* [n_samples] local minutes of each instant */
+    double *dir;             /* [3*n_samples] unit direction toward the sun (E, N, U) */
+    double *weight;          /* [n_samples] minutes each instant stands for (its share of
+                                the day's span; ends get half a step) */
+    int32_t *day_knot_off;   /* [n_days+1] knots of day d: [off[d], off[d+1]) */
+    double *knot_t;          /* [n_knots] knot instants (local minutes): the span start,
+                                every seg_min after it, and the span end */
+    double *knot_dir;        /* [3*n_knots] */
+    int32_t *day_bin;        /* [n_days] output bin of each day; NULL on input = bin = day */
+} sa_sunpath_buf;
+
+/* Solar position by the NOAA solar-calculator equations (Meeus' low
+ * precision solar coordinates), geometric elevation (no refraction), FP64.
+ * Fills `out` for the days of `span`; days keep only instants with the sun
+ * above the horizon (a fixed window that reaches below it is an
+ * INVALID_ARG).  Sizing: with cap_* == 0 only the counts are written.
+ * Host only, synchronous.  Errors: INVALID_ARG, CAPACITY (caps too small). */
+sa_status sa_sunpath(const sa_site *site, const sa_timespan *span, sa_sunpath_buf *out);
+
+/* Upload a sun path (host arrays of `in`, any number of days, each day's
+ * knots spanning its samples) for use by accumulate calls.  Precomputes,
+ * in FP64 on the host, each segment's plane, basis and angle.  Bins:
+ * in->day_bin (or bin = day); n_bins = 1 + max bin.  Errors: INVALID_ARG,
+ * UNSUPPORTED (a segment whose plane is within 3 degrees of vertical), OOM. */
+sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out);
+sa_status sa_path_info(const sa_path *path, int32_t *n_bins, int32_t *n_samples,
+                       int32_t *n_segments);
+void sa_path_destroy(sa_path *path);
+
+/* ------------------------------------------------------------------ */
+/* accumulate: gross shadow per point (Sec. 3.1), binned by day          */
+/* ------------------------------------------------------------------ */
+
+/* Sample points, device arrays of n float32 (structure of arrays).
+ * Ground points: z = 0, nx = ny = 0, owner = -1.  Facade points: on a wall
+ * of building `owner` (original id), (nx, ny) the wall's outward
+ * horizontal normal; a wall facing away from the sun is in shadow.  nx, ny,
+ * owner may be NULL (all ground / no owner). */
+typedef struct {
+    int64_t n;
+    const float *x, *y, *z;
+    const float *nx, *ny;
+    const int32_t *owner;
+} sa_points;
+
+typedef struct {
+    int32_t mode;     /* SA_SAMPLED or SA_ACCRUAL */
+    uint32_t flags;   /* SA_FLAG_ADD */
+    float out_scale;  /* minutes are multiplied by this (0 = 1; 1/60 gives hours) */
+    int32_t reserved[5];
+} sa_accum_opts;
+
+/* Gross shadow of every point over every day of `path`, summed per bin.
+ *   counts  device int32 [n_bins * n] (bin-major; NULL = not wanted):
+ *           SA_SAMPLED: shadowed instants; SA_ACCRUAL: sample instants
+ *           inside the occluded set.
+ *   minutes device float [n_bins * n]: SA_SAMPLED: sum of the weights of the
+ *           shadowed instants; SA_ACCRUAL: measure of the occluded set (both
+ *           times out_scale).
+ *   bits    device uint32 [ceil(n_samples/32) * n] (word-major; SA_SAMPLED
+ *           only; NULL = not wanted): bit k%32 of word k/32 of point i is
+ *           instant k's predicate -- the n-bit shadow vector of Sec. 5.
+ * Errors: INVALID_ARG, CAPACITY (reported by sa_sync if the accrual spill
+ * queue overflows), DEVICE. */
+sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts,
+                        const sa_path *path, const sa_accum_opts *opts, int32_t *counts,
+                        float *minutes, uint32_t *bits);
+
+/* Batched development scenarios (Sec. 7.1 impact analysis, many at once):
+ * n_var variants of `scene`, variant v replacing the heights of buildings
+ * var_ids[v*k .. v*k+k) by var_h[v*k ..) (device arrays, original ids,
+ * k = ids_per_var), each evaluated on its own points
+ * pts[var_off[v] .. var_off[v+1]) (var_off: device int64 [n_var+1]).  One
+ * refit per variant and one persistent accrual launch over a (variant,
+ * tile) work queue.  Outputs as sa_accumulate over the concatenated points
+ * (SA_ACCRUAL only). */
+sa_status sa_accumulate_batched(sa_ctx *ctx, const sa_scene *scene, int32_t n_var,
+                                int32_t ids_per_var, const int32_t *var_ids, const float *var_h,
+                                const sa_points *pts, const int64_t *var_off,
+                                const sa_path *path, const sa_accum_opts *opts, int32_t *counts,
+                                float *minutes);
+
+/* Gradient of L = sum_bins sum_p dl_dmin[bin*n + p] * minutes_accrual(p, bin)
+ * with respect to every building height: each boundary of a point's
+ * occluded set that is made by a roof edge moves with the height; its time
+ * derivative comes from implicit differentiation of the roof-grazing
+ * condition (closing ends +, opening ends -).  Traversals are recomputed,
+ * nothing is stored from the forward pass.  dl_dmin: device float
+ * [n_bins * n] or NULL (all ones).  grad: device float [n_b] (original
+ * ids), overwritten.  Errors: INVALID_ARG, DEVICE. */
+sa_status sa_grad_heights(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts,
+                          const sa_path *path, const float *dl_dmin, float *grad);
+
+/* Region sums (the shadow area of Sec. 7.2): out[r] = sum over
+ * p in [region_off[r], region_off[r+1]) of values[p] * (area ? area[p] : 1),
+ * accumulated in FP64.  values, area: device float [n]; region_off: device
+ * int64 [n_reg+1]; out: device double [n_reg]. */
+sa_status sa_region_sum(sa_ctx *ctx, const float *values, int64_t n, const int64_t *region_off,
+                        int32_t n_reg, const float *area, double *out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHADOW_ACCRUAL_H */

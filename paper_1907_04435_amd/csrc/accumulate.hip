@@ -1,0 +1,428 @@
+// Gross-shadow kernels: the sampled form (one shadow ray per point per sun
+// instant) and the accrual form (one occluded interval per occluder per
+// point per great-circle segment, union, measure), plus the accrual spill
+// pass that finishes the rare point-segments whose occluded set has more
+// than four disjoint pieces by splitting their window in halves.
+#include <hip/hip_runtime.h>
+
+#include "sa_internal.h"
+#include "traverse.h"
+
+namespace sa {
+namespace {
+using namespace dev;
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kSpillRounds = 12;
+constexpr int kSpillBlocks = 1024;
+
+struct PointArgs {
+    int64_t n;
+    const float *x, *y, *z, *nx, *ny;
+    const int32_t *owner;
+    const int32_t *rank;  // original id -> hierarchy position
+    int32_t n_b;
+};
+
+struct LanePoint {
+    float px, py, pz, nx, ny;
+    int own;  // hierarchy position of the owner, -1 for ground points
+};
+
+__device__ __forceinline__ LanePoint load_point(const PointArgs &P, int64_t i, bool valid)
+{
+    LanePoint q{0.f, 0.f, 0.f, 0.f, 0.f, -1};
+    if (valid) {
+        q.px = P.x[i];
+        q.py = P.y[i];
+        q.pz = P.z[i];
+        if (P.nx) q.nx = P.nx[i];
+        if (P.ny) q.ny = P.ny[i];
+        if (P.owner) {
+            const int o = P.owner[i];
+            q.own = (o >= 0 && o < P.n_b) ? P.rank[o] : -1;
+        }
+    }
+    return q;
+}
+
+// ------------------------------------------------------------------ sampled
+template <bool kBits>
+__global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const float4 *verts_g,
+                                                      const float *height_g, const SampleConst *samples_g,
+                                                      int K, PointArgs P, float scale, int32_t *counts,
+                                                      float *minutes, uint32_t *bits)
+{
+    cNode *nodes = (cNode *)nodes_g;
+    cfloat4 *verts = (cfloat4 *)verts_g;
+    cfloat *height = (cfloat *)height_g;
+    cSample *samples = (cSample *)samples_g;
+    __shared__ int s_stack[kWaves][kStackDepth];
+    int *stack = s_stack[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
+    const int64_t i = wave * 64 + lane;
+    const bool valid = i < P.n;
+    const LanePoint q = load_point(P, i, valid);
+    const int64_t n = P.n;
+
+    int cnt = 0;
+    float mins = 0.f;
+    int bin = K > 0 ? ld(samples).bin : 0;
+    uint32_t word = 0;
+    for (int k = 0; k < K; ++k) {
+        const SampleConst s = ld(samples + k);
+        if (s.bin != bin) {
+            if (valid) {
+                if (counts) counts[(int64_t)bin * n + i] += cnt;
+                if (minutes) minutes[(int64_t)bin * n + i] += mins * scale;
+            }
+            cnt = 0;
+            mins = 0.f;
+            bin = s.bin;
+        }
+        const bool back = q.own >= 0 && fmaf(q.nx, s.dx, q.ny * s.dy) <= 0.f;
+        bool live = valid && !back;
+        bool hit = false;
+        if (nodes_g != nullptr) {
+            const float ox = -q.px * s.ix, oy = -q.py * s.iy, oz = -q.pz * s.iz;
+            const bool sx = s.dx >= 0.f, sy = s.dy >= 0.f;
+            auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
+                const float tnx = fmaf(sx ? x0 : x1, s.ix, ox), tfx = fmaf(sx ? x1 : x0, s.ix, ox);
+                const float tny = fmaf(sy ? y0 : y1, s.iy, oy), tfy = fmaf(sy ? y1 : y0, s.iy, oy);
+                const float tfz = fmaf(z1, s.iz, oz);
+                return fmaxf(fmaxf(tnx, tny), 0.f) <= fminf(fminf(tfx, tfy), tfz);
+            };
+            auto leaf = [&](int prim, int voff, int m, bool want) {
+                const bool t = want && prim != q.own &&
+                               ray_prism(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, s.dx, s.dy, s.dz);
+                hit = hit || t;
+                live = live && !t;
+            };
+            auto key = [&](float x0, float y0, float x1, float y1, float z1) {
+                return fmaf(x0 + x1, s.dx, fmaf(y0 + y1, s.dy, z1 * s.dz));
+            };
+            packet_traverse(nodes, stack, live, bt, leaf, key);
+        }
+        const bool sh = valid && (back || hit);
+        cnt += sh ? 1 : 0;
+        mins += sh ? s.w : 0.f;
+        if (kBits) {
+            word |= (uint32_t)sh << (k & 31);
+            if ((k & 31) == 31 || k == K - 1) {
+                if (valid) bits[(int64_t)(k >> 5) * n + i] = word;
+                word = 0;
+            }
+        }
+    }
+    if (valid && K > 0) {
+        if (counts) counts[(int64_t)bin * n + i] += cnt;
+        if (minutes) minutes[(int64_t)bin * n + i] += mins * scale;
+    }
+}
+
+// ------------------------------------------------------------------ accrual
+struct SpillArgs {
+    int4 *out;          // queue to push to
+    uint32_t *counter;  // its length
+    uint32_t *overflow;
+    int32_t cap;
+};
+
+__device__ __forceinline__ void spill_push(const SpillArgs &S, bool want, int64_t i, int j, float w0, float w1)
+{
+    if (!want) return;
+    const uint32_t slot = atomicAdd(S.counter, 1u);
+    if ((int32_t)slot < S.cap)
+        S.out[slot] = make_int4((int)i, j, __float_as_int(w0), __float_as_int(w1));
+    else
+        atomicOr(S.overflow, 1u);
+}
+
+// Measure and sample count of the occluded set of one point over the
+// window [w0, w1] of segment g.  `last_window` says whether w1 is the end
+// of the segment (instants at the window end belong to the next window
+// otherwise).
+__device__ __forceinline__ void measure(const Union4 &U, const SegConst &g, float w0, float w1,
+                                        bool last_window, float &mins, int &cnt)
+{
+    const float scale = g.dt / g.theta;
+    float m = 0.f;
+    int c = 0;
+    const float inv_step = 1.0f / g.step;
+    int kmax = g.ns - 1;
+    if (!last_window) kmax = min(kmax, (int)ceilf((w1 * scale - g.s0) * inv_step) - 1);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (r < U.n) {
+            m += U.hi[r] - U.lo[r];
+            const int klo = max((int)ceilf((U.lo[r] * scale - g.s0) * inv_step), 0);
+            const int khi = min((int)floorf((U.hi[r] * scale - g.s0) * inv_step), kmax);
+            c += max(khi - klo + 1, 0);
+        }
+    }
+    mins += m * scale;
+    cnt += c;
+}
+
+// The occluded set of every live lane's point over its window of segment g:
+// back-face term, then the packet fan traversal.  On return `ov` marks
+// lanes whose set needed more than four pieces.
+__device__ __forceinline__ void accrue_segment(cNode *nodes, int *stack, cfloat4 *verts, cfloat *height,
+                                               const SegConst &g,
+                                               const LanePoint &q, bool active, float w0, float w1,
+                                               Union4 &U, bool &ov)
+{
+    union_clear(U);
+    ov = false;
+    if (!active) return;
+    const float W0u = cosf(w0), W0v = sinf(w0), W1u = cosf(w1), W1v = sinf(w1);
+    bool live = true;
+    if (q.own >= 0) {
+        float a, b;
+        if (backface_interval(q.nx, q.ny, g, w0, w1, a, b)) {
+            union_insert(U, a, b);
+            live = !(a <= w0 && b >= w1);
+        }
+    }
+    if (nodes == nullptr) return;
+    // fan below height z1: the triangle p, p + (z1-pz) ua, p + (z1-pz) ub
+    const float umnx = fminf(0.f, fminf(g.ua_x, g.ub_x)), umxx = fmaxf(0.f, fmaxf(g.ua_x, g.ub_x));
+    const float umny = fminf(0.f, fminf(g.ua_y, g.ub_y)), umxy = fmaxf(0.f, fmaxf(g.ua_y, g.ub_y));
+    // inward normals of the three triangle edges
+    float nax = -g.ua_y, nay = g.ua_x;
+    if (fmaf(nax, g.ub_x, nay * g.ub_y) < 0.f) { nax = -nax; nay = -nay; }
+    float nbx = -g.ub_y, nby = g.ub_x;
+    if (fmaf(nbx, g.ua_x, nby * g.ua_y) < 0.f) { nbx = -nbx; nby = -nby; }
+    float ncx = -(g.ub_y - g.ua_y), ncy = g.ub_x - g.ua_x;
+    if (fmaf(ncx, g.ua_x, ncy * g.ua_y) > 0.f) { ncx = -ncx; ncy = -ncy; }
+    const float kc = fmaf(ncx, g.ua_x, ncy * g.ua_y);  // <= 0
+    const float naP = fmaf(nax, q.px, nay * q.py), nbP = fmaf(nbx, q.px, nby * q.py);
+    const float ncP = fmaf(ncx, q.px, ncy * q.py);
+    auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
+        const float ra = z1 - q.pz;
+        const bool bb = ra >= 0.f && x1 >= fmaf(ra, umnx, q.px) && x0 <= fmaf(ra, umxx, q.px) &&
+                        y1 >= fmaf(ra, umny, q.py) && y0 <= fmaf(ra, umxy, q.py);
+        const float cx = 0.5f * (x0 + x1), cy = 0.5f * (y0 + y1);
+        const float hx = 0.5f * (x1 - x0), hy = 0.5f * (y1 - y0);
+        const bool sa = fmaf(nax, cx, nay * cy) + fmaf(fabsf(nax), hx, fabsf(nay) * hy) >= naP;
+        const bool sb = fmaf(nbx, cx, nby * cy) + fmaf(fabsf(nbx), hx, fabsf(nby) * hy) >= nbP;
+        const bool sc = fmaf(ncx, cx, ncy * cy) + fmaf(fabsf(ncx), hx, fabsf(ncy) * hy) >= fmaf(ra, kc, ncP);
+        return bb && sa && sb && sc;
+    };
+    auto leaf = [&](int prim, int voff, int m, bool want) {
+        const bool go = want && prim != q.own;
+        if (!ballot(go)) return;
+        float a = 0.f, b = 0.f;
+        const int r = go ? prism_interval(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, w0, w1, W0u, W0v,
+                                          W1u, W1v, a, b)
+                         : 0;
+        if (r) {
+            if (!union_insert(U, a, b)) {
+                ov = true;
+                live = false;
+            } else if (U.n == 1 && U.lo[0] <= w0 && U.hi[0] >= w1) {
+                live = false;  // the whole window is in shadow
+            }
+        }
+    };
+    const float mdx = g.e1x + g.e2x * 0.5f * g.theta, mdy = g.e1y + g.e2y * 0.5f * g.theta;
+    auto key = [&](float x0, float y0, float x1, float y1, float z1) {
+        return fmaf(x0 + x1, mdx, (y0 + y1) * mdy);
+    };
+    packet_traverse(nodes, stack, live, bt, leaf, key);
+}
+
+// Roof-covered: inside a footprint (other than the point's own building)
+// and not above that roof -- shadowed from every direction.
+__device__ __forceinline__ bool roof_covered(cNode *nodes, int *stack, cfloat4 *verts, cfloat *height,
+                                             const LanePoint &q, bool valid)
+{
+    bool live = valid, cov = false;
+    if (nodes == nullptr) return false;
+    auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
+        return q.px >= x0 && q.px <= x1 && q.py >= y0 && q.py <= y1 && q.pz <= z1;
+    };
+    auto leaf = [&](int prim, int voff, int m, bool want) {
+        const bool t = want && prim != q.own && q.pz <= ld(height + prim) && in_footprint(verts, voff, m, q.px, q.py);
+        cov = cov || t;
+        live = live && !t;
+    };
+    auto key = [&](float, float, float, float, float) { return 0.f; };
+    packet_traverse(nodes, stack, live, bt, leaf, key);
+    return cov;
+}
+
+__global__ __launch_bounds__(kThreads) void k_accrual(const Node *nodes_g, const float4 *verts_g,
+                                                      const float *height_g, const SegConst *segs_g, int J,
+                                                      PointArgs P, float scale, int32_t *counts, float *minutes,
+                                                      SpillArgs S)
+{
+    cNode *nodes = (cNode *)nodes_g;
+    cfloat4 *verts = (cfloat4 *)verts_g;
+    cfloat *height = (cfloat *)height_g;
+    cSeg *segs = (cSeg *)segs_g;
+    __shared__ int s_stack[kWaves][kStackDepth];
+    int *stack = s_stack[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
+    const int64_t i = wave * 64 + lane;
+    const bool valid = i < P.n;
+    const int64_t n = P.n;
+    const LanePoint q = load_point(P, i, valid);
+    const bool covered = roof_covered(nodes_g ? nodes : nullptr, stack, verts, height, q, valid);
+
+    int cnt = 0;
+    float mins = 0.f;
+    int bin = J > 0 ? ld(segs).bin : 0;
+    for (int j = 0; j < J; ++j) {
+        const SegConst g = ld(segs + j);
+        if (g.bin != bin) {
+            if (valid) {
+                if (counts) counts[(int64_t)bin * n + i] += cnt;
+                if (minutes) minutes[(int64_t)bin * n + i] += mins * scale;
+            }
+            cnt = 0;
+            mins = 0.f;
+            bin = g.bin;
+        }
+        Union4 U;
+        bool ov;
+        accrue_segment(nodes_g ? nodes : nullptr, stack, verts, height, g, q, valid && !covered, 0.f, g.theta, U,
+                       ov);
+        if (covered && valid) {
+            mins += g.dt;
+            cnt += g.ns;
+        } else if (!ov) {
+            measure(U, g, 0.f, g.theta, true, mins, cnt);
+        }
+        spill_push(S, valid && ov, i, j, 0.f, g.theta);
+    }
+    if (valid && J > 0) {
+        if (counts) counts[(int64_t)bin * n + i] += cnt;
+        if (minutes) minutes[(int64_t)bin * n + i] += mins * scale;
+    }
+}
+
+// One spill round: every queued (point, segment, window) is split in two
+// halves; each half is one lane.  Results are added atomically; halves
+// that still overflow go to the next queue.
+__global__ __launch_bounds__(kThreads) void k_spill(const Node *nodes_g, const float4 *verts_g,
+                                                    const float *height_g, const SegConst *segs_g, PointArgs P,
+                                                    float scale, int32_t *counts, float *minutes, const int4 *in,
+                                                    const uint32_t *in_count, int32_t cap, SpillArgs S)
+{
+    cNode *nodes = (cNode *)nodes_g;
+    cfloat4 *verts = (cfloat4 *)verts_g;
+    cfloat *height = (cfloat *)height_g;
+    __shared__ int s_stack[kWaves][kStackDepth];
+    int *stack = s_stack[threadIdx.x >> 6];
+    const int64_t total = 2 * (int64_t)min((int32_t)*in_count, cap);
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < total; base += stride) {
+        const int64_t t = base + threadIdx.x;
+        const bool valid = t < total;
+        int4 e = valid ? in[t >> 1] : make_int4(0, 0, 0, 0);
+        const int64_t i = e.x;
+        const int j = e.y;
+        const float ew0 = __int_as_float(e.z), ew1 = __int_as_float(e.w);
+        const float mid = 0.5f * (ew0 + ew1);
+        const float w0 = (t & 1) ? mid : ew0, w1 = (t & 1) ? ew1 : mid;
+        const LanePoint q = load_point(P, i, valid);
+        const SegConst g = segs_g[valid ? j : 0];
+        Union4 U;
+        bool ov;
+        accrue_segment(nodes_g ? nodes : nullptr, stack, verts, height, g, q, valid, w0, w1, U, ov);
+        if (valid && !ov) {
+            float mins = 0.f;
+            int cnt = 0;
+            measure(U, g, w0, w1, w1 >= g.theta, mins, cnt);
+            const int64_t o = (int64_t)g.bin * P.n + i;
+            if (minutes) atomicAdd(&minutes[o], mins * scale);
+            if (counts) atomicAdd(&counts[o], cnt);
+        }
+        spill_push(S, valid && ov, i, j, w0, w1);
+    }
+}
+
+__global__ void k_zero_u32(uint32_t *p) { *p = 0u; }
+
+__global__ void k_spill_check(const uint32_t *count, uint32_t *overflow)
+{
+    if (*count) atomicOr(overflow, 2u);
+}
+
+}  // namespace
+
+#define SA_CHECK_LAUNCH(what)                                                   \
+    do {                                                                        \
+        hipError_t e_ = hipGetLastError();                                      \
+        if (e_ != hipSuccess) {                                                 \
+            err = std::string(what) + ": " + hipGetErrorString(e_);             \
+            return SA_ERR_DEVICE;                                               \
+        }                                                                       \
+    } while (0)
+
+static PointArgs point_args(const PointsView &pts, const DeviceScene &s)
+{
+    return PointArgs{pts.n, pts.x, pts.y, pts.z, pts.nx, pts.ny, pts.owner, s.rank, s.n_b};
+}
+
+sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
+                         int32_t *counts, float *minutes, uint32_t *bits, hipStream_t st, std::string &err)
+{
+    if (pts.n == 0) return SA_OK;
+    const int64_t waves = (pts.n + 63) / 64;
+    const int64_t grid = (waves + kWaves - 1) / kWaves;
+    if (grid > INT32_MAX) {
+        err = "too many points";
+        return SA_ERR_INVALID_ARG;
+    }
+    const Node *nodes = s.n_b > 0 ? s.nodes : nullptr;
+    if (bits)
+        hipLaunchKernelGGL(k_sampled<true>, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, s.verts, s.height,
+                           p.samples, p.n_samples, point_args(pts, s), scale, counts, minutes, bits);
+    else
+        hipLaunchKernelGGL(k_sampled<false>, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, s.verts,
+                           s.height, p.samples, p.n_samples, point_args(pts, s), scale, counts, minutes, bits);
+    SA_CHECK_LAUNCH("sampled kernel");
+    return SA_OK;
+}
+
+sa_status run_spill(const DeviceScene &s, const DevicePath &p, const PointArgs &P, float scale, int32_t *counts,
+                    float *minutes, SpillQueue &q, hipStream_t st, std::string &err)
+{
+    const Node *nodes = s.n_b > 0 ? s.nodes : nullptr;
+    int cur = 0;
+    for (int r = 0; r < kSpillRounds; ++r) {
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters + (cur ^ 1));
+        SpillArgs S{q.entries[cur ^ 1], q.counters + (cur ^ 1), q.counters + 2, q.capacity};
+        hipLaunchKernelGGL(k_spill, dim3(kSpillBlocks), dim3(kThreads), 0, st, nodes, s.verts, s.height, p.segs, P,
+                           scale, counts, minutes, (const int4 *)q.entries[cur], (const uint32_t *)(q.counters + cur),
+                           q.capacity, S);
+        cur ^= 1;
+    }
+    // anything still queued after the last round is unfinished work
+    hipLaunchKernelGGL(k_spill_check, dim3(1), dim3(1), 0, st, (const uint32_t *)(q.counters + cur), q.counters + 2);
+    SA_CHECK_LAUNCH("accrual spill");
+    return SA_OK;
+}
+
+sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
+                         int32_t *counts, float *minutes, SpillQueue &q, hipStream_t st, std::string &err)
+{
+    if (pts.n == 0) return SA_OK;
+    const int64_t waves = (pts.n + 63) / 64;
+    const int64_t grid = (waves + kWaves - 1) / kWaves;
+    const Node *nodes = s.n_b > 0 ? s.nodes : nullptr;
+    const PointArgs P = point_args(pts, s);
+    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters);
+    SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
+    hipLaunchKernelGGL(k_accrual, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, s.verts, s.height, p.segs,
+                       p.n_segs, P, scale, counts, minutes, S);
+    SA_CHECK_LAUNCH("accrual kernel");
+    return run_spill(s, p, P, scale, counts, minutes, q, st, err);
+}
+
+}  // namespace sa

@@ -1,0 +1,490 @@
+// C entry points of libsa: argument checking, object lifetimes, path
+// preparation, and dispatch to the device code.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "sa_internal.h"
+
+struct sa_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    sa::SpillQueue spill;
+    sa::Scratch scratch;
+};
+
+struct sa_scene {
+    sa_ctx *ctx = nullptr;
+    sa::DeviceScene d;
+    std::vector<int32_t> rank_h;  // original id -> hierarchy position
+};
+
+struct sa_path {
+    sa_ctx *ctx = nullptr;
+    sa::DevicePath d;
+};
+
+namespace {
+
+constexpr int32_t kSpillCapacity = 1 << 20;
+
+sa_status fail(sa_ctx *ctx, sa_status rc, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    return rc;
+}
+
+sa_status hip_fail(sa_ctx *ctx, hipError_t e, const char *what)
+{
+    return fail(ctx, e == hipErrorOutOfMemory ? SA_ERR_OOM : SA_ERR_DEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool set_device(sa_ctx *ctx)
+{
+    return hipSetDevice(ctx->device) == hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *sa_version(void) { return "libsa 0.1 (gfx950)"; }
+
+sa_status sa_create(int32_t device, void *hip_stream, sa_ctx **out)
+{
+    if (!out) return SA_ERR_INVALID_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return SA_ERR_DEVICE;
+    if (hipSetDevice(device) != hipSuccess) return SA_ERR_DEVICE;
+    sa_ctx *c = new (std::nothrow) sa_ctx();
+    if (!c) return SA_ERR_OOM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->spill.capacity = kSpillCapacity;
+    if (hipMalloc((void **)&c->spill.entries[0], sizeof(int4) * kSpillCapacity) != hipSuccess ||
+        hipMalloc((void **)&c->spill.entries[1], sizeof(int4) * kSpillCapacity) != hipSuccess ||
+        hipMalloc((void **)&c->spill.counters, sizeof(uint32_t) * 4) != hipSuccess ||
+        hipMemset(c->spill.counters, 0, sizeof(uint32_t) * 4) != hipSuccess) {
+        sa_destroy(c);
+        return SA_ERR_OOM;
+    }
+    *out = c;
+    return SA_OK;
+}
+
+void sa_destroy(sa_ctx *ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipFree(ctx->spill.entries[0]);
+    (void)hipFree(ctx->spill.entries[1]);
+    (void)hipFree(ctx->spill.counters);
+    (void)hipFree(ctx->scratch.ptr);
+    delete ctx;
+}
+
+sa_status sa_set_stream(sa_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return SA_ERR_INVALID_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return SA_OK;
+}
+
+const char *sa_last_error(const sa_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+sa_status sa_sync(sa_ctx *ctx)
+{
+    if (!ctx) return SA_ERR_INVALID_ARG;
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stream synchronize");
+    uint32_t flag = 0;
+    e = hipMemcpy(&flag, ctx->spill.counters + 2, sizeof(uint32_t), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "read spill flag");
+    if (flag) {
+        (void)hipMemset(ctx->spill.counters + 2, 0, sizeof(uint32_t));
+        return fail(ctx, SA_ERR_CAPACITY,
+                    (flag & 1u) ? "accrual spill queue overflowed: results incomplete"
+                                : "accrual spill rounds exhausted: results incomplete");
+    }
+    return SA_OK;
+}
+
+// ------------------------------------------------------------------ scene
+sa_status sa_scene_upload(sa_ctx *ctx, int32_t n_b, const int32_t *vert_off, const float *xy,
+                          const float *height, sa_scene **out)
+{
+    if (!ctx || !out) return SA_ERR_INVALID_ARG;
+    *out = nullptr;
+    if (n_b < 0 || (n_b > 0 && (!vert_off || !xy || !height)))
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_scene_upload: bad arguments");
+    if (n_b > 0 && vert_off[0] != 0) return fail(ctx, SA_ERR_INVALID_ARG, "sa_scene_upload: vert_off[0] != 0");
+    for (int32_t b = 0; b < n_b; ++b) {
+        const int32_t o = vert_off[b], m = vert_off[b + 1] - o;
+        if (m < 3) return fail(ctx, SA_ERR_GEOMETRY, "prism " + std::to_string(b) + ": fewer than 3 vertices");
+        if (!(height[b] > 0.f) || !std::isfinite(height[b]))
+            return fail(ctx, SA_ERR_GEOMETRY, "prism " + std::to_string(b) + ": height must be > 0");
+        for (int32_t i = 0; i < m; ++i) {
+            const double ax = xy[2 * (o + i)], ay = xy[2 * (o + i) + 1];
+            const int32_t i1 = (i + 1) % m, i2 = (i + 2) % m;
+            const double bx = xy[2 * (o + i1)], by = xy[2 * (o + i1) + 1];
+            const double cx = xy[2 * (o + i2)], cy = xy[2 * (o + i2) + 1];
+            if (!std::isfinite(ax) || !std::isfinite(ay))
+                return fail(ctx, SA_ERR_GEOMETRY, "prism " + std::to_string(b) + ": non-finite vertex");
+            if ((bx - ax) * (cy - by) - (by - ay) * (cx - bx) <= 0.0)
+                return fail(ctx, SA_ERR_GEOMETRY,
+                            "prism " + std::to_string(b) + ": footprint not strictly convex and counter-clockwise");
+        }
+    }
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    sa_scene *s = new (std::nothrow) sa_scene();
+    if (!s) return fail(ctx, SA_ERR_OOM, "host allocation failed");
+    s->ctx = ctx;
+    std::string err;
+    sa_status rc = sa::scene_build(s->d, ctx->stream, n_b, vert_off, xy, height, err);
+    if (rc != SA_OK) {
+        delete s;
+        return fail(ctx, rc, "sa_scene_upload: " + err);
+    }
+    s->rank_h.resize(n_b);
+    if (n_b > 0) {
+        hipError_t e = hipMemcpy(s->rank_h.data(), s->d.rank, sizeof(int32_t) * n_b, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) {
+            sa::scene_free(s->d);
+            delete s;
+            return hip_fail(ctx, e, "sa_scene_upload: rank copy");
+        }
+    }
+    *out = s;
+    return SA_OK;
+}
+
+sa_status sa_scene_set_heights(sa_ctx *ctx, sa_scene *scene, int32_t n, const int32_t *ids, const float *h)
+{
+    if (!ctx || !scene || n < 0 || (n > 0 && (!ids || !h)))
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_scene_set_heights: bad arguments");
+    if (n == 0) return SA_OK;
+    std::vector<int32_t> pos(n);
+    for (int32_t k = 0; k < n; ++k) {
+        if (ids[k] < 0 || ids[k] >= scene->d.n_b)
+            return fail(ctx, SA_ERR_INVALID_ARG, "sa_scene_set_heights: building id out of range");
+        if (!(h[k] > 0.f) || !std::isfinite(h[k])) return fail(ctx, SA_ERR_GEOMETRY, "height must be > 0");
+        pos[k] = scene->rank_h[ids[k]];
+    }
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    // heights are few: scatter them with small copies, then refit on device
+    for (int32_t k = 0; k < n; ++k) {
+        hipError_t e = hipMemcpyAsync(scene->d.height + pos[k], h + k, sizeof(float), hipMemcpyHostToDevice,
+                                      ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "sa_scene_set_heights: copy");
+    }
+    std::string err;
+    sa_status rc = sa::scene_refit(scene->d, ctx->stream, err);
+    if (rc != SA_OK) return fail(ctx, rc, "sa_scene_set_heights: " + err);
+    float mh = 0.f;
+    for (int32_t k = 0; k < n; ++k) mh = std::max(mh, h[k]);
+    scene->d.max_h = std::max(scene->d.max_h, mh);
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sa_scene_set_heights");
+    return SA_OK;
+}
+
+sa_status sa_scene_get_info(const sa_scene *scene, sa_scene_info *out)
+{
+    if (!scene || !out) return SA_ERR_INVALID_ARG;
+    out->n_b = scene->d.n_b;
+    out->n_vert = scene->d.n_vert;
+    out->n_nodes = scene->d.n_nodes;
+    out->depth = scene->d.depth;
+    for (int i = 0; i < 4; ++i) out->bounds[i] = scene->d.bounds[i];
+    out->max_height = scene->d.max_h;
+    return SA_OK;
+}
+
+sa_status sa_scene_read_bvh(sa_ctx *ctx, const sa_scene *scene, void *nodes, int32_t *prim_order)
+{
+    if (!ctx || !scene) return SA_ERR_INVALID_ARG;
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess && nodes && scene->d.n_nodes > 0)
+        e = hipMemcpy(nodes, scene->d.nodes, sizeof(sa::Node) * scene->d.n_nodes, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && prim_order && scene->d.n_b > 0)
+        e = hipMemcpy(prim_order, scene->d.order, sizeof(int32_t) * scene->d.n_b, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sa_scene_read_bvh");
+    return SA_OK;
+}
+
+void sa_scene_destroy(sa_scene *scene)
+{
+    if (!scene) return;
+    (void)hipSetDevice(scene->ctx->device);
+    sa::scene_free(scene->d);
+    delete scene;
+}
+
+// ------------------------------------------------------------------ paths
+sa_status sa_sunpath(const sa_site *site, const sa_timespan *span, sa_sunpath_buf *out)
+{
+    if (!site || !span || !out) return SA_ERR_INVALID_ARG;
+    const bool sizing = out->cap_days == 0 && out->cap_samples == 0 && out->cap_knots == 0;
+    if (!sizing && (!out->day_sample_off || !out->t_min || !out->dir || !out->weight || !out->day_knot_off ||
+                    !out->knot_t || !out->knot_dir))
+        return SA_ERR_INVALID_ARG;
+    std::string err;
+    return sa::sunpath_fill(*site, *span, *out, err);
+}
+
+sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
+{
+    if (!ctx || !in || !out) return SA_ERR_INVALID_ARG;
+    *out = nullptr;
+    const int D = in->n_days;
+    if (D < 1 || in->n_samples < 0 || in->n_knots < 0 || !in->day_sample_off || !in->day_knot_off ||
+        (in->n_samples > 0 && (!in->t_min || !in->dir || !in->weight)) ||
+        (in->n_knots > 0 && (!in->knot_t || !in->knot_dir)))
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload: bad arguments");
+    std::vector<sa::SampleConst> samples(in->n_samples);
+    std::vector<sa::SegConst> segs;
+    int n_bins = 0;
+    for (int d = 0; d < D; ++d) {
+        const int bin = in->day_bin ? in->day_bin[d] : d;
+        if (bin < 0) return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload: negative bin");
+        n_bins = std::max(n_bins, bin + 1);
+        const int s0 = in->day_sample_off[d], s1 = in->day_sample_off[d + 1];
+        const int k0 = in->day_knot_off[d], k1 = in->day_knot_off[d + 1];
+        if (s0 < 0 || s1 < s0 || s1 > in->n_samples || k0 < 0 || k1 < k0 || k1 > in->n_knots)
+            return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload: bad day offsets");
+        for (int k = s0; k < s1; ++k) {
+            const double *dd = in->dir + 3 * k;
+            if (!(dd[2] > 0.0)) return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload: sun below the horizon");
+            sa::SampleConst &c = samples[k];
+            c.dx = (float)dd[0];
+            c.dy = (float)dd[1];
+            c.dz = (float)dd[2];
+            c.w = (float)in->weight[k];
+            auto inv = [](float v) { return 1.0f / (std::fabs(v) < 1e-20f ? std::copysign(1e-20f, v) : v); };
+            c.ix = inv(c.dx);
+            c.iy = inv(c.dy);
+            c.iz = inv(c.dz);
+            c.bin = bin;
+        }
+        const double step = s1 - s0 >= 2 ? in->t_min[s0 + 1] - in->t_min[s0] : 1.0;
+        for (int k = k0; k + 1 < k1; ++k) {
+            const double ta = in->knot_t[k], tb = in->knot_t[k + 1];
+            if (!(tb > ta)) return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload: knots not increasing");
+            const double *a = in->knot_dir + 3 * k, *b = in->knot_dir + 3 * (k + 1);
+            if (!(a[2] > 0.0) || !(b[2] > 0.0))
+                return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload: knot below the horizon");
+            const double c = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+            const double cr[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+            const double sn = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+            const double theta = std::atan2(sn, c);
+            if (!(sn > 1e-12)) return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload: coincident knot directions");
+            double e2[3] = {b[0] - c * a[0], b[1] - c * a[1], b[2] - c * a[2]};
+            const double l2 = std::sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+            for (double &v : e2) v /= l2;
+            const double N[3] = {a[1] * e2[2] - a[2] * e2[1], a[2] * e2[0] - a[0] * e2[2],
+                                 a[0] * e2[1] - a[1] * e2[0]};
+            if (std::fabs(N[2]) < std::sin(3.0 * M_PI / 180.0))
+                return fail(ctx, SA_ERR_UNSUPPORTED, "sa_path_upload: a segment plane is within 3 deg of vertical");
+            const double cx = N[0] / N[2], cy = N[1] / N[2];
+            sa::SegConst g;
+            std::memset(&g, 0, sizeof(g));
+            g.m00 = (float)(a[0] - a[2] * cx);
+            g.m01 = (float)(a[1] - a[2] * cy);
+            g.m10 = (float)(e2[0] - e2[2] * cx);
+            g.m11 = (float)(e2[1] - e2[2] * cy);
+            g.e1z = (float)a[2];
+            g.e2z = (float)e2[2];
+            g.theta = (float)theta;
+            g.dt = (float)(tb - ta);
+            g.ta = (float)ta;
+            g.cth = (float)std::cos(theta);
+            g.sth = (float)std::sin(theta);
+            g.nx = (float)N[0];
+            g.ny = (float)N[1];
+            g.nz = (float)N[2];
+            g.bin = bin;
+            g.day = d;
+            g.e1x = (float)a[0];
+            g.e1y = (float)a[1];
+            g.e2x = (float)e2[0];
+            g.e2y = (float)e2[1];
+            g.ua_x = (float)(a[0] / a[2]);
+            g.ua_y = (float)(a[1] / a[2]);
+            g.ub_x = (float)(b[0] / b[2]);
+            g.ub_y = (float)(b[1] / b[2]);
+            // sample instants attributed to this segment: [ta, tb), the day's
+            // last segment also takes tb
+            const bool last = k + 2 == k1;
+            int first = -1, ns = 0;
+            for (int s = s0; s < s1; ++s) {
+                const double t = in->t_min[s];
+                if (t >= ta && (t < tb || (last && t <= tb))) {
+                    if (first < 0) first = s;
+                    ++ns;
+                }
+            }
+            g.s0 = first >= 0 ? (float)(in->t_min[first] - ta) : 0.f;
+            g.step = (float)step;
+            g.ns = ns;
+            segs.push_back(g);
+        }
+    }
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    sa_path *p = new (std::nothrow) sa_path();
+    if (!p) return fail(ctx, SA_ERR_OOM, "host allocation failed");
+    p->ctx = ctx;
+    p->d.n_days = D;
+    p->d.n_samples = in->n_samples;
+    p->d.n_segs = (int32_t)segs.size();
+    p->d.n_bins = n_bins;
+    p->d.words = (in->n_samples + 31) / 32;
+    hipError_t e = hipSuccess;
+    if (!samples.empty()) {
+        e = hipMalloc((void **)&p->d.samples, sizeof(sa::SampleConst) * samples.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d.samples, samples.data(), sizeof(sa::SampleConst) * samples.size(),
+                          hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && !segs.empty()) {
+        e = hipMalloc((void **)&p->d.segs, sizeof(sa::SegConst) * segs.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d.segs, segs.data(), sizeof(sa::SegConst) * segs.size(), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) {
+        sa_path_destroy(p);
+        return hip_fail(ctx, e, "sa_path_upload");
+    }
+    *out = p;
+    return SA_OK;
+}
+
+sa_status sa_path_info(const sa_path *path, int32_t *n_bins, int32_t *n_samples, int32_t *n_segments)
+{
+    if (!path) return SA_ERR_INVALID_ARG;
+    if (n_bins) *n_bins = path->d.n_bins;
+    if (n_samples) *n_samples = path->d.n_samples;
+    if (n_segments) *n_segments = path->d.n_segs;
+    return SA_OK;
+}
+
+void sa_path_destroy(sa_path *path)
+{
+    if (!path) return;
+    (void)hipSetDevice(path->ctx->device);
+    (void)hipFree(path->d.samples);
+    (void)hipFree(path->d.segs);
+    delete path;
+}
+
+// ------------------------------------------------------------------ accumulate
+static sa_status check_points(sa_ctx *ctx, const sa_points *pts)
+{
+    if (!pts || pts->n < 0 || (pts->n > 0 && (!pts->x || !pts->y || !pts->z)))
+        return fail(ctx, SA_ERR_INVALID_ARG, "bad points");
+    if (pts->n > (int64_t)INT32_MAX) return fail(ctx, SA_ERR_INVALID_ARG, "more than 2^31-1 points");
+    return SA_OK;
+}
+
+static sa::PointsView view(const sa_points *p)
+{
+    return sa::PointsView{p->n, p->x, p->y, p->z, p->nx, p->ny, p->owner};
+}
+
+static sa_status clear_outputs(sa_ctx *ctx, uint32_t flags, int64_t count, int32_t *counts, float *minutes)
+{
+    if (flags & SA_FLAG_ADD) return SA_OK;
+    hipError_t e = hipSuccess;
+    if (counts) e = hipMemsetAsync(counts, 0, sizeof(int32_t) * count, ctx->stream);
+    if (e == hipSuccess && minutes) e = hipMemsetAsync(minutes, 0, sizeof(float) * count, ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "clear outputs");
+    return SA_OK;
+}
+
+sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts, const sa_path *path,
+                        const sa_accum_opts *opts, int32_t *counts, float *minutes, uint32_t *bits)
+{
+    if (!ctx) return SA_ERR_INVALID_ARG;
+    if (!scene || !path || !opts) return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate: null argument");
+    sa_status rc = check_points(ctx, pts);
+    if (rc != SA_OK) return rc;
+    if (opts->mode != SA_SAMPLED && opts->mode != SA_ACCRUAL)
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate: unknown mode");
+    if (bits && opts->mode != SA_SAMPLED)
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate: bit vectors exist for the sampled form only");
+    if (!counts && !minutes && !bits) return SA_OK;
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    const float scale = opts->out_scale == 0.f ? 1.f : opts->out_scale;
+    rc = clear_outputs(ctx, opts->flags, (int64_t)path->d.n_bins * pts->n, counts, minutes);
+    if (rc != SA_OK) return rc;
+    std::string err;
+    if (opts->mode == SA_SAMPLED)
+        rc = sa::launch_sampled(scene->d, path->d, view(pts), scale, counts, minutes, bits, ctx->stream, err);
+    else
+        rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, ctx->spill, ctx->stream,
+                                err);
+    if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate: " + err);
+    return SA_OK;
+}
+
+sa_status sa_accumulate_batched(sa_ctx *ctx, const sa_scene *scene, int32_t n_var, int32_t ids_per_var,
+                                const int32_t *var_ids, const float *var_h, const sa_points *pts,
+                                const int64_t *var_off, const sa_path *path, const sa_accum_opts *opts,
+                                int32_t *counts, float *minutes)
+{
+    if (!ctx) return SA_ERR_INVALID_ARG;
+    if (!scene || !path || !opts || n_var < 0 || ids_per_var < 0 || !var_off ||
+        (n_var > 0 && ids_per_var > 0 && (!var_ids || !var_h)))
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate_batched: bad arguments");
+    if (opts->mode != SA_ACCRUAL) return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate_batched: accrual form only");
+    sa_status rc = check_points(ctx, pts);
+    if (rc != SA_OK) return rc;
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    const float scale = opts->out_scale == 0.f ? 1.f : opts->out_scale;
+    rc = clear_outputs(ctx, opts->flags, (int64_t)path->d.n_bins * pts->n, counts, minutes);
+    if (rc != SA_OK) return rc;
+    std::string err;
+    rc = sa::launch_batched(scene->d, path->d, n_var, ids_per_var, var_ids, var_h, view(pts), var_off, scale,
+                            counts, minutes, ctx->spill, ctx->scratch, ctx->stream, err);
+    if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate_batched: " + err);
+    return SA_OK;
+}
+
+sa_status sa_grad_heights(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts, const sa_path *path,
+                          const float *dl_dmin, float *grad)
+{
+    if (!ctx) return SA_ERR_INVALID_ARG;
+    if (!scene || !path || !grad) return fail(ctx, SA_ERR_INVALID_ARG, "sa_grad_heights: null argument");
+    sa_status rc = check_points(ctx, pts);
+    if (rc != SA_OK) return rc;
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    std::string err;
+    rc = sa::launch_grad(scene->d, path->d, view(pts), dl_dmin, grad, ctx->stream, err);
+    if (rc != SA_OK) return fail(ctx, rc, "sa_grad_heights: " + err);
+    return SA_OK;
+}
+
+sa_status sa_region_sum(sa_ctx *ctx, const float *values, int64_t n, const int64_t *region_off, int32_t n_reg,
+                        const float *area, double *out)
+{
+    if (!ctx) return SA_ERR_INVALID_ARG;
+    if (n < 0 || n_reg < 0 || (n_reg > 0 && (!region_off || !out)) || (n > 0 && !values))
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_region_sum: bad arguments");
+    if (n_reg == 0) return SA_OK;
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    std::string err;
+    sa_status rc = sa::launch_region_sum(values, n, region_off, n_reg, area, out, ctx->stream, err);
+    if (rc != SA_OK) return fail(ctx, rc, "sa_region_sum: " + err);
+    return SA_OK;
+}
+
+}  // extern "C"

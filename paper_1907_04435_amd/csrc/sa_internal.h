@@ -1,0 +1,127 @@
+// Internal types shared by the library's host and device sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/shadow_accrual.h"
+
+namespace sa {
+
+// One interior node of the binary hierarchy: the boxes of both children
+// (footprint-plane box x0,y0,x1,y1 and the top z1; every box starts at
+// z = 0 because every prism stands on the ground) and the child
+// references: >= 0 an interior node, < 0 the leaf ~prim (prism index in
+// hierarchy order).  For leaf children the vertex range of the footprint
+// is stored beside the reference so a leaf costs no extra indirection.
+// 64 bytes: one scalar 16-dword load brings a whole node into SGPRs.
+struct alignas(64) Node {
+    float lx0, ly0, lx1, ly1;
+    float rx0, ry0, rx1, ry1;
+    float lz1, rz1;
+    int32_t left, right;
+    int32_t l_voff, l_m, r_voff, r_m;
+};
+static_assert(sizeof(Node) == 64, "node is one 64-byte line");
+
+// Per sample instant, read uniformly by every lane of a wave.
+struct alignas(32) SampleConst {
+    float dx, dy, dz, w;  // unit direction toward the sun, weight (minutes)
+    float ix, iy, iz;     // 1 / direction (components kept away from zero)
+    int32_t bin;
+};
+
+// Per great-circle segment of the accrual form.  In the segment's plane
+// the direction at angle phi from the first knot is
+// cos(phi) e1 + sin(phi) e2, phi in [0, theta], reached at time
+// t = ta + dt * phi / theta.  An xy offset w from a point maps to the
+// point of the plane above/below it, whose in-plane coordinates are
+// (u, v) = M w and whose height above the point is u * e1z + v * e2z.
+struct alignas(64) SegConst {
+    float m00, m01, m10, m11;    // M
+    float e1z, e2z, theta, dt;   // clip normal (u,v)->z, angle, minutes
+    float ta;                    // start, minutes after local midnight
+    float cth, sth;              // (cos theta, sin theta): end direction in (u, v)
+    float nx, ny, nz;            // plane normal e1 x e2
+    int32_t bin;
+    int32_t day;
+    float e1x, e1y, e2x, e2y;    // horizontal parts of e1, e2 (facade back-face term)
+    float ua_x, ua_y, ub_x, ub_y;  // horizontal offset per metre of rise, at both knots
+    float s0;                    // first sample instant in the segment, minutes after ta
+    float step;                  // sample spacing (minutes)
+    int32_t ns;                  // sample instants attributed to the segment
+    int32_t pad0;
+    float pad1[4];
+};
+static_assert(sizeof(SegConst) == 128, "two lines");
+
+struct DeviceScene {
+    int32_t n_b = 0;
+    int32_t n_vert = 0;
+    int32_t n_nodes = 0;
+    int32_t depth = 0;
+    float bounds[4] = {0, 0, 0, 0};
+    float max_h = 0;
+    Node *nodes = nullptr;       // [n_nodes]
+    float4 *verts = nullptr;     // [n_vert] x, y, edge normal (ey, -ex) in hierarchy order
+    int32_t *voff = nullptr;     // [n_b + 1] hierarchy order
+    float *height = nullptr;     // [n_b] hierarchy order
+    int32_t *order = nullptr;    // [n_b] hierarchy position -> original id
+    int32_t *rank = nullptr;     // [n_b] original id -> hierarchy position
+    int32_t *parent = nullptr;   // [n_nodes + n_b] parent*2+side of interior nodes then leaves
+    int32_t *flags = nullptr;    // [n_nodes] refit arrival counters
+    float4 *pbox = nullptr;      // [n_b] prism footprint boxes, hierarchy order
+};
+
+struct DevicePath {
+    int32_t n_days = 0, n_samples = 0, n_segs = 0, n_bins = 0;
+    SampleConst *samples = nullptr;  // [n_samples]
+    SegConst *segs = nullptr;        // [n_segs]
+    int32_t words = 0;               // ceil(n_samples / 32)
+};
+
+// Host-side builders implemented in the .hip sources.
+sa_status scene_build(DeviceScene &s, hipStream_t st, int32_t n_b, const int32_t *voff,
+                      const float *xy, const float *h, std::string &err);
+sa_status scene_refit(DeviceScene &s, hipStream_t st, std::string &err);
+void scene_free(DeviceScene &s);
+sa_status sunpath_fill(const sa_site &site, const sa_timespan &span, sa_sunpath_buf &out,
+                       std::string &err);
+
+struct PointsView {
+    int64_t n;
+    const float *x, *y, *z, *nx, *ny;
+    const int32_t *owner;
+};
+
+// Scratch owned by a context (grown on demand, freed with it).
+struct Scratch {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct SpillQueue {
+    int4 *entries[2] = {nullptr, nullptr};  // (point, segment, w0 bits, w1 bits)
+    uint32_t *counters = nullptr;           // [0],[1] queue lengths, [2] overflow flag
+    int32_t capacity = 0;
+};
+
+sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
+                         float scale, int32_t *counts, float *minutes, uint32_t *bits,
+                         hipStream_t st, std::string &err);
+sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
+                         float scale, int32_t *counts, float *minutes, SpillQueue &q,
+                         hipStream_t st, std::string &err);
+sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
+                      const float *dl, float *grad, hipStream_t st, std::string &err);
+sa_status launch_region_sum(const float *v, int64_t n, const int64_t *off, int32_t n_reg,
+                            const float *area, double *out, hipStream_t st, std::string &err);
+sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_var, int32_t k,
+                         const int32_t *ids, const float *h, const PointsView &pts,
+                         const int64_t *var_off, float scale, int32_t *counts, float *minutes,
+                         SpillQueue &q, Scratch &scr, hipStream_t st, std::string &err);
+
+}  // namespace sa

@@ -1,0 +1,181 @@
+"""GPU parity: the HIP library against the FP64 CPU oracle on the same
+seeded inputs, through the C ABI.
+
+Bars:
+ * sampled form: per (point, instant) predicate bit-exact except for rays
+   within 1e-5 rad of a silhouette (the oracle's ambiguity mask), which
+   must be at most 1e-4 of all pairs;
+ * accrual form vs the oracle's continuous duration along the same
+   great-circle path: |GPU - oracle| <= 0.01 min for 99.9% of points,
+   mean <= 1e-3 min (float32 geometry against FP64 bisection), and never
+   more than 0.5 min.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1907_04435_amd as sa
+from workloads import Scene, Span, make_c1, make_c2, subset_points
+from workloads.scenes import Day
+
+from gpu_util import check_sampled, run_lib, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return sa.Context(0)
+
+
+@pytest.fixture(scope="module")
+def c2small():
+    return make_c2(n_ground=100_000, n_facade=100_000)
+
+
+def accrual_bar(g, o, label):
+    d = np.abs(g["minutes"] - o["minutes"]).ravel()
+    q999, mean, mx = np.quantile(d, 0.999), d.mean(), d.max()
+    say(f"{label}: |A-D_L| mean {mean:.2e} p99.9 {q999:.2e} max {mx:.2e} min")
+    assert q999 <= 0.01 and mean <= 1e-3 and mx <= 0.5
+
+
+def test_sampled_c1_full(ctx, c1):
+    say("sampled C1 full")
+    g = run_lib(ctx, c1.scene, c1.points, c1.span, sa.SA_SAMPLED, bits=True)
+    o = oracle.sampled(c1.scene, c1.points, oracle.sun_path(c1.span), bits=True, amb=True)
+    frac, nm = check_sampled(g, o, oracle.sun_path(c1.span).w)
+    say(f"  ambiguous fraction {frac:.2e}, mismatched pairs {nm}")
+    assert frac <= 1e-4
+
+
+@pytest.mark.parametrize("seg", [30.0, 60.0])
+def test_accrual_c1(ctx, c1, seg):
+    say(f"accrual C1 seg {seg}")
+    idx = subset_points(c1.points, 2048, seed=5)
+    sub = c1.points.take(idx)
+    g = run_lib(ctx, c1.scene, sub, c1.span, sa.SA_ACCRUAL, seg_min=seg)
+    o = oracle.continuous(c1.scene, sub, oracle.sun_path(c1.span, seg))
+    accrual_bar(g, o, f"C1 L={seg}")
+    # sample instants inside the occluded set: equal except where an end of
+    # the set sits on an instant
+    dc = np.abs(g["counts"] - o["counts"])
+    assert (dc > 0).mean() <= 2e-3 and dc.max() <= 1
+
+
+def test_sampled_c2_subset(ctx, c2small):
+    w = c2small
+    idx = np.concatenate([subset_points(w.points.take(np.arange(100_000)), 192, 1),
+                          100_000 + subset_points(w.points.take(np.arange(100_000, 200_000)), 192, 2)])
+    sub = w.points.take(idx)
+    say("sampled C2 subset", sub.n)
+    g = run_lib(ctx, w.scene, sub, w.span, sa.SA_SAMPLED, bits=True)
+    op = oracle.sun_path(w.span)
+    o = oracle.sampled(w.scene, sub, op, bits=True, amb=True)
+    frac, nm = check_sampled(g, o, op.w)
+    say(f"  ambiguous fraction {frac:.2e}, mismatched pairs {nm}")
+    assert frac <= 1e-4
+
+
+def test_accrual_c2_subset(ctx, c2small):
+    w = c2small
+    idx = np.concatenate([subset_points(w.points.take(np.arange(100_000)), 96, 3),
+                          100_000 + subset_points(w.points.take(np.arange(100_000, 200_000)), 96, 4)])
+    sub = w.points.take(idx)
+    say("accrual C2 subset", sub.n)
+    g = run_lib(ctx, w.scene, sub, w.span, sa.SA_ACCRUAL, seg_min=30.0)
+    o = oracle.continuous(w.scene, sub, oracle.sun_path(w.span, 30.0))
+    accrual_bar(g, o, "C2 L=30")
+
+
+def test_ragged_and_tiny_point_sets(ctx, c1):
+    for n in (1, 63, 65, 200):
+        sub = c1.points.take(np.arange(7, 7 + n * 13, 13))
+        g = run_lib(ctx, c1.scene, sub, c1.span, sa.SA_SAMPLED, bits=True)
+        o = oracle.sampled(c1.scene, sub, oracle.sun_path(c1.span), bits=True, amb=True)
+        check_sampled(g, o, oracle.sun_path(c1.span).w)
+        ga = run_lib(ctx, c1.scene, sub, c1.span, sa.SA_ACCRUAL)
+        oa = oracle.continuous(c1.scene, sub, oracle.sun_path(c1.span, 30.0))
+        assert np.abs(ga["minutes"] - oa["minutes"]).max() <= 0.05
+
+
+def test_zero_points(ctx, c1):
+    sub = c1.points.take(np.arange(0))
+    g = run_lib(ctx, c1.scene, sub, c1.span, sa.SA_SAMPLED)
+    assert g["minutes"].size == 0
+
+
+def test_empty_and_single_building_scenes(ctx, c1):
+    empty = Scene(np.zeros(1, np.int32), np.zeros((0, 2), np.float32), np.zeros(0, np.float32))
+    sub = c1.points.take(np.arange(0, c1.points.n, 101))
+    for mode in (sa.SA_SAMPLED, sa.SA_ACCRUAL):
+        g = run_lib(ctx, empty, sub, c1.span, mode)
+        assert np.all(g["minutes"] == 0) and np.all(g["counts"] == 0)
+    one = c1.scene.subset(np.array([5]))
+    g = run_lib(ctx, one, sub, c1.span, sa.SA_SAMPLED, bits=True)
+    o = oracle.sampled(one, sub, oracle.sun_path(c1.span), bits=True, amb=True)
+    check_sampled(g, o, oracle.sun_path(c1.span).w)
+    ga = run_lib(ctx, one, sub, c1.span, sa.SA_ACCRUAL)
+    oa = oracle.continuous(one, sub, oracle.sun_path(c1.span, 30.0))
+    assert np.abs(ga["minutes"] - oa["minutes"]).max() <= 0.05
+
+
+def test_bvh_structure(ctx, c2small):
+    w = c2small
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    info = sc.info()
+    nodes, order = sc.read_bvh()
+    say("bvh", info)
+    assert info["n_nodes"] == w.scene.n_b - 1 and 1 <= info["depth"] <= 63
+    assert np.array_equal(np.sort(order), np.arange(w.scene.n_b))
+    f = nodes.view(np.float32)
+    # every prism box lies in every box on its path from the root
+    lo = np.minimum.reduceat(w.scene.xy, w.scene.vert_off[:-1], axis=0)
+    hi = np.maximum.reduceat(w.scene.xy, w.scene.vert_off[:-1], axis=0)
+    seen = np.zeros(w.scene.n_b, int)
+    stack = [0]
+    boxes = {0: None}
+    while stack:
+        i = stack.pop()
+        for side, ref in ((0, nodes[i, 10]), (1, nodes[i, 11])):
+            b = f[i, side * 4: side * 4 + 4]
+            z1 = f[i, 8 + side]
+            if ref < 0:
+                prim = order[~ref]
+                assert b[0] <= lo[prim, 0] and b[1] <= lo[prim, 1] and b[2] >= hi[prim, 0] and b[3] >= hi[prim, 1]
+                assert z1 >= w.scene.height[prim]
+                seen[prim] += 1
+            else:
+                stack.append(ref)
+    assert np.all(seen == 1)
+
+
+def test_set_heights_matches_fresh_upload(ctx, c1):
+    """Refit after a height edit gives the same result as uploading the
+    edited scene."""
+    sub = c1.points.take(np.arange(0, c1.points.n, 37))
+    ids = np.array([3, 17, 40])
+    newh = np.array([140.0, 12.0, 99.0], np.float32)
+    edited = Scene(c1.scene.vert_off, c1.scene.xy, c1.scene.height.copy())
+    edited.height[ids] = newh
+    sp = sa.sunpath_for_span(c1.span, 30.0)
+    path = sa.Path(ctx, sp)
+    dp = sa.DevicePoints.from_workload(sub)
+    s1 = sa.Scene.from_workload(ctx, c1.scene)
+    s1.set_heights(ids, newh)
+    s2 = sa.Scene.from_workload(ctx, edited)
+    for mode in (sa.SA_SAMPLED, sa.SA_ACCRUAL):
+        a = sa.accumulate(ctx, s1, dp, path, mode)
+        b = sa.accumulate(ctx, s2, dp, path, mode)
+        ctx.sync()
+        assert np.array_equal(a[0].cpu().numpy(), b[0].cpu().numpy())
+        assert np.array_equal(a[1].cpu().numpy(), b[1].cpu().numpy())
+
+
+def test_invalid_geometry_rejected(ctx):
+    cw = np.array([[0, 0], [0, 10], [10, 10], [10, 0]], np.float32)   # clockwise
+    with pytest.raises(sa.SAError) as e:
+        sa.Scene(ctx, np.array([0, 4], np.int32), cw, np.array([10.0], np.float32))
+    assert e.value.code == -2
+    with pytest.raises(sa.SAError):
+        sa.Scene(ctx, np.array([0, 4], np.int32), cw[::-1].copy(), np.array([-1.0], np.float32))
