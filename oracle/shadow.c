@@ -395,39 +395,103 @@ static void seg_dir_at(const double *da, const double *db, double ta, double tb,
     orc_slerp(da, db, (t - ta) / (tb - ta), d);
 }
 
+/* Does the ray from p along d meet the box of prism b grown by delta on
+ * every side? */
+static int ray_meets_grown_box(const scene64 *S, int b, const double *p, const double *d, double delta)
+{
+    const double *bx = S->box + 4 * b;
+    double g[4] = {bx[0] - delta, bx[1] - delta, bx[2] + delta, bx[3] + delta};
+    double lo = 0.0, hi = INFINITY;
+    double blo[3] = {g[0], g[1], -delta}, bhi[3] = {g[2], g[3], S->H[b] + delta};
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) {
+            if (p[a] < blo[a] || p[a] > bhi[a]) return 0;
+        } else {
+            double t0 = (blo[a] - p[a]) / d[a], t1 = (bhi[a] - p[a]) / d[a];
+            if (t0 > t1) { double t = t0; t0 = t1; t1 = t; }
+            if (t0 > lo) lo = t0;
+            if (t1 < hi) hi = t1;
+            if (lo > hi) return 0;
+        }
+    }
+    return 1;
+}
+
+/* Scan [t0, t1] on G+1 evenly spaced instants for switches of one
+ * occluder's predicate, locating each by bisection to 1e-9 minutes.
+ * `state` carries the predicate value and the start of an open shadowed
+ * run across calls; closed runs are appended to out. */
+static void scan_cell(const scene64 *S, int b, const double *p, const double *nrm, double ta, double tb,
+                      const double *da, const double *db, double t0, double t1, int G, int *state,
+                      double *open_t, ivec *out)
+{
+    double d[3], t_prev = t0;
+    for (int g = 1; g <= G; ++g) {
+        double t = (g == G) ? t1 : t0 + (t1 - t0) * g / G;
+        seg_dir_at(da, db, ta, tb, t, d);
+        int v = occl(S, b, p, nrm, d);
+        if (v != *state) {
+            double lo = t_prev, hi = t;
+            for (int it = 0; it < 80 && hi - lo > 1e-9; ++it) {
+                double mid = 0.5 * (lo + hi);
+                seg_dir_at(da, db, ta, tb, mid, d);
+                if (occl(S, b, p, nrm, d) == *state) lo = mid;
+                else hi = mid;
+            }
+            double sw = 0.5 * (lo + hi);
+            if (v) *open_t = sw;
+            else ivec_push(out, *open_t, sw);
+            *state = v;
+        }
+        t_prev = t;
+    }
+}
+
 /* Times in [ta, tb] at which one occluder shadows p: its predicate sampled
- * on a grid of spacing <= grid, each change located by bisection to 1e-9
- * minutes.  Appends the shadowed intervals to out. */
+ * on a grid of spacing <= grid, each change located by bisection.  A short
+ * shadowed run can hide between two unshadowed grid instants; it can only
+ * do so if the rays at those instants pass within (distance x the angle
+ * turned over the cell) of the prism, so such cells are rescanned 64 times
+ * finer.  (Within one great-circle segment a convex prism shadows p over a
+ * single run, so no unshadowed gap can hide between two shadowed
+ * instants.)  Appends the shadowed intervals to out. */
 static void occluder_intervals(const scene64 *S, int b, const double *p, const double *nrm,
                                double ta, double tb, const double *da, const double *db,
                                double grid, ivec *out)
 {
     int G = (int)ceil((tb - ta) / grid - 1e-12);
     if (G < 1) G = 1;
-    double d[3], open_t = ta, t_prev = ta;
-    int prev = 0;
-    for (int g = 0; g <= G; ++g) {
+    double d[3], open_t = ta;
+    double c = da[0] * db[0] + da[1] * db[1] + da[2] * db[2];
+    double dphi = acos(c > 1.0 ? 1.0 : c) / G;         /* angle turned per cell */
+    double R = 0.0;                                     /* farthest box corner from p */
+    if (b >= 0) {
+        const double *bx = S->box + 4 * b;
+        for (int k = 0; k < 8; ++k) {
+            double q[3] = {(k & 1) ? bx[2] : bx[0], (k & 2) ? bx[3] : bx[1], (k & 4) ? S->H[b] : 0.0};
+            double r = sqrt((q[0] - p[0]) * (q[0] - p[0]) + (q[1] - p[1]) * (q[1] - p[1]) +
+                            (q[2] - p[2]) * (q[2] - p[2]));
+            if (r > R) R = r;
+        }
+    }
+    double delta = 2.0 * R * dphi + 1e-6;
+    seg_dir_at(da, db, ta, tb, ta, d);
+    int state = occl(S, b, p, nrm, d);
+    int near_prev = b >= 0 && ray_meets_grown_box(S, b, p, d, delta);
+    double t_prev = ta;
+    for (int g = 1; g <= G; ++g) {
         double t = (g == G) ? tb : ta + (tb - ta) * g / G;
         seg_dir_at(da, db, ta, tb, t, d);
         int v = occl(S, b, p, nrm, d);
-        if (g > 0 && v != prev) {
-            double lo = t_prev, hi = t;
-            for (int it = 0; it < 80 && hi - lo > 1e-9; ++it) {
-                double mid = 0.5 * (lo + hi);
-                seg_dir_at(da, db, ta, tb, mid, d);
-                if (occl(S, b, p, nrm, d) == prev) lo = mid;
-                else hi = mid;
-            }
-            double sw = 0.5 * (lo + hi);
-            if (v) open_t = sw;
-            else ivec_push(out, open_t, sw);
-        } else if (g == 0 && v) {
-            open_t = ta;
-        }
-        prev = v;
+        int near = b >= 0 && ray_meets_grown_box(S, b, p, d, delta);
+        if (state == 0 && v == 0 && (near || near_prev))
+            scan_cell(S, b, p, nrm, ta, tb, da, db, t_prev, t, 64, &state, &open_t, out);
+        else
+            scan_cell(S, b, p, nrm, ta, tb, da, db, t_prev, t, 1, &state, &open_t, out);
+        near_prev = near;
         t_prev = t;
     }
-    if (prev) ivec_push(out, open_t, tb);
+    if (state) ivec_push(out, open_t, tb);
 }
 
 static void seg_plane(const double *da, const double *db, double *N)

@@ -370,3 +370,24 @@ def test_equinox_path_is_nearly_great_circle(c1):
     assert res[((3, 20), 60.0)] < 0.02
     assert res[((6, 21), 60.0)] > 3 * res[((3, 20), 60.0)]
     assert res[((6, 21), 30.0)] < 0.5 * res[((6, 21), 60.0)]
+
+
+def test_continuous_catches_runs_shorter_than_the_grid():
+    """A thin pole 200 m away shadows a ground point for a few seconds; the
+    default 5-second scan must find that run (gross shadow is the measure of
+    the whole shadowed set, Sec. 3.1) and agree with a 0.05-second scan."""
+    span = Span(40.7, -74.0, [Day(2019, 6, 21, -4.0, (480.0, 1080.0))], step_min=5.0)
+    path = oracle.sun_path(span, seg_min=30.0)
+    # place the pole on the shadow line of the sun at 10:07 local, 200 m out
+    s = oracle.solar(2019, 6, 21, 607.0, -4.0, 40.7, -74.0)
+    d = s[:3]
+    u = d[:2] / np.linalg.norm(d[:2])
+    r = 200.0
+    c = u * r
+    h = r * math.tan(math.radians(s[3])) + 20.0
+    sc = box_scene([(c[0] - 0.03, c[1] - 0.03, c[0] + 0.03, c[1] + 0.03, h)])
+    P = pts([[0.0, 0.0, 0.0]])
+    coarse = oracle.continuous(sc, P, path)["minutes"][0, 0]
+    fine = oracle.continuous(sc, P, path, grid_min=1.0 / 1200.0)["minutes"][0, 0]
+    assert 0.0 < fine < 5.0 / 60.0
+    assert coarse == pytest.approx(fine, abs=1e-6)
