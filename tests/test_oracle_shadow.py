@@ -385,7 +385,7 @@ def test_continuous_catches_runs_shorter_than_the_grid():
     r = 200.0
     c = u * r
     h = r * math.tan(math.radians(s[3])) + 20.0
-    sc = box_scene([(c[0] - 0.03, c[1] - 0.03, c[0] + 0.03, c[1] + 0.03, h)])
+    sc = box_scene([(c[0] - 0.01, c[1] - 0.01, c[0] + 0.01, c[1] + 0.01, h)])
     P = pts([[0.0, 0.0, 0.0]])
     coarse = oracle.continuous(sc, P, path)["minutes"][0, 0]
     fine = oracle.continuous(sc, P, path, grid_min=1.0 / 1200.0)["minutes"][0, 0]
