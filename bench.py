@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Benchmark: gross shadow of the Manhattan-like block scene on one MI355X.
+
+Workload (default): 20,000 convex prisms on an 18 x 60 block grid, 4,000,000
+sample points (2M open-space ground + 2M facade, 1 m lattice), 2019-03-20,
+06-21 and 12-21 sunrise..sunset at 1-minute instants (2,159 instants per
+point): 8.64e9 point-sun-steps per pass.
+
+One step = one pass of the accrual (sun-movement) form over all points and
+days, plus the per-day region sums.  Its throughput in effective
+point-sun-step evaluations per second is the headline value.  The sampled
+form (one ray per point per instant) is timed over the same points in its
+own leg; their ratio and the per-point difference between the two forms
+are reported beside it.  Inputs are resident in device memory before any
+timed region.
+
+Prints one JSON line (rank 0).  Only one GPU is supported.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic cost model, VALU lane-operations per unit of work a lane's own
+# traversal needs ("Roofline"):
+COST = {
+    "ray_box": 8,          # slab test of one child box: 5 FMA, max3, min3, compare
+    "ray_prism": 6,        # per prism: entry/exit select and height compare
+    "ray_edge": 10,        # per footprint edge: 2 sub, 2+2 FMA, rcp, mul, 2 min/max selects
+    "fan_box": 26,         # fan-triangle vs box: rise, 4 FMA + 4 cmp bbox, 3 edge-normal tests
+    "fan_prism": 40,       # per prism: inside/cover and window intersection logic
+    "fan_edge": 36,        # per edge: 2 sub, 4 FMA (u,v), 2 FMA z, clip crossing, 2 tangent updates
+    "insert": 60,          # 4-member interval-set insertion
+}
+LANE_OP_PEAK = 256 * 64 * 2.4e9   # CUs x lanes x clock: one VALU lane-op per lane per cycle
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_ops(work, mode):
+    box, prism, edges, inserts = (int(work[i]) for i in range(4))
+    if mode == "sampled":
+        return box * COST["ray_box"] + prism * COST["ray_prism"] + edges * COST["ray_edge"]
+    return box * COST["fan_box"] + prism * COST["fan_prism"] + edges * COST["fan_edge"] + \
+        inserts * COST["insert"]
+
+
+def cpu_baseline(w, seconds_target=15.0):
+    """The oracle (FP64, brute force, all host threads) on a bounded sample
+    of the same workload: sampled form, a seeded subset of points, every
+    instant of every day."""
+    import oracle
+    from workloads import subset_points
+    threads = oracle.threads_default()
+    path = oracle.sun_path(w.span)
+    ng = w.extra.get("n_ground", w.points.n)
+    n = 64
+    idx = np.concatenate([subset_points(w.points.take(np.arange(ng)), n // 2, 11),
+                          ng + subset_points(w.points.take(np.arange(ng, w.points.n)), n // 2, 12)])
+    t = time.perf_counter()
+    oracle.sampled(w.scene, w.points.take(idx), path, threads=threads)
+    dt = time.perf_counter() - t
+    # grow the sample to land in the target window
+    n2 = int(min(4096, max(n, n * seconds_target / max(dt, 1e-3))))
+    if n2 > n:
+        idx = np.concatenate([subset_points(w.points.take(np.arange(ng)), n2 // 2, 11),
+                              ng + subset_points(w.points.take(np.arange(ng, w.points.n)), n2 // 2, 12)])
+        t = time.perf_counter()
+        oracle.sampled(w.scene, w.points.take(idx), path, threads=threads)
+        dt = time.perf_counter() - t
+    evals = len(idx) * len(path.w)
+    return {"value": evals / dt, "unit": "point-sun-steps/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(idx)} points ({len(idx)//2} ground + {len(idx)//2} facade, seeded) x "
+                      f"{len(path.w)} instants x {w.scene.n_b} prisms, sampled form, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--seg", type=float, default=30.0, help="accrual knot spacing, minutes")
+    ap.add_argument("--sampled-steps", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-work-count", action="store_true")
+    ap.add_argument("--skip-sampled", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(points would shard across GPUs with the scene replicated; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1907_04435_amd as sa
+    from workloads import make_c1, make_c2
+
+    t0 = time.perf_counter()
+    w = make_c2() if args.workload == "c2" else make_c1()
+    log(f"workload {w.name}: {w.scene.n_b} prisms, {w.points.n} points, generated in {time.perf_counter()-t0:.1f} s")
+    ctx = sa.Context(0)
+    stream = ctx.stream
+    scene = sa.Scene.from_workload(ctx, w.scene)
+    sp_acc = sa.sunpath_for_span(w.span, args.seg)
+    path = sa.Path(ctx, sp_acc)
+    pts = sa.DevicePoints.from_workload(w.points)
+    n, K, B = pts.n, path.n_samples, path.n_bins
+    evals = n * K
+    dev = "cuda:0"
+    counts_a = torch.empty((B, n), dtype=torch.int32, device=dev)
+    mins_a = torch.empty((B, n), dtype=torch.float32, device=dev)
+    counts_s = torch.empty((B, n), dtype=torch.int32, device=dev)
+    mins_s = torch.empty((B, n), dtype=torch.float32, device=dev)
+    ng = w.extra.get("n_ground", n)
+    region_off = torch.tensor([0, ng, n], dtype=torch.int64, device=dev)
+    region_out = torch.empty((B, 2), dtype=torch.float64, device=dev)
+    log(f"scene: {scene.info()}; path: {B} bins, {K} instants, {path.n_segments} segments")
+    torch.cuda.synchronize()
+
+    def accrual_step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        sa.sa_accumulate(ctx, scene, pts, path, sa.SA_ACCRUAL, counts_a, mins_a)
+        if ev is not None:
+            ev[1].record(stream)
+        for b in range(B):
+            sa.sa_region_sum(ctx, mins_a[b], region_off, region_out[b])
+
+    for i in range(args.warmup):
+        accrual_step()
+        ctx.sync()
+        log(f"warmup {i} done")
+
+    # ---- timed accrual steps
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record(stream)
+    for i in range(args.steps):
+        accrual_step(evs[i])
+    end.record(stream)
+    ctx.sync()
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(end)
+    launch_ms = [a.elapsed_time(b) for a, b in evs]
+    ms_step = total_ms / args.steps
+    log(f"accrual: {ms_step:.1f} ms/step, launches {['%.1f' % x for x in launch_ms]}")
+
+    result = {
+        "metric": "point-sun-step evals/s (accrual form; sampled form beside it)",
+        "value": evals / (ms_step / 1e3),
+        "unit": "point-sun-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "points": n, "ground_points": ng, "facade_points": n - ng,
+                   "buildings": w.scene.n_b, "instants_per_point": K, "days": B, "seg_min": args.seg,
+                   "point_sun_steps": evals},
+    }
+
+    # ---- sampled leg
+    if not args.skip_sampled:
+        sa.sa_accumulate(ctx, scene, pts, path, sa.SA_SAMPLED, counts_s, mins_s)   # warm
+        ctx.sync()
+        sev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        sev[0].record(stream)
+        for _ in range(args.sampled_steps):
+            sa.sa_accumulate(ctx, scene, pts, path, sa.SA_SAMPLED, counts_s, mins_s)
+        sev[1].record(stream)
+        ctx.sync()
+        s_ms = sev[0].elapsed_time(sev[1]) / args.sampled_steps
+        log(f"sampled: {s_ms:.1f} ms/pass")
+        result["sampled"] = {"value": evals / (s_ms / 1e3), "unit": "point-sun-steps/s", "ms_per_pass": s_ms}
+        result["accrual_over_sampled"] = (evals / (ms_step / 1e3)) / (evals / (s_ms / 1e3))
+        d = (mins_a - mins_s).abs()
+        result["accrual_vs_sampled_minutes"] = {
+            "mean_abs_per_point_day": float(d.mean()), "p99": float(torch.quantile(d.flatten()[::97].float(), 0.99)),
+            "max": float(d.max()), "note": "GPU accrual minus GPU sampled (1-minute instants), per point per day"}
+
+    # ---- instrumented runs: algorithmic work per launch
+    if not args.no_work_count:
+        work = torch.zeros(8, dtype=torch.int64, device=dev)
+        sa.sa_accumulate(ctx, scene, pts, path, sa.SA_ACCRUAL, counts_a, mins_a, work=work)
+        ctx.sync()
+        wa = work.cpu().numpy()
+        ops = algorithmic_ops(wa, "accrual")
+        avg_s = float(np.mean(launch_ms)) / 1e3
+        achieved = ops / avg_s
+        result["roofline"] = {"bound": "alu", "kernel": "k_accrual", "achieved": achieved / 1e12,
+                              "peak": LANE_OP_PEAK / 1e12, "unit": "Tlane-op/s", "frac": achieved / LANE_OP_PEAK,
+                              "traffic": None,
+                              "work_per_launch": {"box_tests": int(wa[0]), "prism_tests": int(wa[1]),
+                                                  "prism_edges": int(wa[2]), "inserts": int(wa[3]),
+                                                  "node_fetches_per_wave": int(wa[4]),
+                                                  "point_segments": int(wa[5]), "spilled": int(wa[6]),
+                                                  "lane_ops": ops}}
+        log(f"accrual work: {wa.tolist()} -> {ops:.3e} lane-ops, {achieved/1e12:.2f} T/s")
+        if not args.skip_sampled:
+            work.zero_()
+            sa.sa_accumulate(ctx, scene, pts, path, sa.SA_SAMPLED, counts_s, mins_s, work=work)
+            ctx.sync()
+            ws = work.cpu().numpy()
+            sops = algorithmic_ops(ws, "sampled")
+            result["sampled"]["roofline_frac"] = (sops / (result["sampled"]["ms_per_pass"] / 1e3)) / LANE_OP_PEAK
+            result["sampled"]["work_per_pass"] = {"box_tests": int(ws[0]), "prism_tests": int(ws[1]),
+                                                  "prism_edges": int(ws[2]), "lane_ops": sops}
+            log(f"sampled work: {ws.tolist()} -> {sops:.3e} lane-ops")
+
+    # ---- CPU baseline (rank 0, N = 1)
+    if not args.no_cpu_baseline:
+        log("cpu baseline ...")
+        result["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

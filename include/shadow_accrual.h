@@ -198,7 +198,15 @@ typedef struct {
     int32_t mode;     /* SA_SAMPLED or SA_ACCRUAL */
     uint32_t flags;   /* SA_FLAG_ADD */
     float out_scale;  /* minutes are multiplied by this (0 = 1; 1/60 gives hours) */
-    int32_t reserved[5];
+    int32_t reserved0;
+    /* Optional device uint64 [8], added to (not cleared): when non-NULL the
+     * launch runs an instrumented instantiation that counts, per lane, the
+     * work its own traversal needed -- [0] child-box tests, [1] prism tests,
+     * [2] footprint edges visited in prism tests, [3] interval insertions,
+     * [4] node fetches (per wave), [5] lanes x units (point-instants or
+     * point-segments), [6] spilled windows, [7] reserved.  Slower; for
+     * measurement only. */
+    uint64_t *work;
 } sa_accum_opts;
 
 /* Gross shadow of every point over every day of `path`, summed per bin.

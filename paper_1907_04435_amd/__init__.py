@@ -68,7 +68,7 @@ class sa_points(C.Structure):
 
 class sa_accum_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("flags", C.c_uint32), ("out_scale", C.c_float),
-                ("reserved", C.c_int32 * 5)]
+                ("reserved0", C.c_int32), ("work", C.c_void_p)]
 
 
 _lib = None
@@ -342,9 +342,10 @@ class DevicePoints:
 # compute entry points
 # --------------------------------------------------------------------------
 def sa_accumulate(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, mode: int, counts=None,
-                  minutes=None, bits=None, flags=0, out_scale=1.0):
-    """Gross shadow into caller-provided device tensors (see the C ABI)."""
-    opts = sa_accum_opts(mode, flags, out_scale)
+                  minutes=None, bits=None, flags=0, out_scale=1.0, work=None):
+    """Gross shadow into caller-provided device tensors (see the C ABI).
+    ``work``: optional device int64 [8] work counters (instrumented run)."""
+    opts = sa_accum_opts(mode, flags, out_scale, 0, _ptr(work))
     ps = pts.struct()
     _check(ctx, lib().sa_accumulate(ctx.handle, scene.handle, C.byref(ps), path.handle, C.byref(opts),
                                     _ptr(counts), _ptr(minutes), _ptr(bits)))
@@ -367,7 +368,7 @@ def sa_accumulate_batched(ctx: Context, scene: Scene, var_ids, var_h, pts: Devic
                           counts=None, minutes=None, flags=0, out_scale=1.0):
     """Batched development variants (device tensors var_ids [V, k] int32,
     var_h [V, k] float32, var_off [V+1] int64)."""
-    opts = sa_accum_opts(SA_ACCRUAL, flags, out_scale)
+    opts = sa_accum_opts(SA_ACCRUAL, flags, out_scale, 0, None)
     ps = pts.struct()
     V, k = int(var_ids.shape[0]), int(var_ids.shape[1]) if var_ids.dim() > 1 else 0
     _check(ctx, lib().sa_accumulate_batched(ctx.handle, scene.handle, V, k, _ptr(var_ids), _ptr(var_h),

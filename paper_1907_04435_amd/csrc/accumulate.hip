@@ -48,12 +48,25 @@ __device__ __forceinline__ LanePoint load_point(const PointArgs &P, int64_t i, b
 }
 
 // ------------------------------------------------------------------ sampled
-template <bool kBits>
+// Sum a per-lane counter over the wave and add it to a global total.
+__device__ __forceinline__ void flush_work(const Work &w, uint64_t *work)
+{
+    uint32_t v[7] = {w.box, w.prism, w.edges, w.inserts, w.nodes, w.units, w.spills};
+#pragma unroll
+    for (int c = 0; c < 7; ++c) {
+        uint64_t s = v[c];
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
+        if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&work[c], (unsigned long long)s);
+    }
+}
+
+template <bool kBits, bool kCount>
 __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const float4 *verts_g,
                                                       const float *height_g, const SampleConst *samples_g,
                                                       int K, PointArgs P, float scale, int32_t *counts,
-                                                      float *minutes, uint32_t *bits)
+                                                      float *minutes, uint32_t *bits, uint64_t *work)
 {
+    Work wk{0, 0, 0, 0, 0, 0, 0};
     cNode *nodes = (cNode *)nodes_g;
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
@@ -95,16 +108,21 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
                 return fmaxf(fmaxf(tnx, tny), 0.f) <= fminf(fminf(tfx, tfy), tfz);
             };
             auto leaf = [&](int prim, int voff, int m, bool want) {
-                const bool t = want && prim != q.own &&
-                               ray_prism(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, s.dx, s.dy, s.dz);
+                const bool go = want && prim != q.own;
+                if constexpr (kCount) {
+                    wk.prism += go ? 1u : 0u;
+                    wk.edges += go ? (uint32_t)m : 0u;
+                }
+                const bool t = go && ray_prism(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, s.dx, s.dy, s.dz);
                 hit = hit || t;
                 live = live && !t;
             };
             auto key = [&](float x0, float y0, float x1, float y1, float z1) {
                 return fmaf(x0 + x1, s.dx, fmaf(y0 + y1, s.dy, z1 * s.dz));
             };
-            packet_traverse(nodes, stack, live, bt, leaf, key);
+            packet_traverse<kCount>(nodes, stack, live, bt, leaf, key, wk);
         }
+        if constexpr (kCount) wk.units += valid ? 1u : 0u;
         const bool sh = valid && (back || hit);
         cnt += sh ? 1 : 0;
         mins += sh ? s.w : 0.f;
@@ -120,6 +138,7 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
         if (counts) counts[(int64_t)bin * n + i] += cnt;
         if (minutes) minutes[(int64_t)bin * n + i] += mins * scale;
     }
+    if constexpr (kCount) flush_work(wk, work);
 }
 
 // ------------------------------------------------------------------ accrual
@@ -169,10 +188,10 @@ __device__ __forceinline__ void measure(const Union4 &U, const SegConst &g, floa
 // The occluded set of every live lane's point over its window of segment g:
 // back-face term, then the packet fan traversal.  On return `ov` marks
 // lanes whose set needed more than four pieces.
+template <bool kCount>
 __device__ __forceinline__ void accrue_segment(cNode *nodes, int *stack, cfloat4 *verts, cfloat *height,
-                                               const SegConst &g,
-                                               const LanePoint &q, bool active, float w0, float w1,
-                                               Union4 &U, bool &ov)
+                                               const SegConst &g, const LanePoint &q, bool active, float w0,
+                                               float w1, Union4 &U, bool &ov, Work &wk)
 {
     union_clear(U);
     ov = false;
@@ -214,10 +233,15 @@ __device__ __forceinline__ void accrue_segment(cNode *nodes, int *stack, cfloat4
     auto leaf = [&](int prim, int voff, int m, bool want) {
         const bool go = want && prim != q.own;
         if (!ballot(go)) return;
+        if constexpr (kCount) {
+            wk.prism += go ? 1u : 0u;
+            wk.edges += go ? (uint32_t)m : 0u;
+        }
         float a = 0.f, b = 0.f;
         const int r = go ? prism_interval(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, w0, w1, W0u, W0v,
                                           W1u, W1v, a, b)
                          : 0;
+        if constexpr (kCount) wk.inserts += r ? 1u : 0u;
         if (r) {
             if (!union_insert(U, a, b)) {
                 ov = true;
@@ -231,7 +255,7 @@ __device__ __forceinline__ void accrue_segment(cNode *nodes, int *stack, cfloat4
     auto key = [&](float x0, float y0, float x1, float y1, float z1) {
         return fmaf(x0 + x1, mdx, (y0 + y1) * mdy);
     };
-    packet_traverse(nodes, stack, live, bt, leaf, key);
+    packet_traverse<kCount>(nodes, stack, live, bt, leaf, key, wk);
 }
 
 // Roof-covered: inside a footprint (other than the point's own building)
@@ -250,15 +274,18 @@ __device__ __forceinline__ bool roof_covered(cNode *nodes, int *stack, cfloat4 *
         live = live && !t;
     };
     auto key = [&](float, float, float, float, float) { return 0.f; };
-    packet_traverse(nodes, stack, live, bt, leaf, key);
+    Work none{0, 0, 0, 0, 0, 0, 0};
+    packet_traverse<false>(nodes, stack, live, bt, leaf, key, none);
     return cov;
 }
 
+template <bool kCount>
 __global__ __launch_bounds__(kThreads) void k_accrual(const Node *nodes_g, const float4 *verts_g,
                                                       const float *height_g, const SegConst *segs_g, int J,
                                                       PointArgs P, float scale, int32_t *counts, float *minutes,
-                                                      SpillArgs S)
+                                                      SpillArgs S, uint64_t *work)
 {
+    Work wk{0, 0, 0, 0, 0, 0, 0};
     cNode *nodes = (cNode *)nodes_g;
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
@@ -289,8 +316,12 @@ __global__ __launch_bounds__(kThreads) void k_accrual(const Node *nodes_g, const
         }
         Union4 U;
         bool ov;
-        accrue_segment(nodes_g ? nodes : nullptr, stack, verts, height, g, q, valid && !covered, 0.f, g.theta, U,
-                       ov);
+        accrue_segment<kCount>(nodes_g ? nodes : nullptr, stack, verts, height, g, q, valid && !covered, 0.f,
+                               g.theta, U, ov, wk);
+        if constexpr (kCount) {
+            wk.units += valid ? 1u : 0u;
+            wk.spills += (valid && ov) ? 1u : 0u;
+        }
         if (covered && valid) {
             mins += g.dt;
             cnt += g.ns;
@@ -303,6 +334,7 @@ __global__ __launch_bounds__(kThreads) void k_accrual(const Node *nodes_g, const
         if (counts) counts[(int64_t)bin * n + i] += cnt;
         if (minutes) minutes[(int64_t)bin * n + i] += mins * scale;
     }
+    if constexpr (kCount) flush_work(wk, work);
 }
 
 // One spill round: every queued (point, segment, window) is split in two
@@ -333,7 +365,8 @@ __global__ __launch_bounds__(kThreads) void k_spill(const Node *nodes_g, const f
         const SegConst g = segs_g[valid ? j : 0];
         Union4 U;
         bool ov;
-        accrue_segment(nodes_g ? nodes : nullptr, stack, verts, height, g, q, valid, w0, w1, U, ov);
+        Work none{0, 0, 0, 0, 0, 0, 0};
+        accrue_segment<false>(nodes_g ? nodes : nullptr, stack, verts, height, g, q, valid, w0, w1, U, ov, none);
         if (valid && !ov) {
             float mins = 0.f;
             int cnt = 0;
@@ -370,7 +403,8 @@ static PointArgs point_args(const PointsView &pts, const DeviceScene &s)
 }
 
 sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
-                         int32_t *counts, float *minutes, uint32_t *bits, hipStream_t st, std::string &err)
+                         int32_t *counts, float *minutes, uint32_t *bits, uint64_t *work, hipStream_t st,
+                         std::string &err)
 {
     if (pts.n == 0) return SA_OK;
     const int64_t waves = (pts.n + 63) / 64;
@@ -380,12 +414,10 @@ sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const Points
         return SA_ERR_INVALID_ARG;
     }
     const Node *nodes = s.n_b > 0 ? s.nodes : nullptr;
-    if (bits)
-        hipLaunchKernelGGL(k_sampled<true>, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, s.verts, s.height,
-                           p.samples, p.n_samples, point_args(pts, s), scale, counts, minutes, bits);
-    else
-        hipLaunchKernelGGL(k_sampled<false>, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, s.verts,
-                           s.height, p.samples, p.n_samples, point_args(pts, s), scale, counts, minutes, bits);
+    auto kern = bits ? (work ? k_sampled<true, true> : k_sampled<true, false>)
+                     : (work ? k_sampled<false, true> : k_sampled<false, false>);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, s.verts, s.height, p.samples,
+                       p.n_samples, point_args(pts, s), scale, counts, minutes, bits, work);
     SA_CHECK_LAUNCH("sampled kernel");
     return SA_OK;
 }
@@ -410,7 +442,8 @@ sa_status run_spill(const DeviceScene &s, const DevicePath &p, const PointArgs &
 }
 
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
-                         int32_t *counts, float *minutes, SpillQueue &q, hipStream_t st, std::string &err)
+                         int32_t *counts, float *minutes, uint64_t *work, SpillQueue &q, hipStream_t st,
+                         std::string &err)
 {
     if (pts.n == 0) return SA_OK;
     const int64_t waves = (pts.n + 63) / 64;
@@ -419,8 +452,8 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
     const PointArgs P = point_args(pts, s);
     hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters);
     SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
-    hipLaunchKernelGGL(k_accrual, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, s.verts, s.height, p.segs,
-                       p.n_segs, P, scale, counts, minutes, S);
+    hipLaunchKernelGGL(work ? k_accrual<true> : k_accrual<false>, dim3((unsigned)grid), dim3(kThreads), 0, st,
+                       nodes, s.verts, s.height, p.segs, p.n_segs, P, scale, counts, minutes, S, work);
     SA_CHECK_LAUNCH("accrual kernel");
     return run_spill(s, p, P, scale, counts, minutes, q, st, err);
 }

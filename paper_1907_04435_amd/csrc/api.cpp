@@ -428,10 +428,11 @@ sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts
     if (rc != SA_OK) return rc;
     std::string err;
     if (opts->mode == SA_SAMPLED)
-        rc = sa::launch_sampled(scene->d, path->d, view(pts), scale, counts, minutes, bits, ctx->stream, err);
+        rc = sa::launch_sampled(scene->d, path->d, view(pts), scale, counts, minutes, bits, opts->work,
+                                ctx->stream, err);
     else
-        rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, ctx->spill, ctx->stream,
-                                err);
+        rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->work, ctx->spill,
+                                ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate: " + err);
     return SA_OK;
 }

@@ -111,10 +111,10 @@ struct SpillQueue {
 
 sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
                          float scale, int32_t *counts, float *minutes, uint32_t *bits,
-                         hipStream_t st, std::string &err);
+                         uint64_t *work, hipStream_t st, std::string &err);
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
-                         float scale, int32_t *counts, float *minutes, SpillQueue &q,
-                         hipStream_t st, std::string &err);
+                         float scale, int32_t *counts, float *minutes, uint64_t *work,
+                         SpillQueue &q, hipStream_t st, std::string &err);
 sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
                       const float *dl, float *grad, hipStream_t st, std::string &err);
 sa_status launch_region_sum(const float *v, int64_t n, const int64_t *off, int32_t n_reg,

@@ -58,20 +58,41 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G)
     return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// Work a lane's own traversal needed (instrumented instantiations only).
+struct Work {
+    uint32_t box, prism, edges, inserts, nodes, units, spills;
+};
+
+__device__ __forceinline__ bool first_active_lane()
+{
+    const int lane = __lane_id();
+    return __builtin_amdgcn_readfirstlane(lane) == lane;
+}
+
 // Packet traversal.  `bt(x0, y0, x1, y1, z1)` is the per-lane child-box
 // test; `leaf(prim, voff, m, want)` processes a leaf for lanes with `want`
 // and may clear `live`.  `key(x0,y0,x1,y1,z1)` orders two wanted children
 // (smaller first).  The walk ends when no lane is live or the stack runs
-// dry.
-template <class BoxTest, class LeafFn, class KeyFn>
+// dry.  A lane only tests the children of nodes it reached itself (a
+// per-lane bit per stack entry remembers whether the lane wanted the pushed
+// node), so leaves no lane reached are skipped.  With kCount, `w`
+// accumulates those box tests and the wave's node fetches.
+template <bool kCount, class BoxTest, class LeafFn, class KeyFn>
 __device__ __forceinline__ void packet_traverse(cNode *nodes, int *stack, bool &live, BoxTest bt, LeafFn leaf,
-                                                KeyFn key)
+                                                KeyFn key, Work &w)
 {
     int sp = 0, node = 0;
+    bool want_cur = live;
+    uint64_t want_stack = 0;
     while (ballot(live)) {
         const Node nd = ld(nodes + node);
-        bool hl = live && nd.left != kNone && bt(nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1);
-        bool hr = live && nd.right != kNone && bt(nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1);
+        if constexpr (kCount) {
+            w.box += (want_cur && live) ? 2u : 0u;
+            w.nodes += first_active_lane() ? 1u : 0u;
+        }
+        const bool mine = live && want_cur;
+        bool hl = mine && nd.left != kNone && bt(nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1);
+        bool hr = mine && nd.right != kNone && bt(nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1);
         if (nd.left < 0 && nd.left != kNone) {
             if (ballot(hl)) leaf(~nd.left, nd.l_voff, nd.l_m, hl);
             hl = false;
@@ -85,15 +106,21 @@ __device__ __forceinline__ void packet_traverse(cNode *nodes, int *stack, bool &
             const bool lfirst = key(nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1) <=
                                 key(nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1);
             stack[sp] = lfirst ? nd.right : nd.left;
+            const bool far = lfirst ? hr : hl;
+            want_stack = far ? (want_stack | (1ull << sp)) : (want_stack & ~(1ull << sp));
+            want_cur = lfirst ? hl : hr;
             ++sp;
             node = uniform(lfirst ? nd.left : nd.right);
         } else if (gl) {
+            want_cur = hl;
             node = uniform(nd.left);
         } else if (gr) {
+            want_cur = hr;
             node = uniform(nd.right);
         } else {
             if (sp == 0) break;
             --sp;
+            want_cur = (want_stack >> sp) & 1ull;
             node = uniform(stack[sp]);
         }
     }
