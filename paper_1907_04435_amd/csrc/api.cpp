@@ -483,7 +483,7 @@ sa_status sa_region_sum(sa_ctx *ctx, const float *values, int64_t n, const int64
     if (n_reg == 0) return SA_OK;
     if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
     std::string err;
-    sa_status rc = sa::launch_region_sum(values, n, region_off, n_reg, area, out, ctx->stream, err);
+    sa_status rc = sa::launch_region_sum(values, n, region_off, n_reg, area, out, ctx->scratch, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_region_sum: " + err);
     return SA_OK;
 }

@@ -118,7 +118,8 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
 sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
                       const float *dl, float *grad, hipStream_t st, std::string &err);
 sa_status launch_region_sum(const float *v, int64_t n, const int64_t *off, int32_t n_reg,
-                            const float *area, double *out, hipStream_t st, std::string &err);
+                            const float *area, double *out, Scratch &scr, hipStream_t st,
+                            std::string &err);
 sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_var, int32_t k,
                          const int32_t *ids, const float *h, const PointsView &pts,
                          const int64_t *var_off, float scale, int32_t *counts, float *minutes,
