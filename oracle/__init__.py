@@ -48,6 +48,8 @@ def lib():
         L.orc_continuous.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, ip, C.c_int, ip, C.c_int,
                                      C.c_double, dp, ip, C.c_int, dp, ip, C.c_int]
         L.orc_slerp.argtypes = [dp, dp, C.c_double, dp]
+        L.orc_grad_implicit.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, ip, ip, C.c_double, dp, dp,
+                                        C.c_int]
         _lib = L
     return _lib
 
@@ -225,3 +227,29 @@ def continuous(scene, pts, path: OraclePath, grid_min=1.0 / 12.0, threads=None):
                          _ptr(st, C.c_double), _ptr(sd, C.c_int32), len(st),
                          _ptr(minutes, C.c_double), _ptr(counts, C.c_int32), threads or threads_default())
     return dict(minutes=minutes, counts=counts)
+
+
+def grad_implicit(scene, pts, path: OraclePath, dl=None, grid_min=1.0 / 12.0, threads=None):
+    """d/dH_b of sum over points and bins of dl[bin, p] * continuous minutes
+    (dl None = all ones), by implicit differentiation at the union
+    boundaries made by roof edges.  FP64 [n_b]."""
+    s, ks = _scene(scene)
+    p, kp = _points(pts)
+    grad = np.zeros(max(scene.n_b, 1), np.float64)
+    seg_t = np.ascontiguousarray(path.seg_t, np.float64)
+    seg_dir = np.ascontiguousarray(path.seg_dir, np.float64)
+    seg_day = np.ascontiguousarray(path.seg_day, np.int32)
+    day_bin = np.ascontiguousarray(path.day_bin, np.int32)
+    d = None if dl is None else np.ascontiguousarray(dl, np.float64)
+    lib().orc_grad_implicit(C.byref(s), C.byref(p), len(seg_t), _ptr(seg_t, C.c_double), _ptr(seg_dir, C.c_double),
+                            _ptr(seg_day, C.c_int32), _ptr(day_bin, C.c_int32), float(grid_min),
+                            _ptr(d, C.c_double), _ptr(grad, C.c_double), threads or threads_default())
+    return grad[:scene.n_b]
+
+
+def with_height(scene, b, h):
+    """Copy of the scene with building b at height h."""
+    from workloads import Scene
+    hh = scene.height.astype(np.float32).copy()
+    hh[b] = h
+    return Scene(scene.vert_off, scene.xy, hh)

@@ -79,9 +79,12 @@ void orc_continuous(const orc_scene *s, const orc_points *p, int n_seg,
                     double *minutes, int32_t *counts, int threads);
 
 /* ---- gradient of sum_p D_L(p) w.r.t. building heights ---- */
+/* grad [n_b]: d/dH_b of sum over points and days of dl_dmin[bin][p] *
+ * (continuous shadowed minutes), dl_dmin NULL = all ones. */
 void orc_grad_implicit(const orc_scene *s, const orc_points *p, int n_seg,
-                       const double *seg_t, const double *seg_dir, double grid_min,
-                       const double *dl_dmin, double *grad, int threads);
+                       const double *seg_t, const double *seg_dir, const int32_t *seg_day,
+                       const int32_t *day_bin, double grid_min, const double *dl_dmin,
+                       double *grad, int threads);
 
 /* slerp on the great circle through a and b at constant angular rate */
 void orc_slerp(const double *a, const double *b, double f, double *out);

@@ -569,10 +569,151 @@ void orc_continuous(const orc_scene *s, const orc_points *p, int n_seg,
     scene64_free(&S);
 }
 
-void orc_grad_implicit(const orc_scene *s, const orc_points *p, int n_seg,
-                       const double *seg_t, const double *seg_dir, double grid_min,
-                       const double *dl_dmin, double *grad, int threads)
+/* ---- gradient of sum_p w(p, day) D_L(p, day) with respect to heights ----
+ *
+ * D_L is the measure of the union of the occluders' shadowed intervals.
+ * A boundary of the union at time t* is an end of one occluder's interval.
+ * If that end is where the ray grazes the occluder's roof edge, t* solves
+ *     g(t, H) = H - z_in(t) = 0,
+ * with z_in(t) the height of the ray where it enters the footprint, so
+ * d(t*) / dH = 1 / z_in'(t*) (implicit function theorem; z_in' by a central
+ * difference in t).  An end made by a vertical edge (the ray leaving the
+ * footprint's angular range) does not move with H.  A union boundary that
+ * closes contributes +d(t*) / dH, one that opens -d(t*) / dH; ties go to the lower
+ * building id. */
+
+/* Height of the ray p + s d where it enters footprint b (s_in >= 0), or -1
+ * if it does not cross the footprint ahead of p. */
+static double entry_height(const scene64 *S, int b, const double *p, const double *d)
 {
-    (void)s; (void)p; (void)n_seg; (void)seg_t; (void)seg_dir; (void)grid_min;
-    (void)dl_dmin; (void)grad; (void)threads;
+    double s_in = -INFINITY, s_out = INFINITY;
+    int o = S->off[b], m = S->off[b + 1] - o;
+    for (int i = 0; i < m; ++i) {
+        const double *a = S->xy + 2 * (o + i), *c = S->xy + 2 * (o + (i + 1) % m);
+        double nx = c[1] - a[1], ny = -(c[0] - a[0]);
+        double num = nx * (a[0] - p[0]) + ny * (a[1] - p[1]);
+        double den = nx * d[0] + ny * d[1];
+        if (den > 0.0) { double t = num / den; if (t < s_out) s_out = t; }
+        else if (den < 0.0) { double t = num / den; if (t > s_in) s_in = t; }
+        else if (num < 0.0) return -1.0;
+    }
+    if (s_in < 0.0 || s_out < s_in) return -1.0;
+    return p[2] + s_in * d[2];
+}
+
+typedef struct { double t; int b; int close; } endpoint;
+
+typedef struct {
+    const scene64 *S;
+    const orc_points *P;
+    int n_seg;
+    const double *seg_t, *seg_dir;
+    const int32_t *seg_day;
+    const int32_t *day_bin;
+    double grid;
+    const double *dl;   /* [n_bins][n] or NULL */
+    double *grad;       /* [n_b] per thread slice */
+    int threads;
+} grad_ctx;
+
+/* d(t*) / dH of one interval end of prism b at time t (0 if a wall edge). */
+static double end_rate(const scene64 *S, int b, const double *p, const double *da, const double *db,
+                       double ta, double tb, double t)
+{
+    if (b < 0) return 0.0;
+    double d[3];
+    seg_dir_at(da, db, ta, tb, t, d);
+    double z = entry_height(S, b, p, d);
+    if (z < 0.0 || fabs(z - S->H[b]) > 1e-4) return 0.0;
+    const double h = 1e-4;       /* minutes */
+    double d0[3], d1[3];
+    seg_dir_at(da, db, ta, tb, t - h, d0);
+    seg_dir_at(da, db, ta, tb, t + h, d1);
+    double z0 = entry_height(S, b, p, d0), z1 = entry_height(S, b, p, d1);
+    if (z0 < 0.0 || z1 < 0.0) return 0.0;
+    double dz = (z1 - z0) / (2 * h);
+    return dz != 0.0 ? 1.0 / dz : 0.0;
+}
+
+static pthread_mutex_t grad_mu = PTHREAD_MUTEX_INITIALIZER;
+
+static void grad_point(void *vctx, int64_t i)
+{
+    grad_ctx *C = (grad_ctx *)vctx;
+    const scene64 *S = C->S;
+    const orc_points *P = C->P;
+    double p[3] = {P->x[i], P->y[i], P->z[i]};
+    double nrm[2] = {P->nx ? P->nx[i] : 0.0, P->ny ? P->ny[i] : 0.0};
+    int owner = P->owner ? P->owner[i] : -1;
+    double *g = (double *)calloc(S->n_b ? S->n_b : 1, sizeof(double));
+    for (int j = 0; j < C->n_seg; ++j) {
+        double ta = C->seg_t[2 * j], tb = C->seg_t[2 * j + 1];
+        const double *da = C->seg_dir + 6 * j, *db = da + 3;
+        int day = C->seg_day ? C->seg_day[j] : 0;
+        int bin = C->day_bin ? C->day_bin[day] : day;
+        double w = C->dl ? C->dl[(int64_t)bin * P->n + i] : 1.0;
+        if (w == 0.0 || !(tb > ta)) continue;
+        /* intervals of every occluder, tagged with the occluder */
+        double N[3];
+        seg_plane(da, db, N);
+        int ne = 0, cap = 64;
+        endpoint *ev = (endpoint *)malloc(sizeof(endpoint) * cap);
+        for (int b = (owner >= 0 ? -1 : 0); b < S->n_b; ++b) {
+            if (b >= 0 && (b == owner || box_off_plane(S, b, p, N))) continue;
+            ivec iv = {0, 0, 0};
+            occluder_intervals(S, b, p, nrm, ta, tb, da, db, C->grid, &iv);
+            for (int k = 0; k < iv.n; ++k) {
+                if (ne + 2 > cap) { cap *= 2; ev = (endpoint *)realloc(ev, sizeof(endpoint) * cap); }
+                ev[ne].t = iv.v[k].lo; ev[ne].b = b; ev[ne].close = 0; ++ne;
+                ev[ne].t = iv.v[k].hi; ev[ne].b = b; ev[ne].close = 1; ++ne;
+            }
+            free(iv.v);
+        }
+        /* sweep: a union boundary is where the number of covering intervals
+         * goes 0 -> 1 (opening) or 1 -> 0 (closing); equal times: opens
+         * first (closed intervals touching merge), then lower id */
+        for (int a = 1; a < ne; ++a) {           /* insertion sort: few events */
+            endpoint e = ev[a];
+            int c = a - 1;
+            while (c >= 0 && (ev[c].t > e.t || (ev[c].t == e.t && (ev[c].close > e.close ||
+                   (ev[c].close == e.close && ev[c].b > e.b))))) {
+                ev[c + 1] = ev[c];
+                --c;
+            }
+            ev[c + 1] = e;
+        }
+        int depth = 0;
+        for (int a = 0; a < ne; ++a) {
+            if (!ev[a].close) {
+                if (depth == 0 && ev[a].t > ta && ev[a].b >= 0)
+                    g[ev[a].b] -= w * end_rate(S, ev[a].b, p, da, db, ta, tb, ev[a].t);
+                ++depth;
+            } else {
+                --depth;
+                if (depth == 0 && ev[a].t < tb && ev[a].b >= 0)
+                    g[ev[a].b] += w * end_rate(S, ev[a].b, p, da, db, ta, tb, ev[a].t);
+            }
+        }
+        free(ev);
+    }
+    pthread_mutex_lock(&grad_mu);
+    for (int b = 0; b < S->n_b; ++b) C->grad[b] += g[b];
+    pthread_mutex_unlock(&grad_mu);
+    free(g);
+}
+
+void orc_grad_implicit(const orc_scene *s, const orc_points *p, int n_seg,
+                       const double *seg_t, const double *seg_dir, const int32_t *seg_day,
+                       const int32_t *day_bin, double grid_min, const double *dl_dmin,
+                       double *grad, int threads)
+{
+    scene64 S;
+    scene64_init(&S, s);
+    memset(grad, 0, sizeof(double) * (s->n_b ? s->n_b : 1));
+    grad_ctx C;
+    memset(&C, 0, sizeof(C));
+    C.S = &S; C.P = p; C.n_seg = n_seg; C.seg_t = seg_t; C.seg_dir = seg_dir; C.seg_day = seg_day;
+    C.day_bin = day_bin; C.grid = grid_min; C.dl = dl_dmin; C.grad = grad;
+    parallel_for(p->n, threads, grad_point, &C);
+    scene64_free(&S);
 }

@@ -385,3 +385,28 @@ def sa_grad_heights(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, d
 def sa_region_sum(ctx: Context, values, region_off, out, area=None):
     _check(ctx, lib().sa_region_sum(ctx.handle, _ptr(values), int(values.numel()), _ptr(region_off),
                                     int(region_off.numel()) - 1, _ptr(area), _ptr(out)))
+
+
+def shadow_minutes_fn():
+    """torch.autograd.Function: heights [n_b] -> accrual minutes [bins, n];
+    backward runs the adjoint kernel (sa_grad_heights)."""
+    import torch
+
+    class ShadowMinutes(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, heights, sactx, scene, pts, path):
+            h = heights.detach().to("cpu", torch.float32).numpy()
+            scene.set_heights(np.arange(scene.n_b, dtype=np.int32), h)
+            minutes = torch.empty((path.n_bins, pts.n), dtype=torch.float32, device=f"cuda:{sactx.device}")
+            sa_accumulate(sactx, scene, pts, path, SA_ACCRUAL, None, minutes)
+            fctx.objs = (sactx, scene, pts, path)
+            return minutes
+
+        @staticmethod
+        def backward(fctx, grad_out):
+            sactx, scene, pts, path = fctx.objs
+            grad = torch.empty(scene.n_b, dtype=torch.float32, device=f"cuda:{sactx.device}")
+            sa_grad_heights(sactx, scene, pts, path, grad_out.contiguous().float(), grad)
+            return grad, None, None, None, None
+
+    return ShadowMinutes

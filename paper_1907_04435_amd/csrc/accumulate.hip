@@ -17,36 +17,6 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kSpillRounds = 12;
 constexpr int kSpillBlocks = 1024;
 
-struct PointArgs {
-    int64_t n;
-    const float *x, *y, *z, *nx, *ny;
-    const int32_t *owner;
-    const int32_t *rank;  // original id -> hierarchy position
-    int32_t n_b;
-};
-
-struct LanePoint {
-    float px, py, pz, nx, ny;
-    int own;  // hierarchy position of the owner, -1 for ground points
-};
-
-__device__ __forceinline__ LanePoint load_point(const PointArgs &P, int64_t i, bool valid)
-{
-    LanePoint q{0.f, 0.f, 0.f, 0.f, 0.f, -1};
-    if (valid) {
-        q.px = P.x[i];
-        q.py = P.y[i];
-        q.pz = P.z[i];
-        if (P.nx) q.nx = P.nx[i];
-        if (P.ny) q.ny = P.ny[i];
-        if (P.owner) {
-            const int o = P.owner[i];
-            q.own = (o >= 0 && o < P.n_b) ? P.rank[o] : -1;
-        }
-    }
-    return q;
-}
-
 // ------------------------------------------------------------------ sampled
 // Sum a per-lane counter over the wave and add it to a global total.
 __device__ __forceinline__ void flush_work(const Work &w, uint64_t *work)
@@ -142,23 +112,6 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
 }
 
 // ------------------------------------------------------------------ accrual
-struct SpillArgs {
-    int4 *out;          // queue to push to
-    uint32_t *counter;  // its length
-    uint32_t *overflow;
-    int32_t cap;
-};
-
-__device__ __forceinline__ void spill_push(const SpillArgs &S, bool want, int64_t i, int j, float w0, float w1)
-{
-    if (!want) return;
-    const uint32_t slot = atomicAdd(S.counter, 1u);
-    if ((int32_t)slot < S.cap)
-        S.out[slot] = make_int4((int)i, j, __float_as_int(w0), __float_as_int(w1));
-    else
-        atomicOr(S.overflow, 1u);
-}
-
 // Measure and sample count of the occluded set of one point over the
 // window [w0, w1] of segment g.  `last_window` says whether w1 is the end
 // of the segment (instants at the window end belong to the next window
@@ -206,30 +159,7 @@ __device__ __forceinline__ void accrue_segment(cNode *nodes, int *stack, cfloat4
         }
     }
     if (nodes == nullptr) return;
-    // fan below height z1: the triangle p, p + (z1-pz) ua, p + (z1-pz) ub
-    const float umnx = fminf(0.f, fminf(g.ua_x, g.ub_x)), umxx = fmaxf(0.f, fmaxf(g.ua_x, g.ub_x));
-    const float umny = fminf(0.f, fminf(g.ua_y, g.ub_y)), umxy = fmaxf(0.f, fmaxf(g.ua_y, g.ub_y));
-    // inward normals of the three triangle edges
-    float nax = -g.ua_y, nay = g.ua_x;
-    if (fmaf(nax, g.ub_x, nay * g.ub_y) < 0.f) { nax = -nax; nay = -nay; }
-    float nbx = -g.ub_y, nby = g.ub_x;
-    if (fmaf(nbx, g.ua_x, nby * g.ua_y) < 0.f) { nbx = -nbx; nby = -nby; }
-    float ncx = -(g.ub_y - g.ua_y), ncy = g.ub_x - g.ua_x;
-    if (fmaf(ncx, g.ua_x, ncy * g.ua_y) > 0.f) { ncx = -ncx; ncy = -ncy; }
-    const float kc = fmaf(ncx, g.ua_x, ncy * g.ua_y);  // <= 0
-    const float naP = fmaf(nax, q.px, nay * q.py), nbP = fmaf(nbx, q.px, nby * q.py);
-    const float ncP = fmaf(ncx, q.px, ncy * q.py);
-    auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
-        const float ra = z1 - q.pz;
-        const bool bb = ra >= 0.f && x1 >= fmaf(ra, umnx, q.px) && x0 <= fmaf(ra, umxx, q.px) &&
-                        y1 >= fmaf(ra, umny, q.py) && y0 <= fmaf(ra, umxy, q.py);
-        const float cx = 0.5f * (x0 + x1), cy = 0.5f * (y0 + y1);
-        const float hx = 0.5f * (x1 - x0), hy = 0.5f * (y1 - y0);
-        const bool sa = fmaf(nax, cx, nay * cy) + fmaf(fabsf(nax), hx, fabsf(nay) * hy) >= naP;
-        const bool sb = fmaf(nbx, cx, nby * cy) + fmaf(fabsf(nbx), hx, fabsf(nby) * hy) >= nbP;
-        const bool sc = fmaf(ncx, cx, ncy * cy) + fmaf(fabsf(ncx), hx, fabsf(ncy) * hy) >= fmaf(ra, kc, ncP);
-        return bb && sa && sb && sc;
-    };
+    const FanTest bt(g, q.px, q.py, q.pz);
     auto leaf = [&](int prim, int voff, int m, bool want) {
         const bool go = want && prim != q.own;
         if (!ballot(go)) return;
@@ -238,8 +168,9 @@ __device__ __forceinline__ void accrue_segment(cNode *nodes, int *stack, cfloat4
             wk.edges += go ? (uint32_t)m : 0u;
         }
         float a = 0.f, b = 0.f;
-        const int r = go ? prism_interval(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, w0, w1, W0u, W0v,
-                                          W1u, W1v, a, b)
+        float da, db;
+        const int r = go ? prism_interval<false>(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, w0, w1,
+                                                 W0u, W0v, W1u, W1v, a, b, da, db)
                          : 0;
         if constexpr (kCount) wk.inserts += r ? 1u : 0u;
         if (r) {

@@ -469,7 +469,7 @@ sa_status sa_grad_heights(sa_ctx *ctx, const sa_scene *scene, const sa_points *p
     if (rc != SA_OK) return rc;
     if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
     std::string err;
-    rc = sa::launch_grad(scene->d, path->d, view(pts), dl_dmin, grad, ctx->stream, err);
+    rc = sa::launch_grad(scene->d, path->d, view(pts), dl_dmin, grad, ctx->spill, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_grad_heights: " + err);
     return SA_OK;
 }

@@ -1,0 +1,212 @@
+// Adjoint of the accrual form with respect to building heights.
+//
+// The gross shadow of a point over a segment is the measure of the union of
+// the occluders' angular intervals, times dt/theta.  Each boundary of that
+// union is one end of one occluder's interval; when that end is a crossing
+// of the clip line z = H (the ray grazing the roof edge), it moves with the
+// height as d(angle)/dH = cross(c, c1 - c0) / (|c|^2 (z1 - z0)) (see
+// prism_interval).  So
+//     dL/dH_b = sum over points and segments of w * dt/theta *
+//               (sum of d(close)/dH - sum of d(open)/dH)
+// over the union boundaries owned by b.  The traversal is recomputed here,
+// nothing is kept from the forward pass; contributions are added with
+// atomics into the caller's gradient (original building ids).
+#include <hip/hip_runtime.h>
+
+#include "sa_internal.h"
+#include "traverse.h"
+
+namespace sa {
+namespace {
+using namespace dev;
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kSpillRounds = 12;
+constexpr int kSpillBlocks = 1024;
+
+struct GradArgs {
+    const float *dl;       // [n_bins * n] or null (all ones)
+    float *grad;           // [n_b], original ids
+    const int32_t *order;  // hierarchy position -> original id
+};
+
+__device__ __forceinline__ void grad_segment(cNode *nodes, int *stack, cfloat4 *verts, cfloat *height,
+                                             const SegConst &g, const LanePoint &q, bool active, float w0, float w1,
+                                             UnionG &U, bool &ov)
+{
+    union_clear(U);
+    ov = false;
+    if (!active) return;
+    const float W0u = cosf(w0), W0v = sinf(w0), W1u = cosf(w1), W1v = sinf(w1);
+    bool live = true;
+    if (q.own >= 0) {
+        float a, b;
+        if (backface_interval(q.nx, q.ny, g, w0, w1, a, b)) {
+            union_insert(U, a, b, -1, -1, 0.f, 0.f);
+            live = !(a <= w0 && b >= w1);
+        }
+    }
+    if (nodes == nullptr) return;
+    const FanTest bt(g, q.px, q.py, q.pz);
+    auto leaf = [&](int prim, int voff, int m, bool want) {
+        const bool go = want && prim != q.own;
+        if (!ballot(go)) return;
+        float a = 0.f, b = 0.f, da = 0.f, db = 0.f;
+        const int r = go ? prism_interval<true>(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, w0, w1,
+                                                W0u, W0v, W1u, W1v, a, b, da, db)
+                         : 0;
+        if (r) {
+            if (!union_insert(U, a, b, prim, prim, da, db)) {
+                ov = true;
+                live = false;
+            } else if (U.n == 1 && U.lo[0] <= w0 && U.hi[0] >= w1) {
+                live = false;  // the whole window is shadowed: no boundary inside it
+            }
+        }
+    };
+    const float mdx = g.e1x + g.e2x * 0.5f * g.theta, mdy = g.e1y + g.e2y * 0.5f * g.theta;
+    auto key = [&](float x0, float y0, float x1, float y1, float) { return fmaf(x0 + x1, mdx, (y0 + y1) * mdy); };
+    Work none{0, 0, 0, 0, 0, 0, 0};
+    packet_traverse<false>(nodes, stack, live, bt, leaf, key, none);
+}
+
+__device__ __forceinline__ void scatter_grad(const UnionG &U, float wscale, const GradArgs &G)
+{
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (r < U.n) {
+            if (U.plo[r] >= 0 && U.dlo[r] != 0.f) atomicAdd(&G.grad[G.order[U.plo[r]]], -wscale * U.dlo[r]);
+            if (U.phi[r] >= 0 && U.dhi[r] != 0.f) atomicAdd(&G.grad[G.order[U.phi[r]]], wscale * U.dhi[r]);
+        }
+    }
+}
+
+__device__ __forceinline__ bool roof_covered_g(cNode *nodes, int *stack, cfloat4 *verts, cfloat *height,
+                                               const LanePoint &q, bool valid)
+{
+    bool live = valid, cov = false;
+    if (nodes == nullptr) return false;
+    auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
+        return q.px >= x0 && q.px <= x1 && q.py >= y0 && q.py <= y1 && q.pz <= z1;
+    };
+    auto leaf = [&](int prim, int voff, int m, bool want) {
+        const bool t = want && prim != q.own && q.pz <= ld(height + prim) && in_footprint(verts, voff, m, q.px, q.py);
+        cov = cov || t;
+        live = live && !t;
+    };
+    auto key = [&](float, float, float, float, float) { return 0.f; };
+    Work none{0, 0, 0, 0, 0, 0, 0};
+    packet_traverse<false>(nodes, stack, live, bt, leaf, key, none);
+    return cov;
+}
+
+__global__ __launch_bounds__(kThreads) void k_grad(const Node *nodes_g, const float4 *verts_g, const float *height_g,
+                                                   const SegConst *segs_g, int J, PointArgs P, GradArgs G,
+                                                   SpillArgs S)
+{
+    cNode *nodes = nodes_g ? (cNode *)nodes_g : nullptr;
+    cfloat4 *verts = (cfloat4 *)verts_g;
+    cfloat *height = (cfloat *)height_g;
+    cSeg *segs = (cSeg *)segs_g;
+    __shared__ int s_stack[kWaves][kStackDepth];
+    int *stack = s_stack[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
+    const int64_t i = wave * 64 + lane;
+    const bool valid = i < P.n;
+    const LanePoint q = load_point(P, i, valid);
+    const bool covered = roof_covered_g(nodes, stack, verts, height, q, valid);
+    int bin = -1;
+    float w = 0.f;
+    for (int j = 0; j < J; ++j) {
+        const SegConst g = ld(segs + j);
+        if (g.bin != bin) {
+            bin = g.bin;
+            w = (valid && G.dl) ? G.dl[(int64_t)bin * P.n + i] : 1.f;
+        }
+        UnionG U;
+        bool ov;
+        grad_segment(nodes, stack, verts, height, g, q, valid && !covered && w != 0.f, 0.f, g.theta, U, ov);
+        if (valid && !covered && !ov && w != 0.f) scatter_grad(U, w * g.dt / g.theta, G);
+        spill_push(S, valid && ov, i, j, 0.f, g.theta);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_grad_spill(const Node *nodes_g, const float4 *verts_g,
+                                                         const float *height_g, const SegConst *segs_g, PointArgs P,
+                                                         GradArgs G, const int4 *in, const uint32_t *in_count,
+                                                         int32_t cap, SpillArgs S)
+{
+    cNode *nodes = nodes_g ? (cNode *)nodes_g : nullptr;
+    cfloat4 *verts = (cfloat4 *)verts_g;
+    cfloat *height = (cfloat *)height_g;
+    __shared__ int s_stack[kWaves][kStackDepth];
+    int *stack = s_stack[threadIdx.x >> 6];
+    const int64_t total = 2 * (int64_t)min((int32_t)*in_count, cap);
+    const int64_t stride = (int64_t)gridDim.x * kThreads;
+    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < total; base += stride) {
+        const int64_t t = base + threadIdx.x;
+        const bool valid = t < total;
+        int4 e = valid ? in[t >> 1] : make_int4(0, 0, 0, 0);
+        const int64_t i = e.x;
+        const int j = e.y;
+        const float ew0 = __int_as_float(e.z), ew1 = __int_as_float(e.w);
+        const float mid = 0.5f * (ew0 + ew1);
+        const float w0 = (t & 1) ? mid : ew0, w1 = (t & 1) ? ew1 : mid;
+        const LanePoint q = load_point(P, i, valid);
+        const SegConst g = segs_g[valid ? j : 0];
+        const float w = (valid && G.dl) ? G.dl[(int64_t)g.bin * P.n + i] : 1.f;
+        UnionG U;
+        bool ov;
+        grad_segment(nodes, stack, verts, height, g, q, valid, w0, w1, U, ov);
+        if (valid && !ov) scatter_grad(U, w * g.dt / g.theta, G);
+        spill_push(S, valid && ov, i, j, w0, w1);
+    }
+}
+
+__global__ void k_zero1(uint32_t *p) { *p = 0u; }
+
+__global__ void k_spill_left(const uint32_t *count, uint32_t *overflow)
+{
+    if (*count) atomicOr(overflow, 2u);
+}
+
+}  // namespace
+
+sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts, const float *dl, float *grad,
+                      SpillQueue &q, hipStream_t st, std::string &err)
+{
+    hipError_t e = hipMemsetAsync(grad, 0, sizeof(float) * (s.n_b > 0 ? s.n_b : 0), st);
+    if (e != hipSuccess) {
+        err = std::string("grad clear: ") + hipGetErrorString(e);
+        return SA_ERR_DEVICE;
+    }
+    if (pts.n == 0 || s.n_b == 0) return SA_OK;
+    const int64_t waves = (pts.n + 63) / 64;
+    const int64_t grid = (waves + kWaves - 1) / kWaves;
+    const PointArgs P{pts.n, pts.x, pts.y, pts.z, pts.nx, pts.ny, pts.owner, s.rank, s.n_b};
+    const GradArgs G{dl, grad, s.order};
+    hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, st, q.counters);
+    SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
+    hipLaunchKernelGGL(k_grad, dim3((unsigned)grid), dim3(kThreads), 0, st, s.nodes, s.verts, s.height, p.segs,
+                       p.n_segs, P, G, S);
+    int cur = 0;
+    for (int r = 0; r < kSpillRounds; ++r) {
+        hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, st, q.counters + (cur ^ 1));
+        SpillArgs S2{q.entries[cur ^ 1], q.counters + (cur ^ 1), q.counters + 2, q.capacity};
+        hipLaunchKernelGGL(k_grad_spill, dim3(kSpillBlocks), dim3(kThreads), 0, st, s.nodes, s.verts, s.height,
+                           p.segs, P, G, (const int4 *)q.entries[cur], (const uint32_t *)(q.counters + cur),
+                           q.capacity, S2);
+        cur ^= 1;
+    }
+    hipLaunchKernelGGL(k_spill_left, dim3(1), dim3(1), 0, st, (const uint32_t *)(q.counters + cur), q.counters + 2);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+        err = std::string("gradient kernels: ") + hipGetErrorString(e);
+        return SA_ERR_DEVICE;
+    }
+    return SA_OK;
+}
+
+}  // namespace sa

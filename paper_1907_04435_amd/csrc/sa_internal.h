@@ -116,7 +116,7 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
                          float scale, int32_t *counts, float *minutes, uint64_t *work,
                          SpillQueue &q, hipStream_t st, std::string &err);
 sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
-                      const float *dl, float *grad, hipStream_t st, std::string &err);
+                      const float *dl, float *grad, SpillQueue &q, hipStream_t st, std::string &err);
 sa_status launch_region_sum(const float *v, int64_t n, const int64_t *off, int32_t n_reg,
                             const float *area, double *out, Scratch &scr, hipStream_t st,
                             std::string &err);

@@ -227,16 +227,24 @@ __device__ __forceinline__ float cross2(float au, float av, float bu, float bv)
 // cross products over the clipped polygon's vertices (the kept footprint
 // vertices and the two clip crossings), and intersected with the window.
 // Returns 0: no overlap, 1: [a, b] written.
+//
+// With kGrad, da / db receive d(a)/dH and d(b)/dH: an end at a clip
+// crossing c = c0 + t (c1 - c0), t = (h - z0) / (z1 - z0), moves with the
+// roof as dc/dH = (c1 - c0) / (z1 - z0), so d(angle)/dH =
+// cross(c, c1 - c0) / (|c|^2 (z1 - z0)); ends at footprint vertices
+// (vertical edges) or clamped to the window do not move.
+template <bool kGrad>
 __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, float H, float px, float py,
                                               float pz, const SegConst &g, float w0, float w1, float W0u,
-                                              float W0v, float W1u, float W1v, float &a, float &b)
+                                              float W0v, float W1u, float W1v, float &a, float &b, float &da,
+                                              float &db)
 {
     const float h = H - pz;
     bool have = false, inside = true;
-    float lou = 0.f, lov = 0.f, hiu = 0.f, hiv = 0.f;
+    float lou = 0.f, lov = 0.f, hiu = 0.f, hiv = 0.f, dlo = 0.f, dhi = 0.f;
     float fu = 0.f, fv = 0.f, fz = 0.f, fwx = 0.f, fwy = 0.f;
     float pu = 0.f, pv = 0.f, pzv = 0.f, pwx = 0.f, pwy = 0.f;
-    auto cand = [&](float cu, float cv, bool ok) {
+    auto cand = [&](float cu, float cv, float dc, bool ok) {
         const bool first = ok && !have;
         const bool new_lo = ok && have && cross2(lou, lov, cu, cv) < 0.f;
         const bool new_hi = ok && have && cross2(hiu, hiv, cu, cv) > 0.f;
@@ -244,6 +252,10 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
         lov = (first || new_lo) ? cv : lov;
         hiu = (first || new_hi) ? cu : hiu;
         hiv = (first || new_hi) ? cv : hiv;
+        if constexpr (kGrad) {
+            dlo = (first || new_lo) ? dc : dlo;
+            dhi = (first || new_hi) ? dc : dhi;
+        }
         have = have || ok;
     };
     for (int e = 0; e <= m; ++e) {
@@ -264,12 +276,17 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
         } else {
             inside = inside && cross2(pwx, pwy, wx, wy) >= 0.f;
             const bool pin = pzv <= h;
-            const float t = (h - pzv) * __builtin_amdgcn_rcpf(z - pzv);
-            cand(fmaf(t, u - pu, pu), fmaf(t, v - pv, pv), pin != in);
+            const float rdz = __builtin_amdgcn_rcpf(z - pzv);
+            const float t = (h - pzv) * rdz;
+            const float cu = fmaf(t, u - pu, pu), cv = fmaf(t, v - pv, pv);
+            float dc = 0.f;
+            if constexpr (kGrad) dc = cross2(cu, cv, u - pu, v - pv) * rdz * __builtin_amdgcn_rcpf(fmaf(cu, cu, cv * cv));
+            cand(cu, cv, dc, pin != in);
         }
-        if (e < m) cand(u, v, in);
+        if (e < m) cand(u, v, 0.f, in);
         pu = u; pv = v; pzv = z; pwx = wx; pwy = wy;
     }
+    da = db = 0.f;
     if (inside) {
         if (h < 0.f) return 0;
         a = w0;
@@ -279,6 +296,7 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
     if (!have) return 0;
     const bool in0 = cross2(lou, lov, W0u, W0v) >= 0.f && cross2(W0u, W0v, hiu, hiv) >= 0.f;
     const bool in1 = cross2(lou, lov, W1u, W1v) >= 0.f && cross2(W1u, W1v, hiu, hiv) >= 0.f;
+    float plo, phi;
     if (in0 && in1) {
         a = w0;
         b = w1;
@@ -286,19 +304,103 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
     }
     if (in0) {
         a = w0;
-        b = fminf(fmaxf(atan2f(hiv, hiu), w0), w1);
+        phi = atan2f(hiv, hiu);
+        b = fminf(fmaxf(phi, w0), w1);
+        if constexpr (kGrad) db = (b == phi) ? dhi : 0.f;
         return 1;
     }
     if (in1) {
-        a = fminf(fmaxf(atan2f(lov, lou), w0), w1);
+        plo = atan2f(lov, lou);
+        a = fminf(fmaxf(plo, w0), w1);
+        if constexpr (kGrad) da = (a == plo) ? dlo : 0.f;
         b = w1;
         return 1;
     }
     const bool lo_in = cross2(W0u, W0v, lou, lov) >= 0.f && cross2(lou, lov, W1u, W1v) >= 0.f;
     if (!lo_in) return 0;
-    a = fminf(fmaxf(atan2f(lov, lou), w0), w1);
-    b = fminf(fmaxf(atan2f(hiv, hiu), w0), w1);
+    plo = atan2f(lov, lou);
+    phi = atan2f(hiv, hiu);
+    a = fminf(fmaxf(plo, w0), w1);
+    b = fminf(fmaxf(phi, w0), w1);
+    if constexpr (kGrad) {
+        da = (a == plo) ? dlo : 0.f;
+        db = (b == phi) ? dhi : 0.f;
+    }
     return 1;
+}
+
+// ---- interval set that also remembers, for every boundary, the prism
+// whose interval end it is and that end's d(angle)/dH ----
+struct UnionG {
+    float lo[4], hi[4], dlo[4], dhi[4];
+    int plo[4], phi[4];
+    int n;
+};
+
+__device__ __forceinline__ void union_clear(UnionG &U)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        U.lo[i] = U.hi[i] = U.dlo[i] = U.dhi[i] = 0.f;
+        U.plo[i] = U.phi[i] = -1;
+    }
+    U.n = 0;
+}
+
+// As union_insert; a merged boundary keeps the owner of the extreme end
+// (equal ends: the lower prism index, -1 for the wall term first).
+__device__ __forceinline__ bool union_insert(UnionG &U, float a, float b, int pa, int pb, float da, float db)
+{
+    int nb = 0, na = 0;
+    float mlo = a, mhi = b, mdlo = da, mdhi = db;
+    int mplo = pa, mphi = pb;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const bool use = i < U.n;
+        const bool before = use && U.hi[i] < a;
+        const bool after = use && U.lo[i] > b;
+        const bool ov = use && !before && !after;
+        nb += before;
+        na += after;
+        const bool tlo = ov && (U.lo[i] < mlo || (U.lo[i] == mlo && U.plo[i] < mplo));
+        const bool thi = ov && (U.hi[i] > mhi || (U.hi[i] == mhi && U.phi[i] < mphi));
+        mlo = tlo ? U.lo[i] : mlo;
+        mdlo = tlo ? U.dlo[i] : mdlo;
+        mplo = tlo ? U.plo[i] : mplo;
+        mhi = thi ? U.hi[i] : mhi;
+        mdhi = thi ? U.dhi[i] : mdhi;
+        mphi = thi ? U.phi[i] : mphi;
+    }
+    const int k = U.n - nb - na;
+    const int nn = nb + 1 + na;
+    if (nn > 4) return false;
+    UnionG R;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int src = j - 1 + k;
+        float slo = U.lo[0], shi = U.hi[0], sdlo = U.dlo[0], sdhi = U.dhi[0];
+        int splo = U.plo[0], sphi = U.phi[0];
+#pragma unroll
+        for (int s = 1; s < 4; ++s) {
+            const bool q = src == s;
+            slo = q ? U.lo[s] : slo;
+            shi = q ? U.hi[s] : shi;
+            sdlo = q ? U.dlo[s] : sdlo;
+            sdhi = q ? U.dhi[s] : sdhi;
+            splo = q ? U.plo[s] : splo;
+            sphi = q ? U.phi[s] : sphi;
+        }
+        const bool keep = j < nb, mid = j == nb;
+        R.lo[j] = keep ? U.lo[j] : (mid ? mlo : slo);
+        R.hi[j] = keep ? U.hi[j] : (mid ? mhi : shi);
+        R.dlo[j] = keep ? U.dlo[j] : (mid ? mdlo : sdlo);
+        R.dhi[j] = keep ? U.dhi[j] : (mid ? mdhi : sdhi);
+        R.plo[j] = keep ? U.plo[j] : (mid ? mplo : splo);
+        R.phi[j] = keep ? U.phi[j] : (mid ? mphi : sphi);
+    }
+    R.n = nn;
+    U = R;
+    return true;
 }
 
 // Facade point whose wall faces away from the sun: n . d(phi) <= 0 with
@@ -327,6 +429,101 @@ __device__ __forceinline__ int backface_interval(float nx, float ny, const SegCo
     }
     return 1;
 }
+
+struct PointArgs {
+    int64_t n;
+    const float *x, *y, *z, *nx, *ny;
+    const int32_t *owner;
+    const int32_t *rank;  // original id -> hierarchy position
+    int32_t n_b;
+};
+
+struct LanePoint {
+    float px, py, pz, nx, ny;
+    int own;  // hierarchy position of the owner, -1 for ground points
+};
+
+__device__ __forceinline__ LanePoint load_point(const PointArgs &P, int64_t i, bool valid)
+{
+    LanePoint q{0.f, 0.f, 0.f, 0.f, 0.f, -1};
+    if (valid) {
+        q.px = P.x[i];
+        q.py = P.y[i];
+        q.pz = P.z[i];
+        if (P.nx) q.nx = P.nx[i];
+        if (P.ny) q.ny = P.ny[i];
+        if (P.owner) {
+            const int o = P.owner[i];
+            q.own = (o >= 0 && o < P.n_b) ? P.rank[o] : -1;
+        }
+    }
+    return q;
+}
+
+struct SpillArgs {
+    int4 *out;          // queue to push to
+    uint32_t *counter;  // its length
+    uint32_t *overflow;
+    int32_t cap;
+};
+
+__device__ __forceinline__ void spill_push(const SpillArgs &S, bool want, int64_t i, int j, float w0, float w1)
+{
+    if (!want) return;
+    const uint32_t slot = atomicAdd(S.counter, 1u);
+    if ((int32_t)slot < S.cap)
+        S.out[slot] = make_int4((int)i, j, __float_as_int(w0), __float_as_int(w1));
+    else
+        atomicOr(S.overflow, 1u);
+}
+
+// Per-lane fan/box test of one segment: the fan of directions from p below
+// height z1 projects on the ground to the triangle p, p + (z1 - pz) ua,
+// p + (z1 - pz) ub (central projection maps the great-circle arc to a
+// segment), so the box test is a 2D separating-axis test against that
+// triangle: its bounding box and its three edge normals.
+struct FanTest {
+    float umnx, umxx, umny, umxy;
+    float nax, nay, nbx, nby, ncx, ncy, kc;
+    float naP, nbP, ncP, px, py, pz;
+
+    __device__ __forceinline__ FanTest(const SegConst &g, float px_, float py_, float pz_)
+    {
+        px = px_;
+        py = py_;
+        pz = pz_;
+        umnx = fminf(0.f, fminf(g.ua_x, g.ub_x));
+        umxx = fmaxf(0.f, fmaxf(g.ua_x, g.ub_x));
+        umny = fminf(0.f, fminf(g.ua_y, g.ub_y));
+        umxy = fmaxf(0.f, fmaxf(g.ua_y, g.ub_y));
+        nax = -g.ua_y;
+        nay = g.ua_x;
+        if (fmaf(nax, g.ub_x, nay * g.ub_y) < 0.f) { nax = -nax; nay = -nay; }
+        nbx = -g.ub_y;
+        nby = g.ub_x;
+        if (fmaf(nbx, g.ua_x, nby * g.ua_y) < 0.f) { nbx = -nbx; nby = -nby; }
+        ncx = -(g.ub_y - g.ua_y);
+        ncy = g.ub_x - g.ua_x;
+        if (fmaf(ncx, g.ua_x, ncy * g.ua_y) > 0.f) { ncx = -ncx; ncy = -ncy; }
+        kc = fmaf(ncx, g.ua_x, ncy * g.ua_y);
+        naP = fmaf(nax, px, nay * py);
+        nbP = fmaf(nbx, px, nby * py);
+        ncP = fmaf(ncx, px, ncy * py);
+    }
+
+    __device__ __forceinline__ bool operator()(float x0, float y0, float x1, float y1, float z1) const
+    {
+        const float ra = z1 - pz;
+        const bool bb = ra >= 0.f && x1 >= fmaf(ra, umnx, px) && x0 <= fmaf(ra, umxx, px) &&
+                        y1 >= fmaf(ra, umny, py) && y0 <= fmaf(ra, umxy, py);
+        const float cx = 0.5f * (x0 + x1), cy = 0.5f * (y0 + y1);
+        const float hx = 0.5f * (x1 - x0), hy = 0.5f * (y1 - y0);
+        const bool sa = fmaf(nax, cx, nay * cy) + fmaf(fabsf(nax), hx, fabsf(nay) * hy) >= naP;
+        const bool sb = fmaf(nbx, cx, nby * cy) + fmaf(fabsf(nbx), hx, fabsf(nby) * hy) >= nbP;
+        const bool sc = fmaf(ncx, cx, ncy * cy) + fmaf(fabsf(ncx), hx, fabsf(ncy) * hy) >= fmaf(ra, kc, ncP);
+        return bb && sa && sb && sc;
+    }
+};
 
 }  // namespace dev
 }  // namespace sa

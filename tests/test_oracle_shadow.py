@@ -391,3 +391,47 @@ def test_continuous_catches_runs_shorter_than_the_grid():
     fine = oracle.continuous(sc, P, path, grid_min=1.0 / 1200.0)["minutes"][0, 0]
     assert 0.0 < fine < 5.0 / 60.0
     assert coarse == pytest.approx(fine, abs=1e-6)
+
+
+# --------------------------------------------------------------------------
+# gradient with respect to heights
+# --------------------------------------------------------------------------
+def test_gradient_implicit_matches_central_differences(c1):
+    """The oracle's implicit-differentiation gradient against FP64 central
+    differences of its own continuous duration (heights rounded to float32,
+    so the difference quotient uses the actual step)."""
+    sub = c1.points.take(np.arange(5, c1.points.n, 331))
+    path = oracle.sun_path(c1.span, 30.0)
+    g = oracle.grad_implicit(c1.scene, sub, path)
+    assert np.all(g >= 0.0)                      # a taller building never shades less
+    for b in list(np.argsort(-g)[:4]) + [int(np.flatnonzero(g == 0)[0])]:
+        H = float(c1.scene.height[b])
+        hp, hm = np.float32(H + 0.01), np.float32(H - 0.01)
+        lp = oracle.continuous(oracle.with_height(c1.scene, b, hp), sub, path)["minutes"].sum()
+        lm = oracle.continuous(oracle.with_height(c1.scene, b, hm), sub, path)["minutes"].sum()
+        fd = (lp - lm) / float(hp - hm)
+        if g[b] == 0:
+            assert abs(fd) < 1e-6
+        else:
+            assert fd == pytest.approx(g[b], rel=2e-4)
+
+
+def test_gradient_lone_box_roof_crossings():
+    """A lone box on a winter morning: ground points where the tip of its
+    shadow (the roof edge) passes have a positive height derivative equal to
+    the central difference; a building far from every sun path owns no
+    boundary (zero)."""
+    span = Span(40.7, -74.0, [Day(2019, 12, 21, -5.0, (540.0, 720.0))], step_min=5.0)
+    path = oracle.sun_path(span, seg_min=30.0)
+    sc = box_scene([(-5, -5, 5, 5, 40.0), (900, 900, 910, 910, 20.0)])
+    gx, gy = np.meshgrid(np.arange(-80.0, 0.0, 8.0) + 0.5, np.arange(40.0, 140.0, 8.0) + 0.5)
+    P = pts(np.stack([gx.ravel(), gy.ravel(), np.zeros(gx.size)], 1))
+    per_point = np.array([oracle.grad_implicit(sc, P.take([i]), path) for i in range(P.n)])
+    assert np.all(per_point >= 0) and np.all(per_point[:, 1] == 0)
+    i = int(np.argmax(per_point[:, 0]))
+    assert per_point[i, 0] > 0
+    one = P.take([i])
+    hp, hm = np.float32(40.01), np.float32(39.99)
+    lp = oracle.continuous(oracle.with_height(sc, 0, hp), one, path)["minutes"].sum()
+    lm = oracle.continuous(oracle.with_height(sc, 0, hm), one, path)["minutes"].sum()
+    assert (lp - lm) / float(hp - hm) == pytest.approx(per_point[i, 0], rel=2e-4)
