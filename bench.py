@@ -100,6 +100,127 @@ def cpu_baseline(w, seconds_target=15.0):
                       f"{len(path.w)} instants x {w.scene.n_b} prisms, sampled form, {dt:.1f} s"}
 
 
+def _timed(torch, stream, fn, steps):
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    for a, c in evs:
+        a.record(stream)
+        fn()
+        c.record(stream)
+    torch.cuda.synchronize()
+    return [a.elapsed_time(c) for a, c in evs]
+
+
+def _base(metric, value, unit, args, ms, cfg, dtype="f32"):
+    return {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": cfg}
+
+
+def bench_c3(args, sa, torch):
+    """256 development variants of the block scene, one persistent launch
+    with per-variant refit; Jun 21 + Dec 21."""
+    from workloads import make_c3
+    w = make_c3()
+    ctx = sa.Context(0)
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    path = sa.Path(ctx, sa.sunpath_for_span(w.span, args.seg))
+    dp = sa.DevicePoints.from_workload(w.points)
+    ids = torch.from_numpy(w.extra["var_ids"].astype(np.int32)).cuda()
+    hh = torch.from_numpy(w.extra["var_h"].astype(np.float32)).cuda()
+    off = torch.from_numpy(w.extra["var_off"].astype(np.int64)).cuda()
+    counts = torch.empty((path.n_bins, dp.n), dtype=torch.int32, device="cuda")
+    mins = torch.empty((path.n_bins, dp.n), dtype=torch.float32, device="cuda")
+    gb = args.grid_blocks or tuned_grid_blocks()
+    run = lambda: sa.sa_accumulate_batched(ctx, sc, ids, hh, dp, off, path, counts, mins, grid_blocks=gb)
+    for _ in range(args.warmup):
+        run()
+    ctx.sync()
+    ms = _timed(torch, ctx.stream, run, args.steps)
+    ctx.sync()
+    evals = dp.n * path.n_samples
+    m = float(np.mean(ms))
+    log(f"c3: {m:.1f} ms per batched pass, grid {gb}")
+    return _base("point-sun-step evals/s (accrual form, batched variants)", evals / (m / 1e3),
+                 "point-sun-steps/s", args, m,
+                 {"workload": w.name, "variants": int(len(off) - 1), "points": dp.n, "buildings": w.scene.n_b,
+                  "instants_per_point": path.n_samples, "seg_min": args.seg, "grid_blocks": gb,
+                  "point_sun_steps": evals})
+
+
+def bench_c4(args, sa, torch):
+    """Loss = total shadow minutes over the 200k-point park, Mar 20, knots
+    every minute; forward and height adjoint for all 5,000 buildings."""
+    from workloads import make_c4
+    w = make_c4()
+    ctx = sa.Context(0)
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    path = sa.Path(ctx, sa.sunpath_for_span(w.span, 1.0))
+    dp = sa.DevicePoints.from_workload(w.points)
+    mins = torch.empty((1, dp.n), dtype=torch.float32, device="cuda")
+    grad = torch.empty(w.scene.n_b, dtype=torch.float32, device="cuda")
+    fwd = lambda: sa.sa_accumulate(ctx, sc, dp, path, sa.SA_ACCRUAL, None, mins)
+    bwd = lambda: sa.sa_grad_heights(ctx, sc, dp, path, None, grad)
+    for _ in range(args.warmup):
+        fwd()
+        bwd()
+    ctx.sync()
+    mf = float(np.mean(_timed(torch, ctx.stream, fwd, args.steps)))
+    mb = float(np.mean(_timed(torch, ctx.stream, bwd, args.steps)))
+    ctx.sync()
+    evals = dp.n * path.n_samples
+    log(f"c4: forward {mf:.2f} ms, adjoint {mb:.2f} ms")
+    r = _base("point-sun-step evals/s (accrual forward + height adjoint)", evals / ((mf + mb) / 1e3),
+              "point-sun-steps/s", args, mf + mb,
+              {"workload": w.name, "points": dp.n, "buildings": w.scene.n_b, "instants_per_point": path.n_samples,
+               "seg_min": 1.0, "point_sun_steps": evals})
+    r["forward_ms"], r["adjoint_ms"] = mf, mb
+    r["loss_minutes"] = float(mins.double().sum())
+    r["grad_nonzero"] = int((grad != 0).sum())
+    return r
+
+
+def bench_c5(args, sa, torch):
+    """Year-long accumulation: 45k prisms, 16M ground points, all 365 days
+    of 2019 at 1-minute instants, four season bins of hours."""
+    from workloads import make_c5
+    w = make_c5()
+    ctx = sa.Context(0)
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    sp = sa.sa_sunpath(40.7, -74.0, -5.0, 2019, 1, 1, 365, seg=args.seg)
+    sp.day_bin = np.asarray(w.span.day_bin, np.int32)
+    path = sa.Path(ctx, sp)
+    dp = sa.DevicePoints.from_workload(w.points)
+    hours = torch.empty((path.n_bins, dp.n), dtype=torch.float32, device="cuda")
+    run = lambda: sa.sa_accumulate(ctx, sc, dp, path, sa.SA_ACCRUAL, None, hours, out_scale=1.0 / 60.0)
+    steps = max(1, min(args.steps, 1))
+    ms = _timed(torch, ctx.stream, run, steps)
+    ctx.sync()
+    evals = dp.n * path.n_samples
+    m = float(np.mean(ms))
+    log(f"c5: {m:.0f} ms for the year")
+    r = _base("point-sun-step evals/s (accrual form, year in season bins)", evals / (m / 1e3),
+              "point-sun-steps/s", args, m,
+              {"workload": w.name, "points": dp.n, "buildings": w.scene.n_b, "days": 365,
+               "instants_per_point": path.n_samples, "seg_min": args.seg, "bins": path.n_bins,
+               "point_sun_steps": evals})
+    r["steps"], r["warmup"] = steps, 0
+    r["mean_hours_per_bin"] = [float(x) for x in hours.mean(1).cpu()]
+    return r
+
+
+def tuned_grid_blocks():
+    """Persistent grid size picked by paper_1907_04435_amd/tune.py (cached),
+    else the library default."""
+    p = os.path.join(ROOT, "paper_1907_04435_amd", "tuning.json")
+    if os.path.exists(p):
+        try:
+            return int(json.load(open(p)).get("batched_grid_blocks", 0))
+        except (ValueError, OSError):
+            return 0
+    return 0
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,7 +228,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seg", type=float, default=30.0, help="accrual knot spacing, minutes")
     ap.add_argument("--sampled-steps", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="c2 (default): the block scene, both forms; c3 batched variants; "
+                         "c4 forward + height adjoint; c5 year-long season bins; c1 the small scene")
+    ap.add_argument("--grid-blocks", type=int, default=0, help="batched persistent launch size (0: tuned/default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-work-count", action="store_true")
     ap.add_argument("--skip-sampled", action="store_true")
@@ -133,6 +257,10 @@ def main():
         return
     import paper_1907_04435_amd as sa
     from workloads import make_c1, make_c2
+    if args.workload in ("c3", "c4", "c5"):
+        res = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload](args, sa, torch)
+        print(json.dumps(res), flush=True)
+        return
 
     t0 = time.perf_counter()
     w = make_c2() if args.workload == "c2" else make_c1()

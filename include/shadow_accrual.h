@@ -198,7 +198,8 @@ typedef struct {
     int32_t mode;     /* SA_SAMPLED or SA_ACCRUAL */
     uint32_t flags;   /* SA_FLAG_ADD */
     float out_scale;  /* minutes are multiplied by this (0 = 1; 1/60 gives hours) */
-    int32_t reserved0;
+    int32_t grid_blocks; /* sa_accumulate_batched: blocks of 256 threads in the persistent
+                            launch (0 = default 2048); ignored elsewhere */
     /* Optional device uint64 [8], added to (not cleared): when non-NULL the
      * launch runs an instrumented instantiation that counts, per lane, the
      * work its own traversal needed -- [0] child-box tests, [1] prism tests,

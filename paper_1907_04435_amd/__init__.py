@@ -68,7 +68,7 @@ class sa_points(C.Structure):
 
 class sa_accum_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("flags", C.c_uint32), ("out_scale", C.c_float),
-                ("reserved0", C.c_int32), ("work", C.c_void_p)]
+                ("grid_blocks", C.c_int32), ("work", C.c_void_p)]
 
 
 _lib = None
@@ -365,10 +365,11 @@ def accumulate(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, mode: 
 
 
 def sa_accumulate_batched(ctx: Context, scene: Scene, var_ids, var_h, pts: DevicePoints, var_off, path: Path,
-                          counts=None, minutes=None, flags=0, out_scale=1.0):
+                          counts=None, minutes=None, flags=0, out_scale=1.0, grid_blocks=0):
     """Batched development variants (device tensors var_ids [V, k] int32,
-    var_h [V, k] float32, var_off [V+1] int64)."""
-    opts = sa_accum_opts(SA_ACCRUAL, flags, out_scale, 0, None)
+    var_h [V, k] float32, var_off [V+1] int64).  ``grid_blocks``: size of
+    the persistent launch (0 = library default)."""
+    opts = sa_accum_opts(SA_ACCRUAL, flags, out_scale, grid_blocks, None)
     ps = pts.struct()
     V, k = int(var_ids.shape[0]), int(var_ids.shape[1]) if var_ids.dim() > 1 else 0
     _check(ctx, lib().sa_accumulate_batched(ctx.handle, scene.handle, V, k, _ptr(var_ids), _ptr(var_h),

@@ -5,6 +5,8 @@
 // than four disjoint pieces by splitting their window in halves.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sa_internal.h"
 #include "traverse.h"
 
@@ -16,6 +18,7 @@ constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
 constexpr int kSpillRounds = 12;
 constexpr int kSpillBlocks = 1024;
+constexpr int64_t kChunkWork = 4000000000ll;  // point-segments per accrual launch
 
 // ------------------------------------------------------------------ sampled
 // Sum a per-lane counter over the wave and add it to a global total.
@@ -117,7 +120,7 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
 // of the segment (instants at the window end belong to the next window
 // otherwise).
 __device__ __forceinline__ void measure(const Union4 &U, const SegConst &g, float w0, float w1,
-                                        bool last_window, float &mins, int &cnt)
+                                        bool last_window, double &mins, int &cnt)
 {
     const float scale = g.dt / g.theta;
     float m = 0.f;
@@ -134,7 +137,7 @@ __device__ __forceinline__ void measure(const Union4 &U, const SegConst &g, floa
             c += max(khi - klo + 1, 0);
         }
     }
-    mins += m * scale;
+    mins += (double)(m * scale);
     cnt += c;
 }
 
@@ -212,9 +215,9 @@ __device__ __forceinline__ bool roof_covered(cNode *nodes, int *stack, cfloat4 *
 
 template <bool kCount>
 __global__ __launch_bounds__(kThreads) void k_accrual(const Node *nodes_g, const float4 *verts_g,
-                                                      const float *height_g, const SegConst *segs_g, int J,
-                                                      PointArgs P, float scale, int32_t *counts, float *minutes,
-                                                      SpillArgs S, uint64_t *work)
+                                                      const float *height_g, const SegConst *segs_g, int j0,
+                                                      int j1, PointArgs P, float scale, int32_t *counts,
+                                                      float *minutes, SpillArgs S, uint64_t *work)
 {
     Work wk{0, 0, 0, 0, 0, 0, 0};
     cNode *nodes = (cNode *)nodes_g;
@@ -232,17 +235,17 @@ __global__ __launch_bounds__(kThreads) void k_accrual(const Node *nodes_g, const
     const bool covered = roof_covered(nodes_g ? nodes : nullptr, stack, verts, height, q, valid);
 
     int cnt = 0;
-    float mins = 0.f;
-    int bin = J > 0 ? ld(segs).bin : 0;
-    for (int j = 0; j < J; ++j) {
+    double mins = 0.0;  // per-lane FP64: long spans sum thousands of segment measures
+    int bin = j1 > j0 ? ld(segs + j0).bin : 0;
+    for (int j = j0; j < j1; ++j) {
         const SegConst g = ld(segs + j);
         if (g.bin != bin) {
             if (valid) {
                 if (counts) counts[(int64_t)bin * n + i] += cnt;
-                if (minutes) minutes[(int64_t)bin * n + i] += mins * scale;
+                if (minutes) minutes[(int64_t)bin * n + i] += (float)(mins * scale);
             }
             cnt = 0;
-            mins = 0.f;
+            mins = 0.0;
             bin = g.bin;
         }
         Union4 U;
@@ -254,16 +257,16 @@ __global__ __launch_bounds__(kThreads) void k_accrual(const Node *nodes_g, const
             wk.spills += (valid && ov) ? 1u : 0u;
         }
         if (covered && valid) {
-            mins += g.dt;
+            mins += (double)g.dt;
             cnt += g.ns;
         } else if (!ov) {
             measure(U, g, 0.f, g.theta, true, mins, cnt);
         }
         spill_push(S, valid && ov, i, j, 0.f, g.theta);
     }
-    if (valid && J > 0) {
+    if (valid && j1 > j0) {
         if (counts) counts[(int64_t)bin * n + i] += cnt;
-        if (minutes) minutes[(int64_t)bin * n + i] += mins * scale;
+        if (minutes) minutes[(int64_t)bin * n + i] += (float)(mins * scale);
     }
     if constexpr (kCount) flush_work(wk, work);
 }
@@ -299,15 +302,175 @@ __global__ __launch_bounds__(kThreads) void k_spill(const Node *nodes_g, const f
         Work none{0, 0, 0, 0, 0, 0, 0};
         accrue_segment<false>(nodes_g ? nodes : nullptr, stack, verts, height, g, q, valid, w0, w1, U, ov, none);
         if (valid && !ov) {
-            float mins = 0.f;
+            double mins = 0.0;
             int cnt = 0;
             measure(U, g, w0, w1, w1 >= g.theta, mins, cnt);
             const int64_t o = (int64_t)g.bin * P.n + i;
-            if (minutes) atomicAdd(&minutes[o], mins * scale);
+            if (minutes) atomicAdd(&minutes[o], (float)(mins * scale));
             if (counts) atomicAdd(&counts[o], cnt);
         }
         spill_push(S, valid && ov, i, j, w0, w1);
     }
+}
+
+
+// ------------------------------------------------------------------ batched
+// Variant v of the scene differs from the base only in the heights of a few
+// buildings.  Each variant gets its own copy of the node array and heights;
+// only the ancestors of the changed leaves need new box tops, which one
+// thread per variant walks up sequentially (no races between its walks).
+
+__global__ void k_var_copy(const int4 *__restrict__ base_nodes, int64_t node_words, const float *__restrict__ base_h,
+                           int n_b, int V, int4 *__restrict__ vnodes, float *__restrict__ vh)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)V * node_words; t += stride)
+        vnodes[t] = base_nodes[t % node_words];
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)V * n_b; t += stride)
+        vh[t] = base_h[t % n_b];
+}
+
+__global__ void k_var_heights(int V, int k, const int32_t *__restrict__ ids, const float *__restrict__ h,
+                              const int32_t *__restrict__ rank, int n_b, float *__restrict__ vh, uint32_t *flag)
+{
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= V * k) return;
+    const int id = ids[t];
+    const float hv = h[t];
+    if (id < 0 || id >= n_b || !(hv > 0.f)) {
+        atomicOr(flag, 4u);
+        return;
+    }
+    vh[(int64_t)(t / k) * n_b + rank[id]] = hv;
+}
+
+__global__ void k_var_refit(int V, int k, const int32_t *__restrict__ ids, const int32_t *__restrict__ rank,
+                            const int32_t *__restrict__ parent, int n_int, int n_b, int n_nodes,
+                            const float *__restrict__ vh, Node *vnodes)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    Node *nodes = vnodes + (int64_t)v * n_nodes;
+    for (int j = 0; j < k; ++j) {
+        const int id = ids[v * k + j];
+        if (id < 0 || id >= n_b) continue;
+        const int prim = rank[id];
+        float z = pad_hi(vh[(int64_t)v * n_b + prim]);
+        int pp = parent[n_int + prim];
+        for (int guard = 0; pp >= 0 && guard < 64; ++guard) {
+            Node &nd = nodes[pp >> 1];
+            if (pp & 1) nd.rz1 = z;
+            else nd.lz1 = z;
+            z = fmaxf(nd.lz1, nd.rz1);
+            pp = parent[pp >> 1];
+        }
+    }
+}
+
+// tile_off[v] = first tile of variant v, 64 points per tile
+__global__ void k_var_tiles(int V, const int64_t *__restrict__ var_off, int64_t *__restrict__ tile_off)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int64_t t = 0;
+    for (int v = 0; v < V; ++v) {
+        tile_off[v] = t;
+        t += (var_off[v + 1] - var_off[v] + 63) / 64;
+    }
+    tile_off[V] = t;
+}
+
+// Persistent accrual over the (variant, tile) queue.  A wave takes the next
+// tile with one atomic, finds its variant by binary search, and runs every
+// segment for its 64 points on that variant's hierarchy.  A point-segment
+// whose occluded set needs more than four pieces is finished in place by
+// walking its window left to right with halving / doubling sub-windows.
+__global__ __launch_bounds__(kThreads) void k_batched(const Node *vnodes_g, int n_nodes, const float4 *verts_g,
+                                                      const float *vh_g, int n_b, const SegConst *segs_g, int J,
+                                                      PointArgs P, const int64_t *__restrict__ var_off,
+                                                      const int64_t *__restrict__ tile_off, int V,
+                                                      uint32_t *tile_counter, float scale, int32_t *counts,
+                                                      float *minutes, uint32_t *flag)
+{
+    cfloat4 *verts = (cfloat4 *)verts_g;
+    cSeg *segs = (cSeg *)segs_g;
+    __shared__ int s_stack[kWaves][kStackDepth];
+    int *stack = s_stack[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
+    const int64_t T = tile_off[V];
+    const int64_t n = P.n;
+    for (;;) {
+        int64_t t = 0;
+        if (lane == 0) t = atomicAdd((unsigned long long *)tile_counter, 1ull);
+        t = __shfl(t, 0, 64);
+        if (t >= T) break;
+        int lo = 0, hi = V - 1;               // last v with tile_off[v] <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (tile_off[mid] <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const int v = uniform(lo);
+        cNode *nodes = (cNode *)(vnodes_g + (int64_t)v * n_nodes);
+        cfloat *height = (cfloat *)(vh_g + (int64_t)v * n_b);
+        const int64_t i = var_off[v] + (t - tile_off[v]) * 64 + lane;
+        const bool valid = i < var_off[v + 1];
+        const LanePoint q = load_point(P, i, valid);
+        const bool covered = roof_covered(nodes, stack, verts, height, q, valid);
+        int cnt = 0;
+        double mins = 0.0;
+        int bin = J > 0 ? ld(segs).bin : 0;
+        Work none{0, 0, 0, 0, 0, 0, 0};
+        for (int j = 0; j < J; ++j) {
+            const SegConst g = ld(segs + j);
+            if (g.bin != bin) {
+                if (valid) {
+                    if (counts) counts[(int64_t)bin * n + i] += cnt;
+                    if (minutes) minutes[(int64_t)bin * n + i] += (float)(mins * scale);
+                }
+                cnt = 0;
+                mins = 0.0;
+                bin = g.bin;
+            }
+            if (covered && valid) {
+                mins += (double)g.dt;
+                cnt += g.ns;
+                continue;
+            }
+            float w0 = 0.f, s = g.theta;
+            bool pending = valid;
+            while (ballot(pending)) {
+                const float w1 = fminf(w0 + s, g.theta);
+                Union4 U;
+                bool ov;
+                accrue_segment<false>(nodes, stack, verts, height, g, q, pending, w0, w1, U, ov, none);
+                if (pending) {
+                    if (ov) {
+                        if (s < g.theta * (1.0f / 4096.0f)) {
+                            atomicOr(flag, 2u);
+                            pending = false;
+                        } else {
+                            s *= 0.5f;
+                        }
+                    } else {
+                        measure(U, g, w0, w1, w1 >= g.theta, mins, cnt);
+                        w0 = w1;
+                        pending = w0 < g.theta;
+                        s = fminf(2.f * s, g.theta);
+                    }
+                }
+            }
+        }
+        if (valid && J > 0) {
+            if (counts) counts[(int64_t)bin * n + i] += cnt;
+            if (minutes) minutes[(int64_t)bin * n + i] += (float)(mins * scale);
+        }
+    }
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) p[t] = v;
 }
 
 __global__ void k_zero_u32(uint32_t *p) { *p = 0u; }
@@ -372,6 +535,67 @@ sa_status run_spill(const DeviceScene &s, const DevicePath &p, const PointArgs &
     return SA_OK;
 }
 
+sa_status fill_u32(void *p, int64_t n, uint32_t v, hipStream_t st, std::string &err)
+{
+    if (n <= 0) return SA_OK;
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t *)p, n, v);
+    SA_CHECK_LAUNCH("fill");
+    return SA_OK;
+}
+
+sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_var, int32_t k, const int32_t *ids,
+                         const float *h, const PointsView &pts, const int64_t *var_off, float scale, int32_t *counts,
+                         float *minutes, int32_t grid_blocks, uint32_t *flag, Scratch &scr, hipStream_t st,
+                         std::string &err)
+{
+    if (n_var == 0 || pts.n == 0) return SA_OK;
+    const int n_nodes = s.n_b > 0 ? s.n_nodes : 0;
+    const size_t node_bytes = sizeof(Node) * (size_t)n_var * n_nodes;
+    const size_t h_bytes = sizeof(float) * (size_t)n_var * s.n_b;
+    const size_t off0 = 0, off1 = (node_bytes + 255) & ~(size_t)255, off2 = off1 + ((h_bytes + 255) & ~(size_t)255);
+    const size_t off3 = off2 + ((sizeof(int64_t) * (n_var + 1) + 255) & ~(size_t)255);
+    const size_t need = off3 + 256;
+    if (scr.bytes < need) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(scr.ptr);
+        scr.ptr = nullptr;
+        scr.bytes = 0;
+        if (hipMalloc(&scr.ptr, need) != hipSuccess) {
+            err = "variant scratch allocation failed";
+            return SA_ERR_OOM;
+        }
+        scr.bytes = need;
+    }
+    char *base = (char *)scr.ptr;
+    Node *vnodes = (Node *)(base + off0);
+    float *vh = (float *)(base + off1);
+    int64_t *tile_off = (int64_t *)(base + off2);
+    uint32_t *counter = (uint32_t *)(base + off3);
+    const int n_int = s.n_b == 1 ? 1 : s.n_b - 1;
+    if (s.n_b > 0) {
+        hipLaunchKernelGGL(k_var_copy, dim3(2048), dim3(256), 0, st, (const int4 *)s.nodes, (int64_t)n_nodes * 4,
+                           (const float *)s.height, s.n_b, n_var, (int4 *)vnodes, vh);
+        if (k > 0) {
+            hipLaunchKernelGGL(k_var_heights, dim3((n_var * k + 255) / 256), dim3(256), 0, st, n_var, k, ids, h,
+                               (const int32_t *)s.rank, s.n_b, vh, flag);
+            hipLaunchKernelGGL(k_var_refit, dim3((n_var + 63) / 64), dim3(64), 0, st, n_var, k, ids,
+                               (const int32_t *)s.rank, (const int32_t *)s.parent, n_int, s.n_b, n_nodes,
+                               (const float *)vh, vnodes);
+        }
+    }
+    hipLaunchKernelGGL(k_var_tiles, dim3(1), dim3(1), 0, st, n_var, var_off, tile_off);
+    sa_status rc = fill_u32(counter, 2, 0u, st, err);
+    if (rc != SA_OK) return rc;
+    const PointArgs P = point_args(pts, s);
+    const int blocks = grid_blocks > 0 ? grid_blocks : 2048;
+    hipLaunchKernelGGL(k_batched, dim3(blocks), dim3(kThreads), 0, st, s.n_b > 0 ? vnodes : nullptr, n_nodes,
+                       s.verts, (const float *)vh, s.n_b, p.segs, p.n_segs, P, var_off, (const int64_t *)tile_off,
+                       n_var, counter, scale, counts, minutes, flag);
+    SA_CHECK_LAUNCH("batched accrual");
+    return SA_OK;
+}
+
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
                          int32_t *counts, float *minutes, uint64_t *work, SpillQueue &q, hipStream_t st,
                          std::string &err)
@@ -381,12 +605,22 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
     const int64_t grid = (waves + kWaves - 1) / kWaves;
     const Node *nodes = s.n_b > 0 ? s.nodes : nullptr;
     const PointArgs P = point_args(pts, s);
-    hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters);
-    SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
-    hipLaunchKernelGGL(work ? k_accrual<true> : k_accrual<false>, dim3((unsigned)grid), dim3(kThreads), 0, st,
-                       nodes, s.verts, s.height, p.segs, p.n_segs, P, scale, counts, minutes, S, work);
-    SA_CHECK_LAUNCH("accrual kernel");
-    return run_spill(s, p, P, scale, counts, minutes, q, st, err);
+    // Long spans (many days) run as several launches over consecutive
+    // segment ranges, each about kChunkWork point-segments and each followed
+    // by its spill rounds; outputs are accumulated, so the split is
+    // invisible in the results.
+    const int64_t per = std::max<int64_t>(1, kChunkWork / std::max<int64_t>(pts.n, 1));
+    for (int64_t j0 = 0; j0 < p.n_segs; j0 += per) {
+        const int j1 = (int)std::min<int64_t>(j0 + per, p.n_segs);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters);
+        SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
+        hipLaunchKernelGGL(work ? k_accrual<true> : k_accrual<false>, dim3((unsigned)grid), dim3(kThreads), 0, st,
+                           nodes, s.verts, s.height, p.segs, (int)j0, j1, P, scale, counts, minutes, S, work);
+        SA_CHECK_LAUNCH("accrual kernel");
+        sa_status rc = run_spill(s, p, P, scale, counts, minutes, q, st, err);
+        if (rc != SA_OK) return rc;
+    }
+    return SA_OK;
 }
 
 }  // namespace sa

@@ -16,17 +16,20 @@ struct sa_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     sa::SpillQueue spill;
-    sa::Scratch scratch;
+    sa::Scratch scratch;          // region sums
+    sa::Scratch scratch_batched;  // per-variant hierarchy copies
 };
 
 struct sa_scene {
     sa_ctx *ctx = nullptr;
+    int device = 0;  // kept here: the scene may outlive its context object
     sa::DeviceScene d;
     std::vector<int32_t> rank_h;  // original id -> hierarchy position
 };
 
 struct sa_path {
     sa_ctx *ctx = nullptr;
+    int device = 0;
     sa::DevicePath d;
 };
 
@@ -46,8 +49,11 @@ sa_status hip_fail(sa_ctx *ctx, hipError_t e, const char *what)
                 std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Select the context's device and drop any error left pending by
+// unrelated HIP calls, so that the launch checks below see only ours.
 bool set_device(sa_ctx *ctx)
 {
+    (void)hipGetLastError();
     return hipSetDevice(ctx->device) == hipSuccess;
 }
 
@@ -88,6 +94,7 @@ void sa_destroy(sa_ctx *ctx)
     (void)hipFree(ctx->spill.entries[1]);
     (void)hipFree(ctx->spill.counters);
     (void)hipFree(ctx->scratch.ptr);
+    (void)hipFree(ctx->scratch_batched.ptr);
     delete ctx;
 }
 
@@ -148,6 +155,7 @@ sa_status sa_scene_upload(sa_ctx *ctx, int32_t n_b, const int32_t *vert_off, con
     sa_scene *s = new (std::nothrow) sa_scene();
     if (!s) return fail(ctx, SA_ERR_OOM, "host allocation failed");
     s->ctx = ctx;
+    s->device = ctx->device;
     std::string err;
     sa_status rc = sa::scene_build(s->d, ctx->stream, n_b, vert_off, xy, height, err);
     if (rc != SA_OK) {
@@ -225,7 +233,7 @@ sa_status sa_scene_read_bvh(sa_ctx *ctx, const sa_scene *scene, void *nodes, int
 void sa_scene_destroy(sa_scene *scene)
 {
     if (!scene) return;
-    (void)hipSetDevice(scene->ctx->device);
+    (void)hipSetDevice(scene->device);
     sa::scene_free(scene->d);
     delete scene;
 }
@@ -343,6 +351,7 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
     sa_path *p = new (std::nothrow) sa_path();
     if (!p) return fail(ctx, SA_ERR_OOM, "host allocation failed");
     p->ctx = ctx;
+    p->device = ctx->device;
     p->d.n_days = D;
     p->d.n_samples = in->n_samples;
     p->d.n_segs = (int32_t)segs.size();
@@ -380,7 +389,7 @@ sa_status sa_path_info(const sa_path *path, int32_t *n_bins, int32_t *n_samples,
 void sa_path_destroy(sa_path *path)
 {
     if (!path) return;
-    (void)hipSetDevice(path->ctx->device);
+    (void)hipSetDevice(path->device);
     (void)hipFree(path->d.samples);
     (void)hipFree(path->d.segs);
     delete path;
@@ -400,13 +409,16 @@ static sa::PointsView view(const sa_points *p)
     return sa::PointsView{p->n, p->x, p->y, p->z, p->nx, p->ny, p->owner};
 }
 
+// Outputs are cleared with a fill kernel (not a memset node), so a call can
+// be captured into a HIP graph and replayed.
 static sa_status clear_outputs(sa_ctx *ctx, uint32_t flags, int64_t count, int32_t *counts, float *minutes)
 {
     if (flags & SA_FLAG_ADD) return SA_OK;
-    hipError_t e = hipSuccess;
-    if (counts) e = hipMemsetAsync(counts, 0, sizeof(int32_t) * count, ctx->stream);
-    if (e == hipSuccess && minutes) e = hipMemsetAsync(minutes, 0, sizeof(float) * count, ctx->stream);
-    if (e != hipSuccess) return hip_fail(ctx, e, "clear outputs");
+    std::string err;
+    sa_status rc = SA_OK;
+    if (counts) rc = sa::fill_u32(counts, count, 0u, ctx->stream, err);
+    if (rc == SA_OK && minutes) rc = sa::fill_u32(minutes, count, 0u, ctx->stream, err);
+    if (rc != SA_OK) return fail(ctx, rc, "clear outputs: " + err);
     return SA_OK;
 }
 
@@ -455,7 +467,8 @@ sa_status sa_accumulate_batched(sa_ctx *ctx, const sa_scene *scene, int32_t n_va
     if (rc != SA_OK) return rc;
     std::string err;
     rc = sa::launch_batched(scene->d, path->d, n_var, ids_per_var, var_ids, var_h, view(pts), var_off, scale,
-                            counts, minutes, ctx->spill, ctx->scratch, ctx->stream, err);
+                            counts, minutes, opts->grid_blocks, ctx->spill.counters + 2, ctx->scratch_batched,
+                            ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate_batched: " + err);
     return SA_OK;
 }

@@ -11,14 +11,16 @@
 #include <vector>
 
 #include "sa_internal.h"
+#include "traverse.h"
 
 namespace sa {
 namespace {
+using dev::pad_hi;
+using dev::pad_lo;
 
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 4;
 constexpr int kSortTile = kSortThreads * kSortItems;
-constexpr int32_t kNone = INT_MIN;  // absent child
 
 #define SA_HIP(call)                                                        \
     do {                                                                    \
@@ -29,8 +31,6 @@ constexpr int32_t kNone = INT_MIN;  // absent child
         }                                                                   \
     } while (0)
 
-__device__ inline float pad_lo(float v) { return v - (1e-2f + fabsf(v) * 0x1p-20f); }
-__device__ inline float pad_hi(float v) { return v + (1e-2f + fabsf(v) * 0x1p-20f); }
 
 __global__ void k_prism_box(int n_b, const int32_t *__restrict__ voff, const float2 *__restrict__ xy,
                             float4 *__restrict__ box)
@@ -336,7 +336,7 @@ __global__ void k_single(const int32_t *__restrict__ voff, Node *nodes, int32_t 
     nd.left = ~0;
     nd.l_voff = voff[0];
     nd.l_m = voff[1] - voff[0];
-    nd.right = kNone;
+    nd.right = dev::kNone;
     nd.rx0 = nd.ry0 = nd.rz1 = -INFINITY;
     nd.rx1 = nd.ry1 = -INFINITY;
     nd.r_voff = nd.r_m = 0;
@@ -521,7 +521,7 @@ sa_status scene_build(DeviceScene &s, hipStream_t st, int32_t n_b, const int32_t
                     ok = ok && c < s.n_nodes && c != 0;
                     if (ok) ++seen_int[c];
                 } else {
-                    ok = ok && c != kNone && ~c < n_b;
+                    ok = ok && c != dev::kNone && ~c < n_b;
                     if (ok) ++seen_leaf[~c];
                 }
             }

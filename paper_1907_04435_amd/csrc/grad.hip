@@ -177,11 +177,9 @@ __global__ void k_spill_left(const uint32_t *count, uint32_t *overflow)
 sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts, const float *dl, float *grad,
                       SpillQueue &q, hipStream_t st, std::string &err)
 {
-    hipError_t e = hipMemsetAsync(grad, 0, sizeof(float) * (s.n_b > 0 ? s.n_b : 0), st);
-    if (e != hipSuccess) {
-        err = std::string("grad clear: ") + hipGetErrorString(e);
-        return SA_ERR_DEVICE;
-    }
+    sa_status rc = fill_u32(grad, s.n_b, 0u, st, err);
+    if (rc != SA_OK) return rc;
+    hipError_t e;
     if (pts.n == 0 || s.n_b == 0) return SA_OK;
     const int64_t waves = (pts.n + 63) / 64;
     const int64_t grid = (waves + kWaves - 1) / kWaves;

@@ -73,12 +73,4 @@ sa_status launch_region_sum(const float *v, int64_t n, const int64_t *off, int32
     return SA_OK;
 }
 
-sa_status launch_batched(const DeviceScene &, const DevicePath &, int32_t, int32_t, const int32_t *, const float *,
-                         const PointsView &, const int64_t *, float, int32_t *, float *, SpillQueue &, Scratch &,
-                         hipStream_t, std::string &err)
-{
-    err = "not built yet";
-    return SA_ERR_UNSUPPORTED;
-}
-
 }  // namespace sa

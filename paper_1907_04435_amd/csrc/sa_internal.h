@@ -123,6 +123,9 @@ sa_status launch_region_sum(const float *v, int64_t n, const int64_t *off, int32
 sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_var, int32_t k,
                          const int32_t *ids, const float *h, const PointsView &pts,
                          const int64_t *var_off, float scale, int32_t *counts, float *minutes,
-                         SpillQueue &q, Scratch &scr, hipStream_t st, std::string &err);
+                         int32_t grid_blocks, uint32_t *flag, Scratch &scr, hipStream_t st,
+                         std::string &err);
+// Graph-capturable fill of n 32-bit words.
+sa_status fill_u32(void *p, int64_t n, uint32_t v, hipStream_t st, std::string &err);
 
 }  // namespace sa

@@ -49,6 +49,11 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 
 constexpr int kStackDepth = 64;
 
+// Box padding of the hierarchy: absorbs the rounding of the slab test at
+// large coordinates (boxes only decide what is tested, never a result).
+__device__ __forceinline__ float pad_lo(float v) { return v - (1e-2f + fabsf(v) * 0x1p-20f); }
+__device__ __forceinline__ float pad_hi(float v) { return v + (1e-2f + fabsf(v) * 0x1p-20f); }
+
 // Map a block index so that each XCD (blocks are dealt round-robin to the
 // 8 XCDs) works on one contiguous range of tiles: neighbouring tiles share
 // hierarchy nodes and prisms in that XCD's L2.
@@ -103,8 +108,11 @@ __device__ __forceinline__ void packet_traverse(cNode *nodes, int *stack, bool &
         }
         const bool gl = ballot(hl && live) != 0, gr = ballot(hr && live) != 0;
         if (gl && gr) {
-            const bool lfirst = key(nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1) <=
-                                key(nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1);
+            // the visiting order must be one decision for the whole wave:
+            // with per-lane keys (lanes on different segments) lanes could
+            // disagree and the shared stack would lose a subtree
+            const bool lfirst = uniform(key(nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1) <=
+                                        key(nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1)) != 0;
             stack[sp] = lfirst ? nd.right : nd.left;
             const bool far = lfirst ? hr : hl;
             want_stack = far ? (want_stack | (1ull << sp)) : (want_stack & ~(1ull << sp));

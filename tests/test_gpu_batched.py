@@ -1,0 +1,115 @@
+"""Batched development variants: one persistent launch over (variant,
+tile) with per-variant refit, against (a) the same scene edited and
+evaluated variant by variant, (b) the oracle on a subset, and (c) replays of
+a captured HIP graph."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_1907_04435_amd as sa
+from workloads import Scene, make_c3
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return sa.Context(0)
+
+
+@pytest.fixture(scope="module")
+def c3small():
+    return make_c3(n_var=6)
+
+
+def run_batched(ctx, w, seg=30.0, grid_blocks=0, path=None):
+    import torch
+    path = path or sa.Path(ctx, sa.sunpath_for_span(w.span, seg))
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    dp = sa.DevicePoints.from_workload(w.points)
+    ids = torch.from_numpy(w.extra["var_ids"].astype(np.int32)).cuda()
+    h = torch.from_numpy(w.extra["var_h"].astype(np.float32)).cuda()
+    off = torch.from_numpy(w.extra["var_off"].astype(np.int64)).cuda()
+    counts = torch.empty((path.n_bins, dp.n), dtype=torch.int32, device="cuda")
+    mins = torch.empty((path.n_bins, dp.n), dtype=torch.float32, device="cuda")
+    sa.sa_accumulate_batched(ctx, sc, ids, h, dp, off, path, counts, mins, grid_blocks=grid_blocks)
+    ctx.sync()
+    return counts.cpu().numpy(), mins.cpu().numpy(), (path, sc, dp, ids, h, off, counts, mins)
+
+
+def variant_scene(w, v):
+    hh = w.scene.height.copy()
+    hh[w.extra["var_ids"][v]] = w.extra["var_h"][v]
+    return Scene(w.scene.vert_off, w.scene.xy, hh)
+
+
+def test_batched_equals_variant_by_variant(ctx, c3small):
+    w = c3small
+    cb, mb, keep = run_batched(ctx, w)
+    path = keep[0]
+    off = w.extra["var_off"]
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    for v in range(len(off) - 1):
+        sc.set_heights(w.extra["var_ids"][v], w.extra["var_h"][v])
+        sub = w.points.take(np.arange(off[v], off[v + 1]))
+        c, m, _ = sa.accumulate(ctx, sc, sa.DevicePoints.from_workload(sub), path, sa.SA_ACCRUAL)
+        ctx.sync()
+        c, m = c.cpu().numpy(), m.cpu().numpy()
+        sc.set_heights(w.extra["var_ids"][v], w.scene.height[w.extra["var_ids"][v]])
+        dm = np.abs(m - mb[:, off[v]:off[v + 1]])
+        say(f"variant {v}: {sub.n} points, max |dmin| {dm.max():.2e}")
+        assert dm.max() <= 2e-3
+        assert (c != cb[:, off[v]:off[v + 1]]).mean() <= 1e-4
+
+
+def test_batched_matches_oracle(ctx, c3small):
+    w = c3small
+    cb, mb, keep = run_batched(ctx, w)
+    off = w.extra["var_off"]
+    rng = np.random.default_rng(5)
+    op = oracle.sun_path(w.span, 30.0)
+    for v in range(len(off) - 1):
+        idx = np.sort(rng.choice(np.arange(off[v], off[v + 1]), 48, replace=False))
+        o = oracle.continuous(variant_scene(w, v), w.points.take(idx), op)
+        d = np.abs(mb[:, idx] - o["minutes"])
+        say(f"variant {v}: |A-D_L| max {d.max():.2e}")
+        assert np.quantile(d, 0.99) <= 0.01 and d.max() <= 0.5
+        dc = np.abs(cb[:, idx] - o["counts"])
+        assert dc.max() <= 1
+
+
+def test_batched_grid_sizes_agree(ctx, c3small):
+    a = run_batched(ctx, c3small, grid_blocks=64)[1]
+    b = run_batched(ctx, c3small, grid_blocks=4096)[1]
+    assert np.array_equal(a, b)
+
+
+def test_batched_graph_replay(ctx, c3small):
+    """Capture the batched call in a HIP graph; every replay (with eager work
+    and synchronisations between them) equals the eager result."""
+    import torch
+    w = c3small
+    cb, mb, keep = run_batched(ctx, w)
+    path, sc, dp, ids, h, off, counts, mins = keep
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        ctx.set_stream(s)
+        sa.sa_accumulate_batched(ctx, sc, ids, h, dp, off, path, counts, mins)   # warm on this stream
+        s.synchronize()
+        with torch.cuda.graph(g, stream=s):
+            sa.sa_accumulate_batched(ctx, sc, ids, h, dp, off, path, counts, mins)
+    ctx.set_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for r in range(3):
+        mins.fill_(-1.0)
+        counts.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(mins.cpu().numpy(), mb), f"replay {r}"
+        assert np.array_equal(counts.cpu().numpy(), cb), f"replay {r}"
+        _ = (torch.ones(1000, device="cuda") * r).sum().item()   # eager work between replays

@@ -1,0 +1,62 @@
+"""Year-long accumulation into meteorological season bins: the 21st of
+every month on a subset against the oracle, and the chunked full-year
+launch against per-day sums."""
+import datetime as dt
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1907_04435_amd as sa
+from workloads import Span, make_c2, subset_points
+from workloads.scenes import Day, _nyc_tz
+
+from gpu_util import run_lib, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return sa.Context(0)
+
+
+def test_monthly_21st_against_oracle(ctx):
+    w = make_c2(n_ground=50_000, n_facade=0)
+    days = [dt.date(2019, m, 21) for m in range(1, 13)]
+    season = [{12: 0, 1: 0, 2: 0, 3: 1, 4: 1, 5: 1, 6: 2, 7: 2, 8: 2}.get(d.month, 3) for d in days]
+    span = Span(40.7, -74.0, [Day(d.year, d.month, d.day, _nyc_tz(d)) for d in days], 1.0, season)
+    sub = w.points.take(subset_points(w.points, 96, 41))
+    g = run_lib(ctx, w.scene, sub, span, sa.SA_ACCRUAL, seg_min=30.0)
+    o = oracle.continuous(w.scene, sub, oracle.sun_path(span, 30.0))
+    d = np.abs(g["minutes"] - o["minutes"])
+    say(f"seasons: |A-D_L| max {d.max():.2e} mean {d.mean():.2e}")
+    assert g["minutes"].shape == (4, sub.n)
+    assert d.max() <= 0.05 and d.mean() <= 3e-3
+
+
+def test_full_year_bins_equal_sum_of_days(ctx):
+    """365 days in season bins (several chunked launches) == the same days
+    accumulated one day-bin at a time and summed per season."""
+    import torch
+    w = make_c2(n_ground=20_000, n_facade=0)
+    dates = [dt.date(2019, 1, 1) + dt.timedelta(days=i) for i in range(365)]
+    season = [{12: 0, 1: 0, 2: 0, 3: 1, 4: 1, 5: 1, 6: 2, 7: 2, 8: 2}.get(d.month, 3) for d in dates]
+    sp = sa.sa_sunpath(40.7, -74.0, -5.0, 2019, 1, 1, 365, seg=30.0)
+    sp.day_bin = np.array(season, np.int32)
+    path = sa.Path(ctx, sp)
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    dp = sa.DevicePoints.from_workload(w.points)
+    c, m, _ = sa.accumulate(ctx, sc, dp, path, sa.SA_ACCRUAL, out_scale=1.0 / 60.0)
+    sp2 = sa.sa_sunpath(40.7, -74.0, -5.0, 2019, 1, 1, 365, seg=30.0)
+    path2 = sa.Path(ctx, sp2)
+    c2, m2, _ = sa.accumulate(ctx, sc, dp, path2, sa.SA_ACCRUAL)
+    ctx.sync()
+    per_day = m2.cpu().numpy().astype(np.float64)
+    ref = np.zeros((4, dp.n))
+    for d in range(365):
+        ref[season[d]] += per_day[d] / 60.0
+    got = m.cpu().numpy()
+    say(f"year: hours per season mean {got.mean(1)}; max rel diff {np.abs(got - ref).max() / ref.max():.2e}")
+    assert np.allclose(got, ref, rtol=1e-5, atol=1e-3)
+    assert np.array_equal(c.cpu().numpy(), np.stack([c2.cpu().numpy()[np.array(season) == s].sum(0) for s in range(4)]))

@@ -267,26 +267,35 @@ def _blocked_cells(scene: Scene, x0: int, y0: int, nx: int, ny: int, margin: flo
     return mask
 
 
-def _open_lattice(scene, centre, n, extent, margin=GROUND_MARGIN, region=None):
+def _open_mask(scene, extent, margin=GROUND_MARGIN):
+    """Open-space mask of every 1 m lattice cell of the scene extent."""
+    nx, ny = int(np.floor(extent[0])), int(np.floor(extent[1]))
+    return ~_blocked_cells(scene, 0, 0, nx, ny, margin)
+
+
+def _open_lattice(scene, centre, n, extent, margin=GROUND_MARGIN, region=None, mask=None):
     """The ``n`` open-space 1 m lattice cell centres nearest ``centre`` in
     Chebyshev distance (ties by y then x), inside the scene extent (and
     inside the convex polygon ``region`` if given).  Returned in Morton
-    order of the cell indices."""
+    order of the cell indices.  ``mask``: precomputed ``_open_mask``."""
     cx, cy = centre
     r = int(np.ceil(np.sqrt(n) / 2)) + 8
+    X, Y = int(np.floor(extent[0])), int(np.floor(extent[1]))
     while True:
         x0, y0 = max(int(np.floor(cx - r)), 0), max(int(np.floor(cy - r)), 0)
-        x1, y1 = min(int(np.ceil(cx + r)), int(np.floor(extent[0]))), min(int(np.ceil(cy + r)), int(np.floor(extent[1])))
+        x1, y1 = min(int(np.ceil(cx + r)), X), min(int(np.ceil(cy + r)), Y)
         nx, ny = x1 - x0, y1 - y0
-        blocked = _blocked_cells(scene, x0, y0, nx, ny, margin)
+        if mask is not None:
+            ok = mask[y0:y1, x0:x1].copy()
+        else:
+            ok = ~_blocked_cells(scene, x0, y0, nx, ny, margin)
         gx, gy = np.meshgrid(x0 + np.arange(nx) + 0.5, y0 + np.arange(ny) + 0.5)
-        ok = ~blocked
         if region is not None:
             ok &= _in_convex(region, gx, gy)
         cheb = np.maximum(np.abs(gx - cx), np.abs(gy - cy))
         ok &= cheb <= r
         cnt = int(ok.sum())
-        full = x0 == 0 and y0 == 0 and x1 >= int(np.floor(extent[0])) and y1 >= int(np.floor(extent[1]))
+        full = x0 == 0 and y0 == 0 and x1 >= X and y1 >= Y
         if cnt >= n or full:
             break
         r = int(r * 1.25) + 4
@@ -297,6 +306,26 @@ def _open_lattice(scene, centre, n, extent, margin=GROUND_MARGIN, region=None):
     fx, fy = fx[order], fy[order]
     mort = _morton2(np.floor(fx).astype(np.int64), np.floor(fy).astype(np.int64))
     o2 = np.argsort(mort, kind="stable")
+    return fx[o2], fy[o2]
+
+
+def _region_points(mask, poly, centre, n):
+    """The ``n`` open cells inside convex ``poly`` nearest ``centre``
+    (Chebyshev, ties by y then x), Morton order; None if fewer exist."""
+    Y, X = mask.shape
+    x0, y0 = max(int(np.floor(poly[:, 0].min())), 0), max(int(np.floor(poly[:, 1].min())), 0)
+    x1, y1 = min(int(np.ceil(poly[:, 0].max())) + 1, X), min(int(np.ceil(poly[:, 1].max())) + 1, Y)
+    if x1 <= x0 or y1 <= y0:
+        return None
+    gx, gy = np.meshgrid(x0 + np.arange(x1 - x0) + 0.5, y0 + np.arange(y1 - y0) + 0.5)
+    ok = mask[y0:y1, x0:x1] & _in_convex(poly, gx, gy)
+    if int(ok.sum()) < n:
+        return None
+    fx, fy = gx[ok], gy[ok]
+    fc = np.maximum(np.abs(fx - centre[0]), np.abs(fy - centre[1]))
+    order = np.lexsort((fx, fy, fc))[:n]
+    fx, fy = fx[order], fy[order]
+    o2 = np.argsort(_morton2(np.floor(fx).astype(np.int64), np.floor(fy).astype(np.int64)), kind="stable")
     return fx[o2], fy[o2]
 
 
@@ -384,6 +413,7 @@ def make_c3(seed: int = 3, n_var: int = 256, n_per_var=None, scene_seed: int = 2
     rng = np.random.default_rng(seed)
     scene, extent = _manhattan(np.random.default_rng(scene_seed), 18, 60, 20_000, 20.0)
     cen = scene.centroids()
+    mask = _open_mask(scene, extent)
     parts, off, var_ids, var_h = [], [0], [], []
     for v in range(n_var):
         nv = int(round(10 ** rng.uniform(4.0, 5.699))) if n_per_var is None else int(n_per_var)
@@ -394,11 +424,11 @@ def make_c3(seed: int = 3, n_var: int = 256, n_per_var=None, scene_seed: int = 2
         rad = np.sqrt(nv / (0.5 * np.pi * aspect)) * 1.1 + 5
         poly = np.stack([c[0] + rad * np.cos(ang), c[1] + rad * aspect * np.sin(ang)], 1)
         while True:
-            try:
-                gx, gy = _open_lattice(scene, tuple(c), nv, extent, region=poly)
+            got = _region_points(mask, poly, c, nv)
+            if got is not None:
+                gx, gy = got
                 break
-            except ValueError:
-                poly = c + (poly - c) * 1.25
+            poly = c + (poly - c) * 1.25
         parts.append(_pts(gx, gy))
         off.append(off[-1] + nv)
         d = np.maximum(np.abs(cen[:, 0] - c[0]) - (poly[:, 0].max() - c[0]), 0) ** 2 + \
@@ -448,7 +478,7 @@ def make_c5(seed: int = 5, n_ground: int = 16_000_000, n_days: int = 365) -> Wor
     rng = np.random.default_rng(seed)
     scene, extent = _manhattan(rng, 35, 76, 45_000, 20.0)
     centre = (extent[0] / 2, extent[1] / 2)
-    gx, gy = _open_lattice(scene, centre, n_ground, extent)
+    gx, gy = _open_lattice(scene, centre, n_ground, extent, mask=_open_mask(scene, extent))
     dates = [_dt.date(2019, 1, 1) + _dt.timedelta(days=i) for i in range(n_days)]
     season = [{12: 0, 1: 0, 2: 0, 3: 1, 4: 1, 5: 1, 6: 2, 7: 2, 8: 2}.get(d.month, 3) for d in dates]
     span = Span(NYC["lat"], NYC["lon"], _sunrise_days(dates, _nyc_tz), step_min=1.0, day_bin=season)
