@@ -81,14 +81,14 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
                 return fmaxf(fmaxf(tnx, tny), 0.f) <= fminf(fminf(tfx, tfy), tfz);
             };
             auto leaf = [&](int prim, int voff, int m, bool want) {
-                const bool go = want && prim != q.own;
+                const bool go = want & (prim != q.own);
                 if constexpr (kCount) {
                     wk.prism += go ? 1u : 0u;
                     wk.edges += go ? (uint32_t)m : 0u;
                 }
-                const bool t = go && ray_prism(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, s.dx, s.dy, s.dz);
-                hit = hit || t;
-                live = live && !t;
+                const bool t = go & ray_prism(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, s.dx, s.dy, s.dz);
+                hit = hit | t;
+                live = live & !t;
             };
             auto key = [&](float x0, float y0, float x1, float y1, float z1) {
                 return fmaf(x0 + x1, s.dx, fmaf(y0 + y1, s.dy, z1 * s.dz));
@@ -152,11 +152,12 @@ __device__ __forceinline__ void accrue_segment(cNode *nodes, int *stack, cfloat4
     union_clear(U);
     ov = false;
     if (!active) return;
-    const float W0u = cosf(w0), W0v = sinf(w0), W1u = cosf(w1), W1v = sinf(w1);
+    float W0u, W0v, W1u, W1v;
+    window_dirs(g, w0, w1, W0u, W0v, W1u, W1v);
     bool live = true;
     if (q.own >= 0) {
         float a, b;
-        if (backface_interval(q.nx, q.ny, g, w0, w1, a, b)) {
+        if (backface_interval(q.nx, q.ny, g, w0, w1, W0u, W0v, W1u, W1v, a, b)) {
             union_insert(U, a, b);
             live = !(a <= w0 && b >= w1);
         }

@@ -38,11 +38,12 @@ __device__ __forceinline__ void grad_segment(cNode *nodes, int *stack, cfloat4 *
     union_clear(U);
     ov = false;
     if (!active) return;
-    const float W0u = cosf(w0), W0v = sinf(w0), W1u = cosf(w1), W1v = sinf(w1);
+    float W0u, W0v, W1u, W1v;
+    window_dirs(g, w0, w1, W0u, W0v, W1u, W1v);
     bool live = true;
     if (q.own >= 0) {
         float a, b;
-        if (backface_interval(q.nx, q.ny, g, w0, w1, a, b)) {
+        if (backface_interval(q.nx, q.ny, g, w0, w1, W0u, W0v, W1u, W1v, a, b)) {
             union_insert(U, a, b, -1, -1, 0.f, 0.f);
             live = !(a <= w0 && b >= w1);
         }

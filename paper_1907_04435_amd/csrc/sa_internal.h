@@ -7,7 +7,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/shadow_accrual.h"
+#include "shadow_accrual.h"
 
 namespace sa {
 

@@ -89,24 +89,28 @@ __device__ __forceinline__ void packet_traverse(cNode *nodes, int *stack, bool &
     int sp = 0, node = 0;
     bool want_cur = live;
     uint64_t want_stack = 0;
+    // Per-lane conditions are combined with bitwise operators, not && : a
+    // short-circuit on a lane value becomes exec-mask branching, and that
+    // scalar bookkeeping, not the box arithmetic, would bound the loop.
     while (ballot(live)) {
         const Node nd = ld(nodes + node);
         if constexpr (kCount) {
             w.box += (want_cur && live) ? 2u : 0u;
             w.nodes += first_active_lane() ? 1u : 0u;
         }
-        const bool mine = live && want_cur;
-        bool hl = mine && nd.left != kNone && bt(nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1);
-        bool hr = mine && nd.right != kNone && bt(nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1);
-        if (nd.left < 0 && nd.left != kNone) {
+        const bool mine = live & want_cur;
+        const bool vl = nd.left != kNone, vr = nd.right != kNone;
+        bool hl = bt(nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1) & mine & vl;
+        bool hr = bt(nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1) & mine & vr;
+        if (nd.left < 0 && vl) {
             if (ballot(hl)) leaf(~nd.left, nd.l_voff, nd.l_m, hl);
             hl = false;
         }
-        if (nd.right < 0 && nd.right != kNone) {
+        if (nd.right < 0 && vr) {
             if (ballot(hr)) leaf(~nd.right, nd.r_voff, nd.r_m, hr);
             hr = false;
         }
-        const bool gl = ballot(hl && live) != 0, gr = ballot(hr && live) != 0;
+        const bool gl = ballot(hl & live) != 0, gr = ballot(hr & live) != 0;
         if (gl && gr) {
             // the visiting order must be one decision for the whole wave:
             // with per-lane keys (lanes on different segments) lanes could
@@ -115,7 +119,8 @@ __device__ __forceinline__ void packet_traverse(cNode *nodes, int *stack, bool &
                                         key(nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1)) != 0;
             stack[sp] = lfirst ? nd.right : nd.left;
             const bool far = lfirst ? hr : hl;
-            want_stack = far ? (want_stack | (1ull << sp)) : (want_stack & ~(1ull << sp));
+            const uint64_t bit = 1ull << sp;
+            want_stack = far ? (want_stack | bit) : (want_stack & ~bit);
             want_cur = lfirst ? hl : hr;
             ++sp;
             node = uniform(lfirst ? nd.left : nd.right);
@@ -145,14 +150,15 @@ __device__ __forceinline__ bool ray_prism(cfloat4 *verts, int voff, int m, float
         const float4 v = ld(verts + voff + e);
         const float wx = v.x - px, wy = v.y - py;
         const float num = fmaf(v.z, wx, v.w * wy);
-        const float den = fmaf(v.z, dx, v.w * dy);
+        const float den = fmaf(v.z, dx, v.w * dy);   // the same for every lane
         const float s = num * __builtin_amdgcn_rcpf(den);
-        if (den > 0.f) s_out = fminf(s_out, s);
-        else if (den < 0.f) s_in = fmaxf(s_in, s);
-        else if (num < 0.f) s_out = -INFINITY;
+        // selects, not branches (see packet_traverse)
+        s_out = den > 0.f ? fminf(s_out, s) : s_out;
+        s_in = den < 0.f ? fmaxf(s_in, s) : s_in;
+        s_out = ((den == 0.f) & (num < 0.f)) ? -INFINITY : s_out;
     }
     const float s0 = fmaxf(s_in, 0.f);
-    return s_out >= s0 && fmaf(s0, dz, pz) <= H;
+    return (s_out >= s0) & (fmaf(s0, dz, pz) <= H);
 }
 
 // Is (px, py) inside (or on) the convex CCW footprint?
@@ -413,12 +419,13 @@ __device__ __forceinline__ bool union_insert(UnionG &U, float a, float b, int pa
 
 // Facade point whose wall faces away from the sun: n . d(phi) <= 0 with
 // d(phi) = cos(phi) e1 + sin(phi) e2.  Over a window narrower than pi the
-// set is one interval.  Returns 0 or 1 with [a, b].
+// set is one interval.  W0, W1: the window's end directions in (u, v).
+// Returns 0 or 1 with [a, b].
 __device__ __forceinline__ int backface_interval(float nx, float ny, const SegConst &g, float w0, float w1,
-                                                 float &a, float &b)
+                                                 float W0u, float W0v, float W1u, float W1v, float &a, float &b)
 {
     const float A = fmaf(nx, g.e1x, ny * g.e1y), B = fmaf(nx, g.e2x, ny * g.e2y);
-    const float f0 = A * cosf(w0) + B * sinf(w0), f1 = A * cosf(w1) + B * sinf(w1);
+    const float f0 = fmaf(A, W0u, B * W0v), f1 = fmaf(A, W1u, B * W1v);
     const bool s0 = f0 <= 0.f, s1 = f1 <= 0.f;
     if (s0 && s1) {
         a = w0;
@@ -436,6 +443,25 @@ __device__ __forceinline__ int backface_interval(float nx, float ny, const SegCo
         b = w1;
     }
     return 1;
+}
+
+// End directions of the window [w0, w1] of segment g in (u, v): exact
+// constants for the whole segment, sincos only for sub-windows.
+__device__ __forceinline__ void window_dirs(const SegConst &g, float w0, float w1, float &W0u, float &W0v,
+                                            float &W1u, float &W1v)
+{
+    if (w0 == 0.f) {
+        W0u = 1.f;
+        W0v = 0.f;
+    } else {
+        sincosf(w0, &W0v, &W0u);
+    }
+    if (w1 == g.theta) {
+        W1u = g.cth;
+        W1v = g.sth;
+    } else {
+        sincosf(w1, &W1v, &W1u);
+    }
 }
 
 struct PointArgs {
