@@ -377,7 +377,7 @@ def main():
                                                   "prism_edges": int(wa[2]), "inserts": int(wa[3]),
                                                   "node_fetches_per_wave": int(wa[4]),
                                                   "point_segments": int(wa[5]), "spilled": int(wa[6]),
-                                                  "lane_ops": ops}}
+                                                  "leaf_visits_per_wave": int(wa[7]), "lane_ops": ops}}
         log(f"accrual work: {wa.tolist()} -> {ops:.3e} lane-ops, {achieved/1e12:.2f} T/s")
         if not args.skip_sampled:
             work.zero_()
@@ -387,7 +387,9 @@ def main():
             sops = algorithmic_ops(ws, "sampled")
             result["sampled"]["roofline_frac"] = (sops / (result["sampled"]["ms_per_pass"] / 1e3)) / LANE_OP_PEAK
             result["sampled"]["work_per_pass"] = {"box_tests": int(ws[0]), "prism_tests": int(ws[1]),
-                                                  "prism_edges": int(ws[2]), "lane_ops": sops}
+                                                  "prism_edges": int(ws[2]),
+                                                  "node_fetches_per_wave": int(ws[4]),
+                                                  "leaf_visits_per_wave": int(ws[7]), "lane_ops": sops}
             log(f"sampled work: {ws.tolist()} -> {sops:.3e} lane-ops")
 
     # ---- CPU baseline (rank 0, N = 1)

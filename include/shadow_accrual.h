@@ -205,7 +205,7 @@ typedef struct {
      * work its own traversal needed -- [0] child-box tests, [1] prism tests,
      * [2] footprint edges visited in prism tests, [3] interval insertions,
      * [4] node fetches (per wave), [5] lanes x units (point-instants or
-     * point-segments), [6] spilled windows, [7] reserved.  Slower; for
+     * point-segments), [6] spilled windows, [7] leaf visits (per wave).  Slower; for
      * measurement only. */
     uint64_t *work;
 } sa_accum_opts;

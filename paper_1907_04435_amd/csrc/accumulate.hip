@@ -24,9 +24,9 @@ constexpr int64_t kChunkWork = 4000000000ll;  // point-segments per accrual laun
 // Sum a per-lane counter over the wave and add it to a global total.
 __device__ __forceinline__ void flush_work(const Work &w, uint64_t *work)
 {
-    uint32_t v[7] = {w.box, w.prism, w.edges, w.inserts, w.nodes, w.units, w.spills};
+    uint32_t v[8] = {w.box, w.prism, w.edges, w.inserts, w.nodes, w.units, w.spills, w.leaves};
 #pragma unroll
-    for (int c = 0; c < 7; ++c) {
+    for (int c = 0; c < 8; ++c) {
         uint64_t s = v[c];
         for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
         if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&work[c], (unsigned long long)s);
@@ -44,8 +44,8 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
     cSample *samples = (cSample *)samples_g;
-    __shared__ int s_stack[kWaves][kStackDepth];
-    int *stack = s_stack[threadIdx.x >> 6];
+    __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    StackEntry *stack = s_stack[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
     const int64_t i = wave * 64 + lane;
@@ -80,11 +80,12 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
                 const float tfz = fmaf(z1, s.iz, oz);
                 return fmaxf(fmaxf(tnx, tny), 0.f) <= fminf(fminf(tfx, tfy), tfz);
             };
-            auto leaf = [&](int prim, int voff, int m, bool want) {
-                const bool go = want & (prim != q.own);
+            auto leaf = [&](int prim, int voff, int m, uint64_t want) {
+                const bool go = lane_in(want & ballot(prim != q.own));
                 if constexpr (kCount) {
                     wk.prism += go ? 1u : 0u;
                     wk.edges += go ? (uint32_t)m : 0u;
+                    wk.leaves += first_active_lane() ? 1u : 0u;
                 }
                 const bool t = go & ray_prism(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, s.dx, s.dy, s.dz);
                 hit = hit | t;
@@ -145,7 +146,7 @@ __device__ __forceinline__ void measure(const Union4 &U, const SegConst &g, floa
 // back-face term, then the packet fan traversal.  On return `ov` marks
 // lanes whose set needed more than four pieces.
 template <bool kCount>
-__device__ __forceinline__ void accrue_segment(cNode *nodes, int *stack, cfloat4 *verts, cfloat *height,
+__device__ __forceinline__ void accrue_segment(cNode *nodes, StackEntry *stack, cfloat4 *verts, cfloat *height,
                                                const SegConst &g, const LanePoint &q, bool active, float w0,
                                                float w1, Union4 &U, bool &ov, Work &wk)
 {
@@ -164,12 +165,14 @@ __device__ __forceinline__ void accrue_segment(cNode *nodes, int *stack, cfloat4
     }
     if (nodes == nullptr) return;
     const FanTest bt(g, q.px, q.py, q.pz);
-    auto leaf = [&](int prim, int voff, int m, bool want) {
-        const bool go = want && prim != q.own;
-        if (!ballot(go)) return;
+    auto leaf = [&](int prim, int voff, int m, uint64_t want) {
+        const uint64_t gm = want & ballot(prim != q.own);
+        if (!gm) return;
+        const bool go = lane_in(gm);
         if constexpr (kCount) {
             wk.prism += go ? 1u : 0u;
             wk.edges += go ? (uint32_t)m : 0u;
+            wk.leaves += first_active_lane() ? 1u : 0u;
         }
         float a = 0.f, b = 0.f;
         float da, db;
@@ -195,7 +198,7 @@ __device__ __forceinline__ void accrue_segment(cNode *nodes, int *stack, cfloat4
 
 // Roof-covered: inside a footprint (other than the point's own building)
 // and not above that roof -- shadowed from every direction.
-__device__ __forceinline__ bool roof_covered(cNode *nodes, int *stack, cfloat4 *verts, cfloat *height,
+__device__ __forceinline__ bool roof_covered(cNode *nodes, StackEntry *stack, cfloat4 *verts, cfloat *height,
                                              const LanePoint &q, bool valid)
 {
     bool live = valid, cov = false;
@@ -203,8 +206,9 @@ __device__ __forceinline__ bool roof_covered(cNode *nodes, int *stack, cfloat4 *
     auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
         return q.px >= x0 && q.px <= x1 && q.py >= y0 && q.py <= y1 && q.pz <= z1;
     };
-    auto leaf = [&](int prim, int voff, int m, bool want) {
-        const bool t = want && prim != q.own && q.pz <= ld(height + prim) && in_footprint(verts, voff, m, q.px, q.py);
+    auto leaf = [&](int prim, int voff, int m, uint64_t want) {
+        const bool t = lane_in(want) && prim != q.own && q.pz <= ld(height + prim) &&
+                       in_footprint(verts, voff, m, q.px, q.py);
         cov = cov || t;
         live = live && !t;
     };
@@ -225,8 +229,8 @@ __global__ __launch_bounds__(kThreads) void k_accrual(const Node *nodes_g, const
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
     cSeg *segs = (cSeg *)segs_g;
-    __shared__ int s_stack[kWaves][kStackDepth];
-    int *stack = s_stack[threadIdx.x >> 6];
+    __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    StackEntry *stack = s_stack[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
     const int64_t i = wave * 64 + lane;
@@ -283,8 +287,8 @@ __global__ __launch_bounds__(kThreads) void k_spill(const Node *nodes_g, const f
     cNode *nodes = (cNode *)nodes_g;
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
-    __shared__ int s_stack[kWaves][kStackDepth];
-    int *stack = s_stack[threadIdx.x >> 6];
+    __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    StackEntry *stack = s_stack[threadIdx.x >> 6];
     const int64_t total = 2 * (int64_t)min((int32_t)*in_count, cap);
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t base = (int64_t)blockIdx.x * kThreads; base < total; base += stride) {
@@ -394,8 +398,8 @@ __global__ __launch_bounds__(kThreads) void k_batched(const Node *vnodes_g, int 
 {
     cfloat4 *verts = (cfloat4 *)verts_g;
     cSeg *segs = (cSeg *)segs_g;
-    __shared__ int s_stack[kWaves][kStackDepth];
-    int *stack = s_stack[threadIdx.x >> 6];
+    __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    StackEntry *stack = s_stack[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     const int64_t T = tile_off[V];
     const int64_t n = P.n;

@@ -31,7 +31,7 @@ struct GradArgs {
     const int32_t *order;  // hierarchy position -> original id
 };
 
-__device__ __forceinline__ void grad_segment(cNode *nodes, int *stack, cfloat4 *verts, cfloat *height,
+__device__ __forceinline__ void grad_segment(cNode *nodes, StackEntry *stack, cfloat4 *verts, cfloat *height,
                                              const SegConst &g, const LanePoint &q, bool active, float w0, float w1,
                                              UnionG &U, bool &ov)
 {
@@ -50,9 +50,10 @@ __device__ __forceinline__ void grad_segment(cNode *nodes, int *stack, cfloat4 *
     }
     if (nodes == nullptr) return;
     const FanTest bt(g, q.px, q.py, q.pz);
-    auto leaf = [&](int prim, int voff, int m, bool want) {
-        const bool go = want && prim != q.own;
-        if (!ballot(go)) return;
+    auto leaf = [&](int prim, int voff, int m, uint64_t want) {
+        const uint64_t gm = want & ballot(prim != q.own);
+        if (!gm) return;
+        const bool go = lane_in(gm);
         float a = 0.f, b = 0.f, da = 0.f, db = 0.f;
         const int r = go ? prism_interval<true>(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, w0, w1,
                                                 W0u, W0v, W1u, W1v, a, b, da, db)
@@ -83,7 +84,7 @@ __device__ __forceinline__ void scatter_grad(const UnionG &U, float wscale, cons
     }
 }
 
-__device__ __forceinline__ bool roof_covered_g(cNode *nodes, int *stack, cfloat4 *verts, cfloat *height,
+__device__ __forceinline__ bool roof_covered_g(cNode *nodes, StackEntry *stack, cfloat4 *verts, cfloat *height,
                                                const LanePoint &q, bool valid)
 {
     bool live = valid, cov = false;
@@ -91,8 +92,9 @@ __device__ __forceinline__ bool roof_covered_g(cNode *nodes, int *stack, cfloat4
     auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
         return q.px >= x0 && q.px <= x1 && q.py >= y0 && q.py <= y1 && q.pz <= z1;
     };
-    auto leaf = [&](int prim, int voff, int m, bool want) {
-        const bool t = want && prim != q.own && q.pz <= ld(height + prim) && in_footprint(verts, voff, m, q.px, q.py);
+    auto leaf = [&](int prim, int voff, int m, uint64_t want) {
+        const bool t = lane_in(want) && prim != q.own && q.pz <= ld(height + prim) &&
+                       in_footprint(verts, voff, m, q.px, q.py);
         cov = cov || t;
         live = live && !t;
     };
@@ -110,8 +112,8 @@ __global__ __launch_bounds__(kThreads) void k_grad(const Node *nodes_g, const fl
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
     cSeg *segs = (cSeg *)segs_g;
-    __shared__ int s_stack[kWaves][kStackDepth];
-    int *stack = s_stack[threadIdx.x >> 6];
+    __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    StackEntry *stack = s_stack[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
     const int64_t i = wave * 64 + lane;
@@ -142,8 +144,8 @@ __global__ __launch_bounds__(kThreads) void k_grad_spill(const Node *nodes_g, co
     cNode *nodes = nodes_g ? (cNode *)nodes_g : nullptr;
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
-    __shared__ int s_stack[kWaves][kStackDepth];
-    int *stack = s_stack[threadIdx.x >> 6];
+    __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    StackEntry *stack = s_stack[threadIdx.x >> 6];
     const int64_t total = 2 * (int64_t)min((int32_t)*in_count, cap);
     const int64_t stride = (int64_t)gridDim.x * kThreads;
     for (int64_t base = (int64_t)blockIdx.x * kThreads; base < total; base += stride) {

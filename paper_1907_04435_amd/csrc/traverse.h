@@ -47,6 +47,13 @@ __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Lane masks of float comparisons: one compare each, straight into a mask
+// (no round trip through a per-lane boolean).
+__device__ __forceinline__ uint64_t ge_mask(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, 3); }
+__device__ __forceinline__ uint64_t le_mask(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, 5); }
+__device__ __forceinline__ uint64_t to_mask(bool b) { return ballot(b); }
+__device__ __forceinline__ uint64_t to_mask(uint64_t m) { return m; }
+
 constexpr int kStackDepth = 64;
 
 // Box padding of the hierarchy: absorbs the rounding of the slab test at
@@ -65,7 +72,7 @@ __device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G)
 
 // Work a lane's own traversal needed (instrumented instantiations only).
 struct Work {
-    uint32_t box, prism, edges, inserts, nodes, units, spills;
+    uint32_t box, prism, edges, inserts, nodes, units, spills, leaves;
 };
 
 __device__ __forceinline__ bool first_active_lane()
@@ -74,67 +81,98 @@ __device__ __forceinline__ bool first_active_lane()
     return __builtin_amdgcn_readfirstlane(lane) == lane;
 }
 
-// Packet traversal.  `bt(x0, y0, x1, y1, z1)` is the per-lane child-box
-// test; `leaf(prim, voff, m, want)` processes a leaf for lanes with `want`
-// and may clear `live`.  `key(x0,y0,x1,y1,z1)` orders two wanted children
-// (smaller first).  The walk ends when no lane is live or the stack runs
-// dry.  A lane only tests the children of nodes it reached itself (a
-// per-lane bit per stack entry remembers whether the lane wanted the pushed
-// node), so leaves no lane reached are skipped.  With kCount, `w`
-// accumulates those box tests and the wave's node fetches.
-template <bool kCount, class BoxTest, class LeafFn, class KeyFn>
-__device__ __forceinline__ void packet_traverse(cNode *nodes, int *stack, bool &live, BoxTest bt, LeafFn leaf,
-                                                KeyFn key, Work &w)
+// One entry of a wave's traversal stack: a deferred node and the mask of
+// the lanes that reached it.
+struct alignas(16) StackEntry {
+    int32_t node;
+    uint32_t lo, hi, pad;
+};
+
+__device__ __forceinline__ uint64_t uniform64(uint32_t lo, uint32_t hi)
 {
+    const uint32_t l = (uint32_t)__builtin_amdgcn_readfirstlane((int)lo);
+    const uint32_t h = (uint32_t)__builtin_amdgcn_readfirstlane((int)hi);
+    return ((uint64_t)h << 32) | l;
+}
+
+// Is this lane's bit set in a wave-uniform mask?  (maps to the exec mask)
+__device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
+
+// Packet traversal.  `bt(x0, y0, x1, y1, z1)` is the per-lane child-box
+// test (a bool, or directly the lane mask of the lanes that pass);
+// `leaf(prim, voff, m, want)` processes a leaf for the lanes in the mask
+// `want` and may clear `live`.  `key(x0,y0,x1,y1,z1)` orders two wanted children
+// (smaller first).  The walk ends when no lane is live or the stack runs
+// dry.  A lane only tests the children of nodes it reached itself: the
+// walk carries the wave mask of the lanes that reached the current node,
+// and every stack entry keeps the mask of the lanes that wanted it, so
+// leaves no lane reached are skipped.  All the bookkeeping is on those
+// wave-uniform masks (scalar registers); the only per-lane work is the box
+// tests.  With kCount, `w` accumulates those box tests and the wave's node
+// fetches.
+template <bool kCount, class BoxTest, class LeafFn, class KeyFn>
+__device__ __forceinline__ void packet_traverse(cNode *nodes, StackEntry *stack, bool &live, BoxTest bt,
+                                                LeafFn leaf, KeyFn key, Work &w)
+{
+    uint64_t alive = ballot(live);  // lanes still live (only a leaf retires lanes)
+    uint64_t cur = alive;
     int sp = 0, node = 0;
-    bool want_cur = live;
-    uint64_t want_stack = 0;
-    // Per-lane conditions are combined with bitwise operators, not && : a
-    // short-circuit on a lane value becomes exec-mask branching, and that
-    // scalar bookkeeping, not the box arithmetic, would bound the loop.
-    while (ballot(live)) {
+    while (cur) {
         const Node nd = ld(nodes + node);
         if constexpr (kCount) {
-            w.box += (want_cur && live) ? 2u : 0u;
+            w.box += lane_in(cur) ? 2u : 0u;
             w.nodes += first_active_lane() ? 1u : 0u;
         }
-        const bool mine = live & want_cur;
-        const bool vl = nd.left != kNone, vr = nd.right != kNone;
-        bool hl = bt(nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1) & mine & vl;
-        bool hr = bt(nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1) & mine & vr;
-        if (nd.left < 0 && vl) {
-            if (ballot(hl)) leaf(~nd.left, nd.l_voff, nd.l_m, hl);
-            hl = false;
+        uint64_t hl = to_mask(bt(nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1)) & cur;
+        uint64_t hr = to_mask(bt(nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1)) & cur;
+        if (nd.left == kNone) hl = 0;
+        if (nd.right == kNone) hr = 0;  // a one-prism hierarchy has only a left child
+        bool leaves = false;
+        if (nd.left < 0 && nd.left != kNone) {
+            if (hl) {
+                leaf(~nd.left, nd.l_voff, nd.l_m, hl);
+                leaves = true;
+            }
+            hl = 0;
         }
-        if (nd.right < 0 && vr) {
-            if (ballot(hr)) leaf(~nd.right, nd.r_voff, nd.r_m, hr);
-            hr = false;
+        if (nd.right < 0 && nd.right != kNone) {
+            if (hr) {
+                leaf(~nd.right, nd.r_voff, nd.r_m, hr);
+                leaves = true;
+            }
+            hr = 0;
         }
-        const bool gl = ballot(hl & live) != 0, gr = ballot(hr & live) != 0;
-        if (gl && gr) {
+        if (leaves) {
+            alive = ballot(live);
+            hl &= alive;
+            hr &= alive;
+        }
+        if (hl && hr) {
             // the visiting order must be one decision for the whole wave:
             // with per-lane keys (lanes on different segments) lanes could
             // disagree and the shared stack would lose a subtree
             const bool lfirst = uniform(key(nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1) <=
                                         key(nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1)) != 0;
-            stack[sp] = lfirst ? nd.right : nd.left;
-            const bool far = lfirst ? hr : hl;
-            const uint64_t bit = 1ull << sp;
-            want_stack = far ? (want_stack | bit) : (want_stack & ~bit);
-            want_cur = lfirst ? hl : hr;
+            const uint64_t mfar = lfirst ? hr : hl;
+            stack[sp] = StackEntry{lfirst ? nd.right : nd.left, (uint32_t)mfar, (uint32_t)(mfar >> 32), 0u};
             ++sp;
-            node = uniform(lfirst ? nd.left : nd.right);
-        } else if (gl) {
-            want_cur = hl;
-            node = uniform(nd.left);
-        } else if (gr) {
-            want_cur = hr;
-            node = uniform(nd.right);
+            node = lfirst ? nd.left : nd.right;
+            cur = lfirst ? hl : hr;
+        } else if (hl) {
+            node = nd.left;
+            cur = hl;
+        } else if (hr) {
+            node = nd.right;
+            cur = hr;
         } else {
-            if (sp == 0) break;
-            --sp;
-            want_cur = (want_stack >> sp) & 1ull;
-            node = uniform(stack[sp]);
+            cur = 0;
+            while (sp > 0 && alive) {
+                --sp;
+                const StackEntry e = stack[sp];
+                node = uniform(e.node);
+                cur = uniform64(e.lo, e.hi) & alive;
+                if (cur) break;
+            }
         }
     }
 }
@@ -515,10 +553,15 @@ __device__ __forceinline__ void spill_push(const SpillArgs &S, bool want, int64_
 // height z1 projects on the ground to the triangle p, p + (z1 - pz) ua,
 // p + (z1 - pz) ub (central projection maps the great-circle arc to a
 // segment), so the box test is a 2D separating-axis test against that
-// triangle: its bounding box and its three edge normals.
+// triangle: its bounding box and its three edge normals.  For an edge with
+// normal n the box point farthest along n is the corner picked by the
+// signs of n, so max n.x over the box is
+//     x1 max(nx,0) + x0 min(nx,0) + y1 max(ny,0) + y0 min(ny,0),
+// a wave-uniform value (the box is the wave's node) compared with the
+// lane's n.p.
 struct FanTest {
     float umnx, umxx, umny, umxy;
-    float nax, nay, nbx, nby, ncx, ncy, kc;
+    float axp, axm, ayp, aym, bxp, bxm, byp, bym, cxp, cxm, cyp, cym, kc;
     float naP, nbP, ncP, px, py, pz;
 
     __device__ __forceinline__ FanTest(const SegConst &g, float px_, float py_, float pz_)
@@ -530,32 +573,50 @@ struct FanTest {
         umxx = fmaxf(0.f, fmaxf(g.ua_x, g.ub_x));
         umny = fminf(0.f, fminf(g.ua_y, g.ub_y));
         umxy = fmaxf(0.f, fmaxf(g.ua_y, g.ub_y));
-        nax = -g.ua_y;
-        nay = g.ua_x;
-        if (fmaf(nax, g.ub_x, nay * g.ub_y) < 0.f) { nax = -nax; nay = -nay; }
-        nbx = -g.ub_y;
-        nby = g.ub_x;
-        if (fmaf(nbx, g.ua_x, nby * g.ua_y) < 0.f) { nbx = -nbx; nby = -nby; }
-        ncx = -(g.ub_y - g.ua_y);
-        ncy = g.ub_x - g.ua_x;
-        if (fmaf(ncx, g.ua_x, ncy * g.ua_y) > 0.f) { ncx = -ncx; ncy = -ncy; }
+        float nax = -g.ua_y, nay = g.ua_x;   // inward normal of p -> A (toward B)
+        if (fmaf(nax, g.ub_x, nay * g.ub_y) < 0.f) {
+            nax = -nax;
+            nay = -nay;
+        }
+        float nbx = -g.ub_y, nby = g.ub_x;   // inward normal of p -> B (toward A)
+        if (fmaf(nbx, g.ua_x, nby * g.ua_y) < 0.f) {
+            nbx = -nbx;
+            nby = -nby;
+        }
+        float ncx = -(g.ub_y - g.ua_y), ncy = g.ub_x - g.ua_x;  // inward normal of A -> B (toward p)
+        if (fmaf(ncx, g.ua_x, ncy * g.ua_y) > 0.f) {
+            ncx = -ncx;
+            ncy = -ncy;
+        }
         kc = fmaf(ncx, g.ua_x, ncy * g.ua_y);
+        axp = fmaxf(nax, 0.f);
+        axm = fminf(nax, 0.f);
+        ayp = fmaxf(nay, 0.f);
+        aym = fminf(nay, 0.f);
+        bxp = fmaxf(nbx, 0.f);
+        bxm = fminf(nbx, 0.f);
+        byp = fmaxf(nby, 0.f);
+        bym = fminf(nby, 0.f);
+        cxp = fmaxf(ncx, 0.f);
+        cxm = fminf(ncx, 0.f);
+        cyp = fmaxf(ncy, 0.f);
+        cym = fminf(ncy, 0.f);
         naP = fmaf(nax, px, nay * py);
         nbP = fmaf(nbx, px, nby * py);
         ncP = fmaf(ncx, px, ncy * py);
     }
 
-    __device__ __forceinline__ bool operator()(float x0, float y0, float x1, float y1, float z1) const
+    __device__ __forceinline__ uint64_t operator()(float x0, float y0, float x1, float y1, float z1) const
     {
         const float ra = z1 - pz;
-        const bool bb = ra >= 0.f && x1 >= fmaf(ra, umnx, px) && x0 <= fmaf(ra, umxx, px) &&
-                        y1 >= fmaf(ra, umny, py) && y0 <= fmaf(ra, umxy, py);
-        const float cx = 0.5f * (x0 + x1), cy = 0.5f * (y0 + y1);
-        const float hx = 0.5f * (x1 - x0), hy = 0.5f * (y1 - y0);
-        const bool sa = fmaf(nax, cx, nay * cy) + fmaf(fabsf(nax), hx, fabsf(nay) * hy) >= naP;
-        const bool sb = fmaf(nbx, cx, nby * cy) + fmaf(fabsf(nbx), hx, fabsf(nby) * hy) >= nbP;
-        const bool sc = fmaf(ncx, cx, ncy * cy) + fmaf(fabsf(ncx), hx, fabsf(ncy) * hy) >= fmaf(ra, kc, ncP);
-        return bb && sa && sb && sc;
+        const float xlo = fmaf(ra, umnx, px), xhi = fmaf(ra, umxx, px);
+        const float ylo = fmaf(ra, umny, py), yhi = fmaf(ra, umxy, py);
+        const float ka = fmaf(y0, aym, fmaf(y1, ayp, fmaf(x0, axm, x1 * axp)));
+        const float kb = fmaf(y0, bym, fmaf(y1, byp, fmaf(x0, bxm, x1 * bxp)));
+        const float kk = fmaf(y0, cym, fmaf(y1, cyp, fmaf(x0, cxm, x1 * cxp)));
+        const float kr = fmaf(ra, kc, ncP);
+        return ge_mask(ra, 0.f) & ge_mask(x1, xlo) & le_mask(x0, xhi) & ge_mask(y1, ylo) & le_mask(y0, yhi) &
+               ge_mask(ka, naP) & ge_mask(kb, nbP) & ge_mask(kk, kr);
     }
 };
 
