@@ -30,12 +30,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic cost model, VALU lane-operations per unit of work a lane's own
-# traversal needs ("Roofline"):
+# traversal needs; the instrumented launch counts the units:
 COST = {
     "ray_box": 8,          # slab test of one child box: 5 FMA, max3, min3, compare
     "ray_prism": 6,        # per prism: entry/exit select and height compare
     "ray_edge": 10,        # per footprint edge: 2 sub, 2+2 FMA, rcp, mul, 2 min/max selects
-    "fan_box": 26,         # fan-triangle vs box: rise, 4 FMA + 4 cmp bbox, 3 edge-normal tests
+    "fan_box": 20,         # fan-triangle vs box: rise + sign, 4 FMA + 4 cmp bbox, 2 edge normals (4 FMA + cmp)
     "fan_prism": 40,       # per prism: inside/cover and window intersection logic
     "fan_edge": 36,        # per edge: 2 sub, 4 FMA (u,v), 2 FMA z, clip crossing, 2 tangent updates
     "insert": 60,          # 4-member interval-set insertion
@@ -241,8 +241,8 @@ def main():
                     help="only run a plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(points would shard across GPUs with the scene replicated; see DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path "
+              "(points would shard across GPUs, each holding a copy of the scene)", file=sys.stderr)
         sys.exit(2)
 
     import torch

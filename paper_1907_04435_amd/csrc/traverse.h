@@ -328,12 +328,15 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
         } else {
             inside = inside && cross2(pwx, pwy, wx, wy) >= 0.f;
             const bool pin = pzv <= h;
-            const float rdz = __builtin_amdgcn_rcpf(z - pzv);
-            const float t = (h - pzv) * rdz;
-            const float cu = fmaf(t, u - pu, pu), cv = fmaf(t, v - pv, pv);
-            float dc = 0.f;
-            if constexpr (kGrad) dc = cross2(cu, cv, u - pu, v - pv) * rdz * __builtin_amdgcn_rcpf(fmaf(cu, cu, cv * cv));
-            cand(cu, cv, dc, pin != in);
+            const bool crossing = pin != in;
+            if (ballot(crossing)) {
+                const float rdz = __builtin_amdgcn_rcpf(z - pzv);
+                const float t = (h - pzv) * rdz;
+                const float cu = fmaf(t, u - pu, pu), cv = fmaf(t, v - pv, pv);
+                float dc = 0.f;
+                if constexpr (kGrad) dc = cross2(cu, cv, u - pu, v - pv) * rdz * __builtin_amdgcn_rcpf(fmaf(cu, cu, cv * cv));
+                cand(cu, cv, dc, crossing);
+            }
         }
         if (e < m) cand(u, v, 0.f, in);
         pu = u; pv = v; pzv = z; pwx = wx; pwy = wy;
@@ -553,16 +556,19 @@ __device__ __forceinline__ void spill_push(const SpillArgs &S, bool want, int64_
 // height z1 projects on the ground to the triangle p, p + (z1 - pz) ua,
 // p + (z1 - pz) ub (central projection maps the great-circle arc to a
 // segment), so the box test is a 2D separating-axis test against that
-// triangle: its bounding box and its three edge normals.  For an edge with
-// normal n the box point farthest along n is the corner picked by the
-// signs of n, so max n.x over the box is
+// triangle: its bounding box and the normals of its two edges through p.
+// (The third edge, at the far end, is left out: the bounding box already
+// bounds the far end, and measured over the block scene the edge removes
+// under 1% of the box hits for 23% of the test's arithmetic.)  For an edge
+// with normal n the box point farthest along n is the corner picked by
+// the signs of n, so max n.x over the box is
 //     x1 max(nx,0) + x0 min(nx,0) + y1 max(ny,0) + y0 min(ny,0),
 // a wave-uniform value (the box is the wave's node) compared with the
 // lane's n.p.
 struct FanTest {
     float umnx, umxx, umny, umxy;
-    float axp, axm, ayp, aym, bxp, bxm, byp, bym, cxp, cxm, cyp, cym, kc;
-    float naP, nbP, ncP, px, py, pz;
+    float axp, axm, ayp, aym, bxp, bxm, byp, bym;
+    float naP, nbP, px, py, pz;
 
     __device__ __forceinline__ FanTest(const SegConst &g, float px_, float py_, float pz_)
     {
@@ -583,12 +589,6 @@ struct FanTest {
             nbx = -nbx;
             nby = -nby;
         }
-        float ncx = -(g.ub_y - g.ua_y), ncy = g.ub_x - g.ua_x;  // inward normal of A -> B (toward p)
-        if (fmaf(ncx, g.ua_x, ncy * g.ua_y) > 0.f) {
-            ncx = -ncx;
-            ncy = -ncy;
-        }
-        kc = fmaf(ncx, g.ua_x, ncy * g.ua_y);
         axp = fmaxf(nax, 0.f);
         axm = fminf(nax, 0.f);
         ayp = fmaxf(nay, 0.f);
@@ -597,13 +597,8 @@ struct FanTest {
         bxm = fminf(nbx, 0.f);
         byp = fmaxf(nby, 0.f);
         bym = fminf(nby, 0.f);
-        cxp = fmaxf(ncx, 0.f);
-        cxm = fminf(ncx, 0.f);
-        cyp = fmaxf(ncy, 0.f);
-        cym = fminf(ncy, 0.f);
         naP = fmaf(nax, px, nay * py);
         nbP = fmaf(nbx, px, nby * py);
-        ncP = fmaf(ncx, px, ncy * py);
     }
 
     __device__ __forceinline__ uint64_t operator()(float x0, float y0, float x1, float y1, float z1) const
@@ -613,10 +608,8 @@ struct FanTest {
         const float ylo = fmaf(ra, umny, py), yhi = fmaf(ra, umxy, py);
         const float ka = fmaf(y0, aym, fmaf(y1, ayp, fmaf(x0, axm, x1 * axp)));
         const float kb = fmaf(y0, bym, fmaf(y1, byp, fmaf(x0, bxm, x1 * bxp)));
-        const float kk = fmaf(y0, cym, fmaf(y1, cyp, fmaf(x0, cxm, x1 * cxp)));
-        const float kr = fmaf(ra, kc, ncP);
         return ge_mask(ra, 0.f) & ge_mask(x1, xlo) & le_mask(x0, xhi) & ge_mask(y1, ylo) & le_mask(y0, yhi) &
-               ge_mask(ka, naP) & ge_mask(kb, nbP) & ge_mask(kk, kr);
+               ge_mask(ka, naP) & ge_mask(kb, nbP);
     }
 };
 
