@@ -123,10 +123,10 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
 __device__ __forceinline__ void measure(const Union4 &U, const SegConst &g, float w0, float w1,
                                         bool last_window, double &mins, int &cnt)
 {
-    const float scale = g.dt / g.theta;
+    const float scale = g.rate;
     float m = 0.f;
     int c = 0;
-    const float inv_step = 1.0f / g.step;
+    const float inv_step = g.inv_step;
     int kmax = g.ns - 1;
     if (!last_window) kmax = min(kmax, (int)ceilf((w1 * scale - g.s0) * inv_step) - 1);
 #pragma unroll
@@ -134,7 +134,9 @@ __device__ __forceinline__ void measure(const Union4 &U, const SegConst &g, floa
         if (r < U.n) {
             m += U.hi[r] - U.lo[r];
             const int klo = max((int)ceilf((U.lo[r] * scale - g.s0) * inv_step), 0);
-            const int khi = min((int)floorf((U.hi[r] * scale - g.s0) * inv_step), kmax);
+            // a set that reaches the window end holds the window's last
+            // instant: taken as is, not through the rounding of w1 * scale
+            const int khi = U.hi[r] >= w1 ? kmax : min((int)floorf((U.hi[r] * scale - g.s0) * inv_step), kmax);
             c += max(khi - klo + 1, 0);
         }
     }
@@ -189,7 +191,7 @@ __device__ __forceinline__ void accrue_segment(cNode *nodes, StackEntry *stack, 
             }
         }
     };
-    const float mdx = g.e1x + g.e2x * 0.5f * g.theta, mdy = g.e1y + g.e2y * 0.5f * g.theta;
+    const float mdx = g.mdx, mdy = g.mdy;
     auto key = [&](float x0, float y0, float x1, float y1, float z1) {
         return fmaf(x0 + x1, mdx, (y0 + y1) * mdy);
     };
@@ -264,13 +266,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
             wk.units += valid ? 1u : 0u;
             wk.spills += (valid && ov) ? 1u : 0u;
         }
+        // Read the segment constants again rather than hold them in
+        // registers across the traversal (an opaque copy of the index keeps
+        // the compiler from reusing the first load): a scalar-cache hit
+        // costs less than spilling them to lanes of a vector register.
+        int jr = j;
+        asm volatile("" : "+s"(jr));
+        const SegConst gm = ld(segs + jr);
         if (covered && valid) {
-            mins += (double)g.dt;
-            cnt += g.ns;
+            mins += (double)gm.dt;
+            cnt += gm.ns;
         } else if (!ov) {
-            measure(U, g, 0.f, g.theta, true, mins, cnt);
+            measure(U, gm, 0.f, gm.theta, true, mins, cnt);
         }
-        spill_push(S, valid && ov, i, j, 0.f, g.theta);
+        spill_push(S, valid && ov, i, j, 0.f, gm.theta);
     }
     if (valid && j1 > j0) {
         if (counts) counts[(int64_t)bin * n + i] += cnt;

@@ -344,6 +344,10 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
             g.s0 = first >= 0 ? (float)(in->t_min[first] - ta) : 0.f;
             g.step = (float)step;
             g.ns = ns;
+            g.rate = (float)((tb - ta) / theta);
+            g.inv_step = (float)(1.0 / step);
+            g.mdx = (float)(a[0] + e2[0] * 0.5 * theta);
+            g.mdy = (float)(a[1] + e2[1] * 0.5 * theta);
             segs.push_back(g);
         }
     }

@@ -67,7 +67,7 @@ __device__ __forceinline__ void grad_segment(cNode *nodes, StackEntry *stack, cf
             }
         }
     };
-    const float mdx = g.e1x + g.e2x * 0.5f * g.theta, mdy = g.e1y + g.e2y * 0.5f * g.theta;
+    const float mdx = g.mdx, mdy = g.mdy;
     auto key = [&](float x0, float y0, float x1, float y1, float) { return fmaf(x0 + x1, mdx, (y0 + y1) * mdy); };
     Work none{0, 0, 0, 0, 0, 0, 0};
     packet_traverse<false>(nodes, stack, live, bt, leaf, key, none);
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kThreads) void k_grad(const Node *nodes_g, const fl
         UnionG U;
         bool ov;
         grad_segment(nodes, stack, verts, height, g, q, valid && !covered && w != 0.f, 0.f, g.theta, U, ov);
-        if (valid && !covered && !ov && w != 0.f) scatter_grad(U, w * g.dt / g.theta, G);
+        if (valid && !covered && !ov && w != 0.f) scatter_grad(U, w * g.rate, G);
         spill_push(S, valid && ov, i, j, 0.f, g.theta);
     }
 }
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kThreads) void k_grad_spill(const Node *nodes_g, co
         UnionG U;
         bool ov;
         grad_segment(nodes, stack, verts, height, g, q, valid, w0, w1, U, ov);
-        if (valid && !ov) scatter_grad(U, w * g.dt / g.theta, G);
+        if (valid && !ov) scatter_grad(U, w * g.rate, G);
         spill_push(S, valid && ov, i, j, w0, w1);
     }
 }

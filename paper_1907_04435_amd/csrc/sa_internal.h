@@ -54,7 +54,9 @@ struct alignas(64) SegConst {
     float step;                  // sample spacing (minutes)
     int32_t ns;                  // sample instants attributed to the segment
     int32_t pad0;
-    float pad1[4];
+    float rate;                  // dt / theta: minutes per radian
+    float inv_step;              // 1 / step
+    float mdx, mdy;              // horizontal part of the direction at theta / 2 (visit order)
 };
 static_assert(sizeof(SegConst) == 128, "two lines");
 

@@ -211,6 +211,71 @@ __device__ __forceinline__ bool in_footprint(cfloat4 *verts, int voff, int m, fl
     return in;
 }
 
+// ---- angles and directions of the segment geometry, written out so that
+// the kernels make no library calls (a call imposes the calling convention
+// on the whole kernel: registers saved and reloaded around every site) ----
+
+// atan on [0, 1].  Above tan(pi/8) the reflection
+// atan(t) = pi/4 + atan((t - 1) / (t + 1)) brings the argument to
+// |u| <= tan(pi/8); there the Taylor series u - u^3/3 + ... - u^15/15 +
+// u^17/17 is within |u|^19/19 < 3e-9 of atan(u).
+__device__ __forceinline__ float atan01(float t)
+{
+    const bool refl = t > 0.41421356f;
+    const float u = refl ? (t - 1.f) * __builtin_amdgcn_rcpf(t + 1.f) : t;
+    const float s = u * u;
+    float p = 1.f / 17.f;
+    p = fmaf(p, s, -1.f / 15.f);
+    p = fmaf(p, s, 1.f / 13.f);
+    p = fmaf(p, s, -1.f / 11.f);
+    p = fmaf(p, s, 1.f / 9.f);
+    p = fmaf(p, s, -1.f / 7.f);
+    p = fmaf(p, s, 1.f / 5.f);
+    p = fmaf(p, s, -1.f / 3.f);
+    p = fmaf(p, s, 1.f);
+    const float r = u * p;
+    return refl ? r + 0.785398163f : r;
+}
+
+// Polar angle of (x, y) in [-pi, pi] (atan2(y, x)), by the octant
+// symmetries atan(y/x) = pi/2 - atan(x/y) and pi - angle for x < 0.
+__device__ __forceinline__ float polar_angle(float x, float y)
+{
+    const float ax = fabsf(x), ay = fabsf(y);
+    const float mx = fmaxf(ax, ay), mn = fminf(ax, ay);
+    const float t = mx > 0.f ? fminf(mn * __builtin_amdgcn_rcpf(mx), 1.f) : 0.f;
+    float r = atan01(t);
+    r = ay > ax ? 1.57079633f - r : r;
+    r = x < 0.f ? 3.14159265f - r : r;
+    return y < 0.f ? -r : r;
+}
+
+// sin and cos of an angle in [0, 2 pi): w = k pi/2 + r with |r| <= pi/4
+// (pi/2 split in two parts, Cody and Waite, so k pi/2 is subtracted
+// without cancellation), Taylor series of sin to r^9 and cos to r^10
+// (truncation below 2e-9), then the quadrant k.
+__device__ __forceinline__ void sincos_small(float w, float &sn, float &cs)
+{
+    const float k = rintf(w * 0.636619772f);
+    float r = fmaf(-k, 1.5703125f, w);
+    r = fmaf(-k, 4.83826794897e-4f, r);
+    const float z = r * r;
+    float ps = -1.f / 362880.f;
+    ps = fmaf(ps, z, 1.f / 5040.f);
+    ps = fmaf(ps, z, -1.f / 120.f);
+    ps = fmaf(ps, z, 1.f / 6.f);
+    const float s = fmaf(-r * z, ps, r);
+    float pc = -1.f / 3628800.f;
+    pc = fmaf(pc, z, 1.f / 40320.f);
+    pc = fmaf(pc, z, -1.f / 720.f);
+    pc = fmaf(pc, z, 1.f / 24.f);
+    pc = fmaf(pc, z, -0.5f);
+    const float c = fmaf(pc, z, 1.f);
+    const int q = (int)k & 3;
+    sn = q == 0 ? s : (q == 1 ? c : (q == 2 ? -s : -c));
+    cs = q == 0 ? c : (q == 1 ? -s : (q == 2 ? -c : s));
+}
+
 // ---- sorted disjoint interval set of at most 4 members, in registers ----
 struct Union4 {
     float lo[4], hi[4];
@@ -359,13 +424,13 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
     }
     if (in0) {
         a = w0;
-        phi = atan2f(hiv, hiu);
+        phi = polar_angle(hiu, hiv);
         b = fminf(fmaxf(phi, w0), w1);
         if constexpr (kGrad) db = (b == phi) ? dhi : 0.f;
         return 1;
     }
     if (in1) {
-        plo = atan2f(lov, lou);
+        plo = polar_angle(lou, lov);
         a = fminf(fmaxf(plo, w0), w1);
         if constexpr (kGrad) da = (a == plo) ? dlo : 0.f;
         b = w1;
@@ -373,8 +438,8 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
     }
     const bool lo_in = cross2(W0u, W0v, lou, lov) >= 0.f && cross2(lou, lov, W1u, W1v) >= 0.f;
     if (!lo_in) return 0;
-    plo = atan2f(lov, lou);
-    phi = atan2f(hiv, hiu);
+    plo = polar_angle(lou, lov);
+    phi = polar_angle(hiu, hiv);
     a = fminf(fmaxf(plo, w0), w1);
     b = fminf(fmaxf(phi, w0), w1);
     if constexpr (kGrad) {
@@ -474,8 +539,9 @@ __device__ __forceinline__ int backface_interval(float nx, float ny, const SegCo
         return 1;
     }
     if (!s0 && !s1) return 0;
-    // zero of A cos + B sin inside the window (|phi| < pi/2 there, B != 0)
-    const float z = fminf(fmaxf(atanf(-A / B), w0), w1);
+    // zero of A cos + B sin inside the window (|phi| < pi/2 there, B != 0):
+    // atan(-A / B), taken as the polar angle of (|B|, -A sign B)
+    const float z = fminf(fmaxf(polar_angle(fabsf(B), B > 0.f ? -A : A), w0), w1);
     if (s0) {
         a = w0;
         b = z;
@@ -495,13 +561,13 @@ __device__ __forceinline__ void window_dirs(const SegConst &g, float w0, float w
         W0u = 1.f;
         W0v = 0.f;
     } else {
-        sincosf(w0, &W0v, &W0u);
+        sincos_small(w0, W0v, W0u);
     }
     if (w1 == g.theta) {
         W1u = g.cth;
         W1v = g.sth;
     } else {
-        sincosf(w1, &W1v, &W1u);
+        sincos_small(w1, W1v, W1u);
     }
 }
 
