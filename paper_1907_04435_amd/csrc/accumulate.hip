@@ -1,8 +1,8 @@
 // Gross-shadow kernels: the sampled form (one shadow ray per point per sun
 // instant) and the accrual form (one occluded interval per occluder per
 // point per great-circle segment, union, measure), plus the accrual spill
-// pass that finishes the rare point-segments whose occluded set has more
-// than four disjoint pieces by splitting their window in halves.
+// rounds that finish the rare point-segments whose occluded set has more
+// than four disjoint pieces by splitting their window 64 ways.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -16,7 +16,9 @@ using namespace dev;
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kSpillRounds = 12;
+// Spill rounds: each refines a window 64-fold, so three rounds reach
+// 1/262144 of a segment.
+constexpr int kSpillRounds = 3;
 constexpr int kSpillBlocks = 1024;
 constexpr int64_t kChunkWork = 4000000000ll;  // point-segments per accrual launch
 
@@ -288,9 +290,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
     if constexpr (kCount) flush_work(wk, work);
 }
 
-// One spill round: every queued (point, segment, window) is split in two
-// halves; each half is one lane.  Results are added atomically; halves
-// that still overflow go to the next queue.
+// One spill round: each queued (point, segment, window) is taken by one
+// wave whose 64 lanes take one 64th of the window each.  Every lane follows
+// the same point along the same segment, so the wave's traversal stays
+// coherent (a lane per queued entry would walk 64 unrelated points).  The
+// lanes' measures are summed across the wave and added with one atomic per
+// output; sub-windows that still need more than four pieces go to the
+// next queue.
 __global__ __launch_bounds__(kThreads) void k_spill(const Node *nodes_g, const float4 *verts_g,
                                                     const float *height_g, const SegConst *segs_g, PointArgs P,
                                                     float scale, int32_t *counts, float *minutes, const int4 *in,
@@ -299,37 +305,43 @@ __global__ __launch_bounds__(kThreads) void k_spill(const Node *nodes_g, const f
     cNode *nodes = (cNode *)nodes_g;
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
+    cSeg *segs = (cSeg *)segs_g;
     __shared__ StackEntry s_stack[kWaves][kStackDepth];
     StackEntry *stack = s_stack[threadIdx.x >> 6];
-    const int64_t total = 2 * (int64_t)min((int32_t)*in_count, cap);
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < total; base += stride) {
-        const int64_t t = base + threadIdx.x;
-        const bool valid = t < total;
-        int4 e = valid ? in[t >> 1] : make_int4(0, 0, 0, 0);
-        const int64_t i = e.x;
-        const int j = e.y;
-        const float ew0 = __int_as_float(e.z), ew1 = __int_as_float(e.w);
-        const float mid = 0.5f * (ew0 + ew1);
-        const float w0 = (t & 1) ? mid : ew0, w1 = (t & 1) ? ew1 : mid;
-        const LanePoint q = load_point(P, i, valid);
-        const SegConst g = segs_g[valid ? j : 0];
+    const int lane = threadIdx.x & 63;
+    const int64_t total = min((int32_t)*in_count, cap);
+    const int64_t stride = (int64_t)gridDim.x * kWaves;
+    for (int64_t e = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); e < total; e += stride) {
+        const int4 en = in[e];
+        const int64_t i = uniform(en.x);
+        const int j = uniform(en.y);
+        const float ew0 = __int_as_float(uniform(en.z)), ew1 = __int_as_float(uniform(en.w));
+        // lane l takes [w0 + l d, w0 + (l + 1) d]: neighbours share the same
+        // rounded boundary, the last lane ends exactly at ew1
+        const float d = (ew1 - ew0) * (1.f / 64.f);
+        const float w0 = lane == 0 ? ew0 : fmaf((float)lane, d, ew0);
+        const float w1 = lane == 63 ? ew1 : fmaf((float)(lane + 1), d, ew0);
+        const LanePoint q = load_point(P, i, true);
+        const SegConst g = ld(segs + j);
         Union4 U;
         bool ov;
         Work none{0, 0, 0, 0, 0, 0, 0};
-        accrue_segment<false>(nodes_g ? nodes : nullptr, stack, verts, height, g, q, valid, w0, w1, U, ov, none);
-        if (valid && !ov) {
-            double mins = 0.0;
-            int cnt = 0;
-            measure(U, g, w0, w1, w1 >= g.theta, mins, cnt);
+        accrue_segment<false>(nodes_g ? nodes : nullptr, stack, verts, height, g, q, true, w0, w1, U, ov, none);
+        double mins = 0.0;
+        int cnt = 0;
+        if (!ov) measure(U, g, w0, w1, w1 >= g.theta, mins, cnt);
+        for (int o = 32; o > 0; o >>= 1) {
+            mins += __shfl_xor(mins, o, 64);
+            cnt += __shfl_xor(cnt, o, 64);
+        }
+        if (lane == 0) {
             const int64_t o = (int64_t)g.bin * P.n + i;
             if (minutes) atomicAdd(&minutes[o], (float)(mins * scale));
             if (counts) atomicAdd(&counts[o], cnt);
         }
-        spill_push(S, valid && ov, i, j, w0, w1);
+        spill_push(S, ov, i, j, w0, w1);
     }
 }
-
 
 // ------------------------------------------------------------------ batched
 // Variant v of the scene differs from the base only in the heights of a few

@@ -22,7 +22,9 @@ using namespace dev;
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kSpillRounds = 12;
+// Spill rounds: each refines a window 64-fold (three reach 1/262144 of a
+// segment).
+constexpr int kSpillRounds = 3;
 constexpr int kSpillBlocks = 1024;
 
 struct GradArgs {
@@ -136,6 +138,10 @@ __global__ __launch_bounds__(kThreads) void k_grad(const Node *nodes_g, const fl
     }
 }
 
+// One spill round of the adjoint: as the accrual spill rounds, one wave per
+// queued (point, segment, window), each lane one 64th of the window.  Ends
+// clamped to a sub-window do not move with a height, so splitting adds no
+// gradient terms.
 __global__ __launch_bounds__(kThreads) void k_grad_spill(const Node *nodes_g, const float4 *verts_g,
                                                          const float *height_g, const SegConst *segs_g, PointArgs P,
                                                          GradArgs G, const int4 *in, const uint32_t *in_count,
@@ -144,27 +150,28 @@ __global__ __launch_bounds__(kThreads) void k_grad_spill(const Node *nodes_g, co
     cNode *nodes = nodes_g ? (cNode *)nodes_g : nullptr;
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
+    cSeg *segs = (cSeg *)segs_g;
     __shared__ StackEntry s_stack[kWaves][kStackDepth];
     StackEntry *stack = s_stack[threadIdx.x >> 6];
-    const int64_t total = 2 * (int64_t)min((int32_t)*in_count, cap);
-    const int64_t stride = (int64_t)gridDim.x * kThreads;
-    for (int64_t base = (int64_t)blockIdx.x * kThreads; base < total; base += stride) {
-        const int64_t t = base + threadIdx.x;
-        const bool valid = t < total;
-        int4 e = valid ? in[t >> 1] : make_int4(0, 0, 0, 0);
-        const int64_t i = e.x;
-        const int j = e.y;
-        const float ew0 = __int_as_float(e.z), ew1 = __int_as_float(e.w);
-        const float mid = 0.5f * (ew0 + ew1);
-        const float w0 = (t & 1) ? mid : ew0, w1 = (t & 1) ? ew1 : mid;
-        const LanePoint q = load_point(P, i, valid);
-        const SegConst g = segs_g[valid ? j : 0];
-        const float w = (valid && G.dl) ? G.dl[(int64_t)g.bin * P.n + i] : 1.f;
+    const int lane = threadIdx.x & 63;
+    const int64_t total = min((int32_t)*in_count, cap);
+    const int64_t stride = (int64_t)gridDim.x * kWaves;
+    for (int64_t e = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); e < total; e += stride) {
+        const int4 en = in[e];
+        const int64_t i = uniform(en.x);
+        const int j = uniform(en.y);
+        const float ew0 = __int_as_float(uniform(en.z)), ew1 = __int_as_float(uniform(en.w));
+        const float d = (ew1 - ew0) * (1.f / 64.f);
+        const float w0 = lane == 0 ? ew0 : fmaf((float)lane, d, ew0);
+        const float w1 = lane == 63 ? ew1 : fmaf((float)(lane + 1), d, ew0);
+        const LanePoint q = load_point(P, i, true);
+        const SegConst g = ld(segs + j);
+        const float w = G.dl ? G.dl[(int64_t)g.bin * P.n + i] : 1.f;
         UnionG U;
         bool ov;
-        grad_segment(nodes, stack, verts, height, g, q, valid, w0, w1, U, ov);
-        if (valid && !ov) scatter_grad(U, w * g.rate, G);
-        spill_push(S, valid && ov, i, j, w0, w1);
+        grad_segment(nodes, stack, verts, height, g, q, true, w0, w1, U, ov);
+        if (!ov) scatter_grad(U, w * g.rate, G);
+        spill_push(S, ov, i, j, w0, w1);
     }
 }
 
