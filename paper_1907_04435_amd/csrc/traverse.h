@@ -51,6 +51,8 @@ __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirs
 // (no round trip through a per-lane boolean).
 __device__ __forceinline__ uint64_t ge_mask(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, 3); }
 __device__ __forceinline__ uint64_t le_mask(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, 5); }
+__device__ __forceinline__ uint64_t lt_mask(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, 4); }
+__device__ __forceinline__ uint64_t gt_mask(float a, float b) { return __builtin_amdgcn_fcmpf(a, b, 2); }
 __device__ __forceinline__ uint64_t to_mask(bool b) { return ballot(b); }
 __device__ __forceinline__ uint64_t to_mask(uint64_t m) { return m; }
 
@@ -357,63 +359,70 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
                                               float &db)
 {
     const float h = H - pz;
-    bool have = false, inside = true;
     float lou = 0.f, lov = 0.f, hiu = 0.f, hiv = 0.f, dlo = 0.f, dhi = 0.f;
-    float fu = 0.f, fv = 0.f, fz = 0.f, fwx = 0.f, fwy = 0.f;
-    float pu = 0.f, pv = 0.f, pzv = 0.f, pwx = 0.f, pwy = 0.f;
-    auto cand = [&](float cu, float cv, float dc, bool ok) {
-        const bool first = ok && !have;
-        const bool new_lo = ok && have && cross2(lou, lov, cu, cv) < 0.f;
-        const bool new_hi = ok && have && cross2(hiu, hiv, cu, cv) > 0.f;
-        lou = (first || new_lo) ? cu : lou;
-        lov = (first || new_lo) ? cv : lov;
-        hiu = (first || new_hi) ? cu : hiu;
-        hiv = (first || new_hi) ? cv : hiv;
+    // Lane masks (scalar registers) for the per-lane flags: which lanes have
+    // a candidate yet, which see the footprint from inside every edge, which
+    // vertices are below the roof line.  Only the selects are vector work.
+    uint64_t have = 0, inside = ~0ull;
+    auto cand = [&](float cu, float cv, float dc, uint64_t ok) {
+        const uint64_t take_lo = ok & (~have | lt_mask(cross2(lou, lov, cu, cv), 0.f));
+        const uint64_t take_hi = ok & (~have | gt_mask(cross2(hiu, hiv, cu, cv), 0.f));
+        lou = lane_in(take_lo) ? cu : lou;
+        lov = lane_in(take_lo) ? cv : lov;
+        hiu = lane_in(take_hi) ? cu : hiu;
+        hiv = lane_in(take_hi) ? cv : hiv;
         if constexpr (kGrad) {
-            dlo = (first || new_lo) ? dc : dlo;
-            dhi = (first || new_hi) ? dc : dhi;
+            dlo = lane_in(take_lo) ? dc : dlo;
+            dhi = lane_in(take_hi) ? dc : dhi;
         }
-        have = have || ok;
+        have |= ok;
     };
-    for (int e = 0; e <= m; ++e) {
-        float u, v, z, wx, wy;
-        if (e < m) {
-            const float4 q = ld(verts + voff + e);
-            wx = q.x - px;
-            wy = q.y - py;
-            u = fmaf(g.m00, wx, g.m01 * wy);
-            v = fmaf(g.m10, wx, g.m11 * wy);
-            z = fmaf(g.e1z, u, g.e2z * v);
-        } else {
-            u = fu; v = fv; z = fz; wx = fwx; wy = fwy;
-        }
-        const bool in = z <= h;
-        if (e == 0) {
-            fu = u; fv = v; fz = z; fwx = wx; fwy = wy;
-        } else {
-            inside = inside && cross2(pwx, pwy, wx, wy) >= 0.f;
-            const bool pin = pzv <= h;
-            const bool crossing = pin != in;
-            if (ballot(crossing)) {
-                const float rdz = __builtin_amdgcn_rcpf(z - pzv);
-                const float t = (h - pzv) * rdz;
-                const float cu = fmaf(t, u - pu, pu), cv = fmaf(t, v - pv, pv);
-                float dc = 0.f;
-                if constexpr (kGrad) dc = cross2(cu, cv, u - pu, v - pv) * rdz * __builtin_amdgcn_rcpf(fmaf(cu, cu, cv * cv));
-                cand(cu, cv, dc, crossing);
-            }
+    // footprint vertex k relative to p: world offset (wx, wy), in-plane
+    // (u, v) and height z of the segment plane above p there
+    auto vertex = [&](int k, float &wx, float &wy, float &u, float &v, float &z) {
+        const float4 q = ld(verts + voff + k);
+        wx = q.x - px;
+        wy = q.y - py;
+        u = fmaf(g.m00, wx, g.m01 * wy);
+        v = fmaf(g.m10, wx, g.m11 * wy);
+        z = fmaf(g.e1z, u, g.e2z * v);
+    };
+    float pwx, pwy, pu, pv, pzv;
+    vertex(0, pwx, pwy, pu, pv, pzv);
+    uint64_t pin = le_mask(pzv, h);
+    cand(pu, pv, 0.f, pin);
+    // edge e runs from vertex e - 1 to vertex e mod m; vertex 0 is read
+    // again for the closing edge rather than kept in registers
+    for (int e = 1; e <= m; ++e) {
+        float wx, wy, u, v, z;
+        vertex(e == m ? 0 : e, wx, wy, u, v, z);
+        const uint64_t in = le_mask(z, h);
+        inside &= ge_mask(cross2(pwx, pwy, wx, wy), 0.f);
+        const uint64_t crossing = (pin ^ in) & ballot(true);
+        if (crossing) {
+            const float rdz = __builtin_amdgcn_rcpf(z - pzv);
+            const float t = (h - pzv) * rdz;
+            const float cu = fmaf(t, u - pu, pu), cv = fmaf(t, v - pv, pv);
+            float dc = 0.f;
+            if constexpr (kGrad) dc = cross2(cu, cv, u - pu, v - pv) * rdz * __builtin_amdgcn_rcpf(fmaf(cu, cu, cv * cv));
+            cand(cu, cv, dc, crossing);
         }
         if (e < m) cand(u, v, 0.f, in);
-        pu = u; pv = v; pzv = z; pwx = wx; pwy = wy;
+        pu = u;
+        pv = v;
+        pzv = z;
+        pwx = wx;
+        pwy = wy;
+        pin = in;
     }
     da = db = 0.f;
-    if (inside) {
+    if (lane_in(inside)) {
         if (h < 0.f) return 0;
         a = w0;
         b = w1;
         return 1;
     }
-    if (!have) return 0;
+    if (!lane_in(have)) return 0;
     const bool in0 = cross2(lou, lov, W0u, W0v) >= 0.f && cross2(W0u, W0v, hiu, hiv) >= 0.f;
     const bool in1 = cross2(lou, lov, W1u, W1v) >= 0.f && cross2(W1u, W1v, hiu, hiv) >= 0.f;
     float plo, phi;
