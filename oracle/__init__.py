@@ -46,7 +46,7 @@ def lib():
         L.orc_sampled.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, ip, C.c_int, ip, dp,
                                   C.POINTER(C.c_uint32), C.POINTER(C.c_uint8), C.c_int]
         L.orc_continuous.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, ip, C.c_int, ip, C.c_int,
-                                     C.c_double, dp, ip, C.c_int, dp, ip, C.c_int]
+                                     C.c_double, dp, ip, C.c_int, dp, ip, dp, C.c_int]
         L.orc_slerp.argtypes = [dp, dp, C.c_double, dp]
         L.orc_grad_implicit.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, ip, ip, C.c_double, dp, dp,
                                         C.c_int]
@@ -208,13 +208,16 @@ def sampled(scene, pts, path: OraclePath, bits=False, amb=False, threads=None):
 
 def continuous(scene, pts, path: OraclePath, grid_min=1.0 / 12.0, threads=None):
     """Continuous gross shadow along the piecewise great-circle path of
-    ``path``'s knots: minutes FP64 [n_bins, n] and counts (sample instants
-    inside the shadowed set) int32 [n_bins, n]."""
+    ``path``'s knots: minutes FP64 [n_bins, n], counts (sample instants
+    inside the shadowed set) int32 [n_bins, n], and longest FP64 [n_bins, n],
+    the continuous shadow of Sec. 3.1 (longest uninterrupted stretch of a
+    day's shadowed set, maximum over the bin's days)."""
     s, ks = _scene(scene)
     p, kp = _points(pts)
     n = pts.n
     minutes = np.zeros((path.n_bins, n), np.float64)
     counts = np.zeros((path.n_bins, n), np.int32)
+    longest = np.zeros((path.n_bins, n), np.float64)
     seg_t = np.ascontiguousarray(path.seg_t, np.float64)
     seg_dir = np.ascontiguousarray(path.seg_dir, np.float64)
     seg_day = np.ascontiguousarray(path.seg_day, np.int32)
@@ -225,8 +228,30 @@ def continuous(scene, pts, path: OraclePath, grid_min=1.0 / 12.0, threads=None):
                          _ptr(seg_dir, C.c_double), _ptr(seg_day, C.c_int32), len(day_bin),
                          _ptr(day_bin, C.c_int32), path.n_bins, float(grid_min),
                          _ptr(st, C.c_double), _ptr(sd, C.c_int32), len(st),
-                         _ptr(minutes, C.c_double), _ptr(counts, C.c_int32), threads or threads_default())
-    return dict(minutes=minutes, counts=counts)
+                         _ptr(minutes, C.c_double), _ptr(counts, C.c_int32), _ptr(longest, C.c_double),
+                         threads or threads_default())
+    return dict(minutes=minutes, counts=counts, longest=longest)
+
+
+def longest_sampled(shadowed, path: OraclePath):
+    """Continuous shadow of the sampled form (Sec. 3.1; with n-bit vectors,
+    Sec. 5: the longest run of consecutive 1's): per point and bin, the
+    largest total weight (minutes) of a run of consecutive shadowed
+    instants within one day, maximum over the bin's days.  ``shadowed``:
+    bool [n, K] predicate per point and instant.  FP64 [n_bins, n]."""
+    sh = np.asarray(shadowed, bool)
+    n = sh.shape[0]
+    out = np.zeros((path.n_bins, n), np.float64)
+    for d in range(len(path.day_bin)):
+        ks = np.flatnonzero(path.sample_day == d)
+        best = np.zeros(n)
+        cur = np.zeros(n)
+        for k in ks:
+            cur = np.where(sh[:, k], cur + path.w[k], 0.0)
+            best = np.maximum(best, cur)
+        b = path.day_bin[d]
+        out[b] = np.maximum(out[b], best)
+    return out
 
 
 def grad_implicit(scene, pts, path: OraclePath, dl=None, grid_min=1.0 / 12.0, threads=None):

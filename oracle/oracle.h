@@ -71,12 +71,14 @@ void orc_sampled(const orc_scene *s, const orc_points *p, int K, const double *d
  * directions, seg_day [n_seg] non-decreasing day index; day_bin [n_days]
  * output bin of each day (NULL: bin = day); sample_t / sample_day: the
  * sample instants counted when inside the day's shadowed set.
- * minutes / counts: [n_bins][n]. */
+ * minutes / counts: [n_bins][n].  longest [n_bins][n] (NULL: not wanted):
+ * the continuous shadow of Sec. 3.1, the longest member of a day's shadowed
+ * set, maximum over the bin's days. */
 void orc_continuous(const orc_scene *s, const orc_points *p, int n_seg,
                     const double *seg_t, const double *seg_dir, const int32_t *seg_day,
                     int n_days, const int32_t *day_bin, int n_bins, double grid_min,
                     const double *sample_t, const int32_t *sample_day, int n_samples,
-                    double *minutes, int32_t *counts, int threads);
+                    double *minutes, int32_t *counts, double *longest, int threads);
 
 /* ---- gradient of sum_p D_L(p) w.r.t. building heights ---- */
 /* grad [n_b]: d/dH_b of sum over points and days of dl_dmin[bin][p] *

@@ -358,6 +358,7 @@ typedef struct {
     int n_samples;
     double *minutes;
     int32_t *counts;
+    double *longest;
     /* gradient mode */
     const double *dl;
     double *grad;
@@ -534,8 +535,13 @@ static void continuous_point(void *vctx, int64_t i)
             segment_intervals(C->S, p, nrm, owner, C->seg_t[2 * j], C->seg_t[2 * j + 1],
                               C->seg_dir + 6 * j, C->seg_dir + 6 * j + 3, C->grid, &day);
         int m = ivec_union(&day);
-        double meas = 0.0;
-        for (int a = 0; a < m; ++a) meas += day.v[a].hi - day.v[a].lo;
+        double meas = 0.0, run = 0.0;
+        for (int a = 0; a < m; ++a) {
+            meas += day.v[a].hi - day.v[a].lo;
+            /* continuous shadow (Sec. 3.1): the longest member of the day's
+             * union; runs that meet at a knot were merged by ivec_union */
+            if (day.v[a].hi - day.v[a].lo > run) run = day.v[a].hi - day.v[a].lo;
+        }
         int cnt = 0;
         for (; k < C->n_samples && C->sample_day[k] == dd; ++k) {
             double t = C->sample_t[k];
@@ -545,6 +551,8 @@ static void continuous_point(void *vctx, int64_t i)
         int bin = C->day_bin ? C->day_bin[dd] : dd;
         if (C->minutes) C->minutes[(int64_t)bin * n + i] += meas;
         if (C->counts) C->counts[(int64_t)bin * n + i] += cnt;
+        /* over several days: the maximum over the bin's days (Sec. 3.1) */
+        if (C->longest && run > C->longest[(int64_t)bin * n + i]) C->longest[(int64_t)bin * n + i] = run;
     }
     free(day.v);
 }
@@ -553,18 +561,19 @@ void orc_continuous(const orc_scene *s, const orc_points *p, int n_seg,
                     const double *seg_t, const double *seg_dir, const int32_t *seg_day,
                     int n_days, const int32_t *day_bin, int n_bins, double grid_min,
                     const double *sample_t, const int32_t *sample_day, int n_samples,
-                    double *minutes, int32_t *counts, int threads)
+                    double *minutes, int32_t *counts, double *longest, int threads)
 {
     scene64 S;
     scene64_init(&S, s);
     if (minutes) memset(minutes, 0, sizeof(double) * (size_t)n_bins * p->n);
     if (counts) memset(counts, 0, sizeof(int32_t) * (size_t)n_bins * p->n);
+    if (longest) memset(longest, 0, sizeof(double) * (size_t)n_bins * p->n);
     cont_ctx C;
     memset(&C, 0, sizeof(C));
     C.S = &S; C.P = p; C.n_seg = n_seg; C.seg_t = seg_t; C.seg_dir = seg_dir;
     C.seg_day = seg_day; C.n_days = n_days; C.day_bin = day_bin; C.grid = grid_min;
     C.sample_t = sample_t; C.sample_day = sample_day; C.n_samples = n_samples;
-    C.minutes = minutes; C.counts = counts;
+    C.minutes = minutes; C.counts = counts; C.longest = longest;
     parallel_for(p->n, threads, continuous_point, &C);
     scene64_free(&S);
 }
