@@ -208,6 +208,19 @@ typedef struct {
      * point-segments), [6] spilled windows, [7] leaf visits (per wave).  Slower; for
      * measurement only. */
     uint64_t *work;
+    /* Optional device float [n_bins * n] (bin-major; NULL = not wanted):
+     * continuous shadow (Sec. 3.1) -- the longest time the point stays in
+     * shadow without interruption within one day, in minutes times
+     * out_scale, the maximum over the bin's days.  SA_SAMPLED: the longest
+     * run of consecutive shadowed instants (Sec. 5), as the sum of their
+     * weights; SA_ACCRUAL: the longest member of the day's shadowed set
+     * along the path, runs that meet at a knot being one run (Sec. 6 joins
+     * per-segment prefix / longest / suffix the same way).  Cleared first
+     * unless SA_FLAG_ADD, which keeps the larger of the stored and the new
+     * value.  With it the accrual form resolves sets of more than four
+     * pieces in segment order inside the kernel (slower).
+     * sa_accumulate_batched: must be NULL. */
+    float *longest;
 } sa_accum_opts;
 
 /* Gross shadow of every point over every day of `path`, summed per bin.

@@ -68,7 +68,7 @@ class sa_points(C.Structure):
 
 class sa_accum_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("flags", C.c_uint32), ("out_scale", C.c_float),
-                ("grid_blocks", C.c_int32), ("work", C.c_void_p)]
+                ("grid_blocks", C.c_int32), ("work", C.c_void_p), ("longest", C.c_void_p)]
 
 
 _lib = None
@@ -342,10 +342,11 @@ class DevicePoints:
 # compute entry points
 # --------------------------------------------------------------------------
 def sa_accumulate(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, mode: int, counts=None,
-                  minutes=None, bits=None, flags=0, out_scale=1.0, work=None):
+                  minutes=None, bits=None, flags=0, out_scale=1.0, work=None, longest=None):
     """Gross shadow into caller-provided device tensors (see the C ABI).
-    ``work``: optional device int64 [8] work counters (instrumented run)."""
-    opts = sa_accum_opts(mode, flags, out_scale, 0, _ptr(work))
+    ``work``: optional device int64 [8] work counters (instrumented run).
+    ``longest``: optional device float32 [bins, n] continuous shadow."""
+    opts = sa_accum_opts(mode, flags, out_scale, 0, _ptr(work), _ptr(longest))
     ps = pts.struct()
     _check(ctx, lib().sa_accumulate(ctx.handle, scene.handle, C.byref(ps), path.handle, C.byref(opts),
                                     _ptr(counts), _ptr(minutes), _ptr(bits)))
@@ -364,12 +365,24 @@ def accumulate(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, mode: 
     return counts, minutes, bits
 
 
+def continuous_shadow(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, mode: int, out_scale=1.0):
+    """Gross and continuous shadow in one pass: returns (minutes [bins, n],
+    longest [bins, n]) float32 device tensors; longest is the longest
+    uninterrupted shadow of a day, maximum over the bin's days."""
+    torch = ctx.torch
+    dev = f"cuda:{ctx.device}"
+    minutes = torch.empty((path.n_bins, pts.n), dtype=torch.float32, device=dev)
+    longest = torch.empty((path.n_bins, pts.n), dtype=torch.float32, device=dev)
+    sa_accumulate(ctx, scene, pts, path, mode, None, minutes, None, 0, out_scale, longest=longest)
+    return minutes, longest
+
+
 def sa_accumulate_batched(ctx: Context, scene: Scene, var_ids, var_h, pts: DevicePoints, var_off, path: Path,
                           counts=None, minutes=None, flags=0, out_scale=1.0, grid_blocks=0):
     """Batched development variants (device tensors var_ids [V, k] int32,
     var_h [V, k] float32, var_off [V+1] int64).  ``grid_blocks``: size of
     the persistent launch (0 = library default)."""
-    opts = sa_accum_opts(SA_ACCRUAL, flags, out_scale, grid_blocks, None)
+    opts = sa_accum_opts(SA_ACCRUAL, flags, out_scale, grid_blocks, None, None)
     ps = pts.struct()
     V, k = int(var_ids.shape[0]), int(var_ids.shape[1]) if var_ids.dim() > 1 else 0
     _check(ctx, lib().sa_accumulate_batched(ctx.handle, scene.handle, V, k, _ptr(var_ids), _ptr(var_h),

@@ -39,7 +39,8 @@ template <bool kBits, bool kCount>
 __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const float4 *verts_g,
                                                       const float *height_g, const SampleConst *samples_g,
                                                       int K, PointArgs P, float scale, int32_t *counts,
-                                                      float *minutes, uint32_t *bits, uint64_t *work)
+                                                      float *minutes, uint32_t *bits, float *longest,
+                                                      uint64_t *work)
 {
     Work wk{0, 0, 0, 0, 0, 0, 0};
     cNode *nodes = (cNode *)nodes_g;
@@ -57,19 +58,29 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
 
     int cnt = 0;
     float mins = 0.f;
-    int bin = K > 0 ? ld(samples).bin : 0;
+    // continuous shadow: the current run of shadowed instants and the
+    // longest run of the bin so far (minutes); a run never crosses a day
+    float run = 0.f, best = 0.f;
+    int bin = K > 0 ? (ld(samples).tag & kBinMask) : 0;
     uint32_t word = 0;
     for (int k = 0; k < K; ++k) {
         const SampleConst s = ld(samples + k);
-        if (s.bin != bin) {
+        const int sbin = s.tag & kBinMask;
+        if (sbin != bin) {
             if (valid) {
                 if (counts) counts[(int64_t)bin * n + i] += cnt;
                 if (minutes) minutes[(int64_t)bin * n + i] += mins * scale;
+                if (longest) {
+                    float &o = longest[(int64_t)bin * n + i];
+                    o = fmaxf(o, best * scale);
+                }
             }
             cnt = 0;
             mins = 0.f;
-            bin = s.bin;
+            best = 0.f;
+            bin = sbin;
         }
+        if (s.tag & kDayStart) run = 0.f;
         const bool back = q.own >= 0 && fmaf(q.nx, s.dx, q.ny * s.dy) <= 0.f;
         bool live = valid && !back;
         bool hit = false;
@@ -102,6 +113,8 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
         const bool sh = valid && (back || hit);
         cnt += sh ? 1 : 0;
         mins += sh ? s.w : 0.f;
+        run = sh ? run + s.w : 0.f;
+        best = fmaxf(best, run);
         if (kBits) {
             word |= (uint32_t)sh << (k & 31);
             if ((k & 31) == 31 || k == K - 1) {
@@ -113,6 +126,10 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
     if (valid && K > 0) {
         if (counts) counts[(int64_t)bin * n + i] += cnt;
         if (minutes) minutes[(int64_t)bin * n + i] += mins * scale;
+        if (longest) {
+            float &o = longest[(int64_t)bin * n + i];
+            o = fmaxf(o, best * scale);
+        }
     }
     if constexpr (kCount) flush_work(wk, work);
 }
@@ -288,6 +305,112 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
         if (minutes) minutes[(int64_t)bin * n + i] += (float)(mins * scale);
     }
     if constexpr (kCount) flush_work(wk, work);
+}
+
+// Continuous shadow (Sec. 3.1) over one window [w0, w1] whose occluded set
+// U is sorted and disjoint: a set that starts at w0 extends the current run
+// (the run so far reached the window start), any gap ends it; best keeps
+// the longest run in minutes.  Applied window after window in time order
+// this joins the per-segment prefix, longest and suffix as Sec. 6 stitches
+// them across the edges of a day's path.
+__device__ __forceinline__ void runs_update(const Union4 &U, float w0, float w1, float rate, float &run, float &best)
+{
+    if (U.n == 0) run = 0.f;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        if (r < U.n) {
+            const float len = (U.hi[r] - U.lo[r]) * rate;
+            run = (r == 0 && U.lo[0] <= w0) ? run + len : len;
+            best = fmaxf(best, run);
+            if (U.hi[r] < w1) run = 0.f;
+        }
+    }
+}
+
+// The accrual form with the continuous shadow of every point.  Runs must be
+// followed in time order, so a segment whose set needs more than four
+// pieces is not queued for the spill rounds: the lane walks that segment
+// window by window from its start (halving the window on overflow,
+// doubling it after a success) while the other lanes wait.  A window would
+// have to shrink below theta / 4096 to raise the overflow flag.
+__global__ __launch_bounds__(kThreads) void k_accrual_runs(const Node *nodes_g, const float4 *verts_g,
+                                                           const float *height_g, const SegConst *segs_g, int j0,
+                                                           int j1, PointArgs P, float scale, int32_t *counts,
+                                                           float *minutes, float *longest, uint32_t *overflow)
+{
+    cNode *nodes = (cNode *)nodes_g;
+    cfloat4 *verts = (cfloat4 *)verts_g;
+    cfloat *height = (cfloat *)height_g;
+    cSeg *segs = (cSeg *)segs_g;
+    __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    StackEntry *stack = s_stack[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
+    const int64_t i = wave * 64 + lane;
+    const bool valid = i < P.n;
+    const int64_t n = P.n;
+    const LanePoint q = load_point(P, i, valid);
+    const bool covered = roof_covered(nodes_g ? nodes : nullptr, stack, verts, height, q, valid);
+    Work none{0, 0, 0, 0, 0, 0, 0};
+
+    int cnt = 0;
+    double mins = 0.0;
+    float run = 0.f, best = 0.f;
+    int bin = j1 > j0 ? ld(segs + j0).bin : 0;
+    int day = j1 > j0 ? ld(segs + j0).day : 0;
+    auto flush = [&]() {
+        if (!valid) return;
+        const int64_t o = (int64_t)bin * n + i;
+        if (counts) counts[o] += cnt;
+        if (minutes) minutes[o] += (float)(mins * scale);
+        if (longest) longest[o] = fmaxf(longest[o], best * scale);
+    };
+    for (int j = j0; j < j1; ++j) {
+        const SegConst g = ld(segs + j);
+        if (g.bin != bin) {
+            flush();
+            cnt = 0;
+            mins = 0.0;
+            best = 0.f;
+            bin = g.bin;
+        }
+        if (g.day != day) {
+            run = 0.f;
+            day = g.day;
+        }
+        if (covered && valid) {
+            mins += (double)g.dt;
+            cnt += g.ns;
+            run += g.dt;
+            best = fmaxf(best, run);
+        }
+        bool pending = valid && !covered;
+        float w0 = 0.f, s = g.theta;
+        while (ballot(pending)) {
+            const float w1 = fminf(w0 + s, g.theta);
+            Union4 U;
+            bool ov;
+            accrue_segment<false>(nodes_g ? nodes : nullptr, stack, verts, height, g, q, pending, w0, w1, U, ov,
+                                  none);
+            if (pending) {
+                if (ov) {
+                    if (s < g.theta * (1.0f / 4096.0f)) {
+                        atomicOr(overflow, 1u);
+                        pending = false;
+                    } else {
+                        s *= 0.5f;
+                    }
+                } else {
+                    measure(U, g, w0, w1, w1 >= g.theta, mins, cnt);
+                    runs_update(U, w0, w1, g.rate, run, best);
+                    w0 = w1;
+                    pending = w0 < g.theta;
+                    s = fminf(2.f * s, g.theta);
+                }
+            }
+        }
+    }
+    if (j1 > j0) flush();
 }
 
 // One spill round: each queued (point, segment, window) is taken by one
@@ -526,8 +649,8 @@ static PointArgs point_args(const PointsView &pts, const DeviceScene &s)
 }
 
 sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
-                         int32_t *counts, float *minutes, uint32_t *bits, uint64_t *work, hipStream_t st,
-                         std::string &err)
+                         int32_t *counts, float *minutes, uint32_t *bits, float *longest, uint64_t *work,
+                         hipStream_t st, std::string &err)
 {
     if (pts.n == 0) return SA_OK;
     const int64_t waves = (pts.n + 63) / 64;
@@ -540,7 +663,7 @@ sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const Points
     auto kern = bits ? (work ? k_sampled<true, true> : k_sampled<true, false>)
                      : (work ? k_sampled<false, true> : k_sampled<false, false>);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, s.verts, s.height, p.samples,
-                       p.n_samples, point_args(pts, s), scale, counts, minutes, bits, work);
+                       p.n_samples, point_args(pts, s), scale, counts, minutes, bits, longest, work);
     SA_CHECK_LAUNCH("sampled kernel");
     return SA_OK;
 }
@@ -626,14 +749,29 @@ sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_va
 }
 
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
-                         int32_t *counts, float *minutes, uint64_t *work, SpillQueue &q, hipStream_t st,
-                         std::string &err)
+                         int32_t *counts, float *minutes, float *longest, uint64_t *work, SpillQueue &q,
+                         hipStream_t st, std::string &err)
 {
     if (pts.n == 0) return SA_OK;
     const int64_t waves = (pts.n + 63) / 64;
     const int64_t grid = (waves + kWaves - 1) / kWaves;
     const Node *nodes = s.n_b > 0 ? s.nodes : nullptr;
     const PointArgs P = point_args(pts, s);
+    if (longest) {
+        // whole days per launch, so a run never spans two launches
+        const int D = (int)p.day_seg_off.size() - 1;
+        const int64_t per = std::max<int64_t>(1, kChunkWork / std::max<int64_t>(pts.n, 1));
+        for (int d0 = 0; d0 < D;) {
+            int d1 = d0 + 1;
+            while (d1 < D && p.day_seg_off[d1 + 1] - p.day_seg_off[d0] <= per) ++d1;
+            hipLaunchKernelGGL(k_accrual_runs, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, s.verts, s.height,
+                               p.segs, p.day_seg_off[d0], p.day_seg_off[d1], P, scale, counts, minutes, longest,
+                               q.counters + 2);
+            SA_CHECK_LAUNCH("accrual kernel (continuous shadow)");
+            d0 = d1;
+        }
+        return SA_OK;
+    }
     // Long spans (many days) run as several launches over consecutive
     // segment ranges, each about kChunkWork point-segments and each followed
     // by its spill rounds; outputs are accumulated, so the split is

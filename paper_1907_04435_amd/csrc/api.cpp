@@ -261,10 +261,12 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload: bad arguments");
     std::vector<sa::SampleConst> samples(in->n_samples);
     std::vector<sa::SegConst> segs;
+    std::vector<int32_t> day_seg_off;
     int n_bins = 0;
     for (int d = 0; d < D; ++d) {
+        day_seg_off.push_back((int32_t)segs.size());
         const int bin = in->day_bin ? in->day_bin[d] : d;
-        if (bin < 0) return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload: negative bin");
+        if (bin < 0 || bin > sa::kBinMask) return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload: bad bin");
         n_bins = std::max(n_bins, bin + 1);
         const int s0 = in->day_sample_off[d], s1 = in->day_sample_off[d + 1];
         const int k0 = in->day_knot_off[d], k1 = in->day_knot_off[d + 1];
@@ -282,7 +284,7 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
             c.ix = inv(c.dx);
             c.iy = inv(c.dy);
             c.iz = inv(c.dz);
-            c.bin = bin;
+            c.tag = bin | (k == s0 ? sa::kDayStart : 0);
         }
         const double step = s1 - s0 >= 2 ? in->t_min[s0 + 1] - in->t_min[s0] : 1.0;
         for (int k = k0; k + 1 < k1; ++k) {
@@ -360,6 +362,8 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
     p->d.n_samples = in->n_samples;
     p->d.n_segs = (int32_t)segs.size();
     p->d.n_bins = n_bins;
+    day_seg_off.push_back((int32_t)segs.size());
+    p->d.day_seg_off = std::move(day_seg_off);
     p->d.words = (in->n_samples + 31) / 32;
     hipError_t e = hipSuccess;
     if (!samples.empty()) {
@@ -415,13 +419,15 @@ static sa::PointsView view(const sa_points *p)
 
 // Outputs are cleared with a fill kernel (not a memset node), so a call can
 // be captured into a HIP graph and replayed.
-static sa_status clear_outputs(sa_ctx *ctx, uint32_t flags, int64_t count, int32_t *counts, float *minutes)
+static sa_status clear_outputs(sa_ctx *ctx, uint32_t flags, int64_t count, int32_t *counts, float *minutes,
+                               float *longest = nullptr)
 {
     if (flags & SA_FLAG_ADD) return SA_OK;
     std::string err;
     sa_status rc = SA_OK;
     if (counts) rc = sa::fill_u32(counts, count, 0u, ctx->stream, err);
     if (rc == SA_OK && minutes) rc = sa::fill_u32(minutes, count, 0u, ctx->stream, err);
+    if (rc == SA_OK && longest) rc = sa::fill_u32(longest, count, 0u, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "clear outputs: " + err);
     return SA_OK;
 }
@@ -437,18 +443,18 @@ sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate: unknown mode");
     if (bits && opts->mode != SA_SAMPLED)
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate: bit vectors exist for the sampled form only");
-    if (!counts && !minutes && !bits) return SA_OK;
+    if (!counts && !minutes && !bits && !opts->longest) return SA_OK;
     if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
     const float scale = opts->out_scale == 0.f ? 1.f : opts->out_scale;
-    rc = clear_outputs(ctx, opts->flags, (int64_t)path->d.n_bins * pts->n, counts, minutes);
+    rc = clear_outputs(ctx, opts->flags, (int64_t)path->d.n_bins * pts->n, counts, minutes, opts->longest);
     if (rc != SA_OK) return rc;
     std::string err;
     if (opts->mode == SA_SAMPLED)
-        rc = sa::launch_sampled(scene->d, path->d, view(pts), scale, counts, minutes, bits, opts->work,
-                                ctx->stream, err);
+        rc = sa::launch_sampled(scene->d, path->d, view(pts), scale, counts, minutes, bits, opts->longest,
+                                opts->work, ctx->stream, err);
     else
-        rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->work, ctx->spill,
-                                ctx->stream, err);
+        rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->longest, opts->work,
+                                ctx->spill, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate: " + err);
     return SA_OK;
 }
@@ -463,6 +469,8 @@ sa_status sa_accumulate_batched(sa_ctx *ctx, const sa_scene *scene, int32_t n_va
         (n_var > 0 && ids_per_var > 0 && (!var_ids || !var_h)))
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate_batched: bad arguments");
     if (opts->mode != SA_ACCRUAL) return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate_batched: accrual form only");
+    if (opts->longest)
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate_batched: continuous shadow is not offered here");
     sa_status rc = check_points(ctx, pts);
     if (rc != SA_OK) return rc;
     if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");

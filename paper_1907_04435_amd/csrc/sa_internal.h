@@ -31,8 +31,10 @@ static_assert(sizeof(Node) == 64, "node is one 64-byte line");
 struct alignas(32) SampleConst {
     float dx, dy, dz, w;  // unit direction toward the sun, weight (minutes)
     float ix, iy, iz;     // 1 / direction (components kept away from zero)
-    int32_t bin;
+    int32_t tag;          // output bin | kDayStart on the first instant of a day
 };
+constexpr int32_t kDayStart = 1 << 30;
+constexpr int32_t kBinMask = kDayStart - 1;
 
 // Per great-circle segment of the accrual form.  In the segment's plane
 // the direction at angle phi from the first knot is
@@ -83,6 +85,7 @@ struct DevicePath {
     SampleConst *samples = nullptr;  // [n_samples]
     SegConst *segs = nullptr;        // [n_segs]
     int32_t words = 0;               // ceil(n_samples / 32)
+    std::vector<int32_t> day_seg_off;  // host: first segment of each day, [n_days + 1]
 };
 
 // Host-side builders implemented in the .hip sources.
@@ -112,10 +115,10 @@ struct SpillQueue {
 };
 
 sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
-                         float scale, int32_t *counts, float *minutes, uint32_t *bits,
+                         float scale, int32_t *counts, float *minutes, uint32_t *bits, float *longest,
                          uint64_t *work, hipStream_t st, std::string &err);
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
-                         float scale, int32_t *counts, float *minutes, uint64_t *work,
+                         float scale, int32_t *counts, float *minutes, float *longest, uint64_t *work,
                          SpillQueue &q, hipStream_t st, std::string &err);
 sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
                       const float *dl, float *grad, SpillQueue &q, hipStream_t st, std::string &err);
