@@ -224,7 +224,7 @@ def tuned_grid_blocks():
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seg", type=float, default=30.0, help="accrual knot spacing, minutes")
     ap.add_argument("--sampled-steps", type=int, default=1)
@@ -235,6 +235,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-work-count", action="store_true")
     ap.add_argument("--skip-sampled", action="store_true")
+    ap.add_argument("--skip-continuous", action="store_true",
+                    help="skip the continuous-shadow leg (accrual form with the longest-run output)")
     ap.add_argument("--no-truth", action="store_true",
                     help="skip the accuracy leg (accrual with 1-minute knots as the continuous truth)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -312,6 +314,8 @@ def main():
     launch_ms = [a.elapsed_time(b) for a, b in evs]
     ms_step = total_ms / args.steps
     log(f"accrual: {ms_step:.1f} ms/step, launches {['%.1f' % x for x in launch_ms]}")
+    launch_stats = {"median": float(np.median(launch_ms)), "min": float(np.min(launch_ms)),
+                    "max": float(np.max(launch_ms))}
 
     result = {
         "metric": "point-sun-step evals/s (accrual form; sampled form beside it)",
@@ -323,7 +327,26 @@ def main():
         "config": {"workload": w.name, "points": n, "ground_points": ng, "facade_points": n - ng,
                    "buildings": w.scene.n_b, "instants_per_point": K, "days": B, "seg_min": args.seg,
                    "point_sun_steps": evals},
+        "accumulate_launch_ms": launch_stats,
     }
+
+    # ---- continuous shadow leg (gross and longest uninterrupted shadow in one pass)
+    if not args.skip_continuous:
+        longest = torch.empty((B, n), dtype=torch.float32, device=dev)
+        sa.sa_accumulate(ctx, scene, pts, path, sa.SA_ACCRUAL, counts_a, mins_a, longest=longest)   # warm
+        ctx.sync()
+        cev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        cev[0].record(stream)
+        for _ in range(2):
+            sa.sa_accumulate(ctx, scene, pts, path, sa.SA_ACCRUAL, counts_a, mins_a, longest=longest)
+        cev[1].record(stream)
+        ctx.sync()
+        c_ms = cev[0].elapsed_time(cev[1]) / 2
+        log(f"continuous shadow: {c_ms:.1f} ms/pass")
+        result["continuous_shadow"] = {"value": evals / (c_ms / 1e3), "unit": "point-sun-steps/s",
+                                       "ms_per_pass": c_ms, "kernel": "k_accrual_runs",
+                                       "mean_longest_minutes": float(longest.double().mean())}
+        del longest
 
     # ---- sampled leg
     if not args.skip_sampled:

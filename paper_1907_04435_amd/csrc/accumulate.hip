@@ -113,8 +113,10 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
         const bool sh = valid && (back || hit);
         cnt += sh ? 1 : 0;
         mins += sh ? s.w : 0.f;
-        run = sh ? run + s.w : 0.f;
-        best = fmaxf(best, run);
+        if (longest) {
+            run = sh ? run + s.w : 0.f;
+            best = fmaxf(best, run);
+        }
         if (kBits) {
             word |= (uint32_t)sh << (k & 31);
             if ((k & 31) == 31 || k == K - 1) {
