@@ -48,6 +48,8 @@ def lib():
         L.orc_continuous.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, ip, C.c_int, ip, C.c_int,
                                      C.c_double, dp, ip, C.c_int, dp, ip, dp, C.c_int]
         L.orc_slerp.argtypes = [dp, dp, C.c_double, dp]
+        L.orc_contribution.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, ip, ip, C.c_int, C.c_double, dp,
+                                       dp, C.c_int]
         L.orc_grad_implicit.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, ip, ip, C.c_double, dp, dp,
                                         C.c_int]
         _lib = L
@@ -252,6 +254,39 @@ def longest_sampled(shadowed, path: OraclePath):
         b = path.day_bin[d]
         out[b] = np.maximum(out[b], best)
     return out
+
+
+def contribution(scene, pts, path: OraclePath, weight=None, grid_min=1.0 / 12.0, threads=None):
+    """Building contribution (Sec. 7.2): FP64 [n_bins, n_b], per building the
+    weighted minutes the points spend in that building's own shadow along
+    the path's great-circle segments (overlapping shadows count for every
+    building that casts them).  ``weight``: per-point weight (area), None
+    = 1."""
+    s, ks = _scene(scene)
+    p, kp = _points(pts)
+    out = np.zeros((path.n_bins, max(scene.n_b, 1)), np.float64)
+    seg_t = np.ascontiguousarray(path.seg_t, np.float64)
+    seg_dir = np.ascontiguousarray(path.seg_dir, np.float64)
+    seg_day = np.ascontiguousarray(path.seg_day, np.int32)
+    day_bin = np.ascontiguousarray(path.day_bin, np.int32)
+    wt = None if weight is None else np.ascontiguousarray(weight, np.float64)
+    lib().orc_contribution(C.byref(s), C.byref(p), len(seg_t), _ptr(seg_t, C.c_double),
+                           _ptr(seg_dir, C.c_double), _ptr(seg_day, C.c_int32), _ptr(day_bin, C.c_int32),
+                           path.n_bins, float(grid_min), _ptr(wt, C.c_double), _ptr(out, C.c_double),
+                           threads or threads_default())
+    return out[:, :scene.n_b]
+
+
+def shadow_score(values, bin_weight, bin_span, area=None):
+    """Shadow score of a region (Sec. 7.2): sum over its points of area(p)
+    times sum over intervals t of w_t * shadow_t(p), with shadow_t(p) the
+    fraction of the interval's daylight the point spends in shadow:
+    values[t, p] (minutes) / bin_span[t] (the interval's daylight minutes).
+    FP64 scalar."""
+    v = np.asarray(values, np.float64)
+    a = np.ones(v.shape[1]) if area is None else np.asarray(area, np.float64)
+    frac = v / np.asarray(bin_span, np.float64)[:, None]
+    return float((np.asarray(bin_weight, np.float64)[:, None] * frac * a[None, :]).sum())
 
 
 def grad_implicit(scene, pts, path: OraclePath, dl=None, grid_min=1.0 / 12.0, threads=None):

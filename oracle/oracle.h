@@ -80,6 +80,16 @@ void orc_continuous(const orc_scene *s, const orc_points *p, int n_seg,
                     const double *sample_t, const int32_t *sample_day, int n_samples,
                     double *minutes, int32_t *counts, double *longest, int threads);
 
+/* ---- building contribution (Sec. 7.2) ---- */
+/* contrib [n_bins][n_b]: per building the weighted minutes the points spend
+ * in that building's own shadow along the path (a moment shadowed by several
+ * buildings counts for each; a facade point's back-facing wall counts for
+ * its own building).  weight [n] (NULL: 1). */
+void orc_contribution(const orc_scene *s, const orc_points *p, int n_seg,
+                      const double *seg_t, const double *seg_dir, const int32_t *seg_day,
+                      const int32_t *day_bin, int n_bins, double grid_min, const double *weight,
+                      double *contrib, int threads);
+
 /* ---- gradient of sum_p D_L(p) w.r.t. building heights ---- */
 /* grad [n_b]: d/dH_b of sum over points and days of dl_dmin[bin][p] *
  * (continuous shadowed minutes), dl_dmin NULL = all ones. */

@@ -726,3 +726,82 @@ void orc_grad_implicit(const orc_scene *s, const orc_points *p, int n_seg,
     parallel_for(p->n, threads, grad_point, &C);
     scene64_free(&S);
 }
+
+/* ---- building contribution (Sec. 7.2): per building, the weighted time
+ * the points spend in that building's own shadow ----
+ *
+ * Each building's shadowed intervals over a point's path are found exactly
+ * as for the continuous duration, but never merged with other buildings':
+ * a moment shadowed by two buildings counts for both.  The shadow of a
+ * facade point's own wall facing away from the sun belongs to its own
+ * building.  contrib[bin][b] += weight(p) x minutes. */
+typedef struct {
+    const scene64 *S;
+    const orc_points *P;
+    int n_seg;
+    const double *seg_t, *seg_dir;
+    const int32_t *seg_day, *day_bin;
+    double grid;
+    const double *weight;
+    int n_b;
+    double *contrib;
+} contrib_ctx;
+
+static pthread_mutex_t contrib_mu = PTHREAD_MUTEX_INITIALIZER;
+
+typedef struct { int64_t k; double v; } kv;
+
+static void contrib_point(void *vctx, int64_t i)
+{
+    contrib_ctx *C = (contrib_ctx *)vctx;
+    const scene64 *S = C->S;
+    const orc_points *P = C->P;
+    double p[3] = {P->x[i], P->y[i], P->z[i]};
+    double nrm[2] = {P->nx ? P->nx[i] : 0.0, P->ny ? P->ny[i] : 0.0};
+    int owner = P->owner ? P->owner[i] : -1;
+    double w = C->weight ? C->weight[i] : 1.0;
+    int n = 0, cap = 64;
+    kv *acc = (kv *)malloc(sizeof(kv) * cap);
+    for (int j = 0; j < C->n_seg; ++j) {
+        double ta = C->seg_t[2 * j], tb = C->seg_t[2 * j + 1];
+        if (!(tb > ta) || w == 0.0) continue;
+        const double *da = C->seg_dir + 6 * j, *db = da + 3;
+        int day = C->seg_day ? C->seg_day[j] : 0;
+        int bin = C->day_bin ? C->day_bin[day] : day;
+        double N[3];
+        seg_plane(da, db, N);
+        for (int b = (owner >= 0 ? -1 : 0); b < S->n_b; ++b) {
+            if (b >= 0 && (b == owner || box_off_plane(S, b, p, N))) continue;
+            ivec iv = {0, 0, 0};
+            occluder_intervals(S, b, p, nrm, ta, tb, da, db, C->grid, &iv);
+            double m = 0.0;
+            for (int k = 0; k < iv.n; ++k) m += iv.v[k].hi - iv.v[k].lo;
+            free(iv.v);
+            if (m == 0.0) continue;
+            if (n == cap) { cap *= 2; acc = (kv *)realloc(acc, sizeof(kv) * cap); }
+            acc[n].k = (int64_t)bin * C->n_b + (b >= 0 ? b : owner);
+            acc[n].v = w * m;
+            ++n;
+        }
+    }
+    pthread_mutex_lock(&contrib_mu);
+    for (int a = 0; a < n; ++a) C->contrib[acc[a].k] += acc[a].v;
+    pthread_mutex_unlock(&contrib_mu);
+    free(acc);
+}
+
+void orc_contribution(const orc_scene *s, const orc_points *p, int n_seg,
+                      const double *seg_t, const double *seg_dir, const int32_t *seg_day,
+                      const int32_t *day_bin, int n_bins, double grid_min, const double *weight,
+                      double *contrib, int threads)
+{
+    scene64 S;
+    scene64_init(&S, s);
+    memset(contrib, 0, sizeof(double) * (size_t)n_bins * (s->n_b ? s->n_b : 1));
+    contrib_ctx C;
+    memset(&C, 0, sizeof(C));
+    C.S = &S; C.P = p; C.n_seg = n_seg; C.seg_t = seg_t; C.seg_dir = seg_dir; C.seg_day = seg_day;
+    C.day_bin = day_bin; C.grid = grid_min; C.weight = weight; C.n_b = s->n_b; C.contrib = contrib;
+    parallel_for(p->n, threads, contrib_point, &C);
+    scene64_free(&S);
+}
