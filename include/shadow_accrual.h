@@ -264,6 +264,38 @@ sa_status sa_accumulate_batched(sa_ctx *ctx, const sa_scene *scene, int32_t n_va
 sa_status sa_grad_heights(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts,
                           const sa_path *path, const float *dl_dmin, float *grad);
 
+/* Building contribution (Sec. 7.2): per output bin and building, the time
+ * the points spend in that building's own shadow along the great-circle
+ * path of `path` (the accrual form), weighted per point (e.g. by the area a
+ * point stands for).  A moment shadowed by several buildings counts for
+ * each of them; a facade point's wall facing away from the sun counts for
+ * its own building; a point under a roof counts its whole span for that
+ * building.
+ *   weight   device float [n] or NULL (all ones)
+ *   contrib  device double [n_bins * n_b], bin-major, original building ids;
+ *            overwritten (minutes x weight).
+ * Errors: INVALID_ARG, DEVICE. */
+sa_status sa_building_contribution(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts,
+                                   const sa_path *path, const float *weight, double *contrib);
+
+/* Daylight minutes of every output bin of a path: the sum of its days'
+ * spans.  span: host double [n_bins].  Errors: INVALID_ARG. */
+sa_status sa_path_bin_span(const sa_path *path, double *span);
+
+/* Region shadow score (Sec. 7.2): out[r] = sum over p in
+ * [region_off[r], region_off[r+1]) of (area ? area[p] : 1) times
+ * sum over bins b of bin_weight[b] * values[b * n + p], accumulated in
+ * FP64.  With values = per-bin shadow minutes and bin_weight[b] =
+ * w_b / span_b (w_b in [-1, 1] the interval's weight, span_b from
+ * sa_path_bin_span) this is the score: the weighted fraction of each
+ * interval's daylight spent in shadow, summed over the region.
+ * values: device float [n_bins * n] (bin-major); bin_weight: device double
+ * [n_bins]; region_off: device int64 [n_reg+1]; area: device float [n] or
+ * NULL; out: device double [n_reg].  Errors: INVALID_ARG, OOM, DEVICE. */
+sa_status sa_region_score(sa_ctx *ctx, const float *values, int32_t n_bins, int64_t n,
+                          const double *bin_weight, const int64_t *region_off, int32_t n_reg,
+                          const float *area, double *out);
+
 /* Region sums (the shadow area of Sec. 7.2): out[r] = sum over
  * p in [region_off[r], region_off[r+1]) of values[p] * (area ? area[p] : 1),
  * accumulated in FP64.  values, area: device float [n]; region_off: device

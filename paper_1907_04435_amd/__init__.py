@@ -29,7 +29,8 @@ _ERRORS = {-1: "INVALID_ARG", -2: "GEOMETRY", -3: "CAPACITY", -4: "OOM", -5: "DE
 EXPORTS = ["sa_create", "sa_destroy", "sa_set_stream", "sa_last_error", "sa_sync", "sa_version",
            "sa_scene_upload", "sa_scene_set_heights", "sa_scene_get_info", "sa_scene_read_bvh",
            "sa_scene_destroy", "sa_sunpath", "sa_path_upload", "sa_path_info", "sa_path_destroy",
-           "sa_accumulate", "sa_accumulate_batched", "sa_grad_heights", "sa_region_sum"]
+           "sa_accumulate", "sa_accumulate_batched", "sa_grad_heights", "sa_region_sum",
+           "sa_building_contribution", "sa_path_bin_span", "sa_region_score"]
 
 
 class SAError(RuntimeError):
@@ -103,6 +104,9 @@ def lib():
                                             C.POINTER(sa_accum_opts), vp, vp]),
             "sa_grad_heights": (i32, [vp, vp, C.POINTER(sa_points), vp, vp, vp]),
             "sa_region_sum": (i32, [vp, vp, i64, vp, i32, vp, vp]),
+            "sa_building_contribution": (i32, [vp, vp, C.POINTER(sa_points), vp, vp, vp]),
+            "sa_path_bin_span": (i32, [vp, vp]),
+            "sa_region_score": (i32, [vp, vp, i32, i64, vp, vp, i32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -307,6 +311,14 @@ class Path:
         _check(ctx, lib().sa_path_info(h, C.byref(nb), C.byref(ns), C.byref(nseg)))
         self.n_bins, self.n_samples, self.n_segments = nb.value, ns.value, nseg.value
 
+    def bin_span(self) -> np.ndarray:
+        """Daylight minutes of every output bin (host float64)."""
+        out = np.zeros(self.n_bins, np.float64)
+        rc = lib().sa_path_bin_span(self.handle, out.ctypes.data)
+        if rc != 0:
+            raise SAError(rc, "sa_path_bin_span failed")
+        return out
+
     def close(self):
         if getattr(self, "handle", None):
             lib().sa_path_destroy(self.handle)
@@ -394,6 +406,40 @@ def sa_grad_heights(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, d
     ps = pts.struct()
     _check(ctx, lib().sa_grad_heights(ctx.handle, scene.handle, C.byref(ps), path.handle, _ptr(dl_dmin),
                                       _ptr(grad)))
+
+
+def sa_building_contribution(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, weight, contrib):
+    ps = pts.struct()
+    _check(ctx, lib().sa_building_contribution(ctx.handle, scene.handle, C.byref(ps), path.handle, _ptr(weight),
+                                               _ptr(contrib)))
+
+
+def building_contribution(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, weight=None):
+    """Per bin and building (original ids) the weighted minutes the points
+    spend in that building's own shadow: device float64 [bins, n_b]."""
+    torch = ctx.torch
+    out = torch.empty((path.n_bins, scene.n_b), dtype=torch.float64, device=f"cuda:{ctx.device}")
+    sa_building_contribution(ctx, scene, pts, path, weight, out)
+    return out
+
+
+def sa_region_score(ctx: Context, values, bin_weight, region_off, out, area=None):
+    n_bins, n = int(values.shape[0]), int(values.shape[1])
+    _check(ctx, lib().sa_region_score(ctx.handle, _ptr(values), n_bins, n, _ptr(bin_weight), _ptr(region_off),
+                                      int(region_off.numel()) - 1, _ptr(area), _ptr(out)))
+
+
+def shadow_score(ctx: Context, path: Path, values, interval_weight, region_off, area=None):
+    """Shadow score of regions (Sec. 7.2) from per-bin shadow minutes
+    ``values`` [bins, n] and one weight in [-1, 1] per bin: returns device
+    float64 [n_regions]."""
+    torch = ctx.torch
+    span = path.bin_span()
+    w = torch.tensor(np.asarray(interval_weight, np.float64) / span, dtype=torch.float64,
+                     device=values.device)
+    out = torch.empty(int(region_off.numel()) - 1, dtype=torch.float64, device=values.device)
+    sa_region_score(ctx, values, w, region_off, out, area)
+    return out
 
 
 def sa_region_sum(ctx: Context, values, region_off, out, area=None):

@@ -468,6 +468,60 @@ __global__ __launch_bounds__(kThreads) void k_spill(const Node *nodes_g, const f
     }
 }
 
+// ------------------------------------------------------------------ contribution
+// Building contribution (Sec. 7.2): every building's own occluded interval
+// over each segment, never merged with the others' and with no early exit
+// (a lane whose window is already shadowed keeps walking: later buildings
+// still count).  The lanes' weighted minutes for one leaf are summed across
+// the wave and added with one FP64 atomic; a back-facing wall counts for
+// the point's own building.
+__global__ __launch_bounds__(kThreads) void k_contrib(const Node *nodes_g, const float4 *verts_g,
+                                                      const float *height_g, const SegConst *segs_g, int j0,
+                                                      int j1, PointArgs P, const float *weight,
+                                                      const int32_t *order, int n_b, double *contrib)
+{
+    cNode *nodes = (cNode *)nodes_g;
+    cfloat4 *verts = (cfloat4 *)verts_g;
+    cfloat *height = (cfloat *)height_g;
+    cSeg *segs = (cSeg *)segs_g;
+    __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    StackEntry *stack = s_stack[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
+    const int64_t i = wave * 64 + lane;
+    const bool valid = i < P.n;
+    const LanePoint q = load_point(P, i, valid);
+    const float wt = valid ? (weight ? weight[i] : 1.f) : 0.f;
+    Work none{0, 0, 0, 0, 0, 0, 0};
+    for (int j = j0; j < j1; ++j) {
+        const SegConst g = ld(segs + j);
+        const bool active = valid & (wt != 0.f);
+        double *row = contrib + (int64_t)g.bin * n_b;
+        if (active && q.own >= 0) {
+            float a, b;
+            if (backface_interval(q.nx, q.ny, g, 0.f, g.theta, 1.f, 0.f, g.cth, g.sth, a, b))
+                atomicAdd(&row[order[q.own]], (double)((b - a) * g.rate * wt));
+        }
+        if (nodes_g == nullptr) continue;
+        bool live = active;
+        const FanTest bt(g, q.px, q.py, q.pz);
+        auto leaf = [&](int prim, int voff, int m, uint64_t want) {
+            const uint64_t gm = want & ballot(prim != q.own);
+            if (!gm) return;
+            const bool go = lane_in(gm);
+            float a = 0.f, b = 0.f, da, db;
+            const int r = go ? prism_interval<false>(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, 0.f,
+                                                     g.theta, 1.f, 0.f, g.cth, g.sth, a, b, da, db)
+                             : 0;
+            double v = r ? (double)((b - a) * g.rate * wt) : 0.0;
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (first_active_lane() && v != 0.0) atomicAdd(&row[order[prim]], v);
+        };
+        auto key = [](float, float, float, float, float) { return 0.f; };
+        packet_traverse<false>(nodes, stack, live, bt, leaf, key, none);
+    }
+}
+
 // ------------------------------------------------------------------ batched
 // Variant v of the scene differs from the base only in the heights of a few
 // buildings.  Each variant gets its own copy of the node array and heights;
@@ -788,6 +842,24 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
         SA_CHECK_LAUNCH("accrual kernel");
         sa_status rc = run_spill(s, p, P, scale, counts, minutes, q, st, err);
         if (rc != SA_OK) return rc;
+    }
+    return SA_OK;
+}
+
+sa_status launch_contribution(const DeviceScene &s, const DevicePath &p, const PointsView &pts, const float *weight,
+                              double *contrib, hipStream_t st, std::string &err)
+{
+    if (pts.n == 0 || s.n_b == 0) return SA_OK;
+    const int64_t waves = (pts.n + 63) / 64;
+    const int64_t grid = (waves + kWaves - 1) / kWaves;
+    const PointArgs P = point_args(pts, s);
+    // long spans: several launches over consecutive segment ranges
+    const int64_t per = std::max<int64_t>(1, kChunkWork / 2 / std::max<int64_t>(pts.n, 1));
+    for (int64_t j0 = 0; j0 < p.n_segs; j0 += per) {
+        const int j1 = (int)std::min<int64_t>(j0 + per, p.n_segs);
+        hipLaunchKernelGGL(k_contrib, dim3((unsigned)grid), dim3(kThreads), 0, st, s.nodes, s.verts, s.height, p.segs,
+                           (int)j0, j1, P, weight, (const int32_t *)s.order, s.n_b, contrib);
+        SA_CHECK_LAUNCH("contribution kernel");
     }
     return SA_OK;
 }

@@ -262,6 +262,7 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
     std::vector<sa::SampleConst> samples(in->n_samples);
     std::vector<sa::SegConst> segs;
     std::vector<int32_t> day_seg_off;
+    std::vector<double> bin_span;  // daylight minutes per bin: the instants' weights add up to each day's span
     int n_bins = 0;
     for (int d = 0; d < D; ++d) {
         day_seg_off.push_back((int32_t)segs.size());
@@ -285,6 +286,8 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
             c.iy = inv(c.dy);
             c.iz = inv(c.dz);
             c.tag = bin | (k == s0 ? sa::kDayStart : 0);
+            if ((int)bin_span.size() <= bin) bin_span.resize(bin + 1, 0.0);
+            bin_span[bin] += in->weight[k];
         }
         const double step = s1 - s0 >= 2 ? in->t_min[s0 + 1] - in->t_min[s0] : 1.0;
         for (int k = k0; k + 1 < k1; ++k) {
@@ -364,6 +367,8 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
     p->d.n_bins = n_bins;
     day_seg_off.push_back((int32_t)segs.size());
     p->d.day_seg_off = std::move(day_seg_off);
+    bin_span.resize(n_bins, 0.0);
+    p->d.bin_span = std::move(bin_span);
     p->d.words = (in->n_samples + 31) / 32;
     hipError_t e = hipSuccess;
     if (!samples.empty()) {
@@ -508,8 +513,47 @@ sa_status sa_region_sum(sa_ctx *ctx, const float *values, int64_t n, const int64
     if (n_reg == 0) return SA_OK;
     if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
     std::string err;
-    sa_status rc = sa::launch_region_sum(values, n, region_off, n_reg, area, out, ctx->scratch, ctx->stream, err);
+    sa_status rc = sa::launch_region_sum(values, 1, n, nullptr, region_off, n_reg, area, out, ctx->scratch,
+                                         ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_region_sum: " + err);
+    return SA_OK;
+}
+
+sa_status sa_region_score(sa_ctx *ctx, const float *values, int32_t n_bins, int64_t n, const double *bin_weight,
+                          const int64_t *region_off, int32_t n_reg, const float *area, double *out)
+{
+    if (!ctx) return SA_ERR_INVALID_ARG;
+    if (n < 0 || n_bins < 1 || n_reg < 0 || !bin_weight || (n_reg > 0 && (!region_off || !out)) ||
+        (n > 0 && !values))
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_region_score: bad arguments");
+    if (n_reg == 0) return SA_OK;
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    std::string err;
+    sa_status rc = sa::launch_region_sum(values, n_bins, n, bin_weight, region_off, n_reg, area, out,
+                                         ctx->scratch, ctx->stream, err);
+    if (rc != SA_OK) return fail(ctx, rc, "sa_region_score: " + err);
+    return SA_OK;
+}
+
+sa_status sa_path_bin_span(const sa_path *path, double *span)
+{
+    if (!path || !span) return SA_ERR_INVALID_ARG;
+    for (int b = 0; b < path->d.n_bins; ++b) span[b] = path->d.bin_span[b];
+    return SA_OK;
+}
+
+sa_status sa_building_contribution(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts, const sa_path *path,
+                                   const float *weight, double *contrib)
+{
+    if (!ctx) return SA_ERR_INVALID_ARG;
+    if (!scene || !path || !contrib) return fail(ctx, SA_ERR_INVALID_ARG, "sa_building_contribution: null argument");
+    sa_status rc = check_points(ctx, pts);
+    if (rc != SA_OK) return rc;
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    std::string err;
+    rc = sa::fill_u32(contrib, 2 * (int64_t)path->d.n_bins * scene->d.n_b, 0u, ctx->stream, err);
+    if (rc == SA_OK) rc = sa::launch_contribution(scene->d, path->d, view(pts), weight, contrib, ctx->stream, err);
+    if (rc != SA_OK) return fail(ctx, rc, "sa_building_contribution: " + err);
     return SA_OK;
 }
 

@@ -1,5 +1,6 @@
 // Region sums of per-point values (the shadow area of Sec. 7.2, with each
-// point standing for area[p] square metres), accumulated in FP64.
+// point standing for area[p] square metres) and their bin-weighted form
+// (the shadow score of Sec. 7.2), accumulated in FP64.
 #include <hip/hip_runtime.h>
 
 #include "sa_internal.h"
@@ -13,8 +14,10 @@ constexpr int kBlocksPerRegion = 128;
 // Phase 1: block b of region r sums a strided share of the region into
 // part[r * kBlocksPerRegion + b] (wave reductions with cross-lane moves,
 // then LDS).  Phase 2 adds each region's partials in a fixed order, so the
-// result does not depend on scheduling.
-__global__ __launch_bounds__(kThreads) void k_region_part(const float *__restrict__ v,
+// result does not depend on scheduling.  With bin weights, a point's value
+// is the weighted sum of its bins' values (bin-major, stride n).
+__global__ __launch_bounds__(kThreads) void k_region_part(const float *__restrict__ v, int n_bins, int64_t n,
+                                                          const double *__restrict__ bin_w,
                                                           const int64_t *__restrict__ off,
                                                           const float *__restrict__ area, double *__restrict__ part)
 {
@@ -23,8 +26,16 @@ __global__ __launch_bounds__(kThreads) void k_region_part(const float *__restric
     const int64_t lo = off[r], hi = off[r + 1];
     double s = 0.0;
     for (int64_t i = lo + (int64_t)blockIdx.x * kThreads + threadIdx.x; i < hi;
-         i += (int64_t)kBlocksPerRegion * kThreads)
-        s += (double)v[i] * (area ? (double)area[i] : 1.0);
+         i += (int64_t)kBlocksPerRegion * kThreads) {
+        double x;
+        if (bin_w) {
+            x = 0.0;
+            for (int b = 0; b < n_bins; ++b) x += bin_w[b] * (double)v[(int64_t)b * n + i];
+        } else {
+            x = (double)v[i];
+        }
+        s += x * (area ? (double)area[i] : 1.0);
+    }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
     __syncthreads();
@@ -47,12 +58,13 @@ __global__ __launch_bounds__(64) void k_region_final(int n_reg, const double *__
 
 }  // namespace
 
-sa_status launch_region_sum(const float *v, int64_t n, const int64_t *off, int32_t n_reg, const float *area,
-                            double *out, Scratch &scr, hipStream_t st, std::string &err)
+sa_status launch_region_sum(const float *v, int n_bins, int64_t n, const double *bin_w, const int64_t *off,
+                            int32_t n_reg, const float *area, double *out, Scratch &scr, hipStream_t st,
+                            std::string &err)
 {
-    (void)n;
     const size_t need = sizeof(double) * (size_t)n_reg * kBlocksPerRegion;
     if (scr.bytes < need) {
+        (void)hipStreamSynchronize(st);
         (void)hipFree(scr.ptr);
         scr.ptr = nullptr;
         scr.bytes = 0;
@@ -63,7 +75,8 @@ sa_status launch_region_sum(const float *v, int64_t n, const int64_t *off, int32
         scr.bytes = need;
     }
     double *part = (double *)scr.ptr;
-    hipLaunchKernelGGL(k_region_part, dim3(kBlocksPerRegion, n_reg), dim3(kThreads), 0, st, v, off, area, part);
+    hipLaunchKernelGGL(k_region_part, dim3(kBlocksPerRegion, n_reg), dim3(kThreads), 0, st, v, n_bins, n, bin_w, off,
+                       area, part);
     hipLaunchKernelGGL(k_region_final, dim3((n_reg + 63) / 64), dim3(64), 0, st, n_reg, (const double *)part, out);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {

@@ -86,6 +86,7 @@ struct DevicePath {
     SegConst *segs = nullptr;        // [n_segs]
     int32_t words = 0;               // ceil(n_samples / 32)
     std::vector<int32_t> day_seg_off;  // host: first segment of each day, [n_days + 1]
+    std::vector<double> bin_span;      // host: daylight minutes of each output bin
 };
 
 // Host-side builders implemented in the .hip sources.
@@ -122,9 +123,11 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
                          SpillQueue &q, hipStream_t st, std::string &err);
 sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
                       const float *dl, float *grad, SpillQueue &q, hipStream_t st, std::string &err);
-sa_status launch_region_sum(const float *v, int64_t n, const int64_t *off, int32_t n_reg,
-                            const float *area, double *out, Scratch &scr, hipStream_t st,
-                            std::string &err);
+sa_status launch_region_sum(const float *v, int n_bins, int64_t n, const double *bin_w,
+                            const int64_t *off, int32_t n_reg, const float *area, double *out,
+                            Scratch &scr, hipStream_t st, std::string &err);
+sa_status launch_contribution(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
+                              const float *weight, double *contrib, hipStream_t st, std::string &err);
 sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_var, int32_t k,
                          const int32_t *ids, const float *h, const PointsView &pts,
                          const int64_t *var_off, float scale, int32_t *counts, float *minutes,
