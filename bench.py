@@ -235,6 +235,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-work-count", action="store_true")
     ap.add_argument("--skip-sampled", action="store_true")
+    ap.add_argument("--skip-contribution", action="store_true",
+                    help="skip the building-contribution leg")
     ap.add_argument("--skip-continuous", action="store_true",
                     help="skip the continuous-shadow leg (accrual form with the longest-run output)")
     ap.add_argument("--no-truth", action="store_true",
@@ -347,6 +349,23 @@ def main():
                                        "ms_per_pass": c_ms, "kernel": "k_accrual_runs",
                                        "mean_longest_minutes": float(longest.double().mean())}
         del longest
+
+    # ---- building contribution leg (every building's own shadow time on the points)
+    if not args.skip_contribution:
+        contrib = torch.empty((B, w.scene.n_b), dtype=torch.float64, device=dev)
+        sa.sa_building_contribution(ctx, scene, pts, path, None, contrib)   # warm
+        ctx.sync()
+        bev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        bev[0].record(stream)
+        sa.sa_building_contribution(ctx, scene, pts, path, None, contrib)
+        bev[1].record(stream)
+        ctx.sync()
+        b_ms = bev[0].elapsed_time(bev[1])
+        log(f"building contribution: {b_ms:.1f} ms/pass")
+        result["building_contribution"] = {"value": evals / (b_ms / 1e3), "unit": "point-sun-steps/s",
+                                           "ms_per_pass": b_ms, "kernel": "k_contrib",
+                                           "buildings_with_shadow": int((contrib > 0).any(0).sum())}
+        del contrib
 
     # ---- sampled leg
     if not args.skip_sampled:
