@@ -233,6 +233,9 @@ typedef struct {
  *   bits    device uint32 [ceil(n_samples/32) * n] (word-major; SA_SAMPLED
  *           only; NULL = not wanted): bit k%32 of word k/32 of point i is
  *           instant k's predicate -- the n-bit shadow vector of Sec. 5.
+ * Results are deterministic except in the last bits of minutes for points
+ * with a spilled point-segment (more than four pieces), whose measures are
+ * added with float atomics in no fixed order.
  * Errors: INVALID_ARG, CAPACITY (reported by sa_sync if the accrual spill
  * queue overflows), DEVICE. */
 sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts,
