@@ -86,12 +86,16 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
         bool hit = false;
         if (nodes_g != nullptr) {
             const float ox = -q.px * s.ix, oy = -q.py * s.iy, oz = -q.pz * s.iz;
-            const bool sx = s.dx >= 0.f, sy = s.dy >= 0.f;
+            // slab test: each axis's entry and exit by min / max (no selects
+            // on the direction's signs); every box starts at z = 0, below
+            // the ray's origin, so only its top bounds the ray in z
             auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
-                const float tnx = fmaf(sx ? x0 : x1, s.ix, ox), tfx = fmaf(sx ? x1 : x0, s.ix, ox);
-                const float tny = fmaf(sy ? y0 : y1, s.iy, oy), tfy = fmaf(sy ? y1 : y0, s.iy, oy);
+                const float ax = fmaf(x0, s.ix, ox), bx = fmaf(x1, s.ix, ox);
+                const float ay = fmaf(y0, s.iy, oy), by = fmaf(y1, s.iy, oy);
                 const float tfz = fmaf(z1, s.iz, oz);
-                return fmaxf(fmaxf(tnx, tny), 0.f) <= fminf(fminf(tfx, tfy), tfz);
+                const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), 0.f);
+                const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), tfz);
+                return le_mask(tn, tf);
             };
             auto leaf = [&](int prim, int voff, int m, uint64_t want) {
                 const bool go = lane_in(want & ballot(prim != q.own));
