@@ -364,56 +364,108 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
     // a candidate yet, which see the footprint from inside every edge, which
     // vertices are below the roof line.  Only the selects are vector work.
     uint64_t have = 0, inside = ~0ull;
-    auto cand = [&](float cu, float cv, float dc, uint64_t ok) {
-        const uint64_t take_lo = ok & (~have | lt_mask(cross2(lou, lov, cu, cv), 0.f));
-        const uint64_t take_hi = ok & (~have | gt_mask(cross2(hiu, hiv, cu, cv), 0.f));
-        lou = lane_in(take_lo) ? cu : lou;
-        lov = lane_in(take_lo) ? cv : lov;
-        hiu = lane_in(take_hi) ? cu : hiu;
-        hiv = lane_in(take_hi) ? cv : hiv;
-        if constexpr (kGrad) {
-            dlo = lane_in(take_lo) ? dc : dlo;
-            dhi = lane_in(take_hi) ? dc : dhi;
+    if constexpr (kGrad) {
+        auto cand = [&](float cu, float cv, float dc, uint64_t ok) {
+            const uint64_t take_lo = ok & (~have | lt_mask(cross2(lou, lov, cu, cv), 0.f));
+            const uint64_t take_hi = ok & (~have | gt_mask(cross2(hiu, hiv, cu, cv), 0.f));
+            lou = lane_in(take_lo) ? cu : lou;
+            lov = lane_in(take_lo) ? cv : lov;
+            hiu = lane_in(take_hi) ? cu : hiu;
+            hiv = lane_in(take_hi) ? cv : hiv;
+            if constexpr (kGrad) {
+                dlo = lane_in(take_lo) ? dc : dlo;
+                dhi = lane_in(take_hi) ? dc : dhi;
+            }
+            have |= ok;
+        };
+        // footprint vertex k relative to p: world offset (wx, wy), in-plane
+        // (u, v) and height z of the segment plane above p there
+        auto vertex = [&](int k, float &wx, float &wy, float &u, float &v, float &z) {
+            const float4 q = ld(verts + voff + k);
+            wx = q.x - px;
+            wy = q.y - py;
+            u = fmaf(g.m00, wx, g.m01 * wy);
+            v = fmaf(g.m10, wx, g.m11 * wy);
+            z = fmaf(g.e1z, u, g.e2z * v);
+        };
+        float pwx, pwy, pu, pv, pzv;
+        vertex(0, pwx, pwy, pu, pv, pzv);
+        uint64_t pin = le_mask(pzv, h);
+        cand(pu, pv, 0.f, pin);
+        // edge e runs from vertex e - 1 to vertex e mod m; vertex 0 is read
+        // again for the closing edge rather than kept in registers
+        for (int e = 1; e <= m; ++e) {
+            float wx, wy, u, v, z;
+            vertex(e == m ? 0 : e, wx, wy, u, v, z);
+            const uint64_t in = le_mask(z, h);
+            inside &= ge_mask(cross2(pwx, pwy, wx, wy), 0.f);
+            const uint64_t crossing = (pin ^ in) & ballot(true);
+            if (crossing) {
+                const float rdz = __builtin_amdgcn_rcpf(z - pzv);
+                const float t = (h - pzv) * rdz;
+                const float cu = fmaf(t, u - pu, pu), cv = fmaf(t, v - pv, pv);
+                float dc = 0.f;
+                if constexpr (kGrad) dc = cross2(cu, cv, u - pu, v - pv) * rdz * __builtin_amdgcn_rcpf(fmaf(cu, cu, cv * cv));
+                cand(cu, cv, dc, crossing);
+            }
+            if (e < m) cand(u, v, 0.f, in);
+            pu = u;
+            pv = v;
+            pzv = z;
+            pwx = wx;
+            pwy = wy;
+            pin = in;
         }
-        have |= ok;
-    };
-    // footprint vertex k relative to p: world offset (wx, wy), in-plane
-    // (u, v) and height z of the segment plane above p there
-    auto vertex = [&](int k, float &wx, float &wy, float &u, float &v, float &z) {
-        const float4 q = ld(verts + voff + k);
-        wx = q.x - px;
-        wy = q.y - py;
-        u = fmaf(g.m00, wx, g.m01 * wy);
-        v = fmaf(g.m10, wx, g.m11 * wy);
-        z = fmaf(g.e1z, u, g.e2z * v);
-    };
-    float pwx, pwy, pu, pv, pzv;
-    vertex(0, pwx, pwy, pu, pv, pzv);
-    uint64_t pin = le_mask(pzv, h);
-    cand(pu, pv, 0.f, pin);
-    // edge e runs from vertex e - 1 to vertex e mod m; vertex 0 is read
-    // again for the closing edge rather than kept in registers
-    for (int e = 1; e <= m; ++e) {
-        float wx, wy, u, v, z;
-        vertex(e == m ? 0 : e, wx, wy, u, v, z);
-        const uint64_t in = le_mask(z, h);
-        inside &= ge_mask(cross2(pwx, pwy, wx, wy), 0.f);
-        const uint64_t crossing = (pin ^ in) & ballot(true);
-        if (crossing) {
-            const float rdz = __builtin_amdgcn_rcpf(z - pzv);
-            const float t = (h - pzv) * rdz;
-            const float cu = fmaf(t, u - pu, pu), cv = fmaf(t, v - pv, pv);
-            float dc = 0.f;
-            if constexpr (kGrad) dc = cross2(cu, cv, u - pu, v - pv) * rdz * __builtin_amdgcn_rcpf(fmaf(cu, cu, cv * cv));
-            cand(cu, cv, dc, crossing);
+    } else {
+        // Without derivatives the extremes are found in world offsets from p:
+        // the map M into the segment plane is linear, so it keeps the angular
+        // order of directions (reverses it when det M < 0), and only the two
+        // extremes are mapped at the end.  z, the plane's height above p at a
+        // footprint point, is linear in the offset too: z = Z1 wx + Z2 wy.
+        const float Z1 = fmaf(g.e1z, g.m00, g.e2z * g.m10), Z2 = fmaf(g.e1z, g.m01, g.e2z * g.m11);
+        float lox = 0.f, loy = 0.f, hix = 0.f, hiy = 0.f;
+        auto cand = [&](float cx, float cy, uint64_t ok) {
+            const uint64_t take_lo = ok & (~have | lt_mask(cross2(lox, loy, cx, cy), 0.f));
+            const uint64_t take_hi = ok & (~have | gt_mask(cross2(hix, hiy, cx, cy), 0.f));
+            lox = lane_in(take_lo) ? cx : lox;
+            loy = lane_in(take_lo) ? cy : loy;
+            hix = lane_in(take_hi) ? cx : hix;
+            hiy = lane_in(take_hi) ? cy : hiy;
+            have |= ok;
+        };
+        auto vertex = [&](int k, float &wx, float &wy, float &z) {
+            const float4 q = ld(verts + voff + k);
+            wx = q.x - px;
+            wy = q.y - py;
+            z = fmaf(Z1, wx, Z2 * wy);
+        };
+        float pwx, pwy, pzv;
+        vertex(0, pwx, pwy, pzv);
+        uint64_t pin = le_mask(pzv, h);
+        cand(pwx, pwy, pin);
+        for (int e = 1; e <= m; ++e) {
+            float wx, wy, z;
+            vertex(e == m ? 0 : e, wx, wy, z);
+            const uint64_t in = le_mask(z, h);
+            inside &= ge_mask(cross2(pwx, pwy, wx, wy), 0.f);
+            const uint64_t crossing = (pin ^ in) & ballot(true);
+            if (crossing) {
+                const float t = (h - pzv) * __builtin_amdgcn_rcpf(z - pzv);
+                cand(fmaf(t, wx - pwx, pwx), fmaf(t, wy - pwy, pwy), crossing);
+            }
+            if (e < m) cand(wx, wy, in);
+            pwx = wx;
+            pwy = wy;
+            pzv = z;
+            pin = in;
         }
-        if (e < m) cand(u, v, 0.f, in);
-        pu = u;
-        pv = v;
-        pzv = z;
-        pwx = wx;
-        pwy = wy;
-        pin = in;
+        const bool flip = fmaf(g.m00, g.m11, -g.m01 * g.m10) < 0.f;
+        const float ax = flip ? hix : lox, ay = flip ? hiy : loy;
+        const float bx = flip ? lox : hix, by = flip ? loy : hiy;
+        lou = fmaf(g.m00, ax, g.m01 * ay);
+        lov = fmaf(g.m10, ax, g.m11 * ay);
+        hiu = fmaf(g.m00, bx, g.m01 * by);
+        hiv = fmaf(g.m10, bx, g.m11 * by);
     }
     da = db = 0.f;
     if (lane_in(inside)) {
