@@ -77,7 +77,10 @@ sa_status sa_set_stream(sa_ctx *ctx, void *hip_stream);
 /* Message of the last failed call on this context ("" if none). */
 const char *sa_last_error(const sa_ctx *ctx);
 /* Wait for the context's stream; reports errors raised by device work
- * since the last sync (spill-queue overflow). */
+ * since the last sync and clears them: CAPACITY if the accrual spill queue
+ * overflowed or an occluded set could not be split finely enough (results
+ * incomplete), INVALID_ARG if a batched variant named a bad building id or
+ * height. */
 sa_status sa_sync(sa_ctx *ctx);
 /* Library version string. */
 const char *sa_version(void);

@@ -401,7 +401,7 @@ __global__ __launch_bounds__(kThreads) void k_accrual_runs(const Node *nodes_g, 
             if (pending) {
                 if (ov) {
                     if (s < g.theta * (1.0f / 4096.0f)) {
-                        atomicOr(overflow, 1u);
+                        atomicOr(overflow, 2u);
                         pending = false;
                     } else {
                         s *= 0.5f;

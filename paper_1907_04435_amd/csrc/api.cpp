@@ -118,9 +118,13 @@ sa_status sa_sync(sa_ctx *ctx)
     if (e != hipSuccess) return hip_fail(ctx, e, "read spill flag");
     if (flag) {
         (void)hipMemset(ctx->spill.counters + 2, 0, sizeof(uint32_t));
+        // bit 0: spill queue full; bit 1: a window could not be split finely
+        // enough; bit 2: a variant named a bad building id or height
+        if (flag & 4u)
+            return fail(ctx, SA_ERR_INVALID_ARG, "batched variants: a building id or height was invalid");
         return fail(ctx, SA_ERR_CAPACITY,
                     (flag & 1u) ? "accrual spill queue overflowed: results incomplete"
-                                : "accrual spill rounds exhausted: results incomplete");
+                                : "occluded set too fragmented to split: results incomplete");
     }
     return SA_OK;
 }

@@ -70,3 +70,19 @@ def test_argument_errors(ctx, setup):
         sa.sa_building_contribution(ctx, sc, dp, path, None, None)         # no output
     assert e.value.code == -1
     ctx.sync()                                                              # nothing left pending
+
+
+def test_batched_bad_variant_reported_at_sync(ctx, setup, c1):
+    """A variant naming a building id outside the scene is rejected on the
+    device; the next sa_sync reports it (and clears it)."""
+    import torch
+    sc, dp, path = setup
+    c, m, _ = outputs(path, dp)
+    ids = torch.tensor([[c1.scene.n_b + 5]], dtype=torch.int32, device="cuda")
+    hh = torch.full((1, 1), 10.0, dtype=torch.float32, device="cuda")
+    off = torch.tensor([0, dp.n], dtype=torch.int64, device="cuda")
+    sa.sa_accumulate_batched(ctx, sc, ids, hh, dp, off, path, c, m)
+    with pytest.raises(sa.SAError) as e:
+        ctx.sync()
+    assert e.value.code == -1
+    ctx.sync()                                                # cleared
