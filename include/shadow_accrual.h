@@ -94,8 +94,9 @@ const char *sa_version(void);
  * vertices), height [n_b] (> 0).  Builds the bounding-volume hierarchy on
  * the device (Morton codes of footprint centres, radix sort, binary radix
  * tree, bottom-up box refit).  Host-synchronous.  n_b == 0 is an empty
- * scene (nothing casts shadow).  Errors: INVALID_ARG, GEOMETRY, CAPACITY
- * (tree deeper than 64 levels), OOM, DEVICE. */
+ * scene (nothing casts shadow); at most 2^25 prisms.  Errors: INVALID_ARG,
+ * GEOMETRY, CAPACITY (more than 2^25 prisms, or a tree deeper than 64
+ * levels), OOM, DEVICE. */
 sa_status sa_scene_upload(sa_ctx *ctx, int32_t n_b, const int32_t *vert_off,
                           const float *xy, const float *height, sa_scene **out);
 
@@ -239,8 +240,13 @@ typedef struct {
  * Results are deterministic except in the last bits of minutes for points
  * with a spilled point-segment (more than four pieces), whose measures are
  * added with float atomics in no fixed order.
+ * SA_ACCRUAL without `longest` keeps a per-segment view of the hierarchy
+ * (64 bytes per node and segment, at most 256 MiB; longer paths run as
+ * several launches) in memory the context owns: grown on first need with
+ * the stream synchronised, kept until sa_destroy.  Under stream capture
+ * make one eager call of the same (or a larger) size first.
  * Errors: INVALID_ARG, CAPACITY (reported by sa_sync if the accrual spill
- * queue overflows), DEVICE. */
+ * queue overflows), OOM, DEVICE. */
 sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts,
                         const sa_path *path, const sa_accum_opts *opts, int32_t *counts,
                         float *minutes, uint32_t *bits);

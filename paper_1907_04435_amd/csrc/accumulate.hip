@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "sa_internal.h"
 #include "traverse.h"
@@ -21,6 +22,7 @@ constexpr int kWaves = kThreads / 64;
 constexpr int kSpillRounds = 3;
 constexpr int kSpillBlocks = 1024;
 constexpr int64_t kChunkWork = 4000000000ll;  // point-segments per accrual launch
+constexpr int64_t kSegNodeBytes = 256ll << 20;  // per-segment node views per accrual launch
 
 // ------------------------------------------------------------------ sampled
 // Sum a per-lane counter over the wave and add it to a global total.
@@ -172,8 +174,19 @@ __device__ __forceinline__ void measure(const Union4 &U, const SegConst &g, floa
 // The occluded set of every live lane's point over its window of segment g:
 // back-face term, then the packet fan traversal.  On return `ov` marks
 // lanes whose set needed more than four pieces.
-template <bool kCount>
-__device__ __forceinline__ void accrue_segment(cNode *nodes, StackEntry *stack, cfloat4 *verts, cfloat *height,
+// Where a traversal reads the hierarchy: the nodes as built (the full fan
+// test at every child) or the views of the current segment (SegFan: seven
+// compares per child).
+struct TreeSrc {
+    cNode *nodes;
+};
+struct SegSrc {
+    cSegNode *nodes;
+    cint *voff;
+};
+
+template <bool kCount, class Src>
+__device__ __forceinline__ void accrue_segment(Src src, StackEntry *stack, cfloat4 *verts, cfloat *height,
                                                const SegConst &g, const LanePoint &q, bool active, float w0,
                                                float w1, Union4 &U, bool &ov, Work &wk)
 {
@@ -190,8 +203,7 @@ __device__ __forceinline__ void accrue_segment(cNode *nodes, StackEntry *stack, 
             live = !(a <= w0 && b >= w1);
         }
     }
-    if (nodes == nullptr) return;
-    const FanTest bt(g, q.px, q.py, q.pz);
+    if (src.nodes == nullptr) return;
     auto leaf = [&](int prim, int voff, int m, uint64_t want) {
         const uint64_t gm = want & ballot(prim != q.own);
         if (!gm) return;
@@ -216,11 +228,65 @@ __device__ __forceinline__ void accrue_segment(cNode *nodes, StackEntry *stack, 
             }
         }
     };
-    const float mdx = g.mdx, mdy = g.mdy;
-    auto key = [&](float x0, float y0, float x1, float y1, float z1) {
-        return fmaf(x0 + x1, mdx, (y0 + y1) * mdy);
-    };
-    packet_traverse<kCount>(nodes, stack, live, bt, leaf, key, wk);
+    if constexpr (std::is_same<Src, SegSrc>::value) {
+        // liveness and overflow as wave masks (see packet_traverse_seg)
+        uint64_t ovm = 0;
+        auto leaf_m = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
+            const uint64_t gm = want & ballot(prim != q.own);
+            if (!gm) return 0;
+            const bool go = lane_in(gm);
+            if constexpr (kCount) {
+                wk.prism += go ? 1u : 0u;
+                wk.edges += go ? (uint32_t)m : 0u;
+                wk.leaves += first_active_lane() ? 1u : 0u;
+            }
+            float a = 0.f, b = 0.f;
+            float da, db;
+            const int r = go ? prism_interval<false>(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, w0, w1,
+                                                     W0u, W0v, W1u, W1v, a, b, da, db)
+                             : 0;
+            if constexpr (kCount) wk.inserts += r ? 1u : 0u;
+            bool over = false, full = false;
+            if (r) {
+                over = !union_insert(U, a, b);
+                full = !over && U.n == 1 && U.lo[0] <= w0 && U.hi[0] >= w1;  // the whole window is in shadow
+            }
+            const uint64_t om = ballot(over);
+            ovm |= om;
+            return om | ballot(full);
+        };
+        const SegFan ft(g, q.px, q.py, q.pz);
+        packet_traverse_seg<kCount>(src.nodes, src.voff, stack, ballot(live), ft, leaf_m, wk);
+        ov = lane_in(ovm);
+    } else {
+        const FanTest bt(g, q.px, q.py, q.pz);
+        const float mdx = g.mdx, mdy = g.mdy;
+        auto key = [&](float x0, float y0, float x1, float y1, float z1) { return seg_key(x0, y0, x1, y1, mdx, mdy); };
+        packet_traverse<kCount>(src.nodes, stack, live, bt, leaf, key, wk);
+    }
+}
+
+// The per-segment node views of segments [j0, j1): one thread per
+// (segment, node), written to out[(j - j0) * n_nodes + node].
+__global__ void k_seg_nodes(const Node *__restrict__ nodes, int n_nodes, const SegConst *__restrict__ segs, int j0,
+                            int j1, SegNode *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)(j1 - j0) * n_nodes) return;
+    const int jj = (int)(t / n_nodes);
+    const int node = (int)(t - (int64_t)jj * n_nodes);
+    const SegConst &g = segs[j0 + jj];
+    const Node nd = nodes[node];
+    const FanGeom f = fan_geom(g);
+    const bool lfirst = seg_key(nd.lx0, nd.ly0, nd.lx1, nd.ly1, g.mdx, g.mdy) <=
+                        seg_key(nd.rx0, nd.ry0, nd.rx1, nd.ry1, g.mdx, g.mdy);
+    SegNode v;
+    const int a = lfirst ? 0 : 1;
+    seg_child(f, nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1, nd.left != kNone, v.c[a]);
+    seg_child(f, nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1, nd.right != kNone, v.c[1 - a]);
+    v.ref[a] = nd.left >= 0 ? nd.left * (int)sizeof(SegNode) : nd.left;
+    v.ref[1 - a] = nd.right >= 0 ? nd.right * (int)sizeof(SegNode) : nd.right;
+    out[t] = v;
 }
 
 // Roof-covered: inside a footprint (other than the point's own building)
@@ -245,14 +311,14 @@ __device__ __forceinline__ bool roof_covered(cNode *nodes, StackEntry *stack, cf
     return cov;
 }
 
-// Seven waves per SIMD: the compiler keeps the kernel within 72 VGPRs
-// (six otherwise), which hides more of the scalar-load and compare-chain
-// latency of the traversal loop.
+// Eight waves per SIMD: the kernel fits in 64 VGPRs (the compiler would
+// settle for fewer waves otherwise), which hides more of the scalar-load
+// and compare-chain latency of the traversal loop.
 template <bool kCount>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_accrual(const Node *nodes_g, const float4 *verts_g,
-                                                      const float *height_g, const SegConst *segs_g, int j0,
-                                                      int j1, PointArgs P, float scale, int32_t *counts,
-                                                      float *minutes, SpillArgs S, uint64_t *work)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_accrual(
+    const Node *nodes_g, const SegNode *snodes_g, int n_nodes, const int32_t *voff_g, const float4 *verts_g,
+    const float *height_g, const SegConst *segs_g, int j0, int j1, PointArgs P, float scale, int32_t *counts,
+    float *minutes, SpillArgs S, uint64_t *work)
 {
     Work wk{0, 0, 0, 0, 0, 0, 0};
     cNode *nodes = (cNode *)nodes_g;
@@ -285,8 +351,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
         }
         Union4 U;
         bool ov;
-        accrue_segment<kCount>(nodes_g ? nodes : nullptr, stack, verts, height, g, q, valid && !covered, 0.f,
-                               g.theta, U, ov, wk);
+        const SegSrc src{snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr,
+                         (cint *)voff_g};
+        accrue_segment<kCount>(src, stack, verts, height, g, q, valid && !covered, 0.f, g.theta, U, ov, wk);
         if constexpr (kCount) {
             wk.units += valid ? 1u : 0u;
             wk.spills += (valid && ov) ? 1u : 0u;
@@ -396,7 +463,7 @@ __global__ __launch_bounds__(kThreads) void k_accrual_runs(const Node *nodes_g, 
             const float w1 = fminf(w0 + s, g.theta);
             Union4 U;
             bool ov;
-            accrue_segment<false>(nodes_g ? nodes : nullptr, stack, verts, height, g, q, pending, w0, w1, U, ov,
+            accrue_segment<false>(TreeSrc{nodes_g ? nodes : nullptr}, stack, verts, height, g, q, pending, w0, w1, U, ov,
                                   none);
             if (pending) {
                 if (ov) {
@@ -455,7 +522,7 @@ __global__ __launch_bounds__(kThreads) void k_spill(const Node *nodes_g, const f
         Union4 U;
         bool ov;
         Work none{0, 0, 0, 0, 0, 0, 0};
-        accrue_segment<false>(nodes_g ? nodes : nullptr, stack, verts, height, g, q, true, w0, w1, U, ov, none);
+        accrue_segment<false>(TreeSrc{nodes_g ? nodes : nullptr}, stack, verts, height, g, q, true, w0, w1, U, ov, none);
         double mins = 0.0;
         int cnt = 0;
         if (!ov) measure(U, g, w0, w1, w1 >= g.theta, mins, cnt);
@@ -654,7 +721,7 @@ __global__ __launch_bounds__(kThreads) void k_batched(const Node *vnodes_g, int 
                 const float w1 = fminf(w0 + s, g.theta);
                 Union4 U;
                 bool ov;
-                accrue_segment<false>(nodes, stack, verts, height, g, q, pending, w0, w1, U, ov, none);
+                accrue_segment<false>(TreeSrc{nodes}, stack, verts, height, g, q, pending, w0, w1, U, ov, none);
                 if (pending) {
                     if (ov) {
                         if (s < g.theta * (1.0f / 4096.0f)) {
@@ -810,7 +877,7 @@ sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_va
 
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
                          int32_t *counts, float *minutes, float *longest, uint64_t *work, SpillQueue &q,
-                         hipStream_t st, std::string &err)
+                         Scratch &scr, hipStream_t st, std::string &err)
 {
     if (pts.n == 0) return SA_OK;
     const int64_t waves = (pts.n + 63) / 64;
@@ -836,13 +903,41 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
     // segment ranges, each about kChunkWork point-segments and each followed
     // by its spill rounds; outputs are accumulated, so the split is
     // invisible in the results.
-    const int64_t per = std::max<int64_t>(1, kChunkWork / std::max<int64_t>(pts.n, 1));
+    // ... and each launch covers at most kSegNodeBytes of per-segment node
+    // views (built just before it by k_seg_nodes in context scratch).
+    int64_t per = std::max<int64_t>(1, kChunkWork / std::max<int64_t>(pts.n, 1));
+    if (nodes) {
+        per = std::min<int64_t>(per, std::max<int64_t>(1, kSegNodeBytes / ((int64_t)s.n_nodes * sizeof(SegNode))));
+        const size_t need = (size_t)std::min<int64_t>(per, p.n_segs) * s.n_nodes * sizeof(SegNode);
+        if (scr.bytes < need) {
+            (void)hipStreamSynchronize(st);
+            (void)hipFree(scr.ptr);
+            scr.ptr = nullptr;
+            scr.bytes = 0;
+            if (hipMalloc(&scr.ptr, need) != hipSuccess) {
+                (void)hipGetLastError();
+                scr.ptr = nullptr;
+                err = "segment node view allocation failed";
+                return SA_ERR_OOM;
+            }
+            scr.bytes = need;
+        }
+    }
     for (int64_t j0 = 0; j0 < p.n_segs; j0 += per) {
         const int j1 = (int)std::min<int64_t>(j0 + per, p.n_segs);
+        SegNode *views = nullptr;
+        if (nodes) {
+            views = (SegNode *)scr.ptr;
+            const int64_t nt = (j1 - j0) * (int64_t)s.n_nodes;
+            hipLaunchKernelGGL(k_seg_nodes, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, nodes, s.n_nodes,
+                               p.segs, (int)j0, j1, views);
+            SA_CHECK_LAUNCH("segment node views");
+        }
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters);
         SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
         hipLaunchKernelGGL(work ? k_accrual<true> : k_accrual<false>, dim3((unsigned)grid), dim3(kThreads), 0, st,
-                           nodes, s.verts, s.height, p.segs, (int)j0, j1, P, scale, counts, minutes, S, work);
+                           nodes, views, s.n_nodes, s.voff, s.verts, s.height, p.segs, (int)j0, j1, P, scale, counts,
+                           minutes, S, work);
         SA_CHECK_LAUNCH("accrual kernel");
         sa_status rc = run_spill(s, p, P, scale, counts, minutes, q, st, err);
         if (rc != SA_OK) return rc;

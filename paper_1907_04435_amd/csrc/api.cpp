@@ -18,6 +18,7 @@ struct sa_ctx {
     sa::SpillQueue spill;
     sa::Scratch scratch;          // region sums
     sa::Scratch scratch_batched;  // per-variant hierarchy copies
+    sa::Scratch scratch_seg;      // per-segment node views of the accrual form
 };
 
 struct sa_scene {
@@ -95,6 +96,7 @@ void sa_destroy(sa_ctx *ctx)
     (void)hipFree(ctx->spill.counters);
     (void)hipFree(ctx->scratch.ptr);
     (void)hipFree(ctx->scratch_batched.ptr);
+    (void)hipFree(ctx->scratch_seg.ptr);
     delete ctx;
 }
 
@@ -138,6 +140,9 @@ sa_status sa_scene_upload(sa_ctx *ctx, int32_t n_b, const int32_t *vert_off, con
     if (n_b < 0 || (n_b > 0 && (!vert_off || !xy || !height)))
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_scene_upload: bad arguments");
     if (n_b > 0 && vert_off[0] != 0) return fail(ctx, SA_ERR_INVALID_ARG, "sa_scene_upload: vert_off[0] != 0");
+    // the accrual traversal addresses per-segment node views (64 bytes
+    // each) with 32-bit byte offsets
+    if (n_b > (1 << 25)) return fail(ctx, SA_ERR_CAPACITY, "sa_scene_upload: more than 2^25 prisms");
     for (int32_t b = 0; b < n_b; ++b) {
         const int32_t o = vert_off[b], m = vert_off[b + 1] - o;
         if (m < 3) return fail(ctx, SA_ERR_GEOMETRY, "prism " + std::to_string(b) + ": fewer than 3 vertices");
@@ -463,7 +468,7 @@ sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts
                                 opts->work, ctx->stream, err);
     else
         rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->longest, opts->work,
-                                ctx->spill, ctx->stream, err);
+                                ctx->spill, ctx->scratch_seg, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate: " + err);
     return SA_OK;
 }

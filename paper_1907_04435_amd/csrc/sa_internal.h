@@ -62,6 +62,17 @@ struct alignas(64) SegConst {
 };
 static_assert(sizeof(SegConst) == 128, "two lines");
 
+// A hierarchy node seen from one accrual segment: for each child, the box
+// terms of the fan test against that segment (z1; the box edges shifted by
+// the fan's per-metre reach: x1 - z1 umnx, x0 - z1 umxx, y1 - z1 umny,
+// y0 - z1 umxy; the two wedge projections), children in the segment's
+// visit order.  64 bytes, one scalar load.
+struct alignas(64) SegNode {
+    float c[2][7];
+    int32_t ref[2];  // interior: byte offset of the child's view; leaf: ~prism; or absent
+};
+static_assert(sizeof(SegNode) == 64, "one line");
+
 struct DeviceScene {
     int32_t n_b = 0;
     int32_t n_vert = 0;
@@ -120,7 +131,7 @@ sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const Points
                          uint64_t *work, hipStream_t st, std::string &err);
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
                          float scale, int32_t *counts, float *minutes, float *longest, uint64_t *work,
-                         SpillQueue &q, hipStream_t st, std::string &err);
+                         SpillQueue &q, Scratch &scr, hipStream_t st, std::string &err);
 sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
                       const float *dl, float *grad, SpillQueue &q, hipStream_t st, std::string &err);
 sa_status launch_region_sum(const float *v, int n_bins, int64_t n, const double *bin_w,

@@ -692,6 +692,53 @@ __device__ __forceinline__ void spill_push(const SpillArgs &S, bool want, int64_
 //     x1 max(nx,0) + x0 min(nx,0) + y1 max(ny,0) + y0 min(ny,0),
 // a wave-uniform value (the box is the wave's node) compared with the
 // lane's n.p.
+// The fan of a segment seen from the xy plane: over the segment the rays
+// from p sweep the wedge between the horizontal offsets ua (first knot) and
+// ub (last knot), reaching (z - pz) * u at height z.  Returned: the
+// per-metre reach box [umnx, umxx] x [umny, umxy] of the wedge and the two
+// inward edge normals na (of p -> ua) and nb (of p -> ub).  Uniform per
+// segment.
+struct FanGeom {
+    float umnx, umxx, umny, umxy;
+    float nax, nay, nbx, nby;
+};
+
+__device__ __forceinline__ FanGeom fan_geom(const SegConst &g)
+{
+    FanGeom f;
+    f.umnx = fminf(0.f, fminf(g.ua_x, g.ub_x));
+    f.umxx = fmaxf(0.f, fmaxf(g.ua_x, g.ub_x));
+    f.umny = fminf(0.f, fminf(g.ua_y, g.ub_y));
+    f.umxy = fmaxf(0.f, fmaxf(g.ua_y, g.ub_y));
+    f.nax = -g.ua_y;
+    f.nay = g.ua_x;  // inward normal of p -> A (toward B)
+    if (fmaf(f.nax, g.ub_x, f.nay * g.ub_y) < 0.f) {
+        f.nax = -f.nax;
+        f.nay = -f.nay;
+    }
+    f.nbx = -g.ub_y;
+    f.nby = g.ub_x;  // inward normal of p -> B (toward A)
+    if (fmaf(f.nbx, g.ua_x, f.nby * g.ua_y) < 0.f) {
+        f.nbx = -f.nbx;
+        f.nby = -f.nby;
+    }
+    return f;
+}
+
+// Largest value of n . x over the box [x0, x1] x [y0, y1] (the corner the
+// normal points to), for a wedge edge normal n.
+__device__ __forceinline__ float box_reach(float x0, float y0, float x1, float y1, float nx, float ny)
+{
+    return fmaf(y0, fminf(ny, 0.f), fmaf(y1, fmaxf(ny, 0.f), fmaf(x0, fminf(nx, 0.f), x1 * fmaxf(nx, 0.f))));
+}
+
+// Visit order of two child boxes in a segment: nearer along the
+// horizontal direction of the mid-segment sun first.
+__device__ __forceinline__ float seg_key(float x0, float y0, float x1, float y1, float mdx, float mdy)
+{
+    return fmaf(x0 + x1, mdx, (y0 + y1) * mdy);
+}
+
 struct FanTest {
     float umnx, umxx, umny, umxy;
     float axp, axm, ayp, aym, bxp, bxm, byp, bym;
@@ -702,30 +749,21 @@ struct FanTest {
         px = px_;
         py = py_;
         pz = pz_;
-        umnx = fminf(0.f, fminf(g.ua_x, g.ub_x));
-        umxx = fmaxf(0.f, fmaxf(g.ua_x, g.ub_x));
-        umny = fminf(0.f, fminf(g.ua_y, g.ub_y));
-        umxy = fmaxf(0.f, fmaxf(g.ua_y, g.ub_y));
-        float nax = -g.ua_y, nay = g.ua_x;   // inward normal of p -> A (toward B)
-        if (fmaf(nax, g.ub_x, nay * g.ub_y) < 0.f) {
-            nax = -nax;
-            nay = -nay;
-        }
-        float nbx = -g.ub_y, nby = g.ub_x;   // inward normal of p -> B (toward A)
-        if (fmaf(nbx, g.ua_x, nby * g.ua_y) < 0.f) {
-            nbx = -nbx;
-            nby = -nby;
-        }
-        axp = fmaxf(nax, 0.f);
-        axm = fminf(nax, 0.f);
-        ayp = fmaxf(nay, 0.f);
-        aym = fminf(nay, 0.f);
-        bxp = fmaxf(nbx, 0.f);
-        bxm = fminf(nbx, 0.f);
-        byp = fmaxf(nby, 0.f);
-        bym = fminf(nby, 0.f);
-        naP = fmaf(nax, px, nay * py);
-        nbP = fmaf(nbx, px, nby * py);
+        const FanGeom f = fan_geom(g);
+        umnx = f.umnx;
+        umxx = f.umxx;
+        umny = f.umny;
+        umxy = f.umxy;
+        axp = fmaxf(f.nax, 0.f);
+        axm = fminf(f.nax, 0.f);
+        ayp = fmaxf(f.nay, 0.f);
+        aym = fminf(f.nay, 0.f);
+        bxp = fmaxf(f.nbx, 0.f);
+        bxm = fminf(f.nbx, 0.f);
+        byp = fmaxf(f.nby, 0.f);
+        bym = fminf(f.nby, 0.f);
+        naP = fmaf(f.nax, px, f.nay * py);
+        nbP = fmaf(f.nbx, px, f.nby * py);
     }
 
     __device__ __forceinline__ uint64_t operator()(float x0, float y0, float x1, float y1, float z1) const
@@ -739,6 +777,184 @@ struct FanTest {
                ge_mask(ka, naP) & ge_mask(kb, nbP);
     }
 };
+
+// ---- the accrual fan test on per-segment node views ----
+//
+// FanTest spends most of its arithmetic on values that are the same for
+// every lane (the wedge projections of the box, the box shifted by the
+// per-metre reach).  CDNA has no scalar floating point, so those values
+// cost full vector instructions at every node visit.  Moving the lane's
+// terms to the other side of each inequality,
+//   x1 >= px + (z1 - pz) umnx   <=>   x1 - z1 umnx >= px - pz umnx,
+// leaves one side that depends only on (segment, box), computed once per
+// segment for the whole hierarchy (SegNode), and one that depends only on
+// (segment, point), computed once per lane and segment (SegFan): a child
+// test becomes seven compares.  Both sides are rounded outward, so the
+// test passes every box that meets the fan exactly (boxes only decide
+// what is tested, never a result).
+
+typedef __attribute__((address_space(4))) const SegNode cSegNode;
+
+__device__ __forceinline__ float round_up_rel(float v) { return v + fabsf(v) * 0x1p-22f; }
+__device__ __forceinline__ float round_dn_rel(float v) { return v - fabsf(v) * 0x1p-22f; }
+
+struct SegFan {
+    float pz, cxl, cxh, cyl, cyh, naP, nbP;
+
+    __device__ __forceinline__ SegFan(const SegConst &g, float px, float py, float pz_)
+    {
+        const FanGeom f = fan_geom(g);
+        pz = pz_;
+        cxl = round_dn_rel(fmaf(-pz, f.umnx, px));
+        cxh = round_up_rel(fmaf(-pz, f.umxx, px));
+        cyl = round_dn_rel(fmaf(-pz, f.umny, py));
+        cyh = round_up_rel(fmaf(-pz, f.umxy, py));
+        naP = fmaf(f.nax, px, f.nay * py);
+        nbP = fmaf(f.nbx, px, f.nby * py);
+    }
+
+    __device__ __forceinline__ uint64_t operator()(const float *c) const
+    {
+        return ge_mask(c[0], pz) & ge_mask(c[1], cxl) & le_mask(c[2], cxh) & ge_mask(c[3], cyl) &
+               le_mask(c[4], cyh) & ge_mask(c[5], naP) & ge_mask(c[6], nbP);
+    }
+
+    // Both children at once, for the lanes in cur.
+    __device__ __forceinline__ void both(const SegNode &nd, uint64_t cur, uint64_t &h0, uint64_t &h1) const
+    {
+        uint64_t sv;
+        asm volatile(
+            "s_mov_b64 %[sv], exec\n"
+            "s_mov_b64 exec, %[cur]\n"
+            "v_cmpx_ge_f32 vcc, %[a0], %[pz]\n"
+            "v_cmpx_ge_f32 vcc, %[a1], %[cxl]\n"
+            "v_cmpx_le_f32 vcc, %[a2], %[cxh]\n"
+            "v_cmpx_ge_f32 vcc, %[a3], %[cyl]\n"
+            "v_cmpx_le_f32 vcc, %[a4], %[cyh]\n"
+            "v_cmpx_ge_f32 vcc, %[a5], %[naP]\n"
+            "v_cmpx_ge_f32 vcc, %[a6], %[nbP]\n"
+            "s_mov_b64 %[h0], exec\n"
+            "s_mov_b64 exec, %[cur]\n"
+            "v_cmpx_ge_f32 vcc, %[b0], %[pz]\n"
+            "v_cmpx_ge_f32 vcc, %[b1], %[cxl]\n"
+            "v_cmpx_le_f32 vcc, %[b2], %[cxh]\n"
+            "v_cmpx_ge_f32 vcc, %[b3], %[cyl]\n"
+            "v_cmpx_le_f32 vcc, %[b4], %[cyh]\n"
+            "v_cmpx_ge_f32 vcc, %[b5], %[naP]\n"
+            "v_cmpx_ge_f32 vcc, %[b6], %[nbP]\n"
+            "s_mov_b64 %[h1], exec\n"
+            "s_mov_b64 exec, %[sv]\n"
+            : [h0] "=&s"(h0), [h1] "=&s"(h1), [sv] "=&s"(sv)
+            : [cur] "s"(cur), [pz] "v"(pz), [cxl] "v"(cxl), [cxh] "v"(cxh), [cyl] "v"(cyl), [cyh] "v"(cyh),
+              [naP] "v"(naP), [nbP] "v"(nbP), [a0] "s"(nd.c[0][0]), [a1] "s"(nd.c[0][1]), [a2] "s"(nd.c[0][2]),
+              [a3] "s"(nd.c[0][3]), [a4] "s"(nd.c[0][4]), [a5] "s"(nd.c[0][5]), [a6] "s"(nd.c[0][6]),
+              [b0] "s"(nd.c[1][0]), [b1] "s"(nd.c[1][1]), [b2] "s"(nd.c[1][2]), [b3] "s"(nd.c[1][3]),
+              [b4] "s"(nd.c[1][4]), [b5] "s"(nd.c[1][5]), [b6] "s"(nd.c[1][6])
+            : "vcc");
+    }
+};
+
+// The box-only side of SegFan's inequalities for one child box.  The
+// shifted edges are formed in double and rounded outward; the wedge
+// projections use FanTest's expression.  An absent child gets a box no
+// lane passes.
+__device__ __forceinline__ void seg_child(const FanGeom &f, float x0, float y0, float x1, float y1, float z1,
+                                          bool present, float *c)
+{
+    if (!present) {
+        c[0] = -INFINITY;  // z1 >= pz fails for every finite pz
+        c[1] = c[3] = c[5] = c[6] = -INFINITY;
+        c[2] = c[4] = INFINITY;
+        return;
+    }
+    c[0] = z1;
+    c[1] = round_up_rel((float)((double)x1 - (double)z1 * f.umnx));
+    c[2] = round_dn_rel((float)((double)x0 - (double)z1 * f.umxx));
+    c[3] = round_up_rel((float)((double)y1 - (double)z1 * f.umny));
+    c[4] = round_dn_rel((float)((double)y0 - (double)z1 * f.umxy));
+    c[5] = box_reach(x0, y0, x1, y1, f.nax, f.nay);
+    c[6] = box_reach(x0, y0, x1, y1, f.nbx, f.nby);
+}
+
+// Packet traversal over the per-segment views (see packet_traverse): the
+// children of a view are already in the segment's visit order, interior
+// references are byte offsets of views (one scalar load with a register
+// offset, no address arithmetic), and a leaf reference's vertex range
+// comes from the hierarchy-order offsets `voff`.
+// Liveness is a wave mask throughout: `leaf(prim, voff, m, want)` returns
+// the mask of lanes it retires, so no per-lane flag is carried around the
+// loop (each such flag costs scalar merges with the exec mask at every
+// iteration).  All leaf handling sits behind one branch, taken only at
+// nodes with a leaf child.
+template <bool kCount, class LeafFn>
+__device__ __forceinline__ void packet_traverse_seg(cSegNode *nodes, cint *voff, StackEntry *stack, uint64_t alive,
+                                                    const SegFan &ft, LeafFn leaf, Work &w)
+{
+    typedef __attribute__((address_space(4))) const char cchar;
+    uint64_t cur = alive;
+    int sp = 0, node = 0;  // byte offset of the current view
+    while (cur) {
+        const SegNode nd = ld((cSegNode *)((cchar *)nodes + (uint32_t)node));
+        if constexpr (kCount) {
+            w.box += lane_in(cur) ? 2u : 0u;
+            w.nodes += first_active_lane() ? 1u : 0u;
+        }
+        uint64_t h0, h1;
+        ft.both(nd, cur, h0, h1);
+        if ((nd.ref[0] | nd.ref[1]) < 0) {
+            uint64_t out = 0;
+            if (nd.ref[0] < 0) {
+                if (h0) {
+                    const int prim = ~nd.ref[0];
+                    const int v0 = ld(voff + prim), v1 = ld(voff + prim + 1);
+                    out |= leaf(prim, v0, v1 - v0, h0);
+                }
+                h0 = 0;
+            }
+            if (nd.ref[1] < 0) {
+                if (h1) {
+                    const int prim = ~nd.ref[1];
+                    const int v0 = ld(voff + prim), v1 = ld(voff + prim + 1);
+                    out |= leaf(prim, v0, v1 - v0, h1);
+                }
+                h1 = 0;
+            }
+            alive &= ~out;
+            h0 &= alive;
+            h1 &= alive;
+        }
+        // Both children wanted: defer the second.  Then go to the first
+        // child wanted.  Written as scalar compare-and-selects: the compiler
+        // turns these conditions into 64-bit lane-mask booleans otherwise
+        // (three or four extra scalar instructions per node).
+        uint64_t defer;
+        asm("s_cmp_lg_u64 %[h0], 0\n"
+            "s_cselect_b64 %[d], %[h1], 0"
+            : [d] "=&s"(defer)
+            : [h0] "s"(h0), [h1] "s"(h1)
+            : "scc");
+        if (defer) {
+            stack[sp] = StackEntry{nd.ref[1], (uint32_t)defer, (uint32_t)(defer >> 32), 0u};
+            ++sp;
+        }
+        asm("s_cmp_lg_u64 %[h0], 0\n"
+            "s_cselect_b32 %[n], %[r0], %[r1]\n"
+            "s_cselect_b64 %[c], %[h0], %[h1]"
+            : [n] "=&s"(node), [c] "=&s"(cur)
+            : [h0] "s"(h0), [h1] "s"(h1), [r0] "s"(nd.ref[0]), [r1] "s"(nd.ref[1])
+            : "scc");
+        if (!cur) {
+            const uint64_t keep = alive;
+            while (sp > 0) {
+                --sp;
+                const StackEntry e = stack[sp];
+                node = uniform(e.node);
+                cur = uniform64(e.lo, e.hi) & keep;
+                if (cur) break;
+            }
+        }
+    }
+}
 
 }  // namespace dev
 }  // namespace sa
