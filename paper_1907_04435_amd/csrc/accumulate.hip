@@ -406,7 +406,8 @@ __device__ __forceinline__ void runs_update(const Union4 &U, float w0, float w1,
 // window by window from its start (halving the window on overflow,
 // doubling it after a success) while the other lanes wait.  A window would
 // have to shrink below theta / 4096 to raise the overflow flag.
-__global__ __launch_bounds__(kThreads) void k_accrual_runs(const Node *nodes_g, const float4 *verts_g,
+__global__ __launch_bounds__(kThreads) void k_accrual_runs(const Node *nodes_g, const SegNode *snodes_g, int n_nodes,
+                                                           const int32_t *voff_g, const float4 *verts_g,
                                                            const float *height_g, const SegConst *segs_g, int j0,
                                                            int j1, PointArgs P, float scale, int32_t *counts,
                                                            float *minutes, float *longest, uint32_t *overflow)
@@ -463,8 +464,9 @@ __global__ __launch_bounds__(kThreads) void k_accrual_runs(const Node *nodes_g, 
             const float w1 = fminf(w0 + s, g.theta);
             Union4 U;
             bool ov;
-            accrue_segment<false>(TreeSrc{nodes_g ? nodes : nullptr}, stack, verts, height, g, q, pending, w0, w1, U, ov,
-                                  none);
+            const SegSrc src{snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr,
+                             (cint *)voff_g};
+            accrue_segment<false>(src, stack, verts, height, g, q, pending, w0, w1, U, ov, none);
             if (pending) {
                 if (ov) {
                     if (s < g.theta * (1.0f / 4096.0f)) {
@@ -493,12 +495,12 @@ __global__ __launch_bounds__(kThreads) void k_accrual_runs(const Node *nodes_g, 
 // lanes' measures are summed across the wave and added with one atomic per
 // output; sub-windows that still need more than four pieces go to the
 // next queue.
-__global__ __launch_bounds__(kThreads) void k_spill(const Node *nodes_g, const float4 *verts_g,
-                                                    const float *height_g, const SegConst *segs_g, PointArgs P,
-                                                    float scale, int32_t *counts, float *minutes, const int4 *in,
-                                                    const uint32_t *in_count, int32_t cap, SpillArgs S)
+__global__ __launch_bounds__(kThreads) void k_spill(const SegNode *snodes_g, int n_nodes, int j0, const int32_t *voff_g,
+                                                    const float4 *verts_g, const float *height_g,
+                                                    const SegConst *segs_g, PointArgs P, float scale, int32_t *counts,
+                                                    float *minutes, const int4 *in, const uint32_t *in_count,
+                                                    int32_t cap, SpillArgs S)
 {
-    cNode *nodes = (cNode *)nodes_g;
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
     cSeg *segs = (cSeg *)segs_g;
@@ -522,7 +524,9 @@ __global__ __launch_bounds__(kThreads) void k_spill(const Node *nodes_g, const f
         Union4 U;
         bool ov;
         Work none{0, 0, 0, 0, 0, 0, 0};
-        accrue_segment<false>(TreeSrc{nodes_g ? nodes : nullptr}, stack, verts, height, g, q, true, w0, w1, U, ov, none);
+        const SegSrc src{snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr,
+                         (cint *)voff_g};
+        accrue_segment<false>(src, stack, verts, height, g, q, true, w0, w1, U, ov, none);
         double mins = 0.0;
         int cnt = 0;
         if (!ov) measure(U, g, w0, w1, w1 >= g.theta, mins, cnt);
@@ -546,12 +550,12 @@ __global__ __launch_bounds__(kThreads) void k_spill(const Node *nodes_g, const f
 // still count).  The lanes' weighted minutes for one leaf are summed across
 // the wave and added with one FP64 atomic; a back-facing wall counts for
 // the point's own building.
-__global__ __launch_bounds__(kThreads) void k_contrib(const Node *nodes_g, const float4 *verts_g,
-                                                      const float *height_g, const SegConst *segs_g, int j0,
-                                                      int j1, PointArgs P, const float *weight,
-                                                      const int32_t *order, int n_b, double *contrib)
+__global__ __launch_bounds__(kThreads) void k_contrib(const SegNode *snodes_g, int n_nodes, const int32_t *voff_g,
+                                                      const float4 *verts_g, const float *height_g,
+                                                      const SegConst *segs_g, int j0, int j1, PointArgs P,
+                                                      const float *weight, const int32_t *order, int n_b,
+                                                      double *contrib)
 {
-    cNode *nodes = (cNode *)nodes_g;
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
     cSeg *segs = (cSeg *)segs_g;
@@ -573,12 +577,11 @@ __global__ __launch_bounds__(kThreads) void k_contrib(const Node *nodes_g, const
             if (backface_interval(q.nx, q.ny, g, 0.f, g.theta, 1.f, 0.f, g.cth, g.sth, a, b))
                 atomicAdd(&row[order[q.own]], (double)((b - a) * g.rate * wt));
         }
-        if (nodes_g == nullptr) continue;
-        bool live = active;
-        const FanTest bt(g, q.px, q.py, q.pz);
-        auto leaf = [&](int prim, int voff, int m, uint64_t want) {
+        if (snodes_g == nullptr) continue;
+        const SegFan ft(g, q.px, q.py, q.pz);
+        auto leaf = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
             const uint64_t gm = want & ballot(prim != q.own);
-            if (!gm) return;
+            if (!gm) return 0;
             const bool go = lane_in(gm);
             float a = 0.f, b = 0.f, da, db;
             const int r = go ? prism_interval<false>(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, 0.f,
@@ -587,9 +590,10 @@ __global__ __launch_bounds__(kThreads) void k_contrib(const Node *nodes_g, const
             double v = r ? (double)((b - a) * g.rate * wt) : 0.0;
             for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
             if (first_active_lane() && v != 0.0) atomicAdd(&row[order[prim]], v);
+            return 0;  // no lane retires: every building counts
         };
-        auto key = [](float, float, float, float, float) { return 0.f; };
-        packet_traverse<false>(nodes, stack, live, bt, leaf, key, none);
+        packet_traverse_seg<false>((cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes), (cint *)voff_g, stack,
+                                   ballot(active), ft, leaf, none);
     }
 }
 
@@ -795,17 +799,16 @@ sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const Points
     return SA_OK;
 }
 
-sa_status run_spill(const DeviceScene &s, const DevicePath &p, const PointArgs &P, float scale, int32_t *counts,
-                    float *minutes, SpillQueue &q, hipStream_t st, std::string &err)
+sa_status run_spill(const DeviceScene &s, const DevicePath &p, const SegNode *views, int j0, const PointArgs &P,
+                    float scale, int32_t *counts, float *minutes, SpillQueue &q, hipStream_t st, std::string &err)
 {
-    const Node *nodes = s.n_b > 0 ? s.nodes : nullptr;
     int cur = 0;
     for (int r = 0; r < kSpillRounds; ++r) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters + (cur ^ 1));
         SpillArgs S{q.entries[cur ^ 1], q.counters + (cur ^ 1), q.counters + 2, q.capacity};
-        hipLaunchKernelGGL(k_spill, dim3(kSpillBlocks), dim3(kThreads), 0, st, nodes, s.verts, s.height, p.segs, P,
-                           scale, counts, minutes, (const int4 *)q.entries[cur], (const uint32_t *)(q.counters + cur),
-                           q.capacity, S);
+        hipLaunchKernelGGL(k_spill, dim3(kSpillBlocks), dim3(kThreads), 0, st, views, s.n_nodes, j0, s.voff, s.verts,
+                           s.height, p.segs, P, scale, counts, minutes, (const int4 *)q.entries[cur],
+                           (const uint32_t *)(q.counters + cur), q.capacity, S);
         cur ^= 1;
     }
     // anything still queued after the last round is unfinished work
@@ -875,6 +878,39 @@ sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_va
     return SA_OK;
 }
 
+int64_t seg_views_cap(const DeviceScene &s)
+{
+    return std::max<int64_t>(1, kSegNodeBytes / ((int64_t)std::max(s.n_nodes, 1) * (int64_t)sizeof(SegNode)));
+}
+
+sa_status build_seg_views(const DeviceScene &s, const DevicePath &p, int j0, int j1, Scratch &scr, hipStream_t st,
+                          SegNode *&views, std::string &err)
+{
+    views = nullptr;
+    if (s.n_b == 0 || j1 <= j0) return SA_OK;
+    const int64_t nt = (int64_t)(j1 - j0) * s.n_nodes;
+    const size_t need = (size_t)nt * sizeof(SegNode);
+    if (scr.bytes < need) {
+        // the previous contents may still be read by queued kernels
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(scr.ptr);
+        scr.ptr = nullptr;
+        scr.bytes = 0;
+        if (hipMalloc(&scr.ptr, need) != hipSuccess) {
+            (void)hipGetLastError();
+            scr.ptr = nullptr;
+            err = "segment node view allocation failed";
+            return SA_ERR_OOM;
+        }
+        scr.bytes = need;
+    }
+    views = (SegNode *)scr.ptr;
+    hipLaunchKernelGGL(k_seg_nodes, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, s.nodes, s.n_nodes, p.segs,
+                       j0, j1, views);
+    SA_CHECK_LAUNCH("segment node views");
+    return SA_OK;
+}
+
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
                          int32_t *counts, float *minutes, float *longest, uint64_t *work, SpillQueue &q,
                          Scratch &scr, hipStream_t st, std::string &err)
@@ -884,80 +920,64 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
     const int64_t grid = (waves + kWaves - 1) / kWaves;
     const Node *nodes = s.n_b > 0 ? s.nodes : nullptr;
     const PointArgs P = point_args(pts, s);
+    // Long spans run as several launches over consecutive segment ranges,
+    // each about kChunkWork point-segments and covering at most
+    // kSegNodeBytes of per-segment node views (built just before it);
+    // outputs are accumulated, so the split is invisible in the results.
+    const int64_t per = std::min(std::max<int64_t>(1, kChunkWork / std::max<int64_t>(pts.n, 1)), seg_views_cap(s));
     if (longest) {
-        // whole days per launch, so a run never spans two launches
+        // whole days per launch, so a run never spans two launches (one
+        // day per launch at least, whatever its views take)
         const int D = (int)p.day_seg_off.size() - 1;
-        const int64_t per = std::max<int64_t>(1, kChunkWork / std::max<int64_t>(pts.n, 1));
         for (int d0 = 0; d0 < D;) {
             int d1 = d0 + 1;
             while (d1 < D && p.day_seg_off[d1 + 1] - p.day_seg_off[d0] <= per) ++d1;
-            hipLaunchKernelGGL(k_accrual_runs, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, s.verts, s.height,
-                               p.segs, p.day_seg_off[d0], p.day_seg_off[d1], P, scale, counts, minutes, longest,
+            const int j0 = p.day_seg_off[d0], j1 = p.day_seg_off[d1];
+            SegNode *views;
+            sa_status rc = build_seg_views(s, p, j0, j1, scr, st, views, err);
+            if (rc != SA_OK) return rc;
+            hipLaunchKernelGGL(k_accrual_runs, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, views, s.n_nodes,
+                               s.voff, s.verts, s.height, p.segs, j0, j1, P, scale, counts, minutes, longest,
                                q.counters + 2);
             SA_CHECK_LAUNCH("accrual kernel (continuous shadow)");
             d0 = d1;
         }
         return SA_OK;
     }
-    // Long spans (many days) run as several launches over consecutive
-    // segment ranges, each about kChunkWork point-segments and each followed
-    // by its spill rounds; outputs are accumulated, so the split is
-    // invisible in the results.
-    // ... and each launch covers at most kSegNodeBytes of per-segment node
-    // views (built just before it by k_seg_nodes in context scratch).
-    int64_t per = std::max<int64_t>(1, kChunkWork / std::max<int64_t>(pts.n, 1));
-    if (nodes) {
-        per = std::min<int64_t>(per, std::max<int64_t>(1, kSegNodeBytes / ((int64_t)s.n_nodes * sizeof(SegNode))));
-        const size_t need = (size_t)std::min<int64_t>(per, p.n_segs) * s.n_nodes * sizeof(SegNode);
-        if (scr.bytes < need) {
-            (void)hipStreamSynchronize(st);
-            (void)hipFree(scr.ptr);
-            scr.ptr = nullptr;
-            scr.bytes = 0;
-            if (hipMalloc(&scr.ptr, need) != hipSuccess) {
-                (void)hipGetLastError();
-                scr.ptr = nullptr;
-                err = "segment node view allocation failed";
-                return SA_ERR_OOM;
-            }
-            scr.bytes = need;
-        }
-    }
     for (int64_t j0 = 0; j0 < p.n_segs; j0 += per) {
         const int j1 = (int)std::min<int64_t>(j0 + per, p.n_segs);
-        SegNode *views = nullptr;
-        if (nodes) {
-            views = (SegNode *)scr.ptr;
-            const int64_t nt = (j1 - j0) * (int64_t)s.n_nodes;
-            hipLaunchKernelGGL(k_seg_nodes, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, nodes, s.n_nodes,
-                               p.segs, (int)j0, j1, views);
-            SA_CHECK_LAUNCH("segment node views");
-        }
+        SegNode *views;
+        sa_status rc = build_seg_views(s, p, (int)j0, j1, scr, st, views, err);
+        if (rc != SA_OK) return rc;
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters);
         SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
         hipLaunchKernelGGL(work ? k_accrual<true> : k_accrual<false>, dim3((unsigned)grid), dim3(kThreads), 0, st,
                            nodes, views, s.n_nodes, s.voff, s.verts, s.height, p.segs, (int)j0, j1, P, scale, counts,
                            minutes, S, work);
         SA_CHECK_LAUNCH("accrual kernel");
-        sa_status rc = run_spill(s, p, P, scale, counts, minutes, q, st, err);
+        rc = run_spill(s, p, views, (int)j0, P, scale, counts, minutes, q, st, err);
         if (rc != SA_OK) return rc;
     }
     return SA_OK;
 }
 
 sa_status launch_contribution(const DeviceScene &s, const DevicePath &p, const PointsView &pts, const float *weight,
-                              double *contrib, hipStream_t st, std::string &err)
+                              double *contrib, Scratch &scr, hipStream_t st, std::string &err)
 {
     if (pts.n == 0 || s.n_b == 0) return SA_OK;
     const int64_t waves = (pts.n + 63) / 64;
     const int64_t grid = (waves + kWaves - 1) / kWaves;
     const PointArgs P = point_args(pts, s);
     // long spans: several launches over consecutive segment ranges
-    const int64_t per = std::max<int64_t>(1, kChunkWork / 2 / std::max<int64_t>(pts.n, 1));
+    const int64_t per =
+        std::min(std::max<int64_t>(1, kChunkWork / 2 / std::max<int64_t>(pts.n, 1)), seg_views_cap(s));
     for (int64_t j0 = 0; j0 < p.n_segs; j0 += per) {
         const int j1 = (int)std::min<int64_t>(j0 + per, p.n_segs);
-        hipLaunchKernelGGL(k_contrib, dim3((unsigned)grid), dim3(kThreads), 0, st, s.nodes, s.verts, s.height, p.segs,
-                           (int)j0, j1, P, weight, (const int32_t *)s.order, s.n_b, contrib);
+        SegNode *views;
+        sa_status rc = build_seg_views(s, p, (int)j0, j1, scr, st, views, err);
+        if (rc != SA_OK) return rc;
+        hipLaunchKernelGGL(k_contrib, dim3((unsigned)grid), dim3(kThreads), 0, st, views, s.n_nodes, s.voff, s.verts,
+                           s.height, p.segs, (int)j0, j1, P, weight, (const int32_t *)s.order, s.n_b, contrib);
         SA_CHECK_LAUNCH("contribution kernel");
     }
     return SA_OK;

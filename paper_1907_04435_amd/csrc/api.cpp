@@ -508,7 +508,7 @@ sa_status sa_grad_heights(sa_ctx *ctx, const sa_scene *scene, const sa_points *p
     if (rc != SA_OK) return rc;
     if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
     std::string err;
-    rc = sa::launch_grad(scene->d, path->d, view(pts), dl_dmin, grad, ctx->spill, ctx->stream, err);
+    rc = sa::launch_grad(scene->d, path->d, view(pts), dl_dmin, grad, ctx->spill, ctx->scratch_seg, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_grad_heights: " + err);
     return SA_OK;
 }
@@ -561,7 +561,8 @@ sa_status sa_building_contribution(sa_ctx *ctx, const sa_scene *scene, const sa_
     if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
     std::string err;
     rc = sa::fill_u32(contrib, 2 * (int64_t)path->d.n_bins * scene->d.n_b, 0u, ctx->stream, err);
-    if (rc == SA_OK) rc = sa::launch_contribution(scene->d, path->d, view(pts), weight, contrib, ctx->stream, err);
+    if (rc == SA_OK)
+        rc = sa::launch_contribution(scene->d, path->d, view(pts), weight, contrib, ctx->scratch_seg, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_building_contribution: " + err);
     return SA_OK;
 }

@@ -13,6 +13,8 @@
 // atomics into the caller's gradient (original building ids).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "sa_internal.h"
 #include "traverse.h"
 
@@ -33,9 +35,9 @@ struct GradArgs {
     const int32_t *order;  // hierarchy position -> original id
 };
 
-__device__ __forceinline__ void grad_segment(cNode *nodes, StackEntry *stack, cfloat4 *verts, cfloat *height,
-                                             const SegConst &g, const LanePoint &q, bool active, float w0, float w1,
-                                             UnionG &U, bool &ov)
+__device__ __forceinline__ void grad_segment(cSegNode *snodes, cint *voff, StackEntry *stack, cfloat4 *verts,
+                                             cfloat *height, const SegConst &g, const LanePoint &q, bool active,
+                                             float w0, float w1, UnionG &U, bool &ov)
 {
     union_clear(U);
     ov = false;
@@ -50,29 +52,30 @@ __device__ __forceinline__ void grad_segment(cNode *nodes, StackEntry *stack, cf
             live = !(a <= w0 && b >= w1);
         }
     }
-    if (nodes == nullptr) return;
-    const FanTest bt(g, q.px, q.py, q.pz);
-    auto leaf = [&](int prim, int voff, int m, uint64_t want) {
+    if (snodes == nullptr) return;
+    uint64_t ovm = 0;
+    auto leaf = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
         const uint64_t gm = want & ballot(prim != q.own);
-        if (!gm) return;
+        if (!gm) return 0;
         const bool go = lane_in(gm);
         float a = 0.f, b = 0.f, da = 0.f, db = 0.f;
         const int r = go ? prism_interval<true>(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, w0, w1,
                                                 W0u, W0v, W1u, W1v, a, b, da, db)
                          : 0;
+        bool over = false, full = false;
         if (r) {
-            if (!union_insert(U, a, b, prim, prim, da, db)) {
-                ov = true;
-                live = false;
-            } else if (U.n == 1 && U.lo[0] <= w0 && U.hi[0] >= w1) {
-                live = false;  // the whole window is shadowed: no boundary inside it
-            }
+            over = !union_insert(U, a, b, prim, prim, da, db);
+            // the whole window is shadowed: no boundary inside it
+            full = !over && U.n == 1 && U.lo[0] <= w0 && U.hi[0] >= w1;
         }
+        const uint64_t om = ballot(over);
+        ovm |= om;
+        return om | ballot(full);
     };
-    const float mdx = g.mdx, mdy = g.mdy;
-    auto key = [&](float x0, float y0, float x1, float y1, float) { return fmaf(x0 + x1, mdx, (y0 + y1) * mdy); };
+    const SegFan ft(g, q.px, q.py, q.pz);
     Work none{0, 0, 0, 0, 0, 0, 0};
-    packet_traverse<false>(nodes, stack, live, bt, leaf, key, none);
+    packet_traverse_seg<false>(snodes, voff, stack, ballot(live), ft, leaf, none);
+    ov = lane_in(ovm);
 }
 
 __device__ __forceinline__ void scatter_grad(const UnionG &U, float wscale, const GradArgs &G)
@@ -106,8 +109,9 @@ __device__ __forceinline__ bool roof_covered_g(cNode *nodes, StackEntry *stack, 
     return cov;
 }
 
-__global__ __launch_bounds__(kThreads) void k_grad(const Node *nodes_g, const float4 *verts_g, const float *height_g,
-                                                   const SegConst *segs_g, int J, PointArgs P, GradArgs G,
+__global__ __launch_bounds__(kThreads) void k_grad(const Node *nodes_g, const SegNode *snodes_g, int n_nodes,
+                                                   const int32_t *voff_g, const float4 *verts_g, const float *height_g,
+                                                   const SegConst *segs_g, int j0, int j1, PointArgs P, GradArgs G,
                                                    SpillArgs S)
 {
     cNode *nodes = nodes_g ? (cNode *)nodes_g : nullptr;
@@ -124,7 +128,7 @@ __global__ __launch_bounds__(kThreads) void k_grad(const Node *nodes_g, const fl
     const bool covered = roof_covered_g(nodes, stack, verts, height, q, valid);
     int bin = -1;
     float w = 0.f;
-    for (int j = 0; j < J; ++j) {
+    for (int j = j0; j < j1; ++j) {
         const SegConst g = ld(segs + j);
         if (g.bin != bin) {
             bin = g.bin;
@@ -132,7 +136,9 @@ __global__ __launch_bounds__(kThreads) void k_grad(const Node *nodes_g, const fl
         }
         UnionG U;
         bool ov;
-        grad_segment(nodes, stack, verts, height, g, q, valid && !covered && w != 0.f, 0.f, g.theta, U, ov);
+        cSegNode *sn = snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr;
+        grad_segment(sn, (cint *)voff_g, stack, verts, height, g, q, valid && !covered && w != 0.f, 0.f, g.theta, U,
+                     ov);
         if (valid && !covered && !ov && w != 0.f) scatter_grad(U, w * g.rate, G);
         spill_push(S, valid && ov, i, j, 0.f, g.theta);
     }
@@ -142,12 +148,12 @@ __global__ __launch_bounds__(kThreads) void k_grad(const Node *nodes_g, const fl
 // queued (point, segment, window), each lane one 64th of the window.  Ends
 // clamped to a sub-window do not move with a height, so splitting adds no
 // gradient terms.
-__global__ __launch_bounds__(kThreads) void k_grad_spill(const Node *nodes_g, const float4 *verts_g,
+__global__ __launch_bounds__(kThreads) void k_grad_spill(const SegNode *snodes_g, int n_nodes, int j0,
+                                                         const int32_t *voff_g, const float4 *verts_g,
                                                          const float *height_g, const SegConst *segs_g, PointArgs P,
                                                          GradArgs G, const int4 *in, const uint32_t *in_count,
                                                          int32_t cap, SpillArgs S)
 {
-    cNode *nodes = nodes_g ? (cNode *)nodes_g : nullptr;
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
     cSeg *segs = (cSeg *)segs_g;
@@ -169,7 +175,8 @@ __global__ __launch_bounds__(kThreads) void k_grad_spill(const Node *nodes_g, co
         const float w = G.dl ? G.dl[(int64_t)g.bin * P.n + i] : 1.f;
         UnionG U;
         bool ov;
-        grad_segment(nodes, stack, verts, height, g, q, true, w0, w1, U, ov);
+        cSegNode *sn = snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr;
+        grad_segment(sn, (cint *)voff_g, stack, verts, height, g, q, true, w0, w1, U, ov);
         if (!ov) scatter_grad(U, w * g.rate, G);
         spill_push(S, ov, i, j, w0, w1);
     }
@@ -185,34 +192,43 @@ __global__ void k_spill_left(const uint32_t *count, uint32_t *overflow)
 }  // namespace
 
 sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts, const float *dl, float *grad,
-                      SpillQueue &q, hipStream_t st, std::string &err)
+                      SpillQueue &q, Scratch &scr, hipStream_t st, std::string &err)
 {
     sa_status rc = fill_u32(grad, s.n_b, 0u, st, err);
     if (rc != SA_OK) return rc;
-    hipError_t e;
     if (pts.n == 0 || s.n_b == 0) return SA_OK;
     const int64_t waves = (pts.n + 63) / 64;
     const int64_t grid = (waves + kWaves - 1) / kWaves;
     const PointArgs P{pts.n, pts.x, pts.y, pts.z, pts.nx, pts.ny, pts.owner, s.rank, s.n_b};
     const GradArgs G{dl, grad, s.order};
-    hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, st, q.counters);
-    SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
-    hipLaunchKernelGGL(k_grad, dim3((unsigned)grid), dim3(kThreads), 0, st, s.nodes, s.verts, s.height, p.segs,
-                       p.n_segs, P, G, S);
-    int cur = 0;
-    for (int r = 0; r < kSpillRounds; ++r) {
-        hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, st, q.counters + (cur ^ 1));
-        SpillArgs S2{q.entries[cur ^ 1], q.counters + (cur ^ 1), q.counters + 2, q.capacity};
-        hipLaunchKernelGGL(k_grad_spill, dim3(kSpillBlocks), dim3(kThreads), 0, st, s.nodes, s.verts, s.height,
-                           p.segs, P, G, (const int4 *)q.entries[cur], (const uint32_t *)(q.counters + cur),
-                           q.capacity, S2);
-        cur ^= 1;
-    }
-    hipLaunchKernelGGL(k_spill_left, dim3(1), dim3(1), 0, st, (const uint32_t *)(q.counters + cur), q.counters + 2);
-    e = hipGetLastError();
-    if (e != hipSuccess) {
-        err = std::string("gradient kernels: ") + hipGetErrorString(e);
-        return SA_ERR_DEVICE;
+    // segment ranges whose per-segment node views fit the budget, each
+    // followed by its spill rounds
+    const int64_t per = seg_views_cap(s);
+    for (int64_t j0 = 0; j0 < p.n_segs; j0 += per) {
+        const int j1 = (int)std::min<int64_t>(j0 + per, p.n_segs);
+        SegNode *views;
+        rc = build_seg_views(s, p, (int)j0, j1, scr, st, views, err);
+        if (rc != SA_OK) return rc;
+        hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, st, q.counters);
+        SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
+        hipLaunchKernelGGL(k_grad, dim3((unsigned)grid), dim3(kThreads), 0, st, s.nodes, views, s.n_nodes, s.voff,
+                           s.verts, s.height, p.segs, (int)j0, j1, P, G, S);
+        int cur = 0;
+        for (int r = 0; r < kSpillRounds; ++r) {
+            hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, st, q.counters + (cur ^ 1));
+            SpillArgs S2{q.entries[cur ^ 1], q.counters + (cur ^ 1), q.counters + 2, q.capacity};
+            hipLaunchKernelGGL(k_grad_spill, dim3(kSpillBlocks), dim3(kThreads), 0, st, views, s.n_nodes, (int)j0,
+                               s.voff, s.verts, s.height, p.segs, P, G, (const int4 *)q.entries[cur],
+                               (const uint32_t *)(q.counters + cur), q.capacity, S2);
+            cur ^= 1;
+        }
+        hipLaunchKernelGGL(k_spill_left, dim3(1), dim3(1), 0, st, (const uint32_t *)(q.counters + cur),
+                           q.counters + 2);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) {
+            err = std::string("gradient kernels: ") + hipGetErrorString(e);
+            return SA_ERR_DEVICE;
+        }
     }
     return SA_OK;
 }

@@ -133,12 +133,21 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
                          float scale, int32_t *counts, float *minutes, float *longest, uint64_t *work,
                          SpillQueue &q, Scratch &scr, hipStream_t st, std::string &err);
 sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
-                      const float *dl, float *grad, SpillQueue &q, hipStream_t st, std::string &err);
+                      const float *dl, float *grad, SpillQueue &q, Scratch &scr, hipStream_t st,
+                      std::string &err);
 sa_status launch_region_sum(const float *v, int n_bins, int64_t n, const double *bin_w,
                             const int64_t *off, int32_t n_reg, const float *area, double *out,
                             Scratch &scr, hipStream_t st, std::string &err);
 sa_status launch_contribution(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
-                              const float *weight, double *contrib, hipStream_t st, std::string &err);
+                              const float *weight, double *contrib, Scratch &scr, hipStream_t st,
+                              std::string &err);
+// Per-segment node views (SegNode) of segments [j0, j1) into scr (grown as
+// needed, with the stream synchronised first); views = nullptr for an
+// empty scene.  seg_views_cap: segments whose views fit the per-launch
+// budget.
+sa_status build_seg_views(const DeviceScene &s, const DevicePath &p, int j0, int j1, Scratch &scr, hipStream_t st,
+                          SegNode *&views, std::string &err);
+int64_t seg_views_cap(const DeviceScene &s);
 sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_var, int32_t k,
                          const int32_t *ids, const float *h, const PointsView &pts,
                          const int64_t *var_off, float scale, int32_t *counts, float *minutes,
