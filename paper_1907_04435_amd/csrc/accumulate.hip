@@ -84,8 +84,7 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
         }
         if (s.tag & kDayStart) run = 0.f;
         const bool back = q.own >= 0 && fmaf(q.nx, s.dx, q.ny * s.dy) <= 0.f;
-        bool live = valid && !back;
-        bool hit = false;
+        uint64_t hitm = 0;
         if (nodes_g != nullptr) {
             const float ox = -q.px * s.ix, oy = -q.py * s.iy, oz = -q.pz * s.iz;
             // slab test: each axis's entry and exit by min / max (no selects
@@ -99,7 +98,7 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
                 const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), tfz);
                 return le_mask(tn, tf);
             };
-            auto leaf = [&](int prim, int voff, int m, uint64_t want) {
+            auto leaf = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
                 const bool go = lane_in(want & ballot(prim != q.own));
                 if constexpr (kCount) {
                     wk.prism += go ? 1u : 0u;
@@ -107,16 +106,17 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
                     wk.leaves += first_active_lane() ? 1u : 0u;
                 }
                 const bool t = go & ray_prism(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, s.dx, s.dy, s.dz);
-                hit = hit | t;
-                live = live & !t;
+                const uint64_t tm = ballot(t);
+                hitm |= tm;
+                return tm;  // a blocked ray needs no further test
             };
             auto key = [&](float x0, float y0, float x1, float y1, float z1) {
                 return fmaf(x0 + x1, s.dx, fmaf(y0 + y1, s.dy, z1 * s.dz));
             };
-            packet_traverse<kCount>(nodes, stack, live, bt, leaf, key, wk);
+            packet_traverse<kCount>(nodes, stack, ballot(valid && !back), bt, leaf, key, wk);
         }
         if constexpr (kCount) wk.units += valid ? 1u : 0u;
-        const bool sh = valid && (back || hit);
+        const bool sh = valid && (back || lane_in(hitm));
         cnt += sh ? 1 : 0;
         mins += sh ? s.w : 0.f;
         if (longest) {
@@ -204,9 +204,11 @@ __device__ __forceinline__ void accrue_segment(Src src, StackEntry *stack, cfloa
         }
     }
     if (src.nodes == nullptr) return;
-    auto leaf = [&](int prim, int voff, int m, uint64_t want) {
+    // liveness and overflow as wave masks (see packet_traverse)
+    uint64_t ovm = 0;
+    auto leaf_m = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
         const uint64_t gm = want & ballot(prim != q.own);
-        if (!gm) return;
+        if (!gm) return 0;
         const bool go = lane_in(gm);
         if constexpr (kCount) {
             wk.prism += go ? 1u : 0u;
@@ -215,46 +217,20 @@ __device__ __forceinline__ void accrue_segment(Src src, StackEntry *stack, cfloa
         }
         float a = 0.f, b = 0.f;
         float da, db;
-        const int r = go ? prism_interval<false>(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, w0, w1,
-                                                 W0u, W0v, W1u, W1v, a, b, da, db)
+        const int r = go ? prism_interval<false>(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, w0, w1, W0u,
+                                                 W0v, W1u, W1v, a, b, da, db)
                          : 0;
         if constexpr (kCount) wk.inserts += r ? 1u : 0u;
+        bool over = false, full = false;
         if (r) {
-            if (!union_insert(U, a, b)) {
-                ov = true;
-                live = false;
-            } else if (U.n == 1 && U.lo[0] <= w0 && U.hi[0] >= w1) {
-                live = false;  // the whole window is in shadow
-            }
+            over = !union_insert(U, a, b);
+            full = !over && U.n == 1 && U.lo[0] <= w0 && U.hi[0] >= w1;  // the whole window is in shadow
         }
+        const uint64_t om = ballot(over);
+        ovm |= om;
+        return om | ballot(full);
     };
     if constexpr (std::is_same<Src, SegSrc>::value) {
-        // liveness and overflow as wave masks (see packet_traverse_seg)
-        uint64_t ovm = 0;
-        auto leaf_m = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
-            const uint64_t gm = want & ballot(prim != q.own);
-            if (!gm) return 0;
-            const bool go = lane_in(gm);
-            if constexpr (kCount) {
-                wk.prism += go ? 1u : 0u;
-                wk.edges += go ? (uint32_t)m : 0u;
-                wk.leaves += first_active_lane() ? 1u : 0u;
-            }
-            float a = 0.f, b = 0.f;
-            float da, db;
-            const int r = go ? prism_interval<false>(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, w0, w1,
-                                                     W0u, W0v, W1u, W1v, a, b, da, db)
-                             : 0;
-            if constexpr (kCount) wk.inserts += r ? 1u : 0u;
-            bool over = false, full = false;
-            if (r) {
-                over = !union_insert(U, a, b);
-                full = !over && U.n == 1 && U.lo[0] <= w0 && U.hi[0] >= w1;  // the whole window is in shadow
-            }
-            const uint64_t om = ballot(over);
-            ovm |= om;
-            return om | ballot(full);
-        };
         const SegFan ft(g, q.px, q.py, q.pz);
         packet_traverse_seg<kCount>(src.nodes, src.voff, stack, ballot(live), ft, leaf_m, wk);
         ov = lane_in(ovm);
@@ -262,7 +238,8 @@ __device__ __forceinline__ void accrue_segment(Src src, StackEntry *stack, cfloa
         const FanTest bt(g, q.px, q.py, q.pz);
         const float mdx = g.mdx, mdy = g.mdy;
         auto key = [&](float x0, float y0, float x1, float y1, float z1) { return seg_key(x0, y0, x1, y1, mdx, mdy); };
-        packet_traverse<kCount>(src.nodes, stack, live, bt, leaf, key, wk);
+        packet_traverse<kCount>(src.nodes, stack, ballot(live), bt, leaf_m, key, wk);
+        ov = lane_in(ovm);
     }
 }
 
@@ -294,21 +271,22 @@ __global__ void k_seg_nodes(const Node *__restrict__ nodes, int n_nodes, const S
 __device__ __forceinline__ bool roof_covered(cNode *nodes, StackEntry *stack, cfloat4 *verts, cfloat *height,
                                              const LanePoint &q, bool valid)
 {
-    bool live = valid, cov = false;
     if (nodes == nullptr) return false;
+    uint64_t covm = 0;
     auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
         return q.px >= x0 && q.px <= x1 && q.py >= y0 && q.py <= y1 && q.pz <= z1;
     };
-    auto leaf = [&](int prim, int voff, int m, uint64_t want) {
+    auto leaf = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
         const bool t = lane_in(want) && prim != q.own && q.pz <= ld(height + prim) &&
                        in_footprint(verts, voff, m, q.px, q.py);
-        cov = cov || t;
-        live = live && !t;
+        const uint64_t tm = ballot(t);
+        covm |= tm;
+        return tm;
     };
     auto key = [&](float, float, float, float, float) { return 0.f; };
     Work none{0, 0, 0, 0, 0, 0, 0};
-    packet_traverse<false>(nodes, stack, live, bt, leaf, key, none);
-    return cov;
+    packet_traverse<false>(nodes, stack, ballot(valid), bt, leaf, key, none);
+    return lane_in(covm);
 }
 
 // Eight waves per SIMD: the kernel fits in 64 VGPRs (the compiler would

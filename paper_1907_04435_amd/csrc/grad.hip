@@ -92,21 +92,22 @@ __device__ __forceinline__ void scatter_grad(const UnionG &U, float wscale, cons
 __device__ __forceinline__ bool roof_covered_g(cNode *nodes, StackEntry *stack, cfloat4 *verts, cfloat *height,
                                                const LanePoint &q, bool valid)
 {
-    bool live = valid, cov = false;
     if (nodes == nullptr) return false;
+    uint64_t covm = 0;
     auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
         return q.px >= x0 && q.px <= x1 && q.py >= y0 && q.py <= y1 && q.pz <= z1;
     };
-    auto leaf = [&](int prim, int voff, int m, uint64_t want) {
+    auto leaf = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
         const bool t = lane_in(want) && prim != q.own && q.pz <= ld(height + prim) &&
                        in_footprint(verts, voff, m, q.px, q.py);
-        cov = cov || t;
-        live = live && !t;
+        const uint64_t tm = ballot(t);
+        covm |= tm;
+        return tm;
     };
     auto key = [&](float, float, float, float, float) { return 0.f; };
     Work none{0, 0, 0, 0, 0, 0, 0};
-    packet_traverse<false>(nodes, stack, live, bt, leaf, key, none);
-    return cov;
+    packet_traverse<false>(nodes, stack, ballot(valid), bt, leaf, key, none);
+    return lane_in(covm);
 }
 
 __global__ __launch_bounds__(kThreads) void k_grad(const Node *nodes_g, const SegNode *snodes_g, int n_nodes,

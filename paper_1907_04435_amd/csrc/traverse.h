@@ -100,79 +100,108 @@ __device__ __forceinline__ uint64_t uniform64(uint32_t lo, uint32_t hi)
 // Is this lane's bit set in a wave-uniform mask?  (maps to the exec mask)
 __device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
+// Scalar helpers of the traversal loops.  Written as compare-and-selects
+// on 64-bit lane masks: the compiler otherwise turns these conditions into
+// lane-mask booleans and spends three or four extra scalar instructions
+// per node on them.
+// defer = h0 != 0 ? h1 : 0 (the second child, when both are wanted)
+__device__ __forceinline__ uint64_t defer_mask(uint64_t h0, uint64_t h1)
+{
+    uint64_t d;
+    asm("s_cmp_lg_u64 %[h0], 0\n"
+        "s_cselect_b64 %[d], %[h1], 0"
+        : [d] "=&s"(d)
+        : [h0] "s"(h0), [h1] "s"(h1)
+        : "scc");
+    return d;
+}
+// (node, cur) = h0 != 0 ? (r0, h0) : (r1, h1) (the first child wanted)
+__device__ __forceinline__ void descend(uint64_t h0, uint64_t h1, int r0, int r1, int &node, uint64_t &cur)
+{
+    asm("s_cmp_lg_u64 %[h0], 0\n"
+        "s_cselect_b32 %[n], %[r0], %[r1]\n"
+        "s_cselect_b64 %[c], %[h0], %[h1]"
+        : [n] "=&s"(node), [c] "=&s"(cur)
+        : [h0] "s"(h0), [h1] "s"(h1), [r0] "s"(r0), [r1] "s"(r1)
+        : "scc");
+}
+
 // Packet traversal.  `bt(x0, y0, x1, y1, z1)` is the per-lane child-box
 // test (a bool, or directly the lane mask of the lanes that pass);
 // `leaf(prim, voff, m, want)` processes a leaf for the lanes in the mask
-// `want` and may clear `live`.  `key(x0,y0,x1,y1,z1)` orders two wanted children
-// (smaller first).  The walk ends when no lane is live or the stack runs
-// dry.  A lane only tests the children of nodes it reached itself: the
-// walk carries the wave mask of the lanes that reached the current node,
-// and every stack entry keeps the mask of the lanes that wanted it, so
-// leaves no lane reached are skipped.  All the bookkeeping is on those
-// wave-uniform masks (scalar registers); the only per-lane work is the box
-// tests.  With kCount, `w` accumulates those box tests and the wave's node
+// `want` and returns the mask of lanes it retires.  `key(x0,y0,x1,y1,z1)`
+// orders two wanted children (smaller first).  The walk starts with the
+// lanes in `alive` and ends when none is left or the stack runs dry.  A
+// lane only tests the children of nodes it reached itself: the walk
+// carries the wave mask of the lanes that reached the current node, and
+// every stack entry keeps the mask of the lanes that wanted it, so leaves
+// no lane reached are skipped.  All the bookkeeping is on those
+// wave-uniform masks (scalar registers; liveness too, so no per-lane flag
+// is carried around the loop); the only per-lane work is the box tests.
+// With kCount, `w` accumulates those box tests and the wave's node
 // fetches.
 template <bool kCount, class BoxTest, class LeafFn, class KeyFn>
-__device__ __forceinline__ void packet_traverse(cNode *nodes, StackEntry *stack, bool &live, BoxTest bt,
+__device__ __forceinline__ void packet_traverse(cNode *nodes, StackEntry *stack, uint64_t alive, BoxTest bt,
                                                 LeafFn leaf, KeyFn key, Work &w)
 {
-    uint64_t alive = ballot(live);  // lanes still live (only a leaf retires lanes)
+    typedef __attribute__((address_space(4))) const char cchar;
     uint64_t cur = alive;
     int sp = 0, node = 0;
     while (cur) {
-        const Node nd = ld(nodes + node);
+        // 64-byte nodes: a shifted index is the register offset of one
+        // scalar load
+        const Node nd = ld((cNode *)((cchar *)nodes + ((uint32_t)node << 6)));
         if constexpr (kCount) {
             w.box += lane_in(cur) ? 2u : 0u;
             w.nodes += first_active_lane() ? 1u : 0u;
         }
-        uint64_t hl = to_mask(bt(nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1)) & cur;
-        uint64_t hr = to_mask(bt(nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1)) & cur;
-        if (nd.left == kNone) hl = 0;
-        if (nd.right == kNone) hr = 0;  // a one-prism hierarchy has only a left child
-        bool leaves = false;
-        if (nd.left < 0 && nd.left != kNone) {
-            if (hl) {
-                leaf(~nd.left, nd.l_voff, nd.l_m, hl);
-                leaves = true;
+        uint64_t h0 = to_mask(bt(nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1)) & cur;
+        uint64_t h1 = to_mask(bt(nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1)) & cur;
+        int r0 = nd.left, r1 = nd.right;
+        if ((r0 | r1) < 0) {
+            // a leaf child, or the absent right child of a one-prism
+            // hierarchy
+            uint64_t out = 0;
+            if (r0 < 0) {
+                if (h0 && r0 != kNone) out |= leaf(~r0, nd.l_voff, nd.l_m, h0);
+                h0 = 0;
             }
-            hl = 0;
-        }
-        if (nd.right < 0 && nd.right != kNone) {
-            if (hr) {
-                leaf(~nd.right, nd.r_voff, nd.r_m, hr);
-                leaves = true;
+            if (r1 < 0) {
+                if (h1 && r1 != kNone) out |= leaf(~r1, nd.r_voff, nd.r_m, h1);
+                h1 = 0;
             }
-            hr = 0;
+            alive &= ~out;
+            h0 &= alive;
+            h1 &= alive;
         }
-        if (leaves) {
-            alive = ballot(live);
-            hl &= alive;
-            hr &= alive;
-        }
-        if (hl && hr) {
+        if (h0 && h1) {
             // the visiting order must be one decision for the whole wave:
             // with per-lane keys (lanes on different segments) lanes could
             // disagree and the shared stack would lose a subtree
-            const bool lfirst = uniform(key(nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1) <=
+            const bool rfirst = uniform(key(nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1) >
                                         key(nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1)) != 0;
-            const uint64_t mfar = lfirst ? hr : hl;
-            stack[sp] = StackEntry{lfirst ? nd.right : nd.left, (uint32_t)mfar, (uint32_t)(mfar >> 32), 0u};
+            if (rfirst) {
+                const uint64_t th = h0;
+                h0 = h1;
+                h1 = th;
+                const int tr = r0;
+                r0 = r1;
+                r1 = tr;
+            }
+        }
+        const uint64_t defer = defer_mask(h0, h1);
+        if (defer) {
+            stack[sp] = StackEntry{r1, (uint32_t)defer, (uint32_t)(defer >> 32), 0u};
             ++sp;
-            node = lfirst ? nd.left : nd.right;
-            cur = lfirst ? hl : hr;
-        } else if (hl) {
-            node = nd.left;
-            cur = hl;
-        } else if (hr) {
-            node = nd.right;
-            cur = hr;
-        } else {
-            cur = 0;
-            while (sp > 0 && alive) {
+        }
+        descend(h0, h1, r0, r1, node, cur);
+        if (!cur) {
+            const uint64_t keep = alive;
+            while (sp > 0) {
                 --sp;
                 const StackEntry e = stack[sp];
                 node = uniform(e.node);
-                cur = uniform64(e.lo, e.hi) & alive;
+                cur = uniform64(e.lo, e.hi) & keep;
                 if (cur) break;
             }
         }
@@ -923,26 +952,13 @@ __device__ __forceinline__ void packet_traverse_seg(cSegNode *nodes, cint *voff,
             h0 &= alive;
             h1 &= alive;
         }
-        // Both children wanted: defer the second.  Then go to the first
-        // child wanted.  Written as scalar compare-and-selects: the compiler
-        // turns these conditions into 64-bit lane-mask booleans otherwise
-        // (three or four extra scalar instructions per node).
-        uint64_t defer;
-        asm("s_cmp_lg_u64 %[h0], 0\n"
-            "s_cselect_b64 %[d], %[h1], 0"
-            : [d] "=&s"(defer)
-            : [h0] "s"(h0), [h1] "s"(h1)
-            : "scc");
+        // both children wanted: defer the second; go to the first wanted
+        const uint64_t defer = defer_mask(h0, h1);
         if (defer) {
             stack[sp] = StackEntry{nd.ref[1], (uint32_t)defer, (uint32_t)(defer >> 32), 0u};
             ++sp;
         }
-        asm("s_cmp_lg_u64 %[h0], 0\n"
-            "s_cselect_b32 %[n], %[r0], %[r1]\n"
-            "s_cselect_b64 %[c], %[h0], %[h1]"
-            : [n] "=&s"(node), [c] "=&s"(cur)
-            : [h0] "s"(h0), [h1] "s"(h1), [r0] "s"(nd.ref[0]), [r1] "s"(nd.ref[1])
-            : "scc");
+        descend(h0, h1, nd.ref[0], nd.ref[1], node, cur);
         if (!cur) {
             const uint64_t keep = alive;
             while (sp > 0) {
