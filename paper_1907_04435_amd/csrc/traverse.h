@@ -468,33 +468,54 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
             wy = q.y - py;
             z = fmaf(Z1, wx, Z2 * wy);
         };
-        float pwx, pwy, pzv;
-        vertex(0, pwx, pwy, pzv);
-        uint64_t pin = le_mask(pzv, h);
-        cand(pwx, pwy, pin);
-        for (int e = 1; e <= m; ++e) {
-            float wx, wy, z;
-            vertex(e == m ? 0 : e, wx, wy, z);
-            const uint64_t in = le_mask(z, h);
-            inside &= ge_mask(cross2(pwx, pwy, wx, wy), 0.f);
-            const uint64_t crossing = (pin ^ in) & ballot(true);
+        // edge from vertex (ax, ay) (height az, below the roof line in the
+        // lanes of ain) to vertex (bx, by, bz, bin)
+        auto edge = [&](float ax, float ay, float az, uint64_t ain, float bx, float by, float bz, uint64_t bin) {
+            inside &= ge_mask(cross2(ax, ay, bx, by), 0.f);
+            const uint64_t crossing = (ain ^ bin) & ballot(true);
             if (crossing) {
-                const float t = (h - pzv) * __builtin_amdgcn_rcpf(z - pzv);
-                cand(fmaf(t, wx - pwx, pwx), fmaf(t, wy - pwy, pwy), crossing);
+                const float t = (h - az) * __builtin_amdgcn_rcpf(bz - az);
+                cand(fmaf(t, bx - ax, ax), fmaf(t, by - ay, ay), crossing);
             }
-            if (e < m) cand(wx, wy, in);
-            pwx = wx;
-            pwy = wy;
-            pzv = z;
-            pin = in;
+        };
+        // Two vertices per trip (A, then B, then A again), so the previous
+        // vertex never has to be copied between registers; the closing edge
+        // back to vertex 0 adds no vertex candidate.
+        float ax, ay, az, bx, by, bz;
+        vertex(0, ax, ay, az);
+        uint64_t ain = le_mask(az, h), bin;
+        cand(ax, ay, ain);
+        int e = 1;
+        for (; e + 1 < m; e += 2) {
+            vertex(e, bx, by, bz);
+            bin = le_mask(bz, h);
+            edge(ax, ay, az, ain, bx, by, bz, bin);
+            cand(bx, by, bin);
+            vertex(e + 1, ax, ay, az);
+            const uint64_t nin = le_mask(az, h);
+            edge(bx, by, bz, bin, ax, ay, az, nin);
+            cand(ax, ay, nin);
+            ain = nin;
         }
+        if (e < m) {  // one vertex left before the closing edge
+            vertex(e, bx, by, bz);
+            bin = le_mask(bz, h);
+            edge(ax, ay, az, ain, bx, by, bz, bin);
+            cand(bx, by, bin);
+            ax = bx;
+            ay = by;
+            az = bz;
+            ain = bin;
+        }
+        vertex(0, bx, by, bz);
+        edge(ax, ay, az, ain, bx, by, bz, le_mask(bz, h));
         const bool flip = fmaf(g.m00, g.m11, -g.m01 * g.m10) < 0.f;
-        const float ax = flip ? hix : lox, ay = flip ? hiy : loy;
-        const float bx = flip ? lox : hix, by = flip ? loy : hiy;
-        lou = fmaf(g.m00, ax, g.m01 * ay);
-        lov = fmaf(g.m10, ax, g.m11 * ay);
-        hiu = fmaf(g.m00, bx, g.m01 * by);
-        hiv = fmaf(g.m10, bx, g.m11 * by);
+        const float fx = flip ? hix : lox, fy = flip ? hiy : loy;
+        const float gx = flip ? lox : hix, gy = flip ? loy : hiy;
+        lou = fmaf(g.m00, fx, g.m01 * fy);
+        lov = fmaf(g.m10, fx, g.m11 * fy);
+        hiu = fmaf(g.m00, gx, g.m01 * gy);
+        hiv = fmaf(g.m10, gx, g.m11 * gy);
     }
     da = db = 0.f;
     if (lane_in(inside)) {
