@@ -118,3 +118,28 @@ def test_overflowing_sets_walked_in_order(ctx):
     say(f"ring: longest {g['longest'].ravel()[:4]}, oracle {o['longest'].ravel()[:4]}")
     assert np.abs(g["minutes"] - o["minutes"]).max() <= 0.01
     assert np.abs(g["longest"] - o["longest"]).max() <= 0.01
+
+
+def test_accrual_longest_over_several_view_launches(ctx):
+    """Twelve days on the block scene (20k prisms): about 300 segments, more
+    than one launch's budget of per-segment node views (256 MiB, ~209
+    segments here), so the continuous-shadow kernel runs in two launches of
+    whole days.  Against the oracle, one bin per day."""
+    import datetime as dt
+    from workloads.scenes import _nyc_tz
+    w = make_c2(n_ground=20_000, n_facade=20_000)
+    idx = np.concatenate([subset_points(w.points.take(np.arange(20_000)), 48, 21),
+                          20_000 + subset_points(w.points.take(np.arange(20_000, 40_000)), 48, 22)])
+    sub = w.points.take(idx)
+    days = [dt.date(2019, m, 21) for m in range(1, 13)]
+    span = Span(40.7, -74.0, [Day(d.year, d.month, d.day, _nyc_tz(d)) for d in days], 1.0)
+    sp = sa.sunpath_for_span(span, 30.0)
+    n_segs = len(sp.knot_t) - sp.n_days
+    assert n_segs * (w.scene.n_b - 1) * 64 > 256 << 20
+    say(f"continuous shadow, 12 days, {n_segs} segments")
+    g = run(ctx, w.scene, sub, span, sa.SA_ACCRUAL)
+    o = oracle.continuous(w.scene, sub, oracle.sun_path(span, 30.0))
+    for k in ("minutes", "longest"):
+        d = np.abs(g[k] - o[k]).ravel()
+        say(f"  {k}: |GPU - oracle| mean {d.mean():.2e} p99.9 {np.quantile(d, 0.999):.2e} max {d.max():.2e}")
+        assert np.quantile(d, 0.999) <= 0.01 and d.mean() <= 1e-3

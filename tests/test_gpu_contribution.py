@@ -88,3 +88,25 @@ def test_bin_span_and_score(ctx):
     ref = [oracle.shadow_score(vals[:, off[r]:off[r + 1]], w12, osp, area[off[r]:off[r + 1]])
            for r in range(len(off) - 1)]
     np.testing.assert_allclose(got.cpu().numpy(), ref, rtol=1e-10, atol=1e-6)
+
+
+def test_contribution_over_several_view_launches(ctx):
+    """Twelve days on the block scene: more segments than one launch's budget
+    of per-segment node views, so the contribution kernel runs in several
+    launches.  Against the oracle, one bin per day."""
+    import datetime as dt
+    from workloads.scenes import _nyc_tz
+    w = make_c2(n_ground=20_000, n_facade=20_000)
+    idx = np.concatenate([subset_points(w.points.take(np.arange(20_000)), 24, 23),
+                          20_000 + subset_points(w.points.take(np.arange(20_000, 40_000)), 24, 24)])
+    sub = w.points.take(idx)
+    days = [dt.date(2019, m, 21) for m in range(1, 13)]
+    span = Span(40.7, -74.0, [Day(d.year, d.month, d.day, _nyc_tz(d)) for d in days], 1.0)
+    sp = sa.sunpath_for_span(span, 30.0)
+    assert (len(sp.knot_t) - sp.n_days) * (w.scene.n_b - 1) * 64 > 256 << 20
+    g = gpu_contrib(ctx, w.scene, sub, span)
+    o = oracle.contribution(w.scene, sub, oracle.sun_path(span, 30.0))
+    d = np.abs(g - o)
+    say(f"contribution, 12 days: max |GPU - oracle| {d.max():.3e} of total {o.sum():.4e}")
+    assert g.shape == o.shape == (12, w.scene.n_b)
+    assert d.max() <= 1e-5 * o.sum() + 0.05

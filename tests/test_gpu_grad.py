@@ -6,7 +6,7 @@ import pytest
 
 import oracle
 import paper_1907_04435_amd as sa
-from workloads import Scene, make_c1, make_c4, subset_points
+from workloads import Scene, Span, make_c1, make_c4, subset_points
 
 from gpu_util import say
 
@@ -137,3 +137,26 @@ def test_autograd_function(ctx, c1):
     big = np.abs(o) > 0.05 * np.abs(o).max()
     gh = H.grad.cpu().numpy()
     assert (np.abs(gh - 2 * o)[big] / np.abs(2 * o)[big]).max() <= 1e-3
+
+
+def test_grad_over_several_view_launches(ctx):
+    """Mar 20 and Jun 21 at 1-minute knots on the differentiation scene:
+    about 1,600 segments, more than one launch's budget of per-segment node
+    views (~840 segments for 5,000 buildings), so the adjoint runs in two
+    launches, the second starting inside Jun 21.  The loss sums over days,
+    so its gradient equals the sum of the single-day gradients."""
+    from workloads.scenes import Day, _nyc_tz
+    import datetime as dt
+    w = make_c4()
+    sub = w.points.take(subset_points(w.points, 20_000, 62))
+    days = [Day(d.year, d.month, d.day, _nyc_tz(d)) for d in (dt.date(2019, 3, 20), dt.date(2019, 6, 21))]
+    both = Span(w.span.lat, w.span.lon, days, 1.0, [0, 0])
+    sp = sa.sunpath_for_span(both, 1.0)
+    assert (len(sp.knot_t) - sp.n_days) * (w.scene.n_b - 1) * 64 > 256 << 20
+    g = gpu_grad(ctx, w.scene, sub, both, 1.0)
+    parts = [gpu_grad(ctx, w.scene, sub, Span(w.span.lat, w.span.lon, [d], 1.0), 1.0) for d in days]
+    ref = parts[0] + parts[1]
+    d = np.abs(g - ref)
+    say(f"two-day gradient: max |both - sum of days| {d.max():.3e} of max |grad| {np.abs(ref).max():.4g}")
+    assert (np.abs(ref) > 0).sum() > 50
+    assert d.max() <= 1e-4 * np.abs(ref).max()
