@@ -565,9 +565,10 @@ __global__ __launch_bounds__(kThreads) void k_contrib(const SegNode *snodes_g, i
             const int r = go ? prism_interval<false>(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, 0.f,
                                                      g.theta, 1.f, 0.f, g.cth, g.sth, a, b, da, db)
                              : 0;
-            double v = r ? (double)((b - a) * g.rate * wt) : 0.0;
-            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-            if (first_active_lane() && v != 0.0) atomicAdd(&row[order[prim]], v);
+            // the wave's total for this building (every lane is active
+            // here: the traversal runs on the whole wave)
+            const float v = wave_sum(r ? (b - a) * g.rate * wt : 0.f);
+            if (first_active_lane() && v != 0.f) atomicAdd(&row[order[prim]], (double)v);
             return 0;  // no lane retires: every building counts
         };
         packet_traverse_seg<false>((cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes), (cint *)voff_g, stack,

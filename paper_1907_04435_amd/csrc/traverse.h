@@ -97,6 +97,29 @@ __device__ __forceinline__ uint64_t uniform64(uint32_t lo, uint32_t hi)
     return ((uint64_t)h << 32) | l;
 }
 
+// Sum of v over all 64 lanes, returned to every lane; call with every lane
+// of the wave active.  Quad permutes and row rotations (DPP, no LDS round
+// trips) leave each 16-lane row's sum in all its lanes; the four row sums
+// are read out and added.
+template <int kCtrl>
+__device__ __forceinline__ float add_dpp(float x)
+{
+    return x + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), kCtrl, 0xF, 0xF, false));
+}
+
+__device__ __forceinline__ float wave_sum(float v)
+{
+    v = add_dpp<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v = add_dpp<0x4E>(v);   // quad_perm [2, 3, 0, 1]: quad sums
+    v = add_dpp<0x124>(v);  // row_ror 4: two quads
+    v = add_dpp<0x128>(v);  // row_ror 8: the row
+    const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+    const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+    const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+    const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
 // Is this lane's bit set in a wave-uniform mask?  (maps to the exec mask)
 __device__ __forceinline__ bool lane_in(uint64_t m) { return __builtin_amdgcn_inverse_ballot_w64(m); }
 
