@@ -183,6 +183,7 @@ struct TreeSrc {
 struct SegSrc {
     cSegNode *nodes;
     cint *voff;
+    int root;  // byte offset of the root's view
 };
 
 template <bool kCount, class Src>
@@ -232,7 +233,7 @@ __device__ __forceinline__ void accrue_segment(Src src, StackEntry *stack, cfloa
     };
     if constexpr (std::is_same<Src, SegSrc>::value) {
         const SegFan ft(g, q.px, q.py, q.pz);
-        packet_traverse_seg<kCount>(src.nodes, src.voff, stack, ballot(live), ft, leaf_m, wk);
+        packet_traverse_seg<kCount>(src.nodes, src.voff, stack, ballot(live), ft, leaf_m, wk, src.root);
         ov = lane_in(ovm);
     } else {
         const FanTest bt(g, q.px, q.py, q.pz);
@@ -243,17 +244,10 @@ __device__ __forceinline__ void accrue_segment(Src src, StackEntry *stack, cfloa
     }
 }
 
-// The per-segment node views of segments [j0, j1): one thread per
-// (segment, node), written to out[(j - j0) * n_nodes + node].
-__global__ void k_seg_nodes(const Node *__restrict__ nodes, int n_nodes, const SegConst *__restrict__ segs, int j0,
-                            int j1, SegNode *__restrict__ out)
+// The view of node `nd` for segment g, with child references r0 (left)
+// and r1 (right) already in view form (byte offsets, or leaf / absent).
+__device__ __forceinline__ SegNode make_view(const Node &nd, int r0, int r1, const SegConst &g)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)(j1 - j0) * n_nodes) return;
-    const int jj = (int)(t / n_nodes);
-    const int node = (int)(t - (int64_t)jj * n_nodes);
-    const SegConst &g = segs[j0 + jj];
-    const Node nd = nodes[node];
     const FanGeom f = fan_geom(g);
     const bool lfirst = seg_key(nd.lx0, nd.ly0, nd.lx1, nd.ly1, g.mdx, g.mdy) <=
                         seg_key(nd.rx0, nd.ry0, nd.rx1, nd.ry1, g.mdx, g.mdy);
@@ -261,9 +255,24 @@ __global__ void k_seg_nodes(const Node *__restrict__ nodes, int n_nodes, const S
     const int a = lfirst ? 0 : 1;
     seg_child(f, nd.lx0, nd.ly0, nd.lx1, nd.ly1, nd.lz1, nd.left != kNone, v.c[a]);
     seg_child(f, nd.rx0, nd.ry0, nd.rx1, nd.ry1, nd.rz1, nd.right != kNone, v.c[1 - a]);
-    v.ref[a] = nd.left >= 0 ? nd.left * (int)sizeof(SegNode) : nd.left;
-    v.ref[1 - a] = nd.right >= 0 ? nd.right * (int)sizeof(SegNode) : nd.right;
-    out[t] = v;
+    v.ref[a] = r0;
+    v.ref[1 - a] = r1;
+    return v;
+}
+
+__device__ __forceinline__ int view_ref(int r) { return r >= 0 ? r * (int)sizeof(SegNode) : r; }
+
+// The per-segment node views of segments [j0, j1): one thread per
+// (segment, node), written to out[(j - j0) * stride + node].
+__global__ void k_seg_nodes(const Node *__restrict__ nodes, int n_nodes, const SegConst *__restrict__ segs, int j0,
+                            int j1, int64_t stride, SegNode *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)(j1 - j0) * n_nodes) return;
+    const int jj = (int)(t / n_nodes);
+    const int node = (int)(t - (int64_t)jj * n_nodes);
+    const Node nd = nodes[node];
+    out[jj * stride + node] = make_view(nd, view_ref(nd.left), view_ref(nd.right), segs[j0 + jj]);
 }
 
 // Roof-covered: inside a footprint (other than the point's own building)
@@ -330,7 +339,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
         Union4 U;
         bool ov;
         const SegSrc src{snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr,
-                         (cint *)voff_g};
+                         (cint *)voff_g, 0};
         accrue_segment<kCount>(src, stack, verts, height, g, q, valid && !covered, 0.f, g.theta, U, ov, wk);
         if constexpr (kCount) {
             wk.units += valid ? 1u : 0u;
@@ -443,7 +452,7 @@ __global__ __launch_bounds__(kThreads) void k_accrual_runs(const Node *nodes_g, 
             Union4 U;
             bool ov;
             const SegSrc src{snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr,
-                             (cint *)voff_g};
+                             (cint *)voff_g, 0};
             accrue_segment<false>(src, stack, verts, height, g, q, pending, w0, w1, U, ov, none);
             if (pending) {
                 if (ov) {
@@ -503,7 +512,7 @@ __global__ __launch_bounds__(kThreads) void k_spill(const SegNode *snodes_g, int
         bool ov;
         Work none{0, 0, 0, 0, 0, 0, 0};
         const SegSrc src{snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr,
-                         (cint *)voff_g};
+                         (cint *)voff_g, 0};
         accrue_segment<false>(src, stack, verts, height, g, q, true, w0, w1, U, ov, none);
         double mins = 0.0;
         int cnt = 0;
@@ -629,6 +638,87 @@ __global__ void k_var_refit(int V, int k, const int32_t *__restrict__ ids, const
     }
 }
 
+// Per-segment views of the variants.  A variant differs from the base only
+// in the boxes of the ancestors of its changed leaves, so it shares the
+// base views everywhere else: each variant gets its own copies of the
+// views of those ancestors ("changed nodes"), whose child references point
+// to the variant's copy where the child changed too and to the base view
+// otherwise.  Every ancestor of a changed node is changed, so a walk
+// started at the variant's copy of the root sees exactly the variant's
+// hierarchy.  Copies of variant v live at view index n_nodes + v * cmax + c.
+
+// vlist[v][0, vcount[v]): the changed interior nodes of variant v (one
+// thread per variant; a chain walk stops at the first node already listed,
+// whose ancestors are listed too); vroot[v]: byte offset of the root's view.
+__global__ void k_var_list(int V, int k, const int32_t *__restrict__ ids, const int32_t *__restrict__ rank,
+                           const int32_t *__restrict__ parent, int n_int, int n_b, int n_nodes, int cmax,
+                           int32_t *__restrict__ vlist, int32_t *__restrict__ vcount, int32_t *__restrict__ vroot)
+{
+    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= V) return;
+    int32_t *L = vlist + (int64_t)v * cmax;
+    int c = 0;
+    for (int j = 0; j < k; ++j) {
+        const int id = ids[v * k + j];
+        if (id < 0 || id >= n_b) continue;
+        int pp = parent[n_int + rank[id]];
+        for (int guard = 0; pp >= 0 && guard < 64 && c < cmax; ++guard) {
+            const int a = pp >> 1;
+            bool seen = false;
+            for (int q = 0; q < c; ++q) seen = seen || L[q] == a;
+            if (seen) break;
+            L[c++] = a;
+            pp = parent[a];
+        }
+    }
+    vcount[v] = c;
+    int root = 0;
+    for (int q = 0; q < c; ++q)
+        if (L[q] == 0) root = (n_nodes + v * cmax + q) * (int)sizeof(SegNode);
+    vroot[v] = root;
+}
+
+// Child references of the copies, in view form: one thread per (variant,
+// copy).
+__global__ void k_var_refs(int V, int cmax, int n_nodes, const Node *__restrict__ nodes,
+                           const int32_t *__restrict__ vlist, const int32_t *__restrict__ vcount, int2 *__restrict__ vref)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)V * cmax) return;
+    const int v = (int)(t / cmax), c = (int)(t - (int64_t)v * cmax);
+    const int n = vcount[v];
+    if (c >= n) return;
+    const int32_t *L = vlist + (int64_t)v * cmax;
+    const Node nd = nodes[L[c]];
+    int r[2] = {nd.left, nd.right};
+    for (int s = 0; s < 2; ++s) {
+        if (r[s] < 0) continue;  // a leaf or absent
+        int at = -1;
+        for (int q = 0; q < n; ++q) at = L[q] == r[s] ? q : at;
+        r[s] = (at >= 0 ? n_nodes + v * cmax + at : r[s]) * (int)sizeof(SegNode);
+    }
+    vref[t] = make_int2(r[0], r[1]);
+}
+
+// The copies' views for segments [j0, j1), from the variants' refitted
+// boxes: one thread per (segment, variant, copy).
+__global__ void k_seg_var(int V, int cmax, int n_nodes, const Node *__restrict__ vnodes,
+                          const int32_t *__restrict__ vlist, const int32_t *__restrict__ vcount,
+                          const int2 *__restrict__ vref, const SegConst *__restrict__ segs, int j0, int j1,
+                          int64_t stride, SegNode *__restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)V * cmax;
+    if (t >= (int64_t)(j1 - j0) * per) return;
+    const int jj = (int)(t / per);
+    const int64_t vc = t - jj * per;
+    const int v = (int)(vc / cmax), c = (int)(vc - (int64_t)v * cmax);
+    if (c >= vcount[v]) return;
+    const Node nd = vnodes[(int64_t)v * n_nodes + vlist[vc]];
+    const int2 r = vref[vc];
+    out[jj * stride + n_nodes + vc] = make_view(nd, r.x, r.y, segs[j0 + jj]);
+}
+
 // tile_off[v] = first tile of variant v, 64 points per tile
 __global__ void k_var_tiles(int V, const int64_t *__restrict__ var_off, int64_t *__restrict__ tile_off)
 {
@@ -646,9 +736,11 @@ __global__ void k_var_tiles(int V, const int64_t *__restrict__ var_off, int64_t 
 // segment for its 64 points on that variant's hierarchy.  A point-segment
 // whose occluded set needs more than four pieces is finished in place by
 // walking its window left to right with halving / doubling sub-windows.
-__global__ __launch_bounds__(kThreads) void k_batched(const Node *vnodes_g, int n_nodes, const float4 *verts_g,
-                                                      const float *vh_g, int n_b, const SegConst *segs_g, int J,
-                                                      PointArgs P, const int64_t *__restrict__ var_off,
+__global__ __launch_bounds__(kThreads) void k_batched(const Node *vnodes_g, int n_nodes, const SegNode *views_g,
+                                                      int64_t stride, const int32_t *voff_g,
+                                                      const int32_t *__restrict__ vroot, const float4 *verts_g,
+                                                      const float *vh_g, int n_b, const SegConst *segs_g, int j0,
+                                                      int j1, PointArgs P, const int64_t *__restrict__ var_off,
                                                       const int64_t *__restrict__ tile_off, int V,
                                                       uint32_t *tile_counter, float scale, int32_t *counts,
                                                       float *minutes, uint32_t *flag)
@@ -678,11 +770,12 @@ __global__ __launch_bounds__(kThreads) void k_batched(const Node *vnodes_g, int 
         const bool valid = i < var_off[v + 1];
         const LanePoint q = load_point(P, i, valid);
         const bool covered = roof_covered(nodes, stack, verts, height, q, valid);
+        const int root = vroot ? vroot[v] : 0;
         int cnt = 0;
         double mins = 0.0;
-        int bin = J > 0 ? ld(segs).bin : 0;
+        int bin = j1 > j0 ? ld(segs + j0).bin : 0;
         Work none{0, 0, 0, 0, 0, 0, 0};
-        for (int j = 0; j < J; ++j) {
+        for (int j = j0; j < j1; ++j) {
             const SegConst g = ld(segs + j);
             if (g.bin != bin) {
                 if (valid) {
@@ -704,7 +797,9 @@ __global__ __launch_bounds__(kThreads) void k_batched(const Node *vnodes_g, int 
                 const float w1 = fminf(w0 + s, g.theta);
                 Union4 U;
                 bool ov;
-                accrue_segment<false>(TreeSrc{nodes}, stack, verts, height, g, q, pending, w0, w1, U, ov, none);
+                const SegSrc src{views_g ? (cSegNode *)(views_g + (int64_t)(j - j0) * stride) : nullptr,
+                                 (cint *)voff_g, root};
+                accrue_segment<false>(src, stack, verts, height, g, q, pending, w0, w1, U, ov, none);
                 if (pending) {
                     if (ov) {
                         if (s < g.theta * (1.0f / 4096.0f)) {
@@ -722,7 +817,7 @@ __global__ __launch_bounds__(kThreads) void k_batched(const Node *vnodes_g, int 
                 }
             }
         }
-        if (valid && J > 0) {
+        if (valid && j1 > j0) {
             if (counts) counts[(int64_t)bin * n + i] += cnt;
             if (minutes) minutes[(int64_t)bin * n + i] += (float)(mins * scale);
         }
@@ -807,32 +902,51 @@ sa_status fill_u32(void *p, int64_t n, uint32_t v, hipStream_t st, std::string &
 
 sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_var, int32_t k, const int32_t *ids,
                          const float *h, const PointsView &pts, const int64_t *var_off, float scale, int32_t *counts,
-                         float *minutes, int32_t grid_blocks, uint32_t *flag, Scratch &scr, hipStream_t st,
-                         std::string &err)
+                         float *minutes, int32_t grid_blocks, uint32_t *flag, Scratch &scr, Scratch &views_scr,
+                         hipStream_t st, std::string &err)
 {
     if (n_var == 0 || pts.n == 0) return SA_OK;
     const int n_nodes = s.n_b > 0 ? s.n_nodes : 0;
-    const size_t node_bytes = sizeof(Node) * (size_t)n_var * n_nodes;
-    const size_t h_bytes = sizeof(float) * (size_t)n_var * s.n_b;
-    const size_t off0 = 0, off1 = (node_bytes + 255) & ~(size_t)255, off2 = off1 + ((h_bytes + 255) & ~(size_t)255);
-    const size_t off3 = off2 + ((sizeof(int64_t) * (n_var + 1) + 255) & ~(size_t)255);
-    const size_t need = off3 + 256;
+    // copies of changed nodes per variant: at most one chain of ancestors
+    // per changed building
+    const int cmax = std::max(1, k * std::max(s.depth, 1));
+    const int64_t stride = (int64_t)n_nodes + (int64_t)n_var * cmax;  // views per segment
+    if (stride * (int64_t)sizeof(SegNode) >= (1ll << 31)) {
+        err = "too many variants x changed buildings for one call (views are addressed with 32-bit offsets)";
+        return SA_ERR_CAPACITY;
+    }
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t node_bytes = up(sizeof(Node) * (size_t)n_var * n_nodes);
+    const size_t h_bytes = up(sizeof(float) * (size_t)n_var * s.n_b);
+    const size_t tile_bytes = up(sizeof(int64_t) * (n_var + 1));
+    const size_t list_bytes = up(sizeof(int32_t) * (size_t)n_var * cmax);
+    const size_t ref_bytes = up(sizeof(int2) * (size_t)n_var * cmax);
+    const size_t cnt_bytes = up(sizeof(int32_t) * (size_t)n_var);
+    const size_t off1 = node_bytes, off2 = off1 + h_bytes, off3 = off2 + tile_bytes, off4 = off3 + list_bytes;
+    const size_t off5 = off4 + ref_bytes, off6 = off5 + cnt_bytes, off7 = off6 + cnt_bytes;
+    const size_t need = off7 + 256;
     if (scr.bytes < need) {
         (void)hipStreamSynchronize(st);
         (void)hipFree(scr.ptr);
         scr.ptr = nullptr;
         scr.bytes = 0;
         if (hipMalloc(&scr.ptr, need) != hipSuccess) {
+            (void)hipGetLastError();
+            scr.ptr = nullptr;
             err = "variant scratch allocation failed";
             return SA_ERR_OOM;
         }
         scr.bytes = need;
     }
     char *base = (char *)scr.ptr;
-    Node *vnodes = (Node *)(base + off0);
+    Node *vnodes = (Node *)base;
     float *vh = (float *)(base + off1);
     int64_t *tile_off = (int64_t *)(base + off2);
-    uint32_t *counter = (uint32_t *)(base + off3);
+    int32_t *vlist = (int32_t *)(base + off3);
+    int2 *vref = (int2 *)(base + off4);
+    int32_t *vcount = (int32_t *)(base + off5);
+    int32_t *vroot = (int32_t *)(base + off6);
+    uint32_t *counter = (uint32_t *)(base + off7);
     const int n_int = s.n_b == 1 ? 1 : s.n_b - 1;
     if (s.n_b > 0) {
         hipLaunchKernelGGL(k_var_copy, dim3(2048), dim3(256), 0, st, (const int4 *)s.nodes, (int64_t)n_nodes * 4,
@@ -844,16 +958,40 @@ sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_va
                                (const int32_t *)s.rank, (const int32_t *)s.parent, n_int, s.n_b, n_nodes,
                                (const float *)vh, vnodes);
         }
+        hipLaunchKernelGGL(k_var_list, dim3((n_var + 63) / 64), dim3(64), 0, st, n_var, k, ids,
+                           (const int32_t *)s.rank, (const int32_t *)s.parent, n_int, s.n_b, n_nodes, cmax, vlist,
+                           vcount, vroot);
+        const int64_t nr = (int64_t)n_var * cmax;
+        hipLaunchKernelGGL(k_var_refs, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, n_var, cmax, n_nodes,
+                           (const Node *)s.nodes, (const int32_t *)vlist, (const int32_t *)vcount, vref);
     }
     hipLaunchKernelGGL(k_var_tiles, dim3(1), dim3(1), 0, st, n_var, var_off, tile_off);
-    sa_status rc = fill_u32(counter, 2, 0u, st, err);
-    if (rc != SA_OK) return rc;
+    SA_CHECK_LAUNCH("variant set-up");
     const PointArgs P = point_args(pts, s);
     const int blocks = grid_blocks > 0 ? grid_blocks : 2048;
-    hipLaunchKernelGGL(k_batched, dim3(blocks), dim3(kThreads), 0, st, s.n_b > 0 ? vnodes : nullptr, n_nodes,
-                       s.verts, (const float *)vh, s.n_b, p.segs, p.n_segs, P, var_off, (const int64_t *)tile_off,
-                       n_var, counter, scale, counts, minutes, flag);
-    SA_CHECK_LAUNCH("batched accrual");
+    // segment ranges whose views (base and every variant's copies) fit the
+    // per-launch budget; outputs accumulate across the launches
+    const int64_t per = std::max<int64_t>(1, kSegNodeBytes / (stride * (int64_t)sizeof(SegNode)));
+    for (int64_t j0 = 0; j0 < std::max(p.n_segs, 1); j0 += per) {
+        const int j1 = (int)std::min<int64_t>(j0 + per, p.n_segs);
+        SegNode *views = nullptr;
+        if (s.n_b > 0 && j1 > j0) {
+            sa_status rc = build_seg_views(s, p, (int)j0, j1, stride, views_scr, st, views, err);
+            if (rc != SA_OK) return rc;
+            const int64_t nt = (int64_t)(j1 - j0) * n_var * cmax;
+            hipLaunchKernelGGL(k_seg_var, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, n_var, cmax, n_nodes,
+                               (const Node *)vnodes, (const int32_t *)vlist, (const int32_t *)vcount,
+                               (const int2 *)vref, p.segs, (int)j0, j1, stride, views);
+            SA_CHECK_LAUNCH("variant segment views");
+        }
+        sa_status rc = fill_u32(counter, 2, 0u, st, err);
+        if (rc != SA_OK) return rc;
+        hipLaunchKernelGGL(k_batched, dim3(blocks), dim3(kThreads), 0, st, s.n_b > 0 ? vnodes : nullptr, n_nodes,
+                           views, stride, s.voff, s.n_b > 0 ? (const int32_t *)vroot : nullptr, s.verts,
+                           (const float *)vh, s.n_b, p.segs, (int)j0, j1, P, var_off, (const int64_t *)tile_off,
+                           n_var, counter, scale, counts, minutes, flag);
+        SA_CHECK_LAUNCH("batched accrual");
+    }
     return SA_OK;
 }
 
@@ -862,13 +1000,13 @@ int64_t seg_views_cap(const DeviceScene &s)
     return std::max<int64_t>(1, kSegNodeBytes / ((int64_t)std::max(s.n_nodes, 1) * (int64_t)sizeof(SegNode)));
 }
 
-sa_status build_seg_views(const DeviceScene &s, const DevicePath &p, int j0, int j1, Scratch &scr, hipStream_t st,
-                          SegNode *&views, std::string &err)
+sa_status build_seg_views(const DeviceScene &s, const DevicePath &p, int j0, int j1, int64_t stride, Scratch &scr,
+                          hipStream_t st, SegNode *&views, std::string &err)
 {
     views = nullptr;
     if (s.n_b == 0 || j1 <= j0) return SA_OK;
     const int64_t nt = (int64_t)(j1 - j0) * s.n_nodes;
-    const size_t need = (size_t)nt * sizeof(SegNode);
+    const size_t need = (size_t)(j1 - j0) * stride * sizeof(SegNode);
     if (scr.bytes < need) {
         // the previous contents may still be read by queued kernels
         (void)hipStreamSynchronize(st);
@@ -885,7 +1023,7 @@ sa_status build_seg_views(const DeviceScene &s, const DevicePath &p, int j0, int
     }
     views = (SegNode *)scr.ptr;
     hipLaunchKernelGGL(k_seg_nodes, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, s.nodes, s.n_nodes, p.segs,
-                       j0, j1, views);
+                       j0, j1, stride, views);
     SA_CHECK_LAUNCH("segment node views");
     return SA_OK;
 }
@@ -913,7 +1051,7 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
             while (d1 < D && p.day_seg_off[d1 + 1] - p.day_seg_off[d0] <= per) ++d1;
             const int j0 = p.day_seg_off[d0], j1 = p.day_seg_off[d1];
             SegNode *views;
-            sa_status rc = build_seg_views(s, p, j0, j1, scr, st, views, err);
+            sa_status rc = build_seg_views(s, p, j0, j1, s.n_nodes, scr, st, views, err);
             if (rc != SA_OK) return rc;
             hipLaunchKernelGGL(k_accrual_runs, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, views, s.n_nodes,
                                s.voff, s.verts, s.height, p.segs, j0, j1, P, scale, counts, minutes, longest,
@@ -926,7 +1064,7 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
     for (int64_t j0 = 0; j0 < p.n_segs; j0 += per) {
         const int j1 = (int)std::min<int64_t>(j0 + per, p.n_segs);
         SegNode *views;
-        sa_status rc = build_seg_views(s, p, (int)j0, j1, scr, st, views, err);
+        sa_status rc = build_seg_views(s, p, (int)j0, j1, s.n_nodes, scr, st, views, err);
         if (rc != SA_OK) return rc;
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters);
         SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
@@ -953,7 +1091,7 @@ sa_status launch_contribution(const DeviceScene &s, const DevicePath &p, const P
     for (int64_t j0 = 0; j0 < p.n_segs; j0 += per) {
         const int j1 = (int)std::min<int64_t>(j0 + per, p.n_segs);
         SegNode *views;
-        sa_status rc = build_seg_views(s, p, (int)j0, j1, scr, st, views, err);
+        sa_status rc = build_seg_views(s, p, (int)j0, j1, s.n_nodes, scr, st, views, err);
         if (rc != SA_OK) return rc;
         hipLaunchKernelGGL(k_contrib, dim3((unsigned)grid), dim3(kThreads), 0, st, views, s.n_nodes, s.voff, s.verts,
                            s.height, p.segs, (int)j0, j1, P, weight, (const int32_t *)s.order, s.n_b, contrib);

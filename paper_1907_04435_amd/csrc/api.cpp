@@ -494,7 +494,7 @@ sa_status sa_accumulate_batched(sa_ctx *ctx, const sa_scene *scene, int32_t n_va
     std::string err;
     rc = sa::launch_batched(scene->d, path->d, n_var, ids_per_var, var_ids, var_h, view(pts), var_off, scale,
                             counts, minutes, opts->grid_blocks, ctx->spill.counters + 2, ctx->scratch_batched,
-                            ctx->stream, err);
+                            ctx->scratch_seg, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate_batched: " + err);
     return SA_OK;
 }

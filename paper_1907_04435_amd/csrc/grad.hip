@@ -208,7 +208,7 @@ sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsVie
     for (int64_t j0 = 0; j0 < p.n_segs; j0 += per) {
         const int j1 = (int)std::min<int64_t>(j0 + per, p.n_segs);
         SegNode *views;
-        rc = build_seg_views(s, p, (int)j0, j1, scr, st, views, err);
+        rc = build_seg_views(s, p, (int)j0, j1, s.n_nodes, scr, st, views, err);
         if (rc != SA_OK) return rc;
         hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, st, q.counters);
         SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};

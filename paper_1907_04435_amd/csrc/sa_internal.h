@@ -142,17 +142,17 @@ sa_status launch_contribution(const DeviceScene &s, const DevicePath &p, const P
                               const float *weight, double *contrib, Scratch &scr, hipStream_t st,
                               std::string &err);
 // Per-segment node views (SegNode) of segments [j0, j1) into scr (grown as
-// needed, with the stream synchronised first); views = nullptr for an
-// empty scene.  seg_views_cap: segments whose views fit the per-launch
+// needed, with the stream synchronised first), segment j's views at
+// (j - j0) * stride; views = nullptr for an empty scene.  seg_views_cap: segments whose views fit the per-launch
 // budget.
-sa_status build_seg_views(const DeviceScene &s, const DevicePath &p, int j0, int j1, Scratch &scr, hipStream_t st,
-                          SegNode *&views, std::string &err);
+sa_status build_seg_views(const DeviceScene &s, const DevicePath &p, int j0, int j1, int64_t stride, Scratch &scr,
+                          hipStream_t st, SegNode *&views, std::string &err);
 int64_t seg_views_cap(const DeviceScene &s);
 sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_var, int32_t k,
                          const int32_t *ids, const float *h, const PointsView &pts,
                          const int64_t *var_off, float scale, int32_t *counts, float *minutes,
-                         int32_t grid_blocks, uint32_t *flag, Scratch &scr, hipStream_t st,
-                         std::string &err);
+                         int32_t grid_blocks, uint32_t *flag, Scratch &scr, Scratch &views_scr,
+                         hipStream_t st, std::string &err);
 // Graph-capturable fill of n 32-bit words.
 sa_status fill_u32(void *p, int64_t n, uint32_t v, hipStream_t st, std::string &err);
 

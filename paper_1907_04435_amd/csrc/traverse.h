@@ -959,13 +959,14 @@ __device__ __forceinline__ void seg_child(const FanGeom &f, float x0, float y0, 
 // loop (each such flag costs scalar merges with the exec mask at every
 // iteration).  All leaf handling sits behind one branch, taken only at
 // nodes with a leaf child.
+// `root` is the byte offset of the view the walk starts at.
 template <bool kCount, class LeafFn>
 __device__ __forceinline__ void packet_traverse_seg(cSegNode *nodes, cint *voff, StackEntry *stack, uint64_t alive,
-                                                    const SegFan &ft, LeafFn leaf, Work &w)
+                                                    const SegFan &ft, LeafFn leaf, Work &w, int root = 0)
 {
     typedef __attribute__((address_space(4))) const char cchar;
     uint64_t cur = alive;
-    int sp = 0, node = 0;  // byte offset of the current view
+    int sp = 0, node = root;  // byte offset of the current view
     while (cur) {
         const SegNode nd = ld((cSegNode *)((cchar *)nodes + (uint32_t)node));
         if constexpr (kCount) {

@@ -113,3 +113,35 @@ def test_batched_graph_replay(ctx, c3small):
         assert np.array_equal(mins.cpu().numpy(), mb), f"replay {r}"
         assert np.array_equal(counts.cpu().numpy(), cb), f"replay {r}"
         _ = (torch.ones(1000, device="cuda") * r).sum().item()   # eager work between replays
+
+
+def test_batched_over_several_view_launches(ctx):
+    """Twelve days (the 21st of each month) for three variants of 2,000
+    points: the segments' views (base plus each variant's copies of its
+    changed nodes) exceed one launch's 256 MiB budget, so the batched
+    kernel runs over several segment ranges.  Equal to evaluating each
+    variant on the edited scene."""
+    import datetime as dt
+    from workloads import Span
+    from workloads.scenes import Day, _nyc_tz
+    w = make_c3(n_var=3, n_per_var=2000, seed=7)
+    days = [dt.date(2019, m, 21) for m in range(1, 13)]
+    span = Span(40.7, -74.0, [Day(d.year, d.month, d.day, _nyc_tz(d)) for d in days], 1.0)
+    sp = sa.sunpath_for_span(span, 30.0)
+    assert (len(sp.knot_t) - sp.n_days) * (w.scene.n_b - 1) * 64 > 256 << 20
+    path = sa.Path(ctx, sp)
+    cb, mb, _ = run_batched(ctx, w, path=path)
+    off = w.extra["var_off"]
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    for v in range(len(off) - 1):
+        sc.set_heights(w.extra["var_ids"][v], w.extra["var_h"][v])
+        sub = w.points.take(np.arange(off[v], off[v + 1]))
+        c, m, _ = sa.accumulate(ctx, sc, sa.DevicePoints.from_workload(sub), path, sa.SA_ACCRUAL)
+        ctx.sync()
+        c, m = c.cpu().numpy(), m.cpu().numpy()
+        sc.set_heights(w.extra["var_ids"][v], w.scene.height[w.extra["var_ids"][v]])
+        dm = np.abs(m - mb[:, off[v]:off[v + 1]])
+        say(f"12 days, variant {v}: max |dmin| {dm.max():.2e}")
+        assert m.shape == (12, sub.n)
+        assert dm.max() <= 2e-3
+        assert (c != cb[:, off[v]:off[v + 1]]).mean() <= 1e-4
