@@ -424,10 +424,8 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
             lov = lane_in(take_lo) ? cv : lov;
             hiu = lane_in(take_hi) ? cu : hiu;
             hiv = lane_in(take_hi) ? cv : hiv;
-            if constexpr (kGrad) {
-                dlo = lane_in(take_lo) ? dc : dlo;
-                dhi = lane_in(take_hi) ? dc : dhi;
-            }
+            dlo = lane_in(take_lo) ? dc : dlo;
+            dhi = lane_in(take_hi) ? dc : dhi;
             have |= ok;
         };
         // footprint vertex k relative to p: world offset (wx, wy), in-plane
@@ -440,34 +438,51 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
             v = fmaf(g.m10, wx, g.m11 * wy);
             z = fmaf(g.e1z, u, g.e2z * v);
         };
-        float pwx, pwy, pu, pv, pzv;
-        vertex(0, pwx, pwy, pu, pv, pzv);
-        uint64_t pin = le_mask(pzv, h);
-        cand(pu, pv, 0.f, pin);
-        // edge e runs from vertex e - 1 to vertex e mod m; vertex 0 is read
-        // again for the closing edge rather than kept in registers
-        for (int e = 1; e <= m; ++e) {
-            float wx, wy, u, v, z;
-            vertex(e == m ? 0 : e, wx, wy, u, v, z);
-            const uint64_t in = le_mask(z, h);
-            inside &= ge_mask(cross2(pwx, pwy, wx, wy), 0.f);
-            const uint64_t crossing = (pin ^ in) & ballot(true);
+        // edge from vertex A to vertex B (world offsets, in-plane
+        // coordinates, plane heights, below-roof masks)
+        auto edge = [&](float awx, float awy, float au, float av, float az, uint64_t ain, float bwx, float bwy,
+                        float bu, float bv, float bz, uint64_t bin) {
+            inside &= ge_mask(cross2(awx, awy, bwx, bwy), 0.f);
+            const uint64_t crossing = (ain ^ bin) & ballot(true);
             if (crossing) {
-                const float rdz = __builtin_amdgcn_rcpf(z - pzv);
-                const float t = (h - pzv) * rdz;
-                const float cu = fmaf(t, u - pu, pu), cv = fmaf(t, v - pv, pv);
-                float dc = 0.f;
-                if constexpr (kGrad) dc = cross2(cu, cv, u - pu, v - pv) * rdz * __builtin_amdgcn_rcpf(fmaf(cu, cu, cv * cv));
+                const float rdz = __builtin_amdgcn_rcpf(bz - az);
+                const float t = (h - az) * rdz;
+                const float cu = fmaf(t, bu - au, au), cv = fmaf(t, bv - av, av);
+                const float dc = cross2(cu, cv, bu - au, bv - av) * rdz * __builtin_amdgcn_rcpf(fmaf(cu, cu, cv * cv));
                 cand(cu, cv, dc, crossing);
             }
-            if (e < m) cand(u, v, 0.f, in);
-            pu = u;
-            pv = v;
-            pzv = z;
-            pwx = wx;
-            pwy = wy;
-            pin = in;
+        };
+        // two vertices per trip, as in the world-offset branch below
+        float awx, awy, au, av, az, bwx, bwy, bu, bv, bz;
+        vertex(0, awx, awy, au, av, az);
+        uint64_t ain = le_mask(az, h), bin;
+        cand(au, av, 0.f, ain);
+        int e = 1;
+        for (; e + 1 < m; e += 2) {
+            vertex(e, bwx, bwy, bu, bv, bz);
+            bin = le_mask(bz, h);
+            edge(awx, awy, au, av, az, ain, bwx, bwy, bu, bv, bz, bin);
+            cand(bu, bv, 0.f, bin);
+            vertex(e + 1, awx, awy, au, av, az);
+            const uint64_t nin = le_mask(az, h);
+            edge(bwx, bwy, bu, bv, bz, bin, awx, awy, au, av, az, nin);
+            cand(au, av, 0.f, nin);
+            ain = nin;
         }
+        if (e < m) {  // one vertex left before the closing edge
+            vertex(e, bwx, bwy, bu, bv, bz);
+            bin = le_mask(bz, h);
+            edge(awx, awy, au, av, az, ain, bwx, bwy, bu, bv, bz, bin);
+            cand(bu, bv, 0.f, bin);
+            awx = bwx;
+            awy = bwy;
+            au = bu;
+            av = bv;
+            az = bz;
+            ain = bin;
+        }
+        vertex(0, bwx, bwy, bu, bv, bz);
+        edge(awx, awy, au, av, az, ain, bwx, bwy, bu, bv, bz, le_mask(bz, h));
     } else {
         // Without derivatives the extremes are found in world offsets from p:
         // the map M into the segment plane is linear, so it keeps the angular
