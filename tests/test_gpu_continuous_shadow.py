@@ -143,3 +143,19 @@ def test_accrual_longest_over_several_view_launches(ctx):
         d = np.abs(g[k] - o[k]).ravel()
         say(f"  {k}: |GPU - oracle| mean {d.mean():.2e} p99.9 {np.quantile(d, 0.999):.2e} max {d.max():.2e}")
         assert np.quantile(d, 0.999) <= 0.01 and d.mean() <= 1e-3
+
+
+def test_sampled_longest_block_scene(ctx):
+    """Block scene (20k prisms), three days at 1-minute instants: the
+    sampled form's longest run must be the definition applied to its own
+    predicate bits (whose parity with the oracle is tested elsewhere)."""
+    w = make_c2(n_ground=20_000, n_facade=20_000)
+    idx = np.concatenate([subset_points(w.points.take(np.arange(20_000)), 64, 31),
+                          20_000 + subset_points(w.points.take(np.arange(20_000, 40_000)), 64, 32)])
+    sub = w.points.take(idx)
+    g = run(ctx, w.scene, sub, w.span, sa.SA_SAMPLED, bits=True)
+    ref = oracle.longest_sampled(g["bits"].astype(bool), oracle.sun_path(w.span))
+    d = np.abs(g["longest"] - ref)
+    say(f"sampled longest, block scene: max |GPU - definition| {d.max():.2e}, mean longest {ref.mean():.1f}")
+    np.testing.assert_allclose(g["longest"], ref, rtol=1e-6, atol=1e-3)
+    assert (ref > 60).mean() > 0.2
