@@ -78,3 +78,17 @@ def test_context_needs_a_device():
         pytest.skip("a HIP device is present")
     with pytest.raises(RuntimeError):
         sa.Context(0)
+
+
+def test_c_consumer_links_against_the_library():
+    """tests/c_consumer.c, a plain C99 program using only the header (built
+    with -Wall -Wextra -Werror by the build step), links against libsa.so
+    and the HIP runtime, and every shared library it needs resolves."""
+    import subprocess
+    exe = os.path.join(ROOT, "tests", "_bin", "c_consumer")
+    if not os.path.exists(exe):
+        import c_consumer_build
+        c_consumer_build.build()
+    r = subprocess.run(["ldd", exe], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    assert "libsa.so" in r.stdout and "not found" not in r.stdout, r.stdout
