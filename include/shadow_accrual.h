@@ -89,9 +89,12 @@ const char *sa_version(void);
 /* scene: buildings as extruded convex prisms (a city model, Sec. 8.2) */
 /* ------------------------------------------------------------------ */
 
-/* Upload n_b prisms from host arrays: vert_off [n_b+1] (CSR offsets into
- * xy), xy [2*vert_off[n_b]] (x, y pairs, counter-clockwise, convex, >= 3
- * vertices), height [n_b] (> 0).  Builds the bounding-volume hierarchy on
+/* Upload n_b prisms from arrays vert_off [n_b+1] (CSR offsets into xy),
+ * xy [2*vert_off[n_b]] (x, y pairs, counter-clockwise, convex, >= 3
+ * vertices), height [n_b] (> 0).  Each array may be host or device memory
+ * (told apart by the runtime's pointer attributes; device arrays are read
+ * through a host copy for validation); all are copied in, the caller keeps
+ * ownership.  Builds the bounding-volume hierarchy on
  * the device (Morton codes of footprint centres, radix sort, binary radix
  * tree, bottom-up box refit).  Host-synchronous.  n_b == 0 is an empty
  * scene (nothing casts shadow); at most 2^25 prisms.  Errors: INVALID_ARG,

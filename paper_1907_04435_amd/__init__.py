@@ -249,16 +249,31 @@ class Context:
             pass
 
 
+def _host_or_device(a, np_dtype, torch_dtype):
+    """(pointer, object to keep alive, length) of a flat array: a numpy
+    array (host) or a device tensor, converted to the given element type."""
+    if getattr(a, "is_cuda", False):
+        t = a.to(torch_dtype).contiguous().reshape(-1)
+        return C.c_void_p(t.data_ptr()), t, int(t.numel())
+    h = np.ascontiguousarray(a, np_dtype).reshape(-1)
+    return _ptr(h), h, len(h)
+
+
 class Scene:
+    """Prisms uploaded from host arrays or device tensors (vert_off int32
+    [n_b + 1], xy float32 [V, 2] or [2V], height float32 [n_b])."""
+
     def __init__(self, ctx: Context, vert_off, xy, height):
+        import torch
         self.ctx = ctx
-        vo = np.ascontiguousarray(vert_off, np.int32)
-        xy = np.ascontiguousarray(xy, np.float32).reshape(-1)
-        h = np.ascontiguousarray(height, np.float32)
+        pv, kv, _ = _host_or_device(vert_off, np.int32, torch.int32)
+        px, kx, _ = _host_or_device(xy, np.float32, torch.float32)
+        ph, kh, n_b = _host_or_device(height, np.float32, torch.float32)
         hd = C.c_void_p()
-        _check(ctx, lib().sa_scene_upload(ctx.handle, len(h), _ptr(vo), _ptr(xy), _ptr(h), C.byref(hd)))
+        _check(ctx, lib().sa_scene_upload(ctx.handle, n_b, pv, px, ph, C.byref(hd)))
+        del kv, kx, kh
         self.handle = hd
-        self.n_b = len(h)
+        self.n_b = n_b
 
     @classmethod
     def from_workload(cls, ctx, scene):

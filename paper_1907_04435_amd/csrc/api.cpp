@@ -60,6 +60,33 @@ bool set_device(sa_ctx *ctx)
 
 }  // namespace
 
+namespace {
+
+// Is p device memory (as opposed to host memory the CPU can read)?
+static bool on_device(const void *p)
+{
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();  // plain host memory on some runtimes
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice && !a.isManaged;
+}
+
+// A host-readable copy of n elements at p: p itself for host memory, else
+// the elements copied into `stash`.
+template <class T>
+static const T *host_view(const T *p, size_t n, std::vector<T> &stash, hipError_t &e)
+{
+    e = hipSuccess;
+    if (n == 0 || !on_device(p)) return p;
+    stash.resize(n);
+    e = hipMemcpy(stash.data(), p, sizeof(T) * n, hipMemcpyDeviceToHost);
+    return stash.data();
+}
+
+}  // namespace
+
 extern "C" {
 
 const char *sa_version(void) { return "libsa 0.1 (gfx950)"; }
@@ -132,14 +159,27 @@ sa_status sa_sync(sa_ctx *ctx)
 }
 
 // ------------------------------------------------------------------ scene
-sa_status sa_scene_upload(sa_ctx *ctx, int32_t n_b, const int32_t *vert_off, const float *xy,
-                          const float *height, sa_scene **out)
+sa_status sa_scene_upload(sa_ctx *ctx, int32_t n_b, const int32_t *vert_off_in, const float *xy_in,
+                          const float *height_in, sa_scene **out)
 {
     if (!ctx || !out) return SA_ERR_INVALID_ARG;
     *out = nullptr;
-    if (n_b < 0 || (n_b > 0 && (!vert_off || !xy || !height)))
+    if (n_b < 0 || (n_b > 0 && (!vert_off_in || !xy_in || !height_in)))
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_scene_upload: bad arguments");
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    // host or device arrays: device ones are read through host copies
+    std::vector<int32_t> off_h;
+    std::vector<float> xy_h, h_h;
+    hipError_t he = hipSuccess;
+    const int32_t *vert_off = n_b > 0 ? host_view(vert_off_in, (size_t)n_b + 1, off_h, he) : vert_off_in;
+    if (he != hipSuccess) return hip_fail(ctx, he, "sa_scene_upload: reading vert_off");
     if (n_b > 0 && vert_off[0] != 0) return fail(ctx, SA_ERR_INVALID_ARG, "sa_scene_upload: vert_off[0] != 0");
+    if (n_b > 0 && vert_off[n_b] < 3 * (int64_t)n_b)
+        return fail(ctx, SA_ERR_GEOMETRY, "sa_scene_upload: fewer than 3 vertices per prism");
+    const float *xy = n_b > 0 ? host_view(xy_in, 2 * (size_t)vert_off[n_b], xy_h, he) : xy_in;
+    if (he != hipSuccess) return hip_fail(ctx, he, "sa_scene_upload: reading xy");
+    const float *height = n_b > 0 ? host_view(height_in, (size_t)n_b, h_h, he) : height_in;
+    if (he != hipSuccess) return hip_fail(ctx, he, "sa_scene_upload: reading height");
     // the accrual traversal addresses per-segment node views (64 bytes
     // each) with 32-bit byte offsets
     if (n_b > (1 << 25)) return fail(ctx, SA_ERR_CAPACITY, "sa_scene_upload: more than 2^25 prisms");

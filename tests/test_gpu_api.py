@@ -86,3 +86,29 @@ def test_batched_bad_variant_reported_at_sync(ctx, setup, c1):
         ctx.sync()
     assert e.value.code == -1
     ctx.sync()                                                # cleared
+
+
+def test_scene_upload_from_device_arrays(ctx, c1):
+    """The scene arrays may live in device memory: the hierarchy and the
+    results equal those of the same scene uploaded from host arrays."""
+    import torch
+    host = sa.Scene.from_workload(ctx, c1.scene)
+    dev = sa.Scene(ctx, torch.from_numpy(c1.scene.vert_off.astype(np.int32)).cuda(),
+                   torch.from_numpy(np.ascontiguousarray(c1.scene.xy, np.float32)).cuda(),
+                   torch.from_numpy(c1.scene.height.astype(np.float32)).cuda())
+    nh, oh = host.read_bvh()
+    nd, od = dev.read_bvh()
+    assert np.array_equal(nh, nd) and np.array_equal(oh, od)
+    sub = c1.points.take(np.arange(0, c1.points.n, 97))
+    dp = sa.DevicePoints.from_workload(sub)
+    path = sa.Path(ctx, sa.sunpath_for_span(c1.span, 30.0))
+    a = sa.accumulate(ctx, host, dp, path, sa.SA_ACCRUAL)[1]
+    b = sa.accumulate(ctx, dev, dp, path, sa.SA_ACCRUAL)[1]
+    ctx.sync()
+    assert torch.equal(a, b)
+    bad = torch.from_numpy(c1.scene.height.astype(np.float32)).cuda()
+    bad[3] = -1.0                                           # validated through the host copy
+    with pytest.raises(sa.SAError) as e:
+        sa.Scene(ctx, torch.from_numpy(c1.scene.vert_off.astype(np.int32)).cuda(),
+                 torch.from_numpy(np.ascontiguousarray(c1.scene.xy, np.float32)).cuda(), bad)
+    assert e.value.code == -2
