@@ -6,7 +6,6 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <type_traits>
 
 #include "sa_internal.h"
 #include "traverse.h"
@@ -174,20 +173,17 @@ __device__ __forceinline__ void measure(const Union4 &U, const SegConst &g, floa
 // The occluded set of every live lane's point over its window of segment g:
 // back-face term, then the packet fan traversal.  On return `ov` marks
 // lanes whose set needed more than four pieces.
-// Where a traversal reads the hierarchy: the nodes as built (the full fan
-// test at every child) or the views of the current segment (SegFan: seven
-// compares per child).
-struct TreeSrc {
-    cNode *nodes;
-};
+// The hierarchy as seen from the current segment: its per-segment node
+// views (SegFan: seven compares per child), the vertex offsets of the
+// leaves, and the view the walk starts at.
 struct SegSrc {
     cSegNode *nodes;
     cint *voff;
     int root;  // byte offset of the root's view
 };
 
-template <bool kCount, class Src>
-__device__ __forceinline__ void accrue_segment(Src src, StackEntry *stack, cfloat4 *verts, cfloat *height,
+template <bool kCount>
+__device__ __forceinline__ void accrue_segment(SegSrc src, StackEntry *stack, cfloat4 *verts, cfloat *height,
                                                const SegConst &g, const LanePoint &q, bool active, float w0,
                                                float w1, Union4 &U, bool &ov, Work &wk)
 {
@@ -231,17 +227,9 @@ __device__ __forceinline__ void accrue_segment(Src src, StackEntry *stack, cfloa
         ovm |= om;
         return om | ballot(full);
     };
-    if constexpr (std::is_same<Src, SegSrc>::value) {
-        const SegFan ft(g, q.px, q.py, q.pz);
-        packet_traverse_seg<kCount>(src.nodes, src.voff, stack, ballot(live), ft, leaf_m, wk, src.root);
-        ov = lane_in(ovm);
-    } else {
-        const FanTest bt(g, q.px, q.py, q.pz);
-        const float mdx = g.mdx, mdy = g.mdy;
-        auto key = [&](float x0, float y0, float x1, float y1, float z1) { return seg_key(x0, y0, x1, y1, mdx, mdy); };
-        packet_traverse<kCount>(src.nodes, stack, ballot(live), bt, leaf_m, key, wk);
-        ov = lane_in(ovm);
-    }
+    const SegFan ft(g, q.px, q.py, q.pz);
+    packet_traverse_seg<kCount>(src.nodes, src.voff, stack, ballot(live), ft, leaf_m, wk, src.root);
+    ov = lane_in(ovm);
 }
 
 // The view of node `nd` for segment g, with child references r0 (left)

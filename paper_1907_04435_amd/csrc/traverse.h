@@ -827,51 +827,14 @@ __device__ __forceinline__ float seg_key(float x0, float y0, float x1, float y1,
     return fmaf(x0 + x1, mdx, (y0 + y1) * mdy);
 }
 
-struct FanTest {
-    float umnx, umxx, umny, umxy;
-    float axp, axm, ayp, aym, bxp, bxm, byp, bym;
-    float naP, nbP, px, py, pz;
-
-    __device__ __forceinline__ FanTest(const SegConst &g, float px_, float py_, float pz_)
-    {
-        px = px_;
-        py = py_;
-        pz = pz_;
-        const FanGeom f = fan_geom(g);
-        umnx = f.umnx;
-        umxx = f.umxx;
-        umny = f.umny;
-        umxy = f.umxy;
-        axp = fmaxf(f.nax, 0.f);
-        axm = fminf(f.nax, 0.f);
-        ayp = fmaxf(f.nay, 0.f);
-        aym = fminf(f.nay, 0.f);
-        bxp = fmaxf(f.nbx, 0.f);
-        bxm = fminf(f.nbx, 0.f);
-        byp = fmaxf(f.nby, 0.f);
-        bym = fminf(f.nby, 0.f);
-        naP = fmaf(f.nax, px, f.nay * py);
-        nbP = fmaf(f.nbx, px, f.nby * py);
-    }
-
-    __device__ __forceinline__ uint64_t operator()(float x0, float y0, float x1, float y1, float z1) const
-    {
-        const float ra = z1 - pz;
-        const float xlo = fmaf(ra, umnx, px), xhi = fmaf(ra, umxx, px);
-        const float ylo = fmaf(ra, umny, py), yhi = fmaf(ra, umxy, py);
-        const float ka = fmaf(y0, aym, fmaf(y1, ayp, fmaf(x0, axm, x1 * axp)));
-        const float kb = fmaf(y0, bym, fmaf(y1, byp, fmaf(x0, bxm, x1 * bxp)));
-        return ge_mask(ra, 0.f) & ge_mask(x1, xlo) & le_mask(x0, xhi) & ge_mask(y1, ylo) & le_mask(y0, yhi) &
-               ge_mask(ka, naP) & ge_mask(kb, nbP);
-    }
-};
-
 // ---- the accrual fan test on per-segment node views ----
 //
-// FanTest spends most of its arithmetic on values that are the same for
-// every lane (the wedge projections of the box, the box shifted by the
-// per-metre reach).  CDNA has no scalar floating point, so those values
-// cost full vector instructions at every node visit.  Moving the lane's
+// A direct fan test of a child box (the wedge edges' box_reach against
+// each lane's n . p, and the box against the fan's bounding box, whose
+// corners move with the box top by the per-metre reach) spends most of its
+// arithmetic on values that are the same for every lane.  CDNA has no
+// scalar floating point, so those values would cost full vector
+// instructions at every node visit.  Moving the lane's
 // terms to the other side of each inequality,
 //   x1 >= px + (z1 - pz) umnx   <=>   x1 - z1 umnx >= px - pz umnx,
 // leaves one side that depends only on (segment, box), computed once per
@@ -944,7 +907,7 @@ struct SegFan {
 
 // The box-only side of SegFan's inequalities for one child box.  The
 // shifted edges are formed in double and rounded outward; the wedge
-// projections use FanTest's expression.  An absent child gets a box no
+// projections are box_reach.  An absent child gets a box no
 // lane passes.
 __device__ __forceinline__ void seg_child(const FanGeom &f, float x0, float y0, float x1, float y1, float z1,
                                           bool present, float *c)
