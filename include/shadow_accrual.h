@@ -52,7 +52,7 @@ typedef int32_t sa_status;
 #define SA_ERR_CAPACITY (-3)     /* a fixed-size structure overflowed (BVH depth, spill queue) */
 #define SA_ERR_OOM (-4)          /* device allocation failed */
 #define SA_ERR_DEVICE (-5)       /* HIP runtime error */
-#define SA_ERR_UNSUPPORTED (-6)  /* e.g. a sun-path plane too close to vertical */
+#define SA_ERR_UNSUPPORTED (-6)  /* a request the library does not handle */
 
 #define SA_SAMPLED 0
 #define SA_ACCRUAL 1
@@ -179,7 +179,7 @@ sa_status sa_sunpath(const sa_site *site, const sa_timespan *span, sa_sunpath_bu
  * knots spanning its samples) for use by accumulate calls.  Precomputes,
  * in FP64 on the host, each segment's plane, basis and angle.  Bins:
  * in->day_bin (or bin = day); n_bins = 1 + max bin.  Errors: INVALID_ARG,
- * UNSUPPORTED (a segment whose plane is within 3 degrees of vertical), OOM. */
+ * OOM. */
 sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out);
 sa_status sa_path_info(const sa_path *path, int32_t *n_bins, int32_t *n_samples,
                        int32_t *n_segments);

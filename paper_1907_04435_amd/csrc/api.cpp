@@ -355,15 +355,16 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
             for (double &v : e2) v /= l2;
             const double N[3] = {a[1] * e2[2] - a[2] * e2[1], a[2] * e2[0] - a[0] * e2[2],
                                  a[0] * e2[1] - a[1] * e2[0]};
-            if (std::fabs(N[2]) < std::sin(3.0 * M_PI / 180.0))
-                return fail(ctx, SA_ERR_UNSUPPORTED, "sa_path_upload: a segment plane is within 3 deg of vertical");
-            const double cx = N[0] / N[2], cy = N[1] / N[2];
+            // the lift of horizontal offsets into the plane, times |nz|:
+            // |nz| (a - a_z N_xy / nz) = |nz| a - sgn(nz) a_z N_xy
+            const double anz = std::fabs(N[2]), sg = N[2] < 0.0 ? -1.0 : 1.0;
             sa::SegConst g;
             std::memset(&g, 0, sizeof(g));
-            g.m00 = (float)(a[0] - a[2] * cx);
-            g.m01 = (float)(a[1] - a[2] * cy);
-            g.m10 = (float)(e2[0] - e2[2] * cx);
-            g.m11 = (float)(e2[1] - e2[2] * cy);
+            g.m00 = (float)(anz * a[0] - sg * a[2] * N[0]);
+            g.m01 = (float)(anz * a[1] - sg * a[2] * N[1]);
+            g.m10 = (float)(anz * e2[0] - sg * e2[2] * N[0]);
+            g.m11 = (float)(anz * e2[1] - sg * e2[2] * N[1]);
+            g.steep = anz < std::sin(5.0 * M_PI / 180.0) ? 1 : 0;
             g.e1z = (float)a[2];
             g.e2z = (float)e2[2];
             g.theta = (float)theta;

@@ -40,10 +40,12 @@ constexpr int32_t kBinMask = kDayStart - 1;
 // the direction at angle phi from the first knot is
 // cos(phi) e1 + sin(phi) e2, phi in [0, theta], reached at time
 // t = ta + dt * phi / theta.  An xy offset w from a point maps to the
-// point of the plane above/below it, whose in-plane coordinates are
-// (u, v) = M w and whose height above the point is u * e1z + v * e2z.
+// point of the plane above/below it, whose in-plane coordinates times
+// |nz| (n = e1 x e2) are (u, v) = M w, and whose height above the point
+// times |nz| is u * e1z + v * e2z (the factor keeps M bounded for planes
+// through the zenith; directions are unchanged by it).
 struct alignas(64) SegConst {
-    float m00, m01, m10, m11;    // M
+    float m00, m01, m10, m11;    // M (scaled by |nz|)
     float e1z, e2z, theta, dt;   // clip normal (u,v)->z, angle, minutes
     float ta;                    // start, minutes after local midnight
     float cth, sth;              // (cos theta, sin theta): end direction in (u, v)
@@ -55,7 +57,7 @@ struct alignas(64) SegConst {
     float s0;                    // first sample instant in the segment, minutes after ta
     float step;                  // sample spacing (minutes)
     int32_t ns;                  // sample instants attributed to the segment
-    int32_t pad0;
+    int32_t steep;               // plane within 5 degrees of vertical: in-plane extreme search
     float rate;                  // dt / theta: minutes per radian
     float inv_step;              // 1 / step
     float mdx, mdy;              // horizontal part of the direction at theta / 2 (visit order)

@@ -392,18 +392,27 @@ __device__ __forceinline__ float cross2(float au, float av, float bu, float bv)
 
 // Occluded angle interval of one prism over the window [w0, w1] of a
 // segment, for a point at p.  In the segment's plane through p the prism
-// is a convex polygon: the footprint (mapped by M to in-plane (u, v))
+// is a convex polygon: the footprint lifted vertically into the plane and
 // clipped to heights <= H.  The directions from p that meet it form one
 // angular interval of span < pi (p is outside); its ends are found by
 // cross products over the clipped polygon's vertices (the kept footprint
 // vertices and the two clip crossings), and intersected with the window.
 // Returns 0: no overlap, 1: [a, b] written.
 //
+// The lift of a horizontal offset w into the plane divides by the plane
+// normal's vertical part nz, which vanishes for a plane through the
+// zenith.  Only directions from p matter, so the segment's map M (and the
+// heights it gives) carries the factor |nz|: vertices stay bounded for
+// every plane, and the clip compares scaled heights with |nz| (H - pz).
+// A clip crossing lies at height H - pz itself, so its in-plane point is
+// formed directly from its world offset c as (e1 . (c, H - pz),
+// e2 . (c, H - pz)), which has no cancellation when nz is small.
+//
 // With kGrad, da / db receive d(a)/dH and d(b)/dH: an end at a clip
-// crossing c = c0 + t (c1 - c0), t = (h - z0) / (z1 - z0), moves with the
-// roof as dc/dH = (c1 - c0) / (z1 - z0), so d(angle)/dH =
-// cross(c, c1 - c0) / (|c|^2 (z1 - z0)); ends at footprint vertices
-// (vertical edges) or clamped to the window do not move.
+// crossing moves with the roof along the lifted edge, dc/dH = (c1 - c0) /
+// (z1 - z0) (the scale cancels), so d(angle)/dH = cross(c, c1 - c0) /
+// (|c|^2 (z1 - z0)); ends at footprint vertices (vertical edges) or
+// clamped to the window do not move.
 template <bool kGrad>
 __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, float H, float px, float py,
                                               float pz, const SegConst &g, float w0, float w1, float W0u,
@@ -411,12 +420,15 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
                                               float &db)
 {
     const float h = H - pz;
+    const float hs = h * fabsf(g.nz);  // the clip height in the scaled plane
     float lou = 0.f, lov = 0.f, hiu = 0.f, hiv = 0.f, dlo = 0.f, dhi = 0.f;
     // Lane masks (scalar registers) for the per-lane flags: which lanes have
     // a candidate yet, which see the footprint from inside every edge, which
     // vertices are below the roof line.  Only the selects are vector work.
     uint64_t have = 0, inside = ~0ull;
-    if constexpr (kGrad) {
+    if (kGrad || g.steep) {
+        // extremes tracked in in-plane coordinates (derivatives, or a plane
+        // too close to vertical for the world-offset shortcut below)
         auto cand = [&](float cu, float cv, float dc, uint64_t ok) {
             const uint64_t take_lo = ok & (~have | lt_mask(cross2(lou, lov, cu, cv), 0.f));
             const uint64_t take_hi = ok & (~have | gt_mask(cross2(hiu, hiv, cu, cv), 0.f));
@@ -424,12 +436,15 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
             lov = lane_in(take_lo) ? cv : lov;
             hiu = lane_in(take_hi) ? cu : hiu;
             hiv = lane_in(take_hi) ? cv : hiv;
-            dlo = lane_in(take_lo) ? dc : dlo;
-            dhi = lane_in(take_hi) ? dc : dhi;
+            if constexpr (kGrad) {
+                dlo = lane_in(take_lo) ? dc : dlo;
+                dhi = lane_in(take_hi) ? dc : dhi;
+            }
             have |= ok;
         };
-        // footprint vertex k relative to p: world offset (wx, wy), in-plane
-        // (u, v) and height z of the segment plane above p there
+        const float e1h = g.e1z * h, e2h = g.e2z * h;
+        // footprint vertex k relative to p: world offset (wx, wy), scaled
+        // in-plane (u, v) and scaled height z of the plane above p there
         auto vertex = [&](int k, float &wx, float &wy, float &u, float &v, float &z) {
             const float4 q = ld(verts + voff + k);
             wx = q.x - px;
@@ -438,40 +453,44 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
             v = fmaf(g.m10, wx, g.m11 * wy);
             z = fmaf(g.e1z, u, g.e2z * v);
         };
-        // edge from vertex A to vertex B (world offsets, in-plane
-        // coordinates, plane heights, below-roof masks)
+        // edge from vertex A to vertex B (world offsets, scaled in-plane
+        // coordinates and heights, below-roof masks)
         auto edge = [&](float awx, float awy, float au, float av, float az, uint64_t ain, float bwx, float bwy,
                         float bu, float bv, float bz, uint64_t bin) {
             inside &= ge_mask(cross2(awx, awy, bwx, bwy), 0.f);
             const uint64_t crossing = (ain ^ bin) & ballot(true);
             if (crossing) {
                 const float rdz = __builtin_amdgcn_rcpf(bz - az);
-                const float t = (h - az) * rdz;
-                const float cu = fmaf(t, bu - au, au), cv = fmaf(t, bv - av, av);
-                const float dc = cross2(cu, cv, bu - au, bv - av) * rdz * __builtin_amdgcn_rcpf(fmaf(cu, cu, cv * cv));
+                const float t = (hs - az) * rdz;
+                const float cx = fmaf(t, bwx - awx, awx), cy = fmaf(t, bwy - awy, awy);
+                const float cu = fmaf(g.e1x, cx, fmaf(g.e1y, cy, e1h));
+                const float cv = fmaf(g.e2x, cx, fmaf(g.e2y, cy, e2h));
+                float dc = 0.f;
+                if constexpr (kGrad)
+                    dc = cross2(cu, cv, bu - au, bv - av) * rdz * __builtin_amdgcn_rcpf(fmaf(cu, cu, cv * cv));
                 cand(cu, cv, dc, crossing);
             }
         };
         // two vertices per trip, as in the world-offset branch below
         float awx, awy, au, av, az, bwx, bwy, bu, bv, bz;
         vertex(0, awx, awy, au, av, az);
-        uint64_t ain = le_mask(az, h), bin;
+        uint64_t ain = le_mask(az, hs), bin;
         cand(au, av, 0.f, ain);
         int e = 1;
         for (; e + 1 < m; e += 2) {
             vertex(e, bwx, bwy, bu, bv, bz);
-            bin = le_mask(bz, h);
+            bin = le_mask(bz, hs);
             edge(awx, awy, au, av, az, ain, bwx, bwy, bu, bv, bz, bin);
             cand(bu, bv, 0.f, bin);
             vertex(e + 1, awx, awy, au, av, az);
-            const uint64_t nin = le_mask(az, h);
+            const uint64_t nin = le_mask(az, hs);
             edge(bwx, bwy, bu, bv, bz, bin, awx, awy, au, av, az, nin);
             cand(au, av, 0.f, nin);
             ain = nin;
         }
         if (e < m) {  // one vertex left before the closing edge
             vertex(e, bwx, bwy, bu, bv, bz);
-            bin = le_mask(bz, h);
+            bin = le_mask(bz, hs);
             edge(awx, awy, au, av, az, ain, bwx, bwy, bu, bv, bz, bin);
             cand(bu, bv, 0.f, bin);
             awx = bwx;
@@ -482,13 +501,14 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
             ain = bin;
         }
         vertex(0, bwx, bwy, bu, bv, bz);
-        edge(awx, awy, au, av, az, ain, bwx, bwy, bu, bv, bz, le_mask(bz, h));
+        edge(awx, awy, au, av, az, ain, bwx, bwy, bu, bv, bz, le_mask(bz, hs));
     } else {
         // Without derivatives the extremes are found in world offsets from p:
         // the map M into the segment plane is linear, so it keeps the angular
         // order of directions (reverses it when det M < 0), and only the two
-        // extremes are mapped at the end.  z, the plane's height above p at a
-        // footprint point, is linear in the offset too: z = Z1 wx + Z2 wy.
+        // extremes are mapped at the end.  z, the plane's (scaled) height
+        // above p at a footprint point, is linear in the offset too:
+        // z = Z1 wx + Z2 wy.
         const float Z1 = fmaf(g.e1z, g.m00, g.e2z * g.m10), Z2 = fmaf(g.e1z, g.m01, g.e2z * g.m11);
         float lox = 0.f, loy = 0.f, hix = 0.f, hiy = 0.f;
         auto cand = [&](float cx, float cy, uint64_t ok) {
@@ -512,7 +532,7 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
             inside &= ge_mask(cross2(ax, ay, bx, by), 0.f);
             const uint64_t crossing = (ain ^ bin) & ballot(true);
             if (crossing) {
-                const float t = (h - az) * __builtin_amdgcn_rcpf(bz - az);
+                const float t = (hs - az) * __builtin_amdgcn_rcpf(bz - az);
                 cand(fmaf(t, bx - ax, ax), fmaf(t, by - ay, ay), crossing);
             }
         };
@@ -521,23 +541,23 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
         // back to vertex 0 adds no vertex candidate.
         float ax, ay, az, bx, by, bz;
         vertex(0, ax, ay, az);
-        uint64_t ain = le_mask(az, h), bin;
+        uint64_t ain = le_mask(az, hs), bin;
         cand(ax, ay, ain);
         int e = 1;
         for (; e + 1 < m; e += 2) {
             vertex(e, bx, by, bz);
-            bin = le_mask(bz, h);
+            bin = le_mask(bz, hs);
             edge(ax, ay, az, ain, bx, by, bz, bin);
             cand(bx, by, bin);
             vertex(e + 1, ax, ay, az);
-            const uint64_t nin = le_mask(az, h);
+            const uint64_t nin = le_mask(az, hs);
             edge(bx, by, bz, bin, ax, ay, az, nin);
             cand(ax, ay, nin);
             ain = nin;
         }
         if (e < m) {  // one vertex left before the closing edge
             vertex(e, bx, by, bz);
-            bin = le_mask(bz, h);
+            bin = le_mask(bz, hs);
             edge(ax, ay, az, ain, bx, by, bz, bin);
             cand(bx, by, bin);
             ax = bx;
@@ -546,7 +566,7 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
             ain = bin;
         }
         vertex(0, bx, by, bz);
-        edge(ax, ay, az, ain, bx, by, bz, le_mask(bz, h));
+        edge(ax, ay, az, ain, bx, by, bz, le_mask(bz, hs));
         const bool flip = fmaf(g.m00, g.m11, -g.m01 * g.m10) < 0.f;
         const float fx = flip ? hix : lox, fy = flip ? hiy : loy;
         const float gx = flip ? lox : hix, gy = flip ? loy : hiy;

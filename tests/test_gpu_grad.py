@@ -42,6 +42,23 @@ def test_grad_c1_matches_oracle(ctx, c1):
     assert np.all(g >= -1e-4 * np.abs(o).max())          # taller never shades less
 
 
+def test_grad_near_vertical_planes(ctx, c1):
+    """The small scene at the equator on the equinox: every segment plane is
+    within 0.2 degrees of vertical (the steep-plane extreme search, clip
+    crossings formed directly in the plane).  Against the oracle."""
+    from workloads.scenes import Day
+    span = Span(-0.2, -78.5, [Day(2019, 3, 20, -5.0)], 5.0)
+    sub = c1.points.take(subset_points(c1.points, 512, 33))
+    g = gpu_grad(ctx, c1.scene, sub, span, 30.0)
+    o = oracle.grad_implicit(c1.scene, sub, oracle.sun_path(span, 30.0))
+    big = np.abs(o) > 0.05 * np.abs(o).max()
+    rel = np.abs(g - o)[big] / np.abs(o)[big]
+    say(f"equator grad: {big.sum()} buildings, rel err max {rel.max():.2e} median {np.median(rel):.2e}")
+    assert big.sum() >= 5
+    assert rel.max() <= 1e-3
+    assert np.abs(g - o)[~big].max() <= 1e-3 * np.abs(o).max()
+
+
 def test_grad_weighted_by_upstream(ctx, c1):
     """dl_dmin scales each point-day's contribution linearly."""
     import torch

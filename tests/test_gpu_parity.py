@@ -219,3 +219,34 @@ def test_full_size_c2_sampled_outputs(ctx):
     d = np.abs(ma.cpu().numpy()[:, idx] - oc["minutes"])
     say(f"full C2 sampled points: ambiguous {na.sum()}, accrual |A-D_L| max {d.max():.2e}")
     assert np.quantile(d, 0.999) <= 0.01 and d.max() <= 0.5
+
+
+@pytest.mark.parametrize("site", ["sydney_winter", "oslo_summer", "quito_equinox"])
+def test_other_sites_and_seasons(ctx, c1, site):
+    """The small scene under other skies: southern hemisphere in June (low
+    northern sun), 60 N at midsummer (an 18-hour day, sun low in the north
+    at both ends) and the equator at the equinox (the sun path through the
+    zenith's neighbourhood: segment planes within a fraction of a degree of
+    vertical).  Both forms against the oracle, sunrise to sunset at
+    5-minute instants."""
+    lat, lon, tz, day = {"sydney_winter": (-33.9, 151.2, 10.0, (2019, 6, 21)),
+                         "oslo_summer": (59.9, 10.7, 2.0, (2019, 6, 21)),
+                         "quito_equinox": (-0.2, -78.5, -5.0, (2019, 3, 20))}[site]
+    span = Span(lat, lon, [Day(day[0], day[1], day[2], tz)], 5.0)
+    sub = c1.points.take(subset_points(c1.points, 1024, seed=17))
+    # planes of the noon segments near the zenith: their vertical part
+    sp = sa.sunpath_for_span(span, 30.0)
+    kd = sp.knot_dir.reshape(-1, 3)
+    nz = np.abs(np.cross(kd[:-1], kd[1:])[:, 2]) / np.linalg.norm(np.cross(kd[:-1], kd[1:]), axis=1)
+    say(f"{site}: smallest |nz| of a segment plane {nz.min():.2e}")
+    if site == "quito_equinox":
+        assert nz.min() < np.sin(np.radians(1.0))     # the steep-plane path is exercised
+    g = run_lib(ctx, c1.scene, sub, span, sa.SA_SAMPLED, bits=True)
+    o = oracle.sampled(c1.scene, sub, oracle.sun_path(span), bits=True, amb=True)
+    frac, n_mism = check_sampled(g, o, oracle.sun_path(span).w)
+    say(f"{site}: {g['K']} instants, ambiguous {frac:.2e}, mismatched bits {n_mism}")
+    assert frac <= 1e-4
+    for seg in (30.0, 60.0):
+        ga = run_lib(ctx, c1.scene, sub, span, sa.SA_ACCRUAL, seg_min=seg)
+        oa = oracle.continuous(c1.scene, sub, oracle.sun_path(span, seg))
+        accrual_bar(ga, oa, f"  {site} L={seg}")
