@@ -542,15 +542,40 @@ __global__ __launch_bounds__(kThreads) void k_contrib(const SegNode *snodes_g, i
     const bool valid = i < P.n;
     const LanePoint q = load_point(P, i, valid);
     const float wt = valid ? (weight ? weight[i] : 1.f) : 0.f;
+    const bool active = valid & (wt != 0.f);
     Work none{0, 0, 0, 0, 0, 0, 0};
+    // Back-facing minutes go to the point's own building: kept per lane
+    // over the bin's segments and added once per bin, with one atomic for
+    // the wave when all its contributing lanes share the building (facade
+    // points come wall by wall, so they nearly always do).
+    double bf = 0.0;
+    int bin = j1 > j0 ? ld(segs + j0).bin : 0;
+    auto flush_backface = [&]() {
+        const uint64_t has = ballot(bf != 0.0);
+        if (!has) return;
+        const int lead = (int)__builtin_ctzll(has);
+        const int o0 = __shfl(q.own, lead, 64);
+        double *row = contrib + (int64_t)bin * n_b;
+        if (!ballot(bf != 0.0 && q.own != o0)) {
+            double s = bf;
+            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+            if (lane == lead) atomicAdd(&row[order[o0]], s);
+        } else if (bf != 0.0) {
+            atomicAdd(&row[order[q.own]], bf);
+        }
+        bf = 0.0;
+    };
     for (int j = j0; j < j1; ++j) {
         const SegConst g = ld(segs + j);
-        const bool active = valid & (wt != 0.f);
+        if (g.bin != bin) {
+            flush_backface();
+            bin = g.bin;
+        }
         double *row = contrib + (int64_t)g.bin * n_b;
         if (active && q.own >= 0) {
             float a, b;
             if (backface_interval(q.nx, q.ny, g, 0.f, g.theta, 1.f, 0.f, g.cth, g.sth, a, b))
-                atomicAdd(&row[order[q.own]], (double)((b - a) * g.rate * wt));
+                bf += (double)((b - a) * g.rate * wt);
         }
         if (snodes_g == nullptr) continue;
         const SegFan ft(g, q.px, q.py, q.pz);
@@ -571,6 +596,7 @@ __global__ __launch_bounds__(kThreads) void k_contrib(const SegNode *snodes_g, i
         packet_traverse_seg<false>((cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes), (cint *)voff_g, stack,
                                    ballot(active), ft, leaf, none);
     }
+    flush_backface();
 }
 
 // ------------------------------------------------------------------ batched
