@@ -243,11 +243,13 @@ typedef struct {
  * Results are deterministic except in the last bits of minutes for points
  * with a spilled point-segment (more than four pieces), whose measures are
  * added with float atomics in no fixed order.
- * SA_ACCRUAL without `longest` keeps a per-segment view of the hierarchy
- * (64 bytes per node and segment, at most 256 MiB; longer paths run as
- * several launches) in memory the context owns: grown on first need with
- * the stream synchronised, kept until sa_destroy.  Under stream capture
- * make one eager call of the same (or a larger) size first.
+ * The accrual form (here, and in sa_accumulate_batched, sa_grad_heights
+ * and sa_building_contribution) keeps a per-segment view of the hierarchy
+ * (64 bytes per node and segment, at most 256 MiB per launch; longer paths
+ * run as several launches, the continuous shadow one day at least) in
+ * memory the context owns: grown on first need with the stream
+ * synchronised, kept until sa_destroy.  Under stream capture make one
+ * eager call of the same (or a larger) size first.
  * Errors: INVALID_ARG, CAPACITY (reported by sa_sync if the accrual spill
  * queue overflows), OOM, DEVICE. */
 sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts,
