@@ -454,10 +454,12 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
             z = fmaf(g.e1z, u, g.e2z * v);
         };
         // edge from vertex A to vertex B (world offsets, scaled in-plane
-        // coordinates and heights, below-roof masks)
+        // coordinates and heights, below-roof masks); returns the lanes for
+        // which the edge faces away from p
         auto edge = [&](float awx, float awy, float au, float av, float az, uint64_t ain, float bwx, float bwy,
-                        float bu, float bv, float bz, uint64_t bin) {
-            inside &= ge_mask(cross2(awx, awy, bwx, bwy), 0.f);
+                        float bu, float bv, float bz, uint64_t bin) -> uint64_t {
+            const uint64_t back = ge_mask(cross2(awx, awy, bwx, bwy), 0.f);
+            inside &= back;
             const uint64_t crossing = (ain ^ bin) & ballot(true);
             if (crossing) {
                 const float rdz = __builtin_amdgcn_rcpf(bz - az);
@@ -470,38 +472,53 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
                     dc = cross2(cu, cv, bu - au, bv - av) * rdz * __builtin_amdgcn_rcpf(fmaf(cu, cu, cv * cv));
                 cand(cu, cv, dc, crossing);
             }
+            return back;
+        };
+        // kept vertices: candidates only at the silhouette (see the
+        // world-offset branch below)
+        auto vcand = [&](float u, float v, uint64_t in, uint64_t b_in, uint64_t b_out) {
+            const uint64_t ok = in & (b_in ^ b_out);
+            if (ok) cand(u, v, 0.f, ok);
         };
         // two vertices per trip, as in the world-offset branch below
         float awx, awy, au, av, az, bwx, bwy, bu, bv, bz;
         vertex(0, awx, awy, au, av, az);
-        uint64_t ain = le_mask(az, hs), bin;
-        cand(au, av, 0.f, ain);
-        int e = 1;
+        uint64_t ain = le_mask(az, hs);
+        vertex(1, bwx, bwy, bu, bv, bz);
+        uint64_t bin = le_mask(bz, hs);
+        const uint64_t back0 = edge(awx, awy, au, av, az, ain, bwx, bwy, bu, bv, bz, bin);
+        uint64_t bprev = back0;
+        int e = 2;
         for (; e + 1 < m; e += 2) {
-            vertex(e, bwx, bwy, bu, bv, bz);
+            vertex(e, awx, awy, au, av, az);
+            ain = le_mask(az, hs);
+            uint64_t back = edge(bwx, bwy, bu, bv, bz, bin, awx, awy, au, av, az, ain);
+            vcand(bu, bv, bin, bprev, back);
+            bprev = back;
+            vertex(e + 1, bwx, bwy, bu, bv, bz);
             bin = le_mask(bz, hs);
-            edge(awx, awy, au, av, az, ain, bwx, bwy, bu, bv, bz, bin);
-            cand(bu, bv, 0.f, bin);
-            vertex(e + 1, awx, awy, au, av, az);
-            const uint64_t nin = le_mask(az, hs);
-            edge(bwx, bwy, bu, bv, bz, bin, awx, awy, au, av, az, nin);
-            cand(au, av, 0.f, nin);
-            ain = nin;
+            back = edge(awx, awy, au, av, az, ain, bwx, bwy, bu, bv, bz, bin);
+            vcand(au, av, ain, bprev, back);
+            bprev = back;
         }
         if (e < m) {  // one vertex left before the closing edge
-            vertex(e, bwx, bwy, bu, bv, bz);
-            bin = le_mask(bz, hs);
-            edge(awx, awy, au, av, az, ain, bwx, bwy, bu, bv, bz, bin);
-            cand(bu, bv, 0.f, bin);
-            awx = bwx;
-            awy = bwy;
-            au = bu;
-            av = bv;
-            az = bz;
-            ain = bin;
+            vertex(e, awx, awy, au, av, az);
+            ain = le_mask(az, hs);
+            const uint64_t back = edge(bwx, bwy, bu, bv, bz, bin, awx, awy, au, av, az, ain);
+            vcand(bu, bv, bin, bprev, back);
+            bprev = back;
+            bwx = awx;
+            bwy = awy;
+            bu = au;
+            bv = av;
+            bz = az;
+            bin = ain;
         }
-        vertex(0, bwx, bwy, bu, bv, bz);
-        edge(awx, awy, au, av, az, ain, bwx, bwy, bu, bv, bz, le_mask(bz, hs));
+        vertex(0, awx, awy, au, av, az);
+        ain = le_mask(az, hs);
+        const uint64_t bclose = edge(bwx, bwy, bu, bv, bz, bin, awx, awy, au, av, az, ain);
+        vcand(bu, bv, bin, bprev, bclose);
+        vcand(au, av, ain, bclose, back0);
     } else {
         // Without derivatives the extremes are found in world offsets from p:
         // the map M into the segment plane is linear, so it keeps the angular
@@ -526,47 +543,71 @@ __device__ __forceinline__ int prism_interval(cfloat4 *verts, int voff, int m, f
             wy = q.y - py;
             z = fmaf(Z1, wx, Z2 * wy);
         };
-        // edge from vertex (ax, ay) (height az, below the roof line in the
-        // lanes of ain) to vertex (bx, by, bz, bin)
-        auto edge = [&](float ax, float ay, float az, uint64_t ain, float bx, float by, float bz, uint64_t bin) {
-            inside &= ge_mask(cross2(ax, ay, bx, by), 0.f);
+        // Edge from vertex (ax, ay) (height az, below the roof line in the
+        // lanes of ain) to vertex (bx, by, bz, bin); returns the lanes for
+        // which the edge faces away from p (p on its inner side).
+        auto edge = [&](float ax, float ay, float az, uint64_t ain, float bx, float by, float bz,
+                        uint64_t bin) -> uint64_t {
+            const uint64_t back = ge_mask(cross2(ax, ay, bx, by), 0.f);
+            inside &= back;
             const uint64_t crossing = (ain ^ bin) & ballot(true);
             if (crossing) {
                 const float t = (hs - az) * __builtin_amdgcn_rcpf(bz - az);
                 cand(fmaf(t, bx - ax, ax), fmaf(t, by - ay, ay), crossing);
             }
+            return back;
+        };
+        // Seen from p outside it, a convex polygon's extreme directions are
+        // at its silhouette vertices, where the edge before and the edge
+        // after face p differently.  The clipped polygon's edges at a kept
+        // footprint vertex lie on the footprint's own edges, so a kept
+        // vertex is a candidate only where the two footprint edges at it
+        // disagree (the clip crossings are always candidates).  A vertex is
+        // weighed once its outgoing edge is known; a vertex no lane needs
+        // is skipped for the whole wave.
+        auto vcand = [&](float x, float y, uint64_t in, uint64_t b_in, uint64_t b_out) {
+            const uint64_t ok = in & (b_in ^ b_out);
+            if (ok) cand(x, y, ok);
         };
         // Two vertices per trip (A, then B, then A again), so the previous
-        // vertex never has to be copied between registers; the closing edge
-        // back to vertex 0 adds no vertex candidate.
+        // vertex never has to be copied between registers; vertex 0 is read
+        // again for the closing edge rather than kept in registers.
         float ax, ay, az, bx, by, bz;
         vertex(0, ax, ay, az);
-        uint64_t ain = le_mask(az, hs), bin;
-        cand(ax, ay, ain);
-        int e = 1;
+        uint64_t ain = le_mask(az, hs);
+        vertex(1, bx, by, bz);
+        uint64_t bin = le_mask(bz, hs);
+        const uint64_t back0 = edge(ax, ay, az, ain, bx, by, bz, bin);  // edge 0 -> 1
+        uint64_t bprev = back0;
+        int e = 2;
         for (; e + 1 < m; e += 2) {
-            vertex(e, bx, by, bz);
+            vertex(e, ax, ay, az);
+            ain = le_mask(az, hs);
+            uint64_t back = edge(bx, by, bz, bin, ax, ay, az, ain);
+            vcand(bx, by, bin, bprev, back);
+            bprev = back;
+            vertex(e + 1, bx, by, bz);
             bin = le_mask(bz, hs);
-            edge(ax, ay, az, ain, bx, by, bz, bin);
-            cand(bx, by, bin);
-            vertex(e + 1, ax, ay, az);
-            const uint64_t nin = le_mask(az, hs);
-            edge(bx, by, bz, bin, ax, ay, az, nin);
-            cand(ax, ay, nin);
-            ain = nin;
+            back = edge(ax, ay, az, ain, bx, by, bz, bin);
+            vcand(ax, ay, ain, bprev, back);
+            bprev = back;
         }
         if (e < m) {  // one vertex left before the closing edge
-            vertex(e, bx, by, bz);
-            bin = le_mask(bz, hs);
-            edge(ax, ay, az, ain, bx, by, bz, bin);
-            cand(bx, by, bin);
-            ax = bx;
-            ay = by;
-            az = bz;
-            ain = bin;
+            vertex(e, ax, ay, az);
+            ain = le_mask(az, hs);
+            const uint64_t back = edge(bx, by, bz, bin, ax, ay, az, ain);
+            vcand(bx, by, bin, bprev, back);
+            bprev = back;
+            bx = ax;
+            by = ay;
+            bz = az;
+            bin = ain;
         }
-        vertex(0, bx, by, bz);
-        edge(ax, ay, az, ain, bx, by, bz, le_mask(bz, hs));
+        vertex(0, ax, ay, az);
+        ain = le_mask(az, hs);
+        const uint64_t bclose = edge(bx, by, bz, bin, ax, ay, az, ain);  // edge m-1 -> 0
+        vcand(bx, by, bin, bprev, bclose);
+        vcand(ax, ay, ain, bclose, back0);
         const bool flip = fmaf(g.m00, g.m11, -g.m01 * g.m10) < 0.f;
         const float fx = flip ? hix : lox, fy = flip ? hiy : loy;
         const float gx = flip ? lox : hix, gy = flip ? loy : hiy;
