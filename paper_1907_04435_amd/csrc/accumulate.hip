@@ -380,8 +380,10 @@ __device__ __forceinline__ void runs_update(const Union4 &U, float w0, float w1,
 // pieces is not queued for the spill rounds: the lane walks that segment
 // window by window from its start (halving the window on overflow,
 // doubling it after a success) while the other lanes wait.  A window would
-// have to shrink below theta / 4096 to raise the overflow flag.
-__global__ __launch_bounds__(kThreads) void k_accrual_runs(const Node *nodes_g, const SegNode *snodes_g, int n_nodes,
+// have to shrink below theta / 4096 to raise the overflow flag.  Seven
+// waves per SIMD (the compiler fits the kernel in 72 VGPRs) measured 4 %
+// faster than the six its natural allocation allows.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_accrual_runs(const Node *nodes_g, const SegNode *snodes_g, int n_nodes,
                                                            const int32_t *voff_g, const float4 *verts_g,
                                                            const float *height_g, const SegConst *segs_g, int j0,
                                                            int j1, PointArgs P, float scale, int32_t *counts,
@@ -750,7 +752,9 @@ __global__ void k_var_tiles(int V, const int64_t *__restrict__ var_off, int64_t 
 // segment for its 64 points on that variant's hierarchy.  A point-segment
 // whose occluded set needs more than four pieces is finished in place by
 // walking its window left to right with halving / doubling sub-windows.
-__global__ __launch_bounds__(kThreads) void k_batched(const Node *vnodes_g, int n_nodes, const SegNode *views_g,
+// Seven waves per SIMD: 72 VGPRs with a few spilled to scratch, measured
+// faster (64.5 ms on 256 variants) than six waves (77 ms) or eight (75 ms).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_batched(const Node *vnodes_g, int n_nodes, const SegNode *views_g,
                                                       int64_t stride, const int32_t *voff_g,
                                                       const int32_t *__restrict__ vroot, const float4 *verts_g,
                                                       const float *vh_g, int n_b, const SegConst *segs_g, int j0,

