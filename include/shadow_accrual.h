@@ -181,6 +181,20 @@ sa_status sa_sunpath(const sa_site *site, const sa_timespan *span, sa_sunpath_bu
  * in->day_bin (or bin = day); n_bins = 1 + max bin.  Errors: INVALID_ARG,
  * OOM. */
 sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out);
+
+/* As sa_path_upload, with the direction graph of Sec. 6 for the accrual
+ * form: the hemisphere is cut into cells of at most bound_deg (rings of
+ * that height in elevation, each cut into azimuth cells of at most that
+ * width), and segments of one output bin whose start and end knots fall in
+ * the same pair of cells become one edge, computed once from the first of
+ * them and weighted by their number (Eq. 2).  Each merged segment keeps its
+ * own duration; sample counts are the edge's times its multiplicity.  An
+ * approximation for exploring long spans: a representative direction up to
+ * about bound_deg away shifts shadow transitions by bound_deg over the
+ * sun's angular speed (about 0.25 degrees per minute).  The sampled form
+ * is unaffected; the continuous shadow needs time order and is refused
+ * (INVALID_ARG).  bound_deg in (0, 90].  Errors as sa_path_upload. */
+sa_status sa_path_upload_graph(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, sa_path **out);
 sa_status sa_path_info(const sa_path *path, int32_t *n_bins, int32_t *n_samples,
                        int32_t *n_segments);
 void sa_path_destroy(sa_path *path);

@@ -28,7 +28,7 @@ _ERRORS = {-1: "INVALID_ARG", -2: "GEOMETRY", -3: "CAPACITY", -4: "OOM", -5: "DE
 # Every entry point declared in include/shadow_accrual.h.
 EXPORTS = ["sa_create", "sa_destroy", "sa_set_stream", "sa_last_error", "sa_sync", "sa_version",
            "sa_scene_upload", "sa_scene_set_heights", "sa_scene_get_info", "sa_scene_read_bvh",
-           "sa_scene_destroy", "sa_sunpath", "sa_path_upload", "sa_path_info", "sa_path_destroy",
+           "sa_scene_destroy", "sa_sunpath", "sa_path_upload", "sa_path_upload_graph", "sa_path_info", "sa_path_destroy",
            "sa_accumulate", "sa_accumulate_batched", "sa_grad_heights", "sa_region_sum",
            "sa_building_contribution", "sa_path_bin_span", "sa_region_score"]
 
@@ -97,6 +97,7 @@ def lib():
             "sa_scene_destroy": (None, [vp]),
             "sa_sunpath": (i32, [C.POINTER(sa_site), C.POINTER(sa_timespan), C.POINTER(sa_sunpath_buf)]),
             "sa_path_upload": (i32, [vp, C.POINTER(sa_sunpath_buf), C.POINTER(vp)]),
+            "sa_path_upload_graph": (i32, [vp, C.POINTER(sa_sunpath_buf), C.c_double, C.POINTER(vp)]),
             "sa_path_info": (i32, [vp, vp, vp, vp]),
             "sa_path_destroy": (None, [vp]),
             "sa_accumulate": (i32, [vp, vp, C.POINTER(sa_points), vp, C.POINTER(sa_accum_opts), vp, vp, vp]),
@@ -310,7 +311,11 @@ class Scene:
 
 
 class Path:
-    def __init__(self, ctx: Context, sp: SunPath):
+    """A sun path on the device.  ``graph_bound_deg``: merge the accrual
+    form's segments into direction-graph edges with cells of that size
+    (sa_path_upload_graph); None keeps every segment."""
+
+    def __init__(self, ctx: Context, sp: SunPath, graph_bound_deg: float | None = None):
         self.ctx = ctx
         self.host = sp
         keep = [np.ascontiguousarray(sp.day_sample_off, np.int32), np.ascontiguousarray(sp.t_min, np.float64),
@@ -320,7 +325,10 @@ class Path:
         buf = sa_sunpath_buf(sp.n_days, sp.n_samples, len(sp.knot_t), sp.n_days, sp.n_samples, len(sp.knot_t),
                              *[k.ctypes.data for k in keep])
         h = C.c_void_p()
-        _check(ctx, lib().sa_path_upload(ctx.handle, C.byref(buf), C.byref(h)))
+        if graph_bound_deg is None:
+            _check(ctx, lib().sa_path_upload(ctx.handle, C.byref(buf), C.byref(h)))
+        else:
+            _check(ctx, lib().sa_path_upload_graph(ctx.handle, C.byref(buf), float(graph_bound_deg), C.byref(h)))
         self.handle = h
         nb, ns, nseg = C.c_int32(), C.c_int32(), C.c_int32()
         _check(ctx, lib().sa_path_info(h, C.byref(nb), C.byref(ns), C.byref(nseg)))

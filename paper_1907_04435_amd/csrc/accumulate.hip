@@ -166,8 +166,8 @@ __device__ __forceinline__ void measure(const Union4 &U, const SegConst &g, floa
             c += max(khi - klo + 1, 0);
         }
     }
-    mins += (double)(m * scale);
-    cnt += c;
+    mins += (double)(m * g.wrate);
+    cnt += c * g.mult;
 }
 
 // The occluded set of every live lane's point over its window of segment g:
@@ -342,7 +342,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
         const SegConst gm = ld(segs + jr);
         if (covered && valid) {
             mins += (double)gm.dt;
-            cnt += gm.ns;
+            cnt += gm.ns_all;
         } else if (!ov) {
             measure(U, gm, 0.f, gm.theta, true, mins, cnt);
         }
@@ -431,7 +431,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
         }
         if (covered && valid) {
             mins += (double)g.dt;
-            cnt += g.ns;
+            cnt += g.ns_all;
             run += g.dt;
             best = fmaxf(best, run);
         }
@@ -577,7 +577,7 @@ __global__ __launch_bounds__(kThreads) void k_contrib(const SegNode *snodes_g, i
         if (active && q.own >= 0) {
             float a, b;
             if (backface_interval(q.nx, q.ny, g, 0.f, g.theta, 1.f, 0.f, g.cth, g.sth, a, b))
-                bf += (double)((b - a) * g.rate * wt);
+                bf += (double)((b - a) * g.wrate * wt);
         }
         if (snodes_g == nullptr) continue;
         const SegFan ft(g, q.px, q.py, q.pz);
@@ -591,7 +591,7 @@ __global__ __launch_bounds__(kThreads) void k_contrib(const SegNode *snodes_g, i
                              : 0;
             // the wave's total for this building (every lane is active
             // here: the traversal runs on the whole wave)
-            const float v = wave_sum(r ? (b - a) * g.rate * wt : 0.f);
+            const float v = wave_sum(r ? (b - a) * g.wrate * wt : 0.f);
             if (first_active_lane() && v != 0.f) atomicAdd(&row[order[prim]], (double)v);
             return 0;  // no lane retires: every building counts
         };
@@ -806,7 +806,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
             }
             if (covered && valid) {
                 mins += (double)g.dt;
-                cnt += g.ns;
+                cnt += g.ns_all;
                 continue;
             }
             float w0 = 0.f, s = g.theta;

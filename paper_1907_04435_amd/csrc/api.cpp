@@ -3,10 +3,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "sa_internal.h"
@@ -299,7 +302,58 @@ sa_status sa_sunpath(const sa_site *site, const sa_timespan *span, sa_sunpath_bu
     return sa::sunpath_fill(*site, *span, *out, err);
 }
 
-sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
+}  // extern "C"
+
+namespace {
+
+// Direction-graph reuse (Sec. 6): the hemisphere is cut into cells of at
+// most `bound` radians (rings of that height in elevation, each cut into
+// azimuth cells of at most that width); segments of one output bin whose
+// start and end knots fall in the same pair of cells are one edge, computed
+// once from its first segment and weighted by how many segments it stands
+// for (Eq. 2 sums the edges' maps by multiplicity).  The edge keeps the
+// first segment's geometry and time map; the minutes per radian its
+// measure is weighted by become the merged segments' total duration over
+// that segment's angle, so each merged segment counts with its own
+// duration; sample counts are scaled by the multiplicity.
+void merge_segments(std::vector<sa::SegConst> &segs, const std::vector<std::array<double, 6>> &knots,
+                    double bound)
+{
+    auto cell = [bound](const double *d) {
+        const double el = std::asin(std::max(-1.0, std::min(1.0, d[2])));
+        const double az = std::atan2(d[0], d[1]);
+        const int64_t ring = (int64_t)std::floor(el / bound);
+        const int64_t naz =
+            std::max<int64_t>(1, (int64_t)std::ceil(2.0 * M_PI * std::cos((double)ring * bound) / bound));
+        const int64_t c = (int64_t)std::floor((az + M_PI) / (2.0 * M_PI) * (double)naz);
+        return ring * 4000000 + std::min(c, naz - 1);
+    };
+    std::map<std::tuple<int32_t, int64_t, int64_t>, size_t> edge;
+    std::vector<sa::SegConst> out;
+    std::vector<double> dt_sum;
+    for (size_t s = 0; s < segs.size(); ++s) {
+        const auto key = std::make_tuple(segs[s].bin, cell(knots[s].data()), cell(knots[s].data() + 3));
+        auto it = edge.find(key);
+        if (it == edge.end()) {
+            edge.emplace(key, out.size());
+            out.push_back(segs[s]);
+            dt_sum.push_back(segs[s].dt);
+            continue;
+        }
+        sa::SegConst &g = out[it->second];
+        dt_sum[it->second] += segs[s].dt;
+        g.mult += 1;
+        g.ns_all += segs[s].ns;
+    }
+    for (size_t e = 0; e < out.size(); ++e) {
+        if (out[e].mult == 1) continue;  // a lone segment keeps its own weights
+        out[e].dt = (float)dt_sum[e];
+        out[e].wrate = (float)(dt_sum[e] / out[e].theta);
+    }
+    segs = std::move(out);
+}
+
+sa_status path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, sa_path **out)
 {
     if (!ctx || !in || !out) return SA_ERR_INVALID_ARG;
     *out = nullptr;
@@ -310,6 +364,7 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload: bad arguments");
     std::vector<sa::SampleConst> samples(in->n_samples);
     std::vector<sa::SegConst> segs;
+    std::vector<std::array<double, 6>> seg_knots;  // knot directions of each segment
     std::vector<int32_t> day_seg_off;
     std::vector<double> bin_span;  // daylight minutes per bin: the instants' weights add up to each day's span
     int n_bins = 0;
@@ -372,9 +427,8 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
             g.ta = (float)ta;
             g.cth = (float)std::cos(theta);
             g.sth = (float)std::sin(theta);
-            g.nx = (float)N[0];
-            g.ny = (float)N[1];
             g.nz = (float)N[2];
+            g.mult = 1;
             g.bin = bin;
             g.day = d;
             g.e1x = (float)a[0];
@@ -397,14 +451,21 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
                 }
             }
             g.s0 = first >= 0 ? (float)(in->t_min[first] - ta) : 0.f;
-            g.step = (float)step;
+            g.wrate = (float)((tb - ta) / theta);
             g.ns = ns;
+            g.ns_all = ns;
             g.rate = (float)((tb - ta) / theta);
             g.inv_step = (float)(1.0 / step);
             g.mdx = (float)(a[0] + e2[0] * 0.5 * theta);
             g.mdy = (float)(a[1] + e2[1] * 0.5 * theta);
             segs.push_back(g);
+            seg_knots.push_back({a[0], a[1], a[2], b[0], b[1], b[2]});
         }
+    }
+    bool merged = false;
+    if (bound_deg > 0.0) {
+        merge_segments(segs, seg_knots, bound_deg * M_PI / 180.0);
+        merged = true;
     }
     if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
     sa_path *p = new (std::nothrow) sa_path();
@@ -415,8 +476,13 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
     p->d.n_samples = in->n_samples;
     p->d.n_segs = (int32_t)segs.size();
     p->d.n_bins = n_bins;
+    if (merged) {
+        // edges mix days: no per-day segment ranges
+        day_seg_off.assign(1, 0);
+    }
     day_seg_off.push_back((int32_t)segs.size());
     p->d.day_seg_off = std::move(day_seg_off);
+    p->d.merged = merged;
     bin_span.resize(n_bins, 0.0);
     p->d.bin_span = std::move(bin_span);
     p->d.words = (in->n_samples + 31) / 32;
@@ -438,6 +504,22 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
     }
     *out = p;
     return SA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
+{
+    return path_upload(ctx, in, 0.0, out);
+}
+
+sa_status sa_path_upload_graph(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, sa_path **out)
+{
+    if (!(bound_deg > 0.0 && bound_deg <= 90.0))
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload_graph: bound must be in (0, 90] degrees");
+    return path_upload(ctx, in, bound_deg, out);
 }
 
 sa_status sa_path_info(const sa_path *path, int32_t *n_bins, int32_t *n_samples, int32_t *n_segments)
@@ -498,6 +580,9 @@ sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate: unknown mode");
     if (bits && opts->mode != SA_SAMPLED)
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate: bit vectors exist for the sampled form only");
+    if (opts->longest && opts->mode == SA_ACCRUAL && path->d.merged)
+        return fail(ctx, SA_ERR_INVALID_ARG,
+                    "sa_accumulate: a direction-graph path has no time order: no continuous shadow");
     if (!counts && !minutes && !bits && !opts->longest) return SA_OK;
     if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
     const float scale = opts->out_scale == 0.f ? 1.f : opts->out_scale;

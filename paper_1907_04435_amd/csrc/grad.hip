@@ -142,7 +142,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
         cSegNode *sn = snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr;
         grad_segment(sn, (cint *)voff_g, stack, verts, height, g, q, valid && !covered && w != 0.f, 0.f, g.theta, U,
                      ov);
-        if (valid && !covered && !ov && w != 0.f) scatter_grad(U, w * g.rate, G);
+        if (valid && !covered && !ov && w != 0.f) scatter_grad(U, w * g.wrate, G);
         spill_push(S, valid && ov, i, j, 0.f, g.theta);
     }
 }
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void k_grad_spill(const SegNode *snodes_g
         bool ov;
         cSegNode *sn = snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr;
         grad_segment(sn, (cint *)voff_g, stack, verts, height, g, q, true, w0, w1, U, ov);
-        if (!ov) scatter_grad(U, w * g.rate, G);
+        if (!ov) scatter_grad(U, w * g.wrate, G);
         spill_push(S, ov, i, j, w0, w1);
     }
 }

@@ -49,13 +49,16 @@ struct alignas(64) SegConst {
     float e1z, e2z, theta, dt;   // clip normal (u,v)->z, angle, minutes
     float ta;                    // start, minutes after local midnight
     float cth, sth;              // (cos theta, sin theta): end direction in (u, v)
-    float nx, ny, nz;            // plane normal e1 x e2
+    float nz;                    // vertical part of the plane normal e1 x e2
+    int32_t mult;                // segments this one stands for (direction graph; else 1)
+    int32_t ns_all;              // their sample instants
     int32_t bin;
     int32_t day;
     float e1x, e1y, e2x, e2y;    // horizontal parts of e1, e2 (facade back-face term)
     float ua_x, ua_y, ub_x, ub_y;  // horizontal offset per metre of rise, at both knots
     float s0;                    // first sample instant in the segment, minutes after ta
-    float step;                  // sample spacing (minutes)
+    float wrate;                 // minutes per radian the measure is weighted by: rate, or for a
+                                 // direction-graph edge its segments' total duration / theta
     int32_t ns;                  // sample instants attributed to the segment
     int32_t steep;               // plane within 5 degrees of vertical: in-plane extreme search
     float rate;                  // dt / theta: minutes per radian
@@ -100,6 +103,7 @@ struct DevicePath {
     int32_t words = 0;               // ceil(n_samples / 32)
     std::vector<int32_t> day_seg_off;  // host: first segment of each day, [n_days + 1]
     std::vector<double> bin_span;      // host: daylight minutes of each output bin
+    bool merged = false;               // host: segments merged into direction-graph edges
 };
 
 // Host-side builders implemented in the .hip sources.

@@ -1,0 +1,113 @@
+"""Direction-graph paths (Sec. 6, sa_path_upload_graph): segments of one
+bin whose knots fall in the same pair of hemisphere cells are computed once
+and weighted by their number.  Exact where the merged segments coincide,
+the same path where nothing merges, and an approximation whose error grows
+with the cell size elsewhere."""
+import datetime as dt
+
+import numpy as np
+import pytest
+
+import paper_1907_04435_amd as sa
+from workloads import Span, make_c2, subset_points
+from workloads.scenes import Day, _nyc_tz
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return sa.Context(0)
+
+
+@pytest.fixture(scope="module")
+def block():
+    w = make_c2(n_ground=20_000, n_facade=20_000)
+    idx = np.concatenate([subset_points(w.points.take(np.arange(20_000)), 2048, 51),
+                          20_000 + subset_points(w.points.take(np.arange(20_000, 40_000)), 2048, 52)])
+    return w.scene, w.points.take(idx)
+
+
+def run(ctx, scene, pts, sp, bound=None, mode=sa.SA_ACCRUAL):
+    path = sa.Path(ctx, sp, graph_bound_deg=bound)
+    sc = sa.Scene.from_workload(ctx, scene)
+    dp = sa.DevicePoints.from_workload(pts)
+    c, m, _ = sa.accumulate(ctx, sc, dp, path, mode)
+    ctx.sync()
+    return c.cpu().numpy(), m.cpu().numpy().astype(np.float64), path.n_segments
+
+
+def days_span(dates, bins):
+    return Span(40.7, -74.0, [Day(d.year, d.month, d.day, _nyc_tz(d)) for d in dates], 1.0, bins)
+
+
+def test_repeated_days_merge_exactly(ctx, block):
+    """The same day four times in one bin: every segment has three exact
+    copies, so the graph keeps a quarter of them and the results equal the
+    plain path's (counts and minutes exactly: the merged weights are exact
+    multiples)."""
+    scene, pts = block
+    sp = sa.sunpath_for_span(days_span([dt.date(2019, 6, 21)] * 4, [0, 0, 0, 0]), 30.0)
+    c0, m0, n0 = run(ctx, scene, pts, sp)
+    c1, m1, n1 = run(ctx, scene, pts, sp, bound=0.5)
+    say(f"repeated days: {n0} segments -> {n1}; max |dmin| {np.abs(m1 - m0).max():.2e}")
+    assert n1 * 4 == n0
+    assert np.array_equal(c0, c1)
+    np.testing.assert_allclose(m1, m0, rtol=1e-6, atol=1e-3)
+
+
+def test_tiny_cells_keep_every_segment(ctx, block):
+    scene, pts = block
+    sp = sa.sunpath_for_span(days_span([dt.date(2019, 3, 20), dt.date(2019, 6, 21), dt.date(2019, 12, 21)],
+                                       [0, 1, 2]), 30.0)
+    c0, m0, n0 = run(ctx, scene, pts, sp)
+    c1, m1, n1 = run(ctx, scene, pts, sp, bound=1e-6)
+    assert n1 == n0
+    # equal but for the order of the spill rounds' float atomics
+    assert np.array_equal(c0, c1)
+    np.testing.assert_allclose(m1, m0, rtol=1e-6, atol=1e-3)
+
+
+def test_error_grows_with_the_cell_size(ctx, block):
+    """Thirty days around the June solstice in one bin: coarser cells merge
+    more segments and cost accuracy, measured against the plain path."""
+    scene, pts = block
+    dates = [dt.date(2019, 6, 6) + dt.timedelta(days=i) for i in range(30)]
+    sp = sa.sunpath_for_span(days_span(dates, [0] * 30), 30.0)
+    c0, m0, n0 = run(ctx, scene, pts, sp)
+    rows = []
+    for b in (0.25, 1.0, 5.0):
+        c1, m1, n1 = run(ctx, scene, pts, sp, bound=b)
+        err = np.abs(m1 - m0).mean() / 30.0          # minutes per point per day
+        tot = abs(m1.sum() - m0.sum()) / m0.sum()
+        rows.append((b, n1, err, tot))
+        say(f"cells {b} deg: {n0} segments -> {n1}, mean |error| {err:.3f} min/point/day, "
+            f"region total off by {tot:.2e}")
+    ns = [r[1] for r in rows]
+    errs = [r[2] for r in rows]
+    assert ns[0] <= n0 and ns[0] >= ns[1] >= ns[2] and ns[2] < n0 / 4
+    assert errs[0] <= errs[2]
+    assert rows[0][2] < 1.0                          # fine cells stay close to the plain path
+
+
+def test_graph_paths_and_other_forms(ctx, block):
+    """The sampled form ignores the graph; the continuous shadow, which
+    needs time order, is refused."""
+    import torch
+    scene, pts = block
+    sp = sa.sunpath_for_span(days_span([dt.date(2019, 6, 21)] * 2, [0, 0]), 30.0)
+    cs0, ms0, _ = run(ctx, scene, pts, sp, mode=sa.SA_SAMPLED)
+    cs1, ms1, _ = run(ctx, scene, pts, sp, bound=1.0, mode=sa.SA_SAMPLED)
+    assert np.array_equal(cs0, cs1) and np.array_equal(ms0, ms1)
+    path = sa.Path(ctx, sp, graph_bound_deg=1.0)
+    sc = sa.Scene.from_workload(ctx, scene)
+    dp = sa.DevicePoints.from_workload(pts)
+    m = torch.empty((path.n_bins, dp.n), dtype=torch.float32, device="cuda")
+    longest = torch.empty_like(m)
+    with pytest.raises(sa.SAError) as e:
+        sa.sa_accumulate(ctx, sc, dp, path, sa.SA_ACCRUAL, None, m, longest=longest)
+    assert e.value.code == -1
+    with pytest.raises(sa.SAError):
+        sa.Path(ctx, sp, graph_bound_deg=0.0)
