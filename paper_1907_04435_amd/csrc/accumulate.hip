@@ -142,6 +142,17 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
 }
 
 // ------------------------------------------------------------------ accrual
+// Segment j's constants read again where they are used after a traversal
+// rather than held in registers across it (an opaque copy of the index
+// keeps the compiler from reusing the first load): a scalar-cache hit
+// costs less than spilling them to lanes of a vector register.
+__device__ __forceinline__ SegConst reload(cSeg *segs, int j)
+{
+    int jr = j;
+    asm volatile("" : "+s"(jr));
+    return ld(segs + jr);
+}
+
 // Measure and sample count of the occluded set of one point over the
 // window [w0, w1] of segment g.  `last_window` says whether w1 is the end
 // of the segment (instants at the window end belong to the next window
@@ -333,13 +344,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
             wk.units += valid ? 1u : 0u;
             wk.spills += (valid && ov) ? 1u : 0u;
         }
-        // Read the segment constants again rather than hold them in
-        // registers across the traversal (an opaque copy of the index keeps
-        // the compiler from reusing the first load): a scalar-cache hit
-        // costs less than spilling them to lanes of a vector register.
-        int jr = j;
-        asm volatile("" : "+s"(jr));
-        const SegConst gm = ld(segs + jr);
+        const SegConst gm = reload(segs, j);
         if (covered && valid) {
             mins += (double)gm.dt;
             cnt += gm.ns_all;
@@ -453,8 +458,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
                         s *= 0.5f;
                     }
                 } else {
-                    measure(U, g, w0, w1, w1 >= g.theta, mins, cnt);
-                    runs_update(U, w0, w1, g.rate, run, best);
+                    const SegConst gm = reload(segs, j);
+                    measure(U, gm, w0, w1, w1 >= gm.theta, mins, cnt);
+                    runs_update(U, w0, w1, gm.rate, run, best);
                     w0 = w1;
                     pending = w0 < g.theta;
                     s = fminf(2.f * s, g.theta);
@@ -766,10 +772,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
     cfloat4 *verts = (cfloat4 *)verts_g;
     cSeg *segs = (cSeg *)segs_g;
     __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    __shared__ int s_P[sizeof(PointArgs) / 4];
     StackEntry *stack = s_stack[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     const int64_t T = tile_off[V];
     const int64_t n = P.n;
+    if (threadIdx.x == 0) lds_park((lds_int *)s_P, P);
+    __syncthreads();
     for (;;) {
         int64_t t = 0;
         if (lane == 0) t = atomicAdd((unsigned long long *)tile_counter, 1ull);
@@ -786,7 +795,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
         cfloat *height = (cfloat *)(vh_g + (int64_t)v * n_b);
         const int64_t i = var_off[v] + (t - tile_off[v]) * 64 + lane;
         const bool valid = i < var_off[v + 1];
-        const LanePoint q = load_point(P, i, valid);
+        const LanePoint q = load_point(lds_uniform<PointArgs>((lds_int *)s_P), i, valid);
         const bool covered = roof_covered(nodes, stack, verts, height, q, valid);
         const int root = vroot ? vroot[v] : 0;
         int cnt = 0;
@@ -827,7 +836,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
                             s *= 0.5f;
                         }
                     } else {
-                        measure(U, g, w0, w1, w1 >= g.theta, mins, cnt);
+                        measure(U, reload(segs, j), w0, w1, w1 >= g.theta, mins, cnt);
                         w0 = w1;
                         pending = w0 < g.theta;
                         s = fminf(2.f * s, g.theta);

@@ -811,6 +811,34 @@ __device__ __forceinline__ LanePoint load_point(const PointArgs &P, int64_t i, b
     return q;
 }
 
+// A kernel argument parked in LDS and read back, wave-uniform, where a
+// persistent loop needs it: the register allocator then has no reason to
+// hold it in scalar registers across the traversal (where it would spill
+// them to vector lanes and restore them on every node visit).  The volatile
+// read keeps the compiler from hoisting the reload out of the loop.
+typedef __attribute__((address_space(3))) int lds_int;
+
+template <class T>
+__device__ __forceinline__ void lds_park(lds_int *w, const T &v)
+{
+    static_assert(sizeof(T) % 4 == 0, "word-sized objects");
+    const int *s = (const int *)&v;
+#pragma unroll
+    for (unsigned k = 0; k < sizeof(T) / 4; ++k) w[k] = s[k];
+}
+
+template <class T>
+__device__ __forceinline__ T lds_uniform(const lds_int *w)
+{
+    static_assert(sizeof(T) % 4 == 0, "word-sized objects");
+    T r;
+    int *d = (int *)&r;
+    const volatile lds_int *p = w;
+#pragma unroll
+    for (unsigned k = 0; k < sizeof(T) / 4; ++k) d[k] = __builtin_amdgcn_readfirstlane(p[k]);
+    return r;
+}
+
 struct SpillArgs {
     int4 *out;          // queue to push to
     uint32_t *counter;  // its length
