@@ -206,6 +206,27 @@ def bench_c5(args, sa, torch):
                "point_sun_steps": evals})
     r["steps"], r["warmup"] = steps, 0
     r["mean_hours_per_bin"] = [float(x) for x in hours.mean(1).cpu()]
+    if not args.skip_graph:
+        # the direction graph of Sec. 6: segments of a season whose knots
+        # share a pair of hemisphere cells computed once; time and error
+        # against the full path above, per cell size
+        base = hours.clone()
+        legs = []
+        for bound in (0.25, 1.0, 5.0):
+            gp = sa.Path(ctx, sp, graph_bound_deg=bound)
+            gh = torch.empty_like(hours)
+            gms = _timed(torch, ctx.stream,
+                         lambda: sa.sa_accumulate(ctx, sc, dp, gp, sa.SA_ACCRUAL, None, gh, out_scale=1.0 / 60.0), 1)
+            ctx.sync()
+            err = float((gh - base).abs().sum(0).mean()) * 60.0 / 365.0
+            tot = float((gh.sum(dtype=torch.float64) - base.sum(dtype=torch.float64)).abs() /
+                        base.sum(dtype=torch.float64))
+            legs.append({"cell_deg": bound, "segments": gp.n_segments, "ms": float(np.mean(gms)),
+                         "mean_abs_error_min_per_point_day": err, "region_total_rel_error": tot})
+            log(f"c5 graph {bound} deg: {gp.n_segments} of {path.n_segments} segments, "
+                f"{legs[-1]['ms']:.0f} ms, mean |error| {err:.3f} min/point/day")
+            gp.close()
+        r["direction_graph"] = {"segments_full": path.n_segments, "legs": legs}
     return r
 
 
@@ -239,6 +260,8 @@ def main():
                     help="skip the building-contribution leg")
     ap.add_argument("--skip-continuous", action="store_true",
                     help="skip the continuous-shadow leg (accrual form with the longest-run output)")
+    ap.add_argument("--skip-graph", action="store_true",
+                    help="c5: skip the direction-graph legs (segments merged across days)")
     ap.add_argument("--no-truth", action="store_true",
                     help="skip the accuracy leg (accrual with 1-minute knots as the continuous truth)")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
