@@ -12,6 +12,10 @@ The C sources (``solar.c``, ``shadow.c``) compute:
     mask;
   * continuous gross shadow along a piecewise great-circle sun path (grid +
     bisection per occluder, union, measure).
+
+In Python on top of those: the continuous shadow of the sampled form, the
+shadow score, and the direction graph of Sec. 6 (hemisphere cells, edges,
+the accrual form over the edges weighted by their members' durations).
 """
 from __future__ import annotations
 
@@ -313,3 +317,59 @@ def with_height(scene, b, h):
     hh = scene.height.astype(np.float32).copy()
     hh[b] = h
     return Scene(scene.vert_off, scene.xy, hh)
+
+
+# --------------------------------------------------------------------------
+# direction graph (Sec. 6)
+# --------------------------------------------------------------------------
+def hemisphere_cell(d, bound_deg):
+    """Cell index of each direction d [..., 3] (east, north, up) when the
+    sky is cut into cells of bounded angular size (Sec. 6 bins the sun's
+    directions so): rings of ``bound`` in elevation, each ring cut into the
+    fewest equal azimuth sectors whose width at the ring's lower edge is at
+    most ``bound``.  int64 key: ring * 4,000,000 + sector."""
+    b = np.radians(float(bound_deg))
+    d = np.asarray(d, np.float64)
+    el = np.arcsin(np.clip(d[..., 2], -1.0, 1.0))
+    az = np.arctan2(d[..., 0], d[..., 1])
+    ring = np.floor(el / b).astype(np.int64)
+    n_sec = np.maximum(1, np.ceil(2.0 * np.pi * np.cos(ring * b) / b)).astype(np.int64)
+    sec = np.minimum(np.floor((az + np.pi) / (2.0 * np.pi) * n_sec).astype(np.int64), n_sec - 1)
+    return ring * 4_000_000 + sec
+
+
+def direction_graph(path: OraclePath, bound_deg):
+    """Edges of the direction graph (Sec. 6): the path's segments grouped by
+    output bin and by the pair of cells that hold their start and end
+    directions.  Returns a list of member-index lists in order of first
+    appearance; the first member of each stands for the edge."""
+    ca = hemisphere_cell(path.seg_dir[:, 0, :], bound_deg)
+    cb = hemisphere_cell(path.seg_dir[:, 1, :], bound_deg)
+    seg_bin = path.day_bin[path.seg_day]
+    groups = {}
+    for j in range(len(path.seg_t)):
+        groups.setdefault((int(seg_bin[j]), int(ca[j]), int(cb[j])), []).append(j)
+    return list(groups.values())
+
+
+def graph_continuous(scene, pts, path: OraclePath, bound_deg, grid_min=1.0 / 12.0, threads=None):
+    """Accrual form over the direction graph (Sec. 6, Eq. 2): every edge's
+    occluded set is computed once, on its first member segment, and each
+    member counts with its own duration: the edge's minutes are the first
+    member's continuous minutes times (sum of the members' durations) /
+    (the first member's duration).  FP64 [n_bins, n] minutes, and the edge
+    lists.  Each first member runs as a day of its own through
+    ``continuous``."""
+    groups = direction_graph(path, bound_deg)
+    reps = np.array([g[0] for g in groups], np.int64)
+    E = len(reps)
+    sub = OraclePath(np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros(0, np.int32), np.zeros(0, np.int32),
+                     path.seg_t[reps], path.seg_dir[reps], np.arange(E, dtype=np.int32),
+                     np.arange(E, dtype=np.int32), E, path.seg_t[reps])
+    per_edge = continuous(scene, pts, sub, grid_min, threads)["minutes"]
+    out = np.zeros((path.n_bins, pts.n), np.float64)
+    dur = path.seg_t[:, 1] - path.seg_t[:, 0]
+    seg_bin = path.day_bin[path.seg_day]
+    for e, g in enumerate(groups):
+        out[seg_bin[g[0]]] += per_edge[e] * (dur[g].sum() / dur[g[0]])
+    return out, groups

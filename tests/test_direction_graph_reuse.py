@@ -1,9 +1,10 @@
-"""The direction graph of Sec. 6 (one accrual computation per pair of
-hemisphere bins, reused by every day whose segment falls in them) is not
-built: on the year-long path it only pays at bin sizes far coarser than the
-accuracy bar allows.  This test keeps that measurement checkable: it counts
-the distinct edges of a year of 30-minute segments at a fine and at the
-paper's 5-degree bin bound (library sun path, host only)."""
+"""Edge counts of the direction graph of Sec. 6 on a year-long path,
+independent of the library and the oracle: the distinct (start bin, end
+bin, duration) triples of a year of 30-minute segments at a fine and at the
+paper's 5-degree bound (library sun path, host only).  At a fine bound
+almost every segment is its own edge; at 5 degrees the reuse is of the
+order the paper reports.  The library's graph (`sa_path_upload_graph`)
+merges within an output bin and is tested on the GPU."""
 import datetime
 
 import numpy as np
