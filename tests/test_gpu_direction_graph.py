@@ -8,8 +8,9 @@ import datetime as dt
 import numpy as np
 import pytest
 
+import oracle
 import paper_1907_04435_amd as sa
-from workloads import Span, make_c2, subset_points
+from workloads import Span, make_c1, make_c2, subset_points
 from workloads.scenes import Day, _nyc_tz
 
 from gpu_util import say
@@ -56,6 +57,27 @@ def test_repeated_days_merge_exactly(ctx, block):
     assert n1 * 4 == n0
     assert np.array_equal(c0, c1)
     np.testing.assert_allclose(m1, m0, rtol=1e-6, atol=1e-3)
+
+
+def test_graph_matches_oracle(ctx):
+    """Twelve days of June in two bins on the small scene, cells of 1
+    degree: the library forms as many edges as the oracle's direction graph,
+    and every point's minutes match the oracle's graph form (each edge from
+    its first member, weighted by its members' durations) to the accrual
+    form's bar per point and day."""
+    w = make_c1()
+    sub = w.points.take(subset_points(w.points, 512, 71))
+    dates = [dt.date(2019, 6, 10) + dt.timedelta(days=i) for i in range(12)]
+    span = Span(40.7, -74.0, [Day(x.year, x.month, x.day, _nyc_tz(x)) for x in dates], 5.0, [0] * 6 + [1] * 6)
+    _, m, n_edges = run(ctx, w.scene, sub, sa.sunpath_for_span(span, 30.0), bound=1.0)
+    opath = oracle.sun_path(span, 30.0)
+    o, groups = oracle.graph_continuous(w.scene, sub, opath, 1.0)
+    mult = max(len(g) for g in groups)
+    d = np.abs(m - o) / 6.0                       # per point and day
+    say(f"graph vs oracle: {len(opath.seg_t)} segments -> {n_edges} edges (oracle {len(groups)}, "
+        f"largest {mult}); per point-day |d| p99.9 {np.quantile(d, 0.999):.2e} mean {d.mean():.2e} max {d.max():.2e}")
+    assert n_edges == len(groups) and mult > 1
+    assert np.quantile(d, 0.999) <= 0.01 and d.mean() <= 1e-3 and d.max() <= 0.5
 
 
 def test_tiny_cells_keep_every_segment(ctx, block):
