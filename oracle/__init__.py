@@ -373,3 +373,148 @@ def graph_continuous(scene, pts, path: OraclePath, bound_deg, grid_min=1.0 / 12.
     for e, g in enumerate(groups):
         out[seg_bin[g[0]]] += per_edge[e] * (dur[g].sum() / dur[g[0]])
     return out, groups
+
+
+# --------------------------------------------------------------------------
+# shadow accrual map, raster form (Sec. 4)
+# --------------------------------------------------------------------------
+def sam_grid(box, a, b, texel):
+    """Shadow plane and texel grid of one segment (Sec. 4): the plane is
+    normal to the start direction ``a`` and lies 1 m behind the corner of
+    ``box`` = (x0, y0, z0, x1, y1, z1) farthest from the sun; (u, v) is an
+    orthonormal basis of it with u horizontal (u = z x a, or east when the
+    sun is at the zenith).  The grid of ``texel``-sized squares covers the
+    box's projections along ``a`` and ``b`` (every intermediate projection
+    lies between them) with one texel of margin; texel (i, j) spans
+    [u0 + i h, u0 + (i + 1) h) x [v0 + j h, v0 + (j + 1) h)."""
+    a = np.asarray(a, np.float64) / np.linalg.norm(a)
+    b = np.asarray(b, np.float64) / np.linalg.norm(b)
+    h = float(texel)
+    u = np.cross([0.0, 0.0, 1.0], a)
+    u = u / np.linalg.norm(u) if np.linalg.norm(u) > 1e-9 else np.array([1.0, 0.0, 0.0])
+    v = np.cross(a, u)
+    x0, y0, z0, x1, y1, z1 = [float(t) for t in box]
+    corners = np.array([[x, y, z] for x in (x0, x1) for y in (y0, y1) for z in (z0, z1)])
+    c = float((corners @ a).min()) - 1.0
+    pu, pv = [], []
+    for d in (a, b):
+        p = sam_project(corners, a, c, d)
+        pu.append(p @ u)
+        pv.append(p @ v)
+    pu, pv = np.concatenate(pu), np.concatenate(pv)
+    u0 = np.floor(pu.min() / h) * h - h
+    v0 = np.floor(pv.min() / h) * h - h
+    nu = int(np.ceil((pu.max() - u0) / h)) + 1
+    nv = int(np.ceil((pv.max() - v0) / h)) + 1
+    return dict(a=a, u=u, v=v, c=c, u0=u0, v0=v0, h=h, nu=nu, nv=nv)
+
+
+def sam_project(x, a, c, d):
+    """Where the shadow of x falls on the plane {y : y.a = c} for sun
+    direction d: x - lam d with lam = (x.a - c) / (d.a), the distance along
+    the light, which is the depth the map compares."""
+    x = np.asarray(x, np.float64)
+    lam = (x @ a - c) / float(np.dot(d, a))
+    return x - lam[..., None] * d
+
+
+def _sam_depth(scene, X, d, grow=0.0):
+    """Per ray X + lam d (lam >= 0; X [m, 3] on the plane): the largest lam
+    at which it leaves a prism (the prism's face nearest the sun), -inf where
+    it meets none.  Each prism clipped as a convex solid (Cyrus-Beck): its
+    height slab and the inner half-plane of every footprint edge, all moved
+    outward by ``grow`` metres (negative: inward)."""
+    m = len(X)
+    best = np.full(m, -np.inf)
+    for k in range(scene.n_b):
+        f = scene.footprint(k).astype(np.float64)
+        H = float(scene.height[k])
+        lo = np.full(m, 0.0)
+        hi = np.full(m, np.inf)
+        # height slab -grow <= z <= H + grow (the sun is above the horizon: d_z > 0)
+        lo = np.maximum(lo, (-grow - X[:, 2]) / d[2])
+        hi = np.minimum(hi, (H + grow - X[:, 2]) / d[2])
+        ok = np.ones(m, bool)
+        for e in range(len(f)):
+            p0, p1 = f[e], f[(e + 1) % len(f)]
+            ex, ey = p1 - p0
+            # inside: cross(e, x - p0) >= -grow |e|, along the ray f0 + lam g
+            f0 = ex * (X[:, 1] - p0[1]) - ey * (X[:, 0] - p0[0]) + grow * np.hypot(ex, ey)
+            g = ex * d[1] - ey * d[0]
+            if g > 0:
+                lo = np.maximum(lo, -f0 / g)
+            elif g < 0:
+                hi = np.minimum(hi, -f0 / g)
+            else:
+                ok &= f0 >= 0
+        hit = ok & (lo <= hi)
+        best = np.where(hit, np.maximum(best, hi), best)
+    return best
+
+
+def sam_segments(path: OraclePath):
+    """Sample instants of each segment: an instant belongs to the segment
+    whose [start, end) holds it, the day's last segment also taking its
+    end.  Returns, per segment, the indices into the path's instants."""
+    out = []
+    for j in range(len(path.seg_t)):
+        ta, tb = path.seg_t[j]
+        day = path.seg_day[j]
+        last = j + 1 == len(path.seg_t) or path.seg_day[j + 1] != day
+        k = np.flatnonzero((path.sample_day == day) & (path.t >= ta) & ((path.t < tb) | (last & (path.t <= tb))))
+        out.append(k)
+    return out
+
+
+def sam(scene, pts, path: OraclePath, texel, bias=0.01, box=None, eps_texel=2e-3, eps_depth=1e-2, delta=5e-3):
+    """Gross shadow by shadow accrual maps (Sec. 4, Step 1 and Step 2), one
+    map per segment with a slice per sample instant: slice k holds, per
+    texel, the depth of the prisms' surface nearest the sun along the ray
+    from the texel's centre in that instant's direction (the great-circle
+    direction at the instant, as the accrual form assumes); a point is in
+    shadow at instant k when that depth at the texel its shadow falls on
+    exceeds its own depth by more than ``bias``.  ``box``: the region every
+    prism lies in, (x0, y0, z0, x1, y1, z1); None = the footprints' extent,
+    0 .. the tallest prism.
+
+    Returns counts int32 and minutes FP64 [n_bins, n], the decisions
+    ``shadowed`` uint8 [n, K], and a flag ``amb`` uint8 [n, K] marking
+    (point, instant) decisions a float32 evaluation may take
+    either way: the shadow within ``eps_texel`` texels of a texel edge, the
+    depths within ``eps_depth`` m of the bias margin, or a decision that
+    changes when every prism grows or shrinks by ``delta`` m."""
+    if box is None:
+        box = (scene.xy[:, 0].min(), scene.xy[:, 1].min(), 0.0,
+               scene.xy[:, 0].max(), scene.xy[:, 1].max(), scene.height.max()) if scene.n_b else None
+    n, K = pts.n, len(path.t)
+    counts = np.zeros((path.n_bins, n), np.int32)
+    minutes = np.zeros((path.n_bins, n), np.float64)
+    amb = np.zeros((n, K), np.uint8)
+    shadowed = np.zeros((n, K), np.uint8)
+    if box is None or n == 0:
+        return dict(counts=counts, minutes=minutes, shadowed=shadowed, amb=amb)
+    Q = np.stack([pts.x, pts.y, pts.z], 1).astype(np.float64)
+    for j, ks in enumerate(sam_segments(path)):
+        a, b = path.seg_dir[j]
+        ta, tb = path.seg_t[j]
+        G = sam_grid(box, a, b, texel)
+        for k in ks:
+            d = slerp(a, b, (path.t[k] - ta) / (tb - ta)) if tb > ta else G["a"]
+            lam = (Q @ G["a"] - G["c"]) / float(d @ G["a"])
+            P = Q - lam[:, None] * d
+            fu, fv = (P @ G["u"] - G["u0"]) / G["h"], (P @ G["v"] - G["v0"]) / G["h"]
+            i, jj = np.floor(fu), np.floor(fv)
+            inside = (i >= 0) & (i < G["nu"]) & (jj >= 0) & (jj < G["nv"])
+            X = G["c"] * G["a"] + (G["u0"] + (i + 0.5) * G["h"])[:, None] * G["u"] + \
+                (G["v0"] + (jj + 0.5) * G["h"])[:, None] * G["v"]
+            dep = {g: np.where(inside, _sam_depth(scene, X, d, g), -np.inf) for g in (0.0, delta, -delta)}
+            s = dep[0.0] > lam + bias
+            near_edge = np.minimum(np.minimum(fu - i, i + 1 - fu), np.minimum(fv - jj, jj + 1 - fv)) < eps_texel
+            near_depth = np.abs(dep[0.0] - lam - bias) <= eps_depth
+            unstable = (dep[delta] > lam + bias) != (dep[-delta] > lam + bias)
+            amb[:, k] = near_edge | near_depth | unstable
+            shadowed[:, k] = s
+            b_ = path.sample_bin[k]
+            counts[b_] += s
+            minutes[b_] += s * path.w[k]
+    return dict(counts=counts, minutes=minutes, shadowed=shadowed, amb=amb)
