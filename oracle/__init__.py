@@ -56,6 +56,7 @@ def lib():
                                        dp, C.c_int]
         L.orc_grad_implicit.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, ip, ip, C.c_double, dp, dp,
                                         C.c_int]
+        L.orc_exit_depths.argtypes = [C.c_void_p, C.c_int64, dp, dp, C.c_double, dp, C.c_int]
         _lib = L
     return _lib
 
@@ -418,7 +419,22 @@ def sam_project(x, a, c, d):
     return x - lam[..., None] * d
 
 
-def _sam_depth(scene, X, d, grow=0.0):
+def exit_depths(scene, X, d, grow=0.0):
+    """Per ray X + lam d (lam >= 0; X [m, 3]): the largest lam at which it
+    leaves a prism (the prism's face nearest the sun), -inf where it meets
+    none; brute force over every prism in C (``orc_exit_depths``), the same
+    steps as ``exit_depths_np``."""
+    s, ks = _scene(scene)
+    X = np.ascontiguousarray(X, np.float64).reshape(-1, 3)
+    d = np.ascontiguousarray(d, np.float64)
+    out = np.empty(len(X))
+    if len(X):
+        lib().orc_exit_depths(C.byref(s), len(X), _ptr(X, C.c_double), _ptr(d, C.c_double), float(grow),
+                              _ptr(out, C.c_double), threads_default())
+    return out
+
+
+def exit_depths_np(scene, X, d, grow=0.0):
     """Per ray X + lam d (lam >= 0; X [m, 3] on the plane): the largest lam
     at which it leaves a prism (the prism's face nearest the sun), -inf where
     it meets none.  Each prism clipped as a convex solid (Cyrus-Beck): its
@@ -507,7 +523,7 @@ def sam(scene, pts, path: OraclePath, texel, bias=0.01, box=None, eps_texel=2e-3
             inside = (i >= 0) & (i < G["nu"]) & (jj >= 0) & (jj < G["nv"])
             X = G["c"] * G["a"] + (G["u0"] + (i + 0.5) * G["h"])[:, None] * G["u"] + \
                 (G["v0"] + (jj + 0.5) * G["h"])[:, None] * G["v"]
-            dep = {g: np.where(inside, _sam_depth(scene, X, d, g), -np.inf) for g in (0.0, delta, -delta)}
+            dep = {g: np.where(inside, exit_depths(scene, X, d, g), -np.inf) for g in (0.0, delta, -delta)}
             s = dep[0.0] > lam + bias
             near_edge = np.minimum(np.minimum(fu - i, i + 1 - fu), np.minimum(fv - jj, jj + 1 - fv)) < eps_texel
             near_depth = np.abs(dep[0.0] - lam - bias) <= eps_depth

@@ -101,6 +101,13 @@ void orc_grad_implicit(const orc_scene *s, const orc_points *p, int n_seg,
 /* slerp on the great circle through a and b at constant angular rate */
 void orc_slerp(const double *a, const double *b, double f, double *out);
 
+/* ---- raster shadow accrual map (Sec. 4) ----
+ * Per ray X[3r..3r+2] + lam d, lam >= 0: the largest lam at which it leaves
+ * a prism (height slab and inner edge half-planes moved outward by grow m),
+ * -INFINITY where it meets none. */
+void orc_exit_depths(const orc_scene *s, int64_t m, const double *X, const double *d, double grow, double *out,
+                     int threads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -805,3 +805,51 @@ void orc_contribution(const orc_scene *s, const orc_points *p, int n_seg,
     parallel_for(p->n, threads, contrib_point, &C);
     scene64_free(&S);
 }
+
+/* ---- raster shadow accrual map depth (Sec. 4) ----
+ * For each ray X[r] + lam d (lam >= 0): the largest lam at which it leaves
+ * a prism, each prism a convex solid clipped by its height slab and the
+ * inner half-plane of every footprint edge, all moved outward by `grow`
+ * metres (negative: inward); -INFINITY where it meets none. */
+typedef struct {
+    const orc_scene *s;
+    const double *X, *d;
+    double grow;
+    double *out;
+} exit_ctx;
+
+static void exit_one(void *arg, int64_t r)
+{
+    const exit_ctx *E = (const exit_ctx *)arg;
+    const orc_scene *s = E->s;
+    const double *x = E->X + 3 * r, *d = E->d;
+    const double grow = E->grow;
+    double best = -INFINITY;
+    for (int b = 0; b < s->n_b; ++b) {
+        const int v0 = s->vert_off[b], v1 = s->vert_off[b + 1];
+        const double H = s->height[b];
+        double lo = fmax(0.0, (-grow - x[2]) / d[2]);
+        double hi = (H + grow - x[2]) / d[2];
+        int ok = 1;
+        for (int v = v0; v < v1 && ok; ++v) {
+            const int w = v + 1 < v1 ? v + 1 : v0;
+            const double p0x = s->xy[2 * v], p0y = s->xy[2 * v + 1];
+            const double ex = s->xy[2 * w] - p0x, ey = s->xy[2 * w + 1] - p0y;
+            /* inside: cross(e, x - p0) >= -grow |e|; along the ray f0 + lam g */
+            const double f0 = ex * (x[1] - p0y) - ey * (x[0] - p0x) + grow * sqrt(ex * ex + ey * ey);
+            const double g = ex * d[1] - ey * d[0];
+            if (g > 0.0) lo = fmax(lo, -f0 / g);
+            else if (g < 0.0) hi = fmin(hi, -f0 / g);
+            else if (f0 < 0.0) ok = 0;
+        }
+        if (ok && lo <= hi && hi > best) best = hi;
+    }
+    E->out[r] = best;
+}
+
+void orc_exit_depths(const orc_scene *s, int64_t m, const double *X, const double *d, double grow, double *out,
+                     int threads)
+{
+    exit_ctx E = {s, X, d, grow, out};
+    parallel_for(m, threads, exit_one, &E);
+}

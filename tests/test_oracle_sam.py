@@ -127,3 +127,17 @@ def test_error_falls_as_texels_shrink():
             exact[:, k] = [oracle.shadow(w.scene, (sub.x[i], sub.y[i], sub.z[i]), d) for i in range(sub.n)]
     miss = [float((oracle.sam(w.scene, sub, path, h)["shadowed"] != exact).mean()) for h in (4.0, 1.0, 0.25)]
     assert miss[0] > miss[1] > miss[2] and miss[2] < 0.01, miss
+
+
+def test_exit_depths_c_equals_numpy():
+    """The C brute force and the numpy statement of the map depth agree on
+    random rays through the small scene, grown, shrunk and as is."""
+    w = make_c1()
+    rng = np.random.default_rng(5)
+    X = np.c_[rng.uniform(-50, 560, 3000), rng.uniform(-50, 560, 3000), rng.uniform(-200, 0, 3000)]
+    for d in ([0.3, -0.2, 0.9], [-0.8, 0.1, 0.3]):
+        d = np.array(d) / np.linalg.norm(d)
+        for g in (0.0, 0.005, -0.005):
+            a, b = oracle.exit_depths(w.scene, X, d, g), oracle.exit_depths_np(w.scene, X, d, g)
+            assert np.isfinite(a).sum() > 100
+            np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-9)
