@@ -183,12 +183,15 @@ sa_status sa_sunpath(const sa_site *site, const sa_timespan *span, sa_sunpath_bu
 sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out);
 
 /* As sa_path_upload, with the direction graph of Sec. 6 for the accrual
- * form: the hemisphere is cut into cells of at most bound_deg (rings of
- * that height in elevation, each cut into azimuth cells of at most that
- * width), and segments of one output bin whose start and end knots fall in
- * the same pair of cells become one edge, computed once from the first of
- * them and weighted by their number (Eq. 2).  Each merged segment keeps its
- * own duration; sample counts are the edge's times its multiplicity.  An
+ * form: the hemisphere is cut into cells of about bound_deg (rings of
+ * that height in elevation, each cut into the fewest equal azimuth sectors
+ * no wider than bound_deg at the ring's lower edge), and segments of one
+ * output bin whose start and end knots fall in the same pair of cells
+ * become one edge, computed once from the first of them and weighted by
+ * their number (Eq. 2).  Each merged segment keeps its own duration; sample
+ * counts are the edge's times its multiplicity.  Every accrual-form call
+ * takes the graph: sa_accumulate, sa_accumulate_batched,
+ * sa_building_contribution and sa_grad_heights.  An
  * approximation for exploring long spans: a representative direction up to
  * about bound_deg away shifts shadow transitions by bound_deg over the
  * sun's angular speed (about 0.25 degrees per minute).  The sampled form
@@ -308,6 +311,37 @@ sa_status sa_grad_heights(sa_ctx *ctx, const sa_scene *scene, const sa_points *p
  * Errors: INVALID_ARG, DEVICE. */
 sa_status sa_building_contribution(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts,
                                    const sa_path *path, const float *weight, double *contrib);
+
+typedef struct {
+    float texel_m;       /* texel edge on the shadow plane, metres (> 0) */
+    float bias_m;        /* depth margin of the shadow test, metres (>= 0) */
+    float box[6];        /* x0, y0, z0, x1, y1, z1: a box that holds every prism; all zero =
+                            the footprints' extent, 0 .. the tallest height the scene has had */
+    uint32_t flags;      /* SA_FLAG_ADD */
+    float out_scale;     /* minutes are multiplied by this (0 = 1) */
+    int64_t max_texels;  /* cap on one segment's map, slices x texels (0 = 2^31) */
+} sa_sam_opts;
+
+/* Gross shadow by raster shadow accrual maps (Sec. 4), the exploration
+ * form: per path segment one map with a depth slice per sample instant
+ * (the instant's direction on the great circle between the knots, as in
+ * the accrual form), over a grid of texel_m squares on a plane normal to
+ * the segment's start direction, 1 m behind the box corner farthest from
+ * the sun.  Step 1 fills every slice in one pass over (slice, prism) pairs:
+ * a texel holds the largest distance along the light at which the ray from
+ * its centre toward the sun leaves a prism.  Step 2 puts each point's
+ * shadow on every slice and counts the instants whose stored depth exceeds
+ * the point's own by more than bias_m.  A raster approximation of
+ * sa_accumulate's sampled form, exact as texel_m -> 0 away from shadow
+ * edges; prisms outside `box` are missed.  Points: ground-type only (any
+ * z; pts->owner, nx and ny must be NULL: walls would shade themselves).
+ * Outputs as sa_accumulate (counts int32, minutes float, [n_bins * n],
+ * either may be NULL).  The library keeps one segment's map in memory the
+ * context owns, grown on first need.  Not for direction-graph paths.
+ * Errors: INVALID_ARG, CAPACITY (a map above max_texels), OOM, DEVICE. */
+sa_status sa_sam_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts,
+                            const sa_path *path, const sa_sam_opts *opts, int32_t *counts,
+                            float *minutes);
 
 /* Daylight minutes of every output bin of a path: the sum of its days'
  * spans.  span: host double [n_bins].  Errors: INVALID_ARG. */

@@ -30,7 +30,7 @@ EXPORTS = ["sa_create", "sa_destroy", "sa_set_stream", "sa_last_error", "sa_sync
            "sa_scene_upload", "sa_scene_set_heights", "sa_scene_get_info", "sa_scene_read_bvh",
            "sa_scene_destroy", "sa_sunpath", "sa_path_upload", "sa_path_upload_graph", "sa_path_info", "sa_path_destroy",
            "sa_accumulate", "sa_accumulate_batched", "sa_grad_heights", "sa_region_sum",
-           "sa_building_contribution", "sa_path_bin_span", "sa_region_score"]
+           "sa_building_contribution", "sa_path_bin_span", "sa_region_score", "sa_sam_accumulate"]
 
 
 class SAError(RuntimeError):
@@ -65,6 +65,11 @@ class sa_scene_info(C.Structure):
 class sa_points(C.Structure):
     _fields_ = [("n", C.c_int64), ("x", C.c_void_p), ("y", C.c_void_p), ("z", C.c_void_p),
                 ("nx", C.c_void_p), ("ny", C.c_void_p), ("owner", C.c_void_p)]
+
+
+class sa_sam_opts(C.Structure):
+    _fields_ = [("texel_m", C.c_float), ("bias_m", C.c_float), ("box", C.c_float * 6), ("flags", C.c_uint32),
+                ("out_scale", C.c_float), ("max_texels", C.c_int64)]
 
 
 class sa_accum_opts(C.Structure):
@@ -106,6 +111,7 @@ def lib():
             "sa_grad_heights": (i32, [vp, vp, C.POINTER(sa_points), vp, vp, vp]),
             "sa_region_sum": (i32, [vp, vp, i64, vp, i32, vp, vp]),
             "sa_building_contribution": (i32, [vp, vp, C.POINTER(sa_points), vp, vp, vp]),
+            "sa_sam_accumulate": (i32, [vp, vp, C.POINTER(sa_points), vp, C.POINTER(sa_sam_opts), vp, vp]),
             "sa_path_bin_span": (i32, [vp, vp]),
             "sa_region_score": (i32, [vp, vp, i32, i64, vp, vp, i32, vp, vp]),
         }
@@ -368,6 +374,16 @@ class DevicePoints:
         return cls(f(pts.x), f(pts.y), f(pts.z), f(pts.nx), f(pts.ny),
                    torch.from_numpy(np.ascontiguousarray(pts.owner, np.int32)).to(device))
 
+    @classmethod
+    def ground_from_workload(cls, pts, device="cuda"):
+        """Positions only, for the raster form (which takes ground-type
+        points); refuses points with an owner or a facade normal."""
+        import torch
+        if np.any(pts.owner >= 0) or np.any(pts.nx != 0) or np.any(pts.ny != 0):
+            raise ValueError("ground-type points only (no owner, no facade normal)")
+        f = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+        return cls(f(pts.x), f(pts.y), f(pts.z))
+
     def struct(self) -> sa_points:
         return sa_points(self.n, _ptr(self.x), _ptr(self.y), _ptr(self.z), _ptr(self.nx), _ptr(self.ny),
                          _ptr(self.owner))
@@ -435,6 +451,29 @@ def sa_building_contribution(ctx: Context, scene: Scene, pts: DevicePoints, path
     ps = pts.struct()
     _check(ctx, lib().sa_building_contribution(ctx.handle, scene.handle, C.byref(ps), path.handle, _ptr(weight),
                                                _ptr(contrib)))
+
+
+def sa_sam_accumulate(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, texel, counts=None, minutes=None,
+                      bias=0.01, box=None, flags=0, out_scale=1.0, max_texels=0):
+    """Gross shadow by raster shadow accrual maps (Sec. 4) into device
+    outputs [bins, n]; ``box``: (x0, y0, z0, x1, y1, z1) holding every prism
+    (None: the scene's own extent)."""
+    b = (C.c_float * 6)(*([0.0] * 6 if box is None else [float(v) for v in box]))
+    opts = sa_sam_opts(float(texel), float(bias), b, flags, out_scale, int(max_texels))
+    ps = pts.struct()
+    _check(ctx, lib().sa_sam_accumulate(ctx.handle, scene.handle, C.byref(ps), path.handle, C.byref(opts),
+                                        _ptr(counts), _ptr(minutes)))
+
+
+def sam_accumulate(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, texel, bias=0.01, box=None):
+    """Allocate outputs and run sa_sam_accumulate: (counts int32, minutes
+    float32), both [bins, n]."""
+    torch = ctx.torch
+    dev = f"cuda:{ctx.device}"
+    counts = torch.empty((path.n_bins, pts.n), dtype=torch.int32, device=dev)
+    minutes = torch.empty((path.n_bins, pts.n), dtype=torch.float32, device=dev)
+    sa_sam_accumulate(ctx, scene, pts, path, texel, counts, minutes, bias=bias, box=box)
+    return counts, minutes
 
 
 def building_contribution(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, weight=None):

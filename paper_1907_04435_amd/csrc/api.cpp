@@ -22,6 +22,7 @@ struct sa_ctx {
     sa::Scratch scratch;          // region sums
     sa::Scratch scratch_batched;  // per-variant hierarchy copies
     sa::Scratch scratch_seg;      // per-segment node views of the accrual form
+    sa::Scratch scratch_sam;      // one segment's raster shadow accrual map
 };
 
 struct sa_scene {
@@ -127,6 +128,7 @@ void sa_destroy(sa_ctx *ctx)
     (void)hipFree(ctx->scratch.ptr);
     (void)hipFree(ctx->scratch_batched.ptr);
     (void)hipFree(ctx->scratch_seg.ptr);
+    (void)hipFree(ctx->scratch_sam.ptr);
     delete ctx;
 }
 
@@ -365,6 +367,8 @@ sa_status path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, s
     std::vector<sa::SampleConst> samples(in->n_samples);
     std::vector<sa::SegConst> segs;
     std::vector<std::array<double, 6>> seg_knots;  // knot directions of each segment
+    std::vector<sa::SamSegHost> seg_host;          // the raster form's per-segment record
+    std::vector<sa::SamSlice> sam(in->n_samples);  // and its slice per instant
     std::vector<int32_t> day_seg_off;
     std::vector<double> bin_span;  // daylight minutes per bin: the instants' weights add up to each day's span
     int n_bins = 0;
@@ -460,6 +464,32 @@ sa_status path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, s
             g.mdy = (float)(a[1] + e2[1] * 0.5 * theta);
             segs.push_back(g);
             seg_knots.push_back({a[0], a[1], a[2], b[0], b[1], b[2]});
+            // raster slices (Sec. 4): each instant's direction on the great
+            // circle from a to b at its share of the segment's time
+            sa::SamSegHost sh;
+            for (int i = 0; i < 3; ++i) {
+                sh.a[i] = a[i];
+                sh.b[i] = b[i];
+            }
+            sh.ta = ta;
+            sh.tb = tb;
+            sh.first = first >= 0 ? first : 0;
+            sh.ns = ns;
+            sh.bin = bin;
+            seg_host.push_back(sh);
+            for (int s = sh.first; s < sh.first + ns; ++s) {
+                const double f = (in->t_min[s] - ta) / (tb - ta);
+                // sin(theta) = sn: a and b are unit vectors
+                const double wa = std::sin((1.0 - f) * theta) / sn, wb = std::sin(f * theta) / sn;
+                const double dd[3] = {wa * a[0] + wb * b[0], wa * a[1] + wb * b[1], wa * a[2] + wb * b[2]};
+                sa::SamSlice &q = sam[s];
+                std::memset(&q, 0, sizeof(q));
+                q.dx = (float)dd[0];
+                q.dy = (float)dd[1];
+                q.dz = (float)dd[2];
+                q.inv_da = (float)(1.0 / (dd[0] * a[0] + dd[1] * a[1] + dd[2] * a[2]));
+                q.w = (float)in->weight[s];
+            }
         }
     }
     bool merged = false;
@@ -483,6 +513,11 @@ sa_status path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, s
     day_seg_off.push_back((int32_t)segs.size());
     p->d.day_seg_off = std::move(day_seg_off);
     p->d.merged = merged;
+    if (!merged) {
+        p->d.seg_host = std::move(seg_host);
+        p->d.sample_t.assign(in->t_min, in->t_min + in->n_samples);
+        p->d.sample_w.assign(in->weight, in->weight + in->n_samples);
+    }
     bin_span.resize(n_bins, 0.0);
     p->d.bin_span = std::move(bin_span);
     p->d.words = (in->n_samples + 31) / 32;
@@ -492,6 +527,11 @@ sa_status path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, s
         if (e == hipSuccess)
             e = hipMemcpy(p->d.samples, samples.data(), sizeof(sa::SampleConst) * samples.size(),
                           hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && !merged && !sam.empty()) {
+        e = hipMalloc((void **)&p->d.sam_slices, sizeof(sa::SamSlice) * sam.size());
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d.sam_slices, sam.data(), sizeof(sa::SamSlice) * sam.size(), hipMemcpyHostToDevice);
     }
     if (e == hipSuccess && !segs.empty()) {
         e = hipMalloc((void **)&p->d.segs, sizeof(sa::SegConst) * segs.size());
@@ -536,6 +576,7 @@ void sa_path_destroy(sa_path *path)
     if (!path) return;
     (void)hipSetDevice(path->device);
     (void)hipFree(path->d.samples);
+    (void)hipFree(path->d.sam_slices);
     (void)hipFree(path->d.segs);
     delete path;
 }
@@ -690,6 +731,52 @@ sa_status sa_building_contribution(sa_ctx *ctx, const sa_scene *scene, const sa_
     if (rc == SA_OK)
         rc = sa::launch_contribution(scene->d, path->d, view(pts), weight, contrib, ctx->scratch_seg, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_building_contribution: " + err);
+    return SA_OK;
+}
+
+sa_status sa_sam_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts, const sa_path *path,
+                            const sa_sam_opts *opts, int32_t *counts, float *minutes)
+{
+    if (!ctx) return SA_ERR_INVALID_ARG;
+    if (!scene || !path || !opts) return fail(ctx, SA_ERR_INVALID_ARG, "sa_sam_accumulate: null argument");
+    sa_status rc = check_points(ctx, pts);
+    if (rc != SA_OK) return rc;
+    if (pts->owner || pts->nx || pts->ny)
+        return fail(ctx, SA_ERR_INVALID_ARG,
+                    "sa_sam_accumulate: ground-type points only (no owner or facade normal arrays)");
+    if (!(opts->texel_m > 0.f) || !(opts->bias_m >= 0.f) || !std::isfinite(opts->texel_m) ||
+        !std::isfinite(opts->bias_m))
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_sam_accumulate: texel must be > 0 and bias >= 0");
+    if (path->d.merged)
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_sam_accumulate: a direction-graph path has no instants per segment");
+    double box[6];
+    bool given = false;
+    for (int i = 0; i < 6; ++i) {
+        box[i] = opts->box[i];
+        given = given || opts->box[i] != 0.f;
+    }
+    if (!given) {
+        box[0] = scene->d.bounds[0];
+        box[1] = scene->d.bounds[1];
+        box[2] = 0.0;
+        box[3] = scene->d.bounds[2];
+        box[4] = scene->d.bounds[3];
+        box[5] = scene->d.max_h;
+    }
+    for (int i = 0; i < 6; ++i)
+        if (!std::isfinite(box[i])) return fail(ctx, SA_ERR_INVALID_ARG, "sa_sam_accumulate: box not finite");
+    if (!(box[3] >= box[0] && box[4] >= box[1] && box[5] >= box[2]))
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_sam_accumulate: empty box");
+    if (!counts && !minutes) return SA_OK;
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    rc = clear_outputs(ctx, opts->flags, (int64_t)path->d.n_bins * pts->n, counts, minutes);
+    if (rc != SA_OK) return rc;
+    const float scale = opts->out_scale == 0.f ? 1.f : opts->out_scale;
+    const int64_t cap = opts->max_texels > 0 ? opts->max_texels : (int64_t)1 << 31;
+    std::string err;
+    rc = sa::launch_sam(scene->d, path->d, view(pts), opts->texel_m, opts->bias_m, box, cap, scale, counts, minutes,
+                        ctx->scratch_sam, ctx->stream, err);
+    if (rc != SA_OK) return fail(ctx, rc, err);
     return SA_OK;
 }
 

@@ -96,14 +96,50 @@ struct DeviceScene {
     float4 *pbox = nullptr;      // [n_b] prism footprint boxes, hierarchy order
 };
 
+// Raster shadow accrual map (Sec. 4) of one segment: the shadow plane
+// (normal a, the segment's start direction) and its texel grid, float32,
+// every coordinate relative to the box centre o.
+struct SamGrid {
+    float ax, ay, az;  // plane normal
+    float ux, uy, uz;  // in-plane basis, u horizontal
+    float vx, vy, vz;
+    float c;           // plane: (x - o).a = c
+    float u0, v0;      // grid corner in (u, v)
+    float h, inv_h;    // texel edge and its inverse
+    int32_t nu, nv;    // texels along u and v
+    float ox, oy, oz;  // o, world coordinates
+    float bias;        // depth margin of the shadow test (m)
+};
+
+// One slice: an instant's direction on the great circle between the
+// segment's knots, 1 / (d.a) (distance along the light per distance from
+// the plane), and the instant's minutes.
+struct SamSlice {
+    float dx, dy, dz, inv_da;
+    float w;
+    int32_t pad[3];
+};
+
+struct SamSegHost {
+    double a[3], b[3];  // knot directions
+    double ta, tb;      // knot times (local minutes)
+    int32_t first, ns;  // its sample instants
+    int32_t bin;
+};
+
 struct DevicePath {
     int32_t n_days = 0, n_samples = 0, n_segs = 0, n_bins = 0;
     SampleConst *samples = nullptr;  // [n_samples]
+    SamSlice *sam_slices = nullptr;  // [n_samples] raster slices (unmerged paths)
     SegConst *segs = nullptr;        // [n_segs]
     int32_t words = 0;               // ceil(n_samples / 32)
     std::vector<int32_t> day_seg_off;  // host: first segment of each day, [n_days + 1]
     std::vector<double> bin_span;      // host: daylight minutes of each output bin
     bool merged = false;               // host: segments merged into direction-graph edges
+    // host, for the raster form: each segment's knot directions, times, its
+    // instants [first, first + ns) and bin; every instant's time and weight
+    std::vector<SamSegHost> seg_host;
+    std::vector<double> sample_t, sample_w;
 };
 
 // Host-side builders implemented in the .hip sources.
@@ -154,6 +190,12 @@ sa_status launch_contribution(const DeviceScene &s, const DevicePath &p, const P
 sa_status build_seg_views(const DeviceScene &s, const DevicePath &p, int j0, int j1, int64_t stride, Scratch &scr,
                           hipStream_t st, SegNode *&views, std::string &err);
 int64_t seg_views_cap(const DeviceScene &s);
+// Gross shadow by raster shadow accrual maps (Sec. 4) into counts/minutes
+// [n_bins * n] (already cleared): per segment a map of slices x nu x nv
+// depths in scr (grown as needed; max_texels caps one segment's map).
+sa_status launch_sam(const DeviceScene &s, const DevicePath &p, const PointsView &pts, double texel,
+                     double bias, const double box[6], int64_t max_texels, float scale, int32_t *counts,
+                     float *minutes, Scratch &scr, hipStream_t st, std::string &err);
 sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_var, int32_t k,
                          const int32_t *ids, const float *h, const PointsView &pts,
                          const int64_t *var_off, float scale, int32_t *counts, float *minutes,
