@@ -10,7 +10,7 @@ import pytest
 
 import oracle
 import paper_1907_04435_amd as sa
-from workloads import Span, make_c1, make_c2, subset_points
+from workloads import Span, make_c1, make_c2, make_c3, subset_points
 from workloads.scenes import Day, _nyc_tz
 
 from gpu_util import say
@@ -78,6 +78,53 @@ def test_graph_matches_oracle(ctx):
         f"largest {mult}); per point-day |d| p99.9 {np.quantile(d, 0.999):.2e} mean {d.mean():.2e} max {d.max():.2e}")
     assert n_edges == len(groups) and mult > 1
     assert np.quantile(d, 0.999) <= 0.01 and d.mean() <= 1e-3 and d.max() <= 0.5
+
+
+def test_exact_merge_in_every_accrual_entry_point(ctx, block):
+    """The June solstice three times in one bin: every edge stands for three
+    identical segments, so building contributions, the height adjoint and
+    batched variants over the graph equal those over the plain path (up to
+    the order of float sums)."""
+    import torch
+    scene, pts = block
+    sp = sa.sunpath_for_span(days_span([dt.date(2019, 6, 21)] * 3, [0, 0, 0]), 30.0)
+    plain, graph = sa.Path(ctx, sp), sa.Path(ctx, sp, graph_bound_deg=0.5)
+    assert graph.n_segments * 3 == plain.n_segments
+    sc = sa.Scene.from_workload(ctx, scene)
+    dp = sa.DevicePoints.from_workload(pts)
+    k0 = sa.building_contribution(ctx, sc, dp, plain).cpu().numpy()
+    k1 = sa.building_contribution(ctx, sc, dp, graph).cpu().numpy()
+    g0 = torch.empty(scene.n_b, dtype=torch.float32, device="cuda")
+    g1 = torch.empty_like(g0)
+    sa.sa_grad_heights(ctx, sc, dp, plain, None, g0)
+    sa.sa_grad_heights(ctx, sc, dp, graph, None, g1)
+    ctx.sync()
+    g0, g1 = g0.cpu().numpy(), g1.cpu().numpy()
+    say(f"exact merge: contribution max rel {np.abs(k1 - k0).max() / np.abs(k0).max():.2e}, "
+        f"gradient max rel {np.abs(g1 - g0).max() / np.abs(g0).max():.2e}")
+    assert (k0 > 0).sum() > 20 and (np.abs(g0) > 0).sum() > 20
+    np.testing.assert_allclose(k1, k0, rtol=1e-5, atol=1e-6 * np.abs(k0).max())
+    np.testing.assert_allclose(g1, g0, rtol=1e-4, atol=1e-5 * np.abs(g0).max())
+
+    w = make_c3(n_var=4)
+    bsp = sa.sunpath_for_span(Span(w.span.lat, w.span.lon, [w.span.days[0]] * 3, w.span.step_min, [0, 0, 0]), 30.0)
+    outs = []
+    for path in (sa.Path(ctx, bsp), sa.Path(ctx, bsp, graph_bound_deg=0.5)):
+        bsc = sa.Scene.from_workload(ctx, w.scene)
+        bdp = sa.DevicePoints.from_workload(w.points)
+        ids = torch.from_numpy(w.extra["var_ids"].astype(np.int32)).cuda()
+        h = torch.from_numpy(w.extra["var_h"].astype(np.float32)).cuda()
+        off = torch.from_numpy(w.extra["var_off"].astype(np.int64)).cuda()
+        c = torch.empty((path.n_bins, bdp.n), dtype=torch.int32, device="cuda")
+        m = torch.empty((path.n_bins, bdp.n), dtype=torch.float32, device="cuda")
+        sa.sa_accumulate_batched(ctx, bsc, ids, h, bdp, off, path, c, m)
+        ctx.sync()
+        outs.append((c.cpu().numpy(), m.cpu().numpy().astype(np.float64)))
+    (c0, m0), (c1, m1) = outs
+    say(f"exact merge, batched: {m0.shape[1]} points, max |dmin| {np.abs(m1 - m0).max():.2e}")
+    assert m0.max() > 0
+    assert np.array_equal(c0, c1)
+    np.testing.assert_allclose(m1, m0, rtol=1e-6, atol=1e-3)
 
 
 def test_tiny_cells_keep_every_segment(ctx, block):
