@@ -180,6 +180,45 @@ def bench_c4(args, sa, torch):
     return r
 
 
+def bench_sam(args, sa, torch):
+    """Raster shadow accrual maps (Sec. 4), the exploration form: the block
+    scene's 2M ground points over June 21 at 1-minute instants, knots every
+    ``--seg`` minutes, ``--texel`` m texels; agreement with the sampled
+    form (a ray per instant along the actual sun direction) on the same
+    points and instants."""
+    from workloads import Span, make_c2
+    w = make_c2(n_facade=0)
+    span = Span(w.span.lat, w.span.lon, [w.span.days[1]], w.span.step_min)
+    ctx = sa.Context(0)
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    path = sa.Path(ctx, sa.sunpath_for_span(span, args.seg))
+    dp = sa.DevicePoints.ground_from_workload(w.points)
+    counts = torch.empty((1, dp.n), dtype=torch.int32, device="cuda")
+    mins = torch.empty((1, dp.n), dtype=torch.float32, device="cuda")
+    run = lambda: sa.sa_sam_accumulate(ctx, sc, dp, path, args.texel, counts, mins)
+    for _ in range(args.warmup):
+        run()
+    ctx.sync()
+    steps = max(1, min(args.steps, 3))
+    ms = _timed(torch, ctx.stream, run, steps)
+    ctx.sync()
+    m = float(np.mean(ms))
+    cs = torch.empty_like(counts)
+    sa.sa_accumulate(ctx, sc, sa.DevicePoints.from_workload(w.points), path, sa.SA_SAMPLED, cs, None)
+    ctx.sync()
+    d = (counts.long() - cs.long()).abs().double()
+    evals = dp.n * path.n_samples
+    log(f"sam: {m:.1f} ms per pass at {args.texel} m texels; |count - sampled| mean {float(d.mean()):.3f}")
+    r = _base("point-sun-step evals/s (raster shadow accrual maps)", evals / (m / 1e3), "point-sun-steps/s", args, m,
+              {"workload": "block scene ground points, Jun 21", "points": dp.n, "buildings": w.scene.n_b,
+               "instants_per_point": path.n_samples, "seg_min": args.seg, "texel_m": args.texel,
+               "point_sun_steps": evals})
+    r["steps"] = steps
+    r["vs_sampled_form"] = {"mean_abs_count_diff": float(d.mean()), "share_of_points_differing": float((d > 0).double().mean()),
+                            "mean_count": float(counts.double().mean()), "mean_count_sampled": float(cs.double().mean())}
+    return r
+
+
 def bench_c5(args, sa, torch):
     """Year-long accumulation: 45k prisms, 16M ground points, all 365 days
     of 2019 at 1-minute instants, four season bins of hours."""
@@ -249,9 +288,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seg", type=float, default=30.0, help="accrual knot spacing, minutes")
     ap.add_argument("--sampled-steps", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "sam"],
                     help="c2 (default): the block scene, both forms; c3 batched variants; "
-                         "c4 forward + height adjoint; c5 year-long season bins; c1 the small scene")
+                         "c4 forward + height adjoint; c5 year-long season bins; c1 the small scene; "
+                         "sam the raster shadow accrual maps on the block scene's ground points")
+    ap.add_argument("--texel", type=float, default=2.0, help="sam: texel edge on the shadow plane, metres")
     ap.add_argument("--grid-blocks", type=int, default=0, help="batched persistent launch size (0: tuned/default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-work-count", action="store_true")
@@ -284,8 +325,8 @@ def main():
         return
     import paper_1907_04435_amd as sa
     from workloads import make_c1, make_c2
-    if args.workload in ("c3", "c4", "c5"):
-        res = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5}[args.workload](args, sa, torch)
+    if args.workload in ("c3", "c4", "c5", "sam"):
+        res = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "sam": bench_sam}[args.workload](args, sa, torch)
         print(json.dumps(res), flush=True)
         return
 

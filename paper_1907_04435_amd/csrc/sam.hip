@@ -28,11 +28,37 @@ __global__ void k_sam_clear(uint32_t *p, int64_t n)
 
 // One wave per (slice, prism): the wave covers the texels of the prism's
 // shadow on the plane (the box of its vertices' projections, clamped to the
-// grid), each lane clipping the ray from its texel centre against the prism
-// (height slab and every footprint edge's inner half-plane).  Depths are
-// positive (the plane lies behind every prism), so their bits order as
-// unsigned integers and an integer maximum keeps the nearest-to-sun face;
-// 0 marks a texel no prism covers.
+// grid) in 8 x 8 tiles, kTilesPerPass at a time in row order, each lane
+// clipping the ray from its texel centre against the prism (height slab
+// and every footprint edge's inner half-plane).  Within the box every
+// clipping bound is an affine function of the texel's offset (i', j') from
+// the box corner: the lanes first project one vertex each and form one
+// edge's three coefficients each, then every pass reads an edge's
+// coefficients from its lane and pays two FMAs and a min or max per texel.
+// Depths are positive (the plane lies behind every prism), so their bits
+// order as unsigned integers and an integer maximum keeps the
+// nearest-to-sun face; 0 marks a texel no prism covers.
+constexpr int kTilesPerPass = 4;
+
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ float lane_value(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 __global__ __launch_bounds__(kThreads) void k_sam_build(const float4 *__restrict__ verts,
                                                         const int32_t *__restrict__ voff,
                                                         const float *__restrict__ height, int n_b, SamGrid g,
@@ -40,6 +66,7 @@ __global__ __launch_bounds__(kThreads) void k_sam_build(const float4 *__restrict
                                                         uint32_t *__restrict__ map)
 {
     const int lane = threadIdx.x & 63;
+    const int lx = lane & 7, ly = lane >> 3;
     const int64_t items = (int64_t)K * n_b;
     const int64_t T = (int64_t)g.nu * g.nv;
     const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
@@ -48,26 +75,34 @@ __global__ __launch_bounds__(kThreads) void k_sam_build(const float4 *__restrict
         const int k = (int)(it / n_b);
         const int b = (int)(it - (int64_t)k * n_b);
         const SamSlice s = slices[k];
-        const int e0 = voff[b], e1 = voff[b + 1];
+        const int e0 = voff[b], ne = voff[b + 1] - e0;
         const float H = height[b];
         const float zlo = -g.oz, zhi = H - g.oz;
-        // the prism's shadow: hull of its 2 x nv vertices' projections
+        // the prism's shadow: hull of its 2 x ne vertices' projections, a
+        // vertex per lane
         float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
-        for (int e = e0; e < e1; ++e) {
-            const float4 q = verts[e];
-            const float rx = q.x - g.ox, ry = q.y - g.oy;
-            for (int top = 0; top < 2; ++top) {
-                const float rz = top ? zhi : zlo;
-                const float lam = (rx * g.ax + ry * g.ay + rz * g.az - g.c) * s.inv_da;
-                const float px = rx - lam * s.dx, py = ry - lam * s.dy, pz = rz - lam * s.dz;
-                const float pu = px * g.ux + py * g.uy + pz * g.uz;
-                const float pv = px * g.vx + py * g.vy + pz * g.vz;
-                umin = fminf(umin, pu);
-                umax = fmaxf(umax, pu);
-                vmin = fminf(vmin, pv);
-                vmax = fmaxf(vmax, pv);
+        for (int c = 0; c < ne; c += 64) {
+            if (c + lane < ne) {
+                const float4 q = verts[e0 + c + lane];
+                const float rx = q.x - g.ox, ry = q.y - g.oy;
+#pragma unroll
+                for (int top = 0; top < 2; ++top) {
+                    const float rz = top ? zhi : zlo;
+                    const float lam = (rx * g.ax + ry * g.ay + rz * g.az - g.c) * s.inv_da;
+                    const float px = rx - lam * s.dx, py = ry - lam * s.dy, pz = rz - lam * s.dz;
+                    const float pu = px * g.ux + py * g.uy + pz * g.uz;
+                    const float pv = px * g.vx + py * g.vy + pz * g.vz;
+                    umin = fminf(umin, pu);
+                    umax = fmaxf(umax, pu);
+                    vmin = fminf(vmin, pv);
+                    vmax = fmaxf(vmax, pv);
+                }
             }
         }
+        umin = wave_min(umin);
+        umax = wave_max(umax);
+        vmin = wave_min(vmin);
+        vmax = wave_max(vmax);
         // a centimetre of slack against the rounding of the projections;
         // clamped in float before the conversion to integers
         const float fi0 = fmaxf(floorf((umin - 0.01f - g.u0) * g.inv_h), 0.f);
@@ -75,29 +110,105 @@ __global__ __launch_bounds__(kThreads) void k_sam_build(const float4 *__restrict
         const float fj0 = fmaxf(floorf((vmin - 0.01f - g.v0) * g.inv_h), 0.f);
         const float fj1 = fminf(floorf((vmax + 0.01f - g.v0) * g.inv_h), (float)(g.nv - 1));
         if (!(fi0 <= fi1 && fj0 <= fj1)) continue;
-        const int i0 = (int)fi0, j0 = (int)fj0;
-        const int W = (int)fi1 - i0 + 1;
-        const int64_t cnt = (int64_t)W * ((int)fj1 - j0 + 1);
+        const int i0 = __builtin_amdgcn_readfirstlane((int)fi0), j0 = __builtin_amdgcn_readfirstlane((int)fj0);
+        const int W = __builtin_amdgcn_readfirstlane((int)fi1) - i0 + 1;
+        const int Hh = __builtin_amdgcn_readfirstlane((int)fj1) - j0 + 1;
+        const int tx_n = (W + 7) >> 3, ty_n = (Hh + 7) >> 3;
         uint32_t *slice = map + (int64_t)k * T;
-        for (int64_t t = lane; t < cnt; t += 64) {
-            const int i = i0 + (int)(t % W), j = j0 + (int)(t / W);
-            const float cu = g.u0 + ((float)i + 0.5f) * g.h, cv = g.v0 + ((float)j + 0.5f) * g.h;
-            const float X = g.c * g.ax + cu * g.ux + cv * g.vx;
-            const float Y = g.c * g.ay + cu * g.uy + cv * g.vy;
-            const float Z = g.c * g.az + cu * g.uz + cv * g.vz;
-            // the sun is above the horizon: s.dz > 0
-            float lo = fmaxf(0.f, (zlo - Z) / s.dz), hi = (zhi - Z) / s.dz;
-            bool ok = true;
-            for (int e = e0; e < e1; ++e) {
-                // (q.z, q.w): the edge's outward normal; inside: n.(x - p0) <= 0
-                const float4 q = verts[e];
-                const float f0 = q.z * (X - (q.x - g.ox)) + q.w * (Y - (q.y - g.oy));
+        // the ray from the centre of texel (i0 + i', j0 + j'):
+        // X0 + i' h u + j' h v + lam d
+        const float cu0 = g.u0 + ((float)i0 + 0.5f) * g.h, cv0 = g.v0 + ((float)j0 + 0.5f) * g.h;
+        const float X0 = g.c * g.ax + cu0 * g.ux + cv0 * g.vx;
+        const float Y0 = g.c * g.ay + cu0 * g.uy + cv0 * g.vy;
+        const float Z0 = g.c * g.az + cu0 * g.uz + cv0 * g.vz;
+        // height slab: lam in [(zlo - Z) / dz, (zhi - Z) / dz]; the sun is
+        // above the horizon (dz > 0)
+        const float inv_dz = 1.f / s.dz;
+        const float zl0 = (zlo - Z0) * inv_dz, zh0 = (zhi - Z0) * inv_dz;
+        const float zi = -g.h * g.uz * inv_dz, zj = -g.h * g.vz * inv_dz;
+        const int n_tiles = tx_n * ty_n;
+        const float fi = (float)lx, fj = (float)ly;
+        const float zl = fmaf(zj, fj, fmaf(zi, fi, zl0)), zh = fmaf(zj, fj, fmaf(zi, fi, zh0));
+        // edge c + lane: along the ray its inner-side function is
+        // f0 + fu i' + fv j' + lam gd (n.(x - p0) with n the outward normal;
+        // inside where <= 0).  kind 1: gd > 0, the crossing
+        // lam = A + B i' + C j' bounds lam from above; kind -1: from below;
+        // kind 0: parallel, (A, B, C) = (f0, fu, fv) must stay <= 0.
+        auto edge_coef = [&](int c, float &eA, float &eB, float &eC, int &kind) {
+            eA = eB = eC = 0.f;
+            kind = 0;
+            if (c + lane < ne) {
+                const float4 q = verts[e0 + c + lane];
+                const float f0 = q.z * (X0 - (q.x - g.ox)) + q.w * (Y0 - (q.y - g.oy));
+                const float fu = g.h * (q.z * g.ux + q.w * g.uy), fv = g.h * (q.z * g.vx + q.w * g.vy);
                 const float gd = q.z * s.dx + q.w * s.dy;
-                if (gd > 0.f) hi = fminf(hi, -f0 / gd);
-                else if (gd < 0.f) lo = fmaxf(lo, -f0 / gd);
-                else ok = ok && f0 <= 0.f;
+                if (gd != 0.f) {
+                    const float rg = -1.f / gd;
+                    eA = f0 * rg;
+                    eB = fu * rg;
+                    eC = fv * rg;
+                    kind = gd > 0.f ? 1 : -1;
+                } else {
+                    eA = f0;
+                    eB = fu;
+                    eC = fv;
+                }
             }
-            if (ok && lo <= hi) atomicMax(slice + (int64_t)j * g.nu + i, __float_as_uint(hi));
+        };
+        float eA0, eB0, eC0;
+        int kind0;
+        edge_coef(0, eA0, eB0, eC0, kind0);  // the first 64 edges, once per (slice, prism)
+        for (int t0 = 0; t0 < n_tiles; t0 += kTilesPerPass) {
+            // the pass's tiles in row order: offsets (in texels) of each
+            // tile's corner, the same for every lane
+            float ox[kTilesPerPass], oy[kTilesPerPass];
+            int tx = t0 % tx_n, ty = t0 / tx_n;
+#pragma unroll
+            for (int r = 0; r < kTilesPerPass; ++r) {
+                ox[r] = (float)(8 * tx);
+                oy[r] = (float)(8 * ty);
+                if (++tx == tx_n) {
+                    tx = 0;
+                    ++ty;
+                }
+            }
+            float lo[kTilesPerPass], hi[kTilesPerPass];
+#pragma unroll
+            for (int r = 0; r < kTilesPerPass; ++r) {
+                lo[r] = fmaxf(0.f, fmaf(zj, oy[r], fmaf(zi, ox[r], zl)));
+                hi[r] = fmaf(zj, oy[r], fmaf(zi, ox[r], zh));
+            }
+            for (int c = 0; c < ne; c += 64) {
+                float eA = eA0, eB = eB0, eC = eC0;
+                int kind = kind0;
+                if (c > 0) edge_coef(c, eA, eB, eC, kind);  // footprints beyond 64 vertices
+                const int m_n = min(64, ne - c);
+                for (int m = 0; m < m_n; ++m) {
+                    const float A = lane_value(eA, m), B = lane_value(eB, m), Cv = lane_value(eC, m);
+                    const int kd = __builtin_amdgcn_readlane(kind, m);
+                    const float base = fmaf(B, fi, fmaf(Cv, fj, A));
+                    if (kd > 0) {
+#pragma unroll
+                        for (int r = 0; r < kTilesPerPass; ++r)
+                            hi[r] = fminf(hi[r], fmaf(Cv, oy[r], fmaf(B, ox[r], base)));
+                    } else if (kd < 0) {
+#pragma unroll
+                        for (int r = 0; r < kTilesPerPass; ++r)
+                            lo[r] = fmaxf(lo[r], fmaf(Cv, oy[r], fmaf(B, ox[r], base)));
+                    } else {
+                        // parallel to the edge: outside it, no hit
+#pragma unroll
+                        for (int r = 0; r < kTilesPerPass; ++r)
+                            if (fmaf(Cv, oy[r], fmaf(B, ox[r], base)) > 0.f) lo[r] = INFINITY;
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < kTilesPerPass; ++r) {
+                const int ii = (int)ox[r] + lx, jj = (int)oy[r] + ly;
+                if (t0 + r < n_tiles && ii < W && jj < Hh && lo[r] <= hi[r])
+                    atomicMax(slice + (int64_t)(j0 + jj) * g.nu + (i0 + ii), __float_as_uint(hi[r]));
+            }
         }
     }
 }
