@@ -23,6 +23,7 @@ struct sa_ctx {
     sa::Scratch scratch_batched;  // per-variant hierarchy copies
     sa::Scratch scratch_seg;      // per-segment node views of the accrual form
     sa::Scratch scratch_sam;      // one segment's raster shadow accrual map
+    uint32_t sam_stamp = 0;       // the last segment stamp written into it
 };
 
 struct sa_scene {
@@ -775,7 +776,7 @@ sa_status sa_sam_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points 
     const int64_t cap = opts->max_texels > 0 ? opts->max_texels : (int64_t)1 << 31;
     std::string err;
     rc = sa::launch_sam(scene->d, path->d, view(pts), opts->texel_m, opts->bias_m, box, cap, scale, counts, minutes,
-                        ctx->scratch_sam, ctx->stream, err);
+                        ctx->scratch_sam, ctx->sam_stamp, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, err);
     return SA_OK;
 }

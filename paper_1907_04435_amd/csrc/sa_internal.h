@@ -192,10 +192,12 @@ sa_status build_seg_views(const DeviceScene &s, const DevicePath &p, int j0, int
 int64_t seg_views_cap(const DeviceScene &s);
 // Gross shadow by raster shadow accrual maps (Sec. 4) into counts/minutes
 // [n_bins * n] (already cleared): per segment a map of slices x nu x nv
-// depths in scr (grown as needed; max_texels caps one segment's map).
+// 64-bit words (stamp, depth) in scr (grown as needed; max_texels caps one
+// segment's map); stamp: the last segment stamp written into scr, kept by
+// the caller with scr.
 sa_status launch_sam(const DeviceScene &s, const DevicePath &p, const PointsView &pts, double texel,
                      double bias, const double box[6], int64_t max_texels, float scale, int32_t *counts,
-                     float *minutes, Scratch &scr, hipStream_t st, std::string &err);
+                     float *minutes, Scratch &scr, uint32_t &stamp, hipStream_t st, std::string &err);
 sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_var, int32_t k,
                          const int32_t *ids, const float *h, const PointsView &pts,
                          const int64_t *var_off, float scale, int32_t *counts, float *minutes,

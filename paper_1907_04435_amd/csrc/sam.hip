@@ -5,7 +5,10 @@
 // largest distance along the light at which the ray from the texel centre
 // toward the sun leaves a prism (its face nearest the sun).  Step 2 puts
 // each point's shadow on every slice and counts the instants whose stored
-// depth exceeds the point's own by more than the bias.
+// depth exceeds the point's own by more than the bias.  Map words are 64
+// bits: a segment stamp above the depth bits, so an integer maximum keeps
+// the current segment's nearest-to-sun depth over any stale word and the
+// map is cleared only when it is allocated or the stamp wraps.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,8 +39,8 @@ __global__ void k_sam_clear(uint32_t *p, int64_t n)
 // edge's three coefficients each, then every pass reads an edge's
 // coefficients from its lane and pays two FMAs and a min or max per texel.
 // Depths are positive (the plane lies behind every prism), so their bits
-// order as unsigned integers and an integer maximum keeps the
-// nearest-to-sun face; 0 marks a texel no prism covers.
+// order as unsigned integers; with the segment's stamp above them a 64-bit
+// integer maximum keeps the nearest-to-sun face of this segment.
 constexpr int kTilesPerPass = 4;
 
 __device__ __forceinline__ float wave_min(float v)
@@ -63,10 +66,11 @@ __global__ __launch_bounds__(kThreads) void k_sam_build(const float4 *__restrict
                                                         const int32_t *__restrict__ voff,
                                                         const float *__restrict__ height, int n_b, SamGrid g,
                                                         const SamSlice *__restrict__ slices, int K,
-                                                        uint32_t *__restrict__ map)
+                                                        unsigned long long *__restrict__ map, uint32_t stamp)
 {
     const int lane = threadIdx.x & 63;
     const int lx = lane & 7, ly = lane >> 3;
+    const unsigned long long tag = (unsigned long long)stamp << 32;
     const int64_t items = (int64_t)K * n_b;
     const int64_t T = (int64_t)g.nu * g.nv;
     const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
@@ -114,7 +118,7 @@ __global__ __launch_bounds__(kThreads) void k_sam_build(const float4 *__restrict
         const int W = __builtin_amdgcn_readfirstlane((int)fi1) - i0 + 1;
         const int Hh = __builtin_amdgcn_readfirstlane((int)fj1) - j0 + 1;
         const int tx_n = (W + 7) >> 3, ty_n = (Hh + 7) >> 3;
-        uint32_t *slice = map + (int64_t)k * T;
+        unsigned long long *slice = map + (int64_t)k * T;
         // the ray from the centre of texel (i0 + i', j0 + j'):
         // X0 + i' h u + j' h v + lam d
         const float cu0 = g.u0 + ((float)i0 + 0.5f) * g.h, cv0 = g.v0 + ((float)j0 + 0.5f) * g.h;
@@ -207,19 +211,20 @@ __global__ __launch_bounds__(kThreads) void k_sam_build(const float4 *__restrict
             for (int r = 0; r < kTilesPerPass; ++r) {
                 const int ii = (int)ox[r] + lx, jj = (int)oy[r] + ly;
                 if (t0 + r < n_tiles && ii < W && jj < Hh && lo[r] <= hi[r])
-                    atomicMax(slice + (int64_t)(j0 + jj) * g.nu + (i0 + ii), __float_as_uint(hi[r]));
+                    atomicMax(slice + (int64_t)(j0 + jj) * g.nu + (i0 + ii), tag | __float_as_uint(hi[r]));
             }
         }
     }
 }
 
 // One thread per point: its shadow on each slice, the stored depth there
-// against its own depth plus the bias; the segment's counts and minutes
-// added to the point's bin.
+// (if written for this segment) against its own depth plus the bias; the
+// segment's counts and minutes added to the point's bin.
 __global__ __launch_bounds__(kThreads) void k_sam_query(const float *__restrict__ px, const float *__restrict__ py,
                                                         const float *__restrict__ pz, int64_t n, SamGrid g,
                                                         const SamSlice *__restrict__ slices, int K,
-                                                        const uint32_t *__restrict__ map, int bin, float scale,
+                                                        const unsigned long long *__restrict__ map, uint32_t stamp,
+                                                        int bin, float scale,
                                                         int32_t *__restrict__ counts, float *__restrict__ minutes)
 {
     const int64_t T = (int64_t)g.nu * g.nv;
@@ -236,8 +241,9 @@ __global__ __launch_bounds__(kThreads) void k_sam_query(const float *__restrict_
             const float fu = floorf((qx * g.ux + qy * g.uy + qz * g.uz - g.u0) * g.inv_h);
             const float fv = floorf((qx * g.vx + qy * g.vy + qz * g.vz - g.v0) * g.inv_h);
             if (fu >= 0.f && fu < (float)g.nu && fv >= 0.f && fv < (float)g.nv) {
-                const uint32_t m = map[(int64_t)k * T + (int64_t)fv * g.nu + (int64_t)fu];
-                if (m != 0u && __uint_as_float(m) > lam + g.bias) {
+                // a word of an earlier segment (another stamp) is empty here
+                const unsigned long long m = map[(int64_t)k * T + (int64_t)fv * g.nu + (int64_t)fu];
+                if ((uint32_t)(m >> 32) == stamp && __uint_as_float((uint32_t)m) > lam + g.bias) {
                     ++cnt;
                     mins += s.w;
                 }
@@ -328,7 +334,7 @@ bool sam_grid(const double box[6], const double *a, const double *b, double h, d
 
 sa_status launch_sam(const DeviceScene &s, const DevicePath &p, const PointsView &pts, double texel,
                      double bias, const double box[6], int64_t max_texels, float scale, int32_t *counts,
-                     float *minutes, Scratch &scr, hipStream_t st, std::string &err)
+                     float *minutes, Scratch &scr, uint32_t &stamp, hipStream_t st, std::string &err)
 {
     if (s.n_b == 0 || pts.n == 0 || p.n_samples == 0) return SA_OK;
     if (!p.sam_slices || p.seg_host.size() != (size_t)p.n_segs) {
@@ -354,7 +360,13 @@ sa_status launch_sam(const DeviceScene &s, const DevicePath &p, const PointsView
         }
         most = std::max(most, (int64_t)grids[j].nu * grids[j].nv * sh.ns);
     }
-    const size_t need = (size_t)most * sizeof(uint32_t);
+    const size_t need = (size_t)most * sizeof(unsigned long long);
+    auto clear_all = [&]() {
+        const int64_t words = (int64_t)(scr.bytes / sizeof(uint32_t));
+        hipLaunchKernelGGL(k_sam_clear, dim3((unsigned)std::min<int64_t>((words + kThreads - 1) / kThreads, 65536)),
+                           dim3(kThreads), 0, st, (uint32_t *)scr.ptr, words);
+        stamp = 0;
+    };
     if (scr.bytes < need) {
         // the previous contents may still be read by queued kernels
         (void)hipStreamSynchronize(st);
@@ -367,26 +379,29 @@ sa_status launch_sam(const DeviceScene &s, const DevicePath &p, const PointsView
             return SA_ERR_OOM;
         }
         scr.bytes = need;
+        clear_all();
+        SA_CHECK_LAUNCH("raster map clear");
     }
-    uint32_t *map = (uint32_t *)scr.ptr;
+    unsigned long long *map = (unsigned long long *)scr.ptr;
     const unsigned qblocks = (unsigned)std::min<int64_t>((pts.n + kThreads - 1) / kThreads, 16384);
     for (size_t j = 0; j < p.seg_host.size(); ++j) {
         const SamSegHost &sh = p.seg_host[j];
         if (sh.ns == 0) continue;
         const SamGrid &g = grids[j];
-        const int64_t texels = (int64_t)g.nu * g.nv * sh.ns;
         const SamSlice *sl = p.sam_slices + sh.first;
-        hipLaunchKernelGGL(k_sam_clear, dim3((unsigned)std::min<int64_t>((texels + kThreads - 1) / kThreads, 65536)),
-                           dim3(kThreads), 0, st, map, texels);
-        SA_CHECK_LAUNCH("raster map clear");
+        if (stamp == 0xffffffffu) {
+            clear_all();
+            SA_CHECK_LAUNCH("raster map clear");
+        }
+        ++stamp;
         const int64_t items = (int64_t)sh.ns * s.n_b;
         hipLaunchKernelGGL(k_sam_build,
                            dim3((unsigned)std::min<int64_t>((items + kWavesPerBlock - 1) / kWavesPerBlock, 32768)),
                            dim3(kThreads), 0, st, (const float4 *)s.verts, (const int32_t *)s.voff,
-                           (const float *)s.height, s.n_b, g, sl, sh.ns, map);
+                           (const float *)s.height, s.n_b, g, sl, sh.ns, map, stamp);
         SA_CHECK_LAUNCH("raster map build");
         hipLaunchKernelGGL(k_sam_query, dim3(qblocks), dim3(kThreads), 0, st, pts.x, pts.y, pts.z, pts.n, g, sl,
-                           sh.ns, (const uint32_t *)map, sh.bin, scale, counts, minutes);
+                           sh.ns, (const unsigned long long *)map, stamp, sh.bin, scale, counts, minutes);
         SA_CHECK_LAUNCH("raster map query");
     }
     return SA_OK;

@@ -132,3 +132,24 @@ def test_sam_edge_cases(ctx):
     assert e.value.code == -3
     with pytest.raises(ValueError):
         sa.DevicePoints.ground_from_workload(make_c2(n_ground=0, n_facade=100).points)
+
+
+def test_sam_repeated_calls_reuse_the_map(ctx):
+    """One context, three calls: 1 m texels, then 0.5 m (a larger map, a
+    new buffer), then 1 m again over the stale words of both: the last call
+    equals the first exactly (words of earlier segments carry older stamps
+    and read as empty)."""
+    w = make_c1()
+    sub = w.points.take(subset_points(w.points, 512, 84))
+    say("sam repeated calls on one context: 1 m, 0.5 m, 1 m")
+    path = sa.Path(ctx, sa.sunpath_for_span(w.span, 30.0))
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    dp = sa.DevicePoints.ground_from_workload(sub)
+    c1, m1 = sa.sam_accumulate(ctx, sc, dp, path, 1.0)
+    c2, m2 = sa.sam_accumulate(ctx, sc, dp, path, 0.5)
+    c3, m3 = sa.sam_accumulate(ctx, sc, dp, path, 1.0)
+    ctx.sync()
+    assert int(c1.sum()) > 0
+    assert np.array_equal(c1.cpu().numpy(), c3.cpu().numpy())
+    assert np.array_equal(m1.cpu().numpy(), m3.cpu().numpy())
+    assert not np.array_equal(c1.cpu().numpy(), c2.cpu().numpy())
