@@ -153,3 +153,32 @@ def test_sam_repeated_calls_reuse_the_map(ctx):
     assert np.array_equal(c1.cpu().numpy(), c3.cpu().numpy())
     assert np.array_equal(m1.cpu().numpy(), m3.cpu().numpy())
     assert not np.array_equal(c1.cpu().numpy(), c2.cpu().numpy())
+
+
+def test_sam_bench_configuration_sampled_points(ctx):
+    """The configuration the raster bench times (the block scene's 2M
+    ground points, June 21 at 1-minute instants, 30-minute knots, 2 m
+    texels, the scene's own box), run on every point; 32 seeded points
+    checked against the oracle's map one by one."""
+    w = make_c2(n_facade=0)
+    span = Span(w.span.lat, w.span.lon, [w.span.days[1]], w.span.step_min)
+    say(f"sam at the bench configuration: {w.points.n} points, 2 m texels")
+    path = sa.Path(ctx, sa.sunpath_for_span(span, 30.0))
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    dp = sa.DevicePoints.ground_from_workload(w.points)
+    c, m = sa.sam_accumulate(ctx, sc, dp, path, 2.0)
+    ctx.sync()
+    idx = subset_points(w.points, 32, 85)
+    c, m = c.cpu().numpy()[:, idx], m.cpu().numpy()[:, idx].astype(np.float64)
+    sub = w.points.take(idx)
+    opath = oracle.sun_path(span, 30.0)
+    o = oracle.sam(w.scene, sub, opath, 2.0, box=box_of(w.scene))
+    n_amb = o["amb"].sum(1)[None, :]
+    w_amb = (o["amb"] * opath.w[None, :]).sum(1)[None, :]
+    dc = np.abs(c.astype(np.int64) - o["counts"])
+    say(f"  {o['amb'].mean():.2%} ambiguous; counts differ at {(dc > 0).sum()} of {dc.size} points; "
+        f"mean count {c.mean():.1f} oracle {o['counts'].mean():.1f}")
+    assert o["counts"].sum() > 0
+    assert np.array_equal(c[n_amb == 0], o["counts"][n_amb == 0])
+    assert np.all(dc <= n_amb)
+    assert np.all(np.abs(m - o["minutes"]) <= w_amb + 1e-3 * (1 + o["minutes"]))
