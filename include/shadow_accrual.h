@@ -196,7 +196,7 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out);
  * about bound_deg away shifts shadow transitions by bound_deg over the
  * sun's angular speed (about 0.25 degrees per minute).  The sampled form
  * is unaffected; the continuous shadow needs time order and is refused
- * (INVALID_ARG).  bound_deg in (0, 90].  Errors as sa_path_upload. */
+ * (INVALID_ARG).  bound_deg in [1e-6, 90].  Errors as sa_path_upload. */
 sa_status sa_path_upload_graph(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, sa_path **out);
 sa_status sa_path_info(const sa_path *path, int32_t *n_bins, int32_t *n_samples,
                        int32_t *n_segments);

@@ -328,7 +328,8 @@ def hemisphere_cell(d, bound_deg):
     sky is cut into cells of bounded angular size (Sec. 6 bins the sun's
     directions so): rings of ``bound`` in elevation, each ring cut into the
     fewest equal azimuth sectors whose width at the ring's lower edge is at
-    most ``bound``.  int64 key: ring * 4,000,000 + sector."""
+    most ``bound``.  int64 key: ring * 2^32 + sector (a ring has fewer
+    than 2^32 sectors for bounds of at least 1e-6 degrees)."""
     b = np.radians(float(bound_deg))
     d = np.asarray(d, np.float64)
     el = np.arcsin(np.clip(d[..., 2], -1.0, 1.0))
@@ -336,7 +337,7 @@ def hemisphere_cell(d, bound_deg):
     ring = np.floor(el / b).astype(np.int64)
     n_sec = np.maximum(1, np.ceil(2.0 * np.pi * np.cos(ring * b) / b)).astype(np.int64)
     sec = np.minimum(np.floor((az + np.pi) / (2.0 * np.pi) * n_sec).astype(np.int64), n_sec - 1)
-    return ring * 4_000_000 + sec
+    return ring * (1 << 32) + sec
 
 
 def direction_graph(path: OraclePath, bound_deg):

@@ -329,7 +329,8 @@ void merge_segments(std::vector<sa::SegConst> &segs, const std::vector<std::arra
         const int64_t naz =
             std::max<int64_t>(1, (int64_t)std::ceil(2.0 * M_PI * std::cos((double)ring * bound) / bound));
         const int64_t c = (int64_t)std::floor((az + M_PI) / (2.0 * M_PI) * (double)naz);
-        return ring * 4000000 + std::min(c, naz - 1);
+        // a ring has fewer than 2^32 sectors for bounds >= 1e-6 degrees
+        return ring * ((int64_t)1 << 32) + std::min(c, naz - 1);
     };
     std::map<std::tuple<int32_t, int64_t, int64_t>, size_t> edge;
     std::vector<sa::SegConst> out;
@@ -558,8 +559,8 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out)
 
 sa_status sa_path_upload_graph(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, sa_path **out)
 {
-    if (!(bound_deg > 0.0 && bound_deg <= 90.0))
-        return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload_graph: bound must be in (0, 90] degrees");
+    if (!(bound_deg >= 1e-6 && bound_deg <= 90.0))
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload_graph: bound must be in [1e-6, 90] degrees");
     return path_upload(ctx, in, bound_deg, out);
 }
 

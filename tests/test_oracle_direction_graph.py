@@ -62,6 +62,25 @@ def test_cells_split_by_azimuth_and_elevation():
     assert c(d(1.0, 11.0), b) == c(d(1.0 + 1e-6, 11.0 + 1e-6), b)
 
 
+def test_cell_keys_of_adjacent_rings_differ_at_the_smallest_bound():
+    """At 1e-6 degrees a ring holds about 3.6e8 sectors: sector 4,000,005 of
+    one ring and sector 5 of the next must still have different keys (a
+    key of ring * 4,000,000 + sector would make them equal)."""
+    bd = 1e-6
+    b = np.radians(bd)
+    r = 1000
+    n_sec = int(np.ceil(2 * np.pi * np.cos(r * b) / b))
+    def d(ring, sec, n):
+        el = (ring + 0.5) * b
+        az = (sec + 0.5) / n * 2 * np.pi - np.pi
+        return np.array([np.cos(el) * np.sin(az), np.cos(el) * np.cos(az), np.sin(el)])
+    n2 = int(np.ceil(2 * np.pi * np.cos((r + 1) * b) / b))
+    k1 = oracle.hemisphere_cell(d(r, 4_000_005, n_sec), bd)
+    k2 = oracle.hemisphere_cell(d(r + 1, 5, n2), bd)
+    assert k1 // (1 << 32) == r and k2 // (1 << 32) == r + 1
+    assert k1 != k2
+
+
 def _small():
     w = make_c1()
     return w, w.points.take(subset_points(w.points, 200, 7))
@@ -74,7 +93,7 @@ def _span(dates, bins):
 def test_tiny_cells_give_the_continuous_form():
     w, pts = _small()
     path = oracle.sun_path(_span([dt.date(2019, 3, 20), dt.date(2019, 6, 21)], [0, 1]), 30.0)
-    g, groups = oracle.graph_continuous(w.scene, pts, path, 1e-7)
+    g, groups = oracle.graph_continuous(w.scene, pts, path, 1e-6)
     assert len(groups) == len(path.seg_t)
     np.testing.assert_allclose(g, oracle.continuous(w.scene, pts, path)["minutes"], rtol=1e-12, atol=1e-9)
 
