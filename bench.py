@@ -214,6 +214,21 @@ def bench_sam(args, sa, torch):
                "instants_per_point": path.n_samples, "seg_min": args.seg, "texel_m": args.texel,
                "point_sun_steps": evals})
     r["steps"] = steps
+    if not args.no_cpu_baseline:
+        # the oracle's raster form on a bounded seeded sample of the same points
+        import oracle
+        from workloads import subset_points
+        sub = w.points.take(subset_points(w.points, 16, 13))
+        box = (float(w.scene.xy[:, 0].min()), float(w.scene.xy[:, 1].min()), 0.0,
+               float(w.scene.xy[:, 0].max()), float(w.scene.xy[:, 1].max()), float(w.scene.height.max()))
+        opath = oracle.sun_path(span, args.seg)
+        t = time.perf_counter()
+        oracle.sam(w.scene, sub, opath, args.texel, box=box)
+        dt = time.perf_counter() - t
+        r["cpu_baseline"] = {"value": sub.n * len(opath.w) / dt, "unit": "point-sun-steps/s",
+                             "cores": oracle.threads_default(), "kind": "oracle",
+                             "sample": f"{sub.n} ground points (seeded) x {len(opath.w)} instants x {w.scene.n_b} "
+                                       f"prisms, raster form with its ambiguity test, {dt:.1f} s"}
     r["vs_sampled_form"] = {"mean_abs_count_diff": float(d.mean()), "share_of_points_differing": float((d > 0).double().mean()),
                             "mean_count": float(counts.double().mean()), "mean_count_sampled": float(cs.double().mean())}
     return r
