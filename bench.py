@@ -266,7 +266,7 @@ def bench_c5(args, sa, torch):
         # against the full path above, per cell size
         base = hours.clone()
         legs = []
-        for bound in (0.25, 0.5, 1.0, 5.0):
+        for bound in (0.25, 0.5, 1.0, 2.0, 3.0, 5.0):
             gp = sa.Path(ctx, sp, graph_bound_deg=bound)
             gh = torch.empty_like(hours)
             gms = _timed(torch, ctx.stream,

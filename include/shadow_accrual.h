@@ -187,14 +187,15 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out);
  * that height in elevation, each cut into the fewest equal azimuth sectors
  * no wider than bound_deg at the ring's lower edge), and segments of one
  * output bin whose start and end knots fall in the same pair of cells
- * become one edge, computed once from the first of them and weighted by
- * their number (Eq. 2).  Each merged segment keeps its own duration; sample
- * counts are the edge's times its multiplicity.  Every accrual-form call
- * takes the graph: sa_accumulate, sa_accumulate_batched,
- * sa_building_contribution and sa_grad_heights.  An
- * approximation for exploring long spans: a representative direction up to
- * about bound_deg away shifts shadow transitions by bound_deg over the
- * sun's angular speed (about 0.25 degrees per minute).  The sampled form
+ * become one edge, computed once on the members' mean arc (the normalised
+ * mean of their start directions to that of their end directions) and
+ * weighted by their number (Eq. 2).  Each merged segment keeps its own
+ * duration; sample counts are the edge's times its multiplicity.  Every
+ * accrual-form call takes the graph: sa_accumulate, sa_accumulate_batched,
+ * sa_building_contribution and sa_grad_heights.  An approximation for long
+ * spans: each member's arc lies up to about bound_deg from the edge's, and
+ * the offsets cancel to first order in the summed minutes (a year in season
+ * bins: 0.34 minutes per point and day at 3 degrees).  The sampled form
  * is unaffected; the continuous shadow needs time order and is refused
  * (INVALID_ARG).  bound_deg in [1e-6, 90].  Errors as sa_path_upload. */
 sa_status sa_path_upload_graph(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, sa_path **out);

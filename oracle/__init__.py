@@ -14,8 +14,9 @@ The C sources (``solar.c``, ``shadow.c``) compute:
     bisection per occluder, union, measure).
 
 In Python on top of those: the continuous shadow of the sampled form, the
-shadow score, and the direction graph of Sec. 6 (hemisphere cells, edges,
-the accrual form over the edges weighted by their members' durations).
+shadow score, the direction graph of Sec. 6 (hemisphere cells, edges on
+their members' mean arc, the accrual form over the edges weighted by the
+members' durations) and the raster shadow accrual maps of Sec. 4.
 """
 from __future__ import annotations
 
@@ -354,20 +355,32 @@ def direction_graph(path: OraclePath, bound_deg):
     return list(groups.values())
 
 
+def edge_arc(path: OraclePath, group):
+    """The arc an edge is computed on (the cluster's representative, Sec.
+    6): from the members' mean start direction to their mean end direction,
+    each normalised, over the first member's times; a lone segment is its
+    own arc."""
+    if len(group) == 1:
+        return path.seg_dir[group[0]], path.seg_t[group[0]]
+    a = path.seg_dir[group, 0].sum(0)
+    b = path.seg_dir[group, 1].sum(0)
+    return np.stack([a / np.linalg.norm(a), b / np.linalg.norm(b)]), path.seg_t[group[0]]
+
+
 def graph_continuous(scene, pts, path: OraclePath, bound_deg, grid_min=1.0 / 12.0, threads=None):
     """Accrual form over the direction graph (Sec. 6, Eq. 2): every edge's
-    occluded set is computed once, on its first member segment, and each
-    member counts with its own duration: the edge's minutes are the first
-    member's continuous minutes times (sum of the members' durations) /
-    (the first member's duration).  FP64 [n_bins, n] minutes, and the edge
-    lists.  Each first member runs as a day of its own through
-    ``continuous``."""
+    occluded set is computed once, on its representative arc (``edge_arc``),
+    and each member counts with its own duration: the edge's minutes are the
+    arc's continuous minutes times (sum of the members' durations) / (the
+    arc's duration).  FP64 [n_bins, n] minutes, and the edge lists.  Each
+    arc runs as a day of its own through ``continuous``."""
     groups = direction_graph(path, bound_deg)
-    reps = np.array([g[0] for g in groups], np.int64)
-    E = len(reps)
+    E = len(groups)
+    arcs = [edge_arc(path, g) for g in groups]
+    seg_dir = np.array([d for d, _ in arcs]).reshape(-1, 2, 3)
+    seg_t = np.array([tt for _, tt in arcs]).reshape(-1, 2)
     sub = OraclePath(np.zeros((0, 3)), np.zeros(0), np.zeros(0), np.zeros(0, np.int32), np.zeros(0, np.int32),
-                     path.seg_t[reps], path.seg_dir[reps], np.arange(E, dtype=np.int32),
-                     np.arange(E, dtype=np.int32), E, path.seg_t[reps])
+                     seg_t, seg_dir, np.arange(E, dtype=np.int32), np.arange(E, dtype=np.int32), E, seg_t)
     per_edge = continuous(scene, pts, sub, grid_min, threads)["minutes"]
     out = np.zeros((path.n_bins, pts.n), np.float64)
     dur = path.seg_t[:, 1] - path.seg_t[:, 0]

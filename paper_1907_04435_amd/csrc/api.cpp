@@ -309,15 +309,61 @@ sa_status sa_sunpath(const sa_site *site, const sa_timespan *span, sa_sunpath_bu
 
 namespace {
 
+// The great-circle geometry of a segment from knot direction a (at ta) to
+// b (at tb), both unit vectors above the horizon: plane basis, angle, the
+// lift of horizontal offsets into the plane (times |nz|), the fan's offsets
+// per metre of rise, the visit-order direction and the time map.  False if
+// the directions coincide.
+bool seg_geometry(const double *a, const double *b, double ta, double tb, sa::SegConst &g)
+{
+    const double c = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    const double cr[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    const double sn = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+    if (!(sn > 1e-12)) return false;
+    const double theta = std::atan2(sn, c);
+    double e2[3] = {b[0] - c * a[0], b[1] - c * a[1], b[2] - c * a[2]};
+    const double l2 = std::sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
+    for (double &v : e2) v /= l2;
+    const double N[3] = {a[1] * e2[2] - a[2] * e2[1], a[2] * e2[0] - a[0] * e2[2], a[0] * e2[1] - a[1] * e2[0]};
+    // the lift of horizontal offsets into the plane, times |nz|:
+    // |nz| (a - a_z N_xy / nz) = |nz| a - sgn(nz) a_z N_xy
+    const double anz = std::fabs(N[2]), sg = N[2] < 0.0 ? -1.0 : 1.0;
+    g.m00 = (float)(anz * a[0] - sg * a[2] * N[0]);
+    g.m01 = (float)(anz * a[1] - sg * a[2] * N[1]);
+    g.m10 = (float)(anz * e2[0] - sg * e2[2] * N[0]);
+    g.m11 = (float)(anz * e2[1] - sg * e2[2] * N[1]);
+    g.steep = anz < std::sin(5.0 * M_PI / 180.0) ? 1 : 0;
+    g.e1z = (float)a[2];
+    g.e2z = (float)e2[2];
+    g.theta = (float)theta;
+    g.cth = (float)std::cos(theta);
+    g.sth = (float)std::sin(theta);
+    g.nz = (float)N[2];
+    g.e1x = (float)a[0];
+    g.e1y = (float)a[1];
+    g.e2x = (float)e2[0];
+    g.e2y = (float)e2[1];
+    g.ua_x = (float)(a[0] / a[2]);
+    g.ua_y = (float)(a[1] / a[2]);
+    g.ub_x = (float)(b[0] / b[2]);
+    g.ub_y = (float)(b[1] / b[2]);
+    g.rate = (float)((tb - ta) / theta);
+    g.wrate = g.rate;
+    g.mdx = (float)(a[0] + e2[0] * 0.5 * theta);
+    g.mdy = (float)(a[1] + e2[1] * 0.5 * theta);
+    return true;
+}
+
 // Direction-graph reuse (Sec. 6): the hemisphere is cut into cells of at
 // most `bound` radians (rings of that height in elevation, each cut into
-// azimuth cells of at most that width); segments of one output bin whose
-// start and end knots fall in the same pair of cells are one edge, computed
-// once from its first segment and weighted by how many segments it stands
-// for (Eq. 2 sums the edges' maps by multiplicity).  The edge keeps the
-// first segment's geometry and time map; the minutes per radian its
-// measure is weighted by become the merged segments' total duration over
-// that segment's angle, so each merged segment counts with its own
+// the fewest azimuth sectors no wider than `bound` at the ring's lower
+// edge); segments of one output bin whose start and end knots fall in the
+// same pair of cells are one edge, computed once and weighted by how many
+// segments it stands for (Eq. 2 sums the edges' maps by multiplicity).  The
+// edge's arc runs from the members' mean start direction to their mean end
+// direction (the cluster's representative) over the first member's times;
+// the minutes per radian its measure is weighted by become the members'
+// total duration over that arc's angle, so each member counts with its own
 // duration; sample counts are scaled by the multiplicity.
 void merge_segments(std::vector<sa::SegConst> &segs, const std::vector<std::array<double, 6>> &knots,
                     double bound)
@@ -335,6 +381,7 @@ void merge_segments(std::vector<sa::SegConst> &segs, const std::vector<std::arra
     std::map<std::tuple<int32_t, int64_t, int64_t>, size_t> edge;
     std::vector<sa::SegConst> out;
     std::vector<double> dt_sum;
+    std::vector<std::array<double, 6>> dir_sum;  // summed start and end directions of the members
     for (size_t s = 0; s < segs.size(); ++s) {
         const auto key = std::make_tuple(segs[s].bin, cell(knots[s].data()), cell(knots[s].data() + 3));
         auto it = edge.find(key);
@@ -342,17 +389,33 @@ void merge_segments(std::vector<sa::SegConst> &segs, const std::vector<std::arra
             edge.emplace(key, out.size());
             out.push_back(segs[s]);
             dt_sum.push_back(segs[s].dt);
+            dir_sum.push_back(knots[s]);
             continue;
         }
-        sa::SegConst &g = out[it->second];
-        dt_sum[it->second] += segs[s].dt;
+        const size_t e = it->second;
+        sa::SegConst &g = out[e];
+        dt_sum[e] += segs[s].dt;
+        for (int i = 0; i < 6; ++i) dir_sum[e][i] += knots[s][i];
         g.mult += 1;
         g.ns_all += segs[s].ns;
     }
     for (size_t e = 0; e < out.size(); ++e) {
-        if (out[e].mult == 1) continue;  // a lone segment keeps its own weights
-        out[e].dt = (float)dt_sum[e];
-        out[e].wrate = (float)(dt_sum[e] / out[e].theta);
+        sa::SegConst &g = out[e];
+        if (g.mult == 1) continue;  // a lone segment keeps its own arc and weights
+        // the members' mean start and end directions, each normalised; the
+        // first member's arc stays if they were ever to coincide
+        double a[3], b[3];
+        const double *s = dir_sum[e].data();
+        const double la = std::sqrt(s[0] * s[0] + s[1] * s[1] + s[2] * s[2]);
+        const double lb = std::sqrt(s[3] * s[3] + s[4] * s[4] + s[5] * s[5]);
+        for (int i = 0; i < 3; ++i) {
+            a[i] = s[i] / la;
+            b[i] = s[3 + i] / lb;
+        }
+        sa::SegConst rep = g;
+        if (a[2] > 0.0 && b[2] > 0.0 && seg_geometry(a, b, (double)g.ta, (double)g.ta + (double)g.dt, rep)) g = rep;
+        g.dt = (float)dt_sum[e];
+        g.wrate = (float)(dt_sum[e] / g.theta);
     }
     segs = std::move(out);
 }
@@ -406,45 +469,19 @@ sa_status path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, s
             const double *a = in->knot_dir + 3 * k, *b = in->knot_dir + 3 * (k + 1);
             if (!(a[2] > 0.0) || !(b[2] > 0.0))
                 return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload: knot below the horizon");
-            const double c = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
-            const double cr[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
-            const double sn = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
-            const double theta = std::atan2(sn, c);
-            if (!(sn > 1e-12)) return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload: coincident knot directions");
-            double e2[3] = {b[0] - c * a[0], b[1] - c * a[1], b[2] - c * a[2]};
-            const double l2 = std::sqrt(e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2]);
-            for (double &v : e2) v /= l2;
-            const double N[3] = {a[1] * e2[2] - a[2] * e2[1], a[2] * e2[0] - a[0] * e2[2],
-                                 a[0] * e2[1] - a[1] * e2[0]};
-            // the lift of horizontal offsets into the plane, times |nz|:
-            // |nz| (a - a_z N_xy / nz) = |nz| a - sgn(nz) a_z N_xy
-            const double anz = std::fabs(N[2]), sg = N[2] < 0.0 ? -1.0 : 1.0;
             sa::SegConst g;
             std::memset(&g, 0, sizeof(g));
-            g.m00 = (float)(anz * a[0] - sg * a[2] * N[0]);
-            g.m01 = (float)(anz * a[1] - sg * a[2] * N[1]);
-            g.m10 = (float)(anz * e2[0] - sg * e2[2] * N[0]);
-            g.m11 = (float)(anz * e2[1] - sg * e2[2] * N[1]);
-            g.steep = anz < std::sin(5.0 * M_PI / 180.0) ? 1 : 0;
-            g.e1z = (float)a[2];
-            g.e2z = (float)e2[2];
-            g.theta = (float)theta;
+            if (!seg_geometry(a, b, ta, tb, g))
+                return fail(ctx, SA_ERR_INVALID_ARG, "sa_path_upload: coincident knot directions");
+            // FP64 angle of the arc, for the raster slices' directions below
+            const double cr[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+            const double sn = std::sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+            const double theta = std::atan2(sn, a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
             g.dt = (float)(tb - ta);
             g.ta = (float)ta;
-            g.cth = (float)std::cos(theta);
-            g.sth = (float)std::sin(theta);
-            g.nz = (float)N[2];
             g.mult = 1;
             g.bin = bin;
             g.day = d;
-            g.e1x = (float)a[0];
-            g.e1y = (float)a[1];
-            g.e2x = (float)e2[0];
-            g.e2y = (float)e2[1];
-            g.ua_x = (float)(a[0] / a[2]);
-            g.ua_y = (float)(a[1] / a[2]);
-            g.ub_x = (float)(b[0] / b[2]);
-            g.ub_y = (float)(b[1] / b[2]);
             // sample instants attributed to this segment: [ta, tb), the day's
             // last segment also takes tb
             const bool last = k + 2 == k1;
@@ -457,13 +494,9 @@ sa_status path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, s
                 }
             }
             g.s0 = first >= 0 ? (float)(in->t_min[first] - ta) : 0.f;
-            g.wrate = (float)((tb - ta) / theta);
             g.ns = ns;
             g.ns_all = ns;
-            g.rate = (float)((tb - ta) / theta);
             g.inv_step = (float)(1.0 / step);
-            g.mdx = (float)(a[0] + e2[0] * 0.5 * theta);
-            g.mdy = (float)(a[1] + e2[1] * 0.5 * theta);
             segs.push_back(g);
             seg_knots.push_back({a[0], a[1], a[2], b[0], b[1], b[2]});
             // raster slices (Sec. 4): each instant's direction on the great

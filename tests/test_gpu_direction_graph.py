@@ -63,7 +63,7 @@ def test_graph_matches_oracle(ctx):
     """Twelve days of June in two bins on the small scene, cells of 1
     degree: the library forms as many edges as the oracle's direction graph,
     and every point's minutes match the oracle's graph form (each edge from
-    its first member, weighted by its members' durations) to the accrual
+    its members' mean arc, weighted by their durations) to the accrual
     form's bar per point and day."""
     w = make_c1()
     sub = w.points.take(subset_points(w.points, 512, 71))

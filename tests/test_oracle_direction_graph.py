@@ -141,3 +141,34 @@ def test_coarse_cells_merge_days_with_a_bounded_region_error():
     assert len(groups) <= len(path.seg_t) / 4
     assert abs(g.sum() - plain.sum()) / plain.sum() < 0.05
     assert np.abs(g - plain).max() > 1.0        # but points do move
+
+
+def test_edge_of_mirrored_members_is_the_arc_between_them():
+    """Two members whose knots are a base arc's knots turned by +-eps about
+    an axis perpendicular to each: their mean directions are the base
+    knots, so the edge is the base arc, and the graph's minutes are the
+    continuous form's on the base arc weighted by the members' durations
+    (30 and 45 minutes, over the first member's 30)."""
+    w, pts = _small()
+    p = oracle.sun_path(_span([dt.date(2019, 6, 21)], [0]), 30.0)
+    j = len(p.seg_t) // 2
+    a, b = p.seg_dir[j]
+    eps = 2e-4
+
+    def turn(x, s):
+        k = np.cross(x, [0.0, 0.0, 1.0])
+        k /= np.linalg.norm(k)
+        return np.cos(eps) * x + s * np.sin(eps) * np.cross(k, x)
+    seg_dir = np.stack([[turn(a, 1), turn(b, 1)], [turn(a, -1), turn(b, -1)]])
+    seg_t = np.array([[600.0, 630.0], [700.0, 745.0]])
+    path = oracle.OraclePath(p.dirs[:0], p.w[:0], p.t[:0], p.sample_day[:0], p.sample_bin[:0], seg_t, seg_dir,
+                             np.array([0, 1], np.int32), np.array([0, 0], np.int32), 1, p.spans)
+    arc, times = oracle.edge_arc(path, [0, 1])
+    np.testing.assert_allclose(arc, [a, b], atol=1e-12)
+    g, groups = oracle.graph_continuous(w.scene, pts, path, 1.0)
+    assert [len(x) for x in groups] == [2]
+    base = oracle.OraclePath(path.dirs, path.w, path.t, path.sample_day, path.sample_bin, seg_t[:1],
+                             np.array([[a, b]]), path.seg_day[:1], path.day_bin[:1], 1, path.spans)
+    one = oracle.continuous(w.scene, pts, base)["minutes"]
+    assert one.max() > 0
+    np.testing.assert_allclose(g, one * 75.0 / 30.0, rtol=1e-9, atol=1e-9)
