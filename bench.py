@@ -281,6 +281,33 @@ def bench_c5(args, sa, torch):
                 f"{legs[-1]['ms']:.0f} ms, mean |error| {err:.3f} min/point/day")
             gp.close()
         r["direction_graph"] = {"segments_full": path.n_segments, "legs": legs}
+        # the same with knots on the clock: every day's inner knots at the
+        # multiples of the spacing in local time, so days share knot times;
+        # errors against the full path on those knots
+        spc = sa.sa_sunpath(40.7, -74.0, -5.0, 2019, 1, 1, 365, seg=args.seg, clock_knots=True)
+        spc.day_bin = np.asarray(w.span.day_bin, np.int32)
+        pc = sa.Path(ctx, spc)
+        basec = torch.empty_like(hours)
+        cms = _timed(torch, ctx.stream,
+                     lambda: sa.sa_accumulate(ctx, sc, dp, pc, sa.SA_ACCRUAL, None, basec, out_scale=1.0 / 60.0), 1)
+        ctx.sync()
+        legs_c = []
+        for bound in (1.0, 3.0, 5.0, 10.0):
+            gp = sa.Path(ctx, spc, graph_bound_deg=bound)
+            gh = torch.empty_like(hours)
+            gms = _timed(torch, ctx.stream,
+                         lambda: sa.sa_accumulate(ctx, sc, dp, gp, sa.SA_ACCRUAL, None, gh, out_scale=1.0 / 60.0), 1)
+            ctx.sync()
+            err = float((gh - basec).abs().sum(0).mean()) * 60.0 / 365.0
+            tot = float((gh.sum(dtype=torch.float64) - basec.sum(dtype=torch.float64)).abs() /
+                        basec.sum(dtype=torch.float64))
+            legs_c.append({"cell_deg": bound, "segments": gp.n_segments, "ms": float(np.mean(gms)),
+                           "mean_abs_error_min_per_point_day": err, "region_total_rel_error": tot})
+            log(f"c5 clock knots, graph {bound} deg: {gp.n_segments} of {pc.n_segments} segments, "
+                f"{legs_c[-1]['ms']:.0f} ms, mean |error| {err:.3f} min/point/day")
+            gp.close()
+        r["direction_graph_clock_knots"] = {"segments_full": pc.n_segments, "ms_full": float(np.mean(cms)),
+                                            "legs": legs_c}
     return r
 
 

@@ -147,6 +147,11 @@ typedef struct {
     double t_end_min;         /* with t_start_min < 0: ignored (last such minute) */
     double step_min;          /* spacing of the sample instants (> 0) */
     double seg_min;           /* knot spacing of the accrual form (> 0) */
+    int32_t knot_clock;       /* 0: knots at t0, t0 + seg_min, ..., and t1 (t0, t1: the day's
+                                 first and last instants); 1: at t0, at every multiple of
+                                 seg_min in local time inside (t0, t1), and at t1, so that
+                                 different days share knot times (the direction graph then
+                                 merges more of their segments) */
 } sa_timespan;
 
 /* Host arrays describing a sun path.  As the output of sa_sunpath the

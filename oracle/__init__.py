@@ -142,10 +142,12 @@ class OraclePath:
     spans: np.ndarray       # [n_days, 2]
 
 
-def sun_path(span, seg_min: float | None = None) -> OraclePath:
+def sun_path(span, seg_min: float | None = None, clock_knots: bool = False) -> OraclePath:
     """Sample instants and great-circle knots for every day of ``span``.
     Knots: T0, T0 + L, T0 + 2L, ... and T1 (the last segment may be
-    shorter); L = ``seg_min`` (default: the sample step)."""
+    shorter); L = ``seg_min`` (default: the sample step).  ``clock_knots``:
+    T0, every multiple of L in local time strictly between T0 and T1, and
+    T1."""
     L = float(seg_min if seg_min is not None else span.step_min)
     dirs, ws, ts, sd, sb = [], [], [], [], []
     seg_t, seg_dir, seg_day, spans = [], [], [], []
@@ -160,9 +162,13 @@ def sun_path(span, seg_min: float | None = None) -> OraclePath:
         if len(t) == 0:
             continue
         T0, T1 = sp
-        knots = list(np.arange(T0, T1, L))
-        if knots[-1] < T1:
-            knots.append(T1)
+        if clock_knots:
+            m = np.floor(T0 / L) + 1.0
+            knots = [T0] + [k * L for k in np.arange(m, np.ceil(T1 / L) + 1.0) if T0 < k * L < T1] + [T1]
+        else:
+            knots = list(np.arange(T0, T1, L))
+            if knots[-1] < T1:
+                knots.append(T1)
         kd = [solar(day.year, day.month, day.day, tk, day.tz_h, span.lat, span.lon)[:3] for tk in knots]
         for j in range(len(knots) - 1):
             seg_t.append((knots[j], knots[j + 1]))

@@ -46,7 +46,7 @@ class sa_site(C.Structure):
 class sa_timespan(C.Structure):
     _fields_ = [("year", C.c_int32), ("month", C.c_int32), ("day", C.c_int32), ("n_days", C.c_int32),
                 ("t_start_min", C.c_double), ("t_end_min", C.c_double), ("step_min", C.c_double),
-                ("seg_min", C.c_double)]
+                ("seg_min", C.c_double), ("knot_clock", C.c_int32)]
 
 
 class sa_sunpath_buf(C.Structure):
@@ -167,12 +167,14 @@ class SunPath:
 
 
 def sa_sunpath(lat, lon, tz_h, year, month, day, n_days=1, t_start=-1.0, t_end=-1.0, step=1.0,
-               seg=30.0) -> SunPath:
+               seg=30.0, clock_knots=False) -> SunPath:
     """Sample instants and great-circle knots of ``n_days`` consecutive days
-    (t_start < 0: sunrise..sunset whole minutes)."""
+    (t_start < 0: sunrise..sunset whole minutes); ``clock_knots``: inner
+    knots at the multiples of ``seg`` in local time (days share knot
+    times) instead of every ``seg`` minutes from each day's first instant."""
     L = lib()
     site = sa_site(lat, lon, tz_h)
-    span = sa_timespan(year, month, day, n_days, t_start, t_end, step, seg)
+    span = sa_timespan(year, month, day, n_days, t_start, t_end, step, seg, 1 if clock_knots else 0)
     buf = sa_sunpath_buf()
     rc = L.sa_sunpath(C.byref(site), C.byref(span), C.byref(buf))
     if rc != SA_OK:
@@ -208,14 +210,14 @@ def concat_paths(paths, day_bin=None) -> SunPath:
                    np.concatenate([p.knot_dir for p in paths]), db)
 
 
-def sunpath_for_span(span, seg_min: float) -> SunPath:
+def sunpath_for_span(span, seg_min: float, clock_knots=False) -> SunPath:
     """Library sun path for a ``workloads.Span`` (one call per day, bins as
     the span says)."""
     paths = []
     for d in span.days:
         t0, t1 = (d.window if d.window is not None else (-1.0, -1.0))
         paths.append(sa_sunpath(span.lat, span.lon, d.tz_h, d.year, d.month, d.day, 1, t0, t1,
-                                span.step_min, seg_min))
+                                span.step_min, seg_min, clock_knots))
     return concat_paths(paths, span.day_bin)
 
 

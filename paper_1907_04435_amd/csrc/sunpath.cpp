@@ -169,10 +169,13 @@ sa_status sunpath_fill(const sa_site &site, const sa_timespan &span, sa_sunpath_
             }
         }
         n_samples += K;
-        // knots: t0, t0 + L, ... and t1
+        // knots: t0, then t0 + L, t0 + 2L, ... (or the multiples of L in
+        // local time after t0), below t1, and t1
         if (K > 0) {
+            const double L = span.seg_min, first_clock = (std::floor(t0 / L) + 1.0) * L;
+            auto knot = [&](int j) { return span.knot_clock ? first_clock + (j - 1) * L : t0 + j * L; };
             int J = 0;
-            for (double tk = t0; tk < t1; tk = t0 + (++J) * span.seg_min) {
+            for (double tk = t0; tk < t1; tk = knot(++J)) {
                 if (!sizing) {
                     if (n_knots + J >= out.cap_knots) {
                         err = "sa_sunpath: cap_knots too small";

@@ -50,7 +50,7 @@ int main(void)
     if (check(sa_scene_upload(ctx, 3, vert_off, xy, height, &scene), "sa_scene_upload")) return 1;
 
     const sa_site site = {40.7, -74.0, -4.0};
-    const sa_timespan span = {2019, 6, 21, 1, -1.0, -1.0, 5.0, 30.0};
+    const sa_timespan span = {2019, 6, 21, 1, -1.0, -1.0, 5.0, 30.0, 0};
     sa_sunpath_buf buf = {0};
     if (check(sa_sunpath(&site, &span, &buf), "sa_sunpath (sizes)")) return 1;
     buf.cap_days = buf.n_days;

@@ -46,12 +46,14 @@ def test_sunpath_sizes_year():
 
 
 @pytest.mark.parametrize("seg", [1.0, 30.0, 60.0])
-def test_sunpath_matches_oracle(seg):
+@pytest.mark.parametrize("clock", [False, True])
+def test_sunpath_matches_oracle(seg, clock):
     c1 = make_c1()
-    spans = [c1.span, Span(40.7, -74.0, [Day(2019, 3, 20, -4.0), Day(2019, 6, 21, -4.0), Day(2019, 12, 21, -5.0)])]
+    spans = [c1.span, Span(40.7, -74.0, [Day(2019, 3, 20, -4.0), Day(2019, 6, 21, -4.0), Day(2019, 12, 21, -5.0)]),
+             Span(40.7, -74.0, [Day(2019, 6, 21, -4.0, (7 * 60 + 13.5, 17 * 60 + 2.0))], 0.5)]
     for span in spans:
-        lp = sa.sunpath_for_span(span, seg)
-        op = oracle.sun_path(span, seg)
+        lp = sa.sunpath_for_span(span, seg, clock_knots=clock)
+        op = oracle.sun_path(span, seg, clock_knots=clock)
         assert lp.n_samples == len(op.w)
         np.testing.assert_allclose(lp.dir, op.dirs, atol=1e-12)
         np.testing.assert_array_equal(lp.t_min, op.t)
@@ -65,6 +67,20 @@ def test_sunpath_matches_oracle(seg):
                 segs_d.append((lp.knot_dir[k], lp.knot_dir[k + 1]))
         np.testing.assert_array_equal(np.array(segs_t), op.seg_t)
         np.testing.assert_allclose(np.array(segs_d), op.seg_dir, atol=1e-12)
+
+
+def test_clock_knots_fall_on_the_clock():
+    """With clock knots every inner knot is a multiple of the spacing in
+    local time, the first and last are the day's first and last instants,
+    and two days share their inner knot times wherever both are in
+    daylight."""
+    p = sa.sa_sunpath(40.7, -74.0, -4.0, 2019, 6, 20, 2, step=1.0, seg=30.0, clock_knots=True)
+    days = [p.knot_t[p.day_knot_off[d]:p.day_knot_off[d + 1]] for d in range(2)]
+    for d, kt in enumerate(days):
+        s = p.t_min[p.day_sample_off[d]:p.day_sample_off[d + 1]]
+        assert kt[0] == s[0] and kt[-1] == s[-1]
+        assert np.all(np.mod(kt[1:-1], 30.0) == 0.0) and np.all(np.diff(kt) > 0)
+    assert len(set(days[0][1:-1]) & set(days[1][1:-1])) >= len(days[0]) - 3
 
 
 def test_sunpath_rejects_night_window():

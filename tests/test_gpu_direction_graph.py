@@ -80,6 +80,34 @@ def test_graph_matches_oracle(ctx):
     assert np.quantile(d, 0.999) <= 0.01 and d.mean() <= 1e-3 and d.max() <= 0.5
 
 
+def test_clock_knots_merge_more_and_match_oracle(ctx):
+    """Knots on the clock (days share knot times): twelve June days in two
+    bins on the small scene.  The plain path matches the oracle's continuous
+    form on the same knots; at 1 degree cells the graph forms the oracle's
+    edges, fewer than with knots counted from each sunrise, and its minutes
+    match the oracle's graph form."""
+    w = make_c1()
+    sub = w.points.take(subset_points(w.points, 512, 72))
+    dates = [dt.date(2019, 6, 10) + dt.timedelta(days=i) for i in range(12)]
+    span = Span(40.7, -74.0, [Day(x.year, x.month, x.day, _nyc_tz(x)) for x in dates], 5.0, [0] * 6 + [1] * 6)
+    opath = oracle.sun_path(span, 30.0, clock_knots=True)
+    sp = sa.sunpath_for_span(span, 30.0, clock_knots=True)
+    _, m0, n0 = run(ctx, w.scene, sub, sp)
+    c0 = oracle.continuous(w.scene, sub, opath)["minutes"]
+    d0 = np.abs(m0 - c0) / 6.0
+    _, m, n_edges = run(ctx, w.scene, sub, sp, bound=1.0)
+    _, _, n_sunrise = run(ctx, w.scene, sub, sa.sunpath_for_span(span, 30.0), bound=1.0)
+    o, groups = oracle.graph_continuous(w.scene, sub, opath, 1.0)
+    d = np.abs(m - o) / 6.0
+    say(f"clock knots: {n0} segments, plain path vs oracle p99.9 {np.quantile(d0, 0.999):.2e}; 1 deg cells -> "
+        f"{n_edges} edges (oracle {len(groups)}, sunrise-counted knots {n_sunrise}); graph vs oracle p99.9 "
+        f"{np.quantile(d, 0.999):.2e} max {d.max():.2e}")
+    assert n0 == len(opath.seg_t)
+    assert np.quantile(d0, 0.999) <= 0.01 and d0.mean() <= 1e-3 and d0.max() <= 0.5
+    assert n_edges == len(groups) and n_edges < n_sunrise
+    assert np.quantile(d, 0.999) <= 0.01 and d.mean() <= 1e-3 and d.max() <= 0.5
+
+
 def test_exact_merge_in_every_accrual_entry_point(ctx, block):
     """The June solstice three times in one bin: every edge stands for three
     identical segments, so building contributions, the height adjoint and
