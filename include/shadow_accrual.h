@@ -342,9 +342,10 @@ typedef struct {
  * edges; prisms outside `box` are missed.  Points: ground-type only (any
  * z; pts->owner, nx and ny must be NULL: walls would shade themselves).
  * Outputs as sa_accumulate (counts int32, minutes float, [n_bins * n],
- * either may be NULL).  The library keeps one segment's map (8 bytes per
- * texel and slice: a segment stamp and the depth) in memory the context
- * owns, grown on first need; calls on one context must not overlap.  Not
+ * either may be NULL).  The library keeps one segment's map (4 bytes per
+ * texel and slice: a segment stamp and the depth to about 1 / 2^24 of its
+ * range) in memory the context owns, grown on first need; calls on one
+ * context must not overlap.  Not
  * for direction-graph paths.
  * Errors: INVALID_ARG, CAPACITY (a map above max_texels), OOM, DEVICE. */
 sa_status sa_sam_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts,

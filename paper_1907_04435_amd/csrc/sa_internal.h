@@ -109,6 +109,7 @@ struct SamGrid {
     int32_t nu, nv;    // texels along u and v
     float ox, oy, oz;  // o, world coordinates
     float bias;        // depth margin of the shadow test (m)
+    float dq, inv_dq;  // depth quantum of the map words (m) and its inverse
 };
 
 // One slice: an instant's direction on the great circle between the

@@ -5,10 +5,12 @@
 // largest distance along the light at which the ray from the texel centre
 // toward the sun leaves a prism (its face nearest the sun).  Step 2 puts
 // each point's shadow on every slice and counts the instants whose stored
-// depth exceeds the point's own by more than the bias.  Map words are 64
-// bits: a segment stamp above the depth bits, so an integer maximum keeps
-// the current segment's nearest-to-sun depth over any stale word and the
-// map is cleared only when it is allocated or the stamp wraps.
+// depth exceeds the point's own by more than the bias.  A map word holds an
+// 8-bit segment stamp above a 24-bit depth (rounded down to a quantum of
+// 1 / 2^24 of the segment's largest possible depth, about a millimetre for
+// a city), so an integer maximum keeps the current segment's
+// nearest-to-sun depth over any stale word, and the map is cleared only
+// when it is allocated or after 255 segments.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -38,9 +40,9 @@ __global__ void k_sam_clear(uint32_t *p, int64_t n)
 // the box corner: the lanes first project one vertex each and form one
 // edge's three coefficients each, then every pass reads an edge's
 // coefficients from its lane and pays two FMAs and a min or max per texel.
-// Depths are positive (the plane lies behind every prism), so their bits
-// order as unsigned integers; with the segment's stamp above them a 64-bit
-// integer maximum keeps the nearest-to-sun face of this segment.
+// Depths are positive (the plane lies behind every prism) and quantised
+// downward; with the segment's stamp above them a 32-bit integer maximum
+// keeps the nearest-to-sun face of this segment.
 constexpr int kTilesPerPass = 4;
 
 __device__ __forceinline__ float wave_min(float v)
@@ -66,11 +68,11 @@ __global__ __launch_bounds__(kThreads) void k_sam_build(const float4 *__restrict
                                                         const int32_t *__restrict__ voff,
                                                         const float *__restrict__ height, int n_b, SamGrid g,
                                                         const SamSlice *__restrict__ slices, int K,
-                                                        unsigned long long *__restrict__ map, uint32_t stamp)
+                                                        uint32_t *__restrict__ map, uint32_t stamp)
 {
     const int lane = threadIdx.x & 63;
     const int lx = lane & 7, ly = lane >> 3;
-    const unsigned long long tag = (unsigned long long)stamp << 32;
+    const uint32_t tag = stamp << 24;
     const int64_t items = (int64_t)K * n_b;
     const int64_t T = (int64_t)g.nu * g.nv;
     const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
@@ -118,7 +120,7 @@ __global__ __launch_bounds__(kThreads) void k_sam_build(const float4 *__restrict
         const int W = __builtin_amdgcn_readfirstlane((int)fi1) - i0 + 1;
         const int Hh = __builtin_amdgcn_readfirstlane((int)fj1) - j0 + 1;
         const int tx_n = (W + 7) >> 3, ty_n = (Hh + 7) >> 3;
-        unsigned long long *slice = map + (int64_t)k * T;
+        uint32_t *slice = map + (int64_t)k * T;
         // the ray from the centre of texel (i0 + i', j0 + j'):
         // X0 + i' h u + j' h v + lam d
         const float cu0 = g.u0 + ((float)i0 + 0.5f) * g.h, cv0 = g.v0 + ((float)j0 + 0.5f) * g.h;
@@ -211,7 +213,8 @@ __global__ __launch_bounds__(kThreads) void k_sam_build(const float4 *__restrict
             for (int r = 0; r < kTilesPerPass; ++r) {
                 const int ii = (int)ox[r] + lx, jj = (int)oy[r] + ly;
                 if (t0 + r < n_tiles && ii < W && jj < Hh && lo[r] <= hi[r])
-                    atomicMax(slice + (int64_t)(j0 + jj) * g.nu + (i0 + ii), tag | __float_as_uint(hi[r]));
+                    atomicMax(slice + (int64_t)(j0 + jj) * g.nu + (i0 + ii),
+                              tag | (uint32_t)fminf(hi[r] * g.inv_dq, 16777215.f));
             }
         }
     }
@@ -223,7 +226,7 @@ __global__ __launch_bounds__(kThreads) void k_sam_build(const float4 *__restrict
 __global__ __launch_bounds__(kThreads) void k_sam_query(const float *__restrict__ px, const float *__restrict__ py,
                                                         const float *__restrict__ pz, int64_t n, SamGrid g,
                                                         const SamSlice *__restrict__ slices, int K,
-                                                        const unsigned long long *__restrict__ map, uint32_t stamp,
+                                                        const uint32_t *__restrict__ map, uint32_t stamp,
                                                         int bin, float scale,
                                                         int32_t *__restrict__ counts, float *__restrict__ minutes)
 {
@@ -242,8 +245,8 @@ __global__ __launch_bounds__(kThreads) void k_sam_query(const float *__restrict_
             const float fv = floorf((qx * g.vx + qy * g.vy + qz * g.vz - g.v0) * g.inv_h);
             if (fu >= 0.f && fu < (float)g.nu && fv >= 0.f && fv < (float)g.nv) {
                 // a word of an earlier segment (another stamp) is empty here
-                const unsigned long long m = map[(int64_t)k * T + (int64_t)fv * g.nu + (int64_t)fu];
-                if ((uint32_t)(m >> 32) == stamp && __uint_as_float((uint32_t)m) > lam + g.bias) {
+                const uint32_t m = map[(int64_t)k * T + (int64_t)fv * g.nu + (int64_t)fu];
+                if ((m >> 24) == stamp && (float)(m & 0xffffffu) * g.dq > lam + g.bias) {
                     ++cnt;
                     mins += s.w;
                 }
@@ -318,6 +321,15 @@ bool sam_grid(const double box[6], const double *a, const double *b, double h, d
     g.oy = (float)o[1];
     g.oz = (float)o[2];
     g.bias = (float)bias;
+    // every slice direction d lies on the arc from a to b, so d.a >= a.b and
+    // no depth exceeds (max corner.a - c) / (a.b); 1 % of slack
+    double cmax = -INFINITY;
+    for (int q = 0; q < 8; ++q) cmax = std::max(cmax, X[q][0] * a[0] + X[q][1] * a[1] + X[q][2] * a[2]);
+    const double ab = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    if (!(ab > 0.0)) return false;
+    const double lam_max = 1.01 * (cmax - c) / ab;
+    g.dq = (float)(lam_max / 16777215.0);
+    g.inv_dq = (float)(16777215.0 / lam_max);
     return true;
 }
 
@@ -360,7 +372,7 @@ sa_status launch_sam(const DeviceScene &s, const DevicePath &p, const PointsView
         }
         most = std::max(most, (int64_t)grids[j].nu * grids[j].nv * sh.ns);
     }
-    const size_t need = (size_t)most * sizeof(unsigned long long);
+    const size_t need = (size_t)most * sizeof(uint32_t);
     auto clear_all = [&]() {
         const int64_t words = (int64_t)(scr.bytes / sizeof(uint32_t));
         hipLaunchKernelGGL(k_sam_clear, dim3((unsigned)std::min<int64_t>((words + kThreads - 1) / kThreads, 65536)),
@@ -382,14 +394,14 @@ sa_status launch_sam(const DeviceScene &s, const DevicePath &p, const PointsView
         clear_all();
         SA_CHECK_LAUNCH("raster map clear");
     }
-    unsigned long long *map = (unsigned long long *)scr.ptr;
+    uint32_t *map = (uint32_t *)scr.ptr;
     const unsigned qblocks = (unsigned)std::min<int64_t>((pts.n + kThreads - 1) / kThreads, 16384);
     for (size_t j = 0; j < p.seg_host.size(); ++j) {
         const SamSegHost &sh = p.seg_host[j];
         if (sh.ns == 0) continue;
         const SamGrid &g = grids[j];
         const SamSlice *sl = p.sam_slices + sh.first;
-        if (stamp == 0xffffffffu) {
+        if (stamp >= 255u) {
             clear_all();
             SA_CHECK_LAUNCH("raster map clear");
         }
@@ -401,7 +413,7 @@ sa_status launch_sam(const DeviceScene &s, const DevicePath &p, const PointsView
                            (const float *)s.height, s.n_b, g, sl, sh.ns, map, stamp);
         SA_CHECK_LAUNCH("raster map build");
         hipLaunchKernelGGL(k_sam_query, dim3(qblocks), dim3(kThreads), 0, st, pts.x, pts.y, pts.z, pts.n, g, sl,
-                           sh.ns, (const unsigned long long *)map, stamp, sh.bin, scale, counts, minutes);
+                           sh.ns, (const uint32_t *)map, stamp, sh.bin, scale, counts, minutes);
         SA_CHECK_LAUNCH("raster map query");
     }
     return SA_OK;

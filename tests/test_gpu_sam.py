@@ -138,7 +138,7 @@ def test_sam_repeated_calls_reuse_the_map(ctx):
     """One context, three calls: 1 m texels, then 0.5 m (a larger map, a
     new buffer), then 1 m again over the stale words of both: the last call
     equals the first exactly (words of earlier segments carry older stamps
-    and read as empty)."""
+    and read as empty); then enough calls to wrap the stamp twice."""
     w = make_c1()
     sub = w.points.take(subset_points(w.points, 512, 84))
     say("sam repeated calls on one context: 1 m, 0.5 m, 1 m")
@@ -153,6 +153,13 @@ def test_sam_repeated_calls_reuse_the_map(ctx):
     assert np.array_equal(c1.cpu().numpy(), c3.cpu().numpy())
     assert np.array_equal(m1.cpu().numpy(), m3.cpu().numpy())
     assert not np.array_equal(c1.cpu().numpy(), c2.cpu().numpy())
+    # past the 8-bit segment stamp's wrap (a map clear every 255 segments):
+    # 27 more calls of this path's segments, every one equal to the first
+    for _ in range(27):
+        c4, m4 = sa.sam_accumulate(ctx, sc, dp, path, 1.0)
+        ctx.sync()
+        assert np.array_equal(c1.cpu().numpy(), c4.cpu().numpy())
+    assert 30 * path.n_segments > 2 * 255
 
 
 def test_sam_bench_configuration_sampled_points(ctx):
