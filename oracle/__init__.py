@@ -52,6 +52,8 @@ def lib():
                                   C.POINTER(C.c_uint32), C.POINTER(C.c_uint8), C.c_int]
         L.orc_continuous.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, ip, C.c_int, ip, C.c_int,
                                      C.c_double, dp, ip, C.c_int, dp, ip, dp, C.c_int]
+        L.orc_continuous_true.argtypes = [C.c_void_p, C.c_void_p, C.c_int, ip, dp, dp, ip, C.c_int, C.c_double,
+                                          C.c_double, C.c_double, C.c_double, dp, dp, C.c_int]
         L.orc_slerp.argtypes = [dp, dp, C.c_double, dp]
         L.orc_contribution.argtypes = [C.c_void_p, C.c_void_p, C.c_int, dp, dp, ip, ip, C.c_int, C.c_double, dp,
                                        dp, C.c_int]
@@ -245,6 +247,35 @@ def continuous(scene, pts, path: OraclePath, grid_min=1.0 / 12.0, threads=None):
                          _ptr(minutes, C.c_double), _ptr(counts, C.c_int32), _ptr(longest, C.c_double),
                          threads or threads_default())
     return dict(minutes=minutes, counts=counts, longest=longest)
+
+
+def continuous_true(scene, pts, span, piece_min=5.0, grid_min=1.0 / 12.0, threads=None, spans=None):
+    """Continuous gross shadow along the sun's actual path (Sec. 3.1, 3.2):
+    per point and day the measure of the times in the day's span [T0, T1]
+    (its first and last daylight instant, or the fixed window) at which the
+    point is in shadow for the FP64 solar direction at that time; per
+    occluder a ``grid_min`` scan (5 s) with every switch bisected, unioned
+    over occluders.  Summed into the span's bins: minutes FP64 [n_bins, n];
+    longest FP64 [n_bins, n] (the longest member of a day's shadowed set,
+    maximum over the bin's days).  ``spans``: [n_days, 2] (T0, T1) to use
+    instead of the span's days."""
+    s, ks = _scene(scene)
+    p, kp = _points(pts)
+    nd = len(span.days)
+    if spans is None:
+        spans = np.array([day_samples(d, span.lat, span.lon, span.step_min)[2] for d in span.days])
+    spans = np.ascontiguousarray(np.asarray(spans, np.float64).reshape(nd, 2))
+    ymd = np.ascontiguousarray([[d.year, d.month, d.day] for d in span.days], np.int32).reshape(nd, 3)
+    tz = np.ascontiguousarray([d.tz_h for d in span.days], np.float64)
+    day_bin = np.ascontiguousarray(span.day_bin if span.day_bin is not None else range(nd), np.int32)
+    n_bins = int(day_bin.max()) + 1 if nd else 0
+    minutes = np.zeros((n_bins, pts.n), np.float64)
+    longest = np.zeros((n_bins, pts.n), np.float64)
+    lib().orc_continuous_true(C.byref(s), C.byref(p), nd, _ptr(ymd, C.c_int32), _ptr(tz, C.c_double),
+                              _ptr(spans, C.c_double), _ptr(day_bin, C.c_int32), n_bins, float(span.lat),
+                              float(span.lon), float(piece_min), float(grid_min), _ptr(minutes, C.c_double),
+                              _ptr(longest, C.c_double), threads or threads_default())
+    return dict(minutes=minutes, longest=longest, spans=spans)
 
 
 def longest_sampled(shadowed, path: OraclePath):

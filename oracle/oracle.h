@@ -80,6 +80,21 @@ void orc_continuous(const orc_scene *s, const orc_points *p, int n_seg,
                     const double *sample_t, const int32_t *sample_day, int n_samples,
                     double *minutes, int32_t *counts, double *longest, int threads);
 
+/* ---- continuous duration along the actual sun path (Sec. 3.1, 3.2) ----
+ * Per point and day: the measure of the times in [T0, T1] at which the
+ * point is in shadow for the sun's actual direction (solar position
+ * equations above, FP64), found per occluder on a `grid_min` scan with
+ * every switch bisected, then unioned.  The day is walked in stretches of
+ * `piece_min` minutes (a prism is skipped for a stretch only when provably
+ * out of reach).  ymd [3 n_days] (year, month, day), tz_h [n_days],
+ * span [2 n_days] (T0, T1 local minutes), day_bin [n_days] (NULL: bin =
+ * day); minutes / longest [n_bins][n] (NULL: not wanted; longest = the
+ * longest member of a day's shadowed set, maximum over the bin's days). */
+void orc_continuous_true(const orc_scene *s, const orc_points *p, int n_days, const int32_t *ymd,
+                         const double *tz_h, const double *span, const int32_t *day_bin, int n_bins,
+                         double lat_deg, double lon_deg, double piece_min, double grid_min,
+                         double *minutes, double *longest, int threads);
+
 /* ---- building contribution (Sec. 7.2) ---- */
 /* contrib [n_bins][n_b]: per building the weighted minutes the points spend
  * in that building's own shadow along the path (a moment shadowed by several

@@ -396,6 +396,43 @@ static void seg_dir_at(const double *da, const double *db, double ta, double tb,
     orc_slerp(da, db, (t - ta) / (tb - ta), d);
 }
 
+/* A stretch of the sun's path as a function of time: either the great
+ * circle between two knot directions at a constant angular rate (the path
+ * model of the accrual form), or the sun's actual direction from the solar
+ * position equations (the definition of Sec. 3.1 / 3.2).  For the actual
+ * path a table of directions at T0 + i * tab_step saves recomputing the
+ * solar position on the scan grid; any other time is computed. */
+typedef struct {
+    int kind;                    /* 0: great circle between knots; 1: actual path */
+    const double *da, *db;       /* kind 0 */
+    double ta, tb;               /* kind 0 */
+    int year, month, day;        /* kind 1 */
+    double tz_h, lat, lon;       /* kind 1 */
+    const double *tab;           /* kind 1: [3 * n_tab] directions, or NULL */
+    double tab_t0, tab_step;
+    int64_t n_tab;
+} sunarc;
+
+static void arc_dir(const sunarc *A, double t, double *d)
+{
+    if (A->kind == 0) {
+        seg_dir_at(A->da, A->db, A->ta, A->tb, t, d);
+        return;
+    }
+    if (A->tab) {
+        double f = (t - A->tab_t0) / A->tab_step;
+        double r = floor(f + 0.5);
+        if (fabs(f - r) < 1e-7 && r >= 0 && r < (double)A->n_tab) {
+            const double *q = A->tab + 3 * (int64_t)r;
+            d[0] = q[0]; d[1] = q[1]; d[2] = q[2];
+            return;
+        }
+    }
+    double sol[9];
+    orc_solar(A->year, A->month, A->day, t, A->tz_h, A->lat, A->lon, sol);
+    d[0] = sol[0]; d[1] = sol[1]; d[2] = sol[2];
+}
+
 /* Does the ray from p along d meet the box of prism b grown by delta on
  * every side? */
 static int ray_meets_grown_box(const scene64 *S, int b, const double *p, const double *d, double delta)
@@ -419,23 +456,22 @@ static int ray_meets_grown_box(const scene64 *S, int b, const double *p, const d
 }
 
 /* Scan [t0, t1] on G+1 evenly spaced instants for switches of one
- * occluder's predicate, locating each by bisection to 1e-9 minutes.
- * `state` carries the predicate value and the start of an open shadowed
- * run across calls; closed runs are appended to out. */
-static void scan_cell(const scene64 *S, int b, const double *p, const double *nrm, double ta, double tb,
-                      const double *da, const double *db, double t0, double t1, int G, int *state,
-                      double *open_t, ivec *out)
+ * occluder's predicate along the path A, locating each by bisection to
+ * 1e-9 minutes.  `state` carries the predicate value and the start of an
+ * open shadowed run across calls; closed runs are appended to out. */
+static void scan_cell(const scene64 *S, int b, const double *p, const double *nrm, const sunarc *A,
+                      double t0, double t1, int G, int *state, double *open_t, ivec *out)
 {
     double d[3], t_prev = t0;
     for (int g = 1; g <= G; ++g) {
         double t = (g == G) ? t1 : t0 + (t1 - t0) * g / G;
-        seg_dir_at(da, db, ta, tb, t, d);
+        arc_dir(A, t, d);
         int v = occl(S, b, p, nrm, d);
         if (v != *state) {
             double lo = t_prev, hi = t;
             for (int it = 0; it < 80 && hi - lo > 1e-9; ++it) {
                 double mid = 0.5 * (lo + hi);
-                seg_dir_at(da, db, ta, tb, mid, d);
+                arc_dir(A, mid, d);
                 if (occl(S, b, p, nrm, d) == *state) lo = mid;
                 else hi = mid;
             }
@@ -448,23 +484,28 @@ static void scan_cell(const scene64 *S, int b, const double *p, const double *nr
     }
 }
 
-/* Times in [ta, tb] at which one occluder shadows p: its predicate sampled
- * on a grid of spacing <= grid, each change located by bisection.  A short
- * shadowed run can hide between two unshadowed grid instants; it can only
- * do so if the rays at those instants pass within (distance x the angle
- * turned over the cell) of the prism, so such cells are rescanned 64 times
- * finer.  (Within one great-circle segment a convex prism shadows p over a
- * single run, so no unshadowed gap can hide between two shadowed
- * instants.)  Appends the shadowed intervals to out. */
-static void occluder_intervals(const scene64 *S, int b, const double *p, const double *nrm,
-                               double ta, double tb, const double *da, const double *db,
-                               double grid, ivec *out)
+/* Times in [ta, tb] at which one occluder shadows p along the path A: its
+ * predicate sampled on a grid of spacing <= grid, each change located by
+ * bisection.  A short shadowed run can hide between two unshadowed grid
+ * instants; it can only do so if the rays at those instants pass within
+ * (distance x the angle turned over the cell) of the prism, so such cells
+ * are rescanned 64 times finer.  (Within one great-circle segment a convex
+ * prism shadows p over a single run, so no unshadowed gap can hide between
+ * two shadowed instants; along the actual path, cut into minutes-long
+ * pieces, a gap could only hide where the path runs within its tiny
+ * curvature of a silhouette for less than one grid cell.)  Appends the
+ * shadowed intervals to out. */
+static void occluder_intervals_arc(const scene64 *S, int b, const double *p, const double *nrm,
+                                   const sunarc *A, double ta, double tb, double grid, ivec *out)
 {
     int G = (int)ceil((tb - ta) / grid - 1e-12);
     if (G < 1) G = 1;
-    double d[3], open_t = ta;
-    double c = da[0] * db[0] + da[1] * db[1] + da[2] * db[2];
+    double d[3], e[3], open_t = ta;
+    arc_dir(A, ta, d);
+    arc_dir(A, tb, e);
+    double c = d[0] * e[0] + d[1] * e[1] + d[2] * e[2];
     double dphi = acos(c > 1.0 ? 1.0 : c) / G;         /* angle turned per cell */
+    if (A->kind == 1) dphi = 1.01 * dphi + 1e-9;       /* the actual path turns at a near-constant rate */
     double R = 0.0;                                     /* farthest box corner from p */
     if (b >= 0) {
         const double *bx = S->box + 4 * b;
@@ -476,23 +517,33 @@ static void occluder_intervals(const scene64 *S, int b, const double *p, const d
         }
     }
     double delta = 2.0 * R * dphi + 1e-6;
-    seg_dir_at(da, db, ta, tb, ta, d);
     int state = occl(S, b, p, nrm, d);
     int near_prev = b >= 0 && ray_meets_grown_box(S, b, p, d, delta);
     double t_prev = ta;
     for (int g = 1; g <= G; ++g) {
         double t = (g == G) ? tb : ta + (tb - ta) * g / G;
-        seg_dir_at(da, db, ta, tb, t, d);
+        arc_dir(A, t, d);
         int v = occl(S, b, p, nrm, d);
         int near = b >= 0 && ray_meets_grown_box(S, b, p, d, delta);
         if (state == 0 && v == 0 && (near || near_prev))
-            scan_cell(S, b, p, nrm, ta, tb, da, db, t_prev, t, 64, &state, &open_t, out);
+            scan_cell(S, b, p, nrm, A, t_prev, t, 64, &state, &open_t, out);
         else
-            scan_cell(S, b, p, nrm, ta, tb, da, db, t_prev, t, 1, &state, &open_t, out);
+            scan_cell(S, b, p, nrm, A, t_prev, t, 1, &state, &open_t, out);
         near_prev = near;
         t_prev = t;
     }
     if (state) ivec_push(out, open_t, tb);
+}
+
+/* The same along the great-circle segment from da (at ta) to db (at tb). */
+static void occluder_intervals(const scene64 *S, int b, const double *p, const double *nrm,
+                               double ta, double tb, const double *da, const double *db,
+                               double grid, ivec *out)
+{
+    sunarc A;
+    memset(&A, 0, sizeof(A));
+    A.kind = 0; A.da = da; A.db = db; A.ta = ta; A.tb = tb;
+    occluder_intervals_arc(S, b, p, nrm, &A, ta, tb, grid, out);
 }
 
 static void seg_plane(const double *da, const double *db, double *N)
@@ -575,6 +626,213 @@ void orc_continuous(const orc_scene *s, const orc_points *p, int n_seg,
     C.sample_t = sample_t; C.sample_day = sample_day; C.n_samples = n_samples;
     C.minutes = minutes; C.counts = counts; C.longest = longest;
     parallel_for(p->n, threads, continuous_point, &C);
+    scene64_free(&S);
+}
+
+/* ---- continuous duration along the actual sun path (Sec. 3.1, 3.2) ----
+ *
+ * D(p) = measure of { t in [T0, T1] : p is in shadow for the sun's actual
+ * direction at t }, per day, summed into the day's bin.  The same
+ * per-occluder scan and bisection as above, with every direction taken
+ * from the solar position equations instead of an interpolated path.  To
+ * keep the brute force affordable the day is cut into hour-long and then
+ * `piece`-long stretches; a prism is skipped for a stretch only when no
+ * ray within the stretch's angular reach of its chord plane can meet the
+ * prism's box (box_off_slab). */
+
+/* Can a ray from p, whose direction lies within an angle eps of the plane
+ * through p with unit normal N, meet prism b's box?  A point q such a ray
+ * meets satisfies |N.(q-p)| <= |q-p| sin(eps).  The function
+ * +-N.(q-p) - |q-p| sin(eps) is concave in q, so if it is positive at every
+ * corner of the box it is positive on the whole box: no such ray meets it.
+ * Returns 1 when the box is out of reach (the prism can be skipped). */
+static int box_off_slab(const scene64 *S, int b, const double *p, const double *N, double sin_eps,
+                        const double *m)
+{
+    const double *bx = S->box + 4 * b;
+    /* behind the stretch: every direction of the stretch makes an acute
+     * angle with m, so a point the rays meet has (q - p).m > 0; a box with
+     * every corner at (q - p).m <= 0 is out of reach */
+    int behind = 1;
+    for (int k = 0; k < 8 && behind; ++k) {
+        double q[3] = {((k & 1) ? bx[2] : bx[0]) - p[0], ((k & 2) ? bx[3] : bx[1]) - p[1],
+                       ((k & 4) ? S->H[b] : 0.0) - p[2]};
+        if (m[0] * q[0] + m[1] * q[1] + m[2] * q[2] > 0.0) behind = 0;
+    }
+    if (behind) return 1;
+    /* bounding sphere first (cheap, weaker) */
+    double c[3] = {0.5 * (bx[0] + bx[2]) - p[0], 0.5 * (bx[1] + bx[3]) - p[1], 0.5 * S->H[b] - p[2]};
+    double r = 0.5 * sqrt((bx[2] - bx[0]) * (bx[2] - bx[0]) + (bx[3] - bx[1]) * (bx[3] - bx[1]) +
+                          S->H[b] * S->H[b]);
+    double dc = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    double f = N[0] * c[0] + N[1] * c[1] + N[2] * c[2];
+    if (fabs(f) - r - (dc + r) * sin_eps > 0.0) return 1;
+    int pos = 1, neg = 1;
+    for (int k = 0; k < 8 && (pos || neg); ++k) {
+        double q[3] = {((k & 1) ? bx[2] : bx[0]) - p[0], ((k & 2) ? bx[3] : bx[1]) - p[1],
+                       ((k & 4) ? S->H[b] : 0.0) - p[2]};
+        double g = N[0] * q[0] + N[1] * q[1] + N[2] * q[2];
+        double m = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]) * sin_eps;
+        if (!(g > m)) pos = 0;
+        if (!(-g > m)) neg = 0;
+    }
+    return pos || neg;
+}
+
+/* Chord plane of the path over [ta, tb] (unit normal N) and a bound on how
+ * far (radians) the path strays from it: the sun's daily circle deviates
+ * from the great circle through two of its points by at most about
+ * beta^2 sin(2 rho) / 16 (beta the hour angle between them, rho the
+ * circle's angular radius), so beta^2 / 8 bounds it twice over; the largest
+ * deviation seen at 15 interior instants, doubled, guards the rest.  m:
+ * the unit mean of the two end directions; an arc of the daily circle
+ * shorter than a half circle stays within the angle between its ends of
+ * that mean, so every direction of a stretch of less than 120 degrees
+ * makes an acute angle with m.  Returns 0 when the chord is too short to
+ * define a plane or too long for m. */
+static int chord_plane(const sunarc *A, double ta, double tb, double *N, double *sin_eps, double *m)
+{
+    double da[3], db[3], d[3];
+    arc_dir(A, ta, da);
+    arc_dir(A, tb, db);
+    seg_plane(da, db, N);
+    if (!(N[0] * N[0] + N[1] * N[1] + N[2] * N[2] > 0.5)) return 0;
+    if (!(da[0] * db[0] + da[1] * db[1] + da[2] * db[2] > -0.5)) return 0;
+    for (int i = 0; i < 3; ++i) m[i] = da[i] + db[i];
+    double mm = sqrt(m[0] * m[0] + m[1] * m[1] + m[2] * m[2]);
+    for (int i = 0; i < 3; ++i) m[i] /= mm;
+    double dev = 0.0;
+    for (int k = 1; k < 16; ++k) {
+        arc_dir(A, ta + (tb - ta) * k / 16.0, d);
+        double v = fabs(N[0] * d[0] + N[1] * d[1] + N[2] * d[2]);
+        if (v > dev) dev = v;
+    }
+    double beta = (tb - ta) * (2.0 * M_PI / 1440.0) * 1.01;
+    double eps = fmax(2.0 * dev, beta * beta / 8.0) + 1e-9;
+    *sin_eps = sin(eps);
+    return 1;
+}
+
+typedef struct {
+    const scene64 *S;
+    const orc_points *P;
+    int n_days;
+    const int32_t *ymd;
+    const double *tz_h, *span;
+    const int32_t *day_bin;
+    double lat, lon, piece, grid, tab_step;
+    double *const *tab;
+    const int64_t *n_tab;
+    double *minutes, *longest;
+} true_ctx;
+
+typedef struct {
+    const int32_t *ymd;
+    const double *tz_h, *span;
+    double lat, lon, step;
+    double *const *tab;
+    const int64_t *n_tab;
+    int n_days;
+} day_table_ctx;
+
+/* one 64th of one day's direction table */
+static void day_table_part(void *vctx, int64_t i)
+{
+    const day_table_ctx *T = (const day_table_ctx *)vctx;
+    int dd = (int)(i / 64), part = (int)(i % 64);
+    int64_t m = T->n_tab[dd], k0 = m * part / 64, k1 = m * (part + 1) / 64;
+    for (int64_t k = k0; k < k1; ++k) {
+        double sol[9];
+        orc_solar(T->ymd[3 * dd], T->ymd[3 * dd + 1], T->ymd[3 * dd + 2], T->span[2 * dd] + k * T->step,
+                  T->tz_h[dd], T->lat, T->lon, sol);
+        T->tab[dd][3 * k] = sol[0]; T->tab[dd][3 * k + 1] = sol[1]; T->tab[dd][3 * k + 2] = sol[2];
+    }
+}
+
+static void true_point(void *vctx, int64_t i)
+{
+    const true_ctx *C = (const true_ctx *)vctx;
+    const scene64 *S = C->S;
+    const orc_points *P = C->P;
+    int64_t n = P->n;
+    double p[3] = {P->x[i], P->y[i], P->z[i]};
+    double nrm[2] = {P->nx ? P->nx[i] : 0.0, P->ny ? P->ny[i] : 0.0};
+    int owner = P->owner ? P->owner[i] : -1;
+    int *cand = (int *)malloc(sizeof(int) * ((size_t)S->n_b + 1));
+    ivec day = {0, 0, 0};
+    for (int dd = 0; dd < C->n_days; ++dd) {
+        double T0 = C->span[2 * dd], T1 = C->span[2 * dd + 1];
+        day.n = 0;
+        sunarc A;
+        memset(&A, 0, sizeof(A));
+        A.kind = 1;
+        A.year = C->ymd[3 * dd]; A.month = C->ymd[3 * dd + 1]; A.day = C->ymd[3 * dd + 2];
+        A.tz_h = C->tz_h[dd]; A.lat = C->lat; A.lon = C->lon;
+        A.tab = C->tab[dd]; A.tab_t0 = T0; A.tab_step = C->tab_step; A.n_tab = C->n_tab[dd];
+        for (double ha = T0; ha < T1; ha += 60.0) {
+            double hb = fmin(ha + 60.0, T1), N[3], se, mid[3];
+            int nc = 0;
+            int plane = chord_plane(&A, ha, hb, N, &se, mid);
+            for (int b = 0; b < S->n_b; ++b)
+                if (b != owner && !(plane && box_off_slab(S, b, p, N, se, mid))) cand[nc++] = b;
+            for (double ta = ha; ta < hb; ta += C->piece) {
+                double tb = fmin(ta + C->piece, hb), M[3], sm, mid2[3];
+                int plane2 = chord_plane(&A, ta, tb, M, &sm, mid2);
+                /* once one occluder shadows the whole stretch the union over it is
+                 * the stretch, whatever the others add: they are skipped */
+                int first = day.n, covered = 0;
+                if (owner >= 0) occluder_intervals_arc(S, -1, p, nrm, &A, ta, tb, C->grid, &day);
+                for (int k = 0; k < nc; ++k) {
+                    for (; first < day.n && !covered; ++first)
+                        covered = day.v[first].lo <= ta && day.v[first].hi >= tb;
+                    if (covered) break;
+                    if (plane2 && box_off_slab(S, cand[k], p, M, sm, mid2)) continue;
+                    occluder_intervals_arc(S, cand[k], p, nrm, &A, ta, tb, C->grid, &day);
+                }
+            }
+        }
+        int m = ivec_union(&day);
+        double meas = 0.0, run = 0.0;
+        for (int a = 0; a < m; ++a) {
+            meas += day.v[a].hi - day.v[a].lo;
+            if (day.v[a].hi - day.v[a].lo > run) run = day.v[a].hi - day.v[a].lo;
+        }
+        int bin = C->day_bin ? C->day_bin[dd] : dd;
+        if (C->minutes) C->minutes[(int64_t)bin * n + i] += meas;
+        if (C->longest && run > C->longest[(int64_t)bin * n + i]) C->longest[(int64_t)bin * n + i] = run;
+    }
+    free(day.v);
+    free(cand);
+}
+
+void orc_continuous_true(const orc_scene *s, const orc_points *p, int n_days, const int32_t *ymd,
+                         const double *tz_h, const double *span, const int32_t *day_bin, int n_bins,
+                         double lat_deg, double lon_deg, double piece_min, double grid_min,
+                         double *minutes, double *longest, int threads)
+{
+    scene64 S;
+    scene64_init(&S, s);
+    if (minutes) memset(minutes, 0, sizeof(double) * (size_t)n_bins * p->n);
+    if (longest) memset(longest, 0, sizeof(double) * (size_t)n_bins * p->n);
+    /* the directions at the scan grid's instants and at the 64 sub-instants
+     * of its finer rescans, once per day for all points */
+    const double tab_step = grid_min / 64.0;
+    double **tab = (double **)calloc(n_days + 1, sizeof(double *));
+    int64_t *n_tab = (int64_t *)calloc(n_days + 1, sizeof(int64_t));
+    for (int dd = 0; dd < n_days; ++dd) {
+        double T0 = span[2 * dd], T1 = span[2 * dd + 1];
+        int64_t m = T1 > T0 ? (int64_t)ceil((T1 - T0) / tab_step) + 1 : 0;
+        n_tab[dd] = m;
+        tab[dd] = (double *)malloc(sizeof(double) * (3 * (size_t)m + 1));
+    }
+    day_table_ctx T = {ymd, tz_h, span, lat_deg, lon_deg, tab_step, tab, n_tab, n_days};
+    parallel_for((int64_t)n_days * 64, threads, day_table_part, &T);
+    true_ctx C = {&S, p, n_days, ymd, tz_h, span, day_bin, lat_deg, lon_deg, piece_min, grid_min,
+                  tab_step, tab, n_tab, minutes, longest};
+    parallel_for(p->n, threads, true_point, &C);
+    for (int dd = 0; dd < n_days; ++dd) free(tab[dd]);
+    free(tab);
+    free(n_tab);
     scene64_free(&S);
 }
 
