@@ -279,6 +279,29 @@ sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts
                         const sa_path *path, const sa_accum_opts *opts, int32_t *counts,
                         float *minutes, uint32_t *bits);
 
+/* For callers that cannot allocate device memory during a call (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): sa_accumulate with the same arguments, outputs and results,
+ * except that it allocates nothing.  The accrual form's per-segment
+ * hierarchy views (64 bytes per node and segment) go to a fixed device
+ * array of SA_NOALLOC_SCRATCH_BYTES that every device the library runs on
+ * holds from its first sa_create until the process ends, and the spill
+ * queue is the one sa_create made for the context; the sampled form needs
+ * no scratch.  A launch covers as many segments as the array holds
+ * (SA_NOALLOC_SCRATCH_BYTES / (64 x interior nodes): 52 on a 20,000-prism
+ * scene), longer paths run as several launches; with opts->longest a
+ * launch must hold a whole day.  Every call on one device shares the array
+ * and its contents are rebuilt by each launch, so calls that overlap on one
+ * device (other streams or contexts) race and must be ordered by the
+ * caller.  Errors: as sa_accumulate; CAPACITY (before any work is
+ * enqueued) when one segment's views (a scene of more than about 1M
+ * prisms) or, with longest, one day's views exceed the array; DEVICE if the
+ * array's address could not be obtained at sa_create. */
+#define SA_NOALLOC_SCRATCH_BYTES (64ll << 20)
+sa_status sa_accumulate_noalloc(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts,
+                                const sa_path *path, const sa_accum_opts *opts, int32_t *counts,
+                                float *minutes, uint32_t *bits);
+
 /* Batched development scenarios (Sec. 7.1 impact analysis, many at once):
  * n_var variants of `scene`, variant v replacing the heights of buildings
  * var_ids[v*k .. v*k+k) by var_h[v*k ..) (device arrays, original ids,

@@ -29,7 +29,7 @@ _ERRORS = {-1: "INVALID_ARG", -2: "GEOMETRY", -3: "CAPACITY", -4: "OOM", -5: "DE
 EXPORTS = ["sa_create", "sa_destroy", "sa_set_stream", "sa_last_error", "sa_sync", "sa_version",
            "sa_scene_upload", "sa_scene_set_heights", "sa_scene_get_info", "sa_scene_read_bvh",
            "sa_scene_destroy", "sa_sunpath", "sa_path_upload", "sa_path_upload_graph", "sa_path_info", "sa_path_destroy",
-           "sa_accumulate", "sa_accumulate_batched", "sa_grad_heights", "sa_region_sum",
+           "sa_accumulate", "sa_accumulate_noalloc", "sa_accumulate_batched", "sa_grad_heights", "sa_region_sum",
            "sa_building_contribution", "sa_path_bin_span", "sa_region_score", "sa_sam_accumulate"]
 
 
@@ -106,6 +106,8 @@ def lib():
             "sa_path_info": (i32, [vp, vp, vp, vp]),
             "sa_path_destroy": (None, [vp]),
             "sa_accumulate": (i32, [vp, vp, C.POINTER(sa_points), vp, C.POINTER(sa_accum_opts), vp, vp, vp]),
+            "sa_accumulate_noalloc": (i32, [vp, vp, C.POINTER(sa_points), vp, C.POINTER(sa_accum_opts), vp, vp,
+                                            vp]),
             "sa_accumulate_batched": (i32, [vp, vp, i32, i32, vp, vp, C.POINTER(sa_points), vp, vp,
                                             C.POINTER(sa_accum_opts), vp, vp]),
             "sa_grad_heights": (i32, [vp, vp, C.POINTER(sa_points), vp, vp, vp]),
@@ -403,6 +405,17 @@ def sa_accumulate(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, mod
     ps = pts.struct()
     _check(ctx, lib().sa_accumulate(ctx.handle, scene.handle, C.byref(ps), path.handle, C.byref(opts),
                                     _ptr(counts), _ptr(minutes), _ptr(bits)))
+
+
+def sa_accumulate_noalloc(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, mode: int, counts=None,
+                          minutes=None, bits=None, flags=0, out_scale=1.0, work=None, longest=None):
+    """sa_accumulate without any allocation inside the call (the library's
+    fixed per-device scratch; see the C ABI): for callers that cannot
+    allocate."""
+    opts = sa_accum_opts(mode, flags, out_scale, 0, _ptr(work), _ptr(longest))
+    ps = pts.struct()
+    _check(ctx, lib().sa_accumulate_noalloc(ctx.handle, scene.handle, C.byref(ps), path.handle, C.byref(opts),
+                                            _ptr(counts), _ptr(minutes), _ptr(bits)))
 
 
 def accumulate(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, mode: int, want_counts=True,

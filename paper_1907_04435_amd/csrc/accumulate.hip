@@ -1022,9 +1022,11 @@ sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_va
     return SA_OK;
 }
 
-int64_t seg_views_cap(const DeviceScene &s)
+int64_t seg_views_cap(const DeviceScene &s, const Scratch &scr)
 {
-    return std::max<int64_t>(1, kSegNodeBytes / ((int64_t)std::max(s.n_nodes, 1) * (int64_t)sizeof(SegNode)));
+    const int64_t per_seg = (int64_t)std::max(s.n_nodes, 1) * (int64_t)sizeof(SegNode);
+    if (scr.fixed) return (int64_t)scr.bytes / per_seg;
+    return std::max<int64_t>(1, kSegNodeBytes / per_seg);
 }
 
 sa_status build_seg_views(const DeviceScene &s, const DevicePath &p, int j0, int j1, int64_t stride, Scratch &scr,
@@ -1034,6 +1036,11 @@ sa_status build_seg_views(const DeviceScene &s, const DevicePath &p, int j0, int
     if (s.n_b == 0 || j1 <= j0) return SA_OK;
     const int64_t nt = (int64_t)(j1 - j0) * s.n_nodes;
     const size_t need = (size_t)(j1 - j0) * stride * sizeof(SegNode);
+    if (scr.bytes < need && scr.fixed) {
+        err = "per-segment node views need " + std::to_string(need) + " bytes, more than the fixed " +
+              std::to_string(scr.bytes);
+        return SA_ERR_CAPACITY;
+    }
     if (scr.bytes < need) {
         // the previous contents may still be read by queued kernels
         (void)hipStreamSynchronize(st);
@@ -1068,11 +1075,24 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
     // each about kChunkWork point-segments and covering at most
     // kSegNodeBytes of per-segment node views (built just before it);
     // outputs are accumulated, so the split is invisible in the results.
-    const int64_t per = std::min(std::max<int64_t>(1, kChunkWork / std::max<int64_t>(pts.n, 1)), seg_views_cap(s));
+    const int64_t cap = seg_views_cap(s, scr);
+    if (s.n_b > 0 && p.n_segs > 0 && cap < 1) {
+        err = "one segment's node views (" + std::to_string((int64_t)s.n_nodes * (int64_t)sizeof(SegNode)) +
+              " bytes) exceed the fixed scratch (" + std::to_string(scr.bytes) + " bytes)";
+        return SA_ERR_CAPACITY;
+    }
+    const int64_t per = std::min(std::max<int64_t>(1, kChunkWork / std::max<int64_t>(pts.n, 1)), std::max<int64_t>(cap, 1));
     if (longest) {
         // whole days per launch, so a run never spans two launches (one
         // day per launch at least, whatever its views take)
         const int D = (int)p.day_seg_off.size() - 1;
+        if (scr.fixed && s.n_b > 0)
+            for (int d = 0; d < D; ++d)
+                if (p.day_seg_off[d + 1] - p.day_seg_off[d] > cap) {
+                    err = "one day's node views (" + std::to_string(p.day_seg_off[d + 1] - p.day_seg_off[d]) +
+                          " segments) exceed the fixed scratch (" + std::to_string(cap) + " segments fit)";
+                    return SA_ERR_CAPACITY;
+                }
         for (int d0 = 0; d0 < D;) {
             int d1 = d0 + 1;
             while (d1 < D && p.day_seg_off[d1 + 1] - p.day_seg_off[d0] <= per) ++d1;
@@ -1114,7 +1134,7 @@ sa_status launch_contribution(const DeviceScene &s, const DevicePath &p, const P
     const PointArgs P = point_args(pts, s);
     // long spans: several launches over consecutive segment ranges
     const int64_t per =
-        std::min(std::max<int64_t>(1, kChunkWork / 2 / std::max<int64_t>(pts.n, 1)), seg_views_cap(s));
+        std::min(std::max<int64_t>(1, kChunkWork / 2 / std::max<int64_t>(pts.n, 1)), seg_views_cap(s, scr));
     for (int64_t j0 = 0; j0 < p.n_segs; j0 += per) {
         const int j1 = (int)std::min<int64_t>(j0 + per, p.n_segs);
         SegNode *views;

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -24,6 +25,8 @@ struct sa_ctx {
     sa::Scratch scratch_seg;      // per-segment node views of the accrual form
     sa::Scratch scratch_sam;      // one segment's raster shadow accrual map
     uint32_t sam_stamp = 0;       // the last segment stamp written into it
+    void *noalloc = nullptr;      // this device's fixed scratch (device address), or null
+    std::string noalloc_err;      // why it is null
 };
 
 struct sa_scene {
@@ -61,6 +64,42 @@ bool set_device(sa_ctx *ctx)
 {
     (void)hipGetLastError();
     return hipSetDevice(ctx->device) == hipSuccess;
+}
+
+}  // namespace
+
+// Fixed device scratch of sa_accumulate_noalloc, for callers that cannot
+// allocate: the accrual form's per-segment hierarchy views.  Every device
+// the library runs on holds its own copy from first use until the process
+// ends.  Host code never uses this name as an address: the device address
+// comes from hipGetSymbolAddress, once per device, in sa_create.
+static __device__ __align__(256) unsigned char scratch[SA_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_noalloc_mu;
+std::map<int, void *> g_noalloc_ptr;  // device -> address of `scratch` on it
+
+// With ctx->device current: the device address of this device's fixed
+// scratch (looked up on the device's first context, then reused).
+void attach_noalloc_scratch(sa_ctx *ctx)
+{
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    auto it = g_noalloc_ptr.find(ctx->device);
+    if (it != g_noalloc_ptr.end()) {
+        ctx->noalloc = it->second;
+        return;
+    }
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        ctx->noalloc = nullptr;
+        ctx->noalloc_err = std::string("fixed scratch unavailable: hipGetSymbolAddress: ") + hipGetErrorString(e);
+        return;
+    }
+    g_noalloc_ptr[ctx->device] = ptr;
+    ctx->noalloc = ptr;
 }
 
 }  // namespace
@@ -115,6 +154,7 @@ sa_status sa_create(int32_t device, void *hip_stream, sa_ctx **out)
         sa_destroy(c);
         return SA_ERR_OOM;
     }
+    attach_noalloc_scratch(c);
     *out = c;
     return SA_OK;
 }
@@ -672,6 +712,57 @@ sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts
         rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->longest, opts->work,
                                 ctx->spill, ctx->scratch_seg, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate: " + err);
+    return SA_OK;
+}
+
+sa_status sa_accumulate_noalloc(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts, const sa_path *path,
+                                const sa_accum_opts *opts, int32_t *counts, float *minutes, uint32_t *bits)
+{
+    if (!ctx) return SA_ERR_INVALID_ARG;
+    if (!scene || !path || !opts) return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate_noalloc: null argument");
+    sa_status rc = check_points(ctx, pts);
+    if (rc != SA_OK) return rc;
+    if (opts->mode != SA_SAMPLED && opts->mode != SA_ACCRUAL)
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate_noalloc: unknown mode");
+    if (bits && opts->mode != SA_SAMPLED)
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate_noalloc: bit vectors exist for the sampled form only");
+    if (opts->longest && opts->mode == SA_ACCRUAL && path->d.merged)
+        return fail(ctx, SA_ERR_INVALID_ARG,
+                    "sa_accumulate_noalloc: a direction-graph path has no time order: no continuous shadow");
+    if (!ctx->noalloc) return fail(ctx, SA_ERR_DEVICE, "sa_accumulate_noalloc: " + ctx->noalloc_err);
+    if (!counts && !minutes && !bits && !opts->longest) return SA_OK;
+    if (opts->mode == SA_ACCRUAL && scene->d.n_b > 0 && path->d.n_segs > 0 && pts->n > 0) {
+        // refuse before any work: a launch must hold one segment's views, and
+        // with the continuous shadow a whole day's
+        const int64_t per_seg = (int64_t)std::max(scene->d.n_nodes, 1) * (int64_t)sizeof(sa::SegNode);
+        const int64_t cap = (int64_t)SA_NOALLOC_SCRATCH_BYTES / per_seg;
+        int64_t need = 1;
+        if (opts->longest)
+            for (size_t d = 0; d + 1 < path->d.day_seg_off.size(); ++d)
+                need = std::max<int64_t>(need, path->d.day_seg_off[d + 1] - path->d.day_seg_off[d]);
+        if (need > cap)
+            return fail(ctx, SA_ERR_CAPACITY,
+                        "sa_accumulate_noalloc: " + std::to_string(need) + " segments of node views (" +
+                            std::to_string(per_seg) + " bytes each) must fit the fixed scratch of " +
+                            std::to_string((int64_t)SA_NOALLOC_SCRATCH_BYTES) + " bytes");
+    }
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    const float scale = opts->out_scale == 0.f ? 1.f : opts->out_scale;
+    rc = clear_outputs(ctx, opts->flags, (int64_t)path->d.n_bins * pts->n, counts, minutes, opts->longest);
+    if (rc != SA_OK) return rc;
+    std::string err;
+    if (opts->mode == SA_SAMPLED) {
+        rc = sa::launch_sampled(scene->d, path->d, view(pts), scale, counts, minutes, bits, opts->longest,
+                                opts->work, ctx->stream, err);
+    } else {
+        sa::Scratch fixed;
+        fixed.ptr = ctx->noalloc;
+        fixed.bytes = (size_t)SA_NOALLOC_SCRATCH_BYTES;
+        fixed.fixed = true;
+        rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->longest, opts->work,
+                                ctx->spill, fixed, ctx->stream, err);
+    }
+    if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate_noalloc: " + err);
     return SA_OK;
 }
 

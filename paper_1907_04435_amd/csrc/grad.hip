@@ -206,7 +206,7 @@ sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsVie
     const GradArgs G{dl, grad, s.order};
     // segment ranges whose per-segment node views fit the budget, each
     // followed by its spill rounds
-    const int64_t per = seg_views_cap(s);
+    const int64_t per = seg_views_cap(s, scr);
     for (int64_t j0 = 0; j0 < p.n_segs; j0 += per) {
         const int j1 = (int)std::min<int64_t>(j0 + per, p.n_segs);
         SegNode *views;

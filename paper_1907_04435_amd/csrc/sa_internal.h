@@ -157,10 +157,12 @@ struct PointsView {
     const int32_t *owner;
 };
 
-// Scratch owned by a context (grown on demand, freed with it).
+// Scratch owned by a context (grown on demand, freed with it), or a fixed
+// buffer the library never grows or frees (fixed = true).
 struct Scratch {
     void *ptr = nullptr;
     size_t bytes = 0;
+    bool fixed = false;
 };
 
 struct SpillQueue {
@@ -185,12 +187,13 @@ sa_status launch_contribution(const DeviceScene &s, const DevicePath &p, const P
                               const float *weight, double *contrib, Scratch &scr, hipStream_t st,
                               std::string &err);
 // Per-segment node views (SegNode) of segments [j0, j1) into scr (grown as
-// needed, with the stream synchronised first), segment j's views at
-// (j - j0) * stride; views = nullptr for an empty scene.  seg_views_cap: segments whose views fit the per-launch
-// budget.
+// needed, with the stream synchronised first; a fixed scr that is too small
+// is a CAPACITY error), segment j's views at (j - j0) * stride; views =
+// nullptr for an empty scene.  seg_views_cap: segments whose views fit the
+// per-launch budget (a fixed scr: its size; 0 if not even one fits).
 sa_status build_seg_views(const DeviceScene &s, const DevicePath &p, int j0, int j1, int64_t stride, Scratch &scr,
                           hipStream_t st, SegNode *&views, std::string &err);
-int64_t seg_views_cap(const DeviceScene &s);
+int64_t seg_views_cap(const DeviceScene &s, const Scratch &scr);
 // Gross shadow by raster shadow accrual maps (Sec. 4) into counts/minutes
 // [n_bins * n] (already cleared): per segment a map of slices x nu x nv
 // 64-bit words (stamp, depth) in scr (grown as needed; max_texels caps one
