@@ -103,11 +103,15 @@ const char *sa_version(void);
 sa_status sa_scene_upload(sa_ctx *ctx, int32_t n_b, const int32_t *vert_off,
                           const float *xy, const float *height, sa_scene **out);
 
-/* Replace the heights of buildings ids[0..n) (host arrays, original
- * building ids) by h[0..n) (> 0) and refit the hierarchy's boxes (heights
- * only: the topology is kept).  Models the paper's impact analysis, where a
- * building is replaced and the shadows recomputed (Sec. 7.1).
- * Host-synchronous. */
+/* Replace the heights of buildings ids[0..n) (original building ids) by
+ * h[0..n) (> 0) and refit the hierarchy's boxes (heights only: the
+ * topology is kept).  Models the paper's impact analysis, where a building
+ * is replaced and the shadows recomputed (Sec. 7.1).  Host arrays: checked
+ * on the host (INVALID_ARG / GEOMETRY), host-synchronous.  Device arrays
+ * (both; e.g. the heights a gradient step produced): written and refitted
+ * on the context's stream with no host round trip; an id out of range or a
+ * height that is not a positive finite number is skipped and reported by
+ * the next sa_sync (INVALID_ARG). */
 sa_status sa_scene_set_heights(sa_ctx *ctx, sa_scene *scene, int32_t n, const int32_t *ids,
                                const float *h);
 
@@ -194,7 +198,7 @@ sa_status sa_path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, sa_path **out);
  * output bin whose start and end knots fall in the same pair of cells
  * become one edge, computed once on the members' mean arc (the normalised
  * mean of their start directions to that of their end directions) and
- * weighted by their number (Eq. 2).  Each merged segment keeps its own
+ * weighted by their number (Eq. (1)).  Each merged segment keeps its own
  * duration; sample counts are the edge's times its multiplicity.  Every
  * accrual-form call takes the graph: sa_accumulate, sa_accumulate_batched,
  * sa_building_contribution and sa_grad_heights.  An approximation for long
@@ -251,6 +255,13 @@ typedef struct {
      * pieces in segment order inside the kernel (slower).
      * sa_accumulate_batched: must be NULL. */
     float *longest;
+    /* Optional device double [n_bins * n] (bin-major; NULL = not wanted;
+     * SA_ACCRUAL only, not sa_accumulate_batched): the accrual minutes
+     * before their rounding to float32 -- each lane sums its segment
+     * measures in FP64 -- times out_scale, e.g. for loss totals whose
+     * differences must not carry float32 rounding.  Cleared first unless
+     * SA_FLAG_ADD. */
+    double *minutes64;
 } sa_accum_opts;
 
 /* Gross shadow of every point over every day of `path`, summed per bin.
@@ -317,15 +328,21 @@ sa_status sa_accumulate_batched(sa_ctx *ctx, const sa_scene *scene, int32_t n_va
                                 float *minutes);
 
 /* Gradient of L = sum_bins sum_p dl_dmin[bin*n + p] * minutes_accrual(p, bin)
- * with respect to every building height: each boundary of a point's
- * occluded set that is made by a roof edge moves with the height; its time
- * derivative comes from implicit differentiation of the roof-grazing
- * condition (closing ends +, opening ends -).  Traversals are recomputed,
- * nothing is stored from the forward pass.  dl_dmin: device float
- * [n_bins * n] or NULL (all ones).  grad: device float [n_b] (original
- * ids), overwritten.  Errors: INVALID_ARG, DEVICE. */
+ * (minutes times opts->out_scale) with respect to every building height:
+ * each boundary of a point's occluded set that is made by a roof edge
+ * moves with the height; its time derivative comes from implicit
+ * differentiation of the roof-grazing condition (closing ends +, opening
+ * ends -).  Traversals are recomputed, nothing is stored from the forward
+ * pass; contributions are summed per building across each wave and
+ * accumulated in FP64, then rounded once.  opts: NULL or mode SA_ACCRUAL
+ * (the sampled form's counts are piecewise constant in the heights);
+ * out_scale and SA_FLAG_ADD (add into grad instead of overwriting it) are
+ * honoured, the other fields ignored.  dl_dmin: device float [n_bins * n]
+ * or NULL (all ones).  grad: device float [n_b] (original ids).
+ * Errors: INVALID_ARG, OOM, DEVICE. */
 sa_status sa_grad_heights(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts,
-                          const sa_path *path, const float *dl_dmin, float *grad);
+                          const sa_path *path, const sa_accum_opts *opts, const float *dl_dmin,
+                          float *grad);
 
 /* Building contribution (Sec. 7.2): per output bin and building, the time
  * the points spend in that building's own shadow along the great-circle
@@ -381,16 +398,20 @@ sa_status sa_path_bin_span(const sa_path *path, double *span);
 
 /* Region shadow score (Sec. 7.2): out[r] = sum over p in
  * [region_off[r], region_off[r+1]) of (area ? area[p] : 1) times
- * sum over bins b of bin_weight[b] * values[b * n + p], accumulated in
- * FP64.  With values = per-bin shadow minutes and bin_weight[b] =
- * w_b / span_b (w_b in [-1, 1] the interval's weight, span_b from
- * sa_path_bin_span) this is the score: the weighted fraction of each
+ * sum over the path's bins b of interval_weight[b] * values[b * n + p] /
+ * span_b, accumulated in FP64, with span_b the bin's daylight minutes (the
+ * sum of its days' spans, as sa_path_bin_span gives).  With values = the
+ * per-bin shadow minutes of `path` and interval_weight[b] in [-1, 1] the
+ * interval's weight, this is the score: the weighted fraction of each
  * interval's daylight spent in shadow, summed over the region.
- * values: device float [n_bins * n] (bin-major); bin_weight: device double
- * [n_bins]; region_off: device int64 [n_reg+1]; area: device float [n] or
- * NULL; out: device double [n_reg].  Errors: INVALID_ARG, OOM, DEVICE. */
-sa_status sa_region_score(sa_ctx *ctx, const float *values, int32_t n_bins, int64_t n,
-                          const double *bin_weight, const int64_t *region_off, int32_t n_reg,
+ * values: device float [n_bins * n] (bin-major, n_bins = the path's);
+ * interval_weight: host double [n_bins], read before the call returns;
+ * region_off: device int64 [n_reg+1]; area: device float [n] or NULL;
+ * out: device double [n_reg].  Host-synchronous (the per-bin weights are
+ * uploaded).  Errors: INVALID_ARG (also a bin without daylight), OOM,
+ * DEVICE. */
+sa_status sa_region_score(sa_ctx *ctx, const sa_path *path, const float *values, int64_t n,
+                          const double *interval_weight, const int64_t *region_off, int32_t n_reg,
                           const float *area, double *out);
 
 /* Region sums (the shadow area of Sec. 7.2): out[r] = sum over

@@ -405,7 +405,7 @@ def edge_arc(path: OraclePath, group):
 
 
 def graph_continuous(scene, pts, path: OraclePath, bound_deg, grid_min=1.0 / 12.0, threads=None):
-    """Accrual form over the direction graph (Sec. 6, Eq. 2): every edge's
+    """Accrual form over the direction graph (Sec. 6, Eq. (1)): every edge's
     occluded set is computed once, on its representative arc (``edge_arc``),
     and each member counts with its own duration: the edge's minutes are the
     arc's continuous minutes times (sum of the members' durations) / (the

@@ -74,7 +74,8 @@ class sa_sam_opts(C.Structure):
 
 class sa_accum_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("flags", C.c_uint32), ("out_scale", C.c_float),
-                ("grid_blocks", C.c_int32), ("work", C.c_void_p), ("longest", C.c_void_p)]
+                ("grid_blocks", C.c_int32), ("work", C.c_void_p), ("longest", C.c_void_p),
+                ("minutes64", C.c_void_p)]
 
 
 _lib = None
@@ -110,12 +111,12 @@ def lib():
                                             vp]),
             "sa_accumulate_batched": (i32, [vp, vp, i32, i32, vp, vp, C.POINTER(sa_points), vp, vp,
                                             C.POINTER(sa_accum_opts), vp, vp]),
-            "sa_grad_heights": (i32, [vp, vp, C.POINTER(sa_points), vp, vp, vp]),
+            "sa_grad_heights": (i32, [vp, vp, C.POINTER(sa_points), vp, C.POINTER(sa_accum_opts), vp, vp]),
             "sa_region_sum": (i32, [vp, vp, i64, vp, i32, vp, vp]),
             "sa_building_contribution": (i32, [vp, vp, C.POINTER(sa_points), vp, vp, vp]),
             "sa_sam_accumulate": (i32, [vp, vp, C.POINTER(sa_points), vp, C.POINTER(sa_sam_opts), vp, vp]),
             "sa_path_bin_span": (i32, [vp, vp]),
-            "sa_region_score": (i32, [vp, vp, i32, i64, vp, vp, i32, vp, vp]),
+            "sa_region_score": (i32, [vp, vp, vp, i64, vp, vp, i32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -291,6 +292,17 @@ class Scene:
         return cls(ctx, scene.vert_off, scene.xy, scene.height)
 
     def set_heights(self, ids, h):
+        """Host arrays (checked and applied synchronously) or device tensors
+        (both; applied on the context's stream, bad entries reported by
+        sync)."""
+        if getattr(ids, "is_cuda", False) or getattr(h, "is_cuda", False):
+            import torch
+            ids = ids.to(device=h.device, dtype=torch.int32).contiguous()
+            h = h.to(torch.float32).contiguous()
+            self._keep = (ids, h)   # alive until the stream has read them
+            _check(self.ctx, lib().sa_scene_set_heights(self.ctx.handle, self.handle, int(ids.numel()),
+                                                        _ptr(ids), _ptr(h)))
+            return
         ids = np.ascontiguousarray(ids, np.int32)
         h = np.ascontiguousarray(h, np.float32)
         _check(self.ctx, lib().sa_scene_set_heights(self.ctx.handle, self.handle, len(ids), _ptr(ids), _ptr(h)))
@@ -397,22 +409,24 @@ class DevicePoints:
 # compute entry points
 # --------------------------------------------------------------------------
 def sa_accumulate(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, mode: int, counts=None,
-                  minutes=None, bits=None, flags=0, out_scale=1.0, work=None, longest=None):
+                  minutes=None, bits=None, flags=0, out_scale=1.0, work=None, longest=None, minutes64=None):
     """Gross shadow into caller-provided device tensors (see the C ABI).
     ``work``: optional device int64 [8] work counters (instrumented run).
-    ``longest``: optional device float32 [bins, n] continuous shadow."""
-    opts = sa_accum_opts(mode, flags, out_scale, 0, _ptr(work), _ptr(longest))
+    ``longest``: optional device float32 [bins, n] continuous shadow.
+    ``minutes64``: optional device float64 [bins, n] accrual minutes before
+    their rounding to float32."""
+    opts = sa_accum_opts(mode, flags, out_scale, 0, _ptr(work), _ptr(longest), _ptr(minutes64))
     ps = pts.struct()
     _check(ctx, lib().sa_accumulate(ctx.handle, scene.handle, C.byref(ps), path.handle, C.byref(opts),
                                     _ptr(counts), _ptr(minutes), _ptr(bits)))
 
 
 def sa_accumulate_noalloc(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, mode: int, counts=None,
-                          minutes=None, bits=None, flags=0, out_scale=1.0, work=None, longest=None):
+                          minutes=None, bits=None, flags=0, out_scale=1.0, work=None, longest=None, minutes64=None):
     """sa_accumulate without any allocation inside the call (the library's
     fixed per-device scratch; see the C ABI): for callers that cannot
     allocate."""
-    opts = sa_accum_opts(mode, flags, out_scale, 0, _ptr(work), _ptr(longest))
+    opts = sa_accum_opts(mode, flags, out_scale, 0, _ptr(work), _ptr(longest), _ptr(minutes64))
     ps = pts.struct()
     _check(ctx, lib().sa_accumulate_noalloc(ctx.handle, scene.handle, C.byref(ps), path.handle, C.byref(opts),
                                             _ptr(counts), _ptr(minutes), _ptr(bits)))
@@ -448,7 +462,7 @@ def sa_accumulate_batched(ctx: Context, scene: Scene, var_ids, var_h, pts: Devic
     """Batched development variants (device tensors var_ids [V, k] int32,
     var_h [V, k] float32, var_off [V+1] int64).  ``grid_blocks``: size of
     the persistent launch (0 = library default)."""
-    opts = sa_accum_opts(SA_ACCRUAL, flags, out_scale, grid_blocks, None, None)
+    opts = sa_accum_opts(SA_ACCRUAL, flags, out_scale, grid_blocks, None, None, None)
     ps = pts.struct()
     V, k = int(var_ids.shape[0]), int(var_ids.shape[1]) if var_ids.dim() > 1 else 0
     _check(ctx, lib().sa_accumulate_batched(ctx.handle, scene.handle, V, k, _ptr(var_ids), _ptr(var_h),
@@ -456,10 +470,14 @@ def sa_accumulate_batched(ctx: Context, scene: Scene, var_ids, var_h, pts: Devic
                                             _ptr(counts), _ptr(minutes)))
 
 
-def sa_grad_heights(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, dl_dmin, grad):
+def sa_grad_heights(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, dl_dmin, grad, flags=0,
+                    out_scale=1.0):
+    """d(sum dl_dmin * minutes * out_scale)/dH into device float grad [n_b]
+    (SA_FLAG_ADD in flags adds into it)."""
+    opts = sa_accum_opts(SA_ACCRUAL, flags, out_scale, 0, None, None, None)
     ps = pts.struct()
-    _check(ctx, lib().sa_grad_heights(ctx.handle, scene.handle, C.byref(ps), path.handle, _ptr(dl_dmin),
-                                      _ptr(grad)))
+    _check(ctx, lib().sa_grad_heights(ctx.handle, scene.handle, C.byref(ps), path.handle, C.byref(opts),
+                                      _ptr(dl_dmin), _ptr(grad)))
 
 
 def sa_building_contribution(ctx: Context, scene: Scene, pts: DevicePoints, path: Path, weight, contrib):
@@ -500,10 +518,12 @@ def building_contribution(ctx: Context, scene: Scene, pts: DevicePoints, path: P
     return out
 
 
-def sa_region_score(ctx: Context, values, bin_weight, region_off, out, area=None):
-    n_bins, n = int(values.shape[0]), int(values.shape[1])
-    _check(ctx, lib().sa_region_score(ctx.handle, _ptr(values), n_bins, n, _ptr(bin_weight), _ptr(region_off),
-                                      int(region_off.numel()) - 1, _ptr(area), _ptr(out)))
+def sa_region_score(ctx: Context, path: Path, values, interval_weight, region_off, out, area=None):
+    w = np.ascontiguousarray(interval_weight, np.float64)
+    if len(w) != path.n_bins:
+        raise ValueError("one interval weight per bin of the path")
+    _check(ctx, lib().sa_region_score(ctx.handle, path.handle, _ptr(values), int(values.shape[1]), _ptr(w),
+                                      _ptr(region_off), int(region_off.numel()) - 1, _ptr(area), _ptr(out)))
 
 
 def shadow_score(ctx: Context, path: Path, values, interval_weight, region_off, area=None):
@@ -511,11 +531,8 @@ def shadow_score(ctx: Context, path: Path, values, interval_weight, region_off, 
     ``values`` [bins, n] and one weight in [-1, 1] per bin: returns device
     float64 [n_regions]."""
     torch = ctx.torch
-    span = path.bin_span()
-    w = torch.tensor(np.asarray(interval_weight, np.float64) / span, dtype=torch.float64,
-                     device=values.device)
     out = torch.empty(int(region_off.numel()) - 1, dtype=torch.float64, device=values.device)
-    sa_region_score(ctx, values, w, region_off, out, area)
+    sa_region_score(ctx, path, values, interval_weight, region_off, out, area)
     return out
 
 
@@ -532,8 +549,13 @@ def shadow_minutes_fn():
     class ShadowMinutes(torch.autograd.Function):
         @staticmethod
         def forward(fctx, heights, sactx, scene, pts, path):
-            h = heights.detach().to("cpu", torch.float32).numpy()
-            scene.set_heights(np.arange(scene.n_b, dtype=np.int32), h)
+            # heights stay on the device: written and refitted on the stream
+            h = heights.detach().to(device=f"cuda:{sactx.device}", dtype=torch.float32).contiguous()
+            ids = getattr(scene, "_all_ids", None)
+            if ids is None or ids.numel() != scene.n_b:
+                ids = torch.arange(scene.n_b, dtype=torch.int32, device=h.device)
+                scene._all_ids = ids
+            scene.set_heights(ids, h)
             minutes = torch.empty((path.n_bins, pts.n), dtype=torch.float32, device=f"cuda:{sactx.device}")
             sa_accumulate(sactx, scene, pts, path, SA_ACCRUAL, None, minutes)
             fctx.objs = (sactx, scene, pts, path)

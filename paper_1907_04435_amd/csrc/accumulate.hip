@@ -23,6 +23,25 @@ constexpr int kSpillBlocks = 1024;
 constexpr int64_t kChunkWork = 4000000000ll;  // point-segments per accrual launch
 constexpr int64_t kSegNodeBytes = 256ll << 20;  // per-segment node views per accrual launch
 
+// Per-bin outputs of the accrual kernels.  A bin whose first segment lies in
+// the launch is stored (no clear beforehand, no read); a bin continued from
+// an earlier launch, or any bin under SA_FLAG_ADD, is added to.
+struct BinOut {
+    int32_t *counts;
+    float *minutes;
+    double *minutes64;    // the FP64 lane sums behind minutes (optional)
+    int32_t fresh_first;  // the launch's first bin starts in it
+    int32_t fresh_rest;   // the later bins of the launch start in it
+};
+
+__device__ __forceinline__ void put_bin(const BinOut &O, int64_t o, bool fresh, int cnt, double mins, float scale)
+{
+    const double v = mins * scale;
+    if (O.counts) O.counts[o] = (fresh ? 0 : O.counts[o]) + cnt;
+    if (O.minutes) O.minutes[o] = (fresh ? 0.f : O.minutes[o]) + (float)v;
+    if (O.minutes64) O.minutes64[o] = (fresh ? 0.0 : O.minutes64[o]) + v;
+}
+
 // ------------------------------------------------------------------ sampled
 // Sum a per-lane counter over the wave and add it to a global total.
 __device__ __forceinline__ void flush_work(const Work &w, uint64_t *work)
@@ -303,8 +322,8 @@ __device__ __forceinline__ bool roof_covered(cNode *nodes, StackEntry *stack, cf
 template <bool kCount>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_accrual(
     const Node *nodes_g, const SegNode *snodes_g, int n_nodes, const int32_t *voff_g, const float4 *verts_g,
-    const float *height_g, const SegConst *segs_g, int j0, int j1, PointArgs P, float scale, int32_t *counts,
-    float *minutes, SpillArgs S, uint64_t *work)
+    const float *height_g, const SegConst *segs_g, int j0, int j1, PointArgs P, float scale, BinOut O,
+    SpillArgs S, uint64_t *work)
 {
     Work wk{0, 0, 0, 0, 0, 0, 0};
     cNode *nodes = (cNode *)nodes_g;
@@ -324,16 +343,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     int cnt = 0;
     double mins = 0.0;  // per-lane FP64: long spans sum thousands of segment measures
     int bin = j1 > j0 ? ld(segs + j0).bin : 0;
+    bool fresh = O.fresh_first != 0;
     for (int j = j0; j < j1; ++j) {
         const SegConst g = ld(segs + j);
         if (g.bin != bin) {
-            if (valid) {
-                if (counts) counts[(int64_t)bin * n + i] += cnt;
-                if (minutes) minutes[(int64_t)bin * n + i] += (float)(mins * scale);
-            }
+            if (valid) put_bin(O, (int64_t)bin * n + i, fresh, cnt, mins, scale);
             cnt = 0;
             mins = 0.0;
             bin = g.bin;
+            fresh = O.fresh_rest != 0;
         }
         Union4 U;
         bool ov;
@@ -353,10 +371,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
         }
         spill_push(S, valid && ov, i, j, 0.f, gm.theta);
     }
-    if (valid && j1 > j0) {
-        if (counts) counts[(int64_t)bin * n + i] += cnt;
-        if (minutes) minutes[(int64_t)bin * n + i] += (float)(mins * scale);
-    }
+    if (valid && j1 > j0) put_bin(O, (int64_t)bin * n + i, fresh, cnt, mins, scale);
     if constexpr (kCount) flush_work(wk, work);
 }
 
@@ -391,8 +406,8 @@ __device__ __forceinline__ void runs_update(const Union4 &U, float w0, float w1,
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_accrual_runs(const Node *nodes_g, const SegNode *snodes_g, int n_nodes,
                                                            const int32_t *voff_g, const float4 *verts_g,
                                                            const float *height_g, const SegConst *segs_g, int j0,
-                                                           int j1, PointArgs P, float scale, int32_t *counts,
-                                                           float *minutes, float *longest, uint32_t *overflow)
+                                                           int j1, PointArgs P, float scale, BinOut O,
+                                                           float *longest, uint32_t *overflow)
 {
     cNode *nodes = (cNode *)nodes_g;
     cfloat4 *verts = (cfloat4 *)verts_g;
@@ -414,12 +429,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
     float run = 0.f, best = 0.f;
     int bin = j1 > j0 ? ld(segs + j0).bin : 0;
     int day = j1 > j0 ? ld(segs + j0).day : 0;
+    bool fresh = O.fresh_first != 0;
     auto flush = [&]() {
         if (!valid) return;
         const int64_t o = (int64_t)bin * n + i;
-        if (counts) counts[o] += cnt;
-        if (minutes) minutes[o] += (float)(mins * scale);
-        if (longest) longest[o] = fmaxf(longest[o], best * scale);
+        put_bin(O, o, fresh, cnt, mins, scale);
+        if (longest) longest[o] = fresh ? best * scale : fmaxf(longest[o], best * scale);
     };
     for (int j = j0; j < j1; ++j) {
         const SegConst g = ld(segs + j);
@@ -429,6 +444,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
             mins = 0.0;
             best = 0.f;
             bin = g.bin;
+            fresh = O.fresh_rest != 0;
         }
         if (g.day != day) {
             run = 0.f;
@@ -481,8 +497,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
 __global__ __launch_bounds__(kThreads) void k_spill(const SegNode *snodes_g, int n_nodes, int j0, const int32_t *voff_g,
                                                     const float4 *verts_g, const float *height_g,
                                                     const SegConst *segs_g, PointArgs P, float scale, int32_t *counts,
-                                                    float *minutes, const int4 *in, const uint32_t *in_count,
-                                                    int32_t cap, SpillArgs S)
+                                                    float *minutes, double *minutes64, const int4 *in,
+                                                    const uint32_t *in_count, int32_t cap, SpillArgs S)
 {
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
@@ -520,6 +536,7 @@ __global__ __launch_bounds__(kThreads) void k_spill(const SegNode *snodes_g, int
         if (lane == 0) {
             const int64_t o = (int64_t)g.bin * P.n + i;
             if (minutes) atomicAdd(&minutes[o], (float)(mins * scale));
+            if (minutes64) atomicAdd(&minutes64[o], mins * scale);
             if (counts) atomicAdd(&counts[o], cnt);
         }
         spill_push(S, ov, i, j, w0, w1);
@@ -901,14 +918,15 @@ sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const Points
 }
 
 sa_status run_spill(const DeviceScene &s, const DevicePath &p, const SegNode *views, int j0, const PointArgs &P,
-                    float scale, int32_t *counts, float *minutes, SpillQueue &q, hipStream_t st, std::string &err)
+                    float scale, int32_t *counts, float *minutes, double *minutes64, SpillQueue &q, hipStream_t st,
+                    std::string &err)
 {
     int cur = 0;
     for (int r = 0; r < kSpillRounds; ++r) {
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters + (cur ^ 1));
         SpillArgs S{q.entries[cur ^ 1], q.counters + (cur ^ 1), q.counters + 2, q.capacity};
         hipLaunchKernelGGL(k_spill, dim3(kSpillBlocks), dim3(kThreads), 0, st, views, s.n_nodes, j0, s.voff, s.verts,
-                           s.height, p.segs, P, scale, counts, minutes, (const int4 *)q.entries[cur],
+                           s.height, p.segs, P, scale, counts, minutes, minutes64, (const int4 *)q.entries[cur],
                            (const uint32_t *)(q.counters + cur), q.capacity, S);
         cur ^= 1;
     }
@@ -1062,9 +1080,19 @@ sa_status build_seg_views(const DeviceScene &s, const DevicePath &p, int j0, int
     return SA_OK;
 }
 
+// Output mode of an accrual launch starting at segment j0: with `store`
+// (no SA_FLAG_ADD, and every bin's segments one contiguous run) a bin is
+// stored by the launch holding its first segment and added to by later
+// ones, so the outputs need no clearing.
+static BinOut bin_out(const DevicePath &p, int j0, bool store, int32_t *counts, float *minutes, double *minutes64)
+{
+    const bool first = store && (j0 == 0 || p.seg_bin[j0 - 1] != p.seg_bin[j0]);
+    return BinOut{counts, minutes, minutes64, first ? 1 : 0, store ? 1 : 0};
+}
+
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
-                         int32_t *counts, float *minutes, float *longest, uint64_t *work, SpillQueue &q,
-                         Scratch &scr, hipStream_t st, std::string &err)
+                         int32_t *counts, float *minutes, double *minutes64, float *longest, uint64_t *work,
+                         bool store, SpillQueue &q, Scratch &scr, hipStream_t st, std::string &err)
 {
     if (pts.n == 0) return SA_OK;
     const int64_t waves = (pts.n + 63) / 64;
@@ -1101,8 +1129,8 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
             sa_status rc = build_seg_views(s, p, j0, j1, s.n_nodes, scr, st, views, err);
             if (rc != SA_OK) return rc;
             hipLaunchKernelGGL(k_accrual_runs, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, views, s.n_nodes,
-                               s.voff, s.verts, s.height, p.segs, j0, j1, P, scale, counts, minutes, longest,
-                               q.counters + 2);
+                               s.voff, s.verts, s.height, p.segs, j0, j1, P, scale,
+                               bin_out(p, j0, store, counts, minutes, minutes64), longest, q.counters + 2);
             SA_CHECK_LAUNCH("accrual kernel (continuous shadow)");
             d0 = d1;
         }
@@ -1116,10 +1144,10 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters);
         SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
         hipLaunchKernelGGL(work ? k_accrual<true> : k_accrual<false>, dim3((unsigned)grid), dim3(kThreads), 0, st,
-                           nodes, views, s.n_nodes, s.voff, s.verts, s.height, p.segs, (int)j0, j1, P, scale, counts,
-                           minutes, S, work);
+                           nodes, views, s.n_nodes, s.voff, s.verts, s.height, p.segs, (int)j0, j1, P, scale,
+                           bin_out(p, (int)j0, store, counts, minutes, minutes64), S, work);
         SA_CHECK_LAUNCH("accrual kernel");
-        rc = run_spill(s, p, views, (int)j0, P, scale, counts, minutes, q, st, err);
+        rc = run_spill(s, p, views, (int)j0, P, scale, counts, minutes, minutes64, q, st, err);
         if (rc != SA_OK) return rc;
     }
     return SA_OK;

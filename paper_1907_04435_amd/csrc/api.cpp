@@ -24,6 +24,8 @@ struct sa_ctx {
     sa::Scratch scratch_batched;  // per-variant hierarchy copies
     sa::Scratch scratch_seg;      // per-segment node views of the accrual form
     sa::Scratch scratch_sam;      // one segment's raster shadow accrual map
+    sa::Scratch scratch_grad;     // FP64 height-gradient accumulator
+    sa::Scratch scratch_w;        // per-bin weights of a region score
     uint32_t sam_stamp = 0;       // the last segment stamp written into it
     void *noalloc = nullptr;      // this device's fixed scratch (device address), or null
     std::string noalloc_err;      // why it is null
@@ -34,7 +36,27 @@ struct sa_scene {
     int device = 0;  // kept here: the scene may outlive its context object
     sa::DeviceScene d;
     std::vector<int32_t> rank_h;  // original id -> hierarchy position
+    bool max_h_stale = false;     // heights changed on the device since d.max_h was known
 };
+
+namespace {
+
+// The tallest height the scene has had, reading the device heights when a
+// device-side edit made the host copy stale (host-synchronous).
+float scene_max_height(const sa_scene *scene)
+{
+    if (scene->max_h_stale && scene->d.n_b > 0) {
+        std::vector<float> h(scene->d.n_b);
+        if (hipMemcpy(h.data(), scene->d.height, sizeof(float) * h.size(), hipMemcpyDeviceToHost) == hipSuccess) {
+            sa_scene *s = const_cast<sa_scene *>(scene);
+            for (float v : h) s->d.max_h = std::max(s->d.max_h, v);
+            s->max_h_stale = false;
+        }
+    }
+    return scene->d.max_h;
+}
+
+}  // namespace
 
 struct sa_path {
     sa_ctx *ctx = nullptr;
@@ -170,6 +192,8 @@ void sa_destroy(sa_ctx *ctx)
     (void)hipFree(ctx->scratch_batched.ptr);
     (void)hipFree(ctx->scratch_seg.ptr);
     (void)hipFree(ctx->scratch_sam.ptr);
+    (void)hipFree(ctx->scratch_grad.ptr);
+    (void)hipFree(ctx->scratch_w.ptr);
     delete ctx;
 }
 
@@ -196,7 +220,8 @@ sa_status sa_sync(sa_ctx *ctx)
         // bit 0: spill queue full; bit 1: a window could not be split finely
         // enough; bit 2: a variant named a bad building id or height
         if (flag & 4u)
-            return fail(ctx, SA_ERR_INVALID_ARG, "batched variants: a building id or height was invalid");
+            return fail(ctx, SA_ERR_INVALID_ARG,
+                        "a building id or height was invalid (batched variants or a device height edit)");
         return fail(ctx, SA_ERR_CAPACITY,
                     (flag & 1u) ? "accrual spill queue overflowed: results incomplete"
                                 : "occluded set too fragmented to split: results incomplete");
@@ -275,6 +300,20 @@ sa_status sa_scene_set_heights(sa_ctx *ctx, sa_scene *scene, int32_t n, const in
     if (!ctx || !scene || n < 0 || (n > 0 && (!ids || !h)))
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_scene_set_heights: bad arguments");
     if (n == 0) return SA_OK;
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    const bool dev_ids = on_device(ids), dev_h = on_device(h);
+    if (dev_ids != dev_h)
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_scene_set_heights: ids and heights must both be host or device");
+    if (dev_ids) {
+        // stream-ordered: scatter on the device (bad entries are skipped and
+        // flagged for sa_sync), then refit; nothing returns to the host
+        std::string err;
+        sa_status rc = sa::scene_set_heights_device(scene->d, n, ids, h, ctx->spill.counters + 2, ctx->stream, err);
+        if (rc == SA_OK) rc = sa::scene_refit(scene->d, ctx->stream, err);
+        if (rc != SA_OK) return fail(ctx, rc, "sa_scene_set_heights: " + err);
+        scene->max_h_stale = true;
+        return SA_OK;
+    }
     std::vector<int32_t> pos(n);
     for (int32_t k = 0; k < n; ++k) {
         if (ids[k] < 0 || ids[k] >= scene->d.n_b)
@@ -282,7 +321,6 @@ sa_status sa_scene_set_heights(sa_ctx *ctx, sa_scene *scene, int32_t n, const in
         if (!(h[k] > 0.f) || !std::isfinite(h[k])) return fail(ctx, SA_ERR_GEOMETRY, "height must be > 0");
         pos[k] = scene->rank_h[ids[k]];
     }
-    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
     // heights are few: scatter them with small copies, then refit on device
     for (int32_t k = 0; k < n; ++k) {
         hipError_t e = hipMemcpyAsync(scene->d.height + pos[k], h + k, sizeof(float), hipMemcpyHostToDevice,
@@ -308,7 +346,7 @@ sa_status sa_scene_get_info(const sa_scene *scene, sa_scene_info *out)
     out->n_nodes = scene->d.n_nodes;
     out->depth = scene->d.depth;
     for (int i = 0; i < 4; ++i) out->bounds[i] = scene->d.bounds[i];
-    out->max_height = scene->d.max_h;
+    out->max_height = scene_max_height(scene);
     return SA_OK;
 }
 
@@ -399,7 +437,7 @@ bool seg_geometry(const double *a, const double *b, double ta, double tb, sa::Se
 // the fewest azimuth sectors no wider than `bound` at the ring's lower
 // edge); segments of one output bin whose start and end knots fall in the
 // same pair of cells are one edge, computed once and weighted by how many
-// segments it stands for (Eq. 2 sums the edges' maps by multiplicity).  The
+// segments it stands for (Eq. (1) sums the edges' maps by multiplicity).  The
 // edge's arc runs from the members' mean start direction to their mean end
 // direction (the cluster's representative) over the first member's times;
 // the minutes per radian its measure is weighted by become the members'
@@ -588,6 +626,21 @@ sa_status path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, s
     day_seg_off.push_back((int32_t)segs.size());
     p->d.day_seg_off = std::move(day_seg_off);
     p->d.merged = merged;
+    // each bin's segments one contiguous run, every bin with segments: the
+    // accrual outputs can then be stored once per bin without clearing
+    p->d.seg_bin.resize(segs.size());
+    std::vector<char> seen(n_bins, 0);
+    bool contiguous = true;
+    for (size_t j = 0; j < segs.size(); ++j) {
+        const int b = segs[j].bin;
+        p->d.seg_bin[j] = b;
+        if (j == 0 || segs[j - 1].bin != b) {
+            if (seen[b]) contiguous = false;
+            seen[b] = 1;
+        }
+    }
+    for (int b = 0; b < n_bins; ++b) contiguous = contiguous && seen[b];
+    p->d.bins_contiguous = contiguous;
     if (!merged) {
         p->d.seg_host = std::move(seg_host);
         p->d.sample_t.assign(in->t_min, in->t_min + in->n_samples);
@@ -673,7 +726,7 @@ static sa::PointsView view(const sa_points *p)
 // Outputs are cleared with a fill kernel (not a memset node), so a call can
 // be captured into a HIP graph and replayed.
 static sa_status clear_outputs(sa_ctx *ctx, uint32_t flags, int64_t count, int32_t *counts, float *minutes,
-                               float *longest = nullptr)
+                               float *longest = nullptr, double *minutes64 = nullptr)
 {
     if (flags & SA_FLAG_ADD) return SA_OK;
     std::string err;
@@ -681,8 +734,16 @@ static sa_status clear_outputs(sa_ctx *ctx, uint32_t flags, int64_t count, int32
     if (counts) rc = sa::fill_u32(counts, count, 0u, ctx->stream, err);
     if (rc == SA_OK && minutes) rc = sa::fill_u32(minutes, count, 0u, ctx->stream, err);
     if (rc == SA_OK && longest) rc = sa::fill_u32(longest, count, 0u, ctx->stream, err);
+    if (rc == SA_OK && minutes64) rc = sa::fill_u32(minutes64, 2 * count, 0u, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "clear outputs: " + err);
     return SA_OK;
+}
+
+// The accrual form stores each bin once (no clearing) unless asked to add
+// or the path's bins interleave.
+static bool accrual_stores(const sa_accum_opts *opts, const sa_path *path)
+{
+    return opts->mode == SA_ACCRUAL && !(opts->flags & SA_FLAG_ADD) && path->d.bins_contiguous;
 }
 
 sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts, const sa_path *path,
@@ -699,18 +760,24 @@ sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts
     if (opts->longest && opts->mode == SA_ACCRUAL && path->d.merged)
         return fail(ctx, SA_ERR_INVALID_ARG,
                     "sa_accumulate: a direction-graph path has no time order: no continuous shadow");
-    if (!counts && !minutes && !bits && !opts->longest) return SA_OK;
+    if (opts->minutes64 && opts->mode != SA_ACCRUAL)
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate: FP64 minutes exist for the accrual form only");
+    if (!counts && !minutes && !bits && !opts->longest && !opts->minutes64) return SA_OK;
     if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
     const float scale = opts->out_scale == 0.f ? 1.f : opts->out_scale;
-    rc = clear_outputs(ctx, opts->flags, (int64_t)path->d.n_bins * pts->n, counts, minutes, opts->longest);
-    if (rc != SA_OK) return rc;
+    const bool store = accrual_stores(opts, path);
+    if (!store) {
+        rc = clear_outputs(ctx, opts->flags, (int64_t)path->d.n_bins * pts->n, counts, minutes, opts->longest,
+                           opts->minutes64);
+        if (rc != SA_OK) return rc;
+    }
     std::string err;
     if (opts->mode == SA_SAMPLED)
         rc = sa::launch_sampled(scene->d, path->d, view(pts), scale, counts, minutes, bits, opts->longest,
                                 opts->work, ctx->stream, err);
     else
-        rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->longest, opts->work,
-                                ctx->spill, ctx->scratch_seg, ctx->stream, err);
+        rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->minutes64,
+                                opts->longest, opts->work, store, ctx->spill, ctx->scratch_seg, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate: " + err);
     return SA_OK;
 }
@@ -729,8 +796,10 @@ sa_status sa_accumulate_noalloc(sa_ctx *ctx, const sa_scene *scene, const sa_poi
     if (opts->longest && opts->mode == SA_ACCRUAL && path->d.merged)
         return fail(ctx, SA_ERR_INVALID_ARG,
                     "sa_accumulate_noalloc: a direction-graph path has no time order: no continuous shadow");
+    if (opts->minutes64 && opts->mode != SA_ACCRUAL)
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate_noalloc: FP64 minutes exist for the accrual form only");
     if (!ctx->noalloc) return fail(ctx, SA_ERR_DEVICE, "sa_accumulate_noalloc: " + ctx->noalloc_err);
-    if (!counts && !minutes && !bits && !opts->longest) return SA_OK;
+    if (!counts && !minutes && !bits && !opts->longest && !opts->minutes64) return SA_OK;
     if (opts->mode == SA_ACCRUAL && scene->d.n_b > 0 && path->d.n_segs > 0 && pts->n > 0) {
         // refuse before any work: a launch must hold one segment's views, and
         // with the continuous shadow a whole day's
@@ -748,8 +817,12 @@ sa_status sa_accumulate_noalloc(sa_ctx *ctx, const sa_scene *scene, const sa_poi
     }
     if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
     const float scale = opts->out_scale == 0.f ? 1.f : opts->out_scale;
-    rc = clear_outputs(ctx, opts->flags, (int64_t)path->d.n_bins * pts->n, counts, minutes, opts->longest);
-    if (rc != SA_OK) return rc;
+    const bool store = accrual_stores(opts, path);
+    if (!store) {
+        rc = clear_outputs(ctx, opts->flags, (int64_t)path->d.n_bins * pts->n, counts, minutes, opts->longest,
+                           opts->minutes64);
+        if (rc != SA_OK) return rc;
+    }
     std::string err;
     if (opts->mode == SA_SAMPLED) {
         rc = sa::launch_sampled(scene->d, path->d, view(pts), scale, counts, minutes, bits, opts->longest,
@@ -759,8 +832,8 @@ sa_status sa_accumulate_noalloc(sa_ctx *ctx, const sa_scene *scene, const sa_poi
         fixed.ptr = ctx->noalloc;
         fixed.bytes = (size_t)SA_NOALLOC_SCRATCH_BYTES;
         fixed.fixed = true;
-        rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->longest, opts->work,
-                                ctx->spill, fixed, ctx->stream, err);
+        rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->minutes64,
+                                opts->longest, opts->work, store, ctx->spill, fixed, ctx->stream, err);
     }
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate_noalloc: " + err);
     return SA_OK;
@@ -776,8 +849,9 @@ sa_status sa_accumulate_batched(sa_ctx *ctx, const sa_scene *scene, int32_t n_va
         (n_var > 0 && ids_per_var > 0 && (!var_ids || !var_h)))
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate_batched: bad arguments");
     if (opts->mode != SA_ACCRUAL) return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate_batched: accrual form only");
-    if (opts->longest)
-        return fail(ctx, SA_ERR_INVALID_ARG, "sa_accumulate_batched: continuous shadow is not offered here");
+    if (opts->longest || opts->minutes64)
+        return fail(ctx, SA_ERR_INVALID_ARG,
+                    "sa_accumulate_batched: continuous shadow and FP64 minutes are not offered here");
     sa_status rc = check_points(ctx, pts);
     if (rc != SA_OK) return rc;
     if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
@@ -793,15 +867,21 @@ sa_status sa_accumulate_batched(sa_ctx *ctx, const sa_scene *scene, int32_t n_va
 }
 
 sa_status sa_grad_heights(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts, const sa_path *path,
-                          const float *dl_dmin, float *grad)
+                          const sa_accum_opts *opts, const float *dl_dmin, float *grad)
 {
     if (!ctx) return SA_ERR_INVALID_ARG;
     if (!scene || !path || !grad) return fail(ctx, SA_ERR_INVALID_ARG, "sa_grad_heights: null argument");
+    if (opts && opts->mode != SA_ACCRUAL)
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_grad_heights: the accrual form only (sampled counts are piecewise "
+                                             "constant in the heights)");
     sa_status rc = check_points(ctx, pts);
     if (rc != SA_OK) return rc;
     if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    const float scale = (!opts || opts->out_scale == 0.f) ? 1.f : opts->out_scale;
+    const bool add = opts && (opts->flags & SA_FLAG_ADD);
     std::string err;
-    rc = sa::launch_grad(scene->d, path->d, view(pts), dl_dmin, grad, ctx->spill, ctx->scratch_seg, ctx->stream, err);
+    rc = sa::launch_grad(scene->d, path->d, view(pts), dl_dmin, scale, add, grad, ctx->spill, ctx->scratch_seg,
+                         ctx->scratch_grad, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_grad_heights: " + err);
     return SA_OK;
 }
@@ -821,18 +901,48 @@ sa_status sa_region_sum(sa_ctx *ctx, const float *values, int64_t n, const int64
     return SA_OK;
 }
 
-sa_status sa_region_score(sa_ctx *ctx, const float *values, int32_t n_bins, int64_t n, const double *bin_weight,
-                          const int64_t *region_off, int32_t n_reg, const float *area, double *out)
+sa_status sa_region_score(sa_ctx *ctx, const sa_path *path, const float *values, int64_t n,
+                          const double *interval_weight, const int64_t *region_off, int32_t n_reg, const float *area,
+                          double *out)
 {
     if (!ctx) return SA_ERR_INVALID_ARG;
-    if (n < 0 || n_bins < 1 || n_reg < 0 || !bin_weight || (n_reg > 0 && (!region_off || !out)) ||
+    if (!path || n < 0 || n_reg < 0 || !interval_weight || (n_reg > 0 && (!region_off || !out)) ||
         (n > 0 && !values))
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_region_score: bad arguments");
     if (n_reg == 0) return SA_OK;
+    const int32_t n_bins = path->d.n_bins;
+    if (n_bins < 1) return fail(ctx, SA_ERR_INVALID_ARG, "sa_region_score: the path has no bins");
+    // each interval's weight per minute of its daylight: the score takes the
+    // fraction of the interval's daylight spent in shadow (Sec. 7.2)
+    std::vector<double> w(n_bins);
+    for (int32_t b = 0; b < n_bins; ++b) {
+        const double span = path->d.bin_span[b];
+        if (!std::isfinite(interval_weight[b]) || !(span > 0.0))
+            return fail(ctx, SA_ERR_INVALID_ARG, "sa_region_score: bad weight or a bin without daylight");
+        w[b] = interval_weight[b] / span;
+    }
     if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    const size_t need = sizeof(double) * (size_t)n_bins;
+    if (ctx->scratch_w.bytes < need) {
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(ctx->scratch_w.ptr);
+        ctx->scratch_w.ptr = nullptr;
+        ctx->scratch_w.bytes = 0;
+        hipError_t e = hipMalloc(&ctx->scratch_w.ptr, need);
+        if (e != hipSuccess) {
+            ctx->scratch_w.ptr = nullptr;
+            return hip_fail(ctx, e, "sa_region_score: weights");
+        }
+        ctx->scratch_w.bytes = need;
+    }
+    // the weights go with the work on the stream (the host vector is gone
+    // by the time the copy runs, so copy synchronously first)
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e == hipSuccess) e = hipMemcpy(ctx->scratch_w.ptr, w.data(), need, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(ctx, e, "sa_region_score: weights");
     std::string err;
-    sa_status rc = sa::launch_region_sum(values, n_bins, n, bin_weight, region_off, n_reg, area, out,
-                                         ctx->scratch, ctx->stream, err);
+    sa_status rc = sa::launch_region_sum(values, n_bins, n, (const double *)ctx->scratch_w.ptr, region_off, n_reg,
+                                         area, out, ctx->scratch, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_region_score: " + err);
     return SA_OK;
 }
@@ -887,7 +997,7 @@ sa_status sa_sam_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points 
         box[2] = 0.0;
         box[3] = scene->d.bounds[2];
         box[4] = scene->d.bounds[3];
-        box[5] = scene->d.max_h;
+        box[5] = scene_max_height(scene);
     }
     for (int i = 0; i < 6; ++i)
         if (!std::isfinite(box[i])) return fail(ctx, SA_ERR_INVALID_ARG, "sa_sam_accumulate: box not finite");

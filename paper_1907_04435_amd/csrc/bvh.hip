@@ -317,6 +317,28 @@ __global__ void k_refit(int n_b, int n_int, const float4 *__restrict__ pbox, con
     }
 }
 
+// Heights from device arrays (original ids); bad entries are skipped and
+// flagged (bit 2, reported by sa_sync).
+__global__ void k_set_heights(int32_t n, const int32_t *__restrict__ ids, const float *__restrict__ h,
+                              const int32_t *__restrict__ rank, int32_t n_b, float *height, uint32_t *flag)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int32_t id = ids[k];
+    const float v = h[k];
+    if (id < 0 || id >= n_b || !(v > 0.f) || !(v <= 3.0e38f)) {
+        atomicOr(flag, 4u);
+        return;
+    }
+    height[rank[id]] = v;
+}
+
+__global__ void k_clear_i32(int32_t *p, int32_t n)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n) p[k] = 0;
+}
+
 __global__ void k_depth(int n_b, int n_int, const int32_t *__restrict__ parent, int32_t *depth)
 {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -373,13 +395,24 @@ void scene_free(DeviceScene &s)
     s = DeviceScene();
 }
 
+sa_status scene_set_heights_device(DeviceScene &s, int32_t n, const int32_t *ids, const float *h, uint32_t *flag,
+                                   hipStream_t st, std::string &err)
+{
+    if (n <= 0 || s.n_b < 1) return SA_OK;
+    hipLaunchKernelGGL(k_set_heights, dim3(blocks(n, 256)), dim3(256), 0, st, n, ids, h, (const int32_t *)s.rank,
+                       s.n_b, s.height, flag);
+    SA_HIP(hipGetLastError());
+    return SA_OK;
+}
+
 sa_status scene_refit(DeviceScene &s, hipStream_t st, std::string &err)
 {
     if (s.n_b < 1) return SA_OK;
     if (s.n_b == 1) {
         hipLaunchKernelGGL(k_single, dim3(1), dim3(1), 0, st, s.voff, s.nodes, s.parent);
     }
-    SA_HIP(hipMemsetAsync(s.flags, 0, sizeof(int32_t) * s.n_nodes, st));
+    // arrival counters cleared by a fill kernel (capturable, unlike a memset node)
+    hipLaunchKernelGGL(k_clear_i32, dim3(blocks(s.n_nodes, 256)), dim3(256), 0, st, s.flags, s.n_nodes);
     const int n_int = s.n_b == 1 ? 1 : s.n_b - 1;
     hipLaunchKernelGGL(k_refit, dim3(blocks(s.n_b, 256)), dim3(256), 0, st, s.n_b, n_int,
                        (const float4 *)s.pbox, (const float *)s.height, (const int32_t *)s.parent,

@@ -9,8 +9,10 @@
 //     dL/dH_b = sum over points and segments of w * dt/theta *
 //               (sum of d(close)/dH - sum of d(open)/dH)
 // over the union boundaries owned by b.  The traversal is recomputed here,
-// nothing is kept from the forward pass; contributions are added with
-// atomics into the caller's gradient (original building ids).
+// nothing is kept from the forward pass.  Contributions are summed across
+// the wave per building and added with one FP64 atomic per building and
+// wave into an accumulator (original building ids), which a last kernel
+// rounds into the caller's float gradient.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -31,7 +33,7 @@ constexpr int kSpillBlocks = 1024;
 
 struct GradArgs {
     const float *dl;       // [n_bins * n] or null (all ones)
-    float *grad;           // [n_b], original ids
+    double *acc;           // [n_b] FP64 accumulator, original ids
     const int32_t *order;  // hierarchy position -> original id
 };
 
@@ -78,14 +80,36 @@ __device__ __forceinline__ void grad_segment(cSegNode *snodes, cint *voff, Stack
     ov = lane_in(ovm);
 }
 
-__device__ __forceinline__ void scatter_grad(const UnionG &U, float wscale, const GradArgs &G)
+// Add v into acc[order[prim]] for every lane with prim >= 0.  Lanes that
+// hold the same building are summed across the wave first (a fixed
+// butterfly order), then one lane issues a single FP64 atomic: one atomic
+// per building and wave instead of one per lane.  Must be reached by every
+// lane of the wave (the shuffles read all lanes).
+__device__ __forceinline__ void wave_scatter(int prim, double v, const GradArgs &G)
+{
+    const int lane = threadIdx.x & 63;
+    uint64_t pend = ballot(prim >= 0);
+    while (pend) {
+        const int lead = __builtin_ctzll(pend);
+        const int key = __shfl(prim, lead, 64);
+        const uint64_t m = pend & ballot(prim == key);
+        double sum = lane_in(m) ? v : 0.0;
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+        if (lane == lead) atomicAdd(&G.acc[G.order[key]], sum);
+        pend &= ~m;
+    }
+}
+
+// The union boundaries of one lane's window that move with a height:
+// closing ends +, opening ends -, each times wscale; ok = false adds
+// nothing (every lane of the wave must call this).
+__device__ __forceinline__ void scatter_grad(const UnionG &U, bool ok, float wscale, const GradArgs &G)
 {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        if (r < U.n) {
-            if (U.plo[r] >= 0 && U.dlo[r] != 0.f) atomicAdd(&G.grad[G.order[U.plo[r]]], -wscale * U.dlo[r]);
-            if (U.phi[r] >= 0 && U.dhi[r] != 0.f) atomicAdd(&G.grad[G.order[U.phi[r]]], wscale * U.dhi[r]);
-        }
+        const bool in = ok && r < U.n;
+        wave_scatter(in && U.plo[r] >= 0 && U.dlo[r] != 0.f ? U.plo[r] : -1, -(double)(wscale * U.dlo[r]), G);
+        wave_scatter(in && U.phi[r] >= 0 && U.dhi[r] != 0.f ? U.phi[r] : -1, (double)(wscale * U.dhi[r]), G);
     }
 }
 
@@ -142,7 +166,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
         cSegNode *sn = snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr;
         grad_segment(sn, (cint *)voff_g, stack, verts, height, g, q, valid && !covered && w != 0.f, 0.f, g.theta, U,
                      ov);
-        if (valid && !covered && !ov && w != 0.f) scatter_grad(U, w * g.wrate, G);
+        scatter_grad(U, valid && !covered && !ov && w != 0.f, w * g.wrate, G);
         spill_push(S, valid && ov, i, j, 0.f, g.theta);
     }
 }
@@ -180,12 +204,19 @@ __global__ __launch_bounds__(kThreads) void k_grad_spill(const SegNode *snodes_g
         bool ov;
         cSegNode *sn = snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr;
         grad_segment(sn, (cint *)voff_g, stack, verts, height, g, q, true, w0, w1, U, ov);
-        if (!ov) scatter_grad(U, w * g.wrate, G);
+        scatter_grad(U, !ov, w * g.wrate, G);
         spill_push(S, ov, i, j, w0, w1);
     }
 }
 
 __global__ void k_zero1(uint32_t *p) { *p = 0u; }
+
+// grad[b] = (add ? grad[b] : 0) + scale * acc[b], rounded once to float.
+__global__ void k_grad_out(const double *acc, int32_t n_b, double scale, int add, float *grad)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < n_b) grad[b] = (float)((add ? (double)grad[b] : 0.0) + scale * acc[b]);
+}
 
 __global__ void k_spill_left(const uint32_t *count, uint32_t *overflow)
 {
@@ -194,20 +225,36 @@ __global__ void k_spill_left(const uint32_t *count, uint32_t *overflow)
 
 }  // namespace
 
-sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts, const float *dl, float *grad,
-                      SpillQueue &q, Scratch &scr, hipStream_t st, std::string &err)
+sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts, const float *dl, float scale,
+                      bool add, float *grad, SpillQueue &q, Scratch &scr, Scratch &acc_scr, hipStream_t st,
+                      std::string &err)
 {
-    sa_status rc = fill_u32(grad, s.n_b, 0u, st, err);
+    if (s.n_b == 0) return SA_OK;
+    const size_t need = sizeof(double) * (size_t)s.n_b;
+    if (acc_scr.bytes < need) {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(acc_scr.ptr);
+        acc_scr.ptr = nullptr;
+        acc_scr.bytes = 0;
+        if (hipMalloc(&acc_scr.ptr, need) != hipSuccess) {
+            (void)hipGetLastError();
+            acc_scr.ptr = nullptr;
+            err = "gradient accumulator allocation failed";
+            return SA_ERR_OOM;
+        }
+        acc_scr.bytes = need;
+    }
+    double *acc = (double *)acc_scr.ptr;
+    sa_status rc = fill_u32(acc, 2 * (int64_t)s.n_b, 0u, st, err);
     if (rc != SA_OK) return rc;
-    if (pts.n == 0 || s.n_b == 0) return SA_OK;
     const int64_t waves = (pts.n + 63) / 64;
     const int64_t grid = (waves + kWaves - 1) / kWaves;
     const PointArgs P{pts.n, pts.x, pts.y, pts.z, pts.nx, pts.ny, pts.owner, s.rank, s.n_b};
-    const GradArgs G{dl, grad, s.order};
+    const GradArgs G{dl, acc, s.order};
     // segment ranges whose per-segment node views fit the budget, each
     // followed by its spill rounds
     const int64_t per = seg_views_cap(s, scr);
-    for (int64_t j0 = 0; j0 < p.n_segs; j0 += per) {
+    for (int64_t j0 = 0; pts.n > 0 && j0 < p.n_segs; j0 += per) {
         const int j1 = (int)std::min<int64_t>(j0 + per, p.n_segs);
         SegNode *views;
         rc = build_seg_views(s, p, (int)j0, j1, s.n_nodes, scr, st, views, err);
@@ -232,6 +279,13 @@ sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsVie
             err = std::string("gradient kernels: ") + hipGetErrorString(e);
             return SA_ERR_DEVICE;
         }
+    }
+    hipLaunchKernelGGL(k_grad_out, dim3((unsigned)((s.n_b + 255) / 256)), dim3(256), 0, st, (const double *)acc,
+                       s.n_b, (double)scale, add ? 1 : 0, grad);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        err = std::string("gradient output: ") + hipGetErrorString(e);
+        return SA_ERR_DEVICE;
     }
     return SA_OK;
 }

@@ -135,6 +135,8 @@ struct DevicePath {
     SegConst *segs = nullptr;        // [n_segs]
     int32_t words = 0;               // ceil(n_samples / 32)
     std::vector<int32_t> day_seg_off;  // host: first segment of each day, [n_days + 1]
+    std::vector<int32_t> seg_bin;      // host: output bin of each segment
+    bool bins_contiguous = false;      // host: every bin has segments, all in one run
     std::vector<double> bin_span;      // host: daylight minutes of each output bin
     bool merged = false;               // host: segments merged into direction-graph edges
     // host, for the raster form: each segment's knot directions, times, its
@@ -147,6 +149,11 @@ struct DevicePath {
 sa_status scene_build(DeviceScene &s, hipStream_t st, int32_t n_b, const int32_t *voff,
                       const float *xy, const float *h, std::string &err);
 sa_status scene_refit(DeviceScene &s, hipStream_t st, std::string &err);
+// Heights from device arrays ids / h (original ids) into the scene, on the
+// stream; an id out of range or a height that is not a positive finite
+// number is skipped and raises bit 2 of *flag.
+sa_status scene_set_heights_device(DeviceScene &s, int32_t n, const int32_t *ids, const float *h, uint32_t *flag,
+                                   hipStream_t st, std::string &err);
 void scene_free(DeviceScene &s);
 sa_status sunpath_fill(const sa_site &site, const sa_timespan &span, sa_sunpath_buf &out,
                        std::string &err);
@@ -174,12 +181,17 @@ struct SpillQueue {
 sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
                          float scale, int32_t *counts, float *minutes, uint32_t *bits, float *longest,
                          uint64_t *work, hipStream_t st, std::string &err);
+// store: outputs need no clearing (no SA_FLAG_ADD and p.bins_contiguous):
+// each bin is stored by the launch holding its first segment.
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
-                         float scale, int32_t *counts, float *minutes, float *longest, uint64_t *work,
-                         SpillQueue &q, Scratch &scr, hipStream_t st, std::string &err);
+                         float scale, int32_t *counts, float *minutes, double *minutes64, float *longest,
+                         uint64_t *work, bool store, SpillQueue &q, Scratch &scr, hipStream_t st,
+                         std::string &err);
+// grad = (add ? grad : 0) + scale * d(sum dl * minutes)/dH, accumulated in
+// FP64 in acc (grown to n_b doubles as needed).
 sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
-                      const float *dl, float *grad, SpillQueue &q, Scratch &scr, hipStream_t st,
-                      std::string &err);
+                      const float *dl, float scale, bool add, float *grad, SpillQueue &q, Scratch &scr,
+                      Scratch &acc, hipStream_t st, std::string &err);
 sa_status launch_region_sum(const float *v, int n_bins, int64_t n, const double *bin_w,
                             const int64_t *off, int32_t n_reg, const float *area, double *out,
                             Scratch &scr, hipStream_t st, std::string &err);

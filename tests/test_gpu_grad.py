@@ -113,15 +113,30 @@ def test_grad_c4_vs_fp64_central_differences(ctx):
 
 
 def test_grad_c4_vs_finite_differences(ctx):
-    """Full differentiation scene (200k park points): central differences
-    of the GPU forward on 64 random buildings with a gradient and 8
-    without.  The loss is piecewise smooth with kinks (a roof edge passing
-    another shadow's edge, grazing paths) inside +-0.5 m for many
-    buildings, so the 0.5 m quotient is not a derivative estimate there;
-    it converges to the adjoint as the step shrinks (the oracle shows the
-    same in FP64).  Asserted: zero-gradient buildings have zero quotients,
-    the error falls with the step, and at 0.02 m the median relative
-    difference is <= 2e-3."""
+    """Full differentiation scene (200k park points, 5,000 buildings, Mar
+    20, 1-minute knots): central differences with dh = 0.5 m on 64 random
+    buildings with a gradient and 8 without, from the forward's FP64
+    per-point minutes.
+
+    The loss is a sum over points of piecewise smooth functions of a
+    height; a point's function has a kink where a roof edge's crossing
+    meets a vertex or another occluder's interval end.  Over +-0.5 m some
+    points of every building kink, so the total's quotient is the mean of a
+    derivative that changes across the bracket (by ~2 %), not the
+    derivative at H.  Kinks are therefore separated per point: a point is
+    smooth over the bracket when its own central differences at 0.5, 0.25
+    and 0.125 m agree (within 2e-3 relative, or 1e-6 min/m) and its forward
+    and backward differences at 0.125 m agree within 5 % (central
+    differences cannot see a kink right at H: they average its two sides
+    at every step, while the adjoint gives the current side); the adjoint
+    is taken with dl_dmin = 1 on the smooth points and 0 elsewhere, and
+    must agree with the smooth points' summed quotient within 1e-3 relative
+    for every building that has smooth points (at least 48 of the 64).
+    Buildings whose every affected point kinks within the bracket, the
+    kinked points' share and their part of the total quotient are
+    reported.  As a whole-loss check, the quotient equals the adjoint
+    averaged over the bracket (midpoint rule, 32 heights): median relative
+    difference <= 5e-4.  Zero-gradient buildings give zero quotients."""
     import torch
     w = make_c4()
     path = sa.Path(ctx, sa.sunpath_for_span(w.span, 1.0))
@@ -129,39 +144,68 @@ def test_grad_c4_vs_finite_differences(ctx):
     dp = sa.DevicePoints.from_workload(w.points)
     g = torch.empty(w.scene.n_b, dtype=torch.float32, device="cuda")
     sa.sa_grad_heights(ctx, sc, dp, path, None, g)
-    mins = torch.empty((1, w.points.n), dtype=torch.float32, device="cuda")
-    off = torch.tensor([0, w.points.n], dtype=torch.int64, device="cuda")
-    tot = torch.empty(1, dtype=torch.float64, device="cuda")
-
-    def loss(b, h):
-        sc.set_heights(np.array([b], np.int32), np.array([h], np.float32))
-        sa.sa_accumulate(ctx, sc, dp, path, sa.SA_ACCRUAL, None, mins)
-        sa.sa_region_sum(ctx, mins[0], off, tot)
-        ctx.sync()
-        return float(tot.item())
     ctx.sync()
     gh = g.cpu().numpy().astype(np.float64)
+
+    def minutes(b, h):
+        sc.set_heights(np.array([b], np.int32), np.array([h], np.float32))
+        m = torch.empty((1, w.points.n), dtype=torch.float64, device="cuda")
+        sa.sa_accumulate(ctx, sc, dp, path, sa.SA_ACCRUAL, minutes64=m)
+        return m[0]
+
+    def adjoint(b, h, dl=None):
+        sc.set_heights(np.array([b], np.int32), np.array([h], np.float32))
+        sa.sa_grad_heights(ctx, sc, dp, path, dl, g)
+        return float(g[b].item())
+
     rng = np.random.default_rng(44)
     pos = np.flatnonzero(gh > 1e-3 * gh.max())
     zero = np.flatnonzero(gh == 0)
-    steps = (0.5, 0.1, 0.02)
-    rel = {dh: [] for dh in steps}
+    dh, nq = 0.5, 32
+    rows = []
     for b in list(rng.choice(pos, 64, replace=False)) + list(rng.choice(zero, 8, replace=False)):
         H = float(w.scene.height[b])
-        for dh in steps:
-            hp, hm = np.float32(H + dh), np.float32(H - dh)
-            fd = (loss(b, hp) - loss(b, hm)) / float(hp - hm)
-            if gh[b] == 0:
-                assert abs(fd) <= 1e-4 * gh.max()
-            else:
-                rel[dh].append(abs(fd - gh[b]) / abs(gh[b]))
-        loss(b, np.float32(H))
-    med = {dh: float(np.median(rel[dh])) for dh in steps}
-    within = {dh: float(np.mean(np.array(rel[dh]) <= 1e-3)) for dh in steps}
-    say(f"c4 adjoint vs FD median rel: {med}; p90 at 0.02: {np.quantile(rel[0.02], 0.9):.2e}; "
-        f"share within 1e-3: {within}")
-    assert med[0.02] <= 2e-3
-    assert med[0.02] < med[0.1] < med[0.5]
+        fd = {}
+        for step in (dh, dh / 2, dh / 4):
+            hp, hm = np.float32(H + step), np.float32(H - step)
+            fd[step] = (minutes(b, hp) - minutes(b, hm)) / float(hp - hm)
+        total = float(fd[dh].sum())
+        if gh[b] == 0:
+            minutes(b, np.float32(H))
+            assert abs(total) <= 1e-4 * gh.max(), (b, total)
+            continue
+        a, m2, m4 = fd[dh], fd[dh / 2], fd[dh / 4]
+        tol = lambda x, y, r: (x - y).abs() <= r * torch.maximum(x.abs(), y.abs()) + 1e-6
+        mid = minutes(b, np.float32(H))
+        hq, hr = np.float32(H + dh / 4), np.float32(H - dh / 4)
+        fwd = (minutes(b, hq) - mid) / float(hq - np.float32(H))
+        bwd = (mid - minutes(b, hr)) / float(np.float32(H) - hr)
+        smooth = tol(a, m2, 2e-3) & tol(a, m4, 2e-3) & tol(m2, m4, 2e-3) & tol(fwd, bwd, 5e-2)
+        fd_s = float((a * smooth).sum())
+        g_s = adjoint(b, np.float32(H), smooth.float().reshape(1, -1).contiguous())
+        hp, hm = np.float32(H + dh), np.float32(H - dh)
+        nodes = [np.float32(float(hm) + (float(hp) - float(hm)) * (k + 0.5) / nq) for k in range(nq)]
+        g_mean = float(np.mean([adjoint(b, h) for h in nodes]))
+        minutes(b, np.float32(H))
+        affected = int((a != 0).sum())
+        rows.append((b, gh[b], total, fd_s, g_s, g_mean, affected, int(((a != 0) & ~smooth).sum()),
+                     int(((a != 0) & smooth).sum())))
+    r = np.array(rows, dtype=np.float64)
+    has = r[:, 8] > 0                      # buildings with smooth affected points
+    rel_smooth = np.abs(r[has, 3] - r[has, 4]) / np.abs(r[has, 4])
+    rel_mean = np.abs(r[:, 2] - r[:, 5]) / np.abs(r[:, 2])
+    rel_at_h = np.abs(r[:, 2] - r[:, 1]) / np.abs(r[:, 1])
+    kink_pts = r[:, 7] / np.maximum(r[:, 6], 1)
+    kink_fd = np.abs(r[:, 2] - r[:, 3]) / np.abs(r[:, 2])
+    say(f"c4 dh=0.5 on {len(r)} buildings: {int(has.sum())} with smooth points, their FD vs adjoint: max rel "
+        f"{rel_smooth.max():.2e}, median {np.median(rel_smooth):.2e}, share within 1e-3 "
+        f"{np.mean(rel_smooth <= 1e-3):.0%}; {int((~has).sum())} with every affected point kinked; kinked "
+        f"points per building: median {np.median(kink_pts):.1%} of affected points, {np.median(kink_fd):.1%} "
+        f"of the quotient; whole loss: FD vs bracket-mean adjoint median {np.median(rel_mean):.2e} (max "
+        f"{rel_mean.max():.2e}), FD vs adjoint at H median {np.median(rel_at_h):.2e}")
+    assert has.sum() >= 48
+    assert np.all(rel_smooth <= 1e-3)
+    assert np.median(rel_mean) <= 5e-4
 
 
 def test_autograd_function(ctx, c1):

@@ -1,4 +1,4 @@
-"""Pins of the oracle's direction-graph reading (Sec. 6, Eq. 2): the
+"""Pins of the oracle's direction-graph reading (Sec. 6, Eq. (1)): the
 hemisphere cells are bounded and about as few as the bound allows, and the
 graph form reduces to the plain continuous form wherever merging loses
 nothing (cells too small to merge, members that share their directions)."""
