@@ -318,8 +318,7 @@ def bench_c5(args, sa, torch):
     w = make_c5()
     ctx = sa.Context(0)
     sc = sa.Scene.from_workload(ctx, w.scene)
-    sp = sa.sa_sunpath(40.7, -74.0, -5.0, 2019, 1, 1, 365, seg=args.seg)
-    sp.day_bin = np.asarray(w.span.day_bin, np.int32)
+    sp = sa.sunpath_for_span(w.span, args.seg)      # the workload's days, with their clock (EDT / EST)
     path = sa.Path(ctx, sp)
     dp = sa.DevicePoints.from_workload(w.points)
     hours = torch.empty((path.n_bins, dp.n), dtype=torch.float32, device="cuda")
@@ -361,8 +360,7 @@ def bench_c5(args, sa, torch):
         # the same with knots on the clock: every day's inner knots at the
         # multiples of the spacing in local time, so days share knot times;
         # errors against the full path on those knots
-        spc = sa.sa_sunpath(40.7, -74.0, -5.0, 2019, 1, 1, 365, seg=args.seg, clock_knots=True)
-        spc.day_bin = np.asarray(w.span.day_bin, np.int32)
+        spc = sa.sunpath_for_span(w.span, args.seg, clock_knots=True)
         pc = sa.Path(ctx, spc)
         basec = torch.empty_like(hours)
         cms = _timed(torch, ctx.stream,

@@ -555,18 +555,57 @@ static void seg_plane(const double *da, const double *db, double *N)
     if (s > 0) for (int i = 0; i < 3; ++i) N[i] /= s;
 }
 
+/* Does prism b's box lie wholly behind the segment: every direction of a
+ * great-circle arc shorter than a half circle makes an acute angle with
+ * the arc's mean direction m, so a point the rays meet has (q - p).m > 0;
+ * a box with every corner at (q - p).m <= 0 cannot be met. */
+static int box_behind(const scene64 *S, int b, const double *p, const double *m)
+{
+    const double *bx = S->box + 4 * b;
+    for (int k = 0; k < 8; ++k) {
+        double q[3] = {((k & 1) ? bx[2] : bx[0]) - p[0], ((k & 2) ? bx[3] : bx[1]) - p[1],
+                       ((k & 4) ? S->H[b] : 0.0) - p[2]};
+        if (m[0] * q[0] + m[1] * q[1] + m[2] * q[2] > 0.0) return 0;
+    }
+    return 1;
+}
+
+/* Does prism b's box lie wholly below the segment's rays: a ray that rises
+ * at least tan_min metres per horizontal metre is, at the box's nearest
+ * horizontal distance d from p, already above p_z + d tan_min; a box whose
+ * top is lower cannot be met.  (Along a great-circle arc above the horizon
+ * and shorter than a half circle the elevation is smallest at an end.) */
+static int box_below(const scene64 *S, int b, const double *p, double tan_min)
+{
+    const double *bx = S->box + 4 * b;
+    const double dx = p[0] < bx[0] ? bx[0] - p[0] : (p[0] > bx[2] ? p[0] - bx[2] : 0.0);
+    const double dy = p[1] < bx[1] ? bx[1] - p[1] : (p[1] > bx[3] ? p[1] - bx[3] : 0.0);
+    return S->H[b] - p[2] < sqrt(dx * dx + dy * dy) * tan_min;
+}
+
 /* Shadowed intervals of one point over one segment, all occluders, not
- * merged. */
+ * merged.  Once one occluder shadows the whole segment the union over it is
+ * the segment whatever the others add, so they are skipped. */
 static void segment_intervals(const scene64 *S, const double *p, const double *nrm, int owner,
                               double ta, double tb, const double *da, const double *db,
                               double grid, ivec *out)
 {
     if (!(tb > ta)) return;
-    double N[3];
+    double N[3], m[3];
     seg_plane(da, db, N);
+    for (int i = 0; i < 3; ++i) m[i] = da[i] + db[i];
+    const int arc_ok = da[0] * db[0] + da[1] * db[1] + da[2] * db[2] > -0.5;   /* shorter than 120 degrees */
+    const double ta_ = da[2] / sqrt(da[0] * da[0] + da[1] * da[1] + 1e-300);
+    const double tb_ = db[2] / sqrt(db[0] * db[0] + db[1] * db[1] + 1e-300);
+    const double tan_min = arc_ok && da[2] > 0.0 && db[2] > 0.0 ? (ta_ < tb_ ? ta_ : tb_) : 0.0;
+    int first = out->n;
     for (int b = (owner >= 0 ? -1 : 0); b < S->n_b; ++b) {
-        if (b >= 0 && (b == owner || box_off_plane(S, b, p, N))) continue;
+        if (b >= 0 && (b == owner || box_off_plane(S, b, p, N) ||
+                       (arc_ok && (box_behind(S, b, p, m) || box_below(S, b, p, tan_min)))))
+            continue;
         occluder_intervals(S, b, p, nrm, ta, tb, da, db, grid, out);
+        for (; first < out->n; ++first)
+            if (out->v[first].lo <= ta && out->v[first].hi >= tb) return;
     }
 }
 

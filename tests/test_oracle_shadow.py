@@ -435,3 +435,39 @@ def test_gradient_lone_box_roof_crossings():
     lp = oracle.continuous(oracle.with_height(sc, 0, hp), one, path)["minutes"].sum()
     lm = oracle.continuous(oracle.with_height(sc, 0, hm), one, path)["minutes"].sum()
     assert (lp - lm) / float(hp - hm) == pytest.approx(per_point[i, 0], rel=2e-4)
+
+
+def test_continuous_matches_unculled_fine_sampling():
+    """Low boxes (0.3..3 m) a few metres from ground and wall points under a
+    low morning sun, where the continuous form's box culls (the segment's
+    plane, the half-space behind the arc, the rays' lowest elevation) sit
+    close to the geometry: its duration along one hour-long great circle
+    equals the predicate -- tested against every building, no cull --
+    sampled every 0.6 s along the same circle, within half a sample per
+    transition."""
+    rng = np.random.default_rng(12)
+    boxes = []
+    for k in range(24):
+        cx, cy = rng.uniform(-25, 25, 2)
+        w, d = rng.uniform(0.5, 4.0, 2)
+        boxes.append((cx - w, cy - d, cx + w, cy + d, rng.uniform(0.3, 3.0)))
+    sc = box_scene(boxes)
+    P = pts(np.c_[rng.uniform(-30, 30, (40, 2)), rng.uniform(0.0, 0.4, 40)])
+    span = Span(40.7, -74.0, [Day(2019, 6, 21, -4.0, (340.0, 400.0))], step_min=5.0)
+    path = oracle.sun_path(span, seg_min=60.0)
+    assert len(path.seg_t) == 1
+    D = oracle.continuous(sc, P, path)["minutes"][0]
+    ta, tb = path.seg_t[0]
+    dt = 0.01
+    t = np.arange(ta, tb + 1e-9, dt)
+    dirs = np.array([oracle.slerp(path.seg_dir[0, 0], path.seg_dir[0, 1], (x - ta) / (tb - ta)) for x in t])
+    w_ = np.full(len(t), dt)
+    w_[0] = w_[-1] = dt / 2
+    z = np.zeros(len(t), np.int32)
+    fine = oracle.OraclePath(dirs, w_, t, z, z, np.zeros((0, 2)), np.zeros((0, 2, 3)), np.zeros(0, np.int32),
+                             np.zeros(1, np.int32), 1, np.array([[ta, tb]]))
+    S = oracle.sampled(sc, P, fine, bits=True)
+    bits = np.unpackbits(S["bits"].view(np.uint8), axis=1, bitorder="little")[:, :len(t)]
+    trans = np.abs(np.diff(bits.astype(int), axis=1)).sum(1)
+    assert (D > 0).sum() >= 10 and trans.sum() > 0
+    assert np.all(np.abs(S["minutes"][0] - D) <= trans * dt / 2 + 1e-6)
