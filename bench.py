@@ -383,6 +383,36 @@ def bench_c5(args, sa, torch):
             gp.close()
         r["direction_graph_clock_knots"] = {"segments_full": pc.n_segments, "ms_full": float(np.mean(cms)),
                                             "legs": legs_c}
+        # the paper's own setting (Sec. 8.2): 9:00 to 15:00 every day in
+        # hourly intervals on the clock, one accumulation over the year;
+        # 2,190 intervals, which the paper's graph at 5 degrees reduces to
+        # 299 edges
+        from workloads import Span
+        from workloads.scenes import Day
+        pdays = [Day(d.year, d.month, d.day, d.tz_h, (540.0, 900.0)) for d in w.span.days]
+        psp = sa.sunpath_for_span(Span(w.span.lat, w.span.lon, pdays, 60.0, [0] * len(pdays)), 60.0,
+                                  clock_knots=True)
+        pfull = sa.Path(ctx, psp)
+        ph = torch.empty((1, dp.n), dtype=torch.float32, device="cuda")
+        pms = _timed(torch, ctx.stream,
+                     lambda: sa.sa_accumulate(ctx, sc, dp, pfull, sa.SA_ACCRUAL, None, ph, out_scale=1.0 / 60.0), 1)
+        ctx.sync()
+        pbase = ph.clone()
+        plegs = []
+        for bound in (1.0, 5.0):
+            gp = sa.Path(ctx, psp, graph_bound_deg=bound)
+            gms = _timed(torch, ctx.stream,
+                         lambda: sa.sa_accumulate(ctx, sc, dp, gp, sa.SA_ACCRUAL, None, ph, out_scale=1.0 / 60.0), 1)
+            ctx.sync()
+            err = float((ph - pbase).abs().mean()) * 60.0 / len(pdays)
+            plegs.append({"cell_deg": bound, "edges": gp.n_segments, "ms": float(np.mean(gms)),
+                          "speedup": float(np.mean(pms)) / float(np.mean(gms)),
+                          "mean_abs_error_min_per_point_day": err})
+            log(f"c5 paper setting, {bound} deg: {pfull.n_segments} intervals -> {gp.n_segments} edges, "
+                f"{plegs[-1]['ms']:.0f} ms vs {float(np.mean(pms)):.0f} ms, error {err:.3f} min/point/day")
+            gp.close()
+        r["direction_graph_paper_setting"] = {"intervals": pfull.n_segments, "ms_full": float(np.mean(pms)),
+                                              "paper": {"intervals": 2190, "edges_5deg": 299}, "legs": plegs}
     return r
 
 

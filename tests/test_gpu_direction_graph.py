@@ -208,3 +208,21 @@ def test_graph_paths_and_other_forms(ctx, block):
     assert e.value.code == -1
     with pytest.raises(sa.SAError):
         sa.Path(ctx, sp, graph_bound_deg=0.0)
+
+
+def test_paper_setting_edge_count(ctx):
+    """The paper's year (Sec. 8.2): 9:00 to 15:00 every day of 2019 in
+    hourly intervals on the clock, one accumulation: the library's graph at
+    5-degree cells holds exactly the oracle's edges (2,190 intervals; the
+    paper reports 299 edges for its own cell layout)."""
+    dates = [dt.date(2019, 1, 1) + dt.timedelta(days=i) for i in range(365)]
+    span = Span(40.7, -74.0, [Day(d.year, d.month, d.day, _nyc_tz(d), (540.0, 900.0)) for d in dates], 60.0,
+                [0] * len(dates))
+    sp = sa.sunpath_for_span(span, 60.0, clock_knots=True)
+    full = sa.Path(ctx, sp)
+    op = oracle.sun_path(span, 60.0, clock_knots=True)
+    assert full.n_segments == len(op.seg_t) == 2190
+    for bound in (1.0, 5.0, 10.0):
+        g = sa.Path(ctx, sp, graph_bound_deg=bound)
+        say(f"  paper year, {bound} deg cells: {g.n_segments} edges (oracle {len(oracle.direction_graph(op, bound))})")
+        assert g.n_segments == len(oracle.direction_graph(op, bound))
