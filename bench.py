@@ -30,15 +30,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Algorithmic cost model, VALU lane-operations per unit of work a lane's own
-# traversal needs; the instrumented launch counts the units:
+# traversal needs (fixed before any kernel was measured); the instrumented
+# launch counts the units:
 COST = {
-    "ray_box": 8,          # slab test of one child box: 5 FMA, max3, min3, compare
-    "ray_prism": 6,        # per prism: entry/exit select and height compare
-    "ray_edge": 10,        # per footprint edge: 2 sub, 2+2 FMA, rcp, mul, 2 min/max selects
-    "fan_box": 20,         # fan-triangle vs box: rise + sign, 4 FMA + 4 cmp bbox, 2 edge normals (4 FMA + cmp)
-    "fan_prism": 40,       # per prism: inside/cover and window intersection logic
-    "fan_edge": 36,        # per edge: 2 sub, 4 FMA (u,v), 2 FMA z, clip crossing, 2 tangent updates
-    "insert": 60,          # 4-member interval-set insertion
+    "ray_box": 14,         # ray vs box slab: 6 FMA + 6 min/max + 2 compares
+    "ray_prism": 6,        # ray vs prism: entry/exit and height compare ...
+    "ray_edge": 8,         # ... plus 8 per footprint edge (2D Cyrus-Beck)
+    "fan_box": 28,         # fan (wedge) vs box: plane-box test and the sector's 2D bound
+    "fan_prism": 40,       # fan vs prism: window intersection, angle by a cross/dot ratio ...
+    "fan_edge": 10,        # ... plus 10 per footprint edge (2 plane distances and the crossing)
+    "insert": 16,          # interval insertion: 4 per comparison, 4 comparisons in the 4-member set
 }
 LANE_OP_PEAK = 256 * 64 * 2.4e9   # CUs x lanes x clock: one VALU lane-op per lane per cycle
 
@@ -137,7 +138,7 @@ def _err_stats(x, ref):
 
 
 def accuracy_vs_oracle(w, sa, ctx, scene, head_seg, segs=(15.0, 20.0, 30.0, 45.0), n=2048):
-    """Method accuracy of both forms against the oracle's continuous
+    """Part of the CPU-baseline leg.  Method accuracy of both forms against the oracle's continuous
     duration along the sun's actual FP64 path (5-second scan and bisection
     per occluder, unioned): a seeded subset of n points (half ground, half
     facade) over every day of the workload; per point-day |form - truth| in
@@ -200,6 +201,8 @@ def bench_c3(args, sa, torch):
     from workloads import make_c3
     w = make_c3()
     ctx = sa.Context(0)
+    from paper_1907_04435_amd import tune
+    launch = {} if args.untuned else tune.apply(ctx)
     sc = sa.Scene.from_workload(ctx, w.scene)
     path = sa.Path(ctx, sa.sunpath_for_span(w.span, args.seg))
     dp = sa.DevicePoints.from_workload(w.points)
@@ -208,7 +211,7 @@ def bench_c3(args, sa, torch):
     off = torch.from_numpy(w.extra["var_off"].astype(np.int64)).cuda()
     counts = torch.empty((path.n_bins, dp.n), dtype=torch.int32, device="cuda")
     mins = torch.empty((path.n_bins, dp.n), dtype=torch.float32, device="cuda")
-    gb = args.grid_blocks or tuned_grid_blocks()
+    gb = args.grid_blocks
     run = lambda: sa.sa_accumulate_batched(ctx, sc, ids, hh, dp, off, path, counts, mins, grid_blocks=gb)
     for _ in range(args.warmup):
         run()
@@ -217,12 +220,13 @@ def bench_c3(args, sa, torch):
     ctx.sync()
     evals = dp.n * path.n_samples
     m = float(np.mean(ms))
-    log(f"c3: {m:.1f} ms per batched pass, grid {gb}")
-    return _base("point-sun-step evals/s (accrual form, batched variants)", evals / (m / 1e3),
-                 "point-sun-steps/s", args, m,
-                 {"workload": w.name, "variants": int(len(off) - 1), "points": dp.n, "buildings": w.scene.n_b,
-                  "instants_per_point": path.n_samples, "seg_min": args.seg, "grid_blocks": gb,
-                  "point_sun_steps": evals})
+    log(f"c3: {m:.1f} ms per batched pass, launch {launch or 'defaults'}")
+    r = _base("point-sun-step evals/s (accrual form, batched variants)", evals / (m / 1e3),
+              "point-sun-steps/s", args, m,
+              {"workload": w.name, "variants": int(len(off) - 1), "points": dp.n, "buildings": w.scene.n_b,
+               "instants_per_point": path.n_samples, "seg_min": args.seg, "point_sun_steps": evals})
+    r["tuning"] = {"grid_blocks_arg": gb, **launch}
+    return r
 
 
 def bench_c4(args, sa, torch):
@@ -416,24 +420,14 @@ def bench_c5(args, sa, torch):
     return r
 
 
-def tuned_grid_blocks():
-    """Persistent grid size picked by paper_1907_04435_amd/tune.py (cached),
-    else the library default."""
-    p = os.path.join(ROOT, "paper_1907_04435_amd", "tuning.json")
-    if os.path.exists(p):
-        try:
-            return int(json.load(open(p)).get("batched_grid_blocks", 0))
-        except (ValueError, OSError):
-            return 0
-    return 0
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--seg", type=float, default=30.0, help="accrual knot spacing, minutes")
+    ap.add_argument("--seg", type=float, default=None,
+                    help="accrual knot spacing, minutes (default: the autotuner's choice, else 30)")
+    ap.add_argument("--untuned", action="store_true", help="ignore the autotuner's cached choices")
     ap.add_argument("--sampled-steps", type=int, default=1)
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5", "sam"],
                     help="c2 (default): the block scene, both forms; c3 batched variants; "
@@ -471,7 +465,12 @@ def main():
         print(json.dumps({"copy_bytes_read": n * 4, "copy_bytes_written": n * 4, "dispatches": 3}))
         return
     import paper_1907_04435_amd as sa
+    from paper_1907_04435_amd import tune
     from workloads import make_c1, make_c2
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    tuned = {} if args.untuned else tune.load(arch)
+    if args.seg is None:
+        args.seg = float(tuned.get("seg_min", 30.0))
     if args.workload in ("c3", "c4", "c5", "sam"):
         res = {"c3": bench_c3, "c4": bench_c4, "c5": bench_c5, "sam": bench_sam}[args.workload](args, sa, torch)
         print(json.dumps(res), flush=True)
@@ -481,6 +480,7 @@ def main():
     w = make_c2() if args.workload == "c2" else make_c1()
     log(f"workload {w.name}: {w.scene.n_b} prisms, {w.points.n} points, generated in {time.perf_counter()-t0:.1f} s")
     ctx = sa.Context(0)
+    launch = tune.apply(ctx, tuned) if tuned else {}
     stream = ctx.stream
     scene = sa.Scene.from_workload(ctx, w.scene)
     sp_acc = sa.sunpath_for_span(w.span, args.seg)
@@ -541,6 +541,8 @@ def main():
                    "buildings": w.scene.n_b, "instants_per_point": K, "days": B, "seg_min": args.seg,
                    "point_sun_steps": evals},
         "accumulate_launch_ms": launch_stats,
+        "tuning": {"source": "paper_1907_04435_amd/tuning.json" if tuned else "defaults", "seg_min": args.seg,
+                   **launch},
     }
 
     # ---- continuous shadow leg (gross and longest uninterrupted shadow in one pass)
@@ -593,13 +595,11 @@ def main():
         result["sampled"] = {"value": evals / (s_ms / 1e3), "unit": "point-sun-steps/s", "ms_per_pass": s_ms}
         result["accrual_over_sampled"] = (evals / (ms_step / 1e3)) / (evals / (s_ms / 1e3))
 
-    # ---- accuracy leg: both forms against the oracle's continuous duration on
-    # the actual sun path (a seeded subset), and, over every point, the
-    # headline accrual and the sampled form against the accrual form with a
-    # knot at every instant (which the subset ties to the oracle)
+    # ---- accuracy over every point: the headline accrual and the sampled
+    # form against the accrual form with a knot at every instant (the CPU
+    # baseline leg below ties that reference to the oracle on a subset)
+    acc = {}
     if not args.no_truth:
-        log("accuracy against the oracle ...")
-        acc = accuracy_vs_oracle(w, sa, ctx, scene, args.seg)
         path1 = sa.Path(ctx, sa.sunpath_for_span(w.span, w.span.step_min))
         truth = torch.empty((B, n), dtype=torch.float32, device=dev)
         sa.sa_accumulate(ctx, scene, pts, path1, sa.SA_ACCRUAL, None, truth)
@@ -615,7 +615,6 @@ def main():
             full["sampled"] = errstats(mins_s)
         acc["all_points_vs_1min_knots"] = full
         result["accuracy_minutes_per_point_day"] = acc
-        log(f"accuracy: {json.dumps(acc)}")
         del truth, path1
 
     # ---- instrumented runs: algorithmic work per launch
@@ -649,10 +648,18 @@ def main():
                                                   "leaf_visits_per_wave": int(ws[7]), "lane_ops": sops}
             log(f"sampled work: {ws.tolist()} -> {sops:.3e} lane-ops")
 
-    # ---- CPU baseline (rank 0, N = 1)
+    # ---- CPU baseline leg (rank 0, N = 1): the oracle timed on the host
+    # cores, and its continuous duration on the actual sun path as the
+    # reference of both forms' accuracy on a seeded subset
     if not args.no_cpu_baseline:
         log("cpu baseline ...")
         result["cpu_baseline"] = cpu_baseline(w)
+        if not args.no_truth:
+            log("accuracy against the oracle ...")
+            ref = accuracy_vs_oracle(w, sa, ctx, scene, args.seg)
+            ref["all_points_vs_1min_knots"] = acc.get("all_points_vs_1min_knots")
+            result["accuracy_minutes_per_point_day"] = ref
+            log(f"accuracy: {json.dumps(ref)}")
     print(json.dumps(result), flush=True)
 
 

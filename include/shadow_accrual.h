@@ -74,6 +74,24 @@ sa_status sa_create(int32_t device, void *hip_stream, sa_ctx **out);
 void sa_destroy(sa_ctx *ctx);
 /* Change the stream later calls enqueue on. */
 sa_status sa_set_stream(sa_ctx *ctx, void *hip_stream);
+
+/* Launch choices of a context that change speed, never results (counts and
+ * bit vectors are equal under every choice; minutes may differ in the last
+ * bits where a bin's float sums are grouped differently).  An autotuner
+ * measures them per device and sets them; zero fields keep the defaults. */
+typedef struct {
+    int32_t accrual_segments_per_launch; /* accrual form: the most path segments one launch covers
+                                            (their per-segment hierarchy views are the launch's working
+                                            set); 0 = as many as the view budget allows */
+    int32_t batched_grid_blocks;         /* sa_accumulate_batched: blocks of the persistent launch when
+                                            opts->grid_blocks is 0; 0 = 2048 */
+    int32_t batched_tiles_per_grab;      /* sa_accumulate_batched: consecutive 64-point tiles a wave takes
+                                            from the work queue per atomic; 0 = 1 */
+    int32_t reserved;                    /* 0 */
+} sa_launch;
+/* Errors: INVALID_ARG (negative or out-of-range values). */
+sa_status sa_set_launch(sa_ctx *ctx, const sa_launch *launch);
+sa_status sa_get_launch(const sa_ctx *ctx, sa_launch *out);
 /* Message of the last failed call on this context ("" if none). */
 const char *sa_last_error(const sa_ctx *ctx);
 /* Wait for the context's stream; reports errors raised by device work

@@ -26,7 +26,8 @@ SA_FLAG_ADD = 1
 _ERRORS = {-1: "INVALID_ARG", -2: "GEOMETRY", -3: "CAPACITY", -4: "OOM", -5: "DEVICE", -6: "UNSUPPORTED"}
 
 # Every entry point declared in include/shadow_accrual.h.
-EXPORTS = ["sa_create", "sa_destroy", "sa_set_stream", "sa_last_error", "sa_sync", "sa_version",
+EXPORTS = ["sa_create", "sa_destroy", "sa_set_stream", "sa_set_launch", "sa_get_launch", "sa_last_error", "sa_sync",
+           "sa_version",
            "sa_scene_upload", "sa_scene_set_heights", "sa_scene_get_info", "sa_scene_read_bvh",
            "sa_scene_destroy", "sa_sunpath", "sa_path_upload", "sa_path_upload_graph", "sa_path_info", "sa_path_destroy",
            "sa_accumulate", "sa_accumulate_noalloc", "sa_accumulate_batched", "sa_grad_heights", "sa_region_sum",
@@ -72,6 +73,11 @@ class sa_sam_opts(C.Structure):
                 ("out_scale", C.c_float), ("max_texels", C.c_int64)]
 
 
+class sa_launch(C.Structure):
+    _fields_ = [("accrual_segments_per_launch", C.c_int32), ("batched_grid_blocks", C.c_int32),
+                ("batched_tiles_per_grab", C.c_int32), ("reserved", C.c_int32)]
+
+
 class sa_accum_opts(C.Structure):
     _fields_ = [("mode", C.c_int32), ("flags", C.c_uint32), ("out_scale", C.c_float),
                 ("grid_blocks", C.c_int32), ("work", C.c_void_p), ("longest", C.c_void_p),
@@ -93,6 +99,8 @@ def lib():
             "sa_create": (i32, [i32, vp, C.POINTER(vp)]),
             "sa_destroy": (None, [vp]),
             "sa_set_stream": (i32, [vp, vp]),
+            "sa_set_launch": (i32, [vp, C.POINTER(sa_launch)]),
+            "sa_get_launch": (i32, [vp, C.POINTER(sa_launch)]),
             "sa_last_error": (C.c_char_p, [vp]),
             "sa_sync": (i32, [vp]),
             "sa_version": (C.c_char_p, []),
@@ -248,6 +256,17 @@ class Context:
 
     def sync(self):
         _check(self, lib().sa_sync(self.handle))
+
+    def set_launch(self, accrual_segments_per_launch=0, batched_grid_blocks=0, batched_tiles_per_grab=0):
+        """Launch choices (speed only; see sa_set_launch)."""
+        _check(self, lib().sa_set_launch(self.handle, C.byref(sa_launch(int(accrual_segments_per_launch),
+                                                                        int(batched_grid_blocks),
+                                                                        int(batched_tiles_per_grab), 0))))
+
+    def get_launch(self) -> dict:
+        l = sa_launch()
+        _check(self, lib().sa_get_launch(self.handle, C.byref(l)))
+        return {k: getattr(l, k) for k, _ in sa_launch._fields_ if k != "reserved"}
 
     def close(self):
         if getattr(self, "handle", None):

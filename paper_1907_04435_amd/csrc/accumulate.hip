@@ -32,11 +32,13 @@ struct BinOut {
     double *minutes64;    // the FP64 lane sums behind minutes (optional)
     int32_t fresh_first;  // the launch's first bin starts in it
     int32_t fresh_rest;   // the later bins of the launch start in it
+    float scale;          // minutes are multiplied by this
+    int32_t pad;
 };
 
-__device__ __forceinline__ void put_bin(const BinOut &O, int64_t o, bool fresh, int cnt, double mins, float scale)
+__device__ __forceinline__ void put_bin(const BinOut &O, int64_t o, bool fresh, int cnt, double mins)
 {
-    const double v = mins * scale;
+    const double v = mins * O.scale;
     if (O.counts) O.counts[o] = (fresh ? 0 : O.counts[o]) + cnt;
     if (O.minutes) O.minutes[o] = (fresh ? 0.f : O.minutes[o]) + (float)v;
     if (O.minutes64) O.minutes64[o] = (fresh ? 0.0 : O.minutes64[o]) + v;
@@ -322,8 +324,8 @@ __device__ __forceinline__ bool roof_covered(cNode *nodes, StackEntry *stack, cf
 template <bool kCount>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_accrual(
     const Node *nodes_g, const SegNode *snodes_g, int n_nodes, const int32_t *voff_g, const float4 *verts_g,
-    const float *height_g, const SegConst *segs_g, int j0, int j1, PointArgs P, float scale, BinOut O,
-    SpillArgs S, uint64_t *work)
+    const float *height_g, const SegConst *segs_g, int j0, int j1, PointArgs P, BinOut O, SpillArgs S,
+    uint64_t *work)
 {
     Work wk{0, 0, 0, 0, 0, 0, 0};
     cNode *nodes = (cNode *)nodes_g;
@@ -331,6 +333,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     cfloat *height = (cfloat *)height_g;
     cSeg *segs = (cSeg *)segs_g;
     __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    // the outputs are needed only when a bin ends: parked in LDS so their
+    // pointers hold no scalar registers through the traversal loop
+    __shared__ int s_O[sizeof(BinOut) / 4];
+    __shared__ int s_S[sizeof(SpillArgs) / 4];
+    if (threadIdx.x == 0) {
+        lds_park((lds_int *)s_O, O);
+        lds_park((lds_int *)s_S, S);
+    }
+    __syncthreads();
     StackEntry *stack = s_stack[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
@@ -343,15 +354,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     int cnt = 0;
     double mins = 0.0;  // per-lane FP64: long spans sum thousands of segment measures
     int bin = j1 > j0 ? ld(segs + j0).bin : 0;
-    bool fresh = O.fresh_first != 0;
+    bool fresh = lds_uniform<BinOut>((lds_int *)s_O).fresh_first != 0;
     for (int j = j0; j < j1; ++j) {
         const SegConst g = ld(segs + j);
         if (g.bin != bin) {
-            if (valid) put_bin(O, (int64_t)bin * n + i, fresh, cnt, mins, scale);
+            const BinOut Ob = lds_uniform<BinOut>((lds_int *)s_O);
+            if (valid) put_bin(Ob, (int64_t)bin * n + i, fresh, cnt, mins);
             cnt = 0;
             mins = 0.0;
             bin = g.bin;
-            fresh = O.fresh_rest != 0;
+            fresh = Ob.fresh_rest != 0;
         }
         Union4 U;
         bool ov;
@@ -369,9 +381,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
         } else if (!ov) {
             measure(U, gm, 0.f, gm.theta, true, mins, cnt);
         }
-        spill_push(S, valid && ov, i, j, 0.f, gm.theta);
+        if (ballot(valid && ov)) spill_push(lds_uniform<SpillArgs>((lds_int *)s_S), valid && ov, i, j, 0.f, gm.theta);
     }
-    if (valid && j1 > j0) put_bin(O, (int64_t)bin * n + i, fresh, cnt, mins, scale);
+    if (valid && j1 > j0) put_bin(lds_uniform<BinOut>((lds_int *)s_O), (int64_t)bin * n + i, fresh, cnt, mins);
     if constexpr (kCount) flush_work(wk, work);
 }
 
@@ -406,14 +418,25 @@ __device__ __forceinline__ void runs_update(const Union4 &U, float w0, float w1,
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_accrual_runs(const Node *nodes_g, const SegNode *snodes_g, int n_nodes,
                                                            const int32_t *voff_g, const float4 *verts_g,
                                                            const float *height_g, const SegConst *segs_g, int j0,
-                                                           int j1, PointArgs P, float scale, BinOut O,
-                                                           float *longest, uint32_t *overflow)
+                                                           int j1, PointArgs P, BinOut O, float *longest,
+                                                           uint32_t *overflow)
 {
     cNode *nodes = (cNode *)nodes_g;
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
     cSeg *segs = (cSeg *)segs_g;
     __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    // outputs (and where to flag overflow) parked in LDS: needed only at a
+    // bin's end, they hold no scalar registers through the traversal
+    __shared__ int s_O[sizeof(BinOut) / 4];
+    __shared__ float *s_longest;
+    __shared__ uint32_t *s_overflow;
+    if (threadIdx.x == 0) {
+        lds_park((lds_int *)s_O, O);
+        s_longest = longest;
+        s_overflow = overflow;
+    }
+    __syncthreads();
     StackEntry *stack = s_stack[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
     const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
@@ -429,12 +452,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
     float run = 0.f, best = 0.f;
     int bin = j1 > j0 ? ld(segs + j0).bin : 0;
     int day = j1 > j0 ? ld(segs + j0).day : 0;
-    bool fresh = O.fresh_first != 0;
+    bool fresh = lds_uniform<BinOut>((lds_int *)s_O).fresh_first != 0;
     auto flush = [&]() {
         if (!valid) return;
         const int64_t o = (int64_t)bin * n + i;
-        put_bin(O, o, fresh, cnt, mins, scale);
-        if (longest) longest[o] = fresh ? best * scale : fmaxf(longest[o], best * scale);
+        const BinOut Ob = lds_uniform<BinOut>((lds_int *)s_O);
+        put_bin(Ob, o, fresh, cnt, mins);
+        float *lg = s_longest;
+        if (lg) lg[o] = fresh ? best * Ob.scale : fmaxf(lg[o], best * Ob.scale);
     };
     for (int j = j0; j < j1; ++j) {
         const SegConst g = ld(segs + j);
@@ -444,7 +469,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
             mins = 0.0;
             best = 0.f;
             bin = g.bin;
-            fresh = O.fresh_rest != 0;
+            fresh = lds_uniform<BinOut>((lds_int *)s_O).fresh_rest != 0;
         }
         if (g.day != day) {
             run = 0.f;
@@ -468,7 +493,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
             if (pending) {
                 if (ov) {
                     if (s < g.theta * (1.0f / 4096.0f)) {
-                        atomicOr(overflow, 2u);
+                        atomicOr(s_overflow, 2u);
                         pending = false;
                     } else {
                         s *= 0.5f;
@@ -783,8 +808,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
                                                       const float *vh_g, int n_b, const SegConst *segs_g, int j0,
                                                       int j1, PointArgs P, const int64_t *__restrict__ var_off,
                                                       const int64_t *__restrict__ tile_off, int V,
-                                                      uint32_t *tile_counter, float scale, int32_t *counts,
-                                                      float *minutes, uint32_t *flag)
+                                                      uint32_t *tile_counter, int32_t grab, float scale,
+                                                      int32_t *counts, float *minutes, uint32_t *flag)
 {
     cfloat4 *verts = (cfloat4 *)verts_g;
     cSeg *segs = (cSeg *)segs_g;
@@ -796,10 +821,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
     const int64_t n = P.n;
     if (threadIdx.x == 0) lds_park((lds_int *)s_P, P);
     __syncthreads();
+    // a wave takes `grab` consecutive (variant, tile) items per atomic
+    int64_t t = 0, t_end = 0;
     for (;;) {
-        int64_t t = 0;
-        if (lane == 0) t = atomicAdd((unsigned long long *)tile_counter, 1ull);
-        t = __shfl(t, 0, 64);
+        if (t >= t_end) {
+            int64_t g0 = 0;
+            if (lane == 0) g0 = atomicAdd((unsigned long long *)tile_counter, (unsigned long long)grab);
+            g0 = __shfl(g0, 0, 64);
+            t = g0;
+            t_end = min(g0 + (int64_t)grab, T);
+        }
         if (t >= T) break;
         int lo = 0, hi = V - 1;               // last v with tile_off[v] <= t
         while (lo < hi) {
@@ -865,6 +896,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
             if (counts) counts[(int64_t)bin * n + i] += cnt;
             if (minutes) minutes[(int64_t)bin * n + i] += (float)(mins * scale);
         }
+        ++t;
     }
 }
 
@@ -947,10 +979,11 @@ sa_status fill_u32(void *p, int64_t n, uint32_t v, hipStream_t st, std::string &
 
 sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_var, int32_t k, const int32_t *ids,
                          const float *h, const PointsView &pts, const int64_t *var_off, float scale, int32_t *counts,
-                         float *minutes, int32_t grid_blocks, uint32_t *flag, Scratch &scr, Scratch &views_scr,
-                         hipStream_t st, std::string &err)
+                         float *minutes, int32_t grid_blocks, int32_t grab, uint32_t *flag, Scratch &scr,
+                         Scratch &views_scr, hipStream_t st, std::string &err)
 {
     if (n_var == 0 || pts.n == 0) return SA_OK;
+    grab = std::max(grab, 1);
     const int n_nodes = s.n_b > 0 ? s.n_nodes : 0;
     // copies of changed nodes per variant: at most one chain of ancestors
     // per changed building
@@ -1034,7 +1067,7 @@ sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_va
         hipLaunchKernelGGL(k_batched, dim3(blocks), dim3(kThreads), 0, st, s.n_b > 0 ? vnodes : nullptr, n_nodes,
                            views, stride, s.voff, s.n_b > 0 ? (const int32_t *)vroot : nullptr, s.verts,
                            (const float *)vh, s.n_b, p.segs, (int)j0, j1, P, var_off, (const int64_t *)tile_off,
-                           n_var, counter, scale, counts, minutes, flag);
+                           n_var, counter, grab, scale, counts, minutes, flag);
         SA_CHECK_LAUNCH("batched accrual");
     }
     return SA_OK;
@@ -1084,15 +1117,17 @@ sa_status build_seg_views(const DeviceScene &s, const DevicePath &p, int j0, int
 // (no SA_FLAG_ADD, and every bin's segments one contiguous run) a bin is
 // stored by the launch holding its first segment and added to by later
 // ones, so the outputs need no clearing.
-static BinOut bin_out(const DevicePath &p, int j0, bool store, int32_t *counts, float *minutes, double *minutes64)
+static BinOut bin_out(const DevicePath &p, int j0, bool store, int32_t *counts, float *minutes, double *minutes64,
+                      float scale)
 {
     const bool first = store && (j0 == 0 || p.seg_bin[j0 - 1] != p.seg_bin[j0]);
-    return BinOut{counts, minutes, minutes64, first ? 1 : 0, store ? 1 : 0};
+    return BinOut{counts, minutes, minutes64, first ? 1 : 0, store ? 1 : 0, scale, 0};
 }
 
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
                          int32_t *counts, float *minutes, double *minutes64, float *longest, uint64_t *work,
-                         bool store, SpillQueue &q, Scratch &scr, hipStream_t st, std::string &err)
+                         bool store, int32_t seg_per_launch, SpillQueue &q, Scratch &scr, hipStream_t st,
+                         std::string &err)
 {
     if (pts.n == 0) return SA_OK;
     const int64_t waves = (pts.n + 63) / 64;
@@ -1109,7 +1144,8 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
               " bytes) exceed the fixed scratch (" + std::to_string(scr.bytes) + " bytes)";
         return SA_ERR_CAPACITY;
     }
-    const int64_t per = std::min(std::max<int64_t>(1, kChunkWork / std::max<int64_t>(pts.n, 1)), std::max<int64_t>(cap, 1));
+    int64_t per = std::min(std::max<int64_t>(1, kChunkWork / std::max<int64_t>(pts.n, 1)), std::max<int64_t>(cap, 1));
+    if (seg_per_launch > 0) per = std::min<int64_t>(per, seg_per_launch);
     if (longest) {
         // whole days per launch, so a run never spans two launches (one
         // day per launch at least, whatever its views take)
@@ -1129,8 +1165,8 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
             sa_status rc = build_seg_views(s, p, j0, j1, s.n_nodes, scr, st, views, err);
             if (rc != SA_OK) return rc;
             hipLaunchKernelGGL(k_accrual_runs, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, views, s.n_nodes,
-                               s.voff, s.verts, s.height, p.segs, j0, j1, P, scale,
-                               bin_out(p, j0, store, counts, minutes, minutes64), longest, q.counters + 2);
+                               s.voff, s.verts, s.height, p.segs, j0, j1, P,
+                               bin_out(p, j0, store, counts, minutes, minutes64, scale), longest, q.counters + 2);
             SA_CHECK_LAUNCH("accrual kernel (continuous shadow)");
             d0 = d1;
         }
@@ -1144,8 +1180,8 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters);
         SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
         hipLaunchKernelGGL(work ? k_accrual<true> : k_accrual<false>, dim3((unsigned)grid), dim3(kThreads), 0, st,
-                           nodes, views, s.n_nodes, s.voff, s.verts, s.height, p.segs, (int)j0, j1, P, scale,
-                           bin_out(p, (int)j0, store, counts, minutes, minutes64), S, work);
+                           nodes, views, s.n_nodes, s.voff, s.verts, s.height, p.segs, (int)j0, j1, P,
+                           bin_out(p, (int)j0, store, counts, minutes, minutes64, scale), S, work);
         SA_CHECK_LAUNCH("accrual kernel");
         rc = run_spill(s, p, views, (int)j0, P, scale, counts, minutes, minutes64, q, st, err);
         if (rc != SA_OK) return rc;

@@ -27,6 +27,7 @@ struct sa_ctx {
     sa::Scratch scratch_grad;     // FP64 height-gradient accumulator
     sa::Scratch scratch_w;        // per-bin weights of a region score
     uint32_t sam_stamp = 0;       // the last segment stamp written into it
+    sa_launch launch = {0, 0, 1, 0};  // tuning choices (sa_set_launch)
     void *noalloc = nullptr;      // this device's fixed scratch (device address), or null
     std::string noalloc_err;      // why it is null
 };
@@ -195,6 +196,24 @@ void sa_destroy(sa_ctx *ctx)
     (void)hipFree(ctx->scratch_grad.ptr);
     (void)hipFree(ctx->scratch_w.ptr);
     delete ctx;
+}
+
+sa_status sa_set_launch(sa_ctx *ctx, const sa_launch *l)
+{
+    if (!ctx || !l) return SA_ERR_INVALID_ARG;
+    if (l->accrual_segments_per_launch < 0 || l->batched_grid_blocks < 0 || l->batched_grid_blocks > (1 << 20) ||
+        l->batched_tiles_per_grab < 0 || l->batched_tiles_per_grab > 1024)
+        return fail(ctx, SA_ERR_INVALID_ARG, "sa_set_launch: value out of range");
+    ctx->launch = *l;
+    if (ctx->launch.batched_tiles_per_grab == 0) ctx->launch.batched_tiles_per_grab = 1;
+    return SA_OK;
+}
+
+sa_status sa_get_launch(const sa_ctx *ctx, sa_launch *l)
+{
+    if (!ctx || !l) return SA_ERR_INVALID_ARG;
+    *l = ctx->launch;
+    return SA_OK;
 }
 
 sa_status sa_set_stream(sa_ctx *ctx, void *hip_stream)
@@ -777,7 +796,8 @@ sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts
                                 opts->work, ctx->stream, err);
     else
         rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->minutes64,
-                                opts->longest, opts->work, store, ctx->spill, ctx->scratch_seg, ctx->stream, err);
+                                opts->longest, opts->work, store, ctx->launch.accrual_segments_per_launch, ctx->spill,
+                                ctx->scratch_seg, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate: " + err);
     return SA_OK;
 }
@@ -833,7 +853,8 @@ sa_status sa_accumulate_noalloc(sa_ctx *ctx, const sa_scene *scene, const sa_poi
         fixed.bytes = (size_t)SA_NOALLOC_SCRATCH_BYTES;
         fixed.fixed = true;
         rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->minutes64,
-                                opts->longest, opts->work, store, ctx->spill, fixed, ctx->stream, err);
+                                opts->longest, opts->work, store, ctx->launch.accrual_segments_per_launch, ctx->spill,
+                                fixed, ctx->stream, err);
     }
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate_noalloc: " + err);
     return SA_OK;
@@ -859,9 +880,10 @@ sa_status sa_accumulate_batched(sa_ctx *ctx, const sa_scene *scene, int32_t n_va
     rc = clear_outputs(ctx, opts->flags, (int64_t)path->d.n_bins * pts->n, counts, minutes);
     if (rc != SA_OK) return rc;
     std::string err;
+    const int32_t grid = opts->grid_blocks > 0 ? opts->grid_blocks : ctx->launch.batched_grid_blocks;
     rc = sa::launch_batched(scene->d, path->d, n_var, ids_per_var, var_ids, var_h, view(pts), var_off, scale,
-                            counts, minutes, opts->grid_blocks, ctx->spill.counters + 2, ctx->scratch_batched,
-                            ctx->scratch_seg, ctx->stream, err);
+                            counts, minutes, grid, ctx->launch.batched_tiles_per_grab, ctx->spill.counters + 2,
+                            ctx->scratch_batched, ctx->scratch_seg, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate_batched: " + err);
     return SA_OK;
 }

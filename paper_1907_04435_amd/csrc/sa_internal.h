@@ -183,10 +183,12 @@ sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const Points
                          uint64_t *work, hipStream_t st, std::string &err);
 // store: outputs need no clearing (no SA_FLAG_ADD and p.bins_contiguous):
 // each bin is stored by the launch holding its first segment.
+// seg_per_launch > 0 caps the segments one launch covers (a tuning choice:
+// the per-segment views a launch reads).
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
                          float scale, int32_t *counts, float *minutes, double *minutes64, float *longest,
-                         uint64_t *work, bool store, SpillQueue &q, Scratch &scr, hipStream_t st,
-                         std::string &err);
+                         uint64_t *work, bool store, int32_t seg_per_launch, SpillQueue &q, Scratch &scr,
+                         hipStream_t st, std::string &err);
 // grad = (add ? grad : 0) + scale * d(sum dl * minutes)/dH, accumulated in
 // FP64 in acc (grown to n_b doubles as needed).
 sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
@@ -217,7 +219,7 @@ sa_status launch_sam(const DeviceScene &s, const DevicePath &p, const PointsView
 sa_status launch_batched(const DeviceScene &s, const DevicePath &p, int32_t n_var, int32_t k,
                          const int32_t *ids, const float *h, const PointsView &pts,
                          const int64_t *var_off, float scale, int32_t *counts, float *minutes,
-                         int32_t grid_blocks, uint32_t *flag, Scratch &scr, Scratch &views_scr,
+                         int32_t grid_blocks, int32_t grab, uint32_t *flag, Scratch &scr, Scratch &views_scr,
                          hipStream_t st, std::string &err);
 // Graph-capturable fill of n 32-bit words.
 sa_status fill_u32(void *p, int64_t n, uint32_t v, hipStream_t st, std::string &err);

@@ -1,0 +1,69 @@
+"""The context's launch choices (sa_set_launch, set by the autotuner)
+change speed only: accrual counts are equal and minutes equal to float
+rounding whatever the segments per launch, and batched counts are equal
+whatever the grid size and the tiles a wave takes per grab.  Bad values
+are refused."""
+import numpy as np
+import pytest
+
+import paper_1907_04435_amd as sa
+from workloads import make_c2, make_c3
+
+from gpu_util import say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return sa.Context(0)
+
+
+def test_accrual_segments_per_launch(ctx):
+    w = make_c2(n_ground=20_000, n_facade=20_000)
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    dp = sa.DevicePoints.from_workload(w.points)
+    path = sa.Path(ctx, sa.sunpath_for_span(w.span, 30.0))
+    out = {}
+    for per in (0, 7, 1):
+        ctx.set_launch(accrual_segments_per_launch=per)
+        c, m, _ = sa.accumulate(ctx, sc, dp, path, sa.SA_ACCRUAL)
+        ctx.sync()
+        out[per] = (c.cpu().numpy(), m.cpu().numpy())
+    ctx.set_launch()
+    for per in (7, 1):
+        np.testing.assert_array_equal(out[per][0], out[0][0])
+        d = np.abs(out[per][1] - out[0][1]).max()
+        say(f"  {per} segments per launch: counts equal, max |minutes diff| {d:.2e}")
+        assert d <= 1e-3
+
+
+def test_batched_grid_and_grab(ctx):
+    import torch
+    w = make_c3(n_var=12, n_per_var=3000)
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    path = sa.Path(ctx, sa.sunpath_for_span(w.span, 30.0))
+    dp = sa.DevicePoints.from_workload(w.points)
+    ids = torch.from_numpy(w.extra["var_ids"].astype(np.int32)).cuda()
+    hh = torch.from_numpy(w.extra["var_h"].astype(np.float32)).cuda()
+    off = torch.from_numpy(w.extra["var_off"].astype(np.int64)).cuda()
+    res = []
+    for gb, grab in ((2048, 1), (64, 3), (300, 8), (1, 1)):
+        ctx.set_launch(batched_grid_blocks=gb, batched_tiles_per_grab=grab)
+        c = torch.empty((path.n_bins, dp.n), dtype=torch.int32, device="cuda")
+        m = torch.empty((path.n_bins, dp.n), dtype=torch.float32, device="cuda")
+        sa.sa_accumulate_batched(ctx, sc, ids, hh, dp, off, path, c, m)
+        ctx.sync()
+        res.append((c.cpu().numpy(), m.cpu().numpy()))
+    ctx.set_launch()
+    for c, m in res[1:]:
+        np.testing.assert_array_equal(c, res[0][0])
+        assert np.abs(m - res[0][1]).max() <= 1e-3
+
+
+def test_bad_launch_values(ctx):
+    with pytest.raises(sa.SAError):
+        ctx.set_launch(accrual_segments_per_launch=-1)
+    with pytest.raises(sa.SAError):
+        ctx.set_launch(batched_tiles_per_grab=5000)
+    assert ctx.get_launch()["batched_tiles_per_grab"] == 1
