@@ -471,3 +471,31 @@ def test_continuous_matches_unculled_fine_sampling():
     trans = np.abs(np.diff(bits.astype(int), axis=1)).sum(1)
     assert (D > 0).sum() >= 10 and trans.sum() > 0
     assert np.all(np.abs(S["minutes"][0] - D) <= trans * dt / 2 + 1e-6)
+
+
+def test_thin_pole_run_matches_great_circle_root_find():
+    """The great-circle form's short-run detection against an analytic
+    crossing: a 2 cm pole 200 m away shadows the point while the azimuth of
+    the path's direction (slerp between the segment's knots) lies between
+    the azimuths of the pole's silhouette corners; both ends by brentq on
+    that azimuth."""
+    from scipy.optimize import brentq
+    span = Span(40.7, -74.0, [Day(2019, 6, 21, -4.0, (480.0, 1080.0))], step_min=5.0)
+    path = oracle.sun_path(span, seg_min=30.0)
+    t_mid = 607.0 + 2.5 / 60.0
+    j = int(np.searchsorted(path.seg_t[:, 0], t_mid, side="right") - 1)
+    ta, tb = path.seg_t[j]
+    on_arc = lambda t: oracle.slerp(path.seg_dir[j, 0], path.seg_dir[j, 1], (t - ta) / (tb - ta))
+    d = on_arc(t_mid)
+    az = math.atan2(d[0], d[1])
+    c = 200.0 * np.array([math.sin(az), math.cos(az)])
+    h = 200.0 * d[2] / math.hypot(d[0], d[1]) + 40.0
+    sc = box_scene([(c[0] - 0.01, c[1] - 0.01, c[0] + 0.01, c[1] + 0.01, h)])
+    corners = np.array(sc.footprint(0), np.float64)
+    az_c = np.arctan2(corners[:, 0], corners[:, 1])
+    arc_az = lambda t: math.atan2(on_arc(t)[0], on_arc(t)[1])
+    t_in = brentq(lambda t: arc_az(t) - az_c.min(), t_mid - 1.0, t_mid + 1.0, xtol=1e-12)
+    t_out = brentq(lambda t: arc_az(t) - az_c.max(), t_mid - 1.0, t_mid + 1.0, xtol=1e-12)
+    D = oracle.continuous(sc, pts([[0.0, 0.0, 0.0]]), path)["minutes"][0, 0]
+    assert 0.0 < abs(t_out - t_in) < 5.0 / 60.0
+    assert D == pytest.approx(abs(t_out - t_in), abs=1e-6)

@@ -235,3 +235,32 @@ def test_box_between_chord_plane_and_actual_path(level):
     hit = np.array([oracle.shadow(sc, (0.0, 0.0, 0.0), oracle.solar(2019, 6, 21, t, -4.0, LAT, LON)[:3]) for t in tt])
     assert hit.any() and not hit[0] and not hit[-1]
     assert D == pytest.approx(hit.sum() / 1200.0, abs=2.0 / 1200.0)
+
+
+def test_thin_pole_run_matches_azimuth_root_find():
+    """A 2 cm square pole 200 m from a ground point, tall enough to block
+    the sun at any elevation it has then, shadows the point for about a
+    second: exactly while the sun's azimuth lies between the azimuths of the
+    pole's two silhouette corners as seen from the point.  Both ends come
+    from brentq on the solar azimuth alone; the 5-second scan must find the
+    run and match them."""
+    t_mid = 607.0 + 2.5 / 60.0                      # between two scan instants
+    s = oracle.solar(2019, 6, 21, t_mid, -4.0, LAT, LON)
+    az = math.radians(s[4])
+    c = 200.0 * np.array([math.sin(az), math.cos(az)])
+    h = 200.0 * math.tan(math.radians(s[3])) + 40.0
+    half = 0.01
+    sc = box_scene([(c[0] - half, c[1] - half, c[0] + half, c[1] + half, h)])
+    corners = np.array(sc.footprint(0), np.float64)
+    az_c = np.arctan2(corners[:, 0], corners[:, 1])          # azimuths of the corners from the point
+    lo, hi = az_c.min(), az_c.max()
+
+    def sun_az(t):
+        return math.radians(oracle.solar(2019, 6, 21, t, -4.0, LAT, LON)[4])
+    t_in = brentq(lambda t: sun_az(t) - lo, t_mid - 1.0, t_mid + 1.0, xtol=1e-12)
+    t_out = brentq(lambda t: sun_az(t) - hi, t_mid - 1.0, t_mid + 1.0, xtol=1e-12)
+    expect = abs(t_out - t_in)
+    span = window_span(6, 21, -4.0, 480.0, 1080.0)
+    D = oracle.continuous_true(sc, pts([[0.0, 0.0, 0.0]]), span)["minutes"][0, 0]
+    assert 0.0 < expect < 5.0 / 60.0
+    assert D == pytest.approx(expect, abs=1e-6)
