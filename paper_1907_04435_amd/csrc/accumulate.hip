@@ -85,6 +85,12 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
     float run = 0.f, best = 0.f;
     int bin = K > 0 ? (ld(samples).tag & kBinMask) : 0;
     uint32_t word = 0;
+    // Occluder cache, one per wave: the prism that blocked the most lanes
+    // at the previous instant is tested first (and not again by the walk);
+    // lanes it blocks are done, and a wave whose every live lane it blocks
+    // skips the traversal.  A blocked ray is blocked whichever prism is
+    // found first, so the predicate is unchanged.
+    int c_prim = -1, c_voff = 0, c_m = 0;
     for (int k = 0; k < K; ++k) {
         const SampleConst s = ld(samples + k);
         const int sbin = s.tag & kBinMask;
@@ -105,6 +111,7 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
         if (s.tag & kDayStart) run = 0.f;
         const bool back = q.own >= 0 && fmaf(q.nx, s.dx, q.ny * s.dy) <= 0.f;
         uint64_t hitm = 0;
+        int b_prim = -1, b_voff = 0, b_m = 0, b_cnt = 0;   // this instant's best blocker
         if (nodes_g != nullptr) {
             const float ox = -q.px * s.ix, oy = -q.py * s.iy, oz = -q.pz * s.iz;
             // slab test: each axis's entry and exit by min / max (no selects
@@ -118,7 +125,12 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
                 const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), tfz);
                 return le_mask(tn, tf);
             };
+            bool cached_seen = false;
             auto leaf = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
+                if (prim == c_prim) {
+                    if (cached_seen) return 0;
+                    cached_seen = true;
+                }
                 const bool go = lane_in(want & ballot(prim != q.own));
                 if constexpr (kCount) {
                     wk.prism += go ? 1u : 0u;
@@ -128,12 +140,25 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
                 const bool t = go & ray_prism(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, s.dx, s.dy, s.dz);
                 const uint64_t tm = ballot(t);
                 hitm |= tm;
+                const int cnt = __builtin_popcountll(tm);
+                if (cnt > b_cnt) {
+                    b_cnt = cnt;
+                    b_prim = prim;
+                    b_voff = voff;
+                    b_m = m;
+                }
                 return tm;  // a blocked ray needs no further test
             };
             auto key = [&](float x0, float y0, float x1, float y1, float z1) {
                 return fmaf(x0 + x1, s.dx, fmaf(y0 + y1, s.dy, z1 * s.dz));
             };
-            packet_traverse<kCount>(nodes, stack, ballot(valid && !back), bt, leaf, key, wk);
+            uint64_t live = ballot(valid && !back);
+            if (c_prim >= 0 && live) live &= ~leaf(c_prim, c_voff, c_m, live);
+            if (live) packet_traverse<kCount>(nodes, stack, live, bt, leaf, key, wk);
+            // keep a blocker only while it blocks some lane
+            c_prim = uniform(b_cnt > 0 ? b_prim : -1);
+            c_voff = uniform(b_voff);
+            c_m = uniform(b_m);
         }
         if constexpr (kCount) wk.units += valid ? 1u : 0u;
         const bool sh = valid && (back || lane_in(hitm));
