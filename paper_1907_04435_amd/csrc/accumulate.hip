@@ -343,13 +343,29 @@ __device__ __forceinline__ bool roof_covered(cNode *nodes, StackEntry *stack, cf
     return lane_in(covm);
 }
 
+// Work of one accrual launch: units (64-point tile, part) in tile-major
+// order, a part being one output bin's run of the launch's segments
+// [j0, j1) -- or all of them, when a bin has two runs in the launch.  The
+// units are cut into eight contiguous ranges, one per XCD (block b runs on
+// XCD b mod 8), each with its own counter; a wave takes one unit per
+// atomic from its XCD's range, then from the others'.  Neighbouring tiles
+// share hierarchy nodes and prisms in their XCD's L2, and the waves stay
+// resident until the work runs out, so no SIMD idles behind a long tile.
+struct Sched {
+    const int32_t *part_start;  // [n_parts + 1] first segment of each part (clipped to [j0, j1)), or null: one part
+    uint32_t *grab;             // eight counters, kGrabStride words apart, zero at launch
+    uint32_t n_tiles;
+    uint32_t n_parts;
+};
+constexpr int kGrabStride = 32;  // one 128-byte line per counter
+
 // Eight waves per SIMD: the kernel fits in 64 VGPRs (the compiler would
 // settle for fewer waves otherwise), which hides more of the scalar-load
 // and compare-chain latency of the traversal loop.
 template <bool kCount>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_accrual(
     const Node *nodes_g, const SegNode *snodes_g, int n_nodes, const int32_t *voff_g, const float4 *verts_g,
-    const float *height_g, const SegConst *segs_g, int j0, int j1, PointArgs P, BinOut O, SpillArgs S,
+    const float *height_g, const SegConst *segs_g, int j0, int j1, Sched W, PointArgs P, BinOut O, SpillArgs S,
     uint64_t *work)
 {
     Work wk{0, 0, 0, 0, 0, 0, 0};
@@ -358,57 +374,84 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     cfloat *height = (cfloat *)height_g;
     cSeg *segs = (cSeg *)segs_g;
     __shared__ StackEntry s_stack[kWaves][kStackDepth];
-    // the outputs are needed only when a bin ends: parked in LDS so their
-    // pointers hold no scalar registers through the traversal loop
+    // the outputs are needed only when a bin ends, the schedule once per
+    // unit: parked in LDS so their pointers hold no scalar registers
+    // through the traversal loop
     __shared__ int s_O[sizeof(BinOut) / 4];
     __shared__ int s_S[sizeof(SpillArgs) / 4];
+    __shared__ int s_W[sizeof(Sched) / 4];
+    __shared__ int s_P[sizeof(PointArgs) / 4];
     if (threadIdx.x == 0) {
         lds_park((lds_int *)s_O, O);
         lds_park((lds_int *)s_S, S);
+        lds_park((lds_int *)s_W, W);
+        lds_park((lds_int *)s_P, P);
     }
     __syncthreads();
     StackEntry *stack = s_stack[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
-    const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
-    const int64_t i = wave * 64 + lane;
-    const bool valid = i < P.n;
-    const int64_t n = P.n;
-    const LanePoint q = load_point(P, i, valid);
-    const bool covered = roof_covered(nodes_g ? nodes : nullptr, stack, verts, height, q, valid);
+    const int xcd = blockIdx.x & 7;
+    for (int k = 0; k < 8; ++k) {
+        const int x = (xcd + k) & 7;
+        for (;;) {
+            const Sched Wd = lds_uniform<Sched>((lds_int *)s_W);
+            const uint32_t n_units = Wd.n_tiles * Wd.n_parts;
+            const uint32_t lo = (uint32_t)((uint64_t)n_units * x >> 3);
+            const uint32_t hi = (uint32_t)((uint64_t)n_units * (x + 1) >> 3);
+            uint32_t got = 0;
+            if (lane == 0) got = atomicAdd(Wd.grab + kGrabStride * x, 1u);
+            got = (uint32_t)__builtin_amdgcn_readlane((int)got, 0);
+            if (got >= hi - lo) break;
+            const uint32_t u = lo + got;
+            // the division runs on the vector unit: its result is made
+            // scalar again for the scalar loads it addresses
+            const uint32_t tile = (uint32_t)uniform((int)(u / Wd.n_parts)), part = u - tile * Wd.n_parts;
+            const int ja = uniform(Wd.part_start ? max(ld((cint *)Wd.part_start + part), j0) : j0);
+            const int jb = uniform(Wd.part_start ? min(ld((cint *)Wd.part_start + part + 1), j1) : j1);
+            const PointArgs Pd = lds_uniform<PointArgs>((lds_int *)s_P);
+            const int64_t n = Pd.n;
+            const int64_t i = (int64_t)tile * 64 + lane;
+            const bool valid = i < n;
+            const LanePoint q = load_point(Pd, i, valid);
+            const bool covered = roof_covered(nodes_g ? nodes : nullptr, stack, verts, height, q, valid);
 
-    int cnt = 0;
-    double mins = 0.0;  // per-lane FP64: long spans sum thousands of segment measures
-    int bin = j1 > j0 ? ld(segs + j0).bin : 0;
-    bool fresh = lds_uniform<BinOut>((lds_int *)s_O).fresh_first != 0;
-    for (int j = j0; j < j1; ++j) {
-        const SegConst g = ld(segs + j);
-        if (g.bin != bin) {
-            const BinOut Ob = lds_uniform<BinOut>((lds_int *)s_O);
-            if (valid) put_bin(Ob, (int64_t)bin * n + i, fresh, cnt, mins);
-            cnt = 0;
-            mins = 0.0;
-            bin = g.bin;
-            fresh = Ob.fresh_rest != 0;
+            int cnt = 0;
+            double mins = 0.0;  // per-lane FP64: long spans sum thousands of segment measures
+            int bin = jb > ja ? ld(segs + ja).bin : 0;
+            const BinOut O0 = lds_uniform<BinOut>((lds_int *)s_O);
+            bool fresh = (ja == j0 ? O0.fresh_first : O0.fresh_rest) != 0;
+            for (int j = ja; j < jb; ++j) {
+                const SegConst g = ld(segs + j);
+                if (g.bin != bin) {
+                    const BinOut Ob = lds_uniform<BinOut>((lds_int *)s_O);
+                    if (valid) put_bin(Ob, (int64_t)bin * n + i, fresh, cnt, mins);
+                    cnt = 0;
+                    mins = 0.0;
+                    bin = g.bin;
+                    fresh = Ob.fresh_rest != 0;
+                }
+                Union4 U;
+                bool ov;
+                const SegSrc src{snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr,
+                                 (cint *)voff_g, 0};
+                accrue_segment<kCount>(src, stack, verts, height, g, q, valid && !covered, 0.f, g.theta, U, ov, wk);
+                if constexpr (kCount) {
+                    wk.units += valid ? 1u : 0u;
+                    wk.spills += (valid && ov) ? 1u : 0u;
+                }
+                const SegConst gm = reload(segs, j);
+                if (covered && valid) {
+                    mins += (double)gm.dt;
+                    cnt += gm.ns_all;
+                } else if (!ov) {
+                    measure(U, gm, 0.f, gm.theta, true, mins, cnt);
+                }
+                if (ballot(valid && ov))
+                    spill_push(lds_uniform<SpillArgs>((lds_int *)s_S), valid && ov, i, j, 0.f, gm.theta);
+            }
+            if (valid && jb > ja) put_bin(lds_uniform<BinOut>((lds_int *)s_O), (int64_t)bin * n + i, fresh, cnt, mins);
         }
-        Union4 U;
-        bool ov;
-        const SegSrc src{snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr,
-                         (cint *)voff_g, 0};
-        accrue_segment<kCount>(src, stack, verts, height, g, q, valid && !covered, 0.f, g.theta, U, ov, wk);
-        if constexpr (kCount) {
-            wk.units += valid ? 1u : 0u;
-            wk.spills += (valid && ov) ? 1u : 0u;
-        }
-        const SegConst gm = reload(segs, j);
-        if (covered && valid) {
-            mins += (double)gm.dt;
-            cnt += gm.ns_all;
-        } else if (!ov) {
-            measure(U, gm, 0.f, gm.theta, true, mins, cnt);
-        }
-        if (ballot(valid && ov)) spill_push(lds_uniform<SpillArgs>((lds_int *)s_S), valid && ov, i, j, 0.f, gm.theta);
     }
-    if (valid && j1 > j0) put_bin(lds_uniform<BinOut>((lds_int *)s_O), (int64_t)bin * n + i, fresh, cnt, mins);
     if constexpr (kCount) flush_work(wk, work);
 }
 
@@ -1149,11 +1192,32 @@ static BinOut bin_out(const DevicePath &p, int j0, bool store, int32_t *counts, 
     return BinOut{counts, minutes, minutes64, first ? 1 : 0, store ? 1 : 0, scale, 0};
 }
 
+// The parts of an accrual launch over [j0, j1): its bin runs (a slice of
+// p.runs) when every bin has one run in it, else one part (null).
+static const int32_t *accrual_parts(const DevicePath &p, int j0, int j1, uint32_t &n_parts)
+{
+    n_parts = 1;
+    if (p.runs == nullptr || p.run_start.size() < 2 || j1 <= j0) return nullptr;
+    const auto &rs = p.run_start;
+    const int r0 = (int)(std::upper_bound(rs.begin(), rs.end(), j0) - rs.begin()) - 1;
+    const int r1 = (int)(std::upper_bound(rs.begin(), rs.end(), j1 - 1) - rs.begin()) - 1;
+    if (r1 <= r0) return nullptr;
+    std::vector<char> seen(std::max(p.n_bins, 1), 0);
+    for (int r = r0; r <= r1; ++r) {
+        const int b = p.seg_bin[rs[r]];
+        if (seen[b]) return nullptr;
+        seen[b] = 1;
+    }
+    n_parts = (uint32_t)(r1 - r0 + 1);
+    return p.runs + r0;
+}
+
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
                          int32_t *counts, float *minutes, double *minutes64, float *longest, uint64_t *work,
-                         bool store, int32_t seg_per_launch, SpillQueue &q, Scratch &scr, hipStream_t st,
+                         bool store, const AccrualLaunch &L, SpillQueue &q, Scratch &scr, hipStream_t st,
                          std::string &err)
 {
+    const int32_t seg_per_launch = L.segments_per_launch;
     if (pts.n == 0) return SA_OK;
     const int64_t waves = (pts.n + 63) / 64;
     const int64_t grid = (waves + kWaves - 1) / kWaves;
@@ -1204,8 +1268,18 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
         if (rc != SA_OK) return rc;
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters);
         SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
-        hipLaunchKernelGGL(work ? k_accrual<true> : k_accrual<false>, dim3((unsigned)grid), dim3(kThreads), 0, st,
-                           nodes, views, s.n_nodes, s.voff, s.verts, s.height, p.segs, (int)j0, j1, P,
+        Sched W{nullptr, q.grab, (uint32_t)waves, 1u};
+        W.part_start = accrual_parts(p, (int)j0, j1, W.n_parts);
+        if ((uint64_t)W.n_tiles * W.n_parts >= (1ull << 31)) {
+            W.part_start = nullptr;  // one part per tile keeps the unit count in range
+            W.n_parts = 1;
+        }
+        const int64_t units = (int64_t)W.n_tiles * W.n_parts;
+        const int64_t blocks = std::min<int64_t>(L.grid_blocks, (units + kWaves - 1) / kWaves);
+        rc = fill_u32(q.grab, 8 * kGrabStride, 0u, st, err);
+        if (rc != SA_OK) return rc;
+        hipLaunchKernelGGL(work ? k_accrual<true> : k_accrual<false>, dim3((unsigned)blocks), dim3(kThreads), 0, st,
+                           nodes, views, s.n_nodes, s.voff, s.verts, s.height, p.segs, (int)j0, j1, W, P,
                            bin_out(p, (int)j0, store, counts, minutes, minutes64, scale), S, work);
         SA_CHECK_LAUNCH("accrual kernel");
         rc = run_spill(s, p, views, (int)j0, P, scale, counts, minutes, minutes64, q, st, err);

@@ -28,6 +28,7 @@ struct sa_ctx {
     sa::Scratch scratch_w;        // per-bin weights of a region score
     uint32_t sam_stamp = 0;       // the last segment stamp written into it
     sa_launch launch = {0, 0, 1, 0};  // tuning choices (sa_set_launch)
+    int32_t n_cu = 256;           // compute units of the device
     void *noalloc = nullptr;      // this device's fixed scratch (device address), or null
     std::string noalloc_err;      // why it is null
 };
@@ -158,6 +159,10 @@ extern "C" {
 
 const char *sa_version(void) { return "libsa 0.1 (gfx950)"; }
 
+// Device words of a context's counters: the spill queue's (lengths,
+// overflow flag), then the accrual launch's eight work counters.
+constexpr int kCounterWords = 64 + 8 * 32;
+
 sa_status sa_create(int32_t device, void *hip_stream, sa_ctx **out)
 {
     if (!out) return SA_ERR_INVALID_ARG;
@@ -172,11 +177,15 @@ sa_status sa_create(int32_t device, void *hip_stream, sa_ctx **out)
     c->spill.capacity = kSpillCapacity;
     if (hipMalloc((void **)&c->spill.entries[0], sizeof(int4) * kSpillCapacity) != hipSuccess ||
         hipMalloc((void **)&c->spill.entries[1], sizeof(int4) * kSpillCapacity) != hipSuccess ||
-        hipMalloc((void **)&c->spill.counters, sizeof(uint32_t) * 4) != hipSuccess ||
-        hipMemset(c->spill.counters, 0, sizeof(uint32_t) * 4) != hipSuccess) {
+        hipMalloc((void **)&c->spill.counters, sizeof(uint32_t) * kCounterWords) != hipSuccess ||
+        hipMemset(c->spill.counters, 0, sizeof(uint32_t) * kCounterWords) != hipSuccess) {
         sa_destroy(c);
         return SA_ERR_OOM;
     }
+    c->spill.grab = c->spill.counters + 64;  // 256 B in, eight 128 B lines
+    int n_cu = 0;
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && n_cu > 0)
+        c->n_cu = n_cu;
     attach_noalloc_scratch(c);
     *out = c;
     return SA_OK;
@@ -202,7 +211,8 @@ sa_status sa_set_launch(sa_ctx *ctx, const sa_launch *l)
 {
     if (!ctx || !l) return SA_ERR_INVALID_ARG;
     if (l->accrual_segments_per_launch < 0 || l->batched_grid_blocks < 0 || l->batched_grid_blocks > (1 << 20) ||
-        l->batched_tiles_per_grab < 0 || l->batched_tiles_per_grab > 1024)
+        l->batched_tiles_per_grab < 0 || l->batched_tiles_per_grab > 1024 || l->accrual_grid_blocks < 0 ||
+        l->accrual_grid_blocks > (1 << 20))
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_set_launch: value out of range");
     ctx->launch = *l;
     if (ctx->launch.batched_tiles_per_grab == 0) ctx->launch.batched_tiles_per_grab = 1;
@@ -660,6 +670,9 @@ sa_status path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, s
     }
     for (int b = 0; b < n_bins; ++b) contiguous = contiguous && seen[b];
     p->d.bins_contiguous = contiguous;
+    for (size_t j = 0; j < segs.size(); ++j)
+        if (j == 0 || segs[j - 1].bin != segs[j].bin) p->d.run_start.push_back((int32_t)j);
+    p->d.run_start.push_back((int32_t)segs.size());
     if (!merged) {
         p->d.seg_host = std::move(seg_host);
         p->d.sample_t.assign(in->t_min, in->t_min + in->n_samples);
@@ -684,6 +697,12 @@ sa_status path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, s
         e = hipMalloc((void **)&p->d.segs, sizeof(sa::SegConst) * segs.size());
         if (e == hipSuccess)
             e = hipMemcpy(p->d.segs, segs.data(), sizeof(sa::SegConst) * segs.size(), hipMemcpyHostToDevice);
+    }
+    if (e == hipSuccess && !segs.empty()) {
+        const size_t nr = p->d.run_start.size();
+        e = hipMalloc((void **)&p->d.runs, sizeof(int32_t) * nr);
+        if (e == hipSuccess)
+            e = hipMemcpy(p->d.runs, p->d.run_start.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
         sa_path_destroy(p);
@@ -725,6 +744,7 @@ void sa_path_destroy(sa_path *path)
     (void)hipFree(path->d.samples);
     (void)hipFree(path->d.sam_slices);
     (void)hipFree(path->d.segs);
+    (void)hipFree(path->d.runs);
     delete path;
 }
 
@@ -756,6 +776,14 @@ static sa_status clear_outputs(sa_ctx *ctx, uint32_t flags, int64_t count, int32
     if (rc == SA_OK && minutes64) rc = sa::fill_u32(minutes64, 2 * count, 0u, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "clear outputs: " + err);
     return SA_OK;
+}
+
+// The accrual launch choices of a context: a persistent grid of eight
+// blocks (32 waves) per compute unit unless tuned otherwise.
+static sa::AccrualLaunch accrual_launch(const sa_ctx *ctx)
+{
+    const int64_t g = ctx->launch.accrual_grid_blocks > 0 ? ctx->launch.accrual_grid_blocks : 8ll * ctx->n_cu;
+    return sa::AccrualLaunch{ctx->launch.accrual_segments_per_launch, g};
 }
 
 // The accrual form stores each bin once (no clearing) unless asked to add
@@ -796,7 +824,7 @@ sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts
                                 opts->work, ctx->stream, err);
     else
         rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->minutes64,
-                                opts->longest, opts->work, store, ctx->launch.accrual_segments_per_launch, ctx->spill,
+                                opts->longest, opts->work, store, accrual_launch(ctx), ctx->spill,
                                 ctx->scratch_seg, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate: " + err);
     return SA_OK;
@@ -853,7 +881,7 @@ sa_status sa_accumulate_noalloc(sa_ctx *ctx, const sa_scene *scene, const sa_poi
         fixed.bytes = (size_t)SA_NOALLOC_SCRATCH_BYTES;
         fixed.fixed = true;
         rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->minutes64,
-                                opts->longest, opts->work, store, ctx->launch.accrual_segments_per_launch, ctx->spill,
+                                opts->longest, opts->work, store, accrual_launch(ctx), ctx->spill,
                                 fixed, ctx->stream, err);
     }
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate_noalloc: " + err);

@@ -137,6 +137,8 @@ struct DevicePath {
     std::vector<int32_t> day_seg_off;  // host: first segment of each day, [n_days + 1]
     std::vector<int32_t> seg_bin;      // host: output bin of each segment
     bool bins_contiguous = false;      // host: every bin has segments, all in one run
+    std::vector<int32_t> run_start;    // host: first segment of each run of equal bins, then n_segs
+    int32_t *runs = nullptr;           // device copy of run_start
     std::vector<double> bin_span;      // host: daylight minutes of each output bin
     bool merged = false;               // host: segments merged into direction-graph edges
     // host, for the raster form: each segment's knot directions, times, its
@@ -175,7 +177,16 @@ struct Scratch {
 struct SpillQueue {
     int4 *entries[2] = {nullptr, nullptr};  // (point, segment, w0 bits, w1 bits)
     uint32_t *counters = nullptr;           // [0],[1] queue lengths, [2] overflow flag
+    uint32_t *grab = nullptr;               // the accrual launch's work counters (eight, 128 B apart)
     int32_t capacity = 0;
+};
+
+// Launch choices of the accrual form: the most segments one launch covers
+// (0: as many as the view budget allows) and the blocks of its persistent
+// launch.
+struct AccrualLaunch {
+    int32_t segments_per_launch;
+    int64_t grid_blocks;
 };
 
 sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
@@ -183,11 +194,10 @@ sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const Points
                          uint64_t *work, hipStream_t st, std::string &err);
 // store: outputs need no clearing (no SA_FLAG_ADD and p.bins_contiguous):
 // each bin is stored by the launch holding its first segment.
-// seg_per_launch > 0 caps the segments one launch covers (a tuning choice:
-// the per-segment views a launch reads).
+// L: the launch choices (segments per launch, persistent grid size).
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
                          float scale, int32_t *counts, float *minutes, double *minutes64, float *longest,
-                         uint64_t *work, bool store, int32_t seg_per_launch, SpillQueue &q, Scratch &scr,
+                         uint64_t *work, bool store, const AccrualLaunch &L, SpillQueue &q, Scratch &scr,
                          hipStream_t st, std::string &err);
 // grad = (add ? grad : 0) + scale * d(sum dl * minutes)/dH, accumulated in
 // FP64 in acc (grown to n_b doubles as needed).

@@ -38,6 +38,36 @@ def test_accrual_segments_per_launch(ctx):
         assert d <= 1e-3
 
 
+def test_accrual_grid_blocks(ctx):
+    """The persistent accrual launch at any size -- one block, blocks not a
+    multiple of the eight XCDs, more blocks than units -- gives the same
+    counts and minutes (each (tile, bin) unit is computed by one wave
+    whichever wave takes it), also with bins that interleave (one part
+    per tile) and with several launches per path."""
+    w = make_c2(n_ground=20_000, n_facade=20_000)
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    dp = sa.DevicePoints.from_workload(w.points)
+    span = w.span
+    paths = {"days": sa.Path(ctx, sa.sunpath_for_span(span, 30.0))}
+    inter = type(span)(span.lat, span.lon, span.days, span.step_min, [0, 1, 0])
+    paths["interleaved bins"] = sa.Path(ctx, sa.sunpath_for_span(inter, 30.0))
+    for name, path in paths.items():
+        res = {}
+        for gb, per in ((0, 0), (1, 0), (13, 0), (100_000, 0), (0, 5)):
+            ctx.set_launch(accrual_grid_blocks=gb, accrual_segments_per_launch=per)
+            c, m, _ = sa.accumulate(ctx, sc, dp, path, sa.SA_ACCRUAL)
+            ctx.sync()
+            res[(gb, per)] = (c.cpu().numpy(), m.cpu().numpy())
+        ctx.set_launch()
+        c0, m0 = res[(0, 0)]
+        assert c0.sum() > 0
+        for key, (c, m) in res.items():
+            np.testing.assert_array_equal(c, c0)
+            d = np.abs(m - m0).max()
+            say(f"  {name}: grid {key[0]}, {key[1]} segments per launch: counts equal, max |minutes diff| {d:.2e}")
+            assert d <= 1e-3
+
+
 def test_batched_grid_and_grab(ctx):
     import torch
     w = make_c3(n_var=12, n_per_var=3000)
@@ -66,4 +96,6 @@ def test_bad_launch_values(ctx):
         ctx.set_launch(accrual_segments_per_launch=-1)
     with pytest.raises(sa.SAError):
         ctx.set_launch(batched_tiles_per_grab=5000)
+    with pytest.raises(sa.SAError):
+        ctx.set_launch(accrual_grid_blocks=-3)
     assert ctx.get_launch()["batched_tiles_per_grab"] == 1
