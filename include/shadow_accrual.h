@@ -87,9 +87,10 @@ typedef struct {
                                             opts->grid_blocks is 0; 0 = 2048 */
     int32_t batched_tiles_per_grab;      /* sa_accumulate_batched: consecutive 64-point tiles a wave takes
                                             from the work queue per atomic; 0 = 1 */
-    int32_t accrual_grid_blocks;         /* accrual form: blocks (of 256 threads) of its persistent launch,
-                                            whose waves take (64-point tile, bin) units from a work
-                                            counter per XCD; 0 = 8 per compute unit */
+    int32_t tile_grid_blocks;            /* sa_accumulate (both forms) and sa_building_contribution:
+                                            blocks (of 256 threads) of their persistent launches, whose
+                                            waves take (64-point tile, bin) units from a work counter
+                                            per XCD; 0 = as many as the device holds at once */
 } sa_launch;
 /* Errors: INVALID_ARG (negative or out-of-range values). */
 sa_status sa_set_launch(sa_ctx *ctx, const sa_launch *launch);

@@ -75,7 +75,7 @@ class sa_sam_opts(C.Structure):
 
 class sa_launch(C.Structure):
     _fields_ = [("accrual_segments_per_launch", C.c_int32), ("batched_grid_blocks", C.c_int32),
-                ("batched_tiles_per_grab", C.c_int32), ("accrual_grid_blocks", C.c_int32)]
+                ("batched_tiles_per_grab", C.c_int32), ("tile_grid_blocks", C.c_int32)]
 
 
 class sa_accum_opts(C.Structure):
@@ -258,12 +258,12 @@ class Context:
         _check(self, lib().sa_sync(self.handle))
 
     def set_launch(self, accrual_segments_per_launch=0, batched_grid_blocks=0, batched_tiles_per_grab=0,
-                   accrual_grid_blocks=0):
+                   tile_grid_blocks=0):
         """Launch choices (speed only; see sa_set_launch)."""
         _check(self, lib().sa_set_launch(self.handle, C.byref(sa_launch(int(accrual_segments_per_launch),
                                                                         int(batched_grid_blocks),
                                                                         int(batched_tiles_per_grab),
-                                                                        int(accrual_grid_blocks)))))
+                                                                        int(tile_grid_blocks)))))
 
     def get_launch(self) -> dict:
         l = sa_launch()

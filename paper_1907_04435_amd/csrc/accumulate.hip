@@ -57,12 +57,85 @@ __device__ __forceinline__ void flush_work(const Work &w, uint64_t *work)
     }
 }
 
+// ------------------------------------------------------ persistent launches
+// The per-tile kernels run as persistent launches: their work is a list of
+// units (64-point tile, part) in tile-major order, a part being one output
+// bin's run of the launch's items (segments or instants) -- or all of
+// them, when a unit has to see several bins.  The units are cut into eight
+// contiguous ranges, one per XCD (block b runs on XCD b mod 8), each with
+// its own counter; a wave takes one unit per atomic from its XCD's range,
+// then from the others'.  Neighbouring tiles share hierarchy nodes and
+// prisms in their XCD's L2, and the waves stay resident until the work
+// runs out: no SIMD idles behind a long tile, and the launch's tail is one
+// unit long.
+struct Sched {
+    const int32_t *part_start;  // [n_parts + 1] first item of each part (clipped to the launch), or null: one part
+    uint32_t *grab;             // eight counters, kGrabStride words apart, zero at launch
+    uint32_t n_tiles;
+    uint32_t n_parts;
+};
+constexpr int kGrabStride = 32;  // one 128-byte line per counter
+
+struct Unit {
+    uint32_t tile;
+    int a, b;  // the unit's items [a, b)
+};
+
+// The next unit of the launch whose Sched is parked at s_W, for items
+// [a0, a1); false when none is left.  k counts the XCD ranges already
+// drained (0 at the start).  Callers pass the unit's bounds through
+// uniform(): set inside this loop, they would otherwise count as
+// per-lane values and could not address scalar loads.
+__device__ __forceinline__ bool next_unit(const lds_int *s_W, int a0, int a1, int &k, Unit &un)
+{
+    const Sched W = lds_uniform<Sched>(s_W);
+    const uint32_t n_units = W.n_tiles * W.n_parts;
+    const int xcd = blockIdx.x & 7;
+    for (; k < 8; ++k) {
+        const int x = (xcd + k) & 7;
+        const uint32_t lo = (uint32_t)((uint64_t)n_units * x >> 3);
+        const uint32_t hi = (uint32_t)((uint64_t)n_units * (x + 1) >> 3);
+        uint32_t got = 0;
+        if ((threadIdx.x & 63) == 0) got = atomicAdd(W.grab + kGrabStride * x, 1u);
+        got = (uint32_t)__builtin_amdgcn_readlane((int)got, 0);
+        if (got < hi - lo) {
+            const uint32_t u = lo + got;
+            // the division runs on the vector unit: its result is made
+            // scalar again for the scalar loads it addresses
+            const uint32_t tile = (uint32_t)uniform((int)(u / W.n_parts));
+            const uint32_t part = u - tile * W.n_parts;
+            un.tile = tile;
+            un.a = W.part_start ? max(ld((cint *)W.part_start + part), a0) : a0;
+            un.b = W.part_start ? min(ld((cint *)W.part_start + part + 1), a1) : a1;
+            return true;
+        }
+    }
+    return false;
+}
+
+// Outputs of the sampled form (parked in LDS by the kernel).
+struct SampOut {
+    int32_t *counts;
+    float *minutes;
+    uint32_t *bits;
+    float *longest;
+    float scale;
+    int32_t pad;
+};
+
+// Adds a unit's sums for one bin (outputs cleared beforehand; a bin of a
+// tile belongs to one unit).
+__device__ __forceinline__ void sampled_put(const SampOut &O, int64_t o, int cnt, float mins, float best)
+{
+    if (O.counts) O.counts[o] += cnt;
+    if (O.minutes) O.minutes[o] += mins * O.scale;
+    if (O.longest) O.longest[o] = fmaxf(O.longest[o], best * O.scale);
+}
+
 template <bool kBits, bool kCount>
 __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const float4 *verts_g,
                                                       const float *height_g, const SampleConst *samples_g,
-                                                      int K, PointArgs P, float scale, int32_t *counts,
-                                                      float *minutes, uint32_t *bits, float *longest,
-                                                      uint64_t *work)
+                                                      int K, Sched W, PointArgs P, SampOut O, uint64_t *work)
 {
     Work wk{0, 0, 0, 0, 0, 0, 0};
     cNode *nodes = (cNode *)nodes_g;
@@ -70,119 +143,123 @@ __global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const
     cfloat *height = (cfloat *)height_g;
     cSample *samples = (cSample *)samples_g;
     __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    // schedule, points and outputs parked in LDS: read once per unit (per
+    // bin for the outputs), they hold no scalar registers in the loop
+    __shared__ int s_W[sizeof(Sched) / 4];
+    __shared__ int s_P[sizeof(PointArgs) / 4];
+    __shared__ int s_O[sizeof(SampOut) / 4];
+    if (threadIdx.x == 0) {
+        lds_park((lds_int *)s_W, W);
+        lds_park((lds_int *)s_P, P);
+        lds_park((lds_int *)s_O, O);
+    }
+    __syncthreads();
     StackEntry *stack = s_stack[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
-    const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
-    const int64_t i = wave * 64 + lane;
-    const bool valid = i < P.n;
-    const LanePoint q = load_point(P, i, valid);
-    const int64_t n = P.n;
+    int kx = 0;
+    Unit un;
+    while (next_unit((lds_int *)s_W, 0, K, kx, un)) {
+        const PointArgs Pd = lds_uniform<PointArgs>((lds_int *)s_P);
+        const int64_t n = Pd.n;
+        const int64_t i = (int64_t)un.tile * 64 + lane;
+        const bool valid = i < n;
+        const LanePoint q = load_point(Pd, i, valid);
+        const int ka = uniform(un.a), kb = uniform(un.b);
 
-    int cnt = 0;
-    float mins = 0.f;
-    // continuous shadow: the current run of shadowed instants and the
-    // longest run of the bin so far (minutes); a run never crosses a day
-    float run = 0.f, best = 0.f;
-    int bin = K > 0 ? (ld(samples).tag & kBinMask) : 0;
-    uint32_t word = 0;
-    // Occluder cache, one per wave: the prism that blocked the most lanes
-    // at the previous instant is tested first (and not again by the walk);
-    // lanes it blocks are done, and a wave whose every live lane it blocks
-    // skips the traversal.  A blocked ray is blocked whichever prism is
-    // found first, so the predicate is unchanged.
-    int c_prim = -1, c_voff = 0, c_m = 0;
-    for (int k = 0; k < K; ++k) {
-        const SampleConst s = ld(samples + k);
-        const int sbin = s.tag & kBinMask;
-        if (sbin != bin) {
-            if (valid) {
-                if (counts) counts[(int64_t)bin * n + i] += cnt;
-                if (minutes) minutes[(int64_t)bin * n + i] += mins * scale;
-                if (longest) {
-                    float &o = longest[(int64_t)bin * n + i];
-                    o = fmaxf(o, best * scale);
-                }
+        int cnt = 0;
+        float mins = 0.f;
+        // continuous shadow: the current run of shadowed instants and the
+        // longest run of the bin so far (minutes); a run never crosses a day
+        float run = 0.f, best = 0.f;
+        int bin = kb > ka ? (ld(samples + ka).tag & kBinMask) : 0;
+        uint32_t word = 0;
+        // Occluder cache, one per wave: the prism that blocked the most
+        // lanes at the previous instant is tested first (and not again by
+        // the walk); lanes it blocks are done, and a wave whose every live
+        // lane it blocks skips the traversal.  A blocked ray is blocked
+        // whichever prism is found first, so the predicate is unchanged.
+        int c_prim = -1, c_voff = 0, c_m = 0;
+        for (int k = ka; k < kb; ++k) {
+            const SampleConst s = ld(samples + k);
+            const int sbin = s.tag & kBinMask;
+            if (sbin != bin) {
+                if (valid) sampled_put(lds_uniform<SampOut>((lds_int *)s_O), (int64_t)bin * n + i, cnt, mins, best);
+                cnt = 0;
+                mins = 0.f;
+                best = 0.f;
+                bin = sbin;
             }
-            cnt = 0;
-            mins = 0.f;
-            best = 0.f;
-            bin = sbin;
-        }
-        if (s.tag & kDayStart) run = 0.f;
-        const bool back = q.own >= 0 && fmaf(q.nx, s.dx, q.ny * s.dy) <= 0.f;
-        uint64_t hitm = 0;
-        int b_prim = -1, b_voff = 0, b_m = 0, b_cnt = 0;   // this instant's best blocker
-        if (nodes_g != nullptr) {
-            const float ox = -q.px * s.ix, oy = -q.py * s.iy, oz = -q.pz * s.iz;
-            // slab test: each axis's entry and exit by min / max (no selects
-            // on the direction's signs); every box starts at z = 0, below
-            // the ray's origin, so only its top bounds the ray in z
-            auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
-                const float ax = fmaf(x0, s.ix, ox), bx = fmaf(x1, s.ix, ox);
-                const float ay = fmaf(y0, s.iy, oy), by = fmaf(y1, s.iy, oy);
-                const float tfz = fmaf(z1, s.iz, oz);
-                const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), 0.f);
-                const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), tfz);
-                return le_mask(tn, tf);
-            };
-            bool cached_seen = false;
-            auto leaf = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
-                if (prim == c_prim) {
-                    if (cached_seen) return 0;
-                    cached_seen = true;
-                }
-                const bool go = lane_in(want & ballot(prim != q.own));
-                if constexpr (kCount) {
-                    wk.prism += go ? 1u : 0u;
-                    wk.edges += go ? (uint32_t)m : 0u;
-                    wk.leaves += first_active_lane() ? 1u : 0u;
-                }
-                const bool t = go & ray_prism(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, s.dx, s.dy, s.dz);
-                const uint64_t tm = ballot(t);
-                hitm |= tm;
-                const int cnt = __builtin_popcountll(tm);
-                if (cnt > b_cnt) {
-                    b_cnt = cnt;
-                    b_prim = prim;
-                    b_voff = voff;
-                    b_m = m;
-                }
-                return tm;  // a blocked ray needs no further test
-            };
-            auto key = [&](float x0, float y0, float x1, float y1, float z1) {
-                return fmaf(x0 + x1, s.dx, fmaf(y0 + y1, s.dy, z1 * s.dz));
-            };
-            uint64_t live = ballot(valid && !back);
-            if (c_prim >= 0 && live) live &= ~leaf(c_prim, c_voff, c_m, live);
-            if (live) packet_traverse<kCount>(nodes, stack, live, bt, leaf, key, wk);
-            // keep a blocker only while it blocks some lane
-            c_prim = uniform(b_cnt > 0 ? b_prim : -1);
-            c_voff = uniform(b_voff);
-            c_m = uniform(b_m);
-        }
-        if constexpr (kCount) wk.units += valid ? 1u : 0u;
-        const bool sh = valid && (back || lane_in(hitm));
-        cnt += sh ? 1 : 0;
-        mins += sh ? s.w : 0.f;
-        if (longest) {
+            if (s.tag & kDayStart) run = 0.f;
+            const bool back = q.own >= 0 && fmaf(q.nx, s.dx, q.ny * s.dy) <= 0.f;
+            uint64_t hitm = 0;
+            int b_prim = -1, b_voff = 0, b_m = 0, b_cnt = 0;  // this instant's best blocker
+            if (nodes_g != nullptr) {
+                const float ox = -q.px * s.ix, oy = -q.py * s.iy, oz = -q.pz * s.iz;
+                // slab test: each axis's entry and exit by min / max (no
+                // selects on the direction's signs); every box starts at
+                // z = 0, below the ray's origin, so only its top bounds the
+                // ray in z
+                auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
+                    const float ax = fmaf(x0, s.ix, ox), bx = fmaf(x1, s.ix, ox);
+                    const float ay = fmaf(y0, s.iy, oy), by = fmaf(y1, s.iy, oy);
+                    const float tfz = fmaf(z1, s.iz, oz);
+                    const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), 0.f);
+                    const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), tfz);
+                    return le_mask(tn, tf);
+                };
+                bool cached_seen = false;
+                auto leaf = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
+                    if (prim == c_prim) {
+                        if (cached_seen) return 0;
+                        cached_seen = true;
+                    }
+                    const bool go = lane_in(want & ballot(prim != q.own));
+                    if constexpr (kCount) {
+                        wk.prism += go ? 1u : 0u;
+                        wk.edges += go ? (uint32_t)m : 0u;
+                        wk.leaves += first_active_lane() ? 1u : 0u;
+                    }
+                    const bool t =
+                        go & ray_prism(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, s.dx, s.dy, s.dz);
+                    const uint64_t tm = ballot(t);
+                    hitm |= tm;
+                    const int cnt = __builtin_popcountll(tm);
+                    if (cnt > b_cnt) {
+                        b_cnt = cnt;
+                        b_prim = prim;
+                        b_voff = voff;
+                        b_m = m;
+                    }
+                    return tm;  // a blocked ray needs no further test
+                };
+                auto key = [&](float x0, float y0, float x1, float y1, float z1) {
+                    return fmaf(x0 + x1, s.dx, fmaf(y0 + y1, s.dy, z1 * s.dz));
+                };
+                uint64_t live = ballot(valid && !back);
+                if (c_prim >= 0 && live) live &= ~leaf(c_prim, c_voff, c_m, live);
+                if (live) packet_traverse<kCount>(nodes, stack, live, bt, leaf, key, wk);
+                // keep a blocker only while it blocks some lane
+                c_prim = uniform(b_cnt > 0 ? b_prim : -1);
+                c_voff = uniform(b_voff);
+                c_m = uniform(b_m);
+            }
+            if constexpr (kCount) wk.units += valid ? 1u : 0u;
+            const bool sh = valid && (back || lane_in(hitm));
+            cnt += sh ? 1 : 0;
+            mins += sh ? s.w : 0.f;
             run = sh ? run + s.w : 0.f;
             best = fmaxf(best, run);
-        }
-        if (kBits) {
-            word |= (uint32_t)sh << (k & 31);
-            if ((k & 31) == 31 || k == K - 1) {
-                if (valid) bits[(int64_t)(k >> 5) * n + i] = word;
-                word = 0;
+            if (kBits) {
+                // a unit with bit vectors covers every instant (one part)
+                word |= (uint32_t)sh << (k & 31);
+                if ((k & 31) == 31 || k == kb - 1) {
+                    uint32_t *bits = lds_uniform<SampOut>((lds_int *)s_O).bits;
+                    if (valid) bits[(int64_t)(k >> 5) * n + i] = word;
+                    word = 0;
+                }
             }
         }
-    }
-    if (valid && K > 0) {
-        if (counts) counts[(int64_t)bin * n + i] += cnt;
-        if (minutes) minutes[(int64_t)bin * n + i] += mins * scale;
-        if (longest) {
-            float &o = longest[(int64_t)bin * n + i];
-            o = fmaxf(o, best * scale);
-        }
+        if (valid && kb > ka) sampled_put(lds_uniform<SampOut>((lds_int *)s_O), (int64_t)bin * n + i, cnt, mins, best);
     }
     if constexpr (kCount) flush_work(wk, work);
 }
@@ -343,22 +420,6 @@ __device__ __forceinline__ bool roof_covered(cNode *nodes, StackEntry *stack, cf
     return lane_in(covm);
 }
 
-// Work of one accrual launch: units (64-point tile, part) in tile-major
-// order, a part being one output bin's run of the launch's segments
-// [j0, j1) -- or all of them, when a bin has two runs in the launch.  The
-// units are cut into eight contiguous ranges, one per XCD (block b runs on
-// XCD b mod 8), each with its own counter; a wave takes one unit per
-// atomic from its XCD's range, then from the others'.  Neighbouring tiles
-// share hierarchy nodes and prisms in their XCD's L2, and the waves stay
-// resident until the work runs out, so no SIMD idles behind a long tile.
-struct Sched {
-    const int32_t *part_start;  // [n_parts + 1] first segment of each part (clipped to [j0, j1)), or null: one part
-    uint32_t *grab;             // eight counters, kGrabStride words apart, zero at launch
-    uint32_t n_tiles;
-    uint32_t n_parts;
-};
-constexpr int kGrabStride = 32;  // one 128-byte line per counter
-
 // Eight waves per SIMD: the kernel fits in 64 VGPRs (the compiler would
 // settle for fewer waves otherwise), which hides more of the scalar-load
 // and compare-chain latency of the traversal loop.
@@ -390,67 +451,52 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     __syncthreads();
     StackEntry *stack = s_stack[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
-    const int xcd = blockIdx.x & 7;
-    for (int k = 0; k < 8; ++k) {
-        const int x = (xcd + k) & 7;
-        for (;;) {
-            const Sched Wd = lds_uniform<Sched>((lds_int *)s_W);
-            const uint32_t n_units = Wd.n_tiles * Wd.n_parts;
-            const uint32_t lo = (uint32_t)((uint64_t)n_units * x >> 3);
-            const uint32_t hi = (uint32_t)((uint64_t)n_units * (x + 1) >> 3);
-            uint32_t got = 0;
-            if (lane == 0) got = atomicAdd(Wd.grab + kGrabStride * x, 1u);
-            got = (uint32_t)__builtin_amdgcn_readlane((int)got, 0);
-            if (got >= hi - lo) break;
-            const uint32_t u = lo + got;
-            // the division runs on the vector unit: its result is made
-            // scalar again for the scalar loads it addresses
-            const uint32_t tile = (uint32_t)uniform((int)(u / Wd.n_parts)), part = u - tile * Wd.n_parts;
-            const int ja = uniform(Wd.part_start ? max(ld((cint *)Wd.part_start + part), j0) : j0);
-            const int jb = uniform(Wd.part_start ? min(ld((cint *)Wd.part_start + part + 1), j1) : j1);
-            const PointArgs Pd = lds_uniform<PointArgs>((lds_int *)s_P);
-            const int64_t n = Pd.n;
-            const int64_t i = (int64_t)tile * 64 + lane;
-            const bool valid = i < n;
-            const LanePoint q = load_point(Pd, i, valid);
-            const bool covered = roof_covered(nodes_g ? nodes : nullptr, stack, verts, height, q, valid);
+    int kx = 0;
+    Unit un;
+    while (next_unit((lds_int *)s_W, j0, j1, kx, un)) {
+        const int ja = uniform(un.a), jb = uniform(un.b);
+        const PointArgs Pd = lds_uniform<PointArgs>((lds_int *)s_P);
+        const int64_t n = Pd.n;
+        const int64_t i = (int64_t)un.tile * 64 + lane;
+        const bool valid = i < n;
+        const LanePoint q = load_point(Pd, i, valid);
+        const bool covered = roof_covered(nodes_g ? nodes : nullptr, stack, verts, height, q, valid);
 
-            int cnt = 0;
-            double mins = 0.0;  // per-lane FP64: long spans sum thousands of segment measures
-            int bin = jb > ja ? ld(segs + ja).bin : 0;
-            const BinOut O0 = lds_uniform<BinOut>((lds_int *)s_O);
-            bool fresh = (ja == j0 ? O0.fresh_first : O0.fresh_rest) != 0;
-            for (int j = ja; j < jb; ++j) {
-                const SegConst g = ld(segs + j);
-                if (g.bin != bin) {
-                    const BinOut Ob = lds_uniform<BinOut>((lds_int *)s_O);
-                    if (valid) put_bin(Ob, (int64_t)bin * n + i, fresh, cnt, mins);
-                    cnt = 0;
-                    mins = 0.0;
-                    bin = g.bin;
-                    fresh = Ob.fresh_rest != 0;
-                }
-                Union4 U;
-                bool ov;
-                const SegSrc src{snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr,
-                                 (cint *)voff_g, 0};
-                accrue_segment<kCount>(src, stack, verts, height, g, q, valid && !covered, 0.f, g.theta, U, ov, wk);
-                if constexpr (kCount) {
-                    wk.units += valid ? 1u : 0u;
-                    wk.spills += (valid && ov) ? 1u : 0u;
-                }
-                const SegConst gm = reload(segs, j);
-                if (covered && valid) {
-                    mins += (double)gm.dt;
-                    cnt += gm.ns_all;
-                } else if (!ov) {
-                    measure(U, gm, 0.f, gm.theta, true, mins, cnt);
-                }
-                if (ballot(valid && ov))
-                    spill_push(lds_uniform<SpillArgs>((lds_int *)s_S), valid && ov, i, j, 0.f, gm.theta);
+        int cnt = 0;
+        double mins = 0.0;  // per-lane FP64: long spans sum thousands of segment measures
+        int bin = jb > ja ? ld(segs + ja).bin : 0;
+        const BinOut O0 = lds_uniform<BinOut>((lds_int *)s_O);
+        bool fresh = (ja == j0 ? O0.fresh_first : O0.fresh_rest) != 0;
+        for (int j = ja; j < jb; ++j) {
+            const SegConst g = ld(segs + j);
+            if (g.bin != bin) {
+                const BinOut Ob = lds_uniform<BinOut>((lds_int *)s_O);
+                if (valid) put_bin(Ob, (int64_t)bin * n + i, fresh, cnt, mins);
+                cnt = 0;
+                mins = 0.0;
+                bin = g.bin;
+                fresh = Ob.fresh_rest != 0;
             }
-            if (valid && jb > ja) put_bin(lds_uniform<BinOut>((lds_int *)s_O), (int64_t)bin * n + i, fresh, cnt, mins);
+            Union4 U;
+            bool ov;
+            const SegSrc src{snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr,
+                             (cint *)voff_g, 0};
+            accrue_segment<kCount>(src, stack, verts, height, g, q, valid && !covered, 0.f, g.theta, U, ov, wk);
+            if constexpr (kCount) {
+                wk.units += valid ? 1u : 0u;
+                wk.spills += (valid && ov) ? 1u : 0u;
+            }
+            const SegConst gm = reload(segs, j);
+            if (covered && valid) {
+                mins += (double)gm.dt;
+                cnt += gm.ns_all;
+            } else if (!ov) {
+                measure(U, gm, 0.f, gm.theta, true, mins, cnt);
+            }
+            if (ballot(valid && ov))
+                spill_push(lds_uniform<SpillArgs>((lds_int *)s_S), valid && ov, i, j, 0.f, gm.theta);
         }
+        if (valid && jb > ja) put_bin(lds_uniform<BinOut>((lds_int *)s_O), (int64_t)bin * n + i, fresh, cnt, mins);
     }
     if constexpr (kCount) flush_work(wk, work);
 }
@@ -483,101 +529,111 @@ __device__ __forceinline__ void runs_update(const Union4 &U, float w0, float w1,
 // have to shrink below theta / 4096 to raise the overflow flag.  Seven
 // waves per SIMD (the compiler fits the kernel in 72 VGPRs) measured 4 %
 // faster than the six its natural allocation allows.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_accrual_runs(const Node *nodes_g, const SegNode *snodes_g, int n_nodes,
-                                                           const int32_t *voff_g, const float4 *verts_g,
-                                                           const float *height_g, const SegConst *segs_g, int j0,
-                                                           int j1, PointArgs P, BinOut O, float *longest,
-                                                           uint32_t *overflow)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_accrual_runs(
+    const Node *nodes_g, const SegNode *snodes_g, int n_nodes, const int32_t *voff_g, const float4 *verts_g,
+    const float *height_g, const SegConst *segs_g, int j0, int j1, Sched W, PointArgs P, BinOut O, float *longest,
+    uint32_t *overflow)
 {
     cNode *nodes = (cNode *)nodes_g;
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
     cSeg *segs = (cSeg *)segs_g;
     __shared__ StackEntry s_stack[kWaves][kStackDepth];
-    // outputs (and where to flag overflow) parked in LDS: needed only at a
-    // bin's end, they hold no scalar registers through the traversal
+    // outputs (and where to flag overflow), schedule and points parked in
+    // LDS: needed once per unit or at a bin's end, they hold no scalar
+    // registers through the traversal
     __shared__ int s_O[sizeof(BinOut) / 4];
+    __shared__ int s_W[sizeof(Sched) / 4];
+    __shared__ int s_P[sizeof(PointArgs) / 4];
     __shared__ float *s_longest;
     __shared__ uint32_t *s_overflow;
     if (threadIdx.x == 0) {
         lds_park((lds_int *)s_O, O);
+        lds_park((lds_int *)s_W, W);
+        lds_park((lds_int *)s_P, P);
         s_longest = longest;
         s_overflow = overflow;
     }
     __syncthreads();
     StackEntry *stack = s_stack[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
-    const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
-    const int64_t i = wave * 64 + lane;
-    const bool valid = i < P.n;
-    const int64_t n = P.n;
-    const LanePoint q = load_point(P, i, valid);
-    const bool covered = roof_covered(nodes_g ? nodes : nullptr, stack, verts, height, q, valid);
     Work none{0, 0, 0, 0, 0, 0, 0};
+    int kx = 0;
+    Unit un;
+    while (next_unit((lds_int *)s_W, j0, j1, kx, un)) {
+        const PointArgs Pd = lds_uniform<PointArgs>((lds_int *)s_P);
+        const int64_t n = Pd.n;
+        const int64_t i = (int64_t)un.tile * 64 + lane;
+        const bool valid = i < n;
+        const LanePoint q = load_point(Pd, i, valid);
+        const bool covered = roof_covered(nodes_g ? nodes : nullptr, stack, verts, height, q, valid);
+        const int ja = uniform(un.a), jb = uniform(un.b);
 
-    int cnt = 0;
-    double mins = 0.0;
-    float run = 0.f, best = 0.f;
-    int bin = j1 > j0 ? ld(segs + j0).bin : 0;
-    int day = j1 > j0 ? ld(segs + j0).day : 0;
-    bool fresh = lds_uniform<BinOut>((lds_int *)s_O).fresh_first != 0;
-    auto flush = [&]() {
-        if (!valid) return;
-        const int64_t o = (int64_t)bin * n + i;
-        const BinOut Ob = lds_uniform<BinOut>((lds_int *)s_O);
-        put_bin(Ob, o, fresh, cnt, mins);
-        float *lg = s_longest;
-        if (lg) lg[o] = fresh ? best * Ob.scale : fmaxf(lg[o], best * Ob.scale);
-    };
-    for (int j = j0; j < j1; ++j) {
-        const SegConst g = ld(segs + j);
-        if (g.bin != bin) {
-            flush();
-            cnt = 0;
-            mins = 0.0;
-            best = 0.f;
-            bin = g.bin;
-            fresh = lds_uniform<BinOut>((lds_int *)s_O).fresh_rest != 0;
-        }
-        if (g.day != day) {
-            run = 0.f;
-            day = g.day;
-        }
-        if (covered && valid) {
-            mins += (double)g.dt;
-            cnt += g.ns_all;
-            run += g.dt;
-            best = fmaxf(best, run);
-        }
-        bool pending = valid && !covered;
-        float w0 = 0.f, s = g.theta;
-        while (ballot(pending)) {
-            const float w1 = fminf(w0 + s, g.theta);
-            Union4 U;
-            bool ov;
-            const SegSrc src{snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr,
-                             (cint *)voff_g, 0};
-            accrue_segment<false>(src, stack, verts, height, g, q, pending, w0, w1, U, ov, none);
-            if (pending) {
-                if (ov) {
-                    if (s < g.theta * (1.0f / 4096.0f)) {
-                        atomicOr(s_overflow, 2u);
-                        pending = false;
+        int cnt = 0;
+        double mins = 0.0;
+        float run = 0.f, best = 0.f;
+        int bin = jb > ja ? ld(segs + ja).bin : 0;
+        int day = jb > ja ? ld(segs + ja).day : 0;
+        const BinOut O0 = lds_uniform<BinOut>((lds_int *)s_O);
+        bool fresh = (ja == j0 ? O0.fresh_first : O0.fresh_rest) != 0;
+        auto flush = [&]() {
+            if (!valid) return;
+            const int64_t o = (int64_t)bin * n + i;
+            const BinOut Ob = lds_uniform<BinOut>((lds_int *)s_O);
+            put_bin(Ob, o, fresh, cnt, mins);
+            float *lg = s_longest;
+            if (lg) lg[o] = fresh ? best * Ob.scale : fmaxf(lg[o], best * Ob.scale);
+        };
+        for (int j = ja; j < jb; ++j) {
+            const SegConst g = ld(segs + j);
+            if (g.bin != bin) {
+                flush();
+                cnt = 0;
+                mins = 0.0;
+                best = 0.f;
+                bin = g.bin;
+                fresh = lds_uniform<BinOut>((lds_int *)s_O).fresh_rest != 0;
+            }
+            if (g.day != day) {
+                run = 0.f;
+                day = g.day;
+            }
+            if (covered && valid) {
+                mins += (double)g.dt;
+                cnt += g.ns_all;
+                run += g.dt;
+                best = fmaxf(best, run);
+            }
+            bool pending = valid && !covered;
+            float w0 = 0.f, s = g.theta;
+            while (ballot(pending)) {
+                const float w1 = fminf(w0 + s, g.theta);
+                Union4 U;
+                bool ov;
+                const SegSrc src{snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr,
+                                 (cint *)voff_g, 0};
+                accrue_segment<false>(src, stack, verts, height, g, q, pending, w0, w1, U, ov, none);
+                if (pending) {
+                    if (ov) {
+                        if (s < g.theta * (1.0f / 4096.0f)) {
+                            atomicOr(s_overflow, 2u);
+                            pending = false;
+                        } else {
+                            s *= 0.5f;
+                        }
                     } else {
-                        s *= 0.5f;
+                        const SegConst gm = reload(segs, j);
+                        measure(U, gm, w0, w1, w1 >= gm.theta, mins, cnt);
+                        runs_update(U, w0, w1, gm.rate, run, best);
+                        w0 = w1;
+                        pending = w0 < g.theta;
+                        s = fminf(2.f * s, g.theta);
                     }
-                } else {
-                    const SegConst gm = reload(segs, j);
-                    measure(U, gm, w0, w1, w1 >= gm.theta, mins, cnt);
-                    runs_update(U, w0, w1, gm.rate, run, best);
-                    w0 = w1;
-                    pending = w0 < g.theta;
-                    s = fminf(2.f * s, g.theta);
                 }
             }
         }
+        if (jb > ja) flush();
     }
-    if (j1 > j0) flush();
 }
 
 // One spill round: each queued (point, segment, window) is taken by one
@@ -645,7 +701,7 @@ __global__ __launch_bounds__(kThreads) void k_spill(const SegNode *snodes_g, int
 // the point's own building.
 __global__ __launch_bounds__(kThreads) void k_contrib(const SegNode *snodes_g, int n_nodes, const int32_t *voff_g,
                                                       const float4 *verts_g, const float *height_g,
-                                                      const SegConst *segs_g, int j0, int j1, PointArgs P,
+                                                      const SegConst *segs_g, int j0, int j1, Sched W, PointArgs P,
                                                       const float *weight, const int32_t *order, int n_b,
                                                       double *contrib)
 {
@@ -653,68 +709,80 @@ __global__ __launch_bounds__(kThreads) void k_contrib(const SegNode *snodes_g, i
     cfloat *height = (cfloat *)height_g;
     cSeg *segs = (cSeg *)segs_g;
     __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    __shared__ int s_W[sizeof(Sched) / 4];
+    __shared__ int s_P[sizeof(PointArgs) / 4];
+    if (threadIdx.x == 0) {
+        lds_park((lds_int *)s_W, W);
+        lds_park((lds_int *)s_P, P);
+    }
+    __syncthreads();
     StackEntry *stack = s_stack[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
-    const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
-    const int64_t i = wave * 64 + lane;
-    const bool valid = i < P.n;
-    const LanePoint q = load_point(P, i, valid);
-    const float wt = valid ? (weight ? weight[i] : 1.f) : 0.f;
-    const bool active = valid & (wt != 0.f);
     Work none{0, 0, 0, 0, 0, 0, 0};
-    // Back-facing minutes go to the point's own building: kept per lane
-    // over the bin's segments and added once per bin, with one atomic for
-    // the wave when all its contributing lanes share the building (facade
-    // points come wall by wall, so they nearly always do).
-    double bf = 0.0;
-    int bin = j1 > j0 ? ld(segs + j0).bin : 0;
-    auto flush_backface = [&]() {
-        const uint64_t has = ballot(bf != 0.0);
-        if (!has) return;
-        const int lead = (int)__builtin_ctzll(has);
-        const int o0 = __shfl(q.own, lead, 64);
-        double *row = contrib + (int64_t)bin * n_b;
-        if (!ballot(bf != 0.0 && q.own != o0)) {
-            double s = bf;
-            for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-            if (lane == lead) atomicAdd(&row[order[o0]], s);
-        } else if (bf != 0.0) {
-            atomicAdd(&row[order[q.own]], bf);
-        }
-        bf = 0.0;
-    };
-    for (int j = j0; j < j1; ++j) {
-        const SegConst g = ld(segs + j);
-        if (g.bin != bin) {
-            flush_backface();
-            bin = g.bin;
-        }
-        double *row = contrib + (int64_t)g.bin * n_b;
-        if (active && q.own >= 0) {
-            float a, b;
-            if (backface_interval(q.nx, q.ny, g, 0.f, g.theta, 1.f, 0.f, g.cth, g.sth, a, b))
-                bf += (double)((b - a) * g.wrate * wt);
-        }
-        if (snodes_g == nullptr) continue;
-        const SegFan ft(g, q.px, q.py, q.pz);
-        auto leaf = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
-            const uint64_t gm = want & ballot(prim != q.own);
-            if (!gm) return 0;
-            const bool go = lane_in(gm);
-            float a = 0.f, b = 0.f, da, db;
-            const int r = go ? prism_interval<false>(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, 0.f,
-                                                     g.theta, 1.f, 0.f, g.cth, g.sth, a, b, da, db)
-                             : 0;
-            // the wave's total for this building (every lane is active
-            // here: the traversal runs on the whole wave)
-            const float v = wave_sum(r ? (b - a) * g.wrate * wt : 0.f);
-            if (first_active_lane() && v != 0.f) atomicAdd(&row[order[prim]], (double)v);
-            return 0;  // no lane retires: every building counts
+    int kx = 0;
+    Unit un;
+    while (next_unit((lds_int *)s_W, j0, j1, kx, un)) {
+        const PointArgs Pd = lds_uniform<PointArgs>((lds_int *)s_P);
+        const int64_t i = (int64_t)un.tile * 64 + lane;
+        const bool valid = i < Pd.n;
+        const LanePoint q = load_point(Pd, i, valid);
+        const float wt = valid ? (weight ? weight[i] : 1.f) : 0.f;
+        const bool active = valid & (wt != 0.f);
+        // Back-facing minutes go to the point's own building: kept per lane
+        // over the bin's segments and added once per bin, with one atomic
+        // for the wave when all its contributing lanes share the building
+        // (facade points come wall by wall, so they nearly always do).
+        const int ja = uniform(un.a), jb = uniform(un.b);
+        double bf = 0.0;
+        int bin = jb > ja ? ld(segs + ja).bin : 0;
+        auto flush_backface = [&]() {
+            const uint64_t has = ballot(bf != 0.0);
+            if (!has) return;
+            const int lead = (int)__builtin_ctzll(has);
+            const int o0 = __shfl(q.own, lead, 64);
+            double *row = contrib + (int64_t)bin * n_b;
+            if (!ballot(bf != 0.0 && q.own != o0)) {
+                double s = bf;
+                for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+                if (lane == lead) atomicAdd(&row[order[o0]], s);
+            } else if (bf != 0.0) {
+                atomicAdd(&row[order[q.own]], bf);
+            }
+            bf = 0.0;
         };
-        packet_traverse_seg<false>((cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes), (cint *)voff_g, stack,
-                                   ballot(active), ft, leaf, none);
+        for (int j = ja; j < jb; ++j) {
+            const SegConst g = ld(segs + j);
+            if (g.bin != bin) {
+                flush_backface();
+                bin = g.bin;
+            }
+            double *row = contrib + (int64_t)g.bin * n_b;
+            if (active && q.own >= 0) {
+                float a, b;
+                if (backface_interval(q.nx, q.ny, g, 0.f, g.theta, 1.f, 0.f, g.cth, g.sth, a, b))
+                    bf += (double)((b - a) * g.wrate * wt);
+            }
+            if (snodes_g == nullptr) continue;
+            const SegFan ft(g, q.px, q.py, q.pz);
+            auto leaf = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
+                const uint64_t gm = want & ballot(prim != q.own);
+                if (!gm) return 0;
+                const bool go = lane_in(gm);
+                float a = 0.f, b = 0.f, da, db;
+                const int r = go ? prism_interval<false>(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, g, 0.f,
+                                                         g.theta, 1.f, 0.f, g.cth, g.sth, a, b, da, db)
+                                 : 0;
+                // the wave's total for this building (every lane is active
+                // here: the traversal runs on the whole wave)
+                const float v = wave_sum(r ? (b - a) * g.wrate * wt : 0.f);
+                if (first_active_lane() && v != 0.f) atomicAdd(&row[order[prim]], (double)v);
+                return 0;  // no lane retires: every building counts
+            };
+            packet_traverse_seg<false>((cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes), (cint *)voff_g, stack,
+                                       ballot(active), ft, leaf, none);
+        }
+        flush_backface();
     }
-    flush_backface();
 }
 
 // ------------------------------------------------------------------ batched
@@ -997,22 +1065,81 @@ static PointArgs point_args(const PointsView &pts, const DeviceScene &s)
     return PointArgs{pts.n, pts.x, pts.y, pts.z, pts.nx, pts.ny, pts.owner, s.rank, s.n_b};
 }
 
+// How a persistent launch may cut a tile's items into parts.
+enum class Split {
+    kNone,        // one part per tile
+    kUniqueBins,  // a part per bin run when no bin has two runs in the launch
+                  // (each (tile, bin) is then one unit's: plain stores)
+    kBinRuns,     // a part per bin run (outputs added atomically)
+};
+
+// The units of a persistent launch over items [a0, a1) (segments or
+// instants, whose bin runs are R) for `tiles` 64-point tiles.
+static Sched plan_units(const BinRuns &R, int a0, int a1, int64_t tiles, Split split, uint32_t *grab)
+{
+    Sched W{nullptr, grab, (uint32_t)tiles, 1u};
+    if (split == Split::kNone || R.dev == nullptr || R.start.size() < 2 || a1 <= a0) return W;
+    const auto &rs = R.start;
+    const int r0 = (int)(std::upper_bound(rs.begin(), rs.end(), a0) - rs.begin()) - 1;
+    const int r1 = (int)(std::upper_bound(rs.begin(), rs.end(), a1 - 1) - rs.begin()) - 1;
+    if (r1 <= r0 || (uint64_t)tiles * (uint64_t)(r1 - r0 + 1) >= (1ull << 31)) return W;
+    if (split == Split::kUniqueBins) {
+        std::vector<int32_t> bins(R.bin.begin() + r0, R.bin.begin() + r1 + 1);
+        std::sort(bins.begin(), bins.end());
+        if (std::adjacent_find(bins.begin(), bins.end()) != bins.end()) return W;
+    }
+    W.part_start = R.dev + r0;
+    W.n_parts = (uint32_t)(r1 - r0 + 1);
+    return W;
+}
+
+// Blocks of a persistent launch of `kern`: the tuned count, else as many
+// as the device holds at once; never more than the units need.
+template <class Kern>
+static int64_t unit_blocks(Kern kern, const TileLaunch &L, const Sched &W)
+{
+    int64_t g = L.grid_blocks;
+    if (g <= 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, 0) != hipSuccess || per_cu < 1) {
+            (void)hipGetLastError();
+            per_cu = 1;
+        }
+        g = (int64_t)per_cu * std::max(L.n_cu, 1);
+    }
+    const int64_t units = (int64_t)W.n_tiles * W.n_parts;
+    return std::max<int64_t>(1, std::min<int64_t>(g, (units + kWaves - 1) / kWaves));
+}
+
+// Tiles of n points, refused beyond what the unit counters address.
+static bool tile_count(int64_t n, int64_t &tiles, std::string &err)
+{
+    tiles = (n + 63) / 64;
+    if (tiles >= (1ll << 31)) {
+        err = "too many points";
+        return false;
+    }
+    return true;
+}
+
 sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
                          int32_t *counts, float *minutes, uint32_t *bits, float *longest, uint64_t *work,
-                         hipStream_t st, std::string &err)
+                         const TileLaunch &L, uint32_t *grab, hipStream_t st, std::string &err)
 {
     if (pts.n == 0) return SA_OK;
-    const int64_t waves = (pts.n + 63) / 64;
-    const int64_t grid = (waves + kWaves - 1) / kWaves;
-    if (grid > INT32_MAX) {
-        err = "too many points";
-        return SA_ERR_INVALID_ARG;
-    }
+    int64_t tiles;
+    if (!tile_count(pts.n, tiles, err)) return SA_ERR_INVALID_ARG;
     const Node *nodes = s.n_b > 0 ? s.nodes : nullptr;
     auto kern = bits ? (work ? k_sampled<true, true> : k_sampled<true, false>)
                      : (work ? k_sampled<false, true> : k_sampled<false, false>);
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, s.verts, s.height, p.samples,
-                       p.n_samples, point_args(pts, s), scale, counts, minutes, bits, longest, work);
+    // bit vectors pack 32 instants a word across bin boundaries: one part
+    // per tile then, so each word has one writer
+    const Sched W = plan_units(p.sample_runs, 0, p.n_samples, tiles, bits ? Split::kNone : Split::kUniqueBins, grab);
+    sa_status rc = fill_u32(grab, 8 * kGrabStride, 0u, st, err);
+    if (rc != SA_OK) return rc;
+    hipLaunchKernelGGL(kern, dim3((unsigned)unit_blocks(kern, L, W)), dim3(kThreads), 0, st, nodes, s.verts,
+                       s.height, p.samples, p.n_samples, W, point_args(pts, s),
+                       SampOut{counts, minutes, bits, longest, scale, 0}, work);
     SA_CHECK_LAUNCH("sampled kernel");
     return SA_OK;
 }
@@ -1192,35 +1319,15 @@ static BinOut bin_out(const DevicePath &p, int j0, bool store, int32_t *counts, 
     return BinOut{counts, minutes, minutes64, first ? 1 : 0, store ? 1 : 0, scale, 0};
 }
 
-// The parts of an accrual launch over [j0, j1): its bin runs (a slice of
-// p.runs) when every bin has one run in it, else one part (null).
-static const int32_t *accrual_parts(const DevicePath &p, int j0, int j1, uint32_t &n_parts)
-{
-    n_parts = 1;
-    if (p.runs == nullptr || p.run_start.size() < 2 || j1 <= j0) return nullptr;
-    const auto &rs = p.run_start;
-    const int r0 = (int)(std::upper_bound(rs.begin(), rs.end(), j0) - rs.begin()) - 1;
-    const int r1 = (int)(std::upper_bound(rs.begin(), rs.end(), j1 - 1) - rs.begin()) - 1;
-    if (r1 <= r0) return nullptr;
-    std::vector<char> seen(std::max(p.n_bins, 1), 0);
-    for (int r = r0; r <= r1; ++r) {
-        const int b = p.seg_bin[rs[r]];
-        if (seen[b]) return nullptr;
-        seen[b] = 1;
-    }
-    n_parts = (uint32_t)(r1 - r0 + 1);
-    return p.runs + r0;
-}
-
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
                          int32_t *counts, float *minutes, double *minutes64, float *longest, uint64_t *work,
-                         bool store, const AccrualLaunch &L, SpillQueue &q, Scratch &scr, hipStream_t st,
+                         bool store, const TileLaunch &L, SpillQueue &q, Scratch &scr, hipStream_t st,
                          std::string &err)
 {
     const int32_t seg_per_launch = L.segments_per_launch;
     if (pts.n == 0) return SA_OK;
-    const int64_t waves = (pts.n + 63) / 64;
-    const int64_t grid = (waves + kWaves - 1) / kWaves;
+    int64_t tiles;
+    if (!tile_count(pts.n, tiles, err)) return SA_ERR_INVALID_ARG;
     const Node *nodes = s.n_b > 0 ? s.nodes : nullptr;
     const PointArgs P = point_args(pts, s);
     // Long spans run as several launches over consecutive segment ranges,
@@ -1253,8 +1360,11 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
             SegNode *views;
             sa_status rc = build_seg_views(s, p, j0, j1, s.n_nodes, scr, st, views, err);
             if (rc != SA_OK) return rc;
-            hipLaunchKernelGGL(k_accrual_runs, dim3((unsigned)grid), dim3(kThreads), 0, st, nodes, views, s.n_nodes,
-                               s.voff, s.verts, s.height, p.segs, j0, j1, P,
+            const Sched W = plan_units(p.seg_runs, j0, j1, tiles, Split::kUniqueBins, q.grab);
+            rc = fill_u32(q.grab, 8 * kGrabStride, 0u, st, err);
+            if (rc != SA_OK) return rc;
+            hipLaunchKernelGGL(k_accrual_runs, dim3((unsigned)unit_blocks(k_accrual_runs, L, W)), dim3(kThreads), 0,
+                               st, nodes, views, s.n_nodes, s.voff, s.verts, s.height, p.segs, j0, j1, W, P,
                                bin_out(p, j0, store, counts, minutes, minutes64, scale), longest, q.counters + 2);
             SA_CHECK_LAUNCH("accrual kernel (continuous shadow)");
             d0 = d1;
@@ -1268,17 +1378,12 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
         if (rc != SA_OK) return rc;
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters);
         SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
-        Sched W{nullptr, q.grab, (uint32_t)waves, 1u};
-        W.part_start = accrual_parts(p, (int)j0, j1, W.n_parts);
-        if ((uint64_t)W.n_tiles * W.n_parts >= (1ull << 31)) {
-            W.part_start = nullptr;  // one part per tile keeps the unit count in range
-            W.n_parts = 1;
-        }
-        const int64_t units = (int64_t)W.n_tiles * W.n_parts;
-        const int64_t blocks = std::min<int64_t>(L.grid_blocks, (units + kWaves - 1) / kWaves);
+        const Sched W = plan_units(p.seg_runs, (int)j0, j1, tiles, Split::kUniqueBins, q.grab);
+        auto kern = work ? k_accrual<true> : k_accrual<false>;
+        const int64_t blocks = unit_blocks(kern, L, W);
         rc = fill_u32(q.grab, 8 * kGrabStride, 0u, st, err);
         if (rc != SA_OK) return rc;
-        hipLaunchKernelGGL(work ? k_accrual<true> : k_accrual<false>, dim3((unsigned)blocks), dim3(kThreads), 0, st,
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kThreads), 0, st,
                            nodes, views, s.n_nodes, s.voff, s.verts, s.height, p.segs, (int)j0, j1, W, P,
                            bin_out(p, (int)j0, store, counts, minutes, minutes64, scale), S, work);
         SA_CHECK_LAUNCH("accrual kernel");
@@ -1289,11 +1394,12 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
 }
 
 sa_status launch_contribution(const DeviceScene &s, const DevicePath &p, const PointsView &pts, const float *weight,
-                              double *contrib, Scratch &scr, hipStream_t st, std::string &err)
+                              double *contrib, const TileLaunch &L, uint32_t *grab, Scratch &scr, hipStream_t st,
+                              std::string &err)
 {
     if (pts.n == 0 || s.n_b == 0) return SA_OK;
-    const int64_t waves = (pts.n + 63) / 64;
-    const int64_t grid = (waves + kWaves - 1) / kWaves;
+    int64_t tiles;
+    if (!tile_count(pts.n, tiles, err)) return SA_ERR_INVALID_ARG;
     const PointArgs P = point_args(pts, s);
     // long spans: several launches over consecutive segment ranges
     const int64_t per =
@@ -1303,8 +1409,12 @@ sa_status launch_contribution(const DeviceScene &s, const DevicePath &p, const P
         SegNode *views;
         sa_status rc = build_seg_views(s, p, (int)j0, j1, s.n_nodes, scr, st, views, err);
         if (rc != SA_OK) return rc;
-        hipLaunchKernelGGL(k_contrib, dim3((unsigned)grid), dim3(kThreads), 0, st, views, s.n_nodes, s.voff, s.verts,
-                           s.height, p.segs, (int)j0, j1, P, weight, (const int32_t *)s.order, s.n_b, contrib);
+        const Sched W = plan_units(p.seg_runs, (int)j0, j1, tiles, Split::kBinRuns, grab);
+        rc = fill_u32(grab, 8 * kGrabStride, 0u, st, err);
+        if (rc != SA_OK) return rc;
+        hipLaunchKernelGGL(k_contrib, dim3((unsigned)unit_blocks(k_contrib, L, W)), dim3(kThreads), 0, st, views,
+                           s.n_nodes, s.voff, s.verts, s.height, p.segs, (int)j0, j1, W, P, weight,
+                           (const int32_t *)s.order, s.n_b, contrib);
         SA_CHECK_LAUNCH("contribution kernel");
     }
     return SA_OK;

@@ -211,8 +211,8 @@ sa_status sa_set_launch(sa_ctx *ctx, const sa_launch *l)
 {
     if (!ctx || !l) return SA_ERR_INVALID_ARG;
     if (l->accrual_segments_per_launch < 0 || l->batched_grid_blocks < 0 || l->batched_grid_blocks > (1 << 20) ||
-        l->batched_tiles_per_grab < 0 || l->batched_tiles_per_grab > 1024 || l->accrual_grid_blocks < 0 ||
-        l->accrual_grid_blocks > (1 << 20))
+        l->batched_tiles_per_grab < 0 || l->batched_tiles_per_grab > 1024 || l->tile_grid_blocks < 0 ||
+        l->tile_grid_blocks > (1 << 20))
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_set_launch: value out of range");
     ctx->launch = *l;
     if (ctx->launch.batched_tiles_per_grab == 0) ctx->launch.batched_tiles_per_grab = 1;
@@ -671,8 +671,19 @@ sa_status path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, s
     for (int b = 0; b < n_bins; ++b) contiguous = contiguous && seen[b];
     p->d.bins_contiguous = contiguous;
     for (size_t j = 0; j < segs.size(); ++j)
-        if (j == 0 || segs[j - 1].bin != segs[j].bin) p->d.run_start.push_back((int32_t)j);
-    p->d.run_start.push_back((int32_t)segs.size());
+        if (j == 0 || segs[j - 1].bin != segs[j].bin) {
+            p->d.seg_runs.start.push_back((int32_t)j);
+            p->d.seg_runs.bin.push_back(segs[j].bin);
+        }
+    p->d.seg_runs.start.push_back((int32_t)segs.size());
+    for (size_t k = 0; k < samples.size(); ++k) {
+        const int b = (int)(samples[k].tag & sa::kBinMask);
+        if (k == 0 || (int)(samples[k - 1].tag & sa::kBinMask) != b) {
+            p->d.sample_runs.start.push_back((int32_t)k);
+            p->d.sample_runs.bin.push_back(b);
+        }
+    }
+    p->d.sample_runs.start.push_back((int32_t)samples.size());
     if (!merged) {
         p->d.seg_host = std::move(seg_host);
         p->d.sample_t.assign(in->t_min, in->t_min + in->n_samples);
@@ -698,11 +709,11 @@ sa_status path_upload(sa_ctx *ctx, const sa_sunpath_buf *in, double bound_deg, s
         if (e == hipSuccess)
             e = hipMemcpy(p->d.segs, segs.data(), sizeof(sa::SegConst) * segs.size(), hipMemcpyHostToDevice);
     }
-    if (e == hipSuccess && !segs.empty()) {
-        const size_t nr = p->d.run_start.size();
-        e = hipMalloc((void **)&p->d.runs, sizeof(int32_t) * nr);
+    for (sa::BinRuns *R : {&p->d.seg_runs, &p->d.sample_runs}) {
+        if (e != hipSuccess || R->start.size() < 2) continue;
+        e = hipMalloc((void **)&R->dev, sizeof(int32_t) * R->start.size());
         if (e == hipSuccess)
-            e = hipMemcpy(p->d.runs, p->d.run_start.data(), sizeof(int32_t) * nr, hipMemcpyHostToDevice);
+            e = hipMemcpy(R->dev, R->start.data(), sizeof(int32_t) * R->start.size(), hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
         sa_path_destroy(p);
@@ -744,7 +755,8 @@ void sa_path_destroy(sa_path *path)
     (void)hipFree(path->d.samples);
     (void)hipFree(path->d.sam_slices);
     (void)hipFree(path->d.segs);
-    (void)hipFree(path->d.runs);
+    (void)hipFree(path->d.seg_runs.dev);
+    (void)hipFree(path->d.sample_runs.dev);
     delete path;
 }
 
@@ -778,12 +790,10 @@ static sa_status clear_outputs(sa_ctx *ctx, uint32_t flags, int64_t count, int32
     return SA_OK;
 }
 
-// The accrual launch choices of a context: a persistent grid of eight
-// blocks (32 waves) per compute unit unless tuned otherwise.
-static sa::AccrualLaunch accrual_launch(const sa_ctx *ctx)
+// The per-tile launch choices of a context.
+static sa::TileLaunch tile_launch(const sa_ctx *ctx)
 {
-    const int64_t g = ctx->launch.accrual_grid_blocks > 0 ? ctx->launch.accrual_grid_blocks : 8ll * ctx->n_cu;
-    return sa::AccrualLaunch{ctx->launch.accrual_segments_per_launch, g};
+    return sa::TileLaunch{ctx->launch.accrual_segments_per_launch, ctx->launch.tile_grid_blocks, ctx->n_cu};
 }
 
 // The accrual form stores each bin once (no clearing) unless asked to add
@@ -821,10 +831,10 @@ sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts
     std::string err;
     if (opts->mode == SA_SAMPLED)
         rc = sa::launch_sampled(scene->d, path->d, view(pts), scale, counts, minutes, bits, opts->longest,
-                                opts->work, ctx->stream, err);
+                                opts->work, tile_launch(ctx), ctx->spill.grab, ctx->stream, err);
     else
         rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->minutes64,
-                                opts->longest, opts->work, store, accrual_launch(ctx), ctx->spill,
+                                opts->longest, opts->work, store, tile_launch(ctx), ctx->spill,
                                 ctx->scratch_seg, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate: " + err);
     return SA_OK;
@@ -874,14 +884,14 @@ sa_status sa_accumulate_noalloc(sa_ctx *ctx, const sa_scene *scene, const sa_poi
     std::string err;
     if (opts->mode == SA_SAMPLED) {
         rc = sa::launch_sampled(scene->d, path->d, view(pts), scale, counts, minutes, bits, opts->longest,
-                                opts->work, ctx->stream, err);
+                                opts->work, tile_launch(ctx), ctx->spill.grab, ctx->stream, err);
     } else {
         sa::Scratch fixed;
         fixed.ptr = ctx->noalloc;
         fixed.bytes = (size_t)SA_NOALLOC_SCRATCH_BYTES;
         fixed.fixed = true;
         rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->minutes64,
-                                opts->longest, opts->work, store, accrual_launch(ctx), ctx->spill,
+                                opts->longest, opts->work, store, tile_launch(ctx), ctx->spill,
                                 fixed, ctx->stream, err);
     }
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate_noalloc: " + err);
@@ -1015,7 +1025,8 @@ sa_status sa_building_contribution(sa_ctx *ctx, const sa_scene *scene, const sa_
     std::string err;
     rc = sa::fill_u32(contrib, 2 * (int64_t)path->d.n_bins * scene->d.n_b, 0u, ctx->stream, err);
     if (rc == SA_OK)
-        rc = sa::launch_contribution(scene->d, path->d, view(pts), weight, contrib, ctx->scratch_seg, ctx->stream, err);
+        rc = sa::launch_contribution(scene->d, path->d, view(pts), weight, contrib, tile_launch(ctx), ctx->spill.grab,
+                                     ctx->scratch_seg, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_building_contribution: " + err);
     return SA_OK;
 }

@@ -128,6 +128,14 @@ struct SamSegHost {
     int32_t bin;
 };
 
+// Maximal runs of consecutive items (segments or instants) with the same
+// output bin: where each starts (then the item count) and its bin, on the
+// host, and the starts on the device.
+struct BinRuns {
+    std::vector<int32_t> start, bin;
+    int32_t *dev = nullptr;
+};
+
 struct DevicePath {
     int32_t n_days = 0, n_samples = 0, n_segs = 0, n_bins = 0;
     SampleConst *samples = nullptr;  // [n_samples]
@@ -137,8 +145,8 @@ struct DevicePath {
     std::vector<int32_t> day_seg_off;  // host: first segment of each day, [n_days + 1]
     std::vector<int32_t> seg_bin;      // host: output bin of each segment
     bool bins_contiguous = false;      // host: every bin has segments, all in one run
-    std::vector<int32_t> run_start;    // host: first segment of each run of equal bins, then n_segs
-    int32_t *runs = nullptr;           // device copy of run_start
+    BinRuns seg_runs;                  // runs of equal bins over the segments
+    BinRuns sample_runs;               // and over the instants
     std::vector<double> bin_span;      // host: daylight minutes of each output bin
     bool merged = false;               // host: segments merged into direction-graph edges
     // host, for the raster form: each segment's knot directions, times, its
@@ -181,23 +189,26 @@ struct SpillQueue {
     int32_t capacity = 0;
 };
 
-// Launch choices of the accrual form: the most segments one launch covers
-// (0: as many as the view budget allows) and the blocks of its persistent
-// launch.
-struct AccrualLaunch {
+// Launch choices of the per-tile kernels: the most segments one accrual
+// launch covers (0: as many as the view budget allows) and the blocks of
+// the persistent launches (0: as many as the device holds at once, from
+// the kernel's occupancy and the device's compute units).
+struct TileLaunch {
     int32_t segments_per_launch;
     int64_t grid_blocks;
+    int32_t n_cu;
 };
 
 sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
                          float scale, int32_t *counts, float *minutes, uint32_t *bits, float *longest,
-                         uint64_t *work, hipStream_t st, std::string &err);
+                         uint64_t *work, const TileLaunch &L, uint32_t *grab, hipStream_t st,
+                         std::string &err);
 // store: outputs need no clearing (no SA_FLAG_ADD and p.bins_contiguous):
 // each bin is stored by the launch holding its first segment.
 // L: the launch choices (segments per launch, persistent grid size).
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
                          float scale, int32_t *counts, float *minutes, double *minutes64, float *longest,
-                         uint64_t *work, bool store, const AccrualLaunch &L, SpillQueue &q, Scratch &scr,
+                         uint64_t *work, bool store, const TileLaunch &L, SpillQueue &q, Scratch &scr,
                          hipStream_t st, std::string &err);
 // grad = (add ? grad : 0) + scale * d(sum dl * minutes)/dH, accumulated in
 // FP64 in acc (grown to n_b doubles as needed).
@@ -208,8 +219,8 @@ sa_status launch_region_sum(const float *v, int n_bins, int64_t n, const double 
                             const int64_t *off, int32_t n_reg, const float *area, double *out,
                             Scratch &scr, hipStream_t st, std::string &err);
 sa_status launch_contribution(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
-                              const float *weight, double *contrib, Scratch &scr, hipStream_t st,
-                              std::string &err);
+                              const float *weight, double *contrib, const TileLaunch &L, uint32_t *grab,
+                              Scratch &scr, hipStream_t st, std::string &err);
 // Per-segment node views (SegNode) of segments [j0, j1) into scr (grown as
 // needed, with the stream synchronised first; a fixed scr that is too small
 // is a CAPACITY error), segment j's views at (j - j0) * stride; views =

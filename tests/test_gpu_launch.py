@@ -38,7 +38,7 @@ def test_accrual_segments_per_launch(ctx):
         assert d <= 1e-3
 
 
-def test_accrual_grid_blocks(ctx):
+def test_tile_grid_blocks(ctx):
     """The persistent accrual launch at any size -- one block, blocks not a
     multiple of the eight XCDs, more blocks than units -- gives the same
     counts and minutes (each (tile, bin) unit is computed by one wave
@@ -54,7 +54,7 @@ def test_accrual_grid_blocks(ctx):
     for name, path in paths.items():
         res = {}
         for gb, per in ((0, 0), (1, 0), (13, 0), (100_000, 0), (0, 5)):
-            ctx.set_launch(accrual_grid_blocks=gb, accrual_segments_per_launch=per)
+            ctx.set_launch(tile_grid_blocks=gb, accrual_segments_per_launch=per)
             c, m, _ = sa.accumulate(ctx, sc, dp, path, sa.SA_ACCRUAL)
             ctx.sync()
             res[(gb, per)] = (c.cpu().numpy(), m.cpu().numpy())
@@ -97,5 +97,5 @@ def test_bad_launch_values(ctx):
     with pytest.raises(sa.SAError):
         ctx.set_launch(batched_tiles_per_grab=5000)
     with pytest.raises(sa.SAError):
-        ctx.set_launch(accrual_grid_blocks=-3)
+        ctx.set_launch(tile_grid_blocks=-3)
     assert ctx.get_launch()["batched_tiles_per_grab"] == 1
