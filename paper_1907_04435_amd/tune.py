@@ -3,6 +3,8 @@
 * ``accrual_segments_per_launch``: how many path segments one accrual
   launch covers (the per-segment hierarchy views it reads are its working
   set), timed on the block scene's 4M points over three days.
+* ``tile_grid_blocks``: blocks of the persistent per-tile launches (0: as
+  many as the device holds at once), timed on the same accrual launch.
 * ``batched_grid_blocks`` x ``batched_tiles_per_grab``: size of the
   persistent (variant, tile) launch of sa_accumulate_batched and how many
   64-point tiles a wave takes per atomic, timed on a 32-variant slice of
@@ -34,7 +36,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
-LAUNCH_KEYS = ("accrual_segments_per_launch", "batched_grid_blocks", "batched_tiles_per_grab")
+LAUNCH_KEYS = ("accrual_segments_per_launch", "batched_grid_blocks", "batched_tiles_per_grab", "tile_grid_blocks")
 
 
 def _time(torch, stream, fn, reps=3):
@@ -83,14 +85,24 @@ def tune_accrual(sa, torch, ctx, log):
     dp = sa.DevicePoints.from_workload(w.points)
     path = sa.Path(ctx, sa.sunpath_for_span(w.span, 30.0))
     m = torch.empty((path.n_bins, dp.n), dtype=torch.float32, device="cuda")
+    run = lambda: sa.sa_accumulate(ctx, sc, dp, path, sa.SA_ACCRUAL, None, m)
     res = {}
     for per in (0, 37, 25, 13, 7, 4):
         ctx.set_launch(accrual_segments_per_launch=per)
-        res[per] = _time(torch, ctx.stream, lambda: sa.sa_accumulate(ctx, sc, dp, path, sa.SA_ACCRUAL, None, m))
+        res[per] = _time(torch, ctx.stream, run)
         log(f"accrual, {per or path.n_segments} segments per launch: {res[per]:.2f} ms")
-    ctx.set_launch()
     best = min(res, key=res.get)
-    return best, {str(k): v for k, v in res.items()}
+    n_cu = torch.cuda.get_device_properties(ctx.device).multi_processor_count
+    gres = {}
+    for per_cu in (0, 4, 6, 8, 12, 16):
+        gb = per_cu * n_cu
+        ctx.set_launch(accrual_segments_per_launch=best, tile_grid_blocks=gb)
+        gres[gb] = _time(torch, ctx.stream, run)
+        log(f"accrual, persistent grid {gb or 'device-resident'} blocks: {gres[gb]:.2f} ms")
+    ctx.set_launch()
+    gbest = min(gres, key=gres.get)
+    return (best, gbest), {"segments_per_launch": {str(k): v for k, v in res.items()},
+                           "grid_blocks": {str(k): v for k, v in gres.items()}}
 
 
 def tune_batched(sa, torch, ctx, log):
@@ -150,10 +162,10 @@ def main():
     ctx = sa.Context(0)
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     t0 = time.time()
-    per, ares = tune_accrual(sa, torch, ctx, log)
+    (per, tgb), ares = tune_accrual(sa, torch, ctx, log)
     (gb, grab), bres = tune_batched(sa, torch, ctx, log)
     L, lres = tune_seg(sa, torch, ctx, log, args.error_bar, args.tail_bar)
-    out = {"arch": arch, "accrual_segments_per_launch": per, "batched_grid_blocks": gb,
+    out = {"arch": arch, "accrual_segments_per_launch": per, "tile_grid_blocks": tgb, "batched_grid_blocks": gb,
            "batched_tiles_per_grab": grab, "seg_min": L, "error_bar": args.error_bar, "tail_bar": args.tail_bar,
            "accrual_sweep_ms": ares, "batched_sweep_ms": bres, "seg_sweep": lres, "seconds": time.time() - t0}
     with open(CACHE, "w") as f:
