@@ -9,13 +9,14 @@
 
 #include "sa_internal.h"
 #include "traverse.h"
+#include "unit_sched.h"
 
 namespace sa {
 namespace {
 using namespace dev;
 
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
+constexpr int kThreads = kSchedThreads;
+constexpr int kWaves = kSchedWaves;
 // Spill rounds: each refines a window 64-fold, so three rounds reach
 // 1/262144 of a segment.
 constexpr int kSpillRounds = 3;
@@ -25,7 +26,8 @@ constexpr int64_t kSegNodeBytes = 256ll << 20;  // per-segment node views per ac
 
 // Per-bin outputs of the accrual kernels.  A bin whose first segment lies in
 // the launch is stored (no clear beforehand, no read); a bin continued from
-// an earlier launch, or any bin under SA_FLAG_ADD, is added to.
+// an earlier launch, or any bin under SA_FLAG_ADD, is added to.  Each
+// (tile, bin) belongs to one unit, so the sums are deterministic.
 struct BinOut {
     int32_t *counts;
     float *minutes;
@@ -55,62 +57,6 @@ __device__ __forceinline__ void flush_work(const Work &w, uint64_t *work)
         for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
         if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&work[c], (unsigned long long)s);
     }
-}
-
-// ------------------------------------------------------ persistent launches
-// The per-tile kernels run as persistent launches: their work is a list of
-// units (64-point tile, part) in tile-major order, a part being one output
-// bin's run of the launch's items (segments or instants) -- or all of
-// them, when a unit has to see several bins.  The units are cut into eight
-// contiguous ranges, one per XCD (block b runs on XCD b mod 8), each with
-// its own counter; a wave takes one unit per atomic from its XCD's range,
-// then from the others'.  Neighbouring tiles share hierarchy nodes and
-// prisms in their XCD's L2, and the waves stay resident until the work
-// runs out: no SIMD idles behind a long tile, and the launch's tail is one
-// unit long.
-struct Sched {
-    const int32_t *part_start;  // [n_parts + 1] first item of each part (clipped to the launch), or null: one part
-    uint32_t *grab;             // eight counters, kGrabStride words apart, zero at launch
-    uint32_t n_tiles;
-    uint32_t n_parts;
-};
-constexpr int kGrabStride = 32;  // one 128-byte line per counter
-
-struct Unit {
-    uint32_t tile;
-    int a, b;  // the unit's items [a, b)
-};
-
-// The next unit of the launch whose Sched is parked at s_W, for items
-// [a0, a1); false when none is left.  k counts the XCD ranges already
-// drained (0 at the start).  Callers pass the unit's bounds through
-// uniform(): set inside this loop, they would otherwise count as
-// per-lane values and could not address scalar loads.
-__device__ __forceinline__ bool next_unit(const lds_int *s_W, int a0, int a1, int &k, Unit &un)
-{
-    const Sched W = lds_uniform<Sched>(s_W);
-    const uint32_t n_units = W.n_tiles * W.n_parts;
-    const int xcd = blockIdx.x & 7;
-    for (; k < 8; ++k) {
-        const int x = (xcd + k) & 7;
-        const uint32_t lo = (uint32_t)((uint64_t)n_units * x >> 3);
-        const uint32_t hi = (uint32_t)((uint64_t)n_units * (x + 1) >> 3);
-        uint32_t got = 0;
-        if ((threadIdx.x & 63) == 0) got = atomicAdd(W.grab + kGrabStride * x, 1u);
-        got = (uint32_t)__builtin_amdgcn_readlane((int)got, 0);
-        if (got < hi - lo) {
-            const uint32_t u = lo + got;
-            // the division runs on the vector unit: its result is made
-            // scalar again for the scalar loads it addresses
-            const uint32_t tile = (uint32_t)uniform((int)(u / W.n_parts));
-            const uint32_t part = u - tile * W.n_parts;
-            un.tile = tile;
-            un.a = W.part_start ? max(ld((cint *)W.part_start + part), a0) : a0;
-            un.b = W.part_start ? min(ld((cint *)W.part_start + part + 1), a1) : a1;
-            return true;
-        }
-    }
-    return false;
 }
 
 // Outputs of the sampled form (parked in LDS by the kernel).
@@ -1065,63 +1011,6 @@ static PointArgs point_args(const PointsView &pts, const DeviceScene &s)
     return PointArgs{pts.n, pts.x, pts.y, pts.z, pts.nx, pts.ny, pts.owner, s.rank, s.n_b};
 }
 
-// How a persistent launch may cut a tile's items into parts.
-enum class Split {
-    kNone,        // one part per tile
-    kUniqueBins,  // a part per bin run when no bin has two runs in the launch
-                  // (each (tile, bin) is then one unit's: plain stores)
-    kBinRuns,     // a part per bin run (outputs added atomically)
-};
-
-// The units of a persistent launch over items [a0, a1) (segments or
-// instants, whose bin runs are R) for `tiles` 64-point tiles.
-static Sched plan_units(const BinRuns &R, int a0, int a1, int64_t tiles, Split split, uint32_t *grab)
-{
-    Sched W{nullptr, grab, (uint32_t)tiles, 1u};
-    if (split == Split::kNone || R.dev == nullptr || R.start.size() < 2 || a1 <= a0) return W;
-    const auto &rs = R.start;
-    const int r0 = (int)(std::upper_bound(rs.begin(), rs.end(), a0) - rs.begin()) - 1;
-    const int r1 = (int)(std::upper_bound(rs.begin(), rs.end(), a1 - 1) - rs.begin()) - 1;
-    if (r1 <= r0 || (uint64_t)tiles * (uint64_t)(r1 - r0 + 1) >= (1ull << 31)) return W;
-    if (split == Split::kUniqueBins) {
-        std::vector<int32_t> bins(R.bin.begin() + r0, R.bin.begin() + r1 + 1);
-        std::sort(bins.begin(), bins.end());
-        if (std::adjacent_find(bins.begin(), bins.end()) != bins.end()) return W;
-    }
-    W.part_start = R.dev + r0;
-    W.n_parts = (uint32_t)(r1 - r0 + 1);
-    return W;
-}
-
-// Blocks of a persistent launch of `kern`: the tuned count, else as many
-// as the device holds at once; never more than the units need.
-template <class Kern>
-static int64_t unit_blocks(Kern kern, const TileLaunch &L, const Sched &W)
-{
-    int64_t g = L.grid_blocks;
-    if (g <= 0) {
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kThreads, 0) != hipSuccess || per_cu < 1) {
-            (void)hipGetLastError();
-            per_cu = 1;
-        }
-        g = (int64_t)per_cu * std::max(L.n_cu, 1);
-    }
-    const int64_t units = (int64_t)W.n_tiles * W.n_parts;
-    return std::max<int64_t>(1, std::min<int64_t>(g, (units + kWaves - 1) / kWaves));
-}
-
-// Tiles of n points, refused beyond what the unit counters address.
-static bool tile_count(int64_t n, int64_t &tiles, std::string &err)
-{
-    tiles = (n + 63) / 64;
-    if (tiles >= (1ll << 31)) {
-        err = "too many points";
-        return false;
-    }
-    return true;
-}
-
 sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
                          int32_t *counts, float *minutes, uint32_t *bits, float *longest, uint64_t *work,
                          const TileLaunch &L, uint32_t *grab, hipStream_t st, std::string &err)
@@ -1134,10 +1023,12 @@ sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const Points
                      : (work ? k_sampled<false, true> : k_sampled<false, false>);
     // bit vectors pack 32 instants a word across bin boundaries: one part
     // per tile then, so each word has one writer
-    const Sched W = plan_units(p.sample_runs, 0, p.n_samples, tiles, bits ? Split::kNone : Split::kUniqueBins, grab);
+    const int64_t res = resident_blocks(kern, L);
+    const Sched W =
+        plan_units(p.sample_runs, 0, p.n_samples, tiles, bits ? Split::kNone : Split::kUniqueBins, res, grab);
     sa_status rc = fill_u32(grab, 8 * kGrabStride, 0u, st, err);
     if (rc != SA_OK) return rc;
-    hipLaunchKernelGGL(kern, dim3((unsigned)unit_blocks(kern, L, W)), dim3(kThreads), 0, st, nodes, s.verts,
+    hipLaunchKernelGGL(kern, dim3((unsigned)unit_blocks(res, W)), dim3(kThreads), 0, st, nodes, s.verts,
                        s.height, p.samples, p.n_samples, W, point_args(pts, s),
                        SampOut{counts, minutes, bits, longest, scale, 0}, work);
     SA_CHECK_LAUNCH("sampled kernel");
@@ -1360,10 +1251,11 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
             SegNode *views;
             sa_status rc = build_seg_views(s, p, j0, j1, s.n_nodes, scr, st, views, err);
             if (rc != SA_OK) return rc;
-            const Sched W = plan_units(p.seg_runs, j0, j1, tiles, Split::kUniqueBins, q.grab);
+            const int64_t res = resident_blocks(k_accrual_runs, L);
+            const Sched W = plan_units(p.seg_runs, j0, j1, tiles, Split::kUniqueBins, res, q.grab);
             rc = fill_u32(q.grab, 8 * kGrabStride, 0u, st, err);
             if (rc != SA_OK) return rc;
-            hipLaunchKernelGGL(k_accrual_runs, dim3((unsigned)unit_blocks(k_accrual_runs, L, W)), dim3(kThreads), 0,
+            hipLaunchKernelGGL(k_accrual_runs, dim3((unsigned)unit_blocks(res, W)), dim3(kThreads), 0,
                                st, nodes, views, s.n_nodes, s.voff, s.verts, s.height, p.segs, j0, j1, W, P,
                                bin_out(p, j0, store, counts, minutes, minutes64, scale), longest, q.counters + 2);
             SA_CHECK_LAUNCH("accrual kernel (continuous shadow)");
@@ -1371,6 +1263,8 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
         }
         return SA_OK;
     }
+    auto kern = work ? k_accrual<true> : k_accrual<false>;
+    const int64_t res = resident_blocks(kern, L);
     for (int64_t j0 = 0; j0 < p.n_segs; j0 += per) {
         const int j1 = (int)std::min<int64_t>(j0 + per, p.n_segs);
         SegNode *views;
@@ -1378,13 +1272,11 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
         if (rc != SA_OK) return rc;
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters);
         SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
-        const Sched W = plan_units(p.seg_runs, (int)j0, j1, tiles, Split::kUniqueBins, q.grab);
-        auto kern = work ? k_accrual<true> : k_accrual<false>;
-        const int64_t blocks = unit_blocks(kern, L, W);
+        const Sched W = plan_units(p.seg_runs, (int)j0, j1, tiles, Split::kUniqueBins, res, q.grab);
         rc = fill_u32(q.grab, 8 * kGrabStride, 0u, st, err);
         if (rc != SA_OK) return rc;
-        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kThreads), 0, st,
-                           nodes, views, s.n_nodes, s.voff, s.verts, s.height, p.segs, (int)j0, j1, W, P,
+        hipLaunchKernelGGL(kern, dim3((unsigned)unit_blocks(res, W)), dim3(kThreads), 0, st, nodes, views, s.n_nodes,
+                           s.voff, s.verts, s.height, p.segs, (int)j0, j1, W, P,
                            bin_out(p, (int)j0, store, counts, minutes, minutes64, scale), S, work);
         SA_CHECK_LAUNCH("accrual kernel");
         rc = run_spill(s, p, views, (int)j0, P, scale, counts, minutes, minutes64, q, st, err);
@@ -1409,10 +1301,11 @@ sa_status launch_contribution(const DeviceScene &s, const DevicePath &p, const P
         SegNode *views;
         sa_status rc = build_seg_views(s, p, (int)j0, j1, s.n_nodes, scr, st, views, err);
         if (rc != SA_OK) return rc;
-        const Sched W = plan_units(p.seg_runs, (int)j0, j1, tiles, Split::kBinRuns, grab);
+        const int64_t res = resident_blocks(k_contrib, L);
+        const Sched W = plan_units(p.seg_runs, (int)j0, j1, tiles, Split::kBinRuns, res, grab);
         rc = fill_u32(grab, 8 * kGrabStride, 0u, st, err);
         if (rc != SA_OK) return rc;
-        hipLaunchKernelGGL(k_contrib, dim3((unsigned)unit_blocks(k_contrib, L, W)), dim3(kThreads), 0, st, views,
+        hipLaunchKernelGGL(k_contrib, dim3((unsigned)unit_blocks(res, W)), dim3(kThreads), 0, st, views,
                            s.n_nodes, s.voff, s.verts, s.height, p.segs, (int)j0, j1, W, P, weight,
                            (const int32_t *)s.order, s.n_b, contrib);
         SA_CHECK_LAUNCH("contribution kernel");

@@ -940,8 +940,8 @@ sa_status sa_grad_heights(sa_ctx *ctx, const sa_scene *scene, const sa_points *p
     const float scale = (!opts || opts->out_scale == 0.f) ? 1.f : opts->out_scale;
     const bool add = opts && (opts->flags & SA_FLAG_ADD);
     std::string err;
-    rc = sa::launch_grad(scene->d, path->d, view(pts), dl_dmin, scale, add, grad, ctx->spill, ctx->scratch_seg,
-                         ctx->scratch_grad, ctx->stream, err);
+    rc = sa::launch_grad(scene->d, path->d, view(pts), dl_dmin, scale, add, grad, tile_launch(ctx), ctx->spill,
+                         ctx->scratch_seg, ctx->scratch_grad, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_grad_heights: " + err);
     return SA_OK;
 }

@@ -19,13 +19,14 @@
 
 #include "sa_internal.h"
 #include "traverse.h"
+#include "unit_sched.h"
 
 namespace sa {
 namespace {
 using namespace dev;
 
-constexpr int kThreads = 256;
-constexpr int kWaves = kThreads / 64;
+constexpr int kThreads = kSchedThreads;
+constexpr int kWaves = kSchedWaves;
 // Spill rounds: each refines a window 64-fold (three reach 1/262144 of a
 // segment).
 constexpr int kSpillRounds = 3;
@@ -135,39 +136,58 @@ __device__ __forceinline__ bool roof_covered_g(cNode *nodes, StackEntry *stack, 
 }
 
 // Seven waves per SIMD (72 VGPRs): 2 % faster than the six of the natural
-// allocation.
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_grad(const Node *nodes_g, const SegNode *snodes_g, int n_nodes,
-                                                   const int32_t *voff_g, const float4 *verts_g, const float *height_g,
-                                                   const SegConst *segs_g, int j0, int j1, PointArgs P, GradArgs G,
-                                                   SpillArgs S)
+// allocation.  Persistent: its units are (tile, chunk of segments), enough
+// of them to keep every wave busy on small point sets (the gradient sums
+// are atomic, so any split adds up the same).
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) void k_grad(
+    const Node *nodes_g, const SegNode *snodes_g, int n_nodes, const int32_t *voff_g, const float4 *verts_g,
+    const float *height_g, const SegConst *segs_g, int j0, int j1, Sched W, PointArgs P, GradArgs G, SpillArgs S)
 {
     cNode *nodes = nodes_g ? (cNode *)nodes_g : nullptr;
     cfloat4 *verts = (cfloat4 *)verts_g;
     cfloat *height = (cfloat *)height_g;
     cSeg *segs = (cSeg *)segs_g;
     __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    __shared__ int s_W[sizeof(Sched) / 4];
+    __shared__ int s_P[sizeof(PointArgs) / 4];
+    __shared__ int s_G[sizeof(GradArgs) / 4];
+    __shared__ int s_S[sizeof(SpillArgs) / 4];
+    if (threadIdx.x == 0) {
+        lds_park((lds_int *)s_W, W);
+        lds_park((lds_int *)s_P, P);
+        lds_park((lds_int *)s_G, G);
+        lds_park((lds_int *)s_S, S);
+    }
+    __syncthreads();
     StackEntry *stack = s_stack[threadIdx.x >> 6];
     const int lane = threadIdx.x & 63;
-    const int64_t wave = xcd_block(blockIdx.x, gridDim.x) * kWaves + (threadIdx.x >> 6);
-    const int64_t i = wave * 64 + lane;
-    const bool valid = i < P.n;
-    const LanePoint q = load_point(P, i, valid);
-    const bool covered = roof_covered_g(nodes, stack, verts, height, q, valid);
-    int bin = -1;
-    float w = 0.f;
-    for (int j = j0; j < j1; ++j) {
-        const SegConst g = ld(segs + j);
-        if (g.bin != bin) {
-            bin = g.bin;
-            w = (valid && G.dl) ? G.dl[(int64_t)bin * P.n + i] : 1.f;
+    int kx = 0;
+    Unit un;
+    while (next_unit((lds_int *)s_W, j0, j1, kx, un)) {
+        const int ja = uniform(un.a), jb = uniform(un.b);
+        const PointArgs Pd = lds_uniform<PointArgs>((lds_int *)s_P);
+        const int64_t i = (int64_t)un.tile * 64 + lane;
+        const bool valid = i < Pd.n;
+        const LanePoint q = load_point(Pd, i, valid);
+        const bool covered = roof_covered_g(nodes, stack, verts, height, q, valid);
+        int bin = -1;
+        float w = 0.f;
+        for (int j = ja; j < jb; ++j) {
+            const SegConst g = ld(segs + j);
+            if (g.bin != bin) {
+                bin = g.bin;
+                const GradArgs Gd = lds_uniform<GradArgs>((lds_int *)s_G);
+                w = (valid && Gd.dl) ? Gd.dl[(int64_t)bin * Pd.n + i] : 1.f;
+            }
+            UnionG U;
+            bool ov;
+            cSegNode *sn = snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr;
+            grad_segment(sn, (cint *)voff_g, stack, verts, height, g, q, valid && !covered && w != 0.f, 0.f, g.theta,
+                         U, ov);
+            scatter_grad(U, valid && !covered && !ov && w != 0.f, w * g.wrate, lds_uniform<GradArgs>((lds_int *)s_G));
+            if (ballot(valid && ov))
+                spill_push(lds_uniform<SpillArgs>((lds_int *)s_S), valid && ov, i, j, 0.f, g.theta);
         }
-        UnionG U;
-        bool ov;
-        cSegNode *sn = snodes_g ? (cSegNode *)(snodes_g + (int64_t)(j - j0) * n_nodes) : nullptr;
-        grad_segment(sn, (cint *)voff_g, stack, verts, height, g, q, valid && !covered && w != 0.f, 0.f, g.theta, U,
-                     ov);
-        scatter_grad(U, valid && !covered && !ov && w != 0.f, w * g.wrate, G);
-        spill_push(S, valid && ov, i, j, 0.f, g.theta);
     }
 }
 
@@ -226,8 +246,8 @@ __global__ void k_spill_left(const uint32_t *count, uint32_t *overflow)
 }  // namespace
 
 sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts, const float *dl, float scale,
-                      bool add, float *grad, SpillQueue &q, Scratch &scr, Scratch &acc_scr, hipStream_t st,
-                      std::string &err)
+                      bool add, float *grad, const TileLaunch &L, SpillQueue &q, Scratch &scr, Scratch &acc_scr,
+                      hipStream_t st, std::string &err)
 {
     if (s.n_b == 0) return SA_OK;
     const size_t need = sizeof(double) * (size_t)s.n_b;
@@ -247,8 +267,9 @@ sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsVie
     double *acc = (double *)acc_scr.ptr;
     sa_status rc = fill_u32(acc, 2 * (int64_t)s.n_b, 0u, st, err);
     if (rc != SA_OK) return rc;
-    const int64_t waves = (pts.n + 63) / 64;
-    const int64_t grid = (waves + kWaves - 1) / kWaves;
+    int64_t tiles;
+    if (!tile_count(pts.n, tiles, err)) return SA_ERR_INVALID_ARG;
+    const int64_t res = resident_blocks(k_grad, L);
     const PointArgs P{pts.n, pts.x, pts.y, pts.z, pts.nx, pts.ny, pts.owner, s.rank, s.n_b};
     const GradArgs G{dl, acc, s.order};
     // segment ranges whose per-segment node views fit the budget, each
@@ -261,8 +282,11 @@ sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsVie
         if (rc != SA_OK) return rc;
         hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, st, q.counters);
         SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
-        hipLaunchKernelGGL(k_grad, dim3((unsigned)grid), dim3(kThreads), 0, st, s.nodes, views, s.n_nodes, s.voff,
-                           s.verts, s.height, p.segs, (int)j0, j1, P, G, S);
+        const Sched W = plan_units(p.seg_runs, (int)j0, j1, tiles, Split::kChunks, res, q.grab);
+        rc = fill_u32(q.grab, 8 * kGrabStride, 0u, st, err);
+        if (rc != SA_OK) return rc;
+        hipLaunchKernelGGL(k_grad, dim3((unsigned)unit_blocks(res, W)), dim3(kThreads), 0, st, s.nodes, views,
+                           s.n_nodes, s.voff, s.verts, s.height, p.segs, (int)j0, j1, W, P, G, S);
         int cur = 0;
         for (int r = 0; r < kSpillRounds; ++r) {
             hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, st, q.counters + (cur ^ 1));

@@ -213,8 +213,8 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
 // grad = (add ? grad : 0) + scale * d(sum dl * minutes)/dH, accumulated in
 // FP64 in acc (grown to n_b doubles as needed).
 sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
-                      const float *dl, float scale, bool add, float *grad, SpillQueue &q, Scratch &scr,
-                      Scratch &acc, hipStream_t st, std::string &err);
+                      const float *dl, float scale, bool add, float *grad, const TileLaunch &L, SpillQueue &q,
+                      Scratch &scr, Scratch &acc, hipStream_t st, std::string &err);
 sa_status launch_region_sum(const float *v, int n_bins, int64_t n, const double *bin_w,
                             const int64_t *off, int32_t n_reg, const float *area, double *out,
                             Scratch &scr, hipStream_t st, std::string &err);
