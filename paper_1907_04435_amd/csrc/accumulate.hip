@@ -78,8 +78,10 @@ __device__ __forceinline__ void sampled_put(const SampOut &O, int64_t o, int cnt
     if (O.longest) O.longest[o] = fmaxf(O.longest[o], best * O.scale);
 }
 
+// Eight waves per SIMD (the compiler's own choice gives seven): 128 ms
+// against 138 on the block scene's three days.
 template <bool kBits, bool kCount>
-__global__ __launch_bounds__(kThreads) void k_sampled(const Node *nodes_g, const float4 *verts_g,
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_sampled(const Node *nodes_g, const float4 *verts_g,
                                                       const float *height_g, const SampleConst *samples_g,
                                                       int K, Sched W, PointArgs P, SampOut O, uint64_t *work)
 {
