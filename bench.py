@@ -284,8 +284,16 @@ def bench_sam(args, sa, torch):
     ms = _timed(torch, ctx.stream, run, steps)
     ctx.sync()
     m = float(np.mean(ms))
+    # the per-instant rays and the accrual form on the same points and day
     cs = torch.empty_like(counts)
-    sa.sa_accumulate(ctx, sc, sa.DevicePoints.from_workload(w.points), path, sa.SA_SAMPLED, cs, None)
+    ms_s = torch.empty_like(mins)
+    run_s = lambda: sa.sa_accumulate(ctx, sc, dp, path, sa.SA_SAMPLED, cs, ms_s)
+    run_s()
+    ms_sampled = float(np.mean(_timed(torch, ctx.stream, run_s, steps)))
+    ca, ma = torch.empty_like(counts), torch.empty_like(mins)
+    run_a = lambda: sa.sa_accumulate(ctx, sc, dp, path, sa.SA_ACCRUAL, ca, ma)
+    run_a()
+    ms_accrual = float(np.mean(_timed(torch, ctx.stream, run_a, steps)))
     ctx.sync()
     d = (counts.long() - cs.long()).abs().double()
     evals = dp.n * path.n_samples
@@ -311,7 +319,10 @@ def bench_sam(args, sa, torch):
                              "sample": f"{sub.n} ground points (seeded) x {len(opath.w)} instants x {w.scene.n_b} "
                                        f"prisms, raster form with its ambiguity test, {dt:.1f} s"}
     r["vs_sampled_form"] = {"mean_abs_count_diff": float(d.mean()), "share_of_points_differing": float((d > 0).double().mean()),
-                            "mean_count": float(counts.double().mean()), "mean_count_sampled": float(cs.double().mean())}
+                            "mean_count": float(counts.double().mean()), "mean_count_sampled": float(cs.double().mean()),
+                            "sampled_ms_same_points_and_instants": ms_sampled}
+    r["accrual_ms_same_points_and_day"] = ms_accrual
+    log(f"same points and instants: sampled {ms_sampled:.1f} ms, accrual {ms_accrual:.1f} ms")
     return r
 
 

@@ -64,20 +64,31 @@ def test_batched_equals_variant_by_variant(ctx, c3small):
         assert (c != cb[:, off[v]:off[v + 1]]).mean() <= 1e-4
 
 
-def test_batched_matches_oracle(ctx, c3small):
-    w = c3small
+def test_batched_matches_oracle(ctx):
+    """Eight variants of the batched scenario workload (each with its own
+    evaluation region and eight buildings raised to 50-500 m) in one
+    persistent launch, 256 seeded points of every variant against the
+    oracle on that variant's scene, both days: the accrual parity bar per
+    point and day (p99.9 <= 0.01 min, mean <= 1e-3 min), counts within one
+    instant (an instant exactly at an interval end may go either way)."""
+    w = make_c3(n_var=8)
     cb, mb, keep = run_batched(ctx, w)
     off = w.extra["var_off"]
     rng = np.random.default_rng(5)
     op = oracle.sun_path(w.span, 30.0)
+    ds, dcs = [], []
     for v in range(len(off) - 1):
-        idx = np.sort(rng.choice(np.arange(off[v], off[v + 1]), 48, replace=False))
+        idx = np.sort(rng.choice(np.arange(off[v], off[v + 1]), 256, replace=False))
         o = oracle.continuous(variant_scene(w, v), w.points.take(idx), op)
         d = np.abs(mb[:, idx] - o["minutes"])
-        say(f"variant {v}: |A-D_L| max {d.max():.2e}")
-        assert np.quantile(d, 0.99) <= 0.01 and d.max() <= 0.5
-        dc = np.abs(cb[:, idx] - o["counts"])
-        assert dc.max() <= 1
+        say(f"variant {v}: {off[v + 1] - off[v]} points, |A-D_L| mean {d.mean():.2e} max {d.max():.2e}")
+        ds.append(d.ravel())
+        dcs.append(np.abs(cb[:, idx] - o["counts"]).ravel())
+    d, dc = np.concatenate(ds), np.concatenate(dcs)
+    say(f"8 variants x 256 points x 2 days: |A-D_L| mean {d.mean():.2e} p99.9 {np.quantile(d, 0.999):.2e} "
+        f"max {d.max():.2e}; counts off by one at {(dc > 0).mean():.2e} of point-days")
+    assert np.quantile(d, 0.999) <= 0.01 and d.mean() <= 1e-3 and d.max() <= 0.5
+    assert dc.max() <= 1
 
 
 def test_batched_grid_sizes_agree(ctx, c3small):
