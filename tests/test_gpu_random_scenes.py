@@ -82,10 +82,11 @@ def test_random_scene_parity(ctx, seed):
     o = oracle.sampled(scene, pts, op, bits=True, amb=True)
     frac, n_mism = check_sampled(g, o, op.w)
     say(f"  sampled: {g['K']} instants, ambiguous {frac:.2e}, mismatched bits {n_mism}")
-    # the bar: bit-exact except within the silhouette band, and at most 1e-4
-    # of the pairs excused that way (how many pairs the band holds is the
-    # scene's and the sky's: near the equator more walls run along the sun's
-    # path, up to 6e-4 of the pairs on one seed here)
+    # the bar: bit-exact outside the silhouette band (check_sampled), and at
+    # most 1e-4 of the pairs actually excused by it (measured: none on every
+    # seed).  How many pairs the band holds is the scene's and the sky's, not
+    # the kernel's: near the equator more roof edges run along the sun's
+    # path, 5.9e-4 of the pairs on one seed here; it is bounded loosely.
     assert n_mism <= 1e-4 * g["bits"].size and frac <= 1e-3
     for seg in (30.0, 60.0):
         ga = run_lib(ctx, scene, pts, span, sa.SA_ACCRUAL, seg_min=seg)
