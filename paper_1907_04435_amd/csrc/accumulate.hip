@@ -23,15 +23,21 @@ constexpr int kSpillRounds = 3;
 constexpr int kSpillBlocks = 1024;
 constexpr int64_t kChunkWork = 4000000000ll;  // point-segments per accrual launch
 constexpr int64_t kSegNodeBytes = 256ll << 20;  // per-segment node views per accrual launch
+constexpr int64_t kPieceBytes = 256ll << 20;    // per-piece sums of an accrual launch on few tiles
 
 // Per-bin outputs of the accrual kernels.  A bin whose first segment lies in
 // the launch is stored (no clear beforehand, no read); a bin continued from
 // an earlier launch, or any bin under SA_FLAG_ADD, is added to.  Each
-// (tile, bin) belongs to one unit, so the sums are deterministic.
+// (tile, bin) belongs to one unit, so the sums are deterministic.  With
+// pieces (pcnt non-null) a unit holds one piece of a bin's run instead and
+// writes its sums to its part's row of pcnt / pmin ([part][n]); a second
+// kernel adds a bin's pieces in order into the outputs.
 struct BinOut {
     int32_t *counts;
     float *minutes;
     double *minutes64;    // the FP64 lane sums behind minutes (optional)
+    int32_t *pcnt;        // per-piece sums, or null
+    double *pmin;
     int32_t fresh_first;  // the launch's first bin starts in it
     int32_t fresh_rest;   // the later bins of the launch start in it
     float scale;          // minutes are multiplied by this
@@ -444,9 +450,41 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
             if (ballot(valid && ov))
                 spill_push(lds_uniform<SpillArgs>((lds_int *)s_S), valid && ov, i, j, 0.f, gm.theta);
         }
-        if (valid && jb > ja) put_bin(lds_uniform<BinOut>((lds_int *)s_O), (int64_t)bin * n + i, fresh, cnt, mins);
+        const BinOut Oe = lds_uniform<BinOut>((lds_int *)s_O);
+        if (Oe.pcnt) {
+            // a piece of one bin's run: its sums go to the part's row
+            if (valid) {
+                Oe.pcnt[(int64_t)un.part * n + i] = cnt;
+                Oe.pmin[(int64_t)un.part * n + i] = mins;
+            }
+        } else if (valid && jb > ja) {
+            put_bin(Oe, (int64_t)bin * n + i, fresh, cnt, mins);
+        }
     }
     if constexpr (kCount) flush_work(wk, work);
+}
+
+// Adds the pieces of every run of a launch, in piece order, into the run's
+// bin: the launch's first run is stored or added to as O says for the
+// launch's first bin, the others as for its later bins.
+__global__ void k_add_pieces(Sched W, int j0, int j1, const SegConst *__restrict__ segs, int64_t n, BinOut O)
+{
+    const int sub = W.sub > 1 ? W.sub : 1;
+    const int runs = (int)W.n_parts / sub;
+    const int64_t total = (int64_t)runs * n;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+        const int r = (int)(t / n);
+        const int64_t i = t - (int64_t)r * n;
+        int cnt = 0;
+        double mins = 0.0;
+        for (int p = r * sub; p < (r + 1) * sub; ++p) {
+            cnt += O.pcnt[(int64_t)p * n + i];
+            mins += O.pmin[(int64_t)p * n + i];
+        }
+        const int bin = segs[max(W.part_start[r], j0)].bin;
+        put_bin(O, (int64_t)bin * n + i, (r == 0 ? O.fresh_first : O.fresh_rest) != 0, cnt, mins);
+    }
 }
 
 // Continuous shadow (Sec. 3.1) over one window [w0, w1] whose occluded set
@@ -1209,13 +1247,13 @@ static BinOut bin_out(const DevicePath &p, int j0, bool store, int32_t *counts, 
                       float scale)
 {
     const bool first = store && (j0 == 0 || p.seg_bin[j0 - 1] != p.seg_bin[j0]);
-    return BinOut{counts, minutes, minutes64, first ? 1 : 0, store ? 1 : 0, scale, 0};
+    return BinOut{counts, minutes, minutes64, nullptr, nullptr, first ? 1 : 0, store ? 1 : 0, scale, 0};
 }
 
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts, float scale,
                          int32_t *counts, float *minutes, double *minutes64, float *longest, uint64_t *work,
-                         bool store, const TileLaunch &L, SpillQueue &q, Scratch &scr, hipStream_t st,
-                         std::string &err)
+                         bool store, const TileLaunch &L, SpillQueue &q, Scratch &scr, Scratch &piece_scr,
+                         hipStream_t st, std::string &err)
 {
     const int32_t seg_per_launch = L.segments_per_launch;
     if (pts.n == 0) return SA_OK;
@@ -1267,6 +1305,36 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
     }
     auto kern = work ? k_accrual<true> : k_accrual<false>;
     const int64_t res = resident_blocks(kern, L);
+    // Too few tiles to give every resident wave several (tile, bin) units:
+    // each bin's run is then cut into pieces, held as per-piece sums in
+    // piece_scr ([part][n] counts and FP64 minutes) and added up in order
+    // by a second kernel, so the results stay deterministic.  Without room
+    // for the sums (a fixed scratch), whole runs.
+    const bool pieces = tiles < 2 * res * kWaves;
+    int64_t max_parts = 1;
+    if (pieces) {
+        const int64_t per_part = (int64_t)pts.n * (int64_t)(sizeof(int32_t) + sizeof(double));
+        if (piece_scr.fixed) {
+            max_parts = (int64_t)piece_scr.bytes / per_part;
+        } else {
+            max_parts = std::max<int64_t>(1, kPieceBytes / per_part);
+            const size_t need = (size_t)(std::min<int64_t>(max_parts, 8 * res * kWaves) * per_part);
+            if (piece_scr.bytes < need) {
+                (void)hipStreamSynchronize(st);  // earlier launches may still read it
+                (void)hipFree(piece_scr.ptr);
+                piece_scr.ptr = nullptr;
+                piece_scr.bytes = 0;
+                if (hipMalloc(&piece_scr.ptr, need) != hipSuccess) {
+                    (void)hipGetLastError();
+                    piece_scr.ptr = nullptr;
+                    err = "accrual piece sums allocation failed";
+                    return SA_ERR_OOM;
+                }
+                piece_scr.bytes = need;
+            }
+            max_parts = (int64_t)piece_scr.bytes / per_part;
+        }
+    }
     for (int64_t j0 = 0; j0 < p.n_segs; j0 += per) {
         const int j1 = (int)std::min<int64_t>(j0 + per, p.n_segs);
         SegNode *views;
@@ -1274,13 +1342,24 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
         if (rc != SA_OK) return rc;
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, st, q.counters);
         SpillArgs S{q.entries[0], q.counters, q.counters + 2, q.capacity};
-        const Sched W = plan_units(p.seg_runs, (int)j0, j1, tiles, Split::kUniqueBins, res, q.grab);
+        const Sched W = plan_units(p.seg_runs, (int)j0, j1, tiles, pieces ? Split::kRunPieces : Split::kUniqueBins,
+                                   res, q.grab, max_parts);
+        BinOut O = bin_out(p, (int)j0, store, counts, minutes, minutes64, scale);
+        if (W.sub > 1) {
+            O.pcnt = (int32_t *)piece_scr.ptr;
+            O.pmin = (double *)((char *)piece_scr.ptr + (size_t)W.n_parts * (size_t)pts.n * sizeof(int32_t));
+        }
         rc = fill_u32(q.grab, 8 * kGrabStride, 0u, st, err);
         if (rc != SA_OK) return rc;
         hipLaunchKernelGGL(kern, dim3((unsigned)unit_blocks(res, W)), dim3(kThreads), 0, st, nodes, views, s.n_nodes,
-                           s.voff, s.verts, s.height, p.segs, (int)j0, j1, W, P,
-                           bin_out(p, (int)j0, store, counts, minutes, minutes64, scale), S, work);
+                           s.voff, s.verts, s.height, p.segs, (int)j0, j1, W, P, O, S, work);
         SA_CHECK_LAUNCH("accrual kernel");
+        if (W.sub > 1) {
+            const int64_t total = (int64_t)(W.n_parts / W.sub) * pts.n;
+            hipLaunchKernelGGL(k_add_pieces, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 65536)), dim3(256),
+                               0, st, W, (int)j0, j1, (const SegConst *)p.segs, pts.n, O);
+            SA_CHECK_LAUNCH("accrual piece sums");
+        }
         rc = run_spill(s, p, views, (int)j0, P, scale, counts, minutes, minutes64, q, st, err);
         if (rc != SA_OK) return rc;
     }

@@ -26,6 +26,7 @@ struct sa_ctx {
     sa::Scratch scratch_sam;      // one segment's raster shadow accrual map
     sa::Scratch scratch_grad;     // FP64 height-gradient accumulator
     sa::Scratch scratch_w;        // per-bin weights of a region score
+    sa::Scratch scratch_piece;    // per-piece sums of accrual launches on few tiles
     uint32_t sam_stamp = 0;       // the last segment stamp written into it
     sa_launch launch = {0, 0, 1, 0};  // tuning choices (sa_set_launch)
     int32_t n_cu = 256;           // compute units of the device
@@ -204,6 +205,7 @@ void sa_destroy(sa_ctx *ctx)
     (void)hipFree(ctx->scratch_sam.ptr);
     (void)hipFree(ctx->scratch_grad.ptr);
     (void)hipFree(ctx->scratch_w.ptr);
+    (void)hipFree(ctx->scratch_piece.ptr);
     delete ctx;
 }
 
@@ -835,7 +837,7 @@ sa_status sa_accumulate(sa_ctx *ctx, const sa_scene *scene, const sa_points *pts
     else
         rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->minutes64,
                                 opts->longest, opts->work, store, tile_launch(ctx), ctx->spill,
-                                ctx->scratch_seg, ctx->stream, err);
+                                ctx->scratch_seg, ctx->scratch_piece, ctx->stream, err);
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate: " + err);
     return SA_OK;
 }
@@ -890,9 +892,11 @@ sa_status sa_accumulate_noalloc(sa_ctx *ctx, const sa_scene *scene, const sa_poi
         fixed.ptr = ctx->noalloc;
         fixed.bytes = (size_t)SA_NOALLOC_SCRATCH_BYTES;
         fixed.fixed = true;
+        sa::Scratch no_pieces;  // whole runs: nothing to allocate
+        no_pieces.fixed = true;
         rc = sa::launch_accrual(scene->d, path->d, view(pts), scale, counts, minutes, opts->minutes64,
                                 opts->longest, opts->work, store, tile_launch(ctx), ctx->spill,
-                                fixed, ctx->stream, err);
+                                fixed, no_pieces, ctx->stream, err);
     }
     if (rc != SA_OK) return fail(ctx, rc, "sa_accumulate_noalloc: " + err);
     return SA_OK;

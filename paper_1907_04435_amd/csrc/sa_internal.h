@@ -206,10 +206,12 @@ sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const Points
 // store: outputs need no clearing (no SA_FLAG_ADD and p.bins_contiguous):
 // each bin is stored by the launch holding its first segment.
 // L: the launch choices (segments per launch, persistent grid size).
+// piece_scr: per-piece sums when the tiles are too few to fill the device
+// (grown on demand unless fixed; a fixed one of 0 bytes keeps whole runs).
 sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
                          float scale, int32_t *counts, float *minutes, double *minutes64, float *longest,
                          uint64_t *work, bool store, const TileLaunch &L, SpillQueue &q, Scratch &scr,
-                         hipStream_t st, std::string &err);
+                         Scratch &piece_scr, hipStream_t st, std::string &err);
 // grad = (add ? grad : 0) + scale * d(sum dl * minutes)/dH, accumulated in
 // FP64 in acc (grown to n_b doubles as needed).
 sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsView &pts,

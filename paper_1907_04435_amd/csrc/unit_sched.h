@@ -29,18 +29,19 @@ constexpr int kSchedWaves = kSchedThreads / 64;  // waves per block
 constexpr int kGrabStride = 32;                  // words between the eight counters (one 128-byte line each)
 
 struct Sched {
-    const int32_t *part_start;  // [n_parts + 1] first item of each part (clipped to the launch), or null
+    const int32_t *part_start;  // first item of each bin run of the launch (clipped to it), or null
     uint32_t *grab;             // eight counters, kGrabStride words apart, zero at launch
     uint32_t n_tiles;
     uint32_t n_parts;
     int32_t chunk;  // without part_start: items per part (0: one part, every item)
-    int32_t pad;
+    int32_t sub;    // with part_start: equal pieces each run is cut into (0 or 1: whole runs)
 };
 
 namespace dev {
 
 struct Unit {
     uint32_t tile;
+    uint32_t part;
     int a, b;  // the unit's items [a, b)
 };
 
@@ -68,9 +69,14 @@ __device__ __forceinline__ bool next_unit(const lds_int *s_W, int a0, int a1, in
             const uint32_t tile = (uint32_t)uniform((int)(u / W.n_parts));
             const uint32_t part = u - tile * W.n_parts;
             un.tile = tile;
+            un.part = part;
             if (W.part_start) {
-                un.a = max(ld((cint *)W.part_start + part), a0);
-                un.b = min(ld((cint *)W.part_start + part + 1), a1);
+                const uint32_t sub = W.sub > 1 ? (uint32_t)W.sub : 1u;
+                const uint32_t run = part / sub, piece = part - run * sub;
+                const int ra = max(ld((cint *)W.part_start + run), a0);
+                const int rb = min(ld((cint *)W.part_start + run + 1), a1);
+                un.a = ra + (int)((int64_t)(rb - ra) * piece / sub);
+                un.b = ra + (int)((int64_t)(rb - ra) * (piece + 1) / sub);
             } else if (W.chunk > 0) {
                 un.a = a0 + (int)part * W.chunk;
                 un.b = min(un.a + W.chunk, a1);
@@ -94,6 +100,8 @@ enum class Split {
     kBinRuns,     // a part per bin run (outputs added atomically)
     kChunks,      // parts of a fixed number of items, enough units to keep every
                   // wave busy (outputs added atomically)
+    kRunPieces,   // as kUniqueBins, each run cut into equal pieces, enough units to
+                  // keep every wave busy (per-piece sums, added in a fixed order after)
 };
 
 // Blocks of a persistent launch of `kern`: the tuned count, else as many
@@ -114,7 +122,7 @@ static int64_t resident_blocks(Kern kern, const TileLaunch &L)
 // instants, whose bin runs are R) for `tiles` 64-point tiles; `blocks` is
 // the launch size (the chunk mode aims at eight units per wave).
 static inline Sched plan_units(const BinRuns &R, int a0, int a1, int64_t tiles, Split split, int64_t blocks,
-                               uint32_t *grab)
+                               uint32_t *grab, int64_t max_parts = 1)
 {
     Sched W{nullptr, grab, (uint32_t)tiles, 1u, 0, 0};
     if (split == Split::kNone || a1 <= a0) return W;
@@ -132,14 +140,29 @@ static inline Sched plan_units(const BinRuns &R, int a0, int a1, int64_t tiles, 
     const auto &rs = R.start;
     const int r0 = (int)(std::upper_bound(rs.begin(), rs.end(), a0) - rs.begin()) - 1;
     const int r1 = (int)(std::upper_bound(rs.begin(), rs.end(), a1 - 1) - rs.begin()) - 1;
-    if (r1 <= r0 || (uint64_t)tiles * (uint64_t)(r1 - r0 + 1) >= (1ull << 31)) return W;
-    if (split == Split::kUniqueBins) {
+    if ((r1 <= r0 && split != Split::kRunPieces) || (uint64_t)tiles * (uint64_t)(r1 - r0 + 1) >= (1ull << 31))
+        return W;
+    if (split == Split::kUniqueBins || split == Split::kRunPieces) {
         std::vector<int32_t> bins(R.bin.begin() + r0, R.bin.begin() + r1 + 1);
         std::sort(bins.begin(), bins.end());
         if (std::adjacent_find(bins.begin(), bins.end()) != bins.end()) return W;
     }
     W.part_start = R.dev + r0;
-    W.n_parts = (uint32_t)(r1 - r0 + 1);
+    const int64_t runs = r1 - r0 + 1;
+    W.n_parts = (uint32_t)runs;
+    if (split == Split::kRunPieces) {
+        // pieces per run: eight units per resident wave, no piece shorter
+        // than one item, no more parts than the caller can hold
+        int shortest = a1 - a0;
+        for (int r = r0; r <= r1; ++r) shortest = std::min(shortest, std::min(rs[r + 1], a1) - std::max(rs[r], a0));
+        const int64_t want = (8 * blocks * kSchedWaves + tiles * runs - 1) / (tiles * runs);
+        int64_t sub = std::min<int64_t>(std::min<int64_t>(want, shortest), std::max<int64_t>(1, max_parts / runs));
+        while (sub > 1 && (uint64_t)tiles * (uint64_t)(runs * sub) >= (1ull << 31)) sub /= 2;
+        if (sub > 1) {
+            W.sub = (int32_t)sub;
+            W.n_parts = (uint32_t)(runs * sub);
+        }
+    }
     return W;
 }
 

@@ -99,3 +99,32 @@ def test_bad_launch_values(ctx):
     with pytest.raises(sa.SAError):
         ctx.set_launch(tile_grid_blocks=-3)
     assert ctx.get_launch()["batched_tiles_per_grab"] == 1
+
+
+def test_few_tiles_pieces_deterministic(ctx):
+    """On few tiles the accrual form cuts each bin's run into pieces and adds
+    the pieces' sums in a fixed order: two calls give bit-identical counts,
+    minutes and FP64 minutes, and they equal whole runs per unit (a
+    one-block launch) up to float rounding."""
+    import torch
+    w = make_c2(n_ground=3_000, n_facade=3_000)
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    dp = sa.DevicePoints.from_workload(w.points)
+    path = sa.Path(ctx, sa.sunpath_for_span(w.span, 30.0))
+    res = []
+    for gb in (0, 0, 1):
+        ctx.set_launch(tile_grid_blocks=gb)
+        c = torch.empty((path.n_bins, dp.n), dtype=torch.int32, device="cuda")
+        m = torch.empty((path.n_bins, dp.n), dtype=torch.float32, device="cuda")
+        m64 = torch.empty((path.n_bins, dp.n), dtype=torch.float64, device="cuda")
+        sa.sa_accumulate(ctx, sc, dp, path, sa.SA_ACCRUAL, c, m, minutes64=m64)
+        ctx.sync()
+        res.append((c.cpu().numpy(), m.cpu().numpy(), m64.cpu().numpy()))
+    ctx.set_launch()
+    for a, b in zip(res[0], res[1]):
+        np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(res[0][0], res[2][0])
+    d = np.abs(res[0][2] - res[2][2]).max()
+    say(f"  pieces vs whole runs: counts equal, max |FP64 minutes diff| {d:.2e}")
+    assert d <= 1e-9 * max(1.0, np.abs(res[2][2]).max())
+    assert np.abs(res[0][1] - res[2][1]).max() <= 1e-3
