@@ -91,6 +91,10 @@ typedef struct {
                                             blocks (of 256 threads) of their persistent launches, whose
                                             waves take (64-point tile, bin) units from a work counter
                                             per XCD; 0 = as many as the device holds at once */
+    int32_t accrual_waves_per_simd;      /* accrual form: occupancy variant of its kernel, 6, 7 or 8
+                                            waves per SIMD (registers per lane shrink as it grows);
+                                            0 = 8 */
+    int32_t reserved[3];                 /* 0 */
 } sa_launch;
 /* Errors: INVALID_ARG (negative or out-of-range values). */
 sa_status sa_set_launch(sa_ctx *ctx, const sa_launch *launch);

@@ -374,11 +374,12 @@ __device__ __forceinline__ bool roof_covered(cNode *nodes, StackEntry *stack, cf
     return lane_in(covm);
 }
 
-// Eight waves per SIMD: the kernel fits in 64 VGPRs (the compiler would
-// settle for fewer waves otherwise), which hides more of the scalar-load
-// and compare-chain latency of the traversal loop.
-template <bool kCount>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_accrual(
+// kOcc waves per SIMD, a launch choice (6, 7 or 8; the tuner measures
+// them).  At 8 the kernel fits in 64 VGPRs (the compiler would settle for
+// fewer waves otherwise), which hides more of the scalar-load and
+// compare-chain latency of the traversal loop.
+template <bool kCount, int kOcc>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kOcc))) void k_accrual(
     const Node *nodes_g, const SegNode *snodes_g, int n_nodes, const int32_t *voff_g, const float4 *verts_g,
     const float *height_g, const SegConst *segs_g, int j0, int j1, Sched W, PointArgs P, BinOut O, SpillArgs S,
     uint64_t *work)
@@ -1303,7 +1304,9 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
         }
         return SA_OK;
     }
-    auto kern = work ? k_accrual<true> : k_accrual<false>;
+    auto kern = work ? k_accrual<true, 8> : k_accrual<false, 8>;
+    if (L.waves_per_simd == 6) kern = work ? k_accrual<true, 6> : k_accrual<false, 6>;
+    if (L.waves_per_simd == 7) kern = work ? k_accrual<true, 7> : k_accrual<false, 7>;
     const int64_t res = resident_blocks(kern, L);
     // Too few tiles to give every resident wave several (tile, bin) units:
     // each bin's run is then cut into pieces, held as per-piece sums in
@@ -1382,8 +1385,10 @@ sa_status launch_contribution(const DeviceScene &s, const DevicePath &p, const P
         SegNode *views;
         sa_status rc = build_seg_views(s, p, (int)j0, j1, s.n_nodes, scr, st, views, err);
         if (rc != SA_OK) return rc;
+        // the sums are atomic: on few tiles the units are chunks of segments
         const int64_t res = resident_blocks(k_contrib, L);
-        const Sched W = plan_units(p.seg_runs, (int)j0, j1, tiles, Split::kBinRuns, res, grab);
+        const Split split = tiles < 2 * res * kWaves ? Split::kChunks : Split::kBinRuns;
+        const Sched W = plan_units(p.seg_runs, (int)j0, j1, tiles, split, res, grab);
         rc = fill_u32(grab, 8 * kGrabStride, 0u, st, err);
         if (rc != SA_OK) return rc;
         hipLaunchKernelGGL(k_contrib, dim3((unsigned)unit_blocks(res, W)), dim3(kThreads), 0, st, views,

@@ -192,11 +192,13 @@ struct SpillQueue {
 // Launch choices of the per-tile kernels: the most segments one accrual
 // launch covers (0: as many as the view budget allows) and the blocks of
 // the persistent launches (0: as many as the device holds at once, from
-// the kernel's occupancy and the device's compute units).
+// the kernel's occupancy and the device's compute units) and the accrual
+// kernel's occupancy variant.
 struct TileLaunch {
     int32_t segments_per_launch;
     int64_t grid_blocks;
     int32_t n_cu;
+    int32_t waves_per_simd;  // the accrual kernel's occupancy variant: 6, 7 or 8 (0: 8)
 };
 
 sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const PointsView &pts,

@@ -5,6 +5,8 @@
   set), timed on the block scene's 4M points over three days.
 * ``tile_grid_blocks``: blocks of the persistent per-tile launches (0: as
   many as the device holds at once), timed on the same accrual launch.
+* ``accrual_waves_per_simd``: the accrual kernel's occupancy variant (6, 7
+  or 8 waves per SIMD), timed on the same launch.
 * ``batched_grid_blocks`` x ``batched_tiles_per_grab``: size of the
   persistent (variant, tile) launch of sa_accumulate_batched and how many
   64-point tiles a wave takes per atomic, timed on a 32-variant slice of
@@ -36,7 +38,8 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
-LAUNCH_KEYS = ("accrual_segments_per_launch", "batched_grid_blocks", "batched_tiles_per_grab", "tile_grid_blocks")
+LAUNCH_KEYS = ("accrual_segments_per_launch", "batched_grid_blocks", "batched_tiles_per_grab", "tile_grid_blocks",
+               "accrual_waves_per_simd")
 
 
 def _time(torch, stream, fn, reps=3):
@@ -99,10 +102,17 @@ def tune_accrual(sa, torch, ctx, log):
         ctx.set_launch(accrual_segments_per_launch=best, tile_grid_blocks=gb)
         gres[gb] = _time(torch, ctx.stream, run)
         log(f"accrual, persistent grid {gb or 'device-resident'} blocks: {gres[gb]:.2f} ms")
-    ctx.set_launch()
     gbest = min(gres, key=gres.get)
-    return (best, gbest), {"segments_per_launch": {str(k): v for k, v in res.items()},
-                           "grid_blocks": {str(k): v for k, v in gres.items()}}
+    wres = {}
+    for occ in (8, 7, 6):
+        ctx.set_launch(accrual_segments_per_launch=best, tile_grid_blocks=gbest, accrual_waves_per_simd=occ)
+        wres[occ] = _time(torch, ctx.stream, run)
+        log(f"accrual, {occ} waves per SIMD: {wres[occ]:.2f} ms")
+    ctx.set_launch()
+    wbest = min(wres, key=wres.get)
+    return (best, gbest, wbest), {"segments_per_launch": {str(k): v for k, v in res.items()},
+                                  "grid_blocks": {str(k): v for k, v in gres.items()},
+                                  "waves_per_simd": {str(k): v for k, v in wres.items()}}
 
 
 def tune_batched(sa, torch, ctx, log):
@@ -162,10 +172,11 @@ def main():
     ctx = sa.Context(0)
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     t0 = time.time()
-    (per, tgb), ares = tune_accrual(sa, torch, ctx, log)
+    (per, tgb, occ), ares = tune_accrual(sa, torch, ctx, log)
     (gb, grab), bres = tune_batched(sa, torch, ctx, log)
     L, lres = tune_seg(sa, torch, ctx, log, args.error_bar, args.tail_bar)
-    out = {"arch": arch, "accrual_segments_per_launch": per, "tile_grid_blocks": tgb, "batched_grid_blocks": gb,
+    out = {"arch": arch, "accrual_segments_per_launch": per, "tile_grid_blocks": tgb,
+           "accrual_waves_per_simd": occ, "batched_grid_blocks": gb,
            "batched_tiles_per_grab": grab, "seg_min": L, "error_bar": args.error_bar, "tail_bar": args.tail_bar,
            "accrual_sweep_ms": ares, "batched_sweep_ms": bres, "seg_sweep": lres, "seconds": time.time() - t0}
     with open(CACHE, "w") as f:

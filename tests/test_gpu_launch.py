@@ -91,6 +91,27 @@ def test_batched_grid_and_grab(ctx):
         assert np.abs(m - res[0][1]).max() <= 1e-3
 
 
+def test_accrual_waves_per_simd(ctx):
+    """The accrual kernel's occupancy variants (6, 7, 8 waves per SIMD) give
+    equal counts and minutes equal to the last bits (the same arithmetic in
+    other registers)."""
+    w = make_c2(n_ground=20_000, n_facade=20_000)
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    dp = sa.DevicePoints.from_workload(w.points)
+    path = sa.Path(ctx, sa.sunpath_for_span(w.span, 30.0))
+    out = {}
+    for occ in (8, 7, 6):
+        ctx.set_launch(accrual_waves_per_simd=occ)
+        assert ctx.get_launch()["accrual_waves_per_simd"] == occ
+        c, m, _ = sa.accumulate(ctx, sc, dp, path, sa.SA_ACCRUAL)
+        ctx.sync()
+        out[occ] = (c.cpu().numpy(), m.cpu().numpy())
+    ctx.set_launch()
+    for occ in (7, 6):
+        np.testing.assert_array_equal(out[occ][0], out[8][0])
+        assert np.abs(out[occ][1] - out[8][1]).max() <= 1e-3
+
+
 def test_bad_launch_values(ctx):
     with pytest.raises(sa.SAError):
         ctx.set_launch(accrual_segments_per_launch=-1)
@@ -98,6 +119,8 @@ def test_bad_launch_values(ctx):
         ctx.set_launch(batched_tiles_per_grab=5000)
     with pytest.raises(sa.SAError):
         ctx.set_launch(tile_grid_blocks=-3)
+    with pytest.raises(sa.SAError):
+        ctx.set_launch(accrual_waves_per_simd=5)
     assert ctx.get_launch()["batched_tiles_per_grab"] == 1
 
 
