@@ -685,8 +685,9 @@ __global__ __launch_bounds__(kThreads) void k_spill(const SegNode *snodes_g, int
 // (a lane whose window is already shadowed keeps walking: later buildings
 // still count).  The lanes' weighted minutes for one leaf are summed across
 // the wave and added with one FP64 atomic; a back-facing wall counts for
-// the point's own building.
-__global__ __launch_bounds__(kThreads) void k_contrib(const SegNode *snodes_g, int n_nodes, const int32_t *voff_g,
+// the point's own building.  Eight waves per SIMD (56 VGPRs): 17.5 ms on
+// the block scene against 19.4 at the compiler's seven.
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_contrib(const SegNode *snodes_g, int n_nodes, const int32_t *voff_g,
                                                       const float4 *verts_g, const float *height_g,
                                                       const SegConst *segs_g, int j0, int j1, Sched W, PointArgs P,
                                                       const float *weight, const int32_t *order, int n_b,

@@ -1,5 +1,6 @@
 """sa_accumulate inside a captured HIP graph: both forms, the spill rounds
-(ring of poles) and the continuous-shadow kernel.  Every replay, with eager
+(ring of poles), the continuous-shadow kernel and the allocation-free entry
+point (whose work counters and clears are fill kernels).  Every replay, with eager
 work and synchronisations between replays, must equal the eager result:
 exactly for counts, and to float rounding for minutes where the spill
 rounds add with atomics (their order, hence the last bits, varies between
@@ -50,7 +51,8 @@ def capture_and_replay(ctx, call, outputs):
         _ = (torch.ones(4096, device="cuda") * r).sum().item()   # eager work between replays
 
 
-@pytest.mark.parametrize("case", ["accrual_small", "sampled_small", "accrual_ring", "continuous_ring"])
+@pytest.mark.parametrize("case", ["accrual_small", "sampled_small", "accrual_ring", "continuous_ring",
+                                  "accrual_noalloc"])
 def test_accumulate_graph_replay(ctx, c1, case):
     import torch
     if case.endswith("ring"):
@@ -67,7 +69,9 @@ def test_accumulate_graph_replay(ctx, c1, case):
     mode = sa.SA_SAMPLED if case.startswith("sampled") else sa.SA_ACCRUAL
     outs = [counts, mins] + ([longest] if longest is not None else [])
 
+    fn = sa.sa_accumulate_noalloc if case.endswith("noalloc") else sa.sa_accumulate
+
     def call():
-        sa.sa_accumulate(ctx, sc, dp, path, mode, counts, mins, longest=longest)
+        fn(ctx, sc, dp, path, mode, counts, mins, longest=longest)
 
     capture_and_replay(ctx, call, outs)
