@@ -1317,12 +1317,13 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
     const bool pieces = tiles < 2 * res * kWaves;
     int64_t max_parts = 1;
     if (pieces) {
+        // counts of every part, then (256-byte aligned) their FP64 minutes
         const int64_t per_part = (int64_t)pts.n * (int64_t)(sizeof(int32_t) + sizeof(double));
         if (piece_scr.fixed) {
-            max_parts = (int64_t)piece_scr.bytes / per_part;
+            max_parts = std::max<int64_t>(0, (int64_t)piece_scr.bytes - 256) / per_part;
         } else {
             max_parts = std::max<int64_t>(1, kPieceBytes / per_part);
-            const size_t need = (size_t)(std::min<int64_t>(max_parts, 8 * res * kWaves) * per_part);
+            const size_t need = (size_t)(std::min<int64_t>(max_parts, 8 * res * kWaves) * per_part) + 256;
             if (piece_scr.bytes < need) {
                 (void)hipStreamSynchronize(st);  // earlier launches may still read it
                 (void)hipFree(piece_scr.ptr);
@@ -1336,7 +1337,7 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
                 }
                 piece_scr.bytes = need;
             }
-            max_parts = (int64_t)piece_scr.bytes / per_part;
+            max_parts = ((int64_t)piece_scr.bytes - 256) / per_part;
         }
     }
     for (int64_t j0 = 0; j0 < p.n_segs; j0 += per) {
@@ -1350,8 +1351,9 @@ sa_status launch_accrual(const DeviceScene &s, const DevicePath &p, const Points
                                    res, q.grab, max_parts);
         BinOut O = bin_out(p, (int)j0, store, counts, minutes, minutes64, scale);
         if (W.sub > 1) {
+            const size_t cnt_bytes = (size_t)W.n_parts * (size_t)pts.n * sizeof(int32_t);
             O.pcnt = (int32_t *)piece_scr.ptr;
-            O.pmin = (double *)((char *)piece_scr.ptr + (size_t)W.n_parts * (size_t)pts.n * sizeof(int32_t));
+            O.pmin = (double *)((char *)piece_scr.ptr + ((cnt_bytes + 255) & ~(size_t)255));
         }
         rc = fill_u32(q.grab, 8 * kGrabStride, 0u, st, err);
         if (rc != SA_OK) return rc;
