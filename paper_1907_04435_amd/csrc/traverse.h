@@ -63,15 +63,6 @@ constexpr int kStackDepth = 64;
 __device__ __forceinline__ float pad_lo(float v) { return v - (1e-2f + fabsf(v) * 0x1p-20f); }
 __device__ __forceinline__ float pad_hi(float v) { return v + (1e-2f + fabsf(v) * 0x1p-20f); }
 
-// Map a block index so that each XCD (blocks are dealt round-robin to the
-// 8 XCDs) works on one contiguous range of tiles: neighbouring tiles share
-// hierarchy nodes and prisms in that XCD's L2.
-__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t G)
-{
-    const int64_t x = b & 7, q = G >> 3, r = G & 7;
-    return x * q + (x < r ? x : r) + (b >> 3);
-}
-
 // Work a lane's own traversal needed (instrumented instantiations only).
 struct Work {
     uint32_t box, prism, edges, inserts, nodes, units, spills, leaves;
