@@ -218,6 +218,142 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     if constexpr (kCount) flush_work(wk, work);
 }
 
+// The sampled form in 8 x 8 packets: a wave holds 8 points of its tile (a
+// point per 8 lanes) at 8 consecutive instants (an instant per lane within
+// the 8), and walks the instants of its unit 8 at a time.  The 8 points
+// are neighbours and the 8 directions lie within minutes of each other, so
+// the packet's rays share more of the hierarchy than 64 points at one
+// instant (block scene: 22 % fewer node visits per packet, 97.7 against
+// 129 ms).  A unit is one bin's run of instants, so every lane's instant
+// falls in the unit's bin; bit vectors (32 instants a word, across bins)
+// stay with k_sampled.  The occluder cache keeps the prism that blocked the
+// most lanes of the previous 8 instants.  The continuous shadow follows the
+// instants in order: the 8 instants of a packet are the same for every
+// point, so each lane replays its point's 8 results (their ballot bits) with
+// the instants' weights read wave-uniform.
+template <bool kCount>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_sampled8(
+    const Node *nodes_g, const float4 *verts_g, const float *height_g, const SampleConst *samples_g, int K, Sched W,
+    PointArgs P, SampOut O, uint64_t *work)
+{
+    Work wk{0, 0, 0, 0, 0, 0, 0};
+    cNode *nodes = (cNode *)nodes_g;
+    cfloat4 *verts = (cfloat4 *)verts_g;
+    cfloat *height = (cfloat *)height_g;
+    cSample *samples = (cSample *)samples_g;
+    __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    __shared__ int s_W[sizeof(Sched) / 4];
+    __shared__ int s_P[sizeof(PointArgs) / 4];
+    __shared__ int s_O[sizeof(SampOut) / 4];
+    if (threadIdx.x == 0) {
+        lds_park((lds_int *)s_W, W);
+        lds_park((lds_int *)s_P, P);
+        lds_park((lds_int *)s_O, O);
+    }
+    __syncthreads();
+    StackEntry *stack = s_stack[threadIdx.x >> 6];
+    const int lane = threadIdx.x & 63;
+    const int slot = lane & 7;    // the lane's instant within the packet
+    const int grp8 = lane & ~7;   // first lane of the lane's point
+    int kx = 0;
+    Unit un;
+    while (next_unit((lds_int *)s_W, 0, K, kx, un)) {
+        const int ka = uniform(un.a), kb = uniform(un.b);
+        if (kb <= ka) continue;
+        const PointArgs Pd = lds_uniform<PointArgs>((lds_int *)s_P);
+        const int64_t n = Pd.n;
+        const int bin = ld(samples + ka).tag & kBinMask;
+        for (int g = 0; g < 8; ++g) {
+            const int64_t i0 = (int64_t)un.tile * 64 + g * 8;  // the packet's first point
+            if (i0 >= n) break;
+            const int64_t i = i0 + (lane >> 3);
+            const bool pvalid = i < n;
+            const LanePoint q = load_point(Pd, pvalid ? i : 0, pvalid);
+            int cnt = 0;
+            float mins = 0.f, run = 0.f, best = 0.f;
+            int c_prim = -1, c_voff = 0, c_m = 0;
+            for (int c0 = ka; c0 < kb; c0 += 8) {
+                const int k = c0 + slot;
+                const bool valid = pvalid && k < kb;
+                const SampleConst s = samples_g[k < kb ? k : ka];
+                // the packet's middle direction orders the children
+                const SampleConst sm = ld(samples + uniform((c0 + min(c0 + 7, kb - 1)) >> 1));
+                const bool back = q.own >= 0 && fmaf(q.nx, s.dx, q.ny * s.dy) <= 0.f;
+                uint64_t hitm = 0;
+                int b_prim = -1, b_voff = 0, b_m = 0, b_cnt = 0;
+                if (nodes_g != nullptr) {
+                    const float ox = -q.px * s.ix, oy = -q.py * s.iy, oz = -q.pz * s.iz;
+                    auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
+                        const float ax = fmaf(x0, s.ix, ox), bx = fmaf(x1, s.ix, ox);
+                        const float ay = fmaf(y0, s.iy, oy), by = fmaf(y1, s.iy, oy);
+                        const float tfz = fmaf(z1, s.iz, oz);
+                        const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), 0.f);
+                        const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), tfz);
+                        return le_mask(tn, tf);
+                    };
+                    bool cached_seen = false;
+                    auto leaf = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
+                        if (prim == c_prim) {
+                            if (cached_seen) return 0;
+                            cached_seen = true;
+                        }
+                        const bool go = lane_in(want & ballot(prim != q.own));
+                        if constexpr (kCount) {
+                            wk.prism += go ? 1u : 0u;
+                            wk.edges += go ? (uint32_t)m : 0u;
+                            wk.leaves += first_active_lane() ? 1u : 0u;
+                        }
+                        const bool t =
+                            go & ray_prism(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, s.dx, s.dy, s.dz);
+                        const uint64_t tm = ballot(t);
+                        hitm |= tm;
+                        const int cn = __builtin_popcountll(tm);
+                        if (cn > b_cnt) {
+                            b_cnt = cn;
+                            b_prim = prim;
+                            b_voff = voff;
+                            b_m = m;
+                        }
+                        return tm;  // a blocked ray needs no further test
+                    };
+                    auto key = [&](float x0, float y0, float x1, float y1, float z1) {
+                        return fmaf(x0 + x1, sm.dx, fmaf(y0 + y1, sm.dy, z1 * sm.dz));
+                    };
+                    uint64_t live = ballot(valid && !back);
+                    if (c_prim >= 0 && live) live &= ~leaf(c_prim, c_voff, c_m, live);
+                    if (live) packet_traverse<kCount>(nodes, stack, live, bt, leaf, key, wk);
+                    c_prim = uniform(b_cnt > 0 ? b_prim : -1);
+                    c_voff = uniform(b_voff);
+                    c_m = uniform(b_m);
+                }
+                if constexpr (kCount) wk.units += valid ? 1u : 0u;
+                const bool sh = valid && (back || lane_in(hitm));
+                cnt += sh ? 1 : 0;
+                mins += sh ? s.w : 0.f;
+                if (lds_uniform<SampOut>((lds_int *)s_O).longest) {
+                    // the point's 8 results in time order (the same in its
+                    // 8 lanes)
+                    const uint32_t mine = (uint32_t)(ballot(sh) >> grp8) & 0xffu;
+                    for (int j = 0; j < 8 && c0 + j < kb; ++j) {
+                        const SampleConst sj = ld(samples + (c0 + j));
+                        if (sj.tag & kDayStart) run = 0.f;
+                        run = ((mine >> j) & 1u) ? run + sj.w : 0.f;
+                        best = fmaxf(best, run);
+                    }
+                }
+            }
+            // the point's 8 lanes together
+            for (int o = 1; o < 8; o <<= 1) {
+                cnt += __shfl_xor(cnt, o, 64);
+                mins += __shfl_xor(mins, o, 64);
+            }
+            if (slot == 0 && pvalid)
+                sampled_put(lds_uniform<SampOut>((lds_int *)s_O), (int64_t)bin * n + i, cnt, mins, best);
+        }
+    }
+    if constexpr (kCount) flush_work(wk, work);
+}
+
 // ------------------------------------------------------------------ accrual
 // Segment j's constants read again where they are used after a traversal
 // rather than held in registers across it (an opaque copy of the index
@@ -1065,9 +1201,14 @@ sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const Points
                      : (work ? k_sampled<false, true> : k_sampled<false, false>);
     // bit vectors pack 32 instants a word across bin boundaries: one part
     // per tile then, so each word has one writer
-    const int64_t res = resident_blocks(kern, L);
-    const Sched W =
-        plan_units(p.sample_runs, 0, p.n_samples, tiles, bits ? Split::kNone : Split::kUniqueBins, res, grab);
+    int64_t res = resident_blocks(kern, L);
+    Sched W = plan_units(p.sample_runs, 0, p.n_samples, tiles, bits ? Split::kNone : Split::kUniqueBins, res, grab);
+    // 8 x 8 packets wherever every unit lies in one bin
+    if (!bits && (W.part_start != nullptr || p.sample_runs.start.size() == 2)) {
+        kern = work ? k_sampled8<true> : k_sampled8<false>;
+        res = resident_blocks(kern, L);
+        W = plan_units(p.sample_runs, 0, p.n_samples, tiles, Split::kUniqueBins, res, grab);
+    }
     sa_status rc = fill_u32(grab, 8 * kGrabStride, 0u, st, err);
     if (rc != SA_OK) return rc;
     hipLaunchKernelGGL(kern, dim3((unsigned)unit_blocks(res, W)), dim3(kThreads), 0, st, nodes, s.verts,
