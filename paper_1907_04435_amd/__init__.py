@@ -76,7 +76,8 @@ class sa_sam_opts(C.Structure):
 class sa_launch(C.Structure):
     _fields_ = [("accrual_segments_per_launch", C.c_int32), ("batched_grid_blocks", C.c_int32),
                 ("batched_tiles_per_grab", C.c_int32), ("tile_grid_blocks", C.c_int32),
-                ("accrual_waves_per_simd", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("accrual_waves_per_simd", C.c_int32), ("sampled_instants_per_packet", C.c_int32),
+                ("reserved", C.c_int32 * 2)]
 
 
 class sa_accum_opts(C.Structure):
@@ -259,10 +260,10 @@ class Context:
         _check(self, lib().sa_sync(self.handle))
 
     def set_launch(self, accrual_segments_per_launch=0, batched_grid_blocks=0, batched_tiles_per_grab=0,
-                   tile_grid_blocks=0, accrual_waves_per_simd=0):
+                   tile_grid_blocks=0, accrual_waves_per_simd=0, sampled_instants_per_packet=0):
         """Launch choices (speed only; see sa_set_launch)."""
         l = sa_launch(int(accrual_segments_per_launch), int(batched_grid_blocks), int(batched_tiles_per_grab),
-                      int(tile_grid_blocks), int(accrual_waves_per_simd))
+                      int(tile_grid_blocks), int(accrual_waves_per_simd), int(sampled_instants_per_packet))
         _check(self, lib().sa_set_launch(self.handle, C.byref(l)))
 
     def get_launch(self) -> dict:

@@ -218,21 +218,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     if constexpr (kCount) flush_work(wk, work);
 }
 
-// The sampled form in 8 x 8 packets: a wave holds 8 points of its tile (a
-// point per 8 lanes) at 8 consecutive instants (an instant per lane within
-// the 8), and walks the instants of its unit 8 at a time.  The 8 points
-// are neighbours and the 8 directions lie within minutes of each other, so
-// the packet's rays share more of the hierarchy than 64 points at one
-// instant (block scene: 22 % fewer node visits per packet, 97.7 against
-// 129 ms).  A unit is one bin's run of instants, so every lane's instant
-// falls in the unit's bin; bit vectors (32 instants a word, across bins)
-// stay with k_sampled.  The occluder cache keeps the prism that blocked the
-// most lanes of the previous 8 instants.  The continuous shadow follows the
-// instants in order: the 8 instants of a packet are the same for every
-// point, so each lane replays its point's 8 results (their ballot bits) with
-// the instants' weights read wave-uniform.
-template <bool kCount>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_sampled8(
+// The sampled form in packets of 64 / kInst points x kInst consecutive
+// instants: a wave holds 64 / kInst points of its tile (kInst lanes each, an
+// instant per lane) and walks the instants of its unit kInst at a time.
+// The points are neighbours and the directions lie within minutes of each
+// other, so a packet's rays share more of the hierarchy than 64 points at
+// one instant (block scene, 8 x 8: 22 % fewer node visits per packet, 99
+// against 129 ms; kInst is a launch choice).  A unit is one bin's run of
+// instants, so every lane's instant falls in the unit's bin; bit vectors
+// (32 instants a word, across bins) stay with k_sampled.  The occluder
+// cache keeps the prism that blocked the most lanes of the previous
+// packet.  The continuous shadow follows the instants in order: a packet's
+// instants are the same for every point, so each lane replays its point's
+// results (their ballot bits) with the instants' weights read wave-uniform.
+template <bool kCount, int kInst>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_sampled_pk(
     const Node *nodes_g, const float4 *verts_g, const float *height_g, const SampleConst *samples_g, int K, Sched W,
     PointArgs P, SampOut O, uint64_t *work)
 {
@@ -252,9 +252,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     }
     __syncthreads();
     StackEntry *stack = s_stack[threadIdx.x >> 6];
+    static_assert(kInst >= 2 && kInst <= 32 && (kInst & (kInst - 1)) == 0, "instants per packet");
+    constexpr int kPts = 64 / kInst;  // points per packet
     const int lane = threadIdx.x & 63;
-    const int slot = lane & 7;    // the lane's instant within the packet
-    const int grp8 = lane & ~7;   // first lane of the lane's point
+    const int slot = lane & (kInst - 1);  // the lane's instant within the packet
+    const int first = lane & ~(kInst - 1);  // first lane of the lane's point
     int kx = 0;
     Unit un;
     while (next_unit((lds_int *)s_W, 0, K, kx, un)) {
@@ -263,21 +265,21 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
         const PointArgs Pd = lds_uniform<PointArgs>((lds_int *)s_P);
         const int64_t n = Pd.n;
         const int bin = ld(samples + ka).tag & kBinMask;
-        for (int g = 0; g < 8; ++g) {
-            const int64_t i0 = (int64_t)un.tile * 64 + g * 8;  // the packet's first point
+        for (int g = 0; g < kInst; ++g) {
+            const int64_t i0 = (int64_t)un.tile * 64 + g * kPts;  // the packet's first point
             if (i0 >= n) break;
-            const int64_t i = i0 + (lane >> 3);
+            const int64_t i = i0 + lane / kInst;
             const bool pvalid = i < n;
             const LanePoint q = load_point(Pd, pvalid ? i : 0, pvalid);
             int cnt = 0;
             float mins = 0.f, run = 0.f, best = 0.f;
             int c_prim = -1, c_voff = 0, c_m = 0;
-            for (int c0 = ka; c0 < kb; c0 += 8) {
+            for (int c0 = ka; c0 < kb; c0 += kInst) {
                 const int k = c0 + slot;
                 const bool valid = pvalid && k < kb;
                 const SampleConst s = samples_g[k < kb ? k : ka];
                 // the packet's middle direction orders the children
-                const SampleConst sm = ld(samples + uniform((c0 + min(c0 + 7, kb - 1)) >> 1));
+                const SampleConst sm = ld(samples + uniform((c0 + min(c0 + kInst - 1, kb - 1)) >> 1));
                 const bool back = q.own >= 0 && fmaf(q.nx, s.dx, q.ny * s.dy) <= 0.f;
                 uint64_t hitm = 0;
                 int b_prim = -1, b_voff = 0, b_m = 0, b_cnt = 0;
@@ -331,10 +333,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
                 cnt += sh ? 1 : 0;
                 mins += sh ? s.w : 0.f;
                 if (lds_uniform<SampOut>((lds_int *)s_O).longest) {
-                    // the point's 8 results in time order (the same in its
-                    // 8 lanes)
-                    const uint32_t mine = (uint32_t)(ballot(sh) >> grp8) & 0xffu;
-                    for (int j = 0; j < 8 && c0 + j < kb; ++j) {
+                    // the point's results in time order (the same in all
+                    // its lanes)
+                    const uint32_t mine = (uint32_t)(ballot(sh) >> first) & (uint32_t)((1ull << kInst) - 1);
+                    for (int j = 0; j < kInst && c0 + j < kb; ++j) {
                         const SampleConst sj = ld(samples + (c0 + j));
                         if (sj.tag & kDayStart) run = 0.f;
                         run = ((mine >> j) & 1u) ? run + sj.w : 0.f;
@@ -342,8 +344,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
                     }
                 }
             }
-            // the point's 8 lanes together
-            for (int o = 1; o < 8; o <<= 1) {
+            // the point's lanes together
+            for (int o = 1; o < kInst; o <<= 1) {
                 cnt += __shfl_xor(cnt, o, 64);
                 mins += __shfl_xor(mins, o, 64);
             }
@@ -1203,9 +1205,11 @@ sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const Points
     // per tile then, so each word has one writer
     int64_t res = resident_blocks(kern, L);
     Sched W = plan_units(p.sample_runs, 0, p.n_samples, tiles, bits ? Split::kNone : Split::kUniqueBins, res, grab);
-    // 8 x 8 packets wherever every unit lies in one bin
+    // packets of several instants wherever every unit lies in one bin
     if (!bits && (W.part_start != nullptr || p.sample_runs.start.size() == 2)) {
-        kern = work ? k_sampled8<true> : k_sampled8<false>;
+        kern = work ? k_sampled_pk<true, 8> : k_sampled_pk<false, 8>;
+        if (L.sampled_instants == 4) kern = work ? k_sampled_pk<true, 4> : k_sampled_pk<false, 4>;
+        if (L.sampled_instants == 16) kern = work ? k_sampled_pk<true, 16> : k_sampled_pk<false, 16>;
         res = resident_blocks(kern, L);
         W = plan_units(p.sample_runs, 0, p.n_samples, tiles, Split::kUniqueBins, res, grab);
     }

@@ -28,7 +28,7 @@ struct sa_ctx {
     sa::Scratch scratch_w;        // per-bin weights of a region score
     sa::Scratch scratch_piece;    // per-piece sums of accrual launches on few tiles
     uint32_t sam_stamp = 0;       // the last segment stamp written into it
-    sa_launch launch = {0, 0, 1, 0, 0, {0, 0, 0}};  // tuning choices (sa_set_launch)
+    sa_launch launch = {0, 0, 1, 0, 0, 0, {0, 0}};  // tuning choices (sa_set_launch)
     int32_t n_cu = 256;           // compute units of the device
     void *noalloc = nullptr;      // this device's fixed scratch (device address), or null
     std::string noalloc_err;      // why it is null
@@ -216,7 +216,9 @@ sa_status sa_set_launch(sa_ctx *ctx, const sa_launch *l)
         l->batched_tiles_per_grab < 0 || l->batched_tiles_per_grab > 1024 || l->tile_grid_blocks < 0 ||
         l->tile_grid_blocks > (1 << 20) ||
         (l->accrual_waves_per_simd != 0 && (l->accrual_waves_per_simd < 6 || l->accrual_waves_per_simd > 8)) ||
-        l->reserved[0] != 0 || l->reserved[1] != 0 || l->reserved[2] != 0)
+        (l->sampled_instants_per_packet != 0 && l->sampled_instants_per_packet != 4 &&
+         l->sampled_instants_per_packet != 8 && l->sampled_instants_per_packet != 16) ||
+        l->reserved[0] != 0 || l->reserved[1] != 0)
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_set_launch: value out of range");
     ctx->launch = *l;
     if (ctx->launch.batched_tiles_per_grab == 0) ctx->launch.batched_tiles_per_grab = 1;
@@ -798,7 +800,7 @@ static sa_status clear_outputs(sa_ctx *ctx, uint32_t flags, int64_t count, int32
 static sa::TileLaunch tile_launch(const sa_ctx *ctx)
 {
     return sa::TileLaunch{ctx->launch.accrual_segments_per_launch, ctx->launch.tile_grid_blocks, ctx->n_cu,
-                          ctx->launch.accrual_waves_per_simd};
+                          ctx->launch.accrual_waves_per_simd, ctx->launch.sampled_instants_per_packet};
 }
 
 // The accrual form stores each bin once (no clearing) unless asked to add

@@ -7,6 +7,9 @@
   many as the device holds at once), timed on the same accrual launch.
 * ``accrual_waves_per_simd``: the accrual kernel's occupancy variant (6, 7
   or 8 waves per SIMD), timed on the same launch.
+* ``sampled_instants_per_packet``: the sampled form's packet shape (4, 8
+  or 16 consecutive instants of 16, 8 or 4 points), timed on the sampled
+  form over the block scene's 4M points and three days.
 * ``batched_grid_blocks`` x ``batched_tiles_per_grab``: size of the
   persistent (variant, tile) launch of sa_accumulate_batched and how many
   64-point tiles a wave takes per atomic, timed on a 32-variant slice of
@@ -40,7 +43,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning.json")
 LAUNCH_KEYS = ("accrual_segments_per_launch", "batched_grid_blocks", "batched_tiles_per_grab", "tile_grid_blocks",
-               "accrual_waves_per_simd")
+               "accrual_waves_per_simd", "sampled_instants_per_packet")
 
 
 def _time(torch, stream, fn, reps=3):
@@ -123,6 +126,22 @@ def tune_accrual(sa, torch, ctx, log):
                                   "waves_per_simd": {str(k): v for k, v in wres.items()}}
 
 
+def tune_sampled(sa, torch, ctx, log):
+    from workloads import make_c2
+    w = make_c2()
+    sc = sa.Scene.from_workload(ctx, w.scene)
+    dp = sa.DevicePoints.from_workload(w.points)
+    path = sa.Path(ctx, sa.sunpath_for_span(w.span, 30.0))
+    m = torch.empty((path.n_bins, dp.n), dtype=torch.float32, device="cuda")
+    res = {}
+    for inst in (8, 4, 16):
+        ctx.set_launch(sampled_instants_per_packet=inst)
+        res[inst] = _time(torch, ctx.stream, lambda: sa.sa_accumulate(ctx, sc, dp, path, sa.SA_SAMPLED, None, m))
+        log(f"sampled, {64 // inst} points x {inst} instants per packet: {res[inst]:.2f} ms")
+    ctx.set_launch()
+    return pick(res, 8), {str(k): v for k, v in res.items()}
+
+
 def tune_batched(sa, torch, ctx, log):
     from workloads import make_c3
     w = make_c3(n_var=32)
@@ -181,12 +200,13 @@ def main():
     arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
     t0 = time.time()
     (per, tgb, occ), ares = tune_accrual(sa, torch, ctx, log)
+    inst, sres = tune_sampled(sa, torch, ctx, log)
     (gb, grab), bres = tune_batched(sa, torch, ctx, log)
     L, lres = tune_seg(sa, torch, ctx, log, args.error_bar, args.tail_bar)
     out = {"arch": arch, "accrual_segments_per_launch": per, "tile_grid_blocks": tgb,
-           "accrual_waves_per_simd": occ, "batched_grid_blocks": gb,
+           "accrual_waves_per_simd": occ, "sampled_instants_per_packet": inst, "batched_grid_blocks": gb,
            "batched_tiles_per_grab": grab, "seg_min": L, "error_bar": args.error_bar, "tail_bar": args.tail_bar,
-           "accrual_sweep_ms": ares, "batched_sweep_ms": bres, "seg_sweep": lres, "seconds": time.time() - t0}
+           "accrual_sweep_ms": ares, "sampled_sweep_ms": sres, "batched_sweep_ms": bres, "seg_sweep": lres, "seconds": time.time() - t0}
     with open(CACHE, "w") as f:
         json.dump(out, f, indent=1)
     log(json.dumps({k: out[k] for k in LAUNCH_KEYS + ("seg_min",)}))

@@ -1,11 +1,11 @@
-"""The sampled form's two packet layouts compute the same predicate per
-(point, instant): 8 points x 8 consecutive instants (counts, minutes and the
-continuous shadow, whenever every work unit lies in one bin) and 64 points x
-1 instant (with bit vectors, or when bins interleave).  Counts are equal,
-minutes equal to float rounding (the sums are grouped differently), the
-continuous shadow equals the definition applied to the other layout's bits;
-and the counts of the 8 x 8 layout agree with the oracle outside the
-silhouette band."""
+"""The sampled form's packet layouts compute the same predicate per (point,
+instant): 64 / k points x k consecutive instants for k = 4, 8, 16 (counts,
+minutes and the continuous shadow, whenever every work unit lies in one bin)
+and 64 points x 1 instant (with bit vectors, or when bins interleave).
+Counts are equal, minutes equal to float rounding (the sums are grouped
+differently), the continuous shadow equals the definition applied to the
+other layout's bits; and the counts of the 8 x 8 layout agree with the
+oracle outside the silhouette band."""
 import numpy as np
 import pytest
 
@@ -23,11 +23,12 @@ def ctx():
     return sa.Context(0)
 
 
-def both_layouts(ctx, scene, pts, span):
-    """(counts, minutes, longest) without bit vectors (8 x 8 packets where
-    units lie in one bin) and (counts, minutes, longest, bits) with them
-    (64 x 1 packets)."""
+def both_layouts(ctx, scene, pts, span, inst=8):
+    """(counts, minutes, longest) without bit vectors (packets of ``inst``
+    instants where units lie in one bin) and (counts, minutes, longest,
+    bits) with them (64 x 1 packets)."""
     import torch
+    ctx.set_launch(sampled_instants_per_packet=inst)
     sp = sa.sunpath_for_span(span, 30.0)   # knots do not matter to the sampled form
     path = sa.Path(ctx, sp)
     sc = sa.Scene.from_workload(ctx, scene)
@@ -45,6 +46,7 @@ def both_layouts(ctx, scene, pts, span):
         if bits:
             r.append(unpack_words(b.cpu().numpy().view(np.uint32).T, K))
         out.append(r)
+    ctx.set_launch()
     return out, sp
 
 
@@ -58,15 +60,17 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("inst", [4, 8, 16])
 @pytest.mark.parametrize("case", sorted(CASES))
-def test_layouts_agree(ctx, case):
+def test_layouts_agree(ctx, case, inst):
     w = make_c2(n_ground=20_000, n_facade=20_000)
-    sub = w.points.take(subset_points(w.points, 1001, 17))   # ragged: not a multiple of 8 or 64
+    sub = w.points.take(subset_points(w.points, 1001, 17))   # ragged: not a multiple of 4, 8, 16 or 64
     span = CASES[case](w)
-    ((c8, m8, l8), (c1, m1, l1, bits)), sp = both_layouts(ctx, w.scene, sub, span)
+    ((c8, m8, l8), (c1, m1, l1, bits)), sp = both_layouts(ctx, w.scene, sub, span, inst)
     np.testing.assert_array_equal(c8, c1)
     dm = np.abs(m8 - m1)
-    say(f"{case}: counts equal over {sub.n} points x {sp.n_samples} instants; max |minutes diff| {dm.max():.2e}")
+    say(f"{case}, {inst} instants per packet: counts equal over {sub.n} points x {sp.n_samples} instants; "
+        f"max |minutes diff| {dm.max():.2e}")
     assert np.all(dm <= 1e-5 * np.abs(m1) + 1e-3)
     ref = oracle.longest_sampled(bits.astype(bool), oracle.sun_path(span))
     np.testing.assert_allclose(l8, ref, rtol=1e-5, atol=1e-3)
