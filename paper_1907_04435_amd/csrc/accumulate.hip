@@ -356,6 +356,179 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     if constexpr (kCount) flush_work(wk, work);
 }
 
+// Counts and minutes of the sampled form through a refill queue.  The
+// packets of k_sampled_pk enter a traversal with about four in five lanes
+// live (block scene: the rest face away from their facade or are blocked
+// by the cached occluder), and every node visit costs the wave the same.
+// Here each packet takes its back-face and cache tests, and its remaining
+// rays go to a per-wave queue in LDS as (instant, point of the group); the
+// walk runs whenever 64 rays are queued, and once more for the rest at the
+// end of the point group.  A queued ray keeps its neighbours: the queue
+// fills in the order of the instants, so a walk holds the group's points at
+// up to two packets' worth of consecutive instants (block scene: 15 %
+// fewer walks, 13 % fewer node fetches, 89.6 against 98.8 ms, equal
+// counts).  A walk's hits add their instant's weight to their point's sum
+// in LDS; the continuous shadow, which needs each point's results in time
+// order, stays with k_sampled_pk.
+template <bool kCount, int kInst>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_sampled_q(
+    const Node *nodes_g, const float4 *verts_g, const float *height_g, const SampleConst *samples_g, int K, Sched W,
+    PointArgs P, SampOut O, uint64_t *work)
+{
+    static_assert(kInst >= 4 && kInst <= 16 && (kInst & (kInst - 1)) == 0, "instants per packet");
+    constexpr int kPts = 64 / kInst;  // points per packet (a group)
+    constexpr int kQueue = 128;       // < 64 waiting plus one packet
+    Work wk{0, 0, 0, 0, 0, 0, 0};
+    cNode *nodes = (cNode *)nodes_g;
+    cfloat4 *verts = (cfloat4 *)verts_g;
+    cfloat *height = (cfloat *)height_g;
+    cSample *samples = (cSample *)samples_g;
+    __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    __shared__ uint32_t s_queue[kWaves][kQueue];
+    __shared__ int s_cnt[kWaves][kPts];
+    __shared__ float s_min[kWaves][kPts];
+    __shared__ int s_W[sizeof(Sched) / 4];
+    __shared__ int s_P[sizeof(PointArgs) / 4];
+    __shared__ int s_O[sizeof(SampOut) / 4];
+    if (threadIdx.x == 0) {
+        lds_park((lds_int *)s_W, W);
+        lds_park((lds_int *)s_P, P);
+        lds_park((lds_int *)s_O, O);
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    StackEntry *stack = s_stack[wave];
+    uint32_t *queue = s_queue[wave];
+    int *g_cnt = s_cnt[wave];
+    float *g_min = s_min[wave];
+    const int lane = threadIdx.x & 63;
+    const int slot = lane & (kInst - 1);  // the lane's instant within the packet
+    int kx = 0;
+    Unit un;
+    while (next_unit((lds_int *)s_W, 0, K, kx, un)) {
+        const int ka = uniform(un.a), kb = uniform(un.b);
+        if (kb <= ka) continue;
+        const int64_t n = lds_uniform<PointArgs>((lds_int *)s_P).n;
+        const int bin = ld(samples + ka).tag & kBinMask;
+        for (int g = 0; g < kInst; ++g) {
+            const int64_t i0 = (int64_t)un.tile * 64 + g * kPts;  // the group's first point
+            if (i0 >= n) break;
+            if (lane < kPts) {
+                g_cnt[lane] = 0;
+                g_min[lane] = 0.f;
+            }
+            int c_prim = -1, c_voff = 0, c_m = 0;  // the occluder cache
+            int queued = 0;
+            // one walk over the first nq queued rays; lanes past nq idle
+            auto walk = [&](int nq) {
+                const bool on = lane < nq;
+                const uint32_t e = on ? queue[lane] : 0u;
+                const int pt = (int)(e & 15u);
+                const SampleConst s = samples_g[on ? (int)(e >> 4) : ka];
+                // the middle ray's direction orders the children
+                const SampleConst sm = ld(samples + uniform((int)(queue[nq >> 1] >> 4)));
+                const LanePoint q = load_point(lds_uniform<PointArgs>((lds_int *)s_P), i0 + pt, on);
+                uint64_t hitm = 0;
+                int b_prim = -1, b_voff = 0, b_m = 0, b_cnt = 0;
+                const float ox = -q.px * s.ix, oy = -q.py * s.iy, oz = -q.pz * s.iz;
+                auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
+                    const float ax = fmaf(x0, s.ix, ox), bx = fmaf(x1, s.ix, ox);
+                    const float ay = fmaf(y0, s.iy, oy), by = fmaf(y1, s.iy, oy);
+                    const float tfz = fmaf(z1, s.iz, oz);
+                    const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), 0.f);
+                    const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), tfz);
+                    return le_mask(tn, tf);
+                };
+                auto leaf = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
+                    const bool go = lane_in(want & ballot(prim != q.own));
+                    if constexpr (kCount) {
+                        wk.prism += go ? 1u : 0u;
+                        wk.edges += go ? (uint32_t)m : 0u;
+                        wk.leaves += first_active_lane() ? 1u : 0u;
+                    }
+                    const bool t =
+                        go & ray_prism(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, s.dx, s.dy, s.dz);
+                    const uint64_t tm = ballot(t);
+                    hitm |= tm;
+                    const int cn = __builtin_popcountll(tm);
+                    if (cn > b_cnt) {
+                        b_cnt = cn;
+                        b_prim = prim;
+                        b_voff = voff;
+                        b_m = m;
+                    }
+                    return tm;  // a blocked ray needs no further test
+                };
+                auto key = [&](float x0, float y0, float x1, float y1, float z1) {
+                    return fmaf(x0 + x1, sm.dx, fmaf(y0 + y1, sm.dy, z1 * sm.dz));
+                };
+                packet_traverse<kCount>(nodes, stack, ballot(on), bt, leaf, key, wk);
+                c_prim = uniform(b_cnt > 0 ? b_prim : -1);
+                c_voff = uniform(b_voff);
+                c_m = uniform(b_m);
+                if (lane_in(hitm)) {
+                    atomicAdd(&g_cnt[pt], 1);
+                    atomicAdd(&g_min[pt], s.w);
+                }
+            };
+            const int64_t i = i0 + lane / kInst;
+            const bool pvalid = i < n;
+            const LanePoint q = load_point(lds_uniform<PointArgs>((lds_int *)s_P), pvalid ? i : 0, pvalid);
+            int cnt = 0;  // this lane's instants settled before any walk
+            float mins = 0.f;
+            for (int c0 = ka; c0 < kb; c0 += kInst) {
+                const int k = c0 + slot;
+                const bool valid = pvalid && k < kb;
+                const SampleConst s = samples_g[k < kb ? k : ka];
+                const bool back = q.own >= 0 && fmaf(q.nx, s.dx, q.ny * s.dy) <= 0.f;
+                uint64_t live = ballot(valid && !back);
+                uint64_t cached = 0;
+                if (nodes_g != nullptr && c_prim >= 0 && live) {
+                    const bool go = lane_in(live & ballot(c_prim != q.own));
+                    if constexpr (kCount) {
+                        wk.prism += go ? 1u : 0u;
+                        wk.edges += go ? (uint32_t)c_m : 0u;
+                        wk.leaves += first_active_lane() ? 1u : 0u;
+                    }
+                    cached = ballot(go & ray_prism(verts, c_voff, c_m, ld(height + c_prim), q.px, q.py, q.pz, s.dx,
+                                                   s.dy, s.dz));
+                    live &= ~cached;
+                }
+                if constexpr (kCount) wk.units += valid ? 1u : 0u;
+                const bool sh = valid && (back || lane_in(cached));
+                cnt += sh ? 1 : 0;
+                mins += sh ? s.w : 0.f;
+                if (nodes_g != nullptr && live) {
+                    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(live >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0u));
+                    if (lane_in(live)) queue[queued + rank] = ((uint32_t)k << 4) | (uint32_t)(lane / kInst);
+                    queued += __builtin_popcountll(live);
+                    if (queued >= 64) {
+                        walk(64);
+                        // the rest (fewer than 64) to the front
+                        const bool more = 64 + lane < queued;
+                        const uint32_t e = more ? queue[64 + lane] : 0u;
+                        if (more) queue[lane] = e;
+                        queued -= 64;
+                    }
+                }
+            }
+            if (queued > 0) walk(queued);
+            // the point's lanes together, then its walks' hits
+            for (int o = 1; o < kInst; o <<= 1) {
+                cnt += __shfl_xor(cnt, o, 64);
+                mins += __shfl_xor(mins, o, 64);
+            }
+            if (slot == 0 && pvalid) {
+                const int pt = lane / kInst;
+                sampled_put(lds_uniform<SampOut>((lds_int *)s_O), (int64_t)bin * n + i, cnt + g_cnt[pt],
+                            mins + g_min[pt], 0.f);
+            }
+        }
+    }
+    if constexpr (kCount) flush_work(wk, work);
+}
+
 // ------------------------------------------------------------------ accrual
 // Segment j's constants read again where they are used after a traversal
 // rather than held in registers across it (an opaque copy of the index
@@ -1205,11 +1378,19 @@ sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const Points
     // per tile then, so each word has one writer
     int64_t res = resident_blocks(kern, L);
     Sched W = plan_units(p.sample_runs, 0, p.n_samples, tiles, bits ? Split::kNone : Split::kUniqueBins, res, grab);
-    // packets of several instants wherever every unit lies in one bin
+    // packets of several instants wherever every unit lies in one bin; a
+    // refill queue unless the continuous shadow asks for time order
     if (!bits && (W.part_start != nullptr || p.sample_runs.start.size() == 2)) {
-        kern = work ? k_sampled_pk<true, 8> : k_sampled_pk<false, 8>;
-        if (L.sampled_instants == 4) kern = work ? k_sampled_pk<true, 4> : k_sampled_pk<false, 4>;
-        if (L.sampled_instants == 16) kern = work ? k_sampled_pk<true, 16> : k_sampled_pk<false, 16>;
+        const int ni = L.sampled_instants;
+        if (longest) {
+            kern = work ? k_sampled_pk<true, 8> : k_sampled_pk<false, 8>;
+            if (ni == 4) kern = work ? k_sampled_pk<true, 4> : k_sampled_pk<false, 4>;
+            if (ni == 16) kern = work ? k_sampled_pk<true, 16> : k_sampled_pk<false, 16>;
+        } else {
+            kern = work ? k_sampled_q<true, 8> : k_sampled_q<false, 8>;
+            if (ni == 4) kern = work ? k_sampled_q<true, 4> : k_sampled_q<false, 4>;
+            if (ni == 16) kern = work ? k_sampled_q<true, 16> : k_sampled_q<false, 16>;
+        }
         res = resident_blocks(kern, L);
         W = plan_units(p.sample_runs, 0, p.n_samples, tiles, Split::kUniqueBins, res, grab);
     }
