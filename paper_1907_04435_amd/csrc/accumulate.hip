@@ -375,7 +375,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     const Node *nodes_g, const float4 *verts_g, const float *height_g, const SampleConst *samples_g, int K, Sched W,
     PointArgs P, SampOut O, uint64_t *work)
 {
-    static_assert(kInst >= 4 && kInst <= 16 && (kInst & (kInst - 1)) == 0, "instants per packet");
+    static_assert(kInst >= 1 && kInst <= 16 && (kInst & (kInst - 1)) == 0, "instants per packet");
     constexpr int kPts = 64 / kInst;  // points per packet (a group)
     constexpr int kQueue = 128;       // < 64 waiting plus one packet
     Work wk{0, 0, 0, 0, 0, 0, 0};
@@ -423,10 +423,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
             auto walk = [&](int nq) {
                 const bool on = lane < nq;
                 const uint32_t e = on ? queue[lane] : 0u;
-                const int pt = (int)(e & 15u);
-                const SampleConst s = samples_g[on ? (int)(e >> 4) : ka];
+                const int pt = (int)(e & 63u);
+                const SampleConst s = samples_g[on ? (int)(e >> 6) : ka];
                 // the middle ray's direction orders the children
-                const SampleConst sm = ld(samples + uniform((int)(queue[nq >> 1] >> 4)));
+                const SampleConst sm = ld(samples + uniform((int)(queue[nq >> 1] >> 6)));
                 const LanePoint q = load_point(lds_uniform<PointArgs>((lds_int *)s_P), i0 + pt, on);
                 uint64_t hitm = 0;
                 int b_prim = -1, b_voff = 0, b_m = 0, b_cnt = 0;
@@ -501,7 +501,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
                 if (nodes_g != nullptr && live) {
                     const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(live >> 32),
                                                                     __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0u));
-                    if (lane_in(live)) queue[queued + rank] = ((uint32_t)k << 4) | (uint32_t)(lane / kInst);
+                    if (lane_in(live)) queue[queued + rank] = ((uint32_t)k << 6) | (uint32_t)(lane / kInst);
                     queued += __builtin_popcountll(live);
                     if (queued >= 64) {
                         walk(64);
@@ -1379,15 +1379,18 @@ sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const Points
     int64_t res = resident_blocks(kern, L);
     Sched W = plan_units(p.sample_runs, 0, p.n_samples, tiles, bits ? Split::kNone : Split::kUniqueBins, res, grab);
     // packets of several instants wherever every unit lies in one bin; a
-    // refill queue unless the continuous shadow asks for time order
+    // refill queue unless the continuous shadow asks for time order (or the
+    // instants overflow a queue entry's 26 bits)
     if (!bits && (W.part_start != nullptr || p.sample_runs.start.size() == 2)) {
         const int ni = L.sampled_instants;
-        if (longest) {
+        if (longest || p.n_samples >= (1 << 26)) {
             kern = work ? k_sampled_pk<true, 8> : k_sampled_pk<false, 8>;
             if (ni == 4) kern = work ? k_sampled_pk<true, 4> : k_sampled_pk<false, 4>;
             if (ni == 16) kern = work ? k_sampled_pk<true, 16> : k_sampled_pk<false, 16>;
         } else {
             kern = work ? k_sampled_q<true, 8> : k_sampled_q<false, 8>;
+            if (ni == 1) kern = work ? k_sampled_q<true, 1> : k_sampled_q<false, 1>;
+            if (ni == 2) kern = work ? k_sampled_q<true, 2> : k_sampled_q<false, 2>;
             if (ni == 4) kern = work ? k_sampled_q<true, 4> : k_sampled_q<false, 4>;
             if (ni == 16) kern = work ? k_sampled_q<true, 16> : k_sampled_q<false, 16>;
         }

@@ -216,8 +216,8 @@ sa_status sa_set_launch(sa_ctx *ctx, const sa_launch *l)
         l->batched_tiles_per_grab < 0 || l->batched_tiles_per_grab > 1024 || l->tile_grid_blocks < 0 ||
         l->tile_grid_blocks > (1 << 20) ||
         (l->accrual_waves_per_simd != 0 && (l->accrual_waves_per_simd < 6 || l->accrual_waves_per_simd > 8)) ||
-        (l->sampled_instants_per_packet != 0 && l->sampled_instants_per_packet != 4 &&
-         l->sampled_instants_per_packet != 8 && l->sampled_instants_per_packet != 16) ||
+        (l->sampled_instants_per_packet < 0 || l->sampled_instants_per_packet > 16 ||
+         (l->sampled_instants_per_packet & (l->sampled_instants_per_packet - 1)) != 0) ||
         l->reserved[0] != 0 || l->reserved[1] != 0)
         return fail(ctx, SA_ERR_INVALID_ARG, "sa_set_launch: value out of range");
     ctx->launch = *l;

@@ -199,7 +199,7 @@ struct TileLaunch {
     int64_t grid_blocks;
     int32_t n_cu;
     int32_t waves_per_simd;  // the accrual kernel's occupancy variant: 6, 7 or 8 (0: 8)
-    int32_t sampled_instants;  // instants per packet of the sampled form: 4, 8 or 16 (0: 8)
+    int32_t sampled_instants;  // instants per packet of the sampled form: 1, 2, 4, 8 or 16 (0: 8)
 };
 
 sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const PointsView &pts,

@@ -7,9 +7,9 @@
   many as the device holds at once), timed on the same accrual launch.
 * ``accrual_waves_per_simd``: the accrual kernel's occupancy variant (6, 7
   or 8 waves per SIMD), timed on the same launch.
-* ``sampled_instants_per_packet``: the sampled form's packet shape (4, 8
-  or 16 consecutive instants of 16, 8 or 4 points), timed on the sampled
-  form over the block scene's 4M points and three days.
+* ``sampled_instants_per_packet``: the sampled form's packet shape (1, 2,
+  4, 8 or 16 consecutive instants of 64 down to 4 points), timed on the
+  sampled form over the block scene's 4M points and three days.
 * ``batched_grid_blocks`` x ``batched_tiles_per_grab``: size of the
   persistent (variant, tile) launch of sa_accumulate_batched and how many
   64-point tiles a wave takes per atomic, timed on a 32-variant slice of
@@ -134,7 +134,7 @@ def tune_sampled(sa, torch, ctx, log):
     path = sa.Path(ctx, sa.sunpath_for_span(w.span, 30.0))
     m = torch.empty((path.n_bins, dp.n), dtype=torch.float32, device="cuda")
     res = {}
-    for inst in (8, 4, 16):
+    for inst in (8, 1, 2, 4, 16):
         ctx.set_launch(sampled_instants_per_packet=inst)
         res[inst] = _time(torch, ctx.stream, lambda: sa.sa_accumulate(ctx, sc, dp, path, sa.SA_SAMPLED, None, m))
         log(f"sampled, {64 // inst} points x {inst} instants per packet: {res[inst]:.2f} ms")

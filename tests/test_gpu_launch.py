@@ -123,6 +123,8 @@ def test_bad_launch_values(ctx):
         ctx.set_launch(accrual_waves_per_simd=5)
     with pytest.raises(sa.SAError):
         ctx.set_launch(sampled_instants_per_packet=6)
+    with pytest.raises(sa.SAError):
+        ctx.set_launch(sampled_instants_per_packet=32)
     assert ctx.get_launch()["batched_tiles_per_grab"] == 1
 
 

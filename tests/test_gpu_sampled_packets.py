@@ -1,9 +1,9 @@
 """The sampled form's kernels compute the same predicate per (point,
 instant) in different lane layouts: packets of 64 / k points x k
-consecutive instants for k = 4, 8, 16, walked as they come when the
-continuous shadow is asked for and refilled to 64 rays through a queue
-otherwise (both whenever every work unit lies in one bin), and 64 points x
-1 instant (with bit vectors, or when bins interleave).  Counts are equal,
+consecutive instants (k = 4, 8, 16, walked as they come, when the
+continuous shadow is asked for; k = 1 ... 16, refilled to 64 rays through
+a queue, otherwise; both whenever every work unit lies in one bin), and 64
+points x 1 instant (with bit vectors, or when bins interleave).  Counts are equal,
 minutes equal to float rounding (the sums are grouped differently), the
 continuous shadow equals the definition applied to the bit vectors; and
 the counts agree with the oracle outside the silhouette band."""
@@ -27,8 +27,8 @@ def ctx():
 def layouts(ctx, scene, pts, span, inst=8):
     """Per call: "queue" (counts and minutes only: the refill queue where
     units lie in one bin), "packets" (with the continuous shadow: packets of
-    ``inst`` instants in time order) and "bits" (with bit vectors: 64 x 1),
-    each a dict of numpy arrays."""
+    ``inst`` instants in time order, 8 for 1 and 2) and "bits" (with bit
+    vectors: 64 x 1), each a dict of numpy arrays."""
     import torch
     ctx.set_launch(sampled_instants_per_packet=inst)
     sp = sa.sunpath_for_span(span, 30.0)   # knots do not matter to the sampled form
@@ -64,7 +64,7 @@ CASES = {
 }
 
 
-@pytest.mark.parametrize("inst", [4, 8, 16])
+@pytest.mark.parametrize("inst", [1, 2, 4, 8, 16])
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_layouts_agree(ctx, case, inst):
     w = make_c2(n_ground=20_000, n_facade=20_000)
