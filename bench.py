@@ -235,6 +235,8 @@ def bench_c4(args, sa, torch):
     from workloads import make_c4
     w = make_c4()
     ctx = sa.Context(0)
+    from paper_1907_04435_amd import tune
+    launch = {} if args.untuned else tune.apply(ctx)
     sc = sa.Scene.from_workload(ctx, w.scene)
     path = sa.Path(ctx, sa.sunpath_for_span(w.span, 1.0))
     dp = sa.DevicePoints.from_workload(w.points)
@@ -256,6 +258,7 @@ def bench_c4(args, sa, torch):
               {"workload": w.name, "points": dp.n, "buildings": w.scene.n_b, "instants_per_point": path.n_samples,
                "seg_min": 1.0, "point_sun_steps": evals})
     r["forward_ms"], r["adjoint_ms"] = mf, mb
+    r["tuning"] = launch
     r["loss_minutes"] = float(mins.double().sum())
     r["grad_nonzero"] = int((grad != 0).sum())
     return r
@@ -271,6 +274,8 @@ def bench_sam(args, sa, torch):
     w = make_c2(n_facade=0)
     span = Span(w.span.lat, w.span.lon, [w.span.days[1]], w.span.step_min)
     ctx = sa.Context(0)
+    from paper_1907_04435_amd import tune
+    launch = {} if args.untuned else tune.apply(ctx)
     sc = sa.Scene.from_workload(ctx, w.scene)
     path = sa.Path(ctx, sa.sunpath_for_span(span, args.seg))
     dp = sa.DevicePoints.ground_from_workload(w.points)
@@ -303,6 +308,7 @@ def bench_sam(args, sa, torch):
                "instants_per_point": path.n_samples, "seg_min": args.seg, "texel_m": args.texel,
                "point_sun_steps": evals})
     r["steps"] = steps
+    r["tuning"] = launch
     if not args.no_cpu_baseline:
         # the oracle's raster form on a bounded seeded sample of the same points
         import oracle
@@ -332,6 +338,8 @@ def bench_c5(args, sa, torch):
     from workloads import make_c5
     w = make_c5()
     ctx = sa.Context(0)
+    from paper_1907_04435_amd import tune
+    launch = {} if args.untuned else tune.apply(ctx)
     sc = sa.Scene.from_workload(ctx, w.scene)
     sp = sa.sunpath_for_span(w.span, args.seg)      # the workload's days, with their clock (EDT / EST)
     path = sa.Path(ctx, sp)
@@ -350,6 +358,7 @@ def bench_c5(args, sa, torch):
                "instants_per_point": path.n_samples, "seg_min": args.seg, "bins": path.n_bins,
                "point_sun_steps": evals})
     r["steps"], r["warmup"] = steps, 0
+    r["tuning"] = launch
     r["mean_hours_per_bin"] = [float(x) for x in hours.mean(1).cpu()]
     if not args.skip_graph:
         # the direction graph of Sec. 6: segments of a season whose knots
