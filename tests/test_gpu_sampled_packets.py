@@ -105,3 +105,27 @@ def test_layouts_against_oracle(ctx):
             f"max |count diff| {int(dc.max())}")
         assert np.all(dc <= na)
         np.testing.assert_array_equal(r[name]["counts"][na == 0], oc[na == 0])
+
+
+@pytest.mark.parametrize("inst", [1, 4, 16])
+def test_queue_on_tiny_and_ragged_sets(ctx, c1, inst):
+    """The refill queue on point sets of 1, 3, 63, 65 and 200 points of the
+    small scene (a single partial group, partial tiles, several tiles), on
+    one building and on an empty scene: counts equal to the bit-vector
+    layout's, and those equal to the oracle's outside the silhouette band."""
+    from workloads import Scene
+    op = oracle.sun_path(c1.span)
+    one = c1.scene.subset(np.array([5]))
+    empty = Scene(np.zeros(1, np.int32), np.zeros((0, 2), np.float32), np.zeros(0, np.float32))
+    for n in (1, 3, 63, 65, 200):
+        sub = c1.points.take(np.arange(7, 7 + n * 13, 13))
+        for scene in (c1.scene, one):
+            r, _ = layouts(ctx, scene, sub, c1.span, inst)
+            np.testing.assert_array_equal(r["queue"]["counts"], r["bits"]["counts"])
+            assert np.abs(r["queue"]["minutes"] - r["bits"]["minutes"]).max() <= 1e-3
+        o = oracle.sampled(c1.scene, sub, op, amb=True)
+        r, _ = layouts(ctx, c1.scene, sub, c1.span, inst)
+        dc = np.abs(r["queue"]["counts"].sum(0) - o["counts"].sum(0))
+        assert np.all(dc <= o["amb"].sum(1))
+        r, _ = layouts(ctx, empty, sub, c1.span, inst)
+        assert np.all(r["queue"]["counts"] == 0) and np.all(r["queue"]["minutes"] == 0)
