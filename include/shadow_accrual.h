@@ -94,10 +94,8 @@ typedef struct {
     int32_t accrual_waves_per_simd;      /* accrual form: occupancy variant of its kernel, 6, 7 or 8
                                             waves per SIMD (registers per lane shrink as it grows);
                                             0 = 8 */
-    int32_t sampled_instants_per_packet; /* sampled form without bit vectors: instants a wave's packet
-                                            takes per point, 1, 2, 4, 8 or 16 (so 64 down to 4
-                                            points); with the continuous shadow 4, 8 or 16 are
-                                            used as given, 1 and 2 as 8; 0 = 8 */
+    int32_t sampled_instants_per_packet; /* sampled form: instants a wave's packet takes per point,
+                                            1, 2, 4, 8 or 16 (so 64 down to 4 points); 0 = 8 */
     int32_t reserved[2];                 /* 0 */
 } sa_launch;
 /* Errors: INVALID_ARG (negative or out-of-range values). */

@@ -84,292 +84,24 @@ __device__ __forceinline__ void sampled_put(const SampOut &O, int64_t o, int cnt
     if (O.longest) O.longest[o] = fmaxf(O.longest[o], best * O.scale);
 }
 
-// Eight waves per SIMD (the compiler's own choice gives seven): 128 ms
-// against 138 on the block scene's three days.
-template <bool kBits, bool kCount>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_sampled(const Node *nodes_g, const float4 *verts_g,
-                                                      const float *height_g, const SampleConst *samples_g,
-                                                      int K, Sched W, PointArgs P, SampOut O, uint64_t *work)
-{
-    Work wk{0, 0, 0, 0, 0, 0, 0};
-    cNode *nodes = (cNode *)nodes_g;
-    cfloat4 *verts = (cfloat4 *)verts_g;
-    cfloat *height = (cfloat *)height_g;
-    cSample *samples = (cSample *)samples_g;
-    __shared__ StackEntry s_stack[kWaves][kStackDepth];
-    // schedule, points and outputs parked in LDS: read once per unit (per
-    // bin for the outputs), they hold no scalar registers in the loop
-    __shared__ int s_W[sizeof(Sched) / 4];
-    __shared__ int s_P[sizeof(PointArgs) / 4];
-    __shared__ int s_O[sizeof(SampOut) / 4];
-    if (threadIdx.x == 0) {
-        lds_park((lds_int *)s_W, W);
-        lds_park((lds_int *)s_P, P);
-        lds_park((lds_int *)s_O, O);
-    }
-    __syncthreads();
-    StackEntry *stack = s_stack[threadIdx.x >> 6];
-    const int lane = threadIdx.x & 63;
-    int kx = 0;
-    Unit un;
-    while (next_unit((lds_int *)s_W, 0, K, kx, un)) {
-        const PointArgs Pd = lds_uniform<PointArgs>((lds_int *)s_P);
-        const int64_t n = Pd.n;
-        const int64_t i = (int64_t)un.tile * 64 + lane;
-        const bool valid = i < n;
-        const LanePoint q = load_point(Pd, i, valid);
-        const int ka = uniform(un.a), kb = uniform(un.b);
-
-        int cnt = 0;
-        float mins = 0.f;
-        // continuous shadow: the current run of shadowed instants and the
-        // longest run of the bin so far (minutes); a run never crosses a day
-        float run = 0.f, best = 0.f;
-        int bin = kb > ka ? (ld(samples + ka).tag & kBinMask) : 0;
-        uint32_t word = 0;
-        // Occluder cache, one per wave: the prism that blocked the most
-        // lanes at the previous instant is tested first (and not again by
-        // the walk); lanes it blocks are done, and a wave whose every live
-        // lane it blocks skips the traversal.  A blocked ray is blocked
-        // whichever prism is found first, so the predicate is unchanged.
-        int c_prim = -1, c_voff = 0, c_m = 0;
-        for (int k = ka; k < kb; ++k) {
-            const SampleConst s = ld(samples + k);
-            const int sbin = s.tag & kBinMask;
-            if (sbin != bin) {
-                if (valid) sampled_put(lds_uniform<SampOut>((lds_int *)s_O), (int64_t)bin * n + i, cnt, mins, best);
-                cnt = 0;
-                mins = 0.f;
-                best = 0.f;
-                bin = sbin;
-            }
-            if (s.tag & kDayStart) run = 0.f;
-            const bool back = q.own >= 0 && fmaf(q.nx, s.dx, q.ny * s.dy) <= 0.f;
-            uint64_t hitm = 0;
-            int b_prim = -1, b_voff = 0, b_m = 0, b_cnt = 0;  // this instant's best blocker
-            if (nodes_g != nullptr) {
-                const float ox = -q.px * s.ix, oy = -q.py * s.iy, oz = -q.pz * s.iz;
-                // slab test: each axis's entry and exit by min / max (no
-                // selects on the direction's signs); every box starts at
-                // z = 0, below the ray's origin, so only its top bounds the
-                // ray in z
-                auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
-                    const float ax = fmaf(x0, s.ix, ox), bx = fmaf(x1, s.ix, ox);
-                    const float ay = fmaf(y0, s.iy, oy), by = fmaf(y1, s.iy, oy);
-                    const float tfz = fmaf(z1, s.iz, oz);
-                    const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), 0.f);
-                    const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), tfz);
-                    return le_mask(tn, tf);
-                };
-                bool cached_seen = false;
-                auto leaf = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
-                    if (prim == c_prim) {
-                        if (cached_seen) return 0;
-                        cached_seen = true;
-                    }
-                    const bool go = lane_in(want & ballot(prim != q.own));
-                    if constexpr (kCount) {
-                        wk.prism += go ? 1u : 0u;
-                        wk.edges += go ? (uint32_t)m : 0u;
-                        wk.leaves += first_active_lane() ? 1u : 0u;
-                    }
-                    const bool t =
-                        go & ray_prism(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, s.dx, s.dy, s.dz);
-                    const uint64_t tm = ballot(t);
-                    hitm |= tm;
-                    const int cnt = __builtin_popcountll(tm);
-                    if (cnt > b_cnt) {
-                        b_cnt = cnt;
-                        b_prim = prim;
-                        b_voff = voff;
-                        b_m = m;
-                    }
-                    return tm;  // a blocked ray needs no further test
-                };
-                auto key = [&](float x0, float y0, float x1, float y1, float z1) {
-                    return fmaf(x0 + x1, s.dx, fmaf(y0 + y1, s.dy, z1 * s.dz));
-                };
-                uint64_t live = ballot(valid && !back);
-                if (c_prim >= 0 && live) live &= ~leaf(c_prim, c_voff, c_m, live);
-                if (live) packet_traverse<kCount>(nodes, stack, live, bt, leaf, key, wk);
-                // keep a blocker only while it blocks some lane
-                c_prim = uniform(b_cnt > 0 ? b_prim : -1);
-                c_voff = uniform(b_voff);
-                c_m = uniform(b_m);
-            }
-            if constexpr (kCount) wk.units += valid ? 1u : 0u;
-            const bool sh = valid && (back || lane_in(hitm));
-            cnt += sh ? 1 : 0;
-            mins += sh ? s.w : 0.f;
-            run = sh ? run + s.w : 0.f;
-            best = fmaxf(best, run);
-            if (kBits) {
-                // a unit with bit vectors covers every instant (one part)
-                word |= (uint32_t)sh << (k & 31);
-                if ((k & 31) == 31 || k == kb - 1) {
-                    uint32_t *bits = lds_uniform<SampOut>((lds_int *)s_O).bits;
-                    if (valid) bits[(int64_t)(k >> 5) * n + i] = word;
-                    word = 0;
-                }
-            }
-        }
-        if (valid && kb > ka) sampled_put(lds_uniform<SampOut>((lds_int *)s_O), (int64_t)bin * n + i, cnt, mins, best);
-    }
-    if constexpr (kCount) flush_work(wk, work);
-}
-
-// The sampled form in packets of 64 / kInst points x kInst consecutive
-// instants: a wave holds 64 / kInst points of its tile (kInst lanes each, an
-// instant per lane) and walks the instants of its unit kInst at a time.
-// The points are neighbours and the directions lie within minutes of each
-// other, so a packet's rays share more of the hierarchy than 64 points at
-// one instant (block scene, 8 x 8: 22 % fewer node visits per packet, 99
-// against 129 ms; kInst is a launch choice).  A unit is one bin's run of
-// instants, so every lane's instant falls in the unit's bin; bit vectors
-// (32 instants a word, across bins) stay with k_sampled.  The occluder
-// cache keeps the prism that blocked the most lanes of the previous
-// packet.  The continuous shadow follows the instants in order: a packet's
-// instants are the same for every point, so each lane replays its point's
-// results (their ballot bits) with the instants' weights read wave-uniform.
-template <bool kCount, int kInst>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_sampled_pk(
-    const Node *nodes_g, const float4 *verts_g, const float *height_g, const SampleConst *samples_g, int K, Sched W,
-    PointArgs P, SampOut O, uint64_t *work)
-{
-    Work wk{0, 0, 0, 0, 0, 0, 0};
-    cNode *nodes = (cNode *)nodes_g;
-    cfloat4 *verts = (cfloat4 *)verts_g;
-    cfloat *height = (cfloat *)height_g;
-    cSample *samples = (cSample *)samples_g;
-    __shared__ StackEntry s_stack[kWaves][kStackDepth];
-    __shared__ int s_W[sizeof(Sched) / 4];
-    __shared__ int s_P[sizeof(PointArgs) / 4];
-    __shared__ int s_O[sizeof(SampOut) / 4];
-    if (threadIdx.x == 0) {
-        lds_park((lds_int *)s_W, W);
-        lds_park((lds_int *)s_P, P);
-        lds_park((lds_int *)s_O, O);
-    }
-    __syncthreads();
-    StackEntry *stack = s_stack[threadIdx.x >> 6];
-    static_assert(kInst >= 2 && kInst <= 32 && (kInst & (kInst - 1)) == 0, "instants per packet");
-    constexpr int kPts = 64 / kInst;  // points per packet
-    const int lane = threadIdx.x & 63;
-    const int slot = lane & (kInst - 1);  // the lane's instant within the packet
-    const int first = lane & ~(kInst - 1);  // first lane of the lane's point
-    int kx = 0;
-    Unit un;
-    while (next_unit((lds_int *)s_W, 0, K, kx, un)) {
-        const int ka = uniform(un.a), kb = uniform(un.b);
-        if (kb <= ka) continue;
-        const PointArgs Pd = lds_uniform<PointArgs>((lds_int *)s_P);
-        const int64_t n = Pd.n;
-        const int bin = ld(samples + ka).tag & kBinMask;
-        for (int g = 0; g < kInst; ++g) {
-            const int64_t i0 = (int64_t)un.tile * 64 + g * kPts;  // the packet's first point
-            if (i0 >= n) break;
-            const int64_t i = i0 + lane / kInst;
-            const bool pvalid = i < n;
-            const LanePoint q = load_point(Pd, pvalid ? i : 0, pvalid);
-            int cnt = 0;
-            float mins = 0.f, run = 0.f, best = 0.f;
-            int c_prim = -1, c_voff = 0, c_m = 0;
-            for (int c0 = ka; c0 < kb; c0 += kInst) {
-                const int k = c0 + slot;
-                const bool valid = pvalid && k < kb;
-                const SampleConst s = samples_g[k < kb ? k : ka];
-                // the packet's middle direction orders the children
-                const SampleConst sm = ld(samples + uniform((c0 + min(c0 + kInst - 1, kb - 1)) >> 1));
-                const bool back = q.own >= 0 && fmaf(q.nx, s.dx, q.ny * s.dy) <= 0.f;
-                uint64_t hitm = 0;
-                int b_prim = -1, b_voff = 0, b_m = 0, b_cnt = 0;
-                if (nodes_g != nullptr) {
-                    const float ox = -q.px * s.ix, oy = -q.py * s.iy, oz = -q.pz * s.iz;
-                    auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
-                        const float ax = fmaf(x0, s.ix, ox), bx = fmaf(x1, s.ix, ox);
-                        const float ay = fmaf(y0, s.iy, oy), by = fmaf(y1, s.iy, oy);
-                        const float tfz = fmaf(z1, s.iz, oz);
-                        const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), 0.f);
-                        const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), tfz);
-                        return le_mask(tn, tf);
-                    };
-                    bool cached_seen = false;
-                    auto leaf = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
-                        if (prim == c_prim) {
-                            if (cached_seen) return 0;
-                            cached_seen = true;
-                        }
-                        const bool go = lane_in(want & ballot(prim != q.own));
-                        if constexpr (kCount) {
-                            wk.prism += go ? 1u : 0u;
-                            wk.edges += go ? (uint32_t)m : 0u;
-                            wk.leaves += first_active_lane() ? 1u : 0u;
-                        }
-                        const bool t =
-                            go & ray_prism(verts, voff, m, ld(height + prim), q.px, q.py, q.pz, s.dx, s.dy, s.dz);
-                        const uint64_t tm = ballot(t);
-                        hitm |= tm;
-                        const int cn = __builtin_popcountll(tm);
-                        if (cn > b_cnt) {
-                            b_cnt = cn;
-                            b_prim = prim;
-                            b_voff = voff;
-                            b_m = m;
-                        }
-                        return tm;  // a blocked ray needs no further test
-                    };
-                    auto key = [&](float x0, float y0, float x1, float y1, float z1) {
-                        return fmaf(x0 + x1, sm.dx, fmaf(y0 + y1, sm.dy, z1 * sm.dz));
-                    };
-                    uint64_t live = ballot(valid && !back);
-                    if (c_prim >= 0 && live) live &= ~leaf(c_prim, c_voff, c_m, live);
-                    if (live) packet_traverse<kCount>(nodes, stack, live, bt, leaf, key, wk);
-                    c_prim = uniform(b_cnt > 0 ? b_prim : -1);
-                    c_voff = uniform(b_voff);
-                    c_m = uniform(b_m);
-                }
-                if constexpr (kCount) wk.units += valid ? 1u : 0u;
-                const bool sh = valid && (back || lane_in(hitm));
-                cnt += sh ? 1 : 0;
-                mins += sh ? s.w : 0.f;
-                if (lds_uniform<SampOut>((lds_int *)s_O).longest) {
-                    // the point's results in time order (the same in all
-                    // its lanes)
-                    const uint32_t mine = (uint32_t)(ballot(sh) >> first) & (uint32_t)((1ull << kInst) - 1);
-                    for (int j = 0; j < kInst && c0 + j < kb; ++j) {
-                        const SampleConst sj = ld(samples + (c0 + j));
-                        if (sj.tag & kDayStart) run = 0.f;
-                        run = ((mine >> j) & 1u) ? run + sj.w : 0.f;
-                        best = fmaxf(best, run);
-                    }
-                }
-            }
-            // the point's lanes together
-            for (int o = 1; o < kInst; o <<= 1) {
-                cnt += __shfl_xor(cnt, o, 64);
-                mins += __shfl_xor(mins, o, 64);
-            }
-            if (slot == 0 && pvalid)
-                sampled_put(lds_uniform<SampOut>((lds_int *)s_O), (int64_t)bin * n + i, cnt, mins, best);
-        }
-    }
-    if constexpr (kCount) flush_work(wk, work);
-}
-
-// Counts and minutes of the sampled form through a refill queue.  The
-// packets of k_sampled_pk enter a traversal with about four in five lanes
+// The sampled form: an any-hit ray per (point, instant), in packets of
+// 64 / kInst neighbouring points x kInst consecutive instants of one
+// 64-point tile (kInst is a launch choice; 16 x 4 on the block scene).  A
+// packet first takes the back-face test and the occluder cache: each wave
+// remembers the prism that blocked the most lanes of its previous walk and
+// tests it first; a blocked ray is blocked whichever prism is found first,
+// so the predicate is unchanged.  The rays left go to a per-wave queue in
+// LDS as (instant, point of the group), and a walk of the hierarchy runs
+// whenever 64 are queued, and once more for the rest at the end of the
+// point group.  A packet enters the queue with about four rays in five
 // live (block scene: the rest face away from their facade or are blocked
-// by the cached occluder), and every node visit costs the wave the same.
-// Here each packet takes its back-face and cache tests, and its remaining
-// rays go to a per-wave queue in LDS as (instant, point of the group); the
-// walk runs whenever 64 rays are queued, and once more for the rest at the
-// end of the point group.  A queued ray keeps its neighbours: the queue
-// fills in the order of the instants, so a walk holds the group's points at
-// up to two packets' worth of consecutive instants (block scene: 15 %
-// fewer walks, 13 % fewer node fetches, 89.6 against 98.8 ms, equal
-// counts).  A walk's hits add their instant's weight to their point's sum
-// in LDS; the continuous shadow, which needs each point's results in time
-// order, stays with k_sampled_pk.
+// by the cached occluder), while every node visit costs the wave the same
+// whatever its live lanes; refilled walks are full.  The queue fills in the
+// order of the instants, so a walk holds the group's points at neighbouring
+// instants.  Eight waves per SIMD (the compiler's own choice gives seven).
+//
+// k_sampled_q: counts and minutes of units that lie in one bin; a walk's
+// hits add their instant's weight to their point's sum in LDS.
 template <bool kCount, int kInst>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_sampled_q(
     const Node *nodes_g, const float4 *verts_g, const float *height_g, const SampleConst *samples_g, int K, Sched W,
@@ -524,6 +256,200 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
                 sampled_put(lds_uniform<SampOut>((lds_int *)s_O), (int64_t)bin * n + i, cnt + g_cnt[pt],
                             mins + g_min[pt], 0.f);
             }
+        }
+    }
+    if constexpr (kCount) flush_work(wk, work);
+}
+
+// k_sampled_qb: the outputs that need every instant's result -- bit
+// vectors, the continuous shadow (in time order), and bins that interleave
+// (a unit then spans them).  The instants of a unit go in windows of kWin
+// (a 2 KB bitmap per wave: 256 instants for 64 points, up to 4096 for 4):
+// each window's packets and walks set their shadowed (point, instant)
+// pairs in a per-wave LDS bitmap, the queue is drained at the window's
+// end, and each point's lane then replays the window's bits in time order:
+// counts, minutes and runs per bin, a run reset at each day's first instant
+// (runs never cross days) and the longest kept per bin.  A queue entry
+// holds the instant's offset in the window, so any path length fits.  With
+// bit vectors a unit is a whole tile from the first instant, so windows
+// start on 32-instant words and the bitmap words are the output words.
+template <bool kCount, int kInst>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_sampled_qb(
+    const Node *nodes_g, const float4 *verts_g, const float *height_g, const SampleConst *samples_g, int K, Sched W,
+    PointArgs P, SampOut O, uint64_t *work)
+{
+    static_assert(kInst >= 1 && kInst <= 16 && (kInst & (kInst - 1)) == 0, "instants per packet");
+    constexpr int kPts = 64 / kInst;  // points per packet (a group)
+    constexpr int kQueue = 128;       // < 64 waiting plus one packet
+    constexpr int kWords = 512 / kPts;  // bitmap words per point and window (2 KB a wave)
+    constexpr int kWin = 32 * kWords;   // instants per window
+    constexpr int kRow = kWords + 1;    // a point's row, padded: lanes reading one word of
+                                        // consecutive points hit different banks
+    Work wk{0, 0, 0, 0, 0, 0, 0};
+    cNode *nodes = (cNode *)nodes_g;
+    cfloat4 *verts = (cfloat4 *)verts_g;
+    cfloat *height = (cfloat *)height_g;
+    cSample *samples = (cSample *)samples_g;
+    __shared__ StackEntry s_stack[kWaves][kStackDepth];
+    __shared__ uint32_t s_queue[kWaves][kQueue];
+    __shared__ uint32_t s_map[kWaves][kPts * kRow];
+    __shared__ int s_W[sizeof(Sched) / 4];
+    __shared__ int s_P[sizeof(PointArgs) / 4];
+    __shared__ int s_O[sizeof(SampOut) / 4];
+    if (threadIdx.x == 0) {
+        lds_park((lds_int *)s_W, W);
+        lds_park((lds_int *)s_P, P);
+        lds_park((lds_int *)s_O, O);
+    }
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    StackEntry *stack = s_stack[wave];
+    uint32_t *queue = s_queue[wave];
+    uint32_t *map = s_map[wave];
+    const int lane = threadIdx.x & 63;
+    const int slot = lane & (kInst - 1);  // the lane's instant within the packet
+    int kx = 0;
+    Unit un;
+    while (next_unit((lds_int *)s_W, 0, K, kx, un)) {
+        const int ka = uniform(un.a), kb = uniform(un.b);
+        if (kb <= ka) continue;
+        const int64_t n = lds_uniform<PointArgs>((lds_int *)s_P).n;
+        for (int g = 0; g < kInst; ++g) {
+            const int64_t i0 = (int64_t)un.tile * 64 + g * kPts;  // the group's first point
+            if (i0 >= n) break;
+            const int64_t i = i0 + lane / kInst;
+            const bool pvalid = i < n;
+            const LanePoint q = load_point(lds_uniform<PointArgs>((lds_int *)s_P), pvalid ? i : 0, pvalid);
+            // replay state of point `lane` of the group (lanes < kPts)
+            const bool rvalid = lane < kPts && i0 + lane < n;
+            int cnt = 0;
+            float mins = 0.f, run = 0.f, best = 0.f;
+            int bin = ld(samples + ka).tag & kBinMask;
+            int c_prim = -1, c_voff = 0, c_m = 0;  // the occluder cache
+            for (int w0 = ka; w0 < kb; w0 += kWin) {
+                const int w1 = min(w0 + kWin, kb);
+                for (int t = lane; t < kPts * kRow; t += 64) map[t] = 0u;
+                int queued = 0;
+                // one walk over the first nq queued rays; lanes past nq idle
+                auto walk = [&](int nq) {
+                    const bool on = lane < nq;
+                    const uint32_t e = on ? queue[lane] : 0u;
+                    const int pt = (int)(e & 63u), j = (int)(e >> 6);
+                    const SampleConst s = samples_g[on ? w0 + j : ka];
+                    // the middle ray's direction orders the children
+                    const SampleConst sm = ld(samples + w0 + uniform((int)(queue[nq >> 1] >> 6)));
+                    const LanePoint qw = load_point(lds_uniform<PointArgs>((lds_int *)s_P), i0 + pt, on);
+                    uint64_t hitm = 0;
+                    int b_prim = -1, b_voff = 0, b_m = 0, b_cnt = 0;
+                    const float ox = -qw.px * s.ix, oy = -qw.py * s.iy, oz = -qw.pz * s.iz;
+                    auto bt = [&](float x0, float y0, float x1, float y1, float z1) {
+                        const float ax = fmaf(x0, s.ix, ox), bx = fmaf(x1, s.ix, ox);
+                        const float ay = fmaf(y0, s.iy, oy), by = fmaf(y1, s.iy, oy);
+                        const float tfz = fmaf(z1, s.iz, oz);
+                        const float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), 0.f);
+                        const float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), tfz);
+                        return le_mask(tn, tf);
+                    };
+                    auto leaf = [&](int prim, int voff, int m, uint64_t want) -> uint64_t {
+                        const bool go = lane_in(want & ballot(prim != qw.own));
+                        if constexpr (kCount) {
+                            wk.prism += go ? 1u : 0u;
+                            wk.edges += go ? (uint32_t)m : 0u;
+                            wk.leaves += first_active_lane() ? 1u : 0u;
+                        }
+                        const bool t = go & ray_prism(verts, voff, m, ld(height + prim), qw.px, qw.py, qw.pz, s.dx,
+                                                      s.dy, s.dz);
+                        const uint64_t tm = ballot(t);
+                        hitm |= tm;
+                        const int cn = __builtin_popcountll(tm);
+                        if (cn > b_cnt) {
+                            b_cnt = cn;
+                            b_prim = prim;
+                            b_voff = voff;
+                            b_m = m;
+                        }
+                        return tm;  // a blocked ray needs no further test
+                    };
+                    auto key = [&](float x0, float y0, float x1, float y1, float z1) {
+                        return fmaf(x0 + x1, sm.dx, fmaf(y0 + y1, sm.dy, z1 * sm.dz));
+                    };
+                    packet_traverse<kCount>(nodes, stack, ballot(on), bt, leaf, key, wk);
+                    c_prim = uniform(b_cnt > 0 ? b_prim : -1);
+                    c_voff = uniform(b_voff);
+                    c_m = uniform(b_m);
+                    if (lane_in(hitm)) atomicOr(&map[pt * kRow + (j >> 5)], 1u << (j & 31));
+                };
+                for (int c0 = w0; c0 < w1; c0 += kInst) {
+                    const int k = c0 + slot;
+                    const bool valid = pvalid && k < w1;
+                    const SampleConst s = samples_g[k < w1 ? k : ka];
+                    const bool back = q.own >= 0 && fmaf(q.nx, s.dx, q.ny * s.dy) <= 0.f;
+                    uint64_t live = ballot(valid && !back);
+                    uint64_t cached = 0;
+                    if (nodes_g != nullptr && c_prim >= 0 && live) {
+                        const bool go = lane_in(live & ballot(c_prim != q.own));
+                        if constexpr (kCount) {
+                            wk.prism += go ? 1u : 0u;
+                            wk.edges += go ? (uint32_t)c_m : 0u;
+                            wk.leaves += first_active_lane() ? 1u : 0u;
+                        }
+                        cached = ballot(go & ray_prism(verts, c_voff, c_m, ld(height + c_prim), q.px, q.py, q.pz,
+                                                       s.dx, s.dy, s.dz));
+                        live &= ~cached;
+                    }
+                    if constexpr (kCount) wk.units += valid ? 1u : 0u;
+                    const int pt = lane / kInst, j = k - w0;
+                    if (valid && (back || lane_in(cached))) atomicOr(&map[pt * kRow + (j >> 5)], 1u << (j & 31));
+                    if (nodes_g != nullptr && live) {
+                        const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(live >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0u));
+                        if (lane_in(live)) queue[queued + rank] = ((uint32_t)j << 6) | (uint32_t)pt;
+                        queued += __builtin_popcountll(live);
+                        if (queued >= 64) {
+                            walk(64);
+                            // the rest (fewer than 64) to the front
+                            const bool more = 64 + lane < queued;
+                            const uint32_t e = more ? queue[64 + lane] : 0u;
+                            if (more) queue[lane] = e;
+                            queued -= 64;
+                        }
+                    }
+                }
+                if (queued > 0) walk(queued);
+                // the window's bitmap words are the output words
+                uint32_t *bits = lds_uniform<SampOut>((lds_int *)s_O).bits;
+                if (bits != nullptr)
+                    for (int t = lane; t < kPts * kWords; t += 64) {
+                        const int wd = t / kPts, p = t - wd * kPts;  // consecutive lanes: consecutive points
+                        if (i0 + p < n && w0 + 32 * wd < w1)
+                            bits[(int64_t)((w0 >> 5) + wd) * n + i0 + p] = map[p * kRow + wd];
+                    }
+                // replay in time order, one point per lane
+                for (int wd = 0; wd < kWords && w0 + 32 * wd < w1; ++wd) {
+                    const uint32_t word = rvalid ? map[lane * kRow + wd] : 0u;
+                    const int jb = min(32, w1 - w0 - 32 * wd);
+                    for (int b = 0; b < jb; ++b) {
+                        const SampleConst sj = ld(samples + (w0 + 32 * wd + b));
+                        const int sbin = sj.tag & kBinMask;
+                        if (sbin != bin) {
+                            if (rvalid)
+                                sampled_put(lds_uniform<SampOut>((lds_int *)s_O), (int64_t)bin * n + i0 + lane, cnt,
+                                            mins, best);
+                            cnt = 0;
+                            mins = 0.f;
+                            best = 0.f;
+                            bin = sbin;
+                        }
+                        if (sj.tag & kDayStart) run = 0.f;
+                        const bool sh = (word >> b) & 1u;
+                        cnt += sh ? 1 : 0;
+                        mins += sh ? sj.w : 0.f;
+                        run = sh ? run + sj.w : 0.f;
+                        best = fmaxf(best, run);
+                    }
+                }
+            }
+            if (rvalid) sampled_put(lds_uniform<SampOut>((lds_int *)s_O), (int64_t)bin * n + i0 + lane, cnt, mins, best);
         }
     }
     if constexpr (kCount) flush_work(wk, work);
@@ -1372,31 +1298,31 @@ sa_status launch_sampled(const DeviceScene &s, const DevicePath &p, const Points
     int64_t tiles;
     if (!tile_count(pts.n, tiles, err)) return SA_ERR_INVALID_ARG;
     const Node *nodes = s.n_b > 0 ? s.nodes : nullptr;
-    auto kern = bits ? (work ? k_sampled<true, true> : k_sampled<true, false>)
-                     : (work ? k_sampled<false, true> : k_sampled<false, false>);
-    // bit vectors pack 32 instants a word across bin boundaries: one part
-    // per tile then, so each word has one writer
+    const int ni = L.sampled_instants;
+    // Counts and minutes of units that lie in one bin: the queue with the
+    // points' sums in LDS (its entries hold the instant, below 2^26).  Bit
+    // vectors, the continuous shadow and bins that interleave: the queue
+    // with a bitmap replayed in time order; bit vectors pack 32 instants a
+    // word across bin boundaries, so a unit is then a whole tile and each
+    // word has one writer.
+    auto kern = work ? k_sampled_qb<true, 8> : k_sampled_qb<false, 8>;
+    if (ni == 1) kern = work ? k_sampled_qb<true, 1> : k_sampled_qb<false, 1>;
+    if (ni == 2) kern = work ? k_sampled_qb<true, 2> : k_sampled_qb<false, 2>;
+    if (ni == 4) kern = work ? k_sampled_qb<true, 4> : k_sampled_qb<false, 4>;
+    if (ni == 16) kern = work ? k_sampled_qb<true, 16> : k_sampled_qb<false, 16>;
+    const Split split = bits ? Split::kNone : Split::kUniqueBins;
     int64_t res = resident_blocks(kern, L);
-    Sched W = plan_units(p.sample_runs, 0, p.n_samples, tiles, bits ? Split::kNone : Split::kUniqueBins, res, grab);
-    // packets of several instants wherever every unit lies in one bin; a
-    // refill queue unless the continuous shadow asks for time order (or the
-    // instants overflow a queue entry's 26 bits)
-    if (!bits && (W.part_start != nullptr || p.sample_runs.start.size() == 2)) {
-        const int ni = L.sampled_instants;
-        if (longest || p.n_samples >= (1 << 26)) {
-            kern = work ? k_sampled_pk<true, 8> : k_sampled_pk<false, 8>;
-            if (ni == 4) kern = work ? k_sampled_pk<true, 4> : k_sampled_pk<false, 4>;
-            if (ni == 16) kern = work ? k_sampled_pk<true, 16> : k_sampled_pk<false, 16>;
-        } else {
-            kern = work ? k_sampled_q<true, 8> : k_sampled_q<false, 8>;
-            if (ni == 1) kern = work ? k_sampled_q<true, 1> : k_sampled_q<false, 1>;
-            if (ni == 2) kern = work ? k_sampled_q<true, 2> : k_sampled_q<false, 2>;
-            if (ni == 4) kern = work ? k_sampled_q<true, 4> : k_sampled_q<false, 4>;
-            if (ni == 16) kern = work ? k_sampled_q<true, 16> : k_sampled_q<false, 16>;
-        }
-        res = resident_blocks(kern, L);
-        W = plan_units(p.sample_runs, 0, p.n_samples, tiles, Split::kUniqueBins, res, grab);
+    Sched W = plan_units(p.sample_runs, 0, p.n_samples, tiles, split, res, grab);
+    if (!bits && !longest && p.n_samples < (1 << 26) &&
+        (W.part_start != nullptr || p.sample_runs.start.size() == 2)) {
+        kern = work ? k_sampled_q<true, 8> : k_sampled_q<false, 8>;
+        if (ni == 1) kern = work ? k_sampled_q<true, 1> : k_sampled_q<false, 1>;
+        if (ni == 2) kern = work ? k_sampled_q<true, 2> : k_sampled_q<false, 2>;
+        if (ni == 4) kern = work ? k_sampled_q<true, 4> : k_sampled_q<false, 4>;
+        if (ni == 16) kern = work ? k_sampled_q<true, 16> : k_sampled_q<false, 16>;
     }
+    res = resident_blocks(kern, L);
+    W = plan_units(p.sample_runs, 0, p.n_samples, tiles, split, res, grab);
     sa_status rc = fill_u32(grab, 8 * kGrabStride, 0u, st, err);
     if (rc != SA_OK) return rc;
     hipLaunchKernelGGL(kern, dim3((unsigned)unit_blocks(res, W)), dim3(kThreads), 0, st, nodes, s.verts,

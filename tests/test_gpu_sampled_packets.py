@@ -1,12 +1,13 @@
-"""The sampled form's kernels compute the same predicate per (point,
-instant) in different lane layouts: packets of 64 / k points x k
-consecutive instants (k = 4, 8, 16, walked as they come, when the
-continuous shadow is asked for; k = 1 ... 16, refilled to 64 rays through
-a queue, otherwise; both whenever every work unit lies in one bin), and 64
-points x 1 instant (with bit vectors, or when bins interleave).  Counts are equal,
-minutes equal to float rounding (the sums are grouped differently), the
-continuous shadow equals the definition applied to the bit vectors; and
-the counts agree with the oracle outside the silhouette band."""
+"""The sampled form's two queue kernels compute the same predicate per
+(point, instant) for every packet shape (64 / k points x k consecutive
+instants, k = 1 ... 16): the one that adds a walk's hits to per-point sums
+(counts and minutes of units in one bin) and the one that sets them in a
+bitmap replayed in time order (bit vectors, the continuous shadow, bins
+that interleave), whether its units are bin runs or whole tiles.  Counts
+are equal, minutes equal to float rounding (the sums are grouped
+differently), the continuous shadow equals the definition applied to the
+bit vectors; and the counts agree with the oracle outside the silhouette
+band."""
 import numpy as np
 import pytest
 
@@ -25,10 +26,11 @@ def ctx():
 
 
 def layouts(ctx, scene, pts, span, inst=8):
-    """Per call: "queue" (counts and minutes only: the refill queue where
-    units lie in one bin), "packets" (with the continuous shadow: packets of
-    ``inst`` instants in time order, 8 for 1 and 2) and "bits" (with bit
-    vectors: 64 x 1), each a dict of numpy arrays."""
+    """Per call, with packets of ``inst`` instants: "sums" (counts and
+    minutes only: per-point sums where units lie in one bin), "runs" (with
+    the continuous shadow: the replayed bitmap, units of one bin run) and
+    "bits" (with bit vectors: the replayed bitmap, a whole tile per unit),
+    each a dict of numpy arrays."""
     import torch
     ctx.set_launch(sampled_instants_per_packet=inst)
     sp = sa.sunpath_for_span(span, 30.0)   # knots do not matter to the sampled form
@@ -37,7 +39,7 @@ def layouts(ctx, scene, pts, span, inst=8):
     dp = sa.DevicePoints.from_workload(pts)
     B, K = path.n_bins, sp.n_samples
     out = {}
-    for name, runs, bits in (("queue", False, False), ("packets", True, False), ("bits", True, True)):
+    for name, runs, bits in (("sums", False, False), ("runs", True, False), ("bits", True, True)):
         c = torch.empty((B, dp.n), dtype=torch.int32, device="cuda")
         m = torch.empty((B, dp.n), dtype=torch.float32, device="cuda")
         L = torch.empty((B, dp.n), dtype=torch.float32, device="cuda") if runs else None
@@ -59,7 +61,7 @@ CASES = {
     "days": lambda w: w.span,
     # one bin over three days: a single run of instants
     "one_bin": lambda w: Span(w.span.lat, w.span.lon, w.span.days, w.span.step_min, [0, 0, 0]),
-    # bins that interleave: the 64 x 1 layout for both calls
+    # bins that interleave: units span bins (the bitmap kernel for every call)
     "interleaved": lambda w: Span(w.span.lat, w.span.lon, w.span.days, w.span.step_min, [0, 1, 0]),
 }
 
@@ -72,14 +74,14 @@ def test_layouts_agree(ctx, case, inst):
     span = CASES[case](w)
     r, sp = layouts(ctx, w.scene, sub, span, inst)
     ref = r["bits"]
-    for name in ("queue", "packets"):
+    for name in ("sums", "runs"):
         np.testing.assert_array_equal(r[name]["counts"], ref["counts"])
         dm = np.abs(r[name]["minutes"] - ref["minutes"])
         say(f"{case}, {inst} instants per packet, {name}: counts equal over {sub.n} points x {sp.n_samples} "
             f"instants; max |minutes diff| {dm.max():.2e}")
         assert np.all(dm <= 1e-5 * np.abs(ref["minutes"]) + 1e-3)
     runs = oracle.longest_sampled(ref["bits"].astype(bool), oracle.sun_path(span))
-    np.testing.assert_allclose(r["packets"]["longest"], runs, rtol=1e-5, atol=1e-3)
+    np.testing.assert_allclose(r["runs"]["longest"], runs, rtol=1e-5, atol=1e-3)
     np.testing.assert_allclose(ref["longest"], runs, rtol=1e-5, atol=1e-3)
     assert (ref["counts"] > 0).mean() > 0.3
 
@@ -99,7 +101,7 @@ def test_layouts_against_oracle(ctx):
     ob = unpack_words(o["bits"], len(op.w)).astype(bool)
     na = np.stack([amb[:, op.sample_day == d].sum(1) for d in range(len(days))])
     oc = np.stack([ob[:, op.sample_day == d].sum(1) for d in range(len(days))])
-    for name in ("queue", "packets", "bits"):
+    for name in ("sums", "runs", "bits"):
         dc = np.abs(r[name]["counts"] - oc)
         say(f"{name} vs oracle: {int((na > 0).sum())} of {na.size} point-days touch the band; "
             f"max |count diff| {int(dc.max())}")
@@ -109,10 +111,11 @@ def test_layouts_against_oracle(ctx):
 
 @pytest.mark.parametrize("inst", [1, 4, 16])
 def test_queue_on_tiny_and_ragged_sets(ctx, c1, inst):
-    """The refill queue on point sets of 1, 3, 63, 65 and 200 points of the
-    small scene (a single partial group, partial tiles, several tiles), on
-    one building and on an empty scene: counts equal to the bit-vector
-    layout's, and those equal to the oracle's outside the silhouette band."""
+    """Both queue kernels on point sets of 1, 3, 63, 65 and 200 points of
+    the small scene (a single partial group, partial tiles, several tiles),
+    on one building and on an empty scene: equal counts in every call, equal
+    to the oracle's outside the silhouette band, and no shadow (no bit set)
+    without buildings."""
     from workloads import Scene
     op = oracle.sun_path(c1.span)
     one = c1.scene.subset(np.array([5]))
@@ -121,11 +124,15 @@ def test_queue_on_tiny_and_ragged_sets(ctx, c1, inst):
         sub = c1.points.take(np.arange(7, 7 + n * 13, 13))
         for scene in (c1.scene, one):
             r, _ = layouts(ctx, scene, sub, c1.span, inst)
-            np.testing.assert_array_equal(r["queue"]["counts"], r["bits"]["counts"])
-            assert np.abs(r["queue"]["minutes"] - r["bits"]["minutes"]).max() <= 1e-3
+            for name in ("sums", "runs"):
+                np.testing.assert_array_equal(r[name]["counts"], r["bits"]["counts"])
+                assert np.abs(r[name]["minutes"] - r["bits"]["minutes"]).max() <= 1e-3
+            np.testing.assert_array_equal(r["bits"]["bits"].sum(1), r["bits"]["counts"].sum(0))
         o = oracle.sampled(c1.scene, sub, op, amb=True)
         r, _ = layouts(ctx, c1.scene, sub, c1.span, inst)
-        dc = np.abs(r["queue"]["counts"].sum(0) - o["counts"].sum(0))
+        dc = np.abs(r["sums"]["counts"].sum(0) - o["counts"].sum(0))
         assert np.all(dc <= o["amb"].sum(1))
         r, _ = layouts(ctx, empty, sub, c1.span, inst)
-        assert np.all(r["queue"]["counts"] == 0) and np.all(r["queue"]["minutes"] == 0)
+        for name in ("sums", "runs", "bits"):
+            assert np.all(r[name]["counts"] == 0) and np.all(r[name]["minutes"] == 0)
+        assert not r["bits"]["bits"].any() and np.all(r["runs"]["longest"] == 0)
