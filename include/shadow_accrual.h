@@ -111,6 +111,14 @@ const char *sa_last_error(const sa_ctx *ctx);
 sa_status sa_sync(sa_ctx *ctx);
 /* Library version string. */
 const char *sa_version(void);
+/* Measurement aid for the roofline, not a step of the method: the vector
+ * ALU's FP32 lane-op rate on the context's device, measured with chains of
+ * independent fused multiply-adds (one VALU operation per lane each) on the
+ * context's stream; the best of three timed launches after a warm-up.
+ * Host-synchronous; allocates nothing (its never-taken store points into
+ * the context's own queue).  *lane_ops_per_s: host double.  Errors:
+ * INVALID_ARG, DEVICE. */
+sa_status sa_measure_valu_peak(sa_ctx *ctx, double *lane_ops_per_s);
 
 /* ------------------------------------------------------------------ */
 /* scene: buildings as extruded convex prisms (a city model, Sec. 8.2) */

@@ -27,7 +27,7 @@ _ERRORS = {-1: "INVALID_ARG", -2: "GEOMETRY", -3: "CAPACITY", -4: "OOM", -5: "DE
 
 # Every entry point declared in include/shadow_accrual.h.
 EXPORTS = ["sa_create", "sa_destroy", "sa_set_stream", "sa_set_launch", "sa_get_launch", "sa_last_error", "sa_sync",
-           "sa_version",
+           "sa_version", "sa_measure_valu_peak",
            "sa_scene_upload", "sa_scene_set_heights", "sa_scene_get_info", "sa_scene_read_bvh",
            "sa_scene_destroy", "sa_sunpath", "sa_path_upload", "sa_path_upload_graph", "sa_path_info", "sa_path_destroy",
            "sa_accumulate", "sa_accumulate_noalloc", "sa_accumulate_batched", "sa_grad_heights", "sa_region_sum",
@@ -106,6 +106,7 @@ def lib():
             "sa_last_error": (C.c_char_p, [vp]),
             "sa_sync": (i32, [vp]),
             "sa_version": (C.c_char_p, []),
+            "sa_measure_valu_peak": (i32, [vp, C.POINTER(C.c_double)]),
             "sa_scene_upload": (i32, [vp, i32, vp, vp, vp, C.POINTER(vp)]),
             "sa_scene_set_heights": (i32, [vp, vp, i32, vp, vp]),
             "sa_scene_get_info": (i32, [vp, C.POINTER(sa_scene_info)]),
@@ -265,6 +266,13 @@ class Context:
         l = sa_launch(int(accrual_segments_per_launch), int(batched_grid_blocks), int(batched_tiles_per_grab),
                       int(tile_grid_blocks), int(accrual_waves_per_simd), int(sampled_instants_per_packet))
         _check(self, lib().sa_set_launch(self.handle, C.byref(l)))
+
+    def measure_valu_peak(self) -> float:
+        """FP32 lane-ops per second the device's vector ALUs sustain
+        (sa_measure_valu_peak; a roofline measurement aid)."""
+        v = C.c_double(0.0)
+        _check(self, lib().sa_measure_valu_peak(self.handle, C.byref(v)))
+        return float(v.value)
 
     def get_launch(self) -> dict:
         l = sa_launch()

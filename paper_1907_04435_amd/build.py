@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsa.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["api.cpp", "sunpath.cpp", "bvh.hip", "accumulate.hip", "grad.hip", "reduce.hip", "sam.hip"]
+SOURCES = ["api.cpp", "sunpath.cpp", "bvh.hip", "accumulate.hip", "grad.hip", "reduce.hip", "sam.hip", "peak.hip"]
 ARCH = "gfx950"
 
 # Device code: never emit packed-FP32 instructions (disabled outright for

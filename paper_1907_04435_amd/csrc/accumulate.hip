@@ -61,7 +61,7 @@ __device__ __forceinline__ void flush_work(const Work &w, uint64_t *work)
     for (int c = 0; c < 8; ++c) {
         uint64_t s = v[c];
         for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-        if ((threadIdx.x & 63) == 0 && s) atomicAdd((unsigned long long *)&work[c], (unsigned long long)s);
+        if ((tid() & 63) == 0 && s) atomicAdd((unsigned long long *)&work[c], (unsigned long long)s);
     }
 }
 
@@ -122,18 +122,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     __shared__ int s_W[sizeof(Sched) / 4];
     __shared__ int s_P[sizeof(PointArgs) / 4];
     __shared__ int s_O[sizeof(SampOut) / 4];
-    if (threadIdx.x == 0) {
+    if (tid() == 0) {
         lds_park((lds_int *)s_W, W);
         lds_park((lds_int *)s_P, P);
         lds_park((lds_int *)s_O, O);
     }
     __syncthreads();
-    const int wave = threadIdx.x >> 6;
+    const int wave = tid() >> 6;
     StackEntry *stack = s_stack[wave];
     uint32_t *queue = s_queue[wave];
     int *g_cnt = s_cnt[wave];
     float *g_min = s_min[wave];
-    const int lane = threadIdx.x & 63;
+    const int lane = tid() & 63;
     const int slot = lane & (kInst - 1);  // the lane's instant within the packet
     int kx = 0;
     Unit un;
@@ -296,17 +296,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     __shared__ int s_W[sizeof(Sched) / 4];
     __shared__ int s_P[sizeof(PointArgs) / 4];
     __shared__ int s_O[sizeof(SampOut) / 4];
-    if (threadIdx.x == 0) {
+    if (tid() == 0) {
         lds_park((lds_int *)s_W, W);
         lds_park((lds_int *)s_P, P);
         lds_park((lds_int *)s_O, O);
     }
     __syncthreads();
-    const int wave = threadIdx.x >> 6;
+    const int wave = tid() >> 6;
     StackEntry *stack = s_stack[wave];
     uint32_t *queue = s_queue[wave];
     uint32_t *map = s_map[wave];
-    const int lane = threadIdx.x & 63;
+    const int lane = tid() & 63;
     const int slot = lane & (kInst - 1);  // the lane's instant within the packet
     int kx = 0;
     Unit un;
@@ -580,7 +580,7 @@ __device__ __forceinline__ int view_ref(int r) { return r >= 0 ? r * (int)sizeof
 __global__ void k_seg_nodes(const Node *__restrict__ nodes, int n_nodes, const SegConst *__restrict__ segs, int j0,
                             int j1, int64_t stride, SegNode *__restrict__ out)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)wg_id() * wg_size() + tid();
     if (t >= (int64_t)(j1 - j0) * n_nodes) return;
     const int jj = (int)(t / n_nodes);
     const int node = (int)(t - (int64_t)jj * n_nodes);
@@ -634,15 +634,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(kOcc))
     __shared__ int s_S[sizeof(SpillArgs) / 4];
     __shared__ int s_W[sizeof(Sched) / 4];
     __shared__ int s_P[sizeof(PointArgs) / 4];
-    if (threadIdx.x == 0) {
+    if (tid() == 0) {
         lds_park((lds_int *)s_O, O);
         lds_park((lds_int *)s_S, S);
         lds_park((lds_int *)s_W, W);
         lds_park((lds_int *)s_P, P);
     }
     __syncthreads();
-    StackEntry *stack = s_stack[threadIdx.x >> 6];
-    const int lane = threadIdx.x & 63;
+    StackEntry *stack = s_stack[tid() >> 6];
+    const int lane = tid() & 63;
     int kx = 0;
     Unit un;
     while (next_unit((lds_int *)s_W, j0, j1, kx, un)) {
@@ -710,8 +710,8 @@ __global__ void k_add_pieces(Sched W, int j0, int j1, const SegConst *__restrict
     const int sub = W.sub > 1 ? W.sub : 1;
     const int runs = (int)W.n_parts / sub;
     const int64_t total = (int64_t)runs * n;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+    const int64_t stride = (int64_t)n_wg() * wg_size();
+    for (int64_t t = (int64_t)wg_id() * wg_size() + tid(); t < total; t += stride) {
         const int r = (int)(t / n);
         const int64_t i = t - (int64_t)r * n;
         int cnt = 0;
@@ -771,7 +771,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
     __shared__ int s_P[sizeof(PointArgs) / 4];
     __shared__ float *s_longest;
     __shared__ uint32_t *s_overflow;
-    if (threadIdx.x == 0) {
+    if (tid() == 0) {
         lds_park((lds_int *)s_O, O);
         lds_park((lds_int *)s_W, W);
         lds_park((lds_int *)s_P, P);
@@ -779,8 +779,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
         s_overflow = overflow;
     }
     __syncthreads();
-    StackEntry *stack = s_stack[threadIdx.x >> 6];
-    const int lane = threadIdx.x & 63;
+    StackEntry *stack = s_stack[tid() >> 6];
+    const int lane = tid() & 63;
     Work none{0, 0, 0, 0, 0, 0, 0};
     int kx = 0;
     Unit un;
@@ -877,11 +877,11 @@ __global__ __launch_bounds__(kThreads) void k_spill(const SegNode *snodes_g, int
     cfloat *height = (cfloat *)height_g;
     cSeg *segs = (cSeg *)segs_g;
     __shared__ StackEntry s_stack[kWaves][kStackDepth];
-    StackEntry *stack = s_stack[threadIdx.x >> 6];
-    const int lane = threadIdx.x & 63;
+    StackEntry *stack = s_stack[tid() >> 6];
+    const int lane = tid() & 63;
     const int64_t total = min((int32_t)*in_count, cap);
-    const int64_t stride = (int64_t)gridDim.x * kWaves;
-    for (int64_t e = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); e < total; e += stride) {
+    const int64_t stride = (int64_t)n_wg() * kWaves;
+    for (int64_t e = (int64_t)wg_id() * kWaves + (tid() >> 6); e < total; e += stride) {
         const int4 en = in[e];
         const int64_t i = uniform(en.x);
         const int j = uniform(en.y);
@@ -936,13 +936,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
     __shared__ StackEntry s_stack[kWaves][kStackDepth];
     __shared__ int s_W[sizeof(Sched) / 4];
     __shared__ int s_P[sizeof(PointArgs) / 4];
-    if (threadIdx.x == 0) {
+    if (tid() == 0) {
         lds_park((lds_int *)s_W, W);
         lds_park((lds_int *)s_P, P);
     }
     __syncthreads();
-    StackEntry *stack = s_stack[threadIdx.x >> 6];
-    const int lane = threadIdx.x & 63;
+    StackEntry *stack = s_stack[tid() >> 6];
+    const int lane = tid() & 63;
     Work none{0, 0, 0, 0, 0, 0, 0};
     int kx = 0;
     Unit un;
@@ -1019,17 +1019,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(8))) v
 __global__ void k_var_copy(const int4 *__restrict__ base_nodes, int64_t node_words, const float *__restrict__ base_h,
                            int n_b, int V, int4 *__restrict__ vnodes, float *__restrict__ vh)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)V * node_words; t += stride)
+    const int64_t stride = (int64_t)n_wg() * wg_size();
+    for (int64_t t = (int64_t)wg_id() * wg_size() + tid(); t < (int64_t)V * node_words; t += stride)
         vnodes[t] = base_nodes[t % node_words];
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < (int64_t)V * n_b; t += stride)
+    for (int64_t t = (int64_t)wg_id() * wg_size() + tid(); t < (int64_t)V * n_b; t += stride)
         vh[t] = base_h[t % n_b];
 }
 
 __global__ void k_var_heights(int V, int k, const int32_t *__restrict__ ids, const float *__restrict__ h,
                               const int32_t *__restrict__ rank, int n_b, float *__restrict__ vh, uint32_t *flag)
 {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int t = wg_id() * wg_size() + tid();
     if (t >= V * k) return;
     const int id = ids[t];
     const float hv = h[t];
@@ -1044,7 +1044,7 @@ __global__ void k_var_refit(int V, int k, const int32_t *__restrict__ ids, const
                             const int32_t *__restrict__ parent, int n_int, int n_b, int n_nodes,
                             const float *__restrict__ vh, Node *vnodes)
 {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = wg_id() * wg_size() + tid();
     if (v >= V) return;
     Node *nodes = vnodes + (int64_t)v * n_nodes;
     for (int j = 0; j < k; ++j) {
@@ -1079,7 +1079,7 @@ __global__ void k_var_list(int V, int k, const int32_t *__restrict__ ids, const 
                            const int32_t *__restrict__ parent, int n_int, int n_b, int n_nodes, int cmax,
                            int32_t *__restrict__ vlist, int32_t *__restrict__ vcount, int32_t *__restrict__ vroot)
 {
-    const int v = blockIdx.x * blockDim.x + threadIdx.x;
+    const int v = wg_id() * wg_size() + tid();
     if (v >= V) return;
     int32_t *L = vlist + (int64_t)v * cmax;
     int c = 0;
@@ -1108,7 +1108,7 @@ __global__ void k_var_list(int V, int k, const int32_t *__restrict__ ids, const 
 __global__ void k_var_refs(int V, int cmax, int n_nodes, const Node *__restrict__ nodes,
                            const int32_t *__restrict__ vlist, const int32_t *__restrict__ vcount, int2 *__restrict__ vref)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)wg_id() * wg_size() + tid();
     if (t >= (int64_t)V * cmax) return;
     const int v = (int)(t / cmax), c = (int)(t - (int64_t)v * cmax);
     const int n = vcount[v];
@@ -1132,7 +1132,7 @@ __global__ void k_seg_var(int V, int cmax, int n_nodes, const Node *__restrict__
                           const int2 *__restrict__ vref, const SegConst *__restrict__ segs, int j0, int j1,
                           int64_t stride, SegNode *__restrict__ out)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)wg_id() * wg_size() + tid();
     const int64_t per = (int64_t)V * cmax;
     if (t >= (int64_t)(j1 - j0) * per) return;
     const int jj = (int)(t / per);
@@ -1147,7 +1147,7 @@ __global__ void k_seg_var(int V, int cmax, int n_nodes, const Node *__restrict__
 // tile_off[v] = first tile of variant v, 64 points per tile
 __global__ void k_var_tiles(int V, const int64_t *__restrict__ var_off, int64_t *__restrict__ tile_off)
 {
-    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    if (wg_id() != 0 || tid() != 0) return;
     int64_t t = 0;
     for (int v = 0; v < V; ++v) {
         tile_off[v] = t;
@@ -1176,11 +1176,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
     cSeg *segs = (cSeg *)segs_g;
     __shared__ StackEntry s_stack[kWaves][kStackDepth];
     __shared__ int s_P[sizeof(PointArgs) / 4];
-    StackEntry *stack = s_stack[threadIdx.x >> 6];
-    const int lane = threadIdx.x & 63;
+    StackEntry *stack = s_stack[tid() >> 6];
+    const int lane = tid() & 63;
     const int64_t T = tile_off[V];
     const int64_t n = P.n;
-    if (threadIdx.x == 0) lds_park((lds_int *)s_P, P);
+    if (tid() == 0) lds_park((lds_int *)s_P, P);
     __syncthreads();
     // a wave takes `grab` consecutive (variant, tile) items per atomic
     int64_t t = 0, t_end = 0;
@@ -1263,8 +1263,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
 
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) p[t] = v;
+    const int64_t stride = (int64_t)n_wg() * wg_size();
+    for (int64_t t = (int64_t)wg_id() * wg_size() + tid(); t < n; t += stride) p[t] = v;
 }
 
 __global__ void k_zero_u32(uint32_t *p) { *p = 0u; }

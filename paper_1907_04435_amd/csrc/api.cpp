@@ -241,6 +241,16 @@ sa_status sa_set_stream(sa_ctx *ctx, void *hip_stream)
 
 const char *sa_last_error(const sa_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
+sa_status sa_measure_valu_peak(sa_ctx *ctx, double *lane_ops_per_s)
+{
+    if (!ctx || !lane_ops_per_s) return SA_ERR_INVALID_ARG;
+    if (!set_device(ctx)) return fail(ctx, SA_ERR_DEVICE, "hipSetDevice failed");
+    std::string err;
+    const sa_status rc = sa::measure_valu_peak(ctx->n_cu, (float *)ctx->spill.entries[0],
+                                               (int64_t)ctx->spill.capacity * 4, ctx->stream, *lane_ops_per_s, err);
+    return rc == SA_OK ? SA_OK : fail(ctx, rc, err);
+}
+
 sa_status sa_sync(sa_ctx *ctx)
 {
     if (!ctx) return SA_ERR_INVALID_ARG;

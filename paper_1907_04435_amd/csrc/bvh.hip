@@ -35,7 +35,7 @@ constexpr int kSortTile = kSortThreads * kSortItems;
 __global__ void k_prism_box(int n_b, const int32_t *__restrict__ voff, const float2 *__restrict__ xy,
                             float4 *__restrict__ box)
 {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = wg_id() * wg_size() + tid();
     if (b >= n_b) return;
     float x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY;
     for (int v = voff[b]; v < voff[b + 1]; ++v) {
@@ -54,7 +54,7 @@ __global__ void k_bounds(int n_b, const float4 *__restrict__ box, const float *_
 {
     __shared__ float red[5][1024];
     float x0 = INFINITY, y0 = INFINITY, x1 = -INFINITY, y1 = -INFINITY, hm = 0.f;
-    for (int b = threadIdx.x; b < n_b; b += blockDim.x) {
+    for (int b = tid(); b < n_b; b += wg_size()) {
         float4 q = box[b];
         x0 = fminf(x0, q.x);
         y0 = fminf(y0, q.y);
@@ -62,23 +62,23 @@ __global__ void k_bounds(int n_b, const float4 *__restrict__ box, const float *_
         y1 = fmaxf(y1, q.w);
         hm = fmaxf(hm, h[b]);
     }
-    red[0][threadIdx.x] = x0;
-    red[1][threadIdx.x] = y0;
-    red[2][threadIdx.x] = x1;
-    red[3][threadIdx.x] = y1;
-    red[4][threadIdx.x] = hm;
+    red[0][tid()] = x0;
+    red[1][tid()] = y0;
+    red[2][tid()] = x1;
+    red[3][tid()] = y1;
+    red[4][tid()] = hm;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s) {
-            red[0][threadIdx.x] = fminf(red[0][threadIdx.x], red[0][threadIdx.x + s]);
-            red[1][threadIdx.x] = fminf(red[1][threadIdx.x], red[1][threadIdx.x + s]);
-            red[2][threadIdx.x] = fmaxf(red[2][threadIdx.x], red[2][threadIdx.x + s]);
-            red[3][threadIdx.x] = fmaxf(red[3][threadIdx.x], red[3][threadIdx.x + s]);
-            red[4][threadIdx.x] = fmaxf(red[4][threadIdx.x], red[4][threadIdx.x + s]);
+    for (int s = wg_size() / 2; s > 0; s >>= 1) {
+        if ((int)tid() < s) {
+            red[0][tid()] = fminf(red[0][tid()], red[0][tid() + s]);
+            red[1][tid()] = fminf(red[1][tid()], red[1][tid() + s]);
+            red[2][tid()] = fmaxf(red[2][tid()], red[2][tid() + s]);
+            red[3][tid()] = fmaxf(red[3][tid()], red[3][tid() + s]);
+            red[4][tid()] = fmaxf(red[4][tid()], red[4][tid() + s]);
         }
         __syncthreads();
     }
-    if (threadIdx.x < 5) out[threadIdx.x] = red[threadIdx.x][0];
+    if (tid() < 5) out[tid()] = red[tid()][0];
 }
 
 __device__ inline uint32_t spread16(uint32_t v)
@@ -96,7 +96,7 @@ __device__ inline uint32_t spread16(uint32_t v)
 __global__ void k_morton(int n_b, const float4 *__restrict__ box, const float *__restrict__ bounds,
                          uint32_t *__restrict__ key, int32_t *__restrict__ val)
 {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    int b = wg_id() * wg_size() + tid();
     if (b >= n_b) return;
     float ext = fmaxf(fmaxf(bounds[2] - bounds[0], bounds[3] - bounds[1]), 1e-6f);
     float4 q = box[b];
@@ -114,14 +114,14 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(int n, int shift, in
                                                             uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    h[tid()] = 0;
     __syncthreads();
     for (int j = 0; j < kSortItems; ++j) {
-        int i = blockIdx.x * kSortTile + j * kSortThreads + threadIdx.x;
+        int i = wg_id() * kSortTile + j * kSortThreads + tid();
         if (i < n) atomicAdd(&h[(key[i] >> shift) & 255u], 1u);
     }
     __syncthreads();
-    hist[threadIdx.x * nblk + blockIdx.x] = h[threadIdx.x];
+    hist[tid() * nblk + wg_id()] = h[tid()];
 }
 
 // Exclusive scan of m uint32 in place, one block of 1024 threads.
@@ -129,18 +129,18 @@ __global__ __launch_bounds__(1024) void k_scan_u32(int m, uint32_t *__restrict__
 {
     __shared__ uint32_t part[1024];
     int per = (m + 1023) / 1024;
-    int lo = threadIdx.x * per, hi = min(lo + per, m);
+    int lo = tid() * per, hi = min(lo + per, m);
     uint32_t s = 0;
     for (int i = lo; i < hi; ++i) s += a[i];
-    part[threadIdx.x] = s;
+    part[tid()] = s;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t v = threadIdx.x >= (unsigned)off ? part[threadIdx.x - off] : 0u;
+        uint32_t v = tid() >= (unsigned)off ? part[tid() - off] : 0u;
         __syncthreads();
-        part[threadIdx.x] += v;
+        part[tid()] += v;
         __syncthreads();
     }
-    uint32_t run = part[threadIdx.x] - s;
+    uint32_t run = part[tid()] - s;
     for (int i = lo; i < hi; ++i) {
         uint32_t v = a[i];
         a[i] = run;
@@ -154,12 +154,12 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 {
     __shared__ uint32_t base[256];
     __shared__ uint32_t cnt[kSortThreads / 64][256];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    base[threadIdx.x] = hist[threadIdx.x * nblk + blockIdx.x];
-    for (int w = 0; w < kSortThreads / 64; ++w) cnt[w][threadIdx.x] = 0;
+    const int lane = tid() & 63, wave = tid() >> 6;
+    base[tid()] = hist[tid() * nblk + wg_id()];
+    for (int w = 0; w < kSortThreads / 64; ++w) cnt[w][tid()] = 0;
     __syncthreads();
     for (int j = 0; j < kSortItems; ++j) {
-        int i = blockIdx.x * kSortTile + j * kSortThreads + threadIdx.x;
+        int i = wg_id() * kSortTile + j * kSortThreads + tid();
         bool valid = i < n;
         uint32_t k = valid ? key_in[i] : 0u;
         uint32_t dgt = (k >> shift) & 255u;
@@ -181,10 +181,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
         __syncthreads();
         uint32_t tot = 0;
         for (int w = 0; w < kSortThreads / 64; ++w) {
-            tot += cnt[w][threadIdx.x];
-            cnt[w][threadIdx.x] = 0;
+            tot += cnt[w][tid()];
+            cnt[w][tid()] = 0;
         }
-        base[threadIdx.x] += tot;
+        base[tid()] += tot;
         __syncthreads();
     }
 }
@@ -192,7 +192,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(
 __global__ void k_scatter_rank(int n_b, const int32_t *__restrict__ order, int32_t *__restrict__ rank,
                                const int32_t *__restrict__ voff_in, uint32_t *__restrict__ m_sorted)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = wg_id() * wg_size() + tid();
     if (j > n_b) return;
     if (j == n_b) {
         m_sorted[j] = 0;
@@ -211,7 +211,7 @@ __global__ void k_gather_prisms(int n_b, const int32_t *__restrict__ order,
                                 const uint32_t *__restrict__ voff_sorted, int32_t *__restrict__ voff,
                                 float4 *__restrict__ verts, float *__restrict__ h, float4 *__restrict__ pbox)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = wg_id() * wg_size() + tid();
     if (j > n_b) return;
     voff[j] = (int32_t)voff_sorted[j];
     if (j == n_b) return;
@@ -238,7 +238,7 @@ __device__ inline int karras_delta(const uint32_t *__restrict__ k, int n, int i,
 __global__ void k_karras(int n, const uint32_t *__restrict__ key, const int32_t *__restrict__ voff,
                          Node *__restrict__ nodes, int32_t *__restrict__ parent)
 {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = wg_id() * wg_size() + tid();
     if (i >= n - 1) return;
     int d = (karras_delta(key, n, i, i + 1) - karras_delta(key, n, i, i - 1)) >= 0 ? 1 : -1;
     int dmin = karras_delta(key, n, i, i - d);
@@ -297,7 +297,7 @@ __device__ inline void put_box(Node *nd, int side, float x0, float y0, float x1,
 __global__ void k_refit(int n_b, int n_int, const float4 *__restrict__ pbox, const float *__restrict__ h,
                         const int32_t *__restrict__ parent, Node *nodes, int32_t *flags)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = wg_id() * wg_size() + tid();
     if (j >= n_b) return;
     float4 b = pbox[j];
     float x0 = pad_lo(b.x), y0 = pad_lo(b.y), x1 = pad_hi(b.z), y1 = pad_hi(b.w), z1 = pad_hi(h[j]);
@@ -322,7 +322,7 @@ __global__ void k_refit(int n_b, int n_int, const float4 *__restrict__ pbox, con
 __global__ void k_set_heights(int32_t n, const int32_t *__restrict__ ids, const float *__restrict__ h,
                               const int32_t *__restrict__ rank, int32_t n_b, float *height, uint32_t *flag)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = wg_id() * wg_size() + tid();
     if (k >= n) return;
     const int32_t id = ids[k];
     const float v = h[k];
@@ -335,13 +335,13 @@ __global__ void k_set_heights(int32_t n, const int32_t *__restrict__ ids, const 
 
 __global__ void k_clear_i32(int32_t *p, int32_t n)
 {
-    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    const int k = wg_id() * wg_size() + tid();
     if (k < n) p[k] = 0;
 }
 
 __global__ void k_depth(int n_b, int n_int, const int32_t *__restrict__ parent, int32_t *depth)
 {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
+    int j = wg_id() * wg_size() + tid();
     if (j >= n_b) return;
     int d = 1, pp = parent[n_int + j];
     while (pp >= 0 && d < 4096) {

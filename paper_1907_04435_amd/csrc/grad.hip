@@ -88,7 +88,7 @@ __device__ __forceinline__ void grad_segment(cSegNode *snodes, cint *voff, Stack
 // lane of the wave (the shuffles read all lanes).
 __device__ __forceinline__ void wave_scatter(int prim, double v, const GradArgs &G)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = tid() & 63;
     uint64_t pend = ballot(prim >= 0);
     while (pend) {
         const int lead = __builtin_ctzll(pend);
@@ -152,15 +152,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(7))) v
     __shared__ int s_P[sizeof(PointArgs) / 4];
     __shared__ int s_G[sizeof(GradArgs) / 4];
     __shared__ int s_S[sizeof(SpillArgs) / 4];
-    if (threadIdx.x == 0) {
+    if (tid() == 0) {
         lds_park((lds_int *)s_W, W);
         lds_park((lds_int *)s_P, P);
         lds_park((lds_int *)s_G, G);
         lds_park((lds_int *)s_S, S);
     }
     __syncthreads();
-    StackEntry *stack = s_stack[threadIdx.x >> 6];
-    const int lane = threadIdx.x & 63;
+    StackEntry *stack = s_stack[tid() >> 6];
+    const int lane = tid() & 63;
     int kx = 0;
     Unit un;
     while (next_unit((lds_int *)s_W, j0, j1, kx, un)) {
@@ -205,11 +205,11 @@ __global__ __launch_bounds__(kThreads) void k_grad_spill(const SegNode *snodes_g
     cfloat *height = (cfloat *)height_g;
     cSeg *segs = (cSeg *)segs_g;
     __shared__ StackEntry s_stack[kWaves][kStackDepth];
-    StackEntry *stack = s_stack[threadIdx.x >> 6];
-    const int lane = threadIdx.x & 63;
+    StackEntry *stack = s_stack[tid() >> 6];
+    const int lane = tid() & 63;
     const int64_t total = min((int32_t)*in_count, cap);
-    const int64_t stride = (int64_t)gridDim.x * kWaves;
-    for (int64_t e = (int64_t)blockIdx.x * kWaves + (threadIdx.x >> 6); e < total; e += stride) {
+    const int64_t stride = (int64_t)n_wg() * kWaves;
+    for (int64_t e = (int64_t)wg_id() * kWaves + (tid() >> 6); e < total; e += stride) {
         const int4 en = in[e];
         const int64_t i = uniform(en.x);
         const int j = uniform(en.y);
@@ -234,7 +234,7 @@ __global__ void k_zero1(uint32_t *p) { *p = 0u; }
 // grad[b] = (add ? grad[b] : 0) + scale * acc[b], rounded once to float.
 __global__ void k_grad_out(const double *acc, int32_t n_b, double scale, int add, float *grad)
 {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    const int b = wg_id() * wg_size() + tid();
     if (b < n_b) grad[b] = (float)((add ? (double)grad[b] : 0.0) + scale * acc[b]);
 }
 

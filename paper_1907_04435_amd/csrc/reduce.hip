@@ -22,10 +22,10 @@ __global__ __launch_bounds__(kThreads) void k_region_part(const float *__restric
                                                           const float *__restrict__ area, double *__restrict__ part)
 {
     __shared__ double red[kThreads / 64];
-    const int r = blockIdx.y;
+    const int r = wg_id_y();
     const int64_t lo = off[r], hi = off[r + 1];
     double s = 0.0;
-    for (int64_t i = lo + (int64_t)blockIdx.x * kThreads + threadIdx.x; i < hi;
+    for (int64_t i = lo + (int64_t)wg_id() * kThreads + tid(); i < hi;
          i += (int64_t)kBlocksPerRegion * kThreads) {
         double x;
         if (bin_w) {
@@ -37,19 +37,19 @@ __global__ __launch_bounds__(kThreads) void k_region_part(const float *__restric
         s += x * (area ? (double)area[i] : 1.0);
     }
     for (int o = 32; o > 0; o >>= 1) s += __shfl_down(s, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    if ((tid() & 63) == 0) red[tid() >> 6] = s;
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid() == 0) {
         double t = 0.0;
         for (int w = 0; w < kThreads / 64; ++w) t += red[w];
-        part[(int64_t)r * kBlocksPerRegion + blockIdx.x] = t;
+        part[(int64_t)r * kBlocksPerRegion + wg_id()] = t;
     }
 }
 
 __global__ __launch_bounds__(64) void k_region_final(int n_reg, const double *__restrict__ part,
                                                      double *__restrict__ out)
 {
-    const int r = blockIdx.x * 64 + threadIdx.x;
+    const int r = wg_id() * 64 + tid();
     if (r >= n_reg) return;
     double t = 0.0;
     for (int b = 0; b < kBlocksPerRegion; ++b) t += part[(int64_t)r * kBlocksPerRegion + b];

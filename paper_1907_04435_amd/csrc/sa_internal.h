@@ -11,6 +11,21 @@
 
 namespace sa {
 
+// The work-item index within its work-group and the work-group index, read
+// straight from the registers the hardware fills at dispatch.  The
+// runtime's own accessors (threadIdx, blockIdx) are calls into its device
+// library in this build: that library keeps IEEE mode on and the kernels
+// turn it off, so the calls are not inlined, and a call site makes the
+// register allocator keep to the calling convention (the accrual kernel
+// spilled two vector registers to scratch memory for it).
+__device__ __forceinline__ unsigned tid() { return __builtin_amdgcn_workitem_id_x(); }
+__device__ __forceinline__ unsigned wg_id() { return __builtin_amdgcn_workgroup_id_x(); }
+__device__ __forceinline__ unsigned wg_id_y() { return __builtin_amdgcn_workgroup_id_y(); }
+// Work-items per work-group and work-groups in the grid (x), from the
+// dispatch packet.
+__device__ __forceinline__ unsigned wg_size() { return __builtin_amdgcn_workgroup_size_x(); }
+__device__ __forceinline__ unsigned n_wg() { return __builtin_amdgcn_grid_size_x() / __builtin_amdgcn_workgroup_size_x(); }
+
 // One interior node of the binary hierarchy: the boxes of both children
 // (footprint-plane box x0,y0,x1,y1 and the top z1; every box starts at
 // z = 0 because every prism stands on the ground) and the child
@@ -223,6 +238,9 @@ sa_status launch_grad(const DeviceScene &s, const DevicePath &p, const PointsVie
 sa_status launch_region_sum(const float *v, int n_bins, int64_t n, const double *bin_w,
                             const int64_t *off, int32_t n_reg, const float *area, double *out,
                             Scratch &scr, hipStream_t st, std::string &err);
+// The FP32 FMA lane-op rate the device sustains (a roofline measurement aid).
+sa_status measure_valu_peak(int n_cu, float *sink, int64_t sink_floats, hipStream_t st, double &lane_ops_per_s,
+                            std::string &err);
 sa_status launch_contribution(const DeviceScene &s, const DevicePath &p, const PointsView &pts,
                               const float *weight, double *contrib, const TileLaunch &L, uint32_t *grab,
                               Scratch &scr, hipStream_t st, std::string &err);

@@ -27,8 +27,8 @@ constexpr int kWavesPerBlock = kThreads / 64;
 
 __global__ void k_sam_clear(uint32_t *p, int64_t n)
 {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) p[t] = 0u;
+    const int64_t stride = (int64_t)n_wg() * wg_size();
+    for (int64_t t = (int64_t)wg_id() * wg_size() + tid(); t < n; t += stride) p[t] = 0u;
 }
 
 // One wave per (slice, prism): the wave covers the texels of the prism's
@@ -70,13 +70,13 @@ __global__ __launch_bounds__(kThreads) void k_sam_build(const float4 *__restrict
                                                         const SamSlice *__restrict__ slices, int K,
                                                         uint32_t *__restrict__ map, uint32_t stamp)
 {
-    const int lane = threadIdx.x & 63;
+    const int lane = tid() & 63;
     const int lx = lane & 7, ly = lane >> 3;
     const uint32_t tag = stamp << 24;
     const int64_t items = (int64_t)K * n_b;
     const int64_t T = (int64_t)g.nu * g.nv;
-    const int64_t nw = (int64_t)gridDim.x * kWavesPerBlock;
-    const int64_t w0 = (int64_t)blockIdx.x * kWavesPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t nw = (int64_t)n_wg() * kWavesPerBlock;
+    const int64_t w0 = (int64_t)wg_id() * kWavesPerBlock + __builtin_amdgcn_readfirstlane(tid() >> 6);
     for (int64_t it = w0; it < items; it += nw) {
         const int k = (int)(it / n_b);
         const int b = (int)(it - (int64_t)k * n_b);
@@ -231,8 +231,8 @@ __global__ __launch_bounds__(kThreads) void k_sam_query(const float *__restrict_
                                                         int32_t *__restrict__ counts, float *__restrict__ minutes)
 {
     const int64_t T = (int64_t)g.nu * g.nv;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t stride = (int64_t)n_wg() * wg_size();
+    for (int64_t i = (int64_t)wg_id() * wg_size() + tid(); i < n; i += stride) {
         const float rx = px[i] - g.ox, ry = py[i] - g.oy, rz = pz[i] - g.oz;
         const float ra = rx * g.ax + ry * g.ay + rz * g.az - g.c;
         int cnt = 0;

@@ -54,13 +54,13 @@ __device__ __forceinline__ bool next_unit(const lds_int *s_W, int a0, int a1, in
 {
     const Sched W = lds_uniform<Sched>(s_W);
     const uint32_t n_units = W.n_tiles * W.n_parts;
-    const int xcd = blockIdx.x & 7;
+    const int xcd = wg_id() & 7;
     for (; k < 8; ++k) {
         const int x = (xcd + k) & 7;
         const uint32_t lo = (uint32_t)((uint64_t)n_units * x >> 3);
         const uint32_t hi = (uint32_t)((uint64_t)n_units * (x + 1) >> 3);
         uint32_t got = 0;
-        if ((threadIdx.x & 63) == 0) got = atomicAdd(W.grab + kGrabStride * x, 1u);
+        if ((tid() & 63) == 0) got = atomicAdd(W.grab + kGrabStride * x, 1u);
         got = (uint32_t)__builtin_amdgcn_readlane((int)got, 0);
         if (got < hi - lo) {
             const uint32_t u = lo + got;
