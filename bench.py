@@ -655,6 +655,21 @@ def main():
                                                   "point_segments": int(wa[5]), "spilled": int(wa[6]),
                                                   "leaf_visits_per_wave": int(wa[7]), "lane_ops": ops}}
         log(f"accrual work: {wa.tolist()} -> {ops:.3e} lane-ops, {achieved/1e12:.2f} T/s")
+        # the derived peaks checked on this device: FP32 FMA chains (lane-op
+        # rate, sa_measure_valu_peak) and a 1 GiB device copy (HBM)
+        valu = ctx.measure_valu_peak()
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        cms = min(_timed(torch, torch.cuda.current_stream(), lambda: dst.copy_(src), 3))
+        copy_gbs = 2 * src.numel() * 4 / (cms / 1e3) / 1e9
+        del src, dst
+        result["roofline"]["peak_check"] = {
+            "valu_lane_ops_per_s": valu, "valu_of_derived_peak": valu / LANE_OP_PEAK,
+            "frac_of_measured_valu": achieved / valu if valu > 0 else None,
+            "copy_GB_per_s": copy_gbs, "copy_of_8TBps": copy_gbs / 8000.0}
+        log(f"peak check: {valu/1e12:.2f} Tlane-op/s FMA chains, {copy_gbs:.0f} GB/s copy")
         if not args.skip_sampled:
             work.zero_()
             sa.sa_accumulate(ctx, scene, pts, path, sa.SA_SAMPLED, counts_s, mins_s, work=work)

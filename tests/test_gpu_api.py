@@ -112,3 +112,16 @@ def test_scene_upload_from_device_arrays(ctx, c1):
         sa.Scene(ctx, torch.from_numpy(c1.scene.vert_off.astype(np.int32)).cuda(),
                  torch.from_numpy(np.ascontiguousarray(c1.scene.xy, np.float32)).cuda(), bad)
     assert e.value.code == -2
+
+
+def test_valu_peak_measurement(ctx):
+    """sa_measure_valu_peak: the FMA-chain lane-op rate lies between a
+    third of the derived peak (256 CU x 64 lanes x 2.4 GHz) and the derived
+    peak itself (the clock's maximum), and repeats within 10 %."""
+    from gpu_util import say
+    derived = 256 * 64 * 2.4e9
+    a, b = ctx.measure_valu_peak(), ctx.measure_valu_peak()
+    say(f"FMA-chain lane-op rate {a / 1e12:.2f} and {b / 1e12:.2f} T/s ({a / derived:.3f} of the derived peak)")
+    for v in (a, b):
+        assert derived / 3 < v < 1.02 * derived
+    assert abs(a - b) <= 0.1 * max(a, b)
