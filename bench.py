@@ -614,6 +614,22 @@ def main():
         log(f"sampled: {s_ms:.1f} ms/pass")
         result["sampled"] = {"value": evals / (s_ms / 1e3), "unit": "point-sun-steps/s", "ms_per_pass": s_ms}
         result["accrual_over_sampled"] = (evals / (ms_step / 1e3)) / (evals / (s_ms / 1e3))
+        # the outputs that need every instant in order (bitmap replay):
+        # bit vectors of Sec. 5 and the continuous shadow, same points
+        if not args.skip_continuous:
+            bits = torch.empty(((K + 31) // 32, n), dtype=torch.int32, device=dev)
+            runs = torch.empty((B, n), dtype=torch.float32, device=dev)
+            ordered = {}
+            for name, kw in (("bit_vectors", {"bits": bits}), ("continuous_shadow", {"longest": runs})):
+                call = lambda: sa.sa_accumulate(ctx, scene, pts, path, sa.SA_SAMPLED, counts_s, mins_s,
+                                                kw.get("bits"), longest=kw.get("longest"))
+                call()
+                ctx.sync()
+                ordered[name] = float(np.median(_timed(torch, stream, call, 3)))
+            result["sampled"]["ordered_outputs_ms_per_pass"] = ordered
+            log(f"sampled with bit vectors {ordered['bit_vectors']:.1f} ms, with the continuous shadow "
+                f"{ordered['continuous_shadow']:.1f} ms")
+            del bits, runs
 
     # ---- accuracy over every point: the headline accrual and the sampled
     # form against the accrual form with a knot at every instant (the CPU
